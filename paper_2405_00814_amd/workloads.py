@@ -1,0 +1,264 @@
+"""Seeded synthetic workloads (inputs only).
+
+This module builds the inputs that both the FP32 HIP path and the FP64 oracle
+consume: grid sizes, spatial and time steps, per-cell material maps, CPML
+thickness, source description, probe cells and the design box of the
+sensitivity study.  It holds none of the update arithmetic: no coefficient
+folding, no CPML profile, no source waveform.  Each consumer turns the
+description below into its own numbers.
+
+Scenes follow the paper's proof-of-concept experiments (Sec. V-A): randomly
+placed axis-aligned objects with random permittivity and conductivity on a
+vacuum background, a point source at a random position, waveforms sampled at
+random cells.  Objects are painted in draw order (later wins) and are kept
+out of the absorbing layer.  All randomness is numpy PCG64 with an explicit
+seed.
+
+The time step comes from a Courant number S: dt = S * min(dx) / c0.  The
+spatial step of the dielectric scenes follows the paper's "20 points per
+shortest wavelength" rule (Sec. V-B), with the shortest wavelength taken at
+three times the Ricker peak frequency in the densest medium.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+C0 = 299792458.0  # speed of light in vacuum, m/s (exact, SI)
+
+SRC_GAUSSIAN = 0
+SRC_RICKER = 1
+
+
+@dataclasses.dataclass
+class Source:
+    """A soft point source: Ez[cell] += amp * g((n+1) dt) after each E update.
+
+    kind: SRC_GAUSSIAN with params (amp, t0, tau), g = exp(-((t - t0)/tau)^2)
+          SRC_RICKER   with params (amp, t0, f),   g = (1 - 2 pi^2 f^2 s^2) exp(-pi^2 f^2 s^2), s = t - t0
+    """
+    cell: Tuple[int, ...]
+    kind: int
+    params: Tuple[float, float, float]
+    component: str = "ez"
+
+
+@dataclasses.dataclass
+class Problem:
+    """One FDTD problem.  Arrays are float32, C order, last axis contiguous."""
+    name: str
+    ndim: int
+    shape: Tuple[int, ...]          # (nx, ny) or (nx, ny, nz), cells incl. CPML
+    dx: Tuple[float, ...]           # per-axis spatial step (m)
+    dt: float                       # time step (s)
+    steps: int                      # number of leapfrog steps of the workload
+    npml: Tuple[int, ...]           # cells per face: -x,+x,-y,+y(,-z,+z)
+    eps_r: Optional[np.ndarray]     # None => vacuum
+    sigma: Optional[np.ndarray]     # None => lossless (S/m)
+    mu_r: Optional[np.ndarray]      # None => 1
+    source: Optional[Source]
+    probes: np.ndarray              # int32 [P, ndim]
+    probe_component: str = "ez"
+    design: Optional[Tuple[int, int, int, int]] = None   # [i0, i1) x [j0, j1)
+    window: Optional[Tuple[int, int]] = None              # loss window (n0, n1]
+    cpml: dict = dataclasses.field(default_factory=lambda: dict(
+        m=3.0, sigma_max=0.0, kappa_max=1.0, alpha_max=0.0, m_alpha=1.0))
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def _interior_cell(rng, shape, margin, avoid=None):
+    for _ in range(100000):
+        c = tuple(int(rng.integers(min(margin, (n - 1) // 2), n - min(margin, (n - 1) // 2)))
+                  for n in shape)
+        if avoid is None or not avoid(c):
+            return c
+    raise ValueError("no admissible cell in grid %s" % (shape,))
+
+
+def _paint_boxes(rng, shape, npml, count, side_lo, side_hi, eps_lo, eps_hi,
+                 sig_hi, eps, sigma):
+    """Axis-aligned boxes with integer sides U{side_lo..side_hi}, corners
+    uniform inside the non-CPML interior, painted in draw order."""
+    nd = len(shape)
+    for _ in range(count):
+        lo, hi = [], []
+        for a in range(nd):
+            inner = shape[a] - npml[2 * a] - npml[2 * a + 1]
+            w = int(rng.integers(side_lo, side_hi + 1))
+            w = min(w, inner)
+            c0 = int(rng.integers(npml[2 * a], npml[2 * a] + inner - w + 1))
+            lo.append(c0)
+            hi.append(c0 + w)
+        er = float(rng.uniform(eps_lo, eps_hi))
+        sl = tuple(slice(l, h) for l, h in zip(lo, hi))
+        eps[sl] = er
+        if sigma is not None:
+            sigma[sl] = float(rng.uniform(0.0, sig_hi))
+
+
+def courant_dt(S: float, dx: Sequence[float]) -> float:
+    return S * min(dx) / C0
+
+
+def dx_for_ricker(f_peak: float, eps_max: float, ppw: int = 20) -> float:
+    """Spatial step from 'ppw points per shortest wavelength', shortest
+    wavelength at 3 * f_peak in the densest medium."""
+    return C0 / (3.0 * f_peak * math.sqrt(eps_max) * ppw)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads (and scaled-down versions of them for parity tests)
+# ---------------------------------------------------------------------------
+
+def cavity2d(n: int = 128, steps: int = 1000, seed: int = 0, nprobes: int = 4,
+             ny: Optional[int] = None) -> Problem:
+    """2D TMz PEC cavity, vacuum, dx = 1 mm, S = 0.99/sqrt(2), Gaussian pulse
+    (tau = 20 dt, t0 = 100 dt) at a seeded interior cell, seeded probes."""
+    rng = np.random.default_rng(seed)
+    ny = n if ny is None else ny
+    shape = (n, ny)
+    dx = (1e-3, 1e-3)
+    dt = courant_dt(0.99 / math.sqrt(2.0), dx)
+    margin = min(8, min(shape) // 4)
+    src = Source(_interior_cell(rng, shape, margin), SRC_GAUSSIAN,
+                 (1.0, 100.0 * dt, 20.0 * dt))
+    probes = np.array([_interior_cell(rng, shape, margin) for _ in range(nprobes)],
+                      dtype=np.int32)
+    return Problem("cavity2d_%dx%d" % shape, 2, shape, dx, dt, steps,
+                   (0, 0, 0, 0), None, None, None, src, probes)
+
+
+def dielectric2d(n: int = 4096, steps: int = 10000, seed: int = 0,
+                 nrect: int = 200, side: Tuple[int, int] = (16, 512),
+                 npml: int = 16, nprobes: int = 8, ny: Optional[int] = None,
+                 lossy: bool = True, f_peak: float = 1e9) -> Problem:
+    """2D TMz with CPML and a random-rectangle scene: eps_r ~ U[1,6],
+    sigma ~ U[0, 0.01] S/m, Ricker source at f_peak, t0 = 1.5/f_peak,
+    dx = lambda_min/20, S = 0.99/sqrt(2)."""
+    rng = np.random.default_rng(seed)
+    ny = n if ny is None else ny
+    shape = (n, ny)
+    pml = (npml,) * 4
+    eps = np.ones(shape, np.float32)
+    sig = np.zeros(shape, np.float32) if lossy else None
+    _paint_boxes(rng, shape, pml, nrect, side[0], side[1], 1.0, 6.0, 0.01, eps, sig)
+    h = dx_for_ricker(f_peak, 6.0)
+    dx = (h, h)
+    dt = courant_dt(0.99 / math.sqrt(2.0), dx)
+    margin = npml + min(8, (min(shape) - 2 * npml) // 4)
+    src = Source(_interior_cell(rng, shape, margin), SRC_RICKER, (1.0, 1.5 / f_peak, f_peak))
+    probes = np.array([_interior_cell(rng, shape, margin) for _ in range(nprobes)],
+                      dtype=np.int32)
+    return Problem("dielectric2d_%dx%d" % shape, 2, shape, dx, dt, steps, pml,
+                   eps, sig, None, src, probes)
+
+
+def yee3d(n: int = 512, steps: int = 2000, seed: int = 0, nbox: int = 500,
+          side: Tuple[int, int] = (8, 96), npml: int = 12, nprobes: int = 8,
+          shape: Optional[Tuple[int, int, int]] = None,
+          tau_steps: float = 68.0) -> Problem:
+    """3D Yee, CPML, random dielectric boxes eps_r ~ U[1,8], sigma = 0,
+    mu_r = 1, z-directed soft Ez source with a Gaussian pulse
+    (tau = tau_steps * dt, t0 = 5 tau), dx = 1 mm, S = 0.99/sqrt(3)."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n) if shape is None else tuple(shape)
+    pml = (npml,) * 6
+    eps = np.ones(shape, np.float32)
+    _paint_boxes(rng, shape, pml, nbox, side[0], side[1], 1.0, 8.0, 0.0, eps, None)
+    dx = (1e-3, 1e-3, 1e-3)
+    dt = courant_dt(0.99 / math.sqrt(3.0), dx)
+    margin = npml + min(8, (min(shape) - 2 * npml) // 4)
+    tau = tau_steps * dt
+    src = Source(_interior_cell(rng, shape, margin), SRC_GAUSSIAN, (1.0, 5.0 * tau, tau))
+    probes = np.array([_interior_cell(rng, shape, margin) for _ in range(nprobes)],
+                      dtype=np.int32)
+    return Problem("yee3d_%dx%dx%d" % shape, 3, shape, dx, dt, steps, pml,
+                   eps, None, None, src, probes)
+
+
+def batch2d(count: int = 256, steps: int = 4000, seed: int = 0,
+            side: Tuple[int, int] = (256, 2048), npml: int = 16,
+            nprobes: int = 4, rect_side: Tuple[int, int] = (16, 256),
+            rect_density: float = 200.0 / 4096 ** 2) -> List[Problem]:
+    """Independent 2D TMz problems with sides drawn independently and
+    uniformly from {side[0]..side[1]} (ny redrawn while equal to nx), each with
+    its own random-rectangle scene (eps_r ~ U[1,6], sigma = 0), Ricker 1 GHz
+    at its own cell, 16-cell CPML, dx = 2.0398 mm, S = 0.99/sqrt(2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    h = dx_for_ricker(1e9, 6.0)
+    dx = (h, h)
+    dt = courant_dt(0.99 / math.sqrt(2.0), dx)
+    for p in range(count):
+        nx = int(rng.integers(side[0], side[1] + 1))
+        ny = int(rng.integers(side[0], side[1] + 1))
+        while ny == nx:
+            ny = int(rng.integers(side[0], side[1] + 1))
+        shape = (nx, ny)
+        pml = (npml,) * 4
+        eps = np.ones(shape, np.float32)
+        nrect = max(1, int(round(rect_density * nx * ny)))
+        _paint_boxes(rng, shape, pml, nrect, rect_side[0], rect_side[1], 1.0, 6.0,
+                     0.0, eps, None)
+        margin = npml + min(8, (min(shape) - 2 * npml) // 4)
+        src = Source(_interior_cell(rng, shape, margin), SRC_RICKER, (1.0, 1.5e-9, 1e9))
+        probes = np.array([_interior_cell(rng, shape, margin) for _ in range(nprobes)],
+                          dtype=np.int32)
+        out.append(Problem("batch2d[%d]_%dx%d" % (p, nx, ny), 2, shape, dx, dt, steps,
+                           pml, eps, None, None, src, probes))
+    return out
+
+
+def adjoint2d(n: int = 1024, steps: int = 4000, seed: int = 0,
+              design: Optional[Tuple[int, int, int, int]] = None,
+              npml: int = 16, nprobes: int = 16) -> Problem:
+    """2D TMz sensitivity study: vacuum with a design box whose eps_r is
+    i.i.d. U[1,4] per cell, Ricker 1 GHz outside the box, probes outside the
+    box and the CPML, loss window (T/2, T]."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n)
+    pml = (npml,) * 4
+    if design is None:
+        a, b = (3 * n) // 8, (5 * n) // 8
+        design = (a, b, a, b)
+    i0, i1, j0, j1 = design
+    eps = np.ones(shape, np.float32)
+    eps[i0:i1, j0:j1] = rng.uniform(1.0, 4.0, size=(i1 - i0, j1 - j0)).astype(np.float32)
+    h = dx_for_ricker(1e9, 4.0)
+    dx = (h, h)
+    dt = courant_dt(0.99 / math.sqrt(2.0), dx)
+    margin = npml + min(8, (n - 2 * npml) // 8)
+
+    def in_design(c):
+        return i0 - 2 <= c[0] < i1 + 2 and j0 - 2 <= c[1] < j1 + 2
+
+    src = Source(_interior_cell(rng, shape, margin, in_design), SRC_RICKER, (1.0, 1.5e-9, 1e9))
+    probes = np.array([_interior_cell(rng, shape, margin, in_design) for _ in range(nprobes)],
+                      dtype=np.int32)
+    return Problem("adjoint2d_%dx%d" % shape, 2, shape, dx, dt, steps, pml, eps,
+                   None, None, src, probes, design=design, window=(steps // 2, steps))
+
+
+def freespace2d(n: int, steps: int = 1024, npml: int = 16) -> Problem:
+    """Paper-shape sweep (Sec. V-C): free space square grid, absorbing layer,
+    Gaussian source at the centre."""
+    shape = (n, n)
+    h = dx_for_ricker(1e9, 1.0)
+    dx = (h, h)
+    dt = courant_dt(0.99 / math.sqrt(2.0), dx)
+    tau = 20.0 * dt
+    src = Source((n // 2, n // 2), SRC_GAUSSIAN, (1.0, 5.0 * tau, tau))
+    probes = np.array([(n // 2 + 3, n // 2 - 5)], dtype=np.int32)
+    return Problem("freespace2d_%dx%d" % shape, 2, shape, dx, dt, steps,
+                   (npml,) * 4, None, None, None, src, probes)
+
+
+def random_state(rng: np.random.Generator, shape, ncomp: int, dtype=np.float64):
+    """Random field components (for linearity / adjoint / resume tests)."""
+    return [rng.standard_normal(shape).astype(dtype) for _ in range(ncomp)]
