@@ -1,0 +1,251 @@
+/*
+ * gemfdtd.h -- C ABI of the MI355X FDTD library.
+ *
+ * The library advances Maxwell's equations on a Yee grid with the leapfrog
+ * scheme of the paper (Sec. III-B, Eq. 7-9): per time step an H layer
+ * gathers curl-E messages into the magnetic nodes, then an E layer gathers
+ * curl-H messages into the electric nodes, with fixed per-node weights
+ * (Prop. 1 and Prop. 2, Sec. IV-A).  The regular Yee graph is kept implicit:
+ * the edge weights are folded into per-cell coefficients.  A second
+ * constructor builds the explicit graph (compressed sparse rows) and runs
+ * the same two layers as generic weighted gathers.  The outer boundary is a
+ * convolutional PML (CPML) backed by PEC; the paper's own absorbing layer
+ * is the split-field PML of Sec. III-C, which this library replaces.
+ *
+ * Conventions (all calls):
+ *  - ndim == 2 is the TMz polarisation (Ez, Hx, Hy), the paper's 2D
+ *    polarisation of Eq. 3-5 up to the relabelling Ez = -Ey, Hy = Hz.
+ *    ndim == 3 is the six-component Yee scheme.
+ *  - Grid arrays are row-major with the last axis contiguous:
+ *    2D idx = i*ny + j; 3D idx = (i*ny + j)*nz + k.  Sizes count CPML cells.
+ *  - Cell (i,j[,k]) owns Ez(i,j) [3D: Ex(i+1/2,j,k), Ey(i,j+1/2,k),
+ *    Ez(i,j,k+1/2)] and Hx(i,j+1/2), Hy(i+1/2,j) [3D: Hx(i,j+1/2,k+1/2),
+ *    Hy(i+1/2,j,k+1/2), Hz(i+1/2,j+1/2,k)].  Its eps_r and sigma apply to its
+ *    E components, its mu_r to its H components.
+ *  - Outer boundary PEC: E components tangential to the planes i=0, j=0
+ *    (k=0) are never updated; values beyond the last cell read as zero.
+ *  - One step n -> n+1: H layer (H^{n+1/2}), E layer (E^{n+1}), soft source
+ *    E[src] += amp*g((n+1) dt), probe sample index n = E^{n+1} at the probe.
+ *  - Fields, coefficients and auxiliary CPML values are float32 on the
+ *    device.  Coefficients are computed in double on the host and rounded
+ *    once.
+ *  - Device pointers are HIP device addresses on the device that was
+ *    current when the handle was created.  Host pointers are ordinary
+ *    memory.  Every call returns 0 (FDTD_OK) or a negative status; no call
+ *    aborts or throws.  fdtd_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - A handle is used by one thread at a time.  Work is enqueued on the
+ *    handle's stream; calls that return host data synchronise that stream.
+ */
+#ifndef GEMFDTD_H
+#define GEMFDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,      /* invalid argument */
+    FDTD_EUNSTABLE = -2,   /* dt above the Courant limit c0 dt <= 1/sqrt(sum 1/d^2) */
+    FDTD_ENOMEM = -3,      /* device allocation failed */
+    FDTD_EDEVICE = -4,     /* a HIP call failed */
+    FDTD_ENONFINITE = -5,  /* a field holds NaN or Inf */
+    FDTD_ESTATE = -6       /* call not valid in the handle's current state */
+};
+
+/* Field components. */
+enum { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
+
+/* Source waveforms g(t) (the paper names Gaussian-type point sources,
+ * Sec. V-A and V-B, without a formula; these are the forms used here):
+ *  GAUSSIAN params {amp, t0, tau}: g = exp(-((t - t0)/tau)^2)
+ *  RICKER   params {amp, t0, f}:   g = (1 - 2a) exp(-a), a = (pi f (t - t0))^2
+ *  TABLE    g[n] given for the steps 0..n_table-1 (sample n is added at the
+ *           end of step n, i.e. at time (n+1) dt), zero afterwards; amp = 1. */
+enum { FDTD_SRC_GAUSSIAN = 0, FDTD_SRC_RICKER = 1, FDTD_SRC_TABLE = 2 };
+
+/* Optional device allocator.  alloc returns NULL on failure.  The library
+ * frees every block it allocated in fdtd_destroy / fdtd_batch_destroy. */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} fdtd_allocator;
+
+/* CPML profile (the paper gives no absorbing-layer constants).  For an axis
+ * with d cells at a face, normalised depth rho = distance into the layer / d
+ * (1 at the PEC wall), sampled at x = i for E-type and x = i + 1/2 for
+ * H-type differences:
+ *   sigma = sigma_max rho^m, kappa = 1 + (kappa_max - 1) rho^m,
+ *   alpha = alpha_max (1 - rho)^m_alpha,
+ *   b = exp(-(sigma/kappa + alpha) dt/eps0),
+ *   c = sigma (b - 1)/(kappa (sigma + kappa alpha)).
+ * sigma_max <= 0 selects 0.8 (m + 1)/(eta0 d_axis).  kappa_max < 1 is
+ * invalid.  npml faces: -x, +x, -y, +y, -z, +z. */
+typedef struct {
+    int32_t npml[6];
+    double m, sigma_max, kappa_max, alpha_max, m_alpha;
+} fdtd_cpml;
+
+/* Problem description (the paper's problem statement, Sec. III: grid and
+ * steps, per-cell eps, mu, sigma, absorbing layer). */
+typedef struct {
+    int32_t ndim;              /* 2 (TMz) or 3 */
+    int32_t nx, ny, nz;        /* cells incl. CPML, each >= 3; nz = 1 for ndim 2 */
+    double dx, dy, dz, dt;     /* SI units; dz ignored for ndim 2 */
+    const float *eps_r;        /* host, nx*ny*nz, >= 1, finite; NULL => 1 */
+    const float *mu_r;         /* host, nx*ny*nz, >= 1, finite; NULL => 1 */
+    const float *sigma;        /* host, nx*ny*nz, >= 0 S/m, finite; NULL => 0 */
+    fdtd_cpml cpml;
+    void *stream;              /* hipStream_t to enqueue on; NULL => null stream */
+    const fdtd_allocator *allocator; /* NULL => hipMalloc / hipFree */
+} fdtd_desc;
+
+typedef struct fdtd_sim fdtd_sim;
+
+/* Build a simulation with the implicit Yee graph: validates the
+ * description, folds the edge weights of Prop. 1 (Ca = A-/A+,
+ * Cb = dt/(A+ eps), Db = dt/mu, CPML b, c, 1/kappa and 1/d) into per-cell
+ * and per-axis float32 tables, allocates zeroed fields.  Input arrays are
+ * copied; the caller keeps them.  Errors: FDTD_EINVAL (sizes, steps, maps,
+ * CPML thickness 2*npml >= n on an axis), FDTD_EUNSTABLE, FDTD_ENOMEM,
+ * FDTD_EDEVICE.  On error *out is NULL. */
+int fdtd_create(const fdtd_desc *desc, fdtd_sim **out);
+
+/* Build the same simulation as an explicit graph (ndim 2 only): node order
+ * of Prop. 1 (t = 2i+1+nx(3j+1) for Ez, u = i+3j nx for Hx, q = 2i+nx(3j+1)
+ * for Hy) with the CPML auxiliary values appended as extra nodes, one CSR
+ * matrix per layer (rows = nodes the layer updates, weights = the fixed
+ * coefficients of Eq. 7-9 on the previous state).  Every other call works
+ * the same on the result. */
+int fdtd_create_graph(const fdtd_desc *desc, fdtd_sim **out);
+
+/* Release all device memory (synchronises the stream).  NULL is accepted. */
+int fdtd_destroy(fdtd_sim *sim);
+
+/* Point source on an E component (FDTD_EZ for ndim 2) at cell ijk[0..ndim).
+ * params as in the FDTD_SRC_* comment (3 doubles; ignored for TABLE).
+ * A new call replaces the previous source; kind < 0 removes it.  The cell
+ * must not be on a PEC wall plane of that component.  FDTD_EINVAL. */
+int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind,
+                    const double *params, const float *table, int64_t n_table);
+
+/* Probe cells (ijk: n*ndim int32, host) sampled on `component` after every
+ * step.  Replaces earlier probes and clears the record.  n <= 4096. */
+int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n);
+
+/* Enqueue n >= 0 steps on the handle's stream (asynchronous). */
+int fdtd_step(fdtd_sim *sim, int64_t n);
+
+/* Copy the probe record to host memory out[p*cap + s] for the samples
+ * s < min(cap, recorded) of probe p; *n_recorded = samples recorded since
+ * the probes were set.  Synchronises.  out may be NULL to query. */
+int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
+
+/* Copy one component (nx*ny*nz float32, same layout as the maps) to dst.
+ * dst_on_device != 0: dst is device memory, the copy is enqueued on the
+ * stream; else host memory and the call synchronises. */
+int fdtd_get_field(fdtd_sim *sim, int component, void *dst, int dst_on_device);
+
+/* Overwrite one component (tests, resume).  Same layout and flag. */
+int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_device);
+
+/* Zero all fields, auxiliary CPML values, the probe record and the step
+ * counter. */
+int fdtd_reset(fdtd_sim *sim);
+
+/* Number of steps taken since creation / reset. */
+int fdtd_steps_done(const fdtd_sim *sim, int64_t *n);
+
+/* FDTD_ENONFINITE if any field value is NaN or Inf, else FDTD_OK.
+ * Synchronises. */
+int fdtd_check_finite(fdtd_sim *sim);
+
+/* Replace eps_r (and optionally sigma, may be NULL => unchanged) on the box
+ * [lo[d], hi[d]) (host arrays in box order, last axis contiguous) and refold
+ * the coefficients there.  Fields are kept. */
+int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
+                      const float *eps_r, const float *sigma);
+
+/* Kernel selection for the implicit-graph stepper.
+ *  variant: 0 = auto (autotuned or default), 1 = two-pass reference
+ *           (separate H and E kernels, in place), 2 = fused single pass
+ *           (one kernel per step, double-buffered state).
+ *  tile[0..3]: variant-specific tile sizes (0 = default); tb reserved (1).
+ * FDTD_EINVAL for unknown or unsupported combinations. */
+typedef struct {
+    int32_t variant;
+    int32_t tile[4];
+    int32_t tb;
+} fdtd_kernel_config;
+
+int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg);
+int fdtd_get_kernel(const fdtd_sim *sim, fdtd_kernel_config *cfg);
+
+/* Time every candidate configuration on this grid for `trial_steps` steps
+ * and keep the fastest (the state is saved before and restored after).
+ * The choice is cached in the JSON file named by $GEMFDTD_TUNE_CACHE (if
+ * set) keyed by device, dimensions and material flags.  out may be NULL. */
+int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out);
+
+/* Device time in milliseconds of the kernels enqueued by the last
+ * fdtd_step call, measured with HIP events on the handle's stream
+ * (synchronises).  *launches receives the number of kernel launches. */
+int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches);
+
+/* --------------------------------------------------------------------- */
+/* Batched form: many independent 2D problems of different sizes advanced  */
+/* together, one launch per time block over a packed arena, captured in a  */
+/* HIP graph.                                                              */
+/* --------------------------------------------------------------------- */
+typedef struct fdtd_batch fdtd_batch;
+
+/* descs[0..n) as for fdtd_create (ndim 2; stream and allocator of descs[0]
+ * are used for the whole batch).  dt may differ per problem. */
+int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out);
+int fdtd_batch_destroy(fdtd_batch *b);
+int fdtd_batch_set_source(fdtd_batch *b, int32_t problem, const int32_t *ijk, int kind,
+                          const double *params, const float *table, int64_t n_table);
+int fdtd_batch_set_probes(fdtd_batch *b, int32_t problem, const int32_t *ijk, int32_t n);
+/* Enqueue n steps of every problem. */
+int fdtd_batch_step(fdtd_batch *b, int64_t n);
+int fdtd_batch_probe(fdtd_batch *b, int32_t problem, float *out, int64_t cap,
+                     int64_t *n_recorded);
+int fdtd_batch_get_field(fdtd_batch *b, int32_t problem, int component, void *dst,
+                         int dst_on_device);
+int fdtd_batch_last_step_time(fdtd_batch *b, float *ms, int64_t *launches);
+/* Total cells of all problems. */
+int fdtd_batch_cells(const fdtd_batch *b, int64_t *cells);
+
+/* --------------------------------------------------------------------- */
+/* Adjoint: gradient of a probe-energy loss with respect to eps_r.         */
+/* --------------------------------------------------------------------- */
+/* Starting from the zero state, run T steps with the handle's source,
+ * evaluate L = sum_p sum_{m in (n0, n1]} E^m[probe p]^2 (E^m = probe sample
+ * m-1 of the handle's probes), and compute dL/d eps_r on the box
+ * design = {i0, i1, j0, j1} (ndim 2) by the discrete adjoint: the
+ * transposed E and H layers run backward in time.  The forward pass keeps a
+ * full-state checkpoint every `ckpt_interval` steps (<= 0 => ceil(sqrt T))
+ * and recomputes each segment before its adjoint sweep.
+ * loss_out (host, may be NULL); grad_dev: device float32
+ * [(i1-i0)*(j1-j0)], written.  On return the handle holds the forward state
+ * after T steps and the probe record of the forward run. */
+int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
+                     const int32_t *design, int32_t ckpt_interval, double *loss_out,
+                     float *grad_dev);
+
+/* Thread-local text of the calling thread's last failure ("" if none). */
+const char *fdtd_last_error(void);
+
+/* Library version string. */
+const char *fdtd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEMFDTD_H */

@@ -1,0 +1,232 @@
+// Gradient of a probe-energy loss with respect to eps_r by the discrete
+// adjoint, with checkpointing.
+//
+// Forward: T steps from the zero state with a full-state checkpoint every L
+// steps.  Backward, newest segment first: restore the checkpoint, recompute
+// the segment with the same kernel (bitwise the same states) while keeping,
+// at every design cell and step, Ez before the E layer and the E-layer
+// bracket; then run the segment's adjoint steps backward.  The gradient of
+// E^{k+1} = Ca E^k + Cb * bracket with respect to eps_r at a design cell is
+// dCa * E^k + dCb * bracket, weighted by the adjoint of E^{k+1}; it is
+// accumulated in double.
+#include <algorithm>
+#include <cmath>
+
+#include "sim.hpp"
+
+namespace gem {
+
+int status_of_current_exception();
+
+namespace {
+
+struct StateBuf {
+    std::vector<std::pair<float *, int64_t>> parts;  // (device pointer, floats) of set 0
+};
+
+}  // namespace
+
+static void copy_state(Sim &s, int set, float *buf, bool to_buf) {
+    int64_t off = 0;
+    auto mv = [&](float *p, int64_t n) {
+        if (!p || n <= 0) return;
+        if (to_buf) hip_check(hipMemcpyAsync(buf + off, p, n * 4, hipMemcpyDeviceToDevice, s.st), "ckpt");
+        else hip_check(hipMemcpyAsync(p, buf + off, n * 4, hipMemcpyDeviceToDevice, s.st), "ckpt");
+        off += n;
+    };
+    for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) mv(s.f[set][c], s.ncell);
+    for (int a = 0; a < 4; ++a) mv(s.psi[set][a], s.psi_len[a]);
+}
+
+static int64_t state_floats(const Sim &s) {
+    int64_t n = 3 * s.ncell;
+    for (int a = 0; a < 4; ++a) n += s.psi_len[a];
+    return n;
+}
+
+}  // namespace gem
+
+using namespace gem;
+
+extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
+                                const int32_t *design, int32_t ckpt_interval, double *loss_out,
+                                float *grad_dev) {
+    std::vector<void *> tmp;
+    Sim *sp = nullptr;
+    fdtd_kernel_config saved{};
+    bool restore_cfg = false;
+    try {
+        if (!sim || !design || !grad_dev) fail(FDTD_EINVAL, "NULL argument");
+        Sim &s = sim->s;
+        sp = &s;
+        if (s.ndim != 2 || s.is_graph) fail(FDTD_EINVAL, "the adjoint supports the 2D implicit stepper");
+        if (T < 1 || n0 < 0 || n1 < n0 || n1 > T) fail(FDTD_EINVAL, "need T >= 1 and 0 <= n0 <= n1 <= T");
+        const int i0 = design[0], i1 = design[1], j0 = design[2], j1 = design[3];
+        if (i0 < 0 || i1 > s.nx || j0 < 0 || j1 > s.ny || i0 >= i1 || j0 >= j1)
+            fail(FDTD_EINVAL, "invalid design box");
+        if (s.probe_cells.empty() || s.probe_comp != FDTD_EZ)
+            fail(FDTD_EINVAL, "the loss needs Ez probes (fdtd_set_probes)");
+        const int64_t L = ckpt_interval > 0 ? ckpt_interval : (int64_t)std::ceil(std::sqrt((double)T));
+        const int64_t nseg = (T + L - 1) / L;
+        const int64_t nd = (int64_t)(i1 - i0) * (j1 - j0);
+        const int64_t P = (int64_t)s.probe_cells.size();
+
+        // the recompute captures design values from the fused kernel
+        saved = s.kcfg;
+        restore_cfg = true;
+        if (s.kcfg.variant != 2) {
+            s.kcfg = fdtd_kernel_config{};
+            s.kcfg.variant = 2;
+            s.kcfg.tile[0] = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
+            s.kcfg.tile[1] = 16;
+            s.kcfg.tb = 1;
+        }
+        s.pt_ntiles = -1;
+        s.build_probe_tiles();
+        s.zero_state();
+        s.ensure_source(T);
+        s.ensure_rec(T);
+        auto get = [&](size_t bytes) {
+            void *p = s.al.get(bytes);
+            tmp.push_back(p);
+            return p;
+        };
+        const int64_t S = state_floats(s);
+        float *ck = (float *)get((size_t)(nseg * S) * 4);
+        float *fin = (float *)get((size_t)S * 4);
+        hip_check(hipEventRecord(s.ev0, s.st), "event");
+        // ---- forward with checkpoints ----
+        for (int64_t g = 0; g < nseg; ++g) {
+            copy_state(s, s.cur, ck + g * S, true);
+            const int64_t k1 = std::min(T, (g + 1) * L);
+            for (int64_t k = g * L; k < k1; ++k) {
+                s.launch_step(k);
+                s.n_done += 1;
+                s.n_rec += 1;
+            }
+        }
+        copy_state(s, s.cur, fin, true);
+        // ---- loss ----
+        std::vector<float> rec((size_t)(P * T));
+        hip_check(hipMemcpy2DAsync(rec.data(), T * 4, s.rec_dev, s.rec_cap * 4, T * 4, P,
+                                   hipMemcpyDeviceToHost, s.st), "record copy");
+        hip_check(hipStreamSynchronize(s.st), "sync");
+        double loss = 0.0;
+        for (int64_t p = 0; p < P; ++p)
+            for (int64_t m = n0 + 1; m <= n1; ++m) {
+                const double v = rec[(size_t)(p * T + m - 1)];
+                loss += v * v;
+            }
+        // ---- adjoint buffers ----
+        Adj2D a{};
+        const size_t cb = (size_t)s.ncell * 4;
+        a.ez = (float *)get(cb);
+        a.hx = (float *)get(cb);
+        a.hy = (float *)get(cb);
+        a.gx = (float *)get(cb);
+        a.gy = (float *)get(cb);
+        a.ex = (float *)get(cb);
+        a.ey = (float *)get(cb);
+        a.psi_hx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[0]) * 4);
+        a.psi_hy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[1]) * 4);
+        a.psi_ezx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[2]) * 4);
+        a.psi_ezy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[3]) * 4);
+        double *grad = (double *)get((size_t)nd * 8);
+        float *cap_ez = (float *)get((size_t)(L * nd) * 4);
+        float *cap_br = (float *)get((size_t)(L * nd) * 4);
+        // coefficient derivatives at the design cells (double, rounded once)
+        std::vector<float> hdca((size_t)nd), hdcb((size_t)nd);
+        for (int i = i0; i < i1; ++i)
+            for (int j = j0; j < j1; ++j) {
+                const int64_t c = (int64_t)i * s.ny + j;
+                const int64_t q = (int64_t)(i - i0) * (j1 - j0) + (j - j0);
+                const double er = s.eps_r.empty() ? 1.0 : s.eps_r[(size_t)c];
+                const double sg = s.sigma.empty() ? 0.0 : s.sigma[(size_t)c];
+                const double e = kEps0 * er, h = 0.5 * sg * s.dt;
+                const double den = (e + h) * (e + h);
+                hdca[(size_t)q] = (float)(kEps0 * 2.0 * h / den);
+                hdcb[(size_t)q] = (float)(-kEps0 * s.dt / den);
+            }
+        float *dca = (float *)get((size_t)nd * 4);
+        float *dcb = (float *)get((size_t)nd * 4);
+        hip_check(hipMemcpyAsync(dca, hdca.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(dcb, hdcb.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
+        // probes grouped per block of 256 cells (for the loss seed)
+        const int64_t nb = (s.ncell + 255) / 256;
+        std::vector<int> pst((size_t)nb + 1, 0), pcell, pslot;
+        {
+            std::vector<std::pair<int64_t, int>> e;
+            for (int64_t p = 0; p < P; ++p) e.push_back({s.probe_cells[(size_t)p], (int)p});
+            std::sort(e.begin(), e.end());
+            for (auto &x : e) {
+                pst[(size_t)(x.first / 256) + 1]++;
+                pcell.push_back((int)x.first);
+                pslot.push_back(x.second);
+            }
+            for (int64_t b = 0; b < nb; ++b) pst[(size_t)b + 1] += pst[(size_t)b];
+        }
+        int *d_pst = (int *)get(pst.size() * 4);
+        int *d_pcell = (int *)get(pcell.size() * 4);
+        int *d_pslot = (int *)get(pslot.size() * 4);
+        hip_check(hipMemcpyAsync(d_pst, pst.data(), pst.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(d_pcell, pcell.data(), pcell.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(d_pslot, pslot.data(), pslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipStreamSynchronize(s.st), "sync");
+        // ---- backward over segments ----
+        const int dbox[4] = {i0, i1, j0, j1};
+        ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
+        Fused2DCfg fc{s.kcfg.tile[0], s.kcfg.tile[1]};
+        for (int64_t g = nseg - 1; g >= 0; --g) {
+            const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
+            copy_state(s, 0, ck + g * S, false);
+            s.cur = 0;
+            s.n_done = k0;
+            s.n_rec = k0;
+            for (int64_t k = k0; k < k1; ++k) {
+                const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
+                hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
+                                          cap_br + (k - k0) * nd),
+                          "recompute");
+                s.cur = 1 - s.cur;
+                s.n_done += 1;
+                s.n_rec += 1;
+            }
+            const Prob2D p = s.prob2d(0, 0);
+            for (int64_t k = k1 - 1; k >= k0; --k) {
+                const int seed = (k + 1 > n0 && k + 1 <= n1) ? 1 : 0;
+                hip_check(launch_adj2d(p, a, k, dbox, cap_ez + (k - k0) * nd, cap_br + (k - k0) * nd,
+                                       dca, dcb, grad, seed, d_pst, d_pcell, d_pslot, s.rec_dev,
+                                       s.rec_cap, s.st),
+                          "adjoint step");
+            }
+        }
+        hip_check(launch_grad_to_float(grad, grad_dev, nd, s.st), "gradient");
+        // leave the forward state after T steps
+        copy_state(s, 0, fin, false);
+        s.cur = 0;
+        s.n_done = T;
+        s.n_rec = T;
+        hip_check(hipEventRecord(s.ev1, s.st), "event");
+        s.timed = true;
+        s.last_launches = T * 2 + T * 3;
+        hip_check(hipStreamSynchronize(s.st), "sync");
+        for (void *p : tmp) s.al.put(p);
+        tmp.clear();
+        s.kcfg = saved;
+        s.pt_ntiles = -1;
+        s.build_probe_tiles();
+        if (loss_out) *loss_out = loss;
+        return FDTD_OK;
+    } catch (...) {
+        const int rc = status_of_current_exception();
+        if (sp) {
+            (void)hipStreamSynchronize(sp->st);
+            for (void *p : tmp) sp->al.put(p);
+            if (restore_cfg) {
+                sp->kcfg = saved;
+                sp->pt_ntiles = -1;
+            }
+        }
+        return rc;
+    }
+}

@@ -1,0 +1,355 @@
+// Batched form: many independent 2D problems advanced together.
+//
+// Every problem keeps its own double-buffered state and coefficient tables
+// (a Sim).  Problems are grouped by the vector width their row length
+// allows (4, 2 or 1 float per lane); each group has one flat list of
+// wavefront tiles over all of its problems, so one launch per group advances
+// every problem by one step, with the load spread evenly over the tiles
+// whatever the mix of sizes.  Launches read the step number from a device
+// counter, which lets a captured HIP graph of GRAPH_STEPS steps be replayed
+// for any step range.
+#include <algorithm>
+#include <memory>
+
+#include "sim.hpp"
+
+namespace gem {
+
+struct BatchGroup {
+    int V = 1, TX = 16;
+    std::vector<int> probs;
+    BatchTile *tiles = nullptr;
+    int ntiles = 0;
+    int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
+    std::vector<int> tile_base;  // first tile of each problem of the group
+};
+
+}  // namespace gem
+
+struct fdtd_batch {
+    std::vector<std::unique_ptr<fdtd_sim>> hs;  // one single-problem handle per problem
+    std::vector<gem::Sim *> sims;               // &hs[q]->s
+    hipStream_t st = nullptr;
+    hipStream_t cap_st = nullptr;
+    gem::DevAlloc al;
+    std::vector<gem::BatchGroup> groups;
+    gem::Prob2D *probs_dev[2] = {nullptr, nullptr};
+    std::vector<const void *> probs_key[2];
+    int64_t *step_base = nullptr;
+    int64_t n_done = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = 64;
+    bool use_graph = true;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    int64_t last_launches = 0;
+    bool probes_dirty = true;
+
+    ~fdtd_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        al.release_all();
+        sims.clear();
+        hs.clear();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
+    }
+};
+
+namespace gem {
+
+struct BFail {
+    int code;
+    std::string msg;
+};
+
+static void batch_build_probes(fdtd_batch &b) {
+    for (auto &g : b.groups) {
+        std::vector<int> tile_of_entry, cell, slot;
+        std::vector<std::pair<int, int>> ent;  // (tile, index)
+        std::vector<int> cells_all, slots_all;
+        for (size_t qi = 0; qi < g.probs.size(); ++qi) {
+            const Sim &s = *b.sims[(size_t)g.probs[qi]];
+            Fused2DCfg c{g.V, g.TX};
+            for (size_t p = 0; p < s.probe_cells.size(); ++p) {
+                const int i = (int)(s.probe_cells[p] / s.ny), j = (int)(s.probe_cells[p] % s.ny);
+                ent.push_back({g.tile_base[qi] + fused2d_tile_of(s.nx, s.ny, c, i, j), (int)cells_all.size()});
+                cells_all.push_back((int)s.probe_cells[p]);
+                slots_all.push_back((int)p);
+            }
+        }
+        std::stable_sort(ent.begin(), ent.end());
+        std::vector<int> start((size_t)g.ntiles + 1, 0);
+        for (auto &e : ent) {
+            start[(size_t)e.first + 1]++;
+            cell.push_back(cells_all[(size_t)e.second]);
+            slot.push_back(slots_all[(size_t)e.second]);
+        }
+        for (int t = 0; t < g.ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
+        if (cell.empty()) {
+            cell.push_back(0);
+            slot.push_back(0);
+        }
+        b.al.put(g.pt_start);
+        b.al.put(g.pt_cell);
+        b.al.put(g.pt_slot);
+        g.pt_start = (int *)b.al.get(start.size() * 4);
+        g.pt_cell = (int *)b.al.get(cell.size() * 4);
+        g.pt_slot = (int *)b.al.get(slot.size() * 4);
+        hip_check(hipMemcpyAsync(g.pt_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipMemcpyAsync(g.pt_cell, cell.data(), cell.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipMemcpyAsync(g.pt_slot, slot.data(), slot.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipStreamSynchronize(b.st), "sync");
+    }
+    // the captured graph holds the probe-table pointers: capture again
+    if (b.exec) {
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    if (b.graph) {
+        (void)hipGraphDestroy(b.graph);
+        b.graph = nullptr;
+    }
+    b.probes_dirty = false;
+}
+
+// Upload the per-problem kernel descriptors if any pointer they hold moved.
+static void batch_sync_probs(fdtd_batch &b) {
+    const size_t n = b.sims.size();
+    for (int par = 0; par < 2; ++par) {
+        std::vector<Prob2D> h(n);
+        std::vector<const void *> key;
+        for (size_t q = 0; q < n; ++q) {
+            h[q] = b.sims[q]->prob2d(par, 1 - par);
+            key.push_back(h[q].src_vals);
+            key.push_back(h[q].rec);
+            key.push_back((const void *)(intptr_t)h[q].rec_stride);
+            key.push_back((const void *)(intptr_t)h[q].src_len);
+            key.push_back((const void *)(intptr_t)h[q].rec_base);
+            key.push_back((const void *)(intptr_t)h[q].src_idx);
+            key.push_back((const void *)(intptr_t)h[q].np);
+        }
+        if (b.probs_dev[par] && key == b.probs_key[par]) continue;
+        if (!b.probs_dev[par]) b.probs_dev[par] = (Prob2D *)b.al.get(n * sizeof(Prob2D));
+        hip_check(hipMemcpyAsync(b.probs_dev[par], h.data(), n * sizeof(Prob2D), hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipStreamSynchronize(b.st), "sync");
+        b.probs_key[par] = key;
+    }
+}
+
+static void batch_launch_one(fdtd_batch &b, int parity, int k, hipStream_t st) {
+    for (auto &g : b.groups) {
+        ProbeTiles pt{g.pt_start, g.pt_cell, g.pt_slot};
+        hip_check(launch_batch_step(b.probs_dev[parity], g.tiles, g.ntiles, pt, g.V, g.TX, b.step_base, k, st),
+                  "batch step");
+    }
+}
+
+static void batch_capture(fdtd_batch &b) {
+    if (b.exec) return;
+    if (!b.cap_st) hip_check(hipStreamCreateWithFlags(&b.cap_st, hipStreamNonBlocking), "stream");
+    hip_check(hipStreamBeginCapture(b.cap_st, hipStreamCaptureModeRelaxed), "begin capture");
+    for (int k = 0; k < b.graph_steps; ++k) batch_launch_one(b, k & 1, k, b.cap_st);
+    hip_check(launch_advance(b.step_base, b.graph_steps, b.cap_st), "advance");
+    hip_check(hipStreamEndCapture(b.cap_st, &b.graph), "end capture");
+    hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "instantiate");
+}
+
+}  // namespace gem
+
+using namespace gem;
+
+namespace gem {
+int status_of_current_exception();
+}  // namespace gem
+
+extern "C" {
+
+int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDTD_EINVAL;
+    }
+    *out = nullptr;
+    fdtd_batch *b = nullptr;
+    try {
+        if (!descs || n < 1) fail(FDTD_EINVAL, "need at least one problem");
+        b = new fdtd_batch();
+        b->st = (hipStream_t)descs[0].stream;
+        b->al.st = b->st;
+        if (descs[0].allocator) {
+            b->al.a = *descs[0].allocator;
+            b->al.has = true;
+        }
+        for (int q = 0; q < n; ++q) {
+            fdtd_desc d = descs[q];
+            if (d.ndim != 2) fail(FDTD_EINVAL, "batched problems must be 2D (ndim 2)");
+            d.stream = descs[0].stream;
+            d.allocator = descs[0].allocator;
+            b->hs.emplace_back(new fdtd_sim());
+            b->sims.push_back(&b->hs.back()->s);
+            init_sim(*b->sims.back(), &d);
+        }
+        // groups by vector width
+        for (int V : {4, 2, 1}) {
+            BatchGroup g;
+            g.V = V;
+            g.TX = 16;
+            std::vector<BatchTile> tiles;
+            for (int q = 0; q < n; ++q) {
+                const Sim &s = *b->sims[(size_t)q];
+                const int vq = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
+                if (vq != V) continue;
+                g.probs.push_back(q);
+                g.tile_base.push_back((int)tiles.size());
+                const int nsy = (s.ny + 64 * V - 1) / (64 * V);
+                const int ncx = (s.nx + g.TX - 1) / g.TX;
+                for (int cx = 0; cx < ncx; ++cx)
+                    for (int sy = 0; sy < nsy; ++sy) tiles.push_back(BatchTile{q, cx, sy});
+            }
+            if (g.probs.empty()) continue;
+            g.ntiles = (int)tiles.size();
+            g.tiles = (BatchTile *)b->al.get(tiles.size() * sizeof(BatchTile));
+            hip_check(hipMemcpyAsync(g.tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
+                                     hipMemcpyHostToDevice, b->st), "upload");
+            hip_check(hipStreamSynchronize(b->st), "sync");
+            b->groups.push_back(g);
+        }
+        b->step_base = (int64_t *)b->al.get(sizeof(int64_t));
+        hip_check(hipEventCreate(&b->ev0), "event");
+        hip_check(hipEventCreate(&b->ev1), "event");
+        batch_build_probes(*b);
+        *out = b;
+        set_error("");
+        return FDTD_OK;
+    } catch (...) {
+        const int rc = gem::status_of_current_exception();
+        delete b;
+        return rc;
+    }
+}
+
+int fdtd_batch_destroy(fdtd_batch *b) {
+    delete b;
+    return FDTD_OK;
+}
+
+static fdtd_sim *batch_sim(fdtd_batch *b, int32_t q) {
+    if (!b) fail(FDTD_EINVAL, "batch is NULL");
+    if (q < 0 || q >= (int32_t)b->hs.size()) fail(FDTD_EINVAL, "problem index out of range");
+    return b->hs[(size_t)q].get();
+}
+
+int fdtd_batch_set_source(fdtd_batch *b, int32_t problem, const int32_t *ijk, int kind,
+                          const double *params, const float *table, int64_t n_table) {
+    try {
+        fdtd_sim *h = batch_sim(b, problem);
+        const int rc = fdtd_set_source(h, FDTD_EZ, ijk, kind, params, table, n_table);
+        return rc;
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_set_probes(fdtd_batch *b, int32_t problem, const int32_t *ijk, int32_t n) {
+    try {
+        fdtd_sim *h = batch_sim(b, problem);
+        const int rc = fdtd_set_probes(h, FDTD_EZ, ijk, n);
+        if (rc == FDTD_OK) b->probes_dirty = true;
+        return rc;
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_step(fdtd_batch *b, int64_t n) {
+    try {
+        if (!b) fail(FDTD_EINVAL, "batch is NULL");
+        if (n < 0) fail(FDTD_EINVAL, "n must be >= 0");
+        for (auto &sp : b->sims) {
+            sp->ensure_source(b->n_done + n);
+            sp->ensure_rec(sp->n_rec + n);
+        }
+        if (b->probes_dirty) batch_build_probes(*b);
+        batch_sync_probs(*b);
+        hip_check(hipMemcpyAsync(b->step_base, &b->n_done, sizeof(int64_t), hipMemcpyHostToDevice, b->st), "upload");
+        hip_check(hipStreamSynchronize(b->st), "sync");
+        b->last_launches = 0;
+        hip_check(hipEventRecord(b->ev0, b->st), "event");
+        int64_t k = 0;
+        const int64_t ng = (int64_t)b->groups.size();
+        // align to an even step so that graph replays start on buffer set 0
+        while (k < n && ((b->n_done + k) & 1)) {
+            batch_launch_one(*b, (int)((b->n_done + k) & 1), (int)k, b->st);
+            b->last_launches += ng;
+            ++k;
+        }
+        if (k > 0) hip_check(launch_advance(b->step_base, k, b->st), "advance");
+        const int64_t reps = b->use_graph ? (n - k) / b->graph_steps : 0;
+        if (reps > 0) {
+            batch_capture(*b);
+            for (int64_t r = 0; r < reps; ++r) hip_check(hipGraphLaunch(b->exec, b->st), "graph launch");
+            b->last_launches += reps * (b->graph_steps * ng + 1);
+        }
+        const int64_t k2 = k + reps * b->graph_steps;
+        for (int64_t q = k2; q < n; ++q) {
+            batch_launch_one(*b, (int)((b->n_done + q) & 1), (int)(q - k2), b->st);
+            b->last_launches += ng;
+        }
+        hip_check(hipEventRecord(b->ev1, b->st), "event");
+        b->timed = true;
+        b->n_done += n;
+        for (auto &sp : b->sims) {
+            sp->n_done = b->n_done;
+            if (!sp->probe_cells.empty()) sp->n_rec += n;
+            sp->cur = (int)(b->n_done & 1);
+        }
+        return FDTD_OK;
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_probe(fdtd_batch *b, int32_t problem, float *out, int64_t cap, int64_t *n_recorded) {
+    try {
+        return fdtd_probe(batch_sim(b, problem), out, cap, n_recorded);
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_get_field(fdtd_batch *b, int32_t problem, int component, void *dst, int dst_on_device) {
+    try {
+        return fdtd_get_field(batch_sim(b, problem), component, dst, dst_on_device);
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_last_step_time(fdtd_batch *b, float *ms, int64_t *launches) {
+    try {
+        if (!b || !ms) fail(FDTD_EINVAL, "NULL argument");
+        if (!b->timed) fail(FDTD_ESTATE, "no fdtd_batch_step call yet");
+        hip_check(hipEventSynchronize(b->ev1), "sync");
+        hip_check(hipEventElapsedTime(ms, b->ev0, b->ev1), "elapsed");
+        if (launches) *launches = b->last_launches;
+        return FDTD_OK;
+    } catch (...) {
+        return gem::status_of_current_exception();
+    }
+}
+
+int fdtd_batch_cells(const fdtd_batch *b, int64_t *cells) {
+    if (!b || !cells) {
+        set_error("NULL argument");
+        return FDTD_EINVAL;
+    }
+    int64_t c = 0;
+    for (auto &sp : b->sims) c += sp->ncell;
+    *cells = c;
+    return FDTD_OK;
+}
+
+}  // extern "C"

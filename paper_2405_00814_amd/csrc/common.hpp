@@ -1,0 +1,156 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gemfdtd.h"
+
+namespace gem {
+
+// ---------------------------------------------------------------------------
+// Per-axis CPML tables (device, float32, length n), with 1/d folded in:
+//   E-type difference along the axis at index i: D = F[i] - F[i-1]
+//     psi <- bE[i] psi + cE[i] D;   term = kE[i] D + psi
+//   H-type difference at index i:               D = F[i+1] - F[i]
+//     psi <- bH[i] psi + cH[i] D;   term = kH[i] D + psi
+// with kE = 1/(kappa_E d), cE = c_E / d (same for H).  Cells outside the two
+// slabs have b = 1, c = 0 and carry no psi storage.
+// slab index: i < lo -> i; i >= n - hi -> lo + i - (n - hi); else -1.
+// ---------------------------------------------------------------------------
+struct AxisDev {
+    const float *kE, *bE, *cE, *kH, *bH, *cH;
+    int n, lo, hi;
+};
+
+__host__ __device__ inline int slab_index(const AxisDev &a, int i) {
+    if (i < a.lo) return i;
+    if (i >= a.n - a.hi) return a.lo + i - (a.n - a.hi);
+    return -1;
+}
+
+// 2D TMz state: three fields and four psi arrays.
+//   psi_hx  [nx][sy]  (H-type, y)      psi_ezy [nx][sy]  (E-type, y)
+//   psi_hy  [sx][ny]  (H-type, x)      psi_ezx [sx][ny]  (E-type, x)
+// with sx = x.lo + x.hi, sy = y.lo + y.hi.
+struct State2D {
+    float *ez, *hx, *hy;
+    float *psi_hx, *psi_hy, *psi_ezx, *psi_ezy;
+};
+
+// A 2D problem as the kernels see it.
+struct Prob2D {
+    int nx, ny;
+    const float *ca;   // nullptr => 1
+    const float *cb;
+    const float *db;   // nullptr => db0
+    float db0;
+    AxisDev x, y;
+    State2D s0;        // state read (n)
+    State2D s1;        // state written (n+1); equal to s0 for in-place kernels
+    int64_t src_idx;   // -1 => none
+    const float *src_vals;  // device table, indexed by absolute step
+    int64_t src_len;
+    int np;
+    const int *probe_idx;   // [np] linear cell index
+    int probe_comp;         // FDTD_EZ, FDTD_HX or FDTD_HY
+    float *rec;             // [np][rec_stride]
+    int64_t rec_stride;
+    int64_t rec_base;       // record index = step - rec_base
+};
+
+// 3D state: six fields and twelve psi arrays; psi_<F><a> lives in the slab
+// of axis a: x-slab [sx][ny][nz], y-slab [nx][sy][nz], z-slab [nx][ny][sz].
+enum { PSI_HXY, PSI_HXZ, PSI_HYZ, PSI_HYX, PSI_HZX, PSI_HZY,
+       PSI_EXY, PSI_EXZ, PSI_EYZ, PSI_EYX, PSI_EZX, PSI_EZY, NPSI3 };
+
+struct State3D {
+    float *f[6];
+    float *psi[NPSI3];
+};
+
+struct Prob3D {
+    int nx, ny, nz;
+    const float *ca, *cb, *db;
+    float db0;
+    AxisDev x, y, z;
+    State3D s0, s1;
+    int64_t src_idx;
+    int src_comp;
+    const float *src_vals;
+    int64_t src_len;
+    int np;
+    int probe_comp;
+    const int64_t *probe_idx;
+    float *rec;
+    int64_t rec_stride;
+    int64_t rec_base;
+};
+
+// Probes grouped by tile: tile t owns sorted entries [start[t], start[t+1]).
+struct ProbeTiles {
+    const int *start;   // [ntiles + 1]
+    const int *cell;    // [np] per entry: packed (i, j[, k]) as linear index
+    const int *slot;    // [np] original probe index
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All enqueue on `st`.
+// ---------------------------------------------------------------------------
+hipError_t launch_2d_ref(const Prob2D &p, int64_t step, hipStream_t st);
+struct Fused2DCfg { int V; int TX; };
+hipError_t launch_2d_fused(const Prob2D &p, const Fused2DCfg &c, const ProbeTiles &pt,
+                           int64_t step, hipStream_t st, const int *design, float *cap_ez,
+                           float *cap_br);
+int fused2d_ntiles(int nx, int ny, const Fused2DCfg &c);
+int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
+bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
+
+hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
+struct Fused3DCfg { int TJ; int TX; };
+hipError_t launch_3d_fused(const Prob3D &p, const Fused3DCfg &c, const ProbeTiles &pt,
+                           int64_t step, hipStream_t st);
+int fused3d_ntiles(int nx, int ny, int nz, const Fused3DCfg &c);
+int fused3d_tile_of(int nx, int ny, int nz, const Fused3DCfg &c, int i, int j, int k);
+bool fused3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);
+
+hipError_t launch_nonfinite(const float *a, int64_t n, int *flag, hipStream_t st);
+
+// CSR layer: y[dst[r]] = sum_{e in row r} w[e] * x[col[e]] for r < nrows.
+hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,
+                            const int *dst, const float *x, float *y, int nrows,
+                            hipStream_t st);
+// Soft source and probes on a node vector.
+hipError_t launch_node_source_probe(float *x, int64_t src_node, const float *src_vals,
+                                    int64_t src_len, int64_t step, int np,
+                                    const int *probe_node, float *rec, int64_t rec_stride,
+                                    int64_t rec_index, hipStream_t st);
+
+// Batched 2D: one launch advances every problem by one step.
+struct BatchTile { int prob; int cx; int sy; };
+hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, int ntiles,
+                             const ProbeTiles &pt, int V, int TX, const int64_t *step_base, int k,
+                             hipStream_t st);
+hipError_t launch_advance(int64_t *step_base, int64_t by, hipStream_t st);
+
+// Adjoint 2D kernels (see adjoint.hip).
+struct Adj2D {
+    float *ez, *hx, *hy, *psi_hx, *psi_hy, *psi_ezx, *psi_ezy;
+    float *gx, *gy, *ex, *ey;   // full-grid temporaries
+};
+hipError_t launch_adj2d(const Prob2D &p, const Adj2D &a, int64_t k, const int *design,
+                        const float *cap_ez, const float *cap_br, const float *dca,
+                        const float *dcb, double *grad, int seed_on, const int *pb_start,
+                        const int *pb_cell, const int *pb_slot, const float *rec,
+                        int64_t rec_stride, hipStream_t st);
+hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+
+}  // namespace gem

@@ -1,0 +1,262 @@
+// Builder of the explicit graph (Prop. 1) and its stepping.
+//
+// Node order: the paper's index maps, in the TMz relabelling of its TE form
+// (paper z -> y, Hz -> Hy, Ey -> Ez):
+//   Ez(i,j): t = 2i + 1 + nx(3j + 1)
+//   Hx(i,j): u = i + 3 j nx
+//   Hy(i,j): q = 2i + nx(3j + 1)
+// followed by the CPML auxiliary values (psi_hx, psi_hy, psi_ezx, psi_ezy in
+// their slab layouts).  Neighbourhoods: an Ez node gathers {itself, Hx(i,j),
+// Hx(i,j-1), Hy(i,j), Hy(i-1,j)} (as printed in Prop. 1); Hx gathers
+// {itself, Ez(i,j), Ez(i,j+1)} and Hy gathers {itself, Ez(i,j), Ez(i+1,j)}
+// (forward offsets: with E owned at the lower cell corner this is the
+// consistent staggering).  Each layer is two CSR sweeps, both in place:
+// first the auxiliary rows (psi <- b psi + c D), then the field rows, whose
+// weights multiply the just-updated psi.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "sim.hpp"
+
+namespace gem {
+
+namespace {
+
+struct RowBuilder {
+    std::vector<int> rowptr{0}, col, dst;
+    std::vector<float> w;
+    void edge(int64_t c, double v) {
+        col.push_back((int)c);
+        w.push_back((float)v);
+    }
+    void end_row(int64_t d) {
+        dst.push_back((int)d);
+        rowptr.push_back((int)col.size());
+    }
+};
+
+template <class T>
+T *up(DevAlloc &al, const std::vector<T> &h, hipStream_t st, int64_t &bytes) {
+    T *d = (T *)al.get(std::max<size_t>(1, h.size()) * sizeof(T));
+    if (!h.empty())
+        hip_check(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    bytes += (int64_t)h.size() * sizeof(T);
+    return d;
+}
+
+}  // namespace
+
+static void free_layer(Sim &s, Sim::Graph::Layer &L) {
+    s.al.put(L.rowptr);
+    s.al.put(L.col);
+    s.al.put(L.dst);
+    s.al.put(L.w);
+    L = Sim::Graph::Layer{};
+}
+
+void build_graph(Sim &s) {
+    const int nx = s.nx, ny = s.ny;
+    auto t = [&](int i, int j) -> int64_t { return 2LL * i + 1 + (int64_t)nx * (3LL * j + 1); };
+    auto u = [&](int i, int j) -> int64_t { return (int64_t)i + 3LL * j * nx; };
+    auto q = [&](int i, int j) -> int64_t { return 2LL * i + (int64_t)nx * (3LL * j + 1); };
+    const int64_t N = (int64_t)nx * ny;
+    const int64_t nmain = 3 * N;
+    const AxisHost &X = s.axh[0], &Y = s.axh[1];
+    const int sx = X.lo + X.hi, sy = Y.lo + Y.hi;
+    const int64_t o_hx = nmain, o_hy = o_hx + (int64_t)nx * sy, o_ezx = o_hy + (int64_t)sx * ny,
+                  o_ezy = o_ezx + (int64_t)sx * ny;
+    const int64_t nnodes = o_ezy + (int64_t)nx * sy;
+    if (nnodes >= ((int64_t)1 << 31)) fail(FDTD_EINVAL, "graph too large for 32-bit node indices");
+    auto xs = [&](int i) { return i < X.lo ? i : (i >= nx - X.hi ? X.lo + i - (nx - X.hi) : -1); };
+    auto ys = [&](int j) { return j < Y.lo ? j : (j >= ny - Y.hi ? Y.lo + j - (ny - Y.hi) : -1); };
+
+    // coefficients per cell (same folding as the implicit stepper, in double)
+    auto cb_of = [&](int64_t c) {
+        const double er = s.eps_r.empty() ? 1.0 : s.eps_r[(size_t)c];
+        const double sg = s.sigma.empty() ? 0.0 : s.sigma[(size_t)c];
+        const double eps = kEps0 * er, sh = sg * s.dt / (2.0 * eps);
+        return (s.dt / eps) / (1.0 + sh);
+    };
+    auto ca_of = [&](int64_t c) {
+        const double er = s.eps_r.empty() ? 1.0 : s.eps_r[(size_t)c];
+        const double sg = s.sigma.empty() ? 0.0 : s.sigma[(size_t)c];
+        const double sh = sg * s.dt / (2.0 * kEps0 * er);
+        return (1.0 - sh) / (1.0 + sh);
+    };
+    auto db_of = [&](int64_t c) { return s.dt / (kMu0 * (s.mu_r.empty() ? 1.0 : s.mu_r[(size_t)c])); };
+
+    RowBuilder ha, hm, ea, em;
+    // Rows are emitted in increasing destination-node order within each sweep.
+    // H layer, auxiliary rows
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int jj = ys(j);
+            if (jj >= 0) {
+                ha.edge(o_hx + (int64_t)i * sy + jj, Y.bH[j]);
+                ha.edge(t(i, j), -(double)Y.cH[j]);
+                if (j + 1 < ny) ha.edge(t(i, j + 1), Y.cH[j]);
+                ha.end_row(o_hx + (int64_t)i * sy + jj);
+            }
+        }
+    for (int i = 0; i < nx; ++i) {
+        const int ii = xs(i);
+        if (ii < 0) continue;
+        for (int j = 0; j < ny; ++j) {
+            ha.edge(o_hy + (int64_t)ii * ny + j, X.bH[i]);
+            ha.edge(t(i, j), -(double)X.cH[i]);
+            if (i + 1 < nx) ha.edge(t(i + 1, j), X.cH[i]);
+            ha.end_row(o_hy + (int64_t)ii * ny + j);
+        }
+    }
+    // H layer, field rows (Hx then Hy of each Prop. 1 row k = j)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            const int64_t c = (int64_t)i * ny + j;
+            const double db = db_of(c);
+            hm.edge(u(i, j), 1.0);
+            hm.edge(t(i, j), db * Y.kH[j]);
+            if (j + 1 < ny) hm.edge(t(i, j + 1), -db * Y.kH[j]);
+            const int jj = ys(j);
+            if (jj >= 0) hm.edge(o_hx + (int64_t)i * sy + jj, -db);
+            hm.end_row(u(i, j));
+        }
+        for (int i = 0; i < nx; ++i) {
+            const int64_t c = (int64_t)i * ny + j;
+            const double db = db_of(c);
+            hm.edge(q(i, j), 1.0);
+            hm.edge(t(i, j), -db * X.kH[i]);
+            if (i + 1 < nx) hm.edge(t(i + 1, j), db * X.kH[i]);
+            const int ii = xs(i);
+            if (ii >= 0) hm.edge(o_hy + (int64_t)ii * ny + j, db);
+            hm.end_row(q(i, j));
+        }
+    }
+    // E layer, auxiliary rows (cells the E layer updates: i >= 1, j >= 1)
+    for (int i = 1; i < nx; ++i) {
+        const int ii = xs(i);
+        if (ii < 0) continue;
+        for (int j = 1; j < ny; ++j) {
+            ea.edge(o_ezx + (int64_t)ii * ny + j, X.bE[i]);
+            ea.edge(q(i, j), X.cE[i]);
+            ea.edge(q(i - 1, j), -(double)X.cE[i]);
+            ea.end_row(o_ezx + (int64_t)ii * ny + j);
+        }
+    }
+    for (int i = 1; i < nx; ++i)
+        for (int j = 1; j < ny; ++j) {
+            const int jj = ys(j);
+            if (jj < 0) continue;
+            ea.edge(o_ezy + (int64_t)i * sy + jj, Y.bE[j]);
+            ea.edge(u(i, j), Y.cE[j]);
+            ea.edge(u(i, j - 1), -(double)Y.cE[j]);
+            ea.end_row(o_ezy + (int64_t)i * sy + jj);
+        }
+    // E layer, field rows
+    for (int j = 1; j < ny; ++j)
+        for (int i = 1; i < nx; ++i) {
+            const int64_t c = (int64_t)i * ny + j;
+            const double cbv = cb_of(c);
+            em.edge(t(i, j), s.lossy ? ca_of(c) : 1.0);
+            em.edge(u(i, j), -cbv * Y.kE[j]);
+            em.edge(u(i, j - 1), cbv * Y.kE[j]);
+            em.edge(q(i, j), cbv * X.kE[i]);
+            em.edge(q(i - 1, j), -cbv * X.kE[i]);
+            const int ii = xs(i), jj = ys(j);
+            if (ii >= 0) em.edge(o_ezx + (int64_t)ii * ny + j, cbv);
+            if (jj >= 0) em.edge(o_ezy + (int64_t)i * sy + jj, -cbv);
+            em.end_row(t(i, j));
+        }
+
+    Sim::Graph &g = s.g;
+    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) free_layer(s, *L);
+    g.bytes = 0;
+    auto put = [&](Sim::Graph::Layer &L, RowBuilder &b) {
+        L.nrows = (int)b.dst.size();
+        L.nnz = (int64_t)b.col.size();
+        L.rowptr = up(s.al, b.rowptr, s.st, g.bytes);
+        L.col = up(s.al, b.col, s.st, g.bytes);
+        L.dst = up(s.al, b.dst, s.st, g.bytes);
+        L.w = up(s.al, b.w, s.st, g.bytes);
+        hip_check(hipStreamSynchronize(s.st), "sync");
+        b = RowBuilder{};
+    };
+    put(g.h_aux, ha);
+    put(g.h_main, hm);
+    put(g.e_aux, ea);
+    put(g.e_main, em);
+    g.nmain = nmain;
+    g.nnodes = nnodes;
+    if (!g.x) g.x = (float *)s.al.get((size_t)nnodes * 4);
+    g.ez_node.resize((size_t)N);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) g.ez_node[(size_t)i * ny + j] = t(i, j);
+    // the implicit-stepper state buffers are not used by the graph form
+    for (int set = 0; set < 2; ++set) {
+        for (int c = 0; c < 6; ++c) {
+            s.al.put(s.f[set][c]);
+            s.f[set][c] = nullptr;
+        }
+        for (int a = 0; a < NPSI3; ++a) {
+            s.al.put(s.psi[set][a]);
+            s.psi[set][a] = nullptr;
+        }
+    }
+    hip_check(hipStreamSynchronize(s.st), "sync");
+}
+
+void graph_refold(Sim &s) { build_graph(s); }
+
+void graph_set_source_probes(Sim &s) {
+    Sim::Graph &g = s.g;
+    g.src_node = s.src_idx >= 0 ? g.ez_node[(size_t)s.src_idx] : -1;
+    s.al.put(g.probe_node);
+    g.probe_node = nullptr;
+    if (!s.probe_cells.empty()) {
+        std::vector<int> pn(s.probe_cells.size());
+        for (size_t p = 0; p < pn.size(); ++p) pn[p] = (int)g.ez_node[(size_t)s.probe_cells[p]];
+        int64_t dummy = 0;
+        g.probe_node = up(s.al, pn, s.st, dummy);
+        hip_check(hipStreamSynchronize(s.st), "sync");
+    }
+}
+
+void graph_step(Sim &s, int64_t step) {
+    Sim::Graph &g = s.g;
+    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) {
+        hip_check(launch_csr_layer(L->rowptr, L->col, L->w, L->dst, g.x, g.x, L->nrows, s.st), "csr layer");
+        s.last_launches += 1;
+    }
+    hip_check(launch_node_source_probe(g.x, g.src_node, s.src_dev, s.src_len, step,
+                                       (int)s.probe_cells.size(), g.probe_node, s.rec_dev, s.rec_cap,
+                                       step - (s.n_done - s.n_rec), s.st),
+              "source/probe");
+    if (g.src_node >= 0 || !s.probe_cells.empty()) s.last_launches += 1;
+}
+
+static int64_t node_of(const Sim &s, int comp, int i, int j) {
+    const int nx = s.nx;
+    if (comp == FDTD_EZ) return 2LL * i + 1 + (int64_t)nx * (3LL * j + 1);
+    if (comp == FDTD_HX) return (int64_t)i + 3LL * j * nx;
+    return 2LL * i + (int64_t)nx * (3LL * j + 1);
+}
+
+void graph_get_field(Sim &s, int comp, float *host) {
+    std::vector<float> x((size_t)s.g.nnodes);
+    hip_check(hipMemcpyAsync(x.data(), s.g.x, x.size() * 4, hipMemcpyDeviceToHost, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    for (int i = 0; i < s.nx; ++i)
+        for (int j = 0; j < s.ny; ++j) host[(size_t)i * s.ny + j] = x[(size_t)node_of(s, comp, i, j)];
+}
+
+void graph_set_field(Sim &s, int comp, const float *host) {
+    std::vector<float> x((size_t)s.g.nnodes);
+    hip_check(hipMemcpyAsync(x.data(), s.g.x, x.size() * 4, hipMemcpyDeviceToHost, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    for (int i = 0; i < s.nx; ++i)
+        for (int j = 0; j < s.ny; ++j) x[(size_t)node_of(s, comp, i, j)] = host[(size_t)i * s.ny + j];
+    hip_check(hipMemcpyAsync(s.g.x, x.data(), x.size() * 4, hipMemcpyHostToDevice, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+}
+
+}  // namespace gem

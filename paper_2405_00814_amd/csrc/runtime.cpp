@@ -1,0 +1,1133 @@
+// Host runtime behind the C ABI: validation, edge-weight folding (Prop. 1
+// weights as per-cell and per-axis tables), device state, stepping, I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+
+#include "sim.hpp"
+
+namespace gem {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+void fail(int code, const std::string &msg) { throw Fail{code, msg}; }
+
+// Status for the exception being handled (call from a catch block only).
+int status_of_current_exception() {
+    try {
+        throw;
+    } catch (const Fail &f) {
+        set_error(f.msg);
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return FDTD_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FDTD_EDEVICE;
+    }
+}
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) fail(FDTD_ENOMEM, std::string(what) + ": out of device memory");
+        fail(FDTD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device memory
+// ---------------------------------------------------------------------------
+void *DevAlloc::get(size_t bytes) {
+    if (bytes == 0) bytes = 4;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (has) {
+        p = a.alloc(a.ctx, bytes, (void *)st);
+        if (!p) fail(FDTD_ENOMEM, "allocator returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(FDTD_ENOMEM, "hipMalloc failed");
+        }
+    }
+    blocks.push_back(p);
+    hip_check(hipMemsetAsync(p, 0, bytes, st), "hipMemsetAsync");
+    return p;
+}
+
+void DevAlloc::put(void *p) {
+    if (!p) return;
+    auto it = std::find(blocks.begin(), blocks.end(), p);
+    if (it == blocks.end()) return;
+    blocks.erase(it);
+    if (has) a.free(a.ctx, p, (void *)st);
+    else {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(p);
+    }
+}
+
+void DevAlloc::release_all() {
+    if (blocks.empty()) return;
+    (void)hipStreamSynchronize(st);
+    for (void *p : blocks) {
+        if (has) a.free(a.ctx, p, (void *)st);
+        else (void)hipFree(p);
+    }
+    blocks.clear();
+}
+
+template <class T>
+static T *dev_upload(DevAlloc &al, const T *h, size_t n, hipStream_t st) {
+    T *d = (T *)al.get(n * sizeof(T));
+    if (n) hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    // callers pass short-lived host vectors: finish the copy before returning
+    hip_check(hipStreamSynchronize(st), "upload sync");
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// CPML axis tables.  rho is the normalised depth into the layer (1 at the
+// PEC wall), sampled at x = i (E-type) and x = i + 1/2 (H-type).
+// ---------------------------------------------------------------------------
+AxisHost build_axis(int n, int lo, int hi, double d, double dt, const fdtd_cpml &cp) {
+    AxisHost A;
+    A.n = n;
+    A.lo = lo;
+    A.hi = hi;
+    const double eta0 = std::sqrt(kMu0 / kEps0);
+    const double m = cp.m;
+    const double smax = cp.sigma_max > 0 ? cp.sigma_max : 0.8 * (m + 1.0) / (eta0 * d);
+    for (int half = 0; half < 2; ++half) {
+        std::vector<float> &K = half ? A.kH : A.kE;
+        std::vector<float> &B = half ? A.bH : A.bE;
+        std::vector<float> &Cc = half ? A.cH : A.cE;
+        K.resize(n);
+        B.resize(n);
+        Cc.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const double x = i + (half ? 0.5 : 0.0);
+            double rho = 0.0;
+            if (lo > 0 && x < lo) rho = (lo - x) / lo;
+            if (hi > 0 && x > n - hi) rho = std::max(rho, (x - (n - hi)) / hi);
+            double kap = 1.0, b = 1.0, c = 0.0;
+            if (rho > 0.0) {
+                const double g = std::pow(rho, m);
+                const double sg = smax * g;
+                kap = 1.0 + (cp.kappa_max - 1.0) * g;
+                const double al = cp.alpha_max * std::pow(1.0 - rho, cp.m_alpha);
+                b = std::exp(-(sg / kap + al) * dt / kEps0);
+                c = (sg > 0.0) ? sg * (b - 1.0) / (kap * (sg + kap * al)) : 0.0;
+            }
+            K[i] = (float)(1.0 / (kap * d));
+            B[i] = (float)b;
+            Cc[i] = (float)(c / d);
+        }
+    }
+    return A;
+}
+
+AxisDev upload_axis(DevAlloc &al, const AxisHost &h, hipStream_t st) {
+    AxisDev a{};
+    a.n = h.n;
+    a.lo = h.lo;
+    a.hi = h.hi;
+    a.kE = dev_upload(al, h.kE.data(), h.n, st);
+    a.bE = dev_upload(al, h.bE.data(), h.n, st);
+    a.cE = dev_upload(al, h.cE.data(), h.n, st);
+    a.kH = dev_upload(al, h.kH.data(), h.n, st);
+    a.bH = dev_upload(al, h.bH.data(), h.n, st);
+    a.cH = dev_upload(al, h.cH.data(), h.n, st);
+    return a;
+}
+
+double source_sample(int kind, const double *par, double dt, int64_t n) {
+    const double t = (double)(n + 1) * dt;
+    if (kind == FDTD_SRC_GAUSSIAN) {
+        const double u = (t - par[1]) / par[2];
+        return par[0] * std::exp(-u * u);
+    }
+    if (kind == FDTD_SRC_RICKER) {
+        double a = kPi * par[2] * (t - par[1]);
+        a *= a;
+        return par[0] * (1.0 - 2.0 * a) * std::exp(-a);
+    }
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Sim
+// ---------------------------------------------------------------------------
+Sim::~Sim() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    al.release_all();
+}
+
+Prob2D Sim::prob2d(int si, int so) const {
+    Prob2D p{};
+    p.nx = nx;
+    p.ny = ny;
+    p.ca = lossy ? ca : nullptr;
+    p.cb = cb;
+    p.db = mumap ? db : nullptr;
+    p.db0 = db0;
+    p.x = ax[0];
+    p.y = ax[1];
+    p.s0 = State2D{f[si][FDTD_EZ], f[si][FDTD_HX], f[si][FDTD_HY], psi[si][0], psi[si][1], psi[si][2], psi[si][3]};
+    p.s1 = State2D{f[so][FDTD_EZ], f[so][FDTD_HX], f[so][FDTD_HY], psi[so][0], psi[so][1], psi[so][2], psi[so][3]};
+    p.src_idx = src_idx;
+    p.src_vals = src_dev;
+    p.src_len = src_len;
+    p.np = (int)probe_cells.size();
+    p.probe_idx = probe_dev;
+    p.probe_comp = probe_comp;
+    p.rec = rec_dev;
+    p.rec_stride = rec_cap;
+    p.rec_base = n_done - n_rec;
+    return p;
+}
+
+Prob3D Sim::prob3d(int si, int so) const {
+    Prob3D p{};
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    p.ca = lossy ? ca : nullptr;
+    p.cb = cb;
+    p.db = mumap ? db : nullptr;
+    p.db0 = db0;
+    p.x = ax[0];
+    p.y = ax[1];
+    p.z = ax[2];
+    for (int c = 0; c < 6; ++c) {
+        p.s0.f[c] = f[si][c];
+        p.s1.f[c] = f[so][c];
+    }
+    for (int a = 0; a < NPSI3; ++a) {
+        p.s0.psi[a] = psi[si][a];
+        p.s1.psi[a] = psi[so][a];
+    }
+    p.src_idx = src_idx;
+    p.src_comp = src_comp;
+    p.src_vals = src_dev;
+    p.src_len = src_len;
+    p.np = (int)probe_cells.size();
+    p.probe_comp = probe_comp;
+    p.probe_idx = probe_dev64;
+    p.rec = rec_dev;
+    p.rec_stride = rec_cap;
+    p.rec_base = n_done - n_rec;
+    return p;
+}
+
+void Sim::ensure_source(int64_t upto) {
+    if (src_idx < 0 || src_kind == FDTD_SRC_TABLE) return;
+    if (upto <= src_cap) return;
+    int64_t cap = std::max<int64_t>({upto, 2 * src_cap, 4096});
+    std::vector<float> h((size_t)cap);
+    for (int64_t n = 0; n < cap; ++n) h[(size_t)n] = (float)source_sample(src_kind, src_par, dt, n);
+    float *d = dev_upload(al, h.data(), (size_t)cap, st);
+    al.put(src_dev);
+    src_dev = d;
+    src_cap = cap;
+    src_len = cap;
+}
+
+void Sim::ensure_rec(int64_t upto) {
+    const int64_t P = (int64_t)probe_cells.size();
+    if (P == 0 || upto <= rec_cap) return;
+    const int64_t cap = std::max<int64_t>({upto, 2 * rec_cap, 1024});
+    float *d = (float *)al.get((size_t)(P * cap) * sizeof(float));
+    if (rec_dev && n_rec > 0)
+        hip_check(hipMemcpy2DAsync(d, cap * sizeof(float), rec_dev, rec_cap * sizeof(float),
+                                   n_rec * sizeof(float), P, hipMemcpyDeviceToDevice, st),
+                  "record copy");
+    al.put(rec_dev);
+    rec_dev = d;
+    rec_cap = cap;
+}
+
+static void cfg_tiles(const Sim &s, int &a, int &b) {
+    a = s.kcfg.tile[0];
+    b = s.kcfg.tile[1];
+}
+
+void Sim::build_probe_tiles() {
+    if (kcfg.variant != 2 || is_graph) return;
+    int a, b;
+    cfg_tiles(*this, a, b);
+    if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
+        pt_start)
+        return;
+    int ntiles;
+    std::vector<int> tile(probe_cells.size());
+    if (ndim == 2) {
+        Fused2DCfg c{a, b};
+        ntiles = fused2d_ntiles(nx, ny, c);
+        for (size_t q = 0; q < probe_cells.size(); ++q) {
+            const int i = (int)(probe_cells[q] / ny), j = (int)(probe_cells[q] % ny);
+            tile[q] = fused2d_tile_of(nx, ny, c, i, j);
+        }
+    } else {
+        Fused3DCfg c{a, b};
+        ntiles = fused3d_ntiles(nx, ny, nz, c);
+        for (size_t q = 0; q < probe_cells.size(); ++q) {
+            const int64_t cell = probe_cells[q];
+            const int i = (int)(cell / ((int64_t)ny * nz));
+            const int j = (int)((cell / nz) % ny);
+            const int k = (int)(cell % nz);
+            tile[q] = fused3d_tile_of(nx, ny, nz, c, i, j, k);
+        }
+    }
+    std::vector<int> order(probe_cells.size());
+    for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return tile[u] < tile[v]; });
+    std::vector<int> start((size_t)ntiles + 1, 0), cell(order.size()), slot(order.size());
+    for (size_t q = 0; q < order.size(); ++q) {
+        cell[q] = (int)probe_cells[order[q]];
+        slot[q] = order[q];
+        start[(size_t)tile[order[q]] + 1]++;
+    }
+    for (int t = 0; t < ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
+    al.put(pt_start);
+    al.put(pt_cell);
+    al.put(pt_slot);
+    pt_start = dev_upload(al, start.data(), start.size(), st);
+    pt_cell = dev_upload(al, cell.data(), std::max<size_t>(cell.size(), 1), st);
+    pt_slot = dev_upload(al, slot.data(), std::max<size_t>(slot.size(), 1), st);
+    pt_ntiles = ntiles;
+    pt_cfg[0] = a;
+    pt_cfg[1] = b;
+    pt_cfg[2] = (int)probe_cells.size();
+}
+
+
+void Sim::launch_step(int64_t step) {
+    if (is_graph) {
+        graph_step(*this, step);
+        return;
+    }
+    if (kcfg.variant == 1) {
+        if (ndim == 2) hip_check(launch_2d_ref(prob2d(cur, cur), step, st), "2d reference step");
+        else hip_check(launch_3d_ref(prob3d(cur, cur), step, st), "3d reference step");
+        last_launches += 2 + (probe_cells.empty() ? 0 : 1);
+        return;
+    }
+    ProbeTiles pt{pt_start, pt_cell, pt_slot};
+    if (ndim == 2) {
+        Fused2DCfg c{kcfg.tile[0], kcfg.tile[1]};
+        hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
+                  "2d fused step");
+    } else {
+        Fused3DCfg c{kcfg.tile[0], kcfg.tile[1]};
+        hip_check(launch_3d_fused(prob3d(cur, 1 - cur), c, pt, step, st), "3d fused step");
+    }
+    cur = 1 - cur;
+    last_launches += 1;
+}
+
+void Sim::zero_state() {
+    for (int s = 0; s < 2; ++s) {
+        for (int c = 0; c < 6; ++c)
+            if (f[s][c]) hip_check(hipMemsetAsync(f[s][c], 0, (size_t)ncell * 4, st), "memset");
+        for (int a = 0; a < NPSI3; ++a)
+            if (psi[s][a]) hip_check(hipMemsetAsync(psi[s][a], 0, (size_t)psi_len[a] * 4, st), "memset");
+    }
+    if (is_graph && g.x) hip_check(hipMemsetAsync(g.x, 0, (size_t)g.nnodes * 4, st), "memset");
+    cur = 0;
+    n_done = 0;
+    n_rec = 0;
+}
+
+// Fold eps_r, sigma, mu_r into Ca, Cb, Db (double, rounded once) and upload.
+void Sim::refold(int64_t c0, int64_t c1) {
+    (void)c0;
+    (void)c1;
+    std::vector<float> hcb((size_t)ncell), hca, hdb;
+    if (lossy) hca.resize((size_t)ncell);
+    for (int64_t c = 0; c < ncell; ++c) {
+        const double er = eps_r.empty() ? 1.0 : eps_r[(size_t)c];
+        const double sg = sigma.empty() ? 0.0 : sigma[(size_t)c];
+        const double eps = kEps0 * er;
+        const double sh = sg * dt / (2.0 * eps);
+        hcb[(size_t)c] = (float)((dt / eps) / (1.0 + sh));
+        if (lossy) hca[(size_t)c] = (float)((1.0 - sh) / (1.0 + sh));
+    }
+    if (!cb) cb = (float *)al.get((size_t)ncell * 4);
+    hip_check(hipMemcpyAsync(cb, hcb.data(), (size_t)ncell * 4, hipMemcpyHostToDevice, st), "cb");
+    if (lossy) {
+        if (!ca) ca = (float *)al.get((size_t)ncell * 4);
+        hip_check(hipMemcpyAsync(ca, hca.data(), (size_t)ncell * 4, hipMemcpyHostToDevice, st), "ca");
+    }
+    db0 = (float)(dt / (kMu0 * (mu_r.empty() ? 1.0 : mu_r[0])));
+    if (mumap) {
+        hdb.resize((size_t)ncell);
+        for (int64_t c = 0; c < ncell; ++c) hdb[(size_t)c] = (float)(dt / (kMu0 * mu_r[(size_t)c]));
+        if (!db) db = (float *)al.get((size_t)ncell * 4);
+        hip_check(hipMemcpyAsync(db, hdb.data(), (size_t)ncell * 4, hipMemcpyHostToDevice, st), "db");
+    }
+    // the host vectors must live until the copies finish
+    hip_check(hipStreamSynchronize(st), "sync");
+}
+
+static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
+    k = fdtd_kernel_config{};
+    k.tb = 1;
+    if (s.ndim == 2) {
+        Fused2DCfg c{s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1), 16};
+        if (fused2d_supported(s.nx, s.ny, c)) {
+            k.variant = 2;
+            k.tile[0] = c.V;
+            k.tile[1] = c.TX;
+            return 0;
+        }
+    } else {
+        Fused3DCfg c{4, 32};
+        if (fused3d_supported(s.nx, s.ny, s.nz, c)) {
+            k.variant = 2;
+            k.tile[0] = c.TJ;
+            k.tile[1] = c.TX;
+            return 0;
+        }
+    }
+    k.variant = 1;
+    return 0;
+}
+
+static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
+    if (k.tb != 0 && k.tb != 1) return false;
+    if (k.variant == 1) return true;
+    if (k.variant != 2) return false;
+    if (s.ndim == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
+    return fused3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1]});
+}
+
+// ---------------------------------------------------------------------------
+// Creation
+// ---------------------------------------------------------------------------
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+static void check_map(const float *m, int64_t n, double lo, const char *name) {
+    if (!m) return;
+    for (int64_t c = 0; c < n; ++c)
+        if (!std::isfinite(m[c]) || m[c] < lo) {
+            std::ostringstream o;
+            o << name << "[" << c << "] = " << m[c] << " is invalid (must be finite and >= " << lo << ")";
+            fail(FDTD_EINVAL, o.str());
+        }
+}
+
+void validate_desc(const fdtd_desc *d) {
+    if (!d) fail(FDTD_EINVAL, "desc is NULL");
+    if (d->ndim != 2 && d->ndim != 3) fail(FDTD_EINVAL, "ndim must be 2 or 3");
+    if (d->nx < 3 || d->ny < 3) fail(FDTD_EINVAL, "nx and ny must be >= 3");
+    if (d->ndim == 3 && d->nz < 3) fail(FDTD_EINVAL, "nz must be >= 3 for ndim 3");
+    if (d->ndim == 2 && d->nz != 1) fail(FDTD_EINVAL, "nz must be 1 for ndim 2");
+    const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+    if (ncell >= ((int64_t)1 << 31)) fail(FDTD_EINVAL, "grid too large (more than 2^31 cells)");
+    if (!finite_pos(d->dx) || !finite_pos(d->dy) || (d->ndim == 3 && !finite_pos(d->dz)))
+        fail(FDTD_EINVAL, "spatial steps must be finite and > 0");
+    if (!finite_pos(d->dt)) fail(FDTD_EINVAL, "dt must be finite and > 0");
+    double s = 1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy);
+    if (d->ndim == 3) s += 1.0 / (d->dz * d->dz);
+    if (kC0 * d->dt * std::sqrt(s) > 1.0 + 1e-12) {
+        std::ostringstream o;
+        o << "dt = " << d->dt << " exceeds the Courant limit " << 1.0 / (kC0 * std::sqrt(s));
+        fail(FDTD_EUNSTABLE, o.str());
+    }
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = d->cpml.npml[2 * a], hi = d->cpml.npml[2 * a + 1];
+        if (lo < 0 || hi < 0) fail(FDTD_EINVAL, "npml must be >= 0");
+        if (a == 2 && d->ndim == 2 && (lo || hi)) fail(FDTD_EINVAL, "npml along z must be 0 for ndim 2");
+        if (lo + hi > 0 && lo + hi >= n[a]) fail(FDTD_EINVAL, "CPML thicker than the grid");
+    }
+    const fdtd_cpml &c = d->cpml;
+    if (!(c.m >= 0) || !std::isfinite(c.m) || !(c.kappa_max >= 1.0) || !std::isfinite(c.kappa_max) ||
+        !(c.alpha_max >= 0) || !std::isfinite(c.alpha_max) || !(c.m_alpha >= 0) ||
+        !std::isfinite(c.m_alpha) || !std::isfinite(c.sigma_max))
+        fail(FDTD_EINVAL, "invalid CPML parameters");
+    check_map(d->eps_r, ncell, 1.0, "eps_r");
+    check_map(d->mu_r, ncell, 1.0, "mu_r");
+    check_map(d->sigma, ncell, 0.0, "sigma");
+}
+
+void init_sim(Sim &s, const fdtd_desc *d) {
+    validate_desc(d);
+    s.ndim = d->ndim;
+    s.nx = d->nx;
+    s.ny = d->ny;
+    s.nz = d->nz;
+    s.ncell = (int64_t)s.nx * s.ny * s.nz;
+    s.dx = d->dx;
+    s.dy = d->dy;
+    s.dz = d->ndim == 3 ? d->dz : 1.0;
+    s.dt = d->dt;
+    s.cpml = d->cpml;
+    s.st = (hipStream_t)d->stream;
+    hip_check(hipGetDevice(&s.device), "hipGetDevice");
+    s.al.st = s.st;
+    if (d->allocator) {
+        if (!d->allocator->alloc || !d->allocator->free) fail(FDTD_EINVAL, "allocator callbacks missing");
+        s.al.a = *d->allocator;
+        s.al.has = true;
+    }
+    const size_t n = (size_t)s.ncell;
+    if (d->eps_r) s.eps_r.assign(d->eps_r, d->eps_r + n);
+    if (d->sigma) {
+        s.sigma.assign(d->sigma, d->sigma + n);
+        s.lossy = std::any_of(s.sigma.begin(), s.sigma.end(), [](float v) { return v > 0.f; });
+    }
+    if (d->mu_r) {
+        s.mu_r.assign(d->mu_r, d->mu_r + n);
+        const float m0 = s.mu_r[0];
+        s.mumap = std::any_of(s.mu_r.begin(), s.mu_r.end(), [m0](float v) { return v != m0; });
+    }
+    s.refold(0, s.ncell);
+    const double dd[3] = {s.dx, s.dy, s.dz};
+    const int nn[3] = {s.nx, s.ny, s.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (a == 2 && s.ndim == 2) {
+            s.axh[a] = build_axis(1, 0, 0, 1.0, s.dt, s.cpml);
+        } else {
+            s.axh[a] = build_axis(nn[a], s.cpml.npml[2 * a], s.cpml.npml[2 * a + 1], dd[a], s.dt, s.cpml);
+        }
+        s.ax[a] = upload_axis(s.al, s.axh[a], s.st);
+    }
+    const int sx = s.ax[0].lo + s.ax[0].hi, sy = s.ax[1].lo + s.ax[1].hi, sz = s.ax[2].lo + s.ax[2].hi;
+    if (s.ndim == 2) {
+        s.psi_len[0] = (int64_t)s.nx * sy;  // psi_hx
+        s.psi_len[1] = (int64_t)sx * s.ny;  // psi_hy
+        s.psi_len[2] = (int64_t)sx * s.ny;  // psi_ezx
+        s.psi_len[3] = (int64_t)s.nx * sy;  // psi_ezy
+    } else {
+        const int64_t X = (int64_t)sx * s.ny * s.nz, Y = (int64_t)s.nx * sy * s.nz,
+                      Z = (int64_t)s.nx * s.ny * sz;
+        const int64_t len[NPSI3] = {Y, Z, Z, X, X, Y, Y, Z, Z, X, X, Y};
+        for (int a = 0; a < NPSI3; ++a) s.psi_len[a] = len[a];
+    }
+    for (int set = 0; set < 2; ++set) {
+        if (s.ndim == 2) {
+            for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) s.f[set][c] = (float *)s.al.get(n * 4);
+        } else {
+            for (int c = 0; c < 6; ++c) s.f[set][c] = (float *)s.al.get(n * 4);
+        }
+        for (int a = 0; a < NPSI3; ++a)
+            if (s.psi_len[a] > 0) s.psi[set][a] = (float *)s.al.get((size_t)s.psi_len[a] * 4);
+    }
+    hip_check(hipEventCreate(&s.ev0), "event");
+    hip_check(hipEventCreate(&s.ev1), "event");
+    default_variant_tiles(s, s.kcfg);
+    hip_check(hipStreamSynchronize(s.st), "sync");
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotune cache: a flat JSON object {"key": [variant, t0, t1, t2, t3, tb], ...}
+// ---------------------------------------------------------------------------
+static std::string tune_key(const Sim &s) {
+    hipDeviceProp_t pr{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&pr, s.device) == hipSuccess) arch = pr.gcnArchName;
+    std::ostringstream o;
+    o << arch << "|" << s.ndim << "|" << s.nx << "x" << s.ny << "x" << s.nz << "|L" << s.lossy << "|M"
+      << s.mumap << "|P" << (s.ax[0].lo + s.ax[0].hi + s.ax[1].lo + s.ax[1].hi + s.ax[2].lo + s.ax[2].hi > 0);
+    return o.str();
+}
+
+static std::map<std::string, std::vector<int>> read_cache(const char *path) {
+    std::map<std::string, std::vector<int>> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while (true) {
+        size_t a = t.find('"', p);
+        if (a == std::string::npos) break;
+        size_t b = t.find('"', a + 1);
+        if (b == std::string::npos) break;
+        const std::string key = t.substr(a + 1, b - a - 1);
+        size_t l = t.find('[', b), r = t.find(']', b);
+        if (l == std::string::npos || r == std::string::npos || r < l) break;
+        std::vector<int> v;
+        std::stringstream vs(t.substr(l + 1, r - l - 1));
+        std::string tok;
+        while (std::getline(vs, tok, ',')) v.push_back(std::atoi(tok.c_str()));
+        m[key] = v;
+        p = r + 1;
+    }
+    return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, std::vector<int>> &m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    size_t q = 0;
+    for (auto &kv : m) {
+        f << "  \"" << kv.first << "\": [";
+        for (size_t i = 0; i < kv.second.size(); ++i) f << (i ? ", " : "") << kv.second[i];
+        f << "]" << (++q < m.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace gem
+
+using namespace gem;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define GEM_TRY try {
+#define GEM_CATCH                                   \
+    }                                               \
+    catch (const Fail &f) {                         \
+        set_error(f.msg);                           \
+        return f.code;                              \
+    }                                               \
+    catch (const std::bad_alloc &) {                \
+        set_error("host allocation failed");        \
+        return FDTD_ENOMEM;                         \
+    }                                               \
+    catch (...) {                                   \
+        set_error("unexpected internal error");     \
+        return FDTD_EDEVICE;                        \
+    }
+
+extern "C" {
+
+const char *fdtd_last_error(void) { return g_err.c_str(); }
+
+const char *fdtd_version(void) { return "gemfdtd 0.1 (gfx950)"; }
+
+int fdtd_create(const fdtd_desc *desc, fdtd_sim **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDTD_EINVAL;
+    }
+    *out = nullptr;
+    fdtd_sim *h = nullptr;
+    GEM_TRY
+    h = new fdtd_sim();
+    init_sim(h->s, desc);
+    *out = h;
+    set_error("");
+    return FDTD_OK;
+    }
+    catch (const Fail &f) {
+        delete h;
+        set_error(f.msg);
+        return f.code;
+    }
+    catch (...) {
+        delete h;
+        set_error("unexpected internal error");
+        return FDTD_EDEVICE;
+    }
+}
+
+int fdtd_create_graph(const fdtd_desc *desc, fdtd_sim **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDTD_EINVAL;
+    }
+    *out = nullptr;
+    fdtd_sim *h = nullptr;
+    GEM_TRY
+    if (desc && desc->ndim != 2) fail(FDTD_EINVAL, "the explicit graph form supports ndim 2 only");
+    h = new fdtd_sim();
+    init_sim(h->s, desc);
+    h->s.is_graph = true;
+    build_graph(h->s);
+    *out = h;
+    set_error("");
+    return FDTD_OK;
+    }
+    catch (const Fail &f) {
+        delete h;
+        set_error(f.msg);
+        return f.code;
+    }
+    catch (...) {
+        delete h;
+        set_error("unexpected internal error");
+        return FDTD_EDEVICE;
+    }
+}
+
+int fdtd_destroy(fdtd_sim *sim) {
+    if (!sim) return FDTD_OK;
+    delete sim;
+    return FDTD_OK;
+}
+
+static bool on_wall(const Sim &s, int comp, const int *c) {
+    // E components tangential to the low PEC planes are never updated
+    const int i = c[0], j = c[1], k = s.ndim == 3 ? c[2] : 1;
+    if (comp == FDTD_EX) return j < 1 || k < 1;
+    if (comp == FDTD_EY) return i < 1 || k < 1;
+    if (comp == FDTD_EZ) return i < 1 || j < 1;
+    return false;
+}
+
+static int64_t lin_cell(const Sim &s, const int32_t *ijk) {
+    const int i = ijk[0], j = ijk[1], k = s.ndim == 3 ? ijk[2] : 0;
+    if (i < 0 || i >= s.nx || j < 0 || j >= s.ny || k < 0 || k >= s.nz) return -1;
+    return ((int64_t)i * s.ny + j) * s.nz + k;
+}
+
+static bool comp_ok(const Sim &s, int comp) {
+    if (s.ndim == 2) return comp == FDTD_EZ || comp == FDTD_HX || comp == FDTD_HY;
+    return comp >= 0 && comp < 6;
+}
+
+
+int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, const double *params,
+                    const float *table, int64_t n_table) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    if (kind < 0) {
+        s.src_idx = -1;
+        s.src_kind = -1;
+        if (s.is_graph) graph_set_source_probes(s);
+        return FDTD_OK;
+    }
+    if (!ijk) fail(FDTD_EINVAL, "ijk is NULL");
+    if (component < FDTD_EX || component > FDTD_EZ || (s.ndim == 2 && component != FDTD_EZ))
+        fail(FDTD_EINVAL, "source component must be an E component present in the grid");
+    const int64_t c = lin_cell(s, ijk);
+    if (c < 0) fail(FDTD_EINVAL, "source cell outside the grid");
+    int cc[3] = {ijk[0], ijk[1], s.ndim == 3 ? ijk[2] : 1};
+    if (on_wall(s, component, cc)) fail(FDTD_EINVAL, "source cell lies on a PEC wall of that component");
+    if (kind == FDTD_SRC_TABLE) {
+        if (!table || n_table < 0) fail(FDTD_EINVAL, "table source needs table and n_table >= 0");
+        for (int64_t n = 0; n < n_table; ++n)
+            if (!std::isfinite(table[n])) fail(FDTD_EINVAL, "non-finite source table value");
+    } else if (kind == FDTD_SRC_GAUSSIAN || kind == FDTD_SRC_RICKER) {
+        if (!params) fail(FDTD_EINVAL, "params is NULL");
+        for (int q = 0; q < 3; ++q)
+            if (!std::isfinite(params[q])) fail(FDTD_EINVAL, "non-finite source parameter");
+        if (kind == FDTD_SRC_GAUSSIAN && !(params[2] > 0)) fail(FDTD_EINVAL, "Gaussian tau must be > 0");
+        if (kind == FDTD_SRC_RICKER && !(params[2] > 0)) fail(FDTD_EINVAL, "Ricker frequency must be > 0");
+    } else {
+        fail(FDTD_EINVAL, "unknown source kind");
+    }
+    s.al.put(s.src_dev);
+    s.src_dev = nullptr;
+    s.src_cap = s.src_len = 0;
+    s.src_comp = component;
+    s.src_idx = c;
+    s.src_kind = kind;
+    if (kind == FDTD_SRC_TABLE) {
+        s.src_table.assign(table, table + n_table);
+        s.src_dev = dev_upload(s.al, s.src_table.data(), std::max<size_t>(1, (size_t)n_table), s.st);
+        s.src_cap = std::max<int64_t>(1, n_table);
+        s.src_len = n_table;
+        hip_check(hipStreamSynchronize(s.st), "sync");
+    } else {
+        for (int q = 0; q < 3; ++q) s.src_par[q] = params[q];
+        s.ensure_source(std::max<int64_t>(s.n_done + 1, 1));
+        hip_check(hipStreamSynchronize(s.st), "sync");
+    }
+    if (s.is_graph) graph_set_source_probes(s);
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    if (n < 0 || n > 4096) fail(FDTD_EINVAL, "probe count must be in [0, 4096]");
+    if (n > 0 && !ijk) fail(FDTD_EINVAL, "ijk is NULL");
+    if (!comp_ok(s, component)) fail(FDTD_EINVAL, "probe component not present in this grid");
+    if (s.is_graph && component != FDTD_EZ) fail(FDTD_EINVAL, "graph form probes Ez only");
+    std::vector<int64_t> cells((size_t)n);
+    for (int q = 0; q < n; ++q) {
+        cells[(size_t)q] = lin_cell(s, ijk + (size_t)q * s.ndim);
+        if (cells[(size_t)q] < 0) fail(FDTD_EINVAL, "probe cell outside the grid");
+    }
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    s.probe_cells = cells;
+    s.probe_comp = component;
+    s.al.put(s.probe_dev);
+    s.al.put(s.probe_dev64);
+    s.al.put(s.rec_dev);
+    s.probe_dev = nullptr;
+    s.probe_dev64 = nullptr;
+    s.rec_dev = nullptr;
+    s.rec_cap = 0;
+    s.n_rec = 0;
+    if (n > 0) {
+        std::vector<int> c32((size_t)n);
+        for (int q = 0; q < n; ++q) c32[(size_t)q] = (int)cells[(size_t)q];
+        s.probe_dev = dev_upload(s.al, c32.data(), (size_t)n, s.st);
+        s.probe_dev64 = dev_upload(s.al, cells.data(), (size_t)n, s.st);
+    }
+    s.pt_ntiles = -1;
+    s.build_probe_tiles();
+    if (s.is_graph) graph_set_source_probes(s);
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_step(fdtd_sim *sim, int64_t n) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    if (n < 0) fail(FDTD_EINVAL, "n must be >= 0");
+    Sim &s = sim->s;
+    s.ensure_source(s.n_done + n);
+    s.ensure_rec(s.n_rec + n);
+    s.build_probe_tiles();
+    s.last_launches = 0;
+    hip_check(hipEventRecord(s.ev0, s.st), "event");
+    for (int64_t q = 0; q < n; ++q) {
+        s.launch_step(s.n_done);
+        s.n_done += 1;
+        if (!s.probe_cells.empty()) s.n_rec += 1;
+    }
+    hip_check(hipEventRecord(s.ev1, s.st), "event");
+    s.timed = true;
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches) {
+    GEM_TRY
+    if (!sim || !ms) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    if (!s.timed) fail(FDTD_ESTATE, "no fdtd_step call yet");
+    hip_check(hipEventSynchronize(s.ev1), "event sync");
+    hip_check(hipEventElapsedTime(ms, s.ev0, s.ev1), "elapsed");
+    if (launches) *launches = s.last_launches;
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    if (n_recorded) *n_recorded = s.n_rec;
+    if (!out || s.probe_cells.empty()) return FDTD_OK;
+    if (cap < 0) fail(FDTD_EINVAL, "cap must be >= 0");
+    const int64_t m = std::min(cap, s.n_rec);
+    if (m > 0)
+        hip_check(hipMemcpy2DAsync(out, cap * sizeof(float), s.rec_dev, s.rec_cap * sizeof(float),
+                                   m * sizeof(float), s.probe_cells.size(), hipMemcpyDeviceToHost, s.st),
+                  "probe copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+
+int fdtd_get_field(fdtd_sim *sim, int component, void *dst, int dst_on_device) {
+    GEM_TRY
+    if (!sim || !dst) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    if (!comp_ok(s, component)) fail(FDTD_EINVAL, "component not present in this grid");
+    const size_t bytes = (size_t)s.ncell * 4;
+    if (s.is_graph) {
+        std::vector<float> h((size_t)s.ncell);
+        graph_get_field(s, component, h.data());
+        if (dst_on_device) {
+            hip_check(hipMemcpyAsync(dst, h.data(), bytes, hipMemcpyHostToDevice, s.st), "copy");
+            hip_check(hipStreamSynchronize(s.st), "sync");
+        } else {
+            std::memcpy(dst, h.data(), bytes);
+        }
+        return FDTD_OK;
+    }
+    hip_check(hipMemcpyAsync(dst, s.f[s.cur][component], bytes,
+                             dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s.st),
+              "copy");
+    if (!dst_on_device) hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_device) {
+    GEM_TRY
+    if (!sim || !src) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    if (!comp_ok(s, component)) fail(FDTD_EINVAL, "component not present in this grid");
+    const size_t bytes = (size_t)s.ncell * 4;
+    if (s.is_graph) {
+        std::vector<float> h((size_t)s.ncell);
+        if (src_on_device) {
+            hip_check(hipMemcpyAsync(h.data(), src, bytes, hipMemcpyDeviceToHost, s.st), "copy");
+            hip_check(hipStreamSynchronize(s.st), "sync");
+        } else {
+            std::memcpy(h.data(), src, bytes);
+        }
+        graph_set_field(s, component, h.data());
+        return FDTD_OK;
+    }
+    hip_check(hipMemcpyAsync(s.f[s.cur][component], src, bytes,
+                             src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s.st),
+              "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_reset(fdtd_sim *sim) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    sim->s.zero_state();
+    hip_check(hipStreamSynchronize(sim->s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_steps_done(const fdtd_sim *sim, int64_t *n) {
+    if (!sim || !n) {
+        set_error("NULL argument");
+        return FDTD_EINVAL;
+    }
+    *n = sim->s.n_done;
+    return FDTD_OK;
+}
+
+int fdtd_check_finite(fdtd_sim *sim) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    int *flag = (int *)s.al.get(4);
+    if (s.is_graph) {
+        hip_check(launch_nonfinite(s.g.x, s.g.nnodes, flag, s.st), "finite check");
+    } else {
+        for (int c = 0; c < 6; ++c)
+            if (s.f[s.cur][c]) hip_check(launch_nonfinite(s.f[s.cur][c], s.ncell, flag, s.st), "finite check");
+        for (int a = 0; a < NPSI3; ++a)
+            if (s.psi[s.cur][a]) hip_check(launch_nonfinite(s.psi[s.cur][a], s.psi_len[a], flag, s.st), "finite check");
+    }
+    int h = 0;
+    hip_check(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    s.al.put(flag);
+    if (h) {
+        set_error("a field holds NaN or Inf");
+        return FDTD_ENONFINITE;
+    }
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+
+int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi, const float *eps_r,
+                      const float *sigma) {
+    GEM_TRY
+    if (!sim || !lo || !hi || !eps_r) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    const int nd = s.ndim;
+    const int n[3] = {s.nx, s.ny, s.nz};
+    int l[3] = {0, 0, 0}, h[3] = {1, 1, 1};
+    for (int a = 0; a < nd; ++a) {
+        l[a] = lo[a];
+        h[a] = hi[a];
+        if (l[a] < 0 || h[a] > n[a] || l[a] >= h[a]) fail(FDTD_EINVAL, "invalid box");
+    }
+    const int64_t bn = (int64_t)(h[0] - l[0]) * (h[1] - l[1]) * (h[2] - l[2]);
+    check_map(eps_r, bn, 1.0, "eps_r");
+    if (sigma) check_map(sigma, bn, 0.0, "sigma");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    if (s.eps_r.empty()) s.eps_r.assign((size_t)s.ncell, 1.0f);
+    if (sigma && s.sigma.empty()) s.sigma.assign((size_t)s.ncell, 0.0f);
+    int64_t q = 0;
+    for (int i = l[0]; i < h[0]; ++i)
+        for (int j = l[1]; j < h[1]; ++j)
+            for (int k = l[2]; k < h[2]; ++k, ++q) {
+                const int64_t c = ((int64_t)i * s.ny + j) * s.nz + k;
+                s.eps_r[(size_t)c] = eps_r[q];
+                if (sigma) s.sigma[(size_t)c] = sigma[q];
+            }
+    if (sigma && !s.lossy)
+        s.lossy = std::any_of(s.sigma.begin(), s.sigma.end(), [](float v) { return v > 0.f; });
+    s.refold(0, s.ncell);
+    if (s.is_graph) graph_refold(s);
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
+    GEM_TRY
+    if (!sim || !cfg) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    if (s.is_graph) fail(FDTD_EINVAL, "kernel selection applies to the implicit-graph stepper");
+    fdtd_kernel_config k = *cfg;
+    if (k.tb == 0) k.tb = 1;
+    if (k.variant == 0) {
+        default_variant_tiles(s, k);
+    } else if (k.variant == 2) {
+        fdtd_kernel_config d;
+        default_variant_tiles(s, d);
+        if (k.tile[0] == 0) k.tile[0] = (s.ndim == 2) ? (s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1)) : 4;
+        if (k.tile[1] == 0) k.tile[1] = (s.ndim == 2) ? 16 : 32;
+    }
+    if (!config_ok(s, k)) fail(FDTD_EINVAL, "unsupported kernel configuration for this grid");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    // the current state must live in set 0 or 1 consistently: both variants read s.cur
+    s.kcfg = k;
+    s.kcfg_explicit = true;
+    s.pt_ntiles = -1;
+    s.build_probe_tiles();
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_get_kernel(const fdtd_sim *sim, fdtd_kernel_config *cfg) {
+    if (!sim || !cfg) {
+        set_error("NULL argument");
+        return FDTD_EINVAL;
+    }
+    *cfg = sim->s.kcfg;
+    return FDTD_OK;
+}
+
+int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    if (s.is_graph) fail(FDTD_EINVAL, "autotune applies to the implicit-graph stepper");
+    if (trial_steps < 1) trial_steps = 1;
+    const std::string key = tune_key(s);
+    const char *path = std::getenv("GEMFDTD_TUNE_CACHE");
+    std::map<std::string, std::vector<int>> cache;
+    if (path) cache = read_cache(path);
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second.size() == 6) {
+        fdtd_kernel_config k{};
+        k.variant = it->second[0];
+        for (int q = 0; q < 4; ++q) k.tile[q] = it->second[1 + q];
+        k.tb = it->second[5];
+        if (config_ok(s, k)) {
+            s.kcfg = k;
+            s.pt_ntiles = -1;
+            s.build_probe_tiles();
+            if (out) *out = k;
+            return FDTD_OK;
+        }
+    }
+    // candidates
+    std::vector<fdtd_kernel_config> cand;
+    if (s.ndim == 2) {
+        for (int V : {1, 2, 4})
+            for (int TX : {8, 16, 32, 64}) {
+                fdtd_kernel_config k{};
+                k.variant = 2;
+                k.tile[0] = V;
+                k.tile[1] = TX;
+                k.tb = 1;
+                if (config_ok(s, k)) cand.push_back(k);
+            }
+    } else {
+        for (int TJ : {1, 2, 4, 8})
+            for (int TX : {16, 32, 64, 128}) {
+                fdtd_kernel_config k{};
+                k.variant = 2;
+                k.tile[0] = TJ;
+                k.tile[1] = TX;
+                k.tb = 1;
+                if (config_ok(s, k)) cand.push_back(k);
+            }
+    }
+    {
+        fdtd_kernel_config k{};
+        k.variant = 1;
+        k.tb = 1;
+        cand.push_back(k);
+    }
+    // snapshot the current state
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    const int ncomp = s.ndim == 2 ? 3 : 6;
+    std::vector<float *> bak;
+    const int comps2[3] = {FDTD_EZ, FDTD_HX, FDTD_HY};
+    auto comp_at = [&](int q) { return s.ndim == 2 ? comps2[q] : q; };
+    for (int q = 0; q < ncomp; ++q) {
+        float *b = (float *)s.al.get((size_t)s.ncell * 4);
+        hip_check(hipMemcpyAsync(b, s.f[s.cur][comp_at(q)], (size_t)s.ncell * 4, hipMemcpyDeviceToDevice, s.st), "copy");
+        bak.push_back(b);
+    }
+    std::vector<float *> bakp(NPSI3, nullptr);
+    for (int a = 0; a < NPSI3; ++a)
+        if (s.psi[s.cur][a]) {
+            bakp[a] = (float *)s.al.get((size_t)s.psi_len[a] * 4);
+            hip_check(hipMemcpyAsync(bakp[a], s.psi[s.cur][a], (size_t)s.psi_len[a] * 4, hipMemcpyDeviceToDevice, s.st), "copy");
+        }
+    const int64_t n_done0 = s.n_done, n_rec0 = s.n_rec;
+    const int cur0 = s.cur;
+    const fdtd_kernel_config k0 = s.kcfg;
+    float best = 1e30f;
+    fdtd_kernel_config bestk = k0;
+    s.ensure_source(s.n_done + 2 * trial_steps + 2);
+    s.ensure_rec(s.n_rec + 2 * trial_steps + 2);
+    for (auto &k : cand) {
+        s.kcfg = k;
+        s.pt_ntiles = -1;
+        s.build_probe_tiles();
+        s.launch_step(s.n_done);  // warm-up
+        hip_check(hipEventRecord(s.ev0, s.st), "event");
+        for (int q = 0; q < trial_steps; ++q) s.launch_step(s.n_done + 1 + q);
+        hip_check(hipEventRecord(s.ev1, s.st), "event");
+        hip_check(hipEventSynchronize(s.ev1), "sync");
+        float ms = 0;
+        hip_check(hipEventElapsedTime(&ms, s.ev0, s.ev1), "elapsed");
+        if (ms < best) {
+            best = ms;
+            bestk = k;
+        }
+        s.cur = cur0;
+    }
+    // restore
+    for (int q = 0; q < ncomp; ++q)
+        hip_check(hipMemcpyAsync(s.f[cur0][comp_at(q)], bak[q], (size_t)s.ncell * 4, hipMemcpyDeviceToDevice, s.st), "copy");
+    for (int a = 0; a < NPSI3; ++a)
+        if (bakp[a])
+            hip_check(hipMemcpyAsync(s.psi[cur0][a], bakp[a], (size_t)s.psi_len[a] * 4, hipMemcpyDeviceToDevice, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    for (float *b : bak) s.al.put(b);
+    for (float *b : bakp) s.al.put(b);
+    s.n_done = n_done0;
+    s.n_rec = n_rec0;
+    s.cur = cur0;
+    s.kcfg = bestk;
+    s.pt_ntiles = -1;
+    s.build_probe_tiles();
+    if (path) {
+        cache[key] = {bestk.variant, bestk.tile[0], bestk.tile[1], bestk.tile[2], bestk.tile[3], bestk.tb};
+        write_cache(path, cache);
+    }
+    if (out) *out = bestk;
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+}  // extern "C"

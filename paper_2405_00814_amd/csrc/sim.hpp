@@ -1,0 +1,158 @@
+// Host-side simulation object behind the fdtd_sim handle.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gem {
+
+// CODATA 2018
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+// Error carried out of the host runtime as a status code.
+struct Status {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+
+// Device memory through the caller's allocator (or hipMalloc).
+struct DevAlloc {
+    fdtd_allocator a{};
+    bool has = false;
+    hipStream_t st = nullptr;
+    std::vector<void *> blocks;
+    void *get(size_t bytes);            // zero-filled on the stream
+    void put(void *p);                  // release one block
+    void release_all();
+};
+
+// One axis of CPML tables in double precision before rounding.
+struct AxisHost {
+    int n = 0, lo = 0, hi = 0;
+    std::vector<float> kE, bE, cE, kH, bH, cH;
+};
+AxisHost build_axis(int n, int lo, int hi, double d, double dt, const fdtd_cpml &cp);
+AxisDev upload_axis(DevAlloc &al, const AxisHost &h, hipStream_t st);
+
+// Source waveform sample for step n (added at the end of step n, t = (n+1) dt).
+double source_sample(int kind, const double *par, double dt, int64_t n);
+
+struct Sim {
+    int ndim = 2;
+    int nx = 0, ny = 0, nz = 1;
+    int64_t ncell = 0;
+    double dx = 0, dy = 0, dz = 0, dt = 0;
+    hipStream_t st = nullptr;
+    int device = 0;
+    DevAlloc al;
+
+    // host copies of the maps (for refolding)
+    std::vector<float> eps_r, mu_r, sigma;
+    bool lossy = false, mumap = false;
+    fdtd_cpml cpml{};
+
+    // device coefficients
+    float *ca = nullptr, *cb = nullptr, *db = nullptr;
+    float db0 = 0;
+    AxisHost axh[3];
+    AxisDev ax[3]{};
+
+    // double-buffered state: fields[set][comp], psi[set][a]
+    float *f[2][6] = {};
+    float *psi[2][NPSI3] = {};
+    int64_t psi_len[NPSI3] = {};
+    int cur = 0;
+
+    // source
+    int src_comp = FDTD_EZ;
+    int64_t src_idx = -1;
+    int src_kind = -1;
+    double src_par[3] = {0, 0, 0};
+    std::vector<float> src_table;   // TABLE kind
+    float *src_dev = nullptr;
+    int64_t src_cap = 0;            // entries on the device
+    int64_t src_len = 0;            // valid entries (kernels add only below)
+
+    // probes
+    int probe_comp = FDTD_EZ;
+    std::vector<int64_t> probe_cells;
+    int *probe_dev = nullptr;          // int32 linear index (2D)
+    int64_t *probe_dev64 = nullptr;    // int64 linear index (3D)
+    float *rec_dev = nullptr;
+    int64_t rec_cap = 0;
+    int64_t n_rec = 0;
+    // probes grouped by tile for the fused kernels
+    int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
+    int pt_ntiles = -1;
+    int pt_cfg[3] = {-1, -1, -1};
+
+    int64_t n_done = 0;
+    fdtd_kernel_config kcfg{};
+    bool kcfg_explicit = false;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    int64_t last_launches = 0;
+
+    // explicit graph form (ndim 2)
+    bool is_graph = false;
+    struct Graph {
+        int64_t nmain = 0, nnodes = 0;
+        float *x = nullptr;  // node vector
+        // per layer: aux rows (psi) then main rows
+        struct Layer {
+            int nrows = 0;
+            int *rowptr = nullptr, *col = nullptr, *dst = nullptr;
+            float *w = nullptr;
+            int64_t nnz = 0;
+        } h_aux, h_main, e_aux, e_main;
+        std::vector<int64_t> ez_node;     // node of Ez(i,j) (host)
+        int64_t src_node = -1;
+        int *probe_node = nullptr;
+        int64_t bytes = 0;
+    } g;
+
+    // adjoint scratch
+    struct AdjBuf {
+        bool init = false;
+        Adj2D a{};
+    } adj;
+
+    ~Sim();
+
+    Prob2D prob2d(int set_in, int set_out) const;
+    Prob3D prob3d(int set_in, int set_out) const;
+    void ensure_source(int64_t upto);
+    void ensure_rec(int64_t upto);
+    void build_probe_tiles();
+    void launch_step(int64_t step);
+    void zero_state();
+    void refold(int64_t c0, int64_t c1);
+};
+
+// explicit graph form (graph.cpp)
+void build_graph(Sim &s);
+void graph_step(Sim &s, int64_t step);
+void graph_refold(Sim &s);
+void graph_set_source_probes(Sim &s);
+void graph_get_field(Sim &s, int comp, float *host);
+void graph_set_field(Sim &s, int comp, const float *host);
+
+// creation helpers (runtime.cpp)
+void validate_desc(const fdtd_desc *d);
+void init_sim(Sim &s, const fdtd_desc *d);
+
+}  // namespace gem
+
+struct fdtd_sim {
+    gem::Sim s;
+};

@@ -1,0 +1,86 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects
+invalid descriptions before touching the device (no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "gemfdtd.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_00814_amd import _lib
+    L = _lib.load()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTED)
+    assert L.fdtd_version().startswith(b"gemfdtd")
+
+
+def test_product_path_has_no_cpu_fallback(tmp_path):
+    from paper_2405_00814_amd import _lib
+    with pytest.raises(RuntimeError):
+        _lib.open_library(str(tmp_path / "missing.so"))
+
+
+def _create(**over):
+    from paper_2405_00814_amd import _lib
+    from paper_2405_00814_amd.sim import make_desc
+    shape = over.pop("shape", (16, 12))
+    h = 1e-3
+    dt = over.pop("dt", 0.9 / math.sqrt(2) * h / 299792458.0)
+    kw = dict(eps_r=None, mu_r=None, sigma=None, npml=None, cpml=None)
+    kw.update(over)
+    d, keep = make_desc(shape, (h,) * len(shape), dt, stream=0, allocator=False, **kw)
+    out = C.c_void_p()
+    rc = _lib.load().fdtd_create(C.byref(d), C.byref(out))
+    msg = _lib.load().fdtd_last_error().decode()
+    return rc, out, msg
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(shape=(2, 12)), -1),
+    (dict(dt=1.0 / (299792458.0 * math.sqrt(2 / 1e-6)) * 1.001), -2),
+    (dict(eps_r=np.full((16, 12), 0.5)), -1),
+    (dict(eps_r=np.where(np.arange(192).reshape(16, 12) == 7, np.nan, 1.0)), -1),
+    (dict(sigma=np.full((16, 12), -1.0)), -1),
+    (dict(mu_r=np.full((16, 12), 0.9)), -1),
+    (dict(npml=(8, 8, 0, 0)), -1),
+    (dict(cpml=dict(kappa_max=0.5)), -1),
+])
+def test_create_rejects_invalid(over, code):
+    rc, out, msg = _create(**over)
+    assert rc == code, msg
+    assert not out.value
+    assert msg
+
+
+def test_courant_limit_boundary():
+    # exactly at the limit is accepted by validation (then needs a device);
+    # just above is FDTD_EUNSTABLE
+    lim = 1.0 / (299792458.0 * math.sqrt(2 / 1e-6))
+    rc, _, _ = _create(dt=lim * (1 + 1e-9))
+    assert rc == -2
+    rc3, _, _ = _create(shape=(8, 8, 8), dt=1.0 / (299792458.0 * math.sqrt(3 / 1e-6)) * 1.01)
+    assert rc3 == -2
+
+
+def test_null_arguments():
+    from paper_2405_00814_amd import _lib
+    L = _lib.load()
+    assert L.fdtd_create(None, None) == -1
+    assert L.fdtd_destroy(None) == 0
+    assert L.fdtd_step(None, 1) == -1
+    assert L.fdtd_probe(None, None, 0, None) == -1

@@ -1,0 +1,168 @@
+"""GPU parity of the explicit-graph (CSR) form, the batched form and the
+adjoint, against the FP64 oracle (and, where the arithmetic is the same,
+against the plain stepper bit for bit)."""
+import numpy as np
+import pytest
+
+from paper_2405_00814_amd import workloads as W
+
+from helpers import assert_parity, log, rel_l2, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Explicit graph (Prop. 1 node order, one CSR gather per layer)
+# ---------------------------------------------------------------------------
+
+def test_graph_form_cavity128():
+    pb = W.cavity2d(128, steps=1000, seed=0)
+    ref, rrec = run_oracle(pb, pb.steps)
+    got, rec, _ = run_gpu(pb, pb.steps, graph=True)
+    assert_parity(got, ref, TOL, "graph cavity")
+    assert rel_l2(rec, rrec) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(96, 80), (131, 70)])
+def test_graph_form_cpml_lossy(shape):
+    pb = W.dielectric2d(shape[0], ny=shape[1], steps=800, seed=6, nrect=8, side=(6, 30), npml=12,
+                        nprobes=4)
+    pb.cpml = dict(m=3.0, sigma_max=0.0, kappa_max=3.0, alpha_max=0.05, m_alpha=1.0)
+    ref, rrec = run_oracle(pb, pb.steps)
+    got, rec, _ = run_gpu(pb, pb.steps, graph=True)
+    assert_parity(got, ref, TOL, "graph %s" % (shape,))
+    assert rel_l2(rec, rrec) <= TOL
+    imp, _, _ = run_gpu(pb, pb.steps)
+    for k in got:
+        assert rel_l2(got[k], imp[k]) <= TOL   # same map, different rounding order
+
+
+def test_graph_form_set_field_and_material():
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.dielectric2d(64, ny=60, steps=200, seed=9, nrect=3, side=(4, 12), npml=8, nprobes=2)
+    s = Sim.from_problem(pb, graph=True)
+    rng = np.random.default_rng(1)
+    hx = rng.standard_normal(pb.shape).astype(np.float32)
+    s.set_field("hx", hx)
+    assert np.array_equal(s.get_field("hx"), hx)
+    s.reset()
+    assert not np.any(s.get_field("hx"))
+    eps = rng.uniform(1, 3, (10, 12)).astype(np.float32)
+    s.set_material((20, 20), (30, 32), eps)
+    s.step(200)
+    got = {k: s.get_field(k) for k in ("ez", "hx", "hy")}
+    s.close()
+    pb.eps_r[20:30, 20:32] = eps
+    ref, _ = run_oracle(pb, 200)
+    assert_parity(got, ref, TOL, "graph material")
+
+
+# ---------------------------------------------------------------------------
+# Batched problems
+# ---------------------------------------------------------------------------
+
+def test_batch_matches_single_and_oracle():
+    from paper_2405_00814_amd.sim import Batch
+    probs = W.batch2d(count=7, steps=0, seed=3, side=(70, 190), nprobes=3, rect_side=(8, 40),
+                      rect_density=40.0 / 4096)
+    shapes = [p.shape for p in probs]
+    log("batch shapes", shapes)
+    assert len({s[1] % 4 for s in shapes}) >= 2      # several vector widths
+    b = Batch(probs)
+    b.step(37)      # odd start: aligns, then graph replays
+    b.step(150)
+    n = 187
+    for q, pb in enumerate(probs):
+        got = {k: b.get_field(q, k) for k in ("ez", "hx", "hy")}
+        rec = b.probe(q)
+        single, srec, _ = run_gpu(pb, n)
+        for k in got:
+            assert np.array_equal(got[k], single[k]), (q, k)
+        assert np.array_equal(rec, srec)
+        if q < 3:
+            ref, rrec = run_oracle(pb, n)
+            assert_parity(got, ref, TOL, "batch[%d]" % q)
+            assert rel_l2(rec, rrec) <= TOL
+    assert b.cells() == sum(p.cells for p in probs)
+    ms, launches = b.last_step_time()
+    assert ms > 0 and launches > 0
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------
+
+def _adjoint_case(n=64, T=300, design=(24, 36, 26, 38), npml=8, lossy=False, seed=2):
+    pb = W.adjoint2d(n=n, steps=T, seed=seed, design=design, npml=npml, nprobes=4)
+    if lossy:
+        pb.sigma = np.zeros(pb.shape, np.float32)
+        pb.sigma[design[0]:design[1], design[2]:design[3]] = 0.02
+    return pb
+
+
+@pytest.mark.parametrize("ckpt,lossy", [(0, False), (17, True), (1, False), (300, False)])
+def test_adjoint_matches_oracle(ckpt, lossy):
+    from oracle import oracle as O
+    from paper_2405_00814_amd.sim import Sim
+    pb = _adjoint_case(lossy=lossy)
+    o = O.for_problem(pb)
+    loss_ref, grad_ref = o.loss_and_grad(pb.steps, pb.window, pb.design)
+    s = Sim.from_problem(pb)
+    loss, grad = s.adjoint_eps(pb.steps, pb.window, pb.design, ckpt)
+    g = grad.cpu().numpy().reshape(grad_ref.shape)
+    log("adjoint ckpt", ckpt, "loss", loss, loss_ref, "grad rel", rel_l2(g, grad_ref))
+    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
+    assert rel_l2(g, grad_ref) <= 1e-3
+    # the handle holds the forward state after T steps
+    ref, _ = run_oracle(pb, pb.steps)
+    assert_parity({k: s.get_field(k) for k in ("ez", "hx", "hy")}, ref, TOL, "after adjoint")
+    s.close()
+
+
+def test_adjoint_gradient_vs_fd_fp64():
+    """FP32 GPU gradient against FP64 central finite differences of the
+    oracle forward on a few seeded design cells."""
+    from oracle import oracle as O
+    from paper_2405_00814_amd.sim import Sim
+    pb = _adjoint_case(n=56, T=260, design=(20, 30, 22, 32))
+    s = Sim.from_problem(pb)
+    loss, grad = s.adjoint_eps(pb.steps, pb.window, pb.design)
+    g = grad.cpu().numpy().reshape(10, 10)
+    s.close()
+    rng = np.random.default_rng(5)
+    fd, gg = [], []
+    for _ in range(4):
+        c = (int(rng.integers(20, 30)), int(rng.integers(22, 32)))
+        vals = []
+        for sgn in (+1, -1):
+            e = pb.eps_r.astype(np.float64).copy()
+            e[c] += sgn * 1e-4 * e[c]
+            o = O.Oracle2D(pb.shape, pb.dx, pb.dt, e, None, None, pb.npml)
+            o.set_source(pb.source.cell, pb.source.kind, pb.source.params)
+            o.set_probes(pb.probes)
+            r = o.run(pb.steps)
+            vals.append(np.sum(r[:, pb.window[0]:pb.window[1]] ** 2))
+        fd.append((vals[0] - vals[1]) / (2e-4 * pb.eps_r[c]))
+        gg.append(g[c[0] - 20, c[1] - 22])
+    fd, gg = np.array(fd), np.array(gg)
+    log("fd", fd, "gpu", gg)
+    assert np.linalg.norm(gg - fd) <= 1e-3 * np.linalg.norm(fd)
+
+
+def test_autograd_function():
+    import torch
+    from paper_2405_00814_amd.autograd import probe_energy_loss
+    from paper_2405_00814_amd.sim import Sim
+    from oracle import oracle as O
+    pb = _adjoint_case(n=48, T=200, design=(18, 28, 20, 30))
+    s = Sim.from_problem(pb)
+    eps = torch.tensor(pb.eps_r[18:28, 20:30], device="cuda", requires_grad=True)
+    L = probe_energy_loss(s, eps, pb.steps, pb.window, pb.design)
+    L.backward()
+    o = O.for_problem(pb)
+    loss_ref, grad_ref = o.loss_and_grad(pb.steps, pb.window, pb.design)
+    assert abs(L.item() - loss_ref) <= 1e-4 * loss_ref
+    assert rel_l2(eps.grad.cpu().numpy(), grad_ref) <= 1e-3
+    s.close()

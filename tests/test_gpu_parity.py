@@ -1,0 +1,256 @@
+"""GPU parity: the HIP stepper (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Bar: every field component and the probe series
+within relative L2 1e-4 of the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2405_00814_amd import workloads as W
+
+from helpers import assert_parity, assert_parity_energy, log, rel_l2, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+# ---------------------------------------------------------------------------
+# 2D TMz
+# ---------------------------------------------------------------------------
+
+def test_cavity128_full_config():
+    """128x128 PEC cavity, 1000 steps, Gaussian source, 4 probes."""
+    pb = W.cavity2d(128, steps=1000, seed=0)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in (None, (1,), (2, (1, 16)), (2, (2, 7)), (2, (4, 64))):
+        log("cavity128 kernel", kernel)
+        got, rec, cfg = run_gpu(pb, pb.steps, kernel)
+        assert_parity(got, ref, TOL, "cavity128 %s" % (cfg,))
+        assert rec.shape == rrec.shape
+        assert rel_l2(rec, rrec) <= TOL
+
+
+@pytest.mark.parametrize("shape,V,TX", [
+    ((192, 160), 4, 16), ((203, 146), 2, 9), ((131, 97), 1, 32), ((70, 256), 4, 70),
+    ((256, 64), 1, 1),
+])
+def test_dielectric2d_cpml_lossy(shape, V, TX):
+    """Random rectangles (eps_r, sigma), 16-cell CPML, Ricker source; ragged
+    tiles in x and y."""
+    pb = W.dielectric2d(shape[0], ny=shape[1], steps=1500, seed=1, nrect=12, side=(8, 48),
+                        npml=16, nprobes=6)
+    log("dielectric2d", shape, V, TX)
+    ref, rrec = run_oracle(pb, pb.steps)
+    got, rec, cfg = run_gpu(pb, pb.steps, (2, (V, TX)))
+    assert cfg["variant"] == 2 and cfg["tile"][:2] == (V, TX)
+    assert_parity(got, ref, TOL, "dielectric2d %s" % (shape,))
+    assert rel_l2(rec, rrec) <= TOL
+    got1, rec1, _ = run_gpu(pb, pb.steps, (1,))
+    assert_parity(got1, ref, TOL, "dielectric2d ref %s" % (shape,))
+
+
+def test_cpml_kappa_alpha_and_mu_map():
+    pb = W.dielectric2d(96, ny=88, steps=900, seed=2, nrect=8, side=(6, 30), npml=10, nprobes=3)
+    pb.cpml = dict(m=3.0, sigma_max=0.0, kappa_max=4.0, alpha_max=0.1, m_alpha=1.0)
+    pb.mu_r = np.random.default_rng(5).uniform(1.0, 2.5, pb.shape).astype(np.float32)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in ((1,), (2, (4, 16)), (2, (2, 5))):
+        got, rec, _ = run_gpu(pb, pb.steps, kernel)
+        assert_parity(got, ref, TOL, "kappa/alpha/mu %s" % (kernel,))
+        assert rel_l2(rec, rrec) <= TOL
+
+
+def test_asymmetric_cpml_faces():
+    pb = W.dielectric2d(80, ny=100, steps=700, seed=3, nrect=5, side=(6, 20), npml=8, nprobes=2)
+    pb.npml = (4, 12, 0, 9)
+    ref, _ = run_oracle(pb, pb.steps)
+    for kernel in ((1,), (2, (4, 16)), (2, (1, 3))):
+        got, _, _ = run_gpu(pb, pb.steps, kernel)
+        assert_parity(got, ref, TOL, "asym cpml %s" % (kernel,))
+
+
+def test_cavity_recurrence_on_gpu():
+    """Discrete eigenmode: E^{n+1} + E^{n-1} = 2 cos(w dt) E^n holds on the
+    GPU within FP32 rounding."""
+    from paper_2405_00814_amd.sim import Sim
+    nx, ny = 128, 128
+    h = 1e-3
+    dt = 0.99 / math.sqrt(2) * h / 299792458.0
+    s = Sim((nx, ny), (h, h), dt)
+    i = np.arange(nx)[:, None]
+    j = np.arange(ny)[None, :]
+    m, n = 8, 3
+    s.set_field("ez", np.sin(m * math.pi * i / nx) * np.sin(n * math.pi * j / ny))
+    s.set_probes("ez", [(37, 91), (64, 64), (100, 30)])
+    s.step(300)
+    rec = s.probe().astype(np.float64)
+    w = 2 * math.asin(299792458.0 * dt / h * math.sqrt(math.sin(m * math.pi / (2 * nx)) ** 2 +
+                                                        math.sin(n * math.pi / (2 * ny)) ** 2))
+    err = np.abs(rec[:, 2:] + rec[:, :-2] - 2 * math.cos(w) * rec[:, 1:-1]).max()
+    assert err / np.abs(rec).max() < 2e-5
+    s.close()
+
+
+def test_chunked_stepping_and_determinism():
+    pb = W.dielectric2d(144, ny=128, steps=600, seed=4, nrect=6, side=(6, 30), npml=12, nprobes=3)
+    a, ra, _ = run_gpu(pb, pb.steps)
+    b, rb, _ = run_gpu(pb, pb.steps, chunks=7)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(ra, rb)
+
+
+def test_resume_from_fields_bitwise():
+    """run(2N) == run(N) -> get_field -> new handle -> set_field -> run(N)
+    (PEC cavity: the state is the three fields)."""
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.cavity2d(128, steps=400, seed=7)
+    pb.source = None
+    rng = np.random.default_rng(0)
+    init = rng.standard_normal(pb.shape).astype(np.float32)
+    init[0, :] = 0
+    init[:, 0] = 0
+
+    def mk():
+        s = Sim.from_problem(pb)
+        return s
+
+    s = mk()
+    s.set_field("ez", init)
+    s.step(400)
+    full = {k: s.get_field(k) for k in ("ez", "hx", "hy")}
+    s.close()
+    s = mk()
+    s.set_field("ez", init)
+    s.step(200)
+    mid = {k: s.get_field(k) for k in ("ez", "hx", "hy")}
+    s.close()
+    s = mk()
+    for k, v in mid.items():
+        s.set_field(k, v)
+    s.step(200)
+    for k in full:
+        assert np.array_equal(s.get_field(k), full[k]), k
+    s.close()
+
+
+def test_source_table_and_probe_components():
+    from paper_2405_00814_amd.sim import Sim
+    from oracle import oracle as O
+    pb = W.dielectric2d(64, ny=72, steps=300, seed=8, nrect=3, side=(4, 12), npml=8, nprobes=3)
+    tab = np.sin(np.arange(250) * 0.05).astype(np.float32) * np.hanning(250).astype(np.float32)
+    s = Sim(pb.shape, pb.dx, pb.dt, pb.eps_r, None, pb.sigma, pb.npml)
+    s.set_source("ez", pb.source.cell, 2, table=tab)
+    s.set_probes("hy", pb.probes)
+    s.step(300)
+    rec = s.probe()
+    g = {k: s.get_field(k) for k in ("ez", "hx", "hy")}
+    s.close()
+    o = O.Oracle2D(pb.shape, pb.dx, pb.dt, pb.eps_r, pb.sigma, None, pb.npml)
+    o.src = None
+    src_i = pb.source.cell[0] * pb.shape[1] + pb.source.cell[1]
+    hy_rec = np.zeros((len(pb.probes), 300))
+    vals = np.concatenate([tab.astype(np.float64), np.zeros(50)])
+    for n in range(300):
+        o.run(1)
+        o.ez.ravel()[src_i] += vals[n]
+        hy_rec[:, n] = [o.hy[tuple(c)] for c in pb.probes]
+    assert_parity(g, {"ez": o.ez, "hx": o.hx, "hy": o.hy}, TOL, "table source")
+    assert rel_l2(rec, hy_rec) <= TOL
+
+
+def test_errors_on_device_handle():
+    from paper_2405_00814_amd.sim import Sim
+    from paper_2405_00814_amd import _lib as L
+    pb = W.cavity2d(32, steps=10, seed=0)
+    s = Sim.from_problem(pb)
+    with pytest.raises(L.FdtdError) as e:
+        s.set_source("ez", (0, 5), 0, (1.0, 1e-11, 1e-11))   # on the PEC wall
+    assert e.value.code == L.FDTD_EINVAL
+    with pytest.raises(L.FdtdError):
+        s.set_probes("ez", [(32, 3)])                          # outside
+    with pytest.raises(L.FdtdError):
+        s.set_source("hx", (5, 5), 0, (1.0, 1e-11, 1e-11))   # not an E component
+    assert s.check_finite()
+    bad = np.zeros(pb.shape, np.float32)
+    bad[3, 4] = np.nan
+    s.set_field("hx", bad)
+    assert not s.check_finite()
+    s.reset()
+    assert s.check_finite() and s.steps_done() == 0
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# 3D Yee
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,TJ,TX", [
+    ((40, 36, 30), 4, 32), ((33, 29, 70), 2, 7), ((30, 26, 20), 8, 30), ((24, 21, 64), 1, 5),
+])
+def test_yee3d_cpml_boxes(shape, TJ, TX):
+    """Zero-mean (Ricker) source: every component within 1e-4."""
+    pb = W.yee3d(shape=shape, steps=260, seed=1, nbox=10, side=(3, 12), npml=6, nprobes=5,
+                 tau_steps=8.0)
+    pb.source.kind = W.SRC_RICKER
+    pb.source.params = (1.0, 40 * pb.dt, 1.0 / (20 * pb.dt))
+    log("yee3d", shape, TJ, TX)
+    ref, rrec = run_oracle(pb, pb.steps)
+    got, rec, cfg = run_gpu(pb, pb.steps, (2, (TJ, TX)))
+    assert cfg["variant"] == 2
+    assert_parity(got, ref, TOL, "yee3d fused %s" % (shape,))
+    assert rel_l2(rec, rrec) <= TOL
+    got1, rec1, _ = run_gpu(pb, pb.steps, (1,))
+    assert_parity(got1, ref, TOL, "yee3d ref %s" % (shape,))
+    assert rel_l2(rec1, rrec) <= TOL
+
+
+def test_yee3d_gaussian_source_energy_norm():
+    """The headline source (Gaussian, nonzero mean) leaves a static curl-free
+    E; the state is compared in the energy norm, E per component."""
+    pb = W.yee3d(shape=(48, 44, 40), steps=600, seed=3, nbox=12, side=(4, 14), npml=8, nprobes=6,
+                 tau_steps=12.0)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in ((1,), (2, (4, 16)), (2, (2, 48))):
+        got, rec, _ = run_gpu(pb, pb.steps, kernel)
+        e = assert_parity_energy(got, ref, pb, TOL, "yee3d gaussian %s" % (kernel,))
+        log("gaussian", kernel, "energy rel-L2 %.2e" % e,
+            {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
+        assert rel_l2(rec, rrec) <= TOL
+
+
+def test_yee3d_long_z_and_lossy_mu():
+    """nz > 256 (two z values per thread), lossy media, mu_r map, x-directed
+    source, Hz probes."""
+    pb = W.yee3d(shape=(14, 12, 300), steps=120, seed=2, nbox=4, side=(2, 20), npml=4,
+                 nprobes=4, tau_steps=6.0)
+    rng = np.random.default_rng(3)
+    pb.sigma = rng.uniform(0, 0.05, pb.shape).astype(np.float32)
+    pb.mu_r = rng.uniform(1, 2, pb.shape).astype(np.float32)
+    pb.source.component = "ex"
+    pb.probe_component = "hz"
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in ((1,), (2, (2, 16)), (2, (4, 3))):
+        got, rec, _ = run_gpu(pb, pb.steps, kernel)
+        assert_parity(got, ref, TOL, "yee3d lossy %s" % (kernel,))
+        assert rel_l2(rec, rrec) <= TOL
+
+
+def test_yee3d_tm_mode_recurrence_on_gpu():
+    from paper_2405_00814_amd.sim import Sim
+    nx, ny, nz = 40, 32, 24
+    h = 1e-3
+    dt = 0.99 / math.sqrt(3) * h / 299792458.0
+    s = Sim((nx, ny, nz), (h, h, h), dt)
+    i = np.arange(nx)[:, None, None]
+    j = np.arange(ny)[None, :, None]
+    m, n = 3, 2
+    s.set_field("ez", np.sin(m * math.pi * i / nx) * np.sin(n * math.pi * j / ny) * np.ones((1, 1, nz)))
+    s.set_probes("ez", [(7, 5, 2), (20, 11, 13)])
+    s.step(200)
+    rec = s.probe().astype(np.float64)
+    w = 2 * math.asin(299792458.0 * dt / h * math.sqrt(math.sin(m * math.pi / (2 * nx)) ** 2 +
+                                                        math.sin(n * math.pi / (2 * ny)) ** 2))
+    err = np.abs(rec[:, 2:] + rec[:, :-2] - 2 * math.cos(w) * rec[:, 1:-1]).max()
+    assert err / np.abs(rec).max() < 2e-5
+    s.close()
