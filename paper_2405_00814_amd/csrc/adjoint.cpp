@@ -77,8 +77,8 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         if (s.kcfg.variant != 2) {
             s.kcfg = fdtd_kernel_config{};
             s.kcfg.variant = 2;
-            s.kcfg.tile[0] = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
-            s.kcfg.tile[1] = 16;
+            s.kcfg.tile[0] = s.ny % 2 == 0 ? 2 : 1;
+            s.kcfg.tile[1] = 8;
             s.kcfg.tb = 1;
         }
         s.pt_ntiles = -1;

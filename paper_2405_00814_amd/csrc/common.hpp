@@ -110,12 +110,29 @@ int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
 
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
-struct Fused3DCfg { int TJ; int TX; };
-hipError_t launch_3d_fused(const Prob3D &p, const Fused3DCfg &c, const ProbeTiles &pt,
-                           int64_t step, hipStream_t st);
-int fused3d_ntiles(int nx, int ny, int nz, const Fused3DCfg &c);
-int fused3d_tile_of(int nx, int ny, int nz, const Fused3DCfg &c, int i, int j, int k);
-bool fused3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);
+// Fused 3D: one workgroup covers 4 y rows x 64*V z cells of one x plane.
+// V: z cells per thread in the middle z range; Ve: in the z-slab end
+// ranges (0 = the widest of 4, 2, 1 dividing nz).
+struct Fused3DCfg { int V; int Ve; };
+// One launch of the fused 3D kernel over a list of workgroup tiles.
+struct Wave3DLaunch {
+    int V, LZ;        // z cells per thread, threads per z row (64, or 16/V)
+    bool pxy, pz;     // CPML code for x/y slabs, z slabs
+    int kbase, klim;  // z range covered
+    int nkz, njt;     // z segments per (plane, band); bands of 4*64/LZ rows
+    int off, n;       // tile list entries [off, off + n) (multiple of 8)
+};
+struct Wave3DPlan {
+    std::vector<Wave3DLaunch> l;
+    std::vector<int> tiles;  // host copy of the concatenated tile lists
+};
+void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
+                 const int *zlohi, Wave3DPlan &pl);
+hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tiles,
+                          const ProbeTiles &pt, int64_t step, hipStream_t st);
+int wave3d_ngroups(int nx, int ny);
+int wave3d_group_of(int ny, int i, int j);
+bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);
 
 hipError_t launch_nonfinite(const float *a, int64_t n, int *flag, hipStream_t st);
 

@@ -220,19 +220,33 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
 
     const float sval = (p.src_idx >= 0 && step < p.src_len) ? p.src_vals[step] : 0.f;
 
+    // The loads of a row are issued one iteration ahead (software pipelining):
+    // stage holds Ez(ip+1), Hx(ip), Hy(ip) and the coefficients of row ip.
+    float s_ezn[V], s_hx[V], s_hy[V], s_cb[V], s_ca[V], s_db[V];
+    auto load_row = [&](int ip) {
+        const int64_t rp = (int64_t)ip * ny;
+#pragma unroll
+        for (int v = 0; v < V; ++v) { s_ezn[v] = 0.f; s_hx[v] = s_hy[v] = s_cb[v] = 0.f; s_ca[v] = 1.f; s_db[v] = p.db0; }
+        if (valid) {
+            if (ip + 1 < nx) ldv<V>(s_ezn, p.s0.ez + rp + ny + jb);
+            ldv<V>(s_hx, p.s0.hx + rp + jb);
+            ldv<V>(s_hy, p.s0.hy + rp + jb);
+            ldv<V>(s_cb, p.cb + rp + jb);
+            if (lossy) ldv<V>(s_ca, p.ca + rp + jb);
+            if (mumap) ldv<V>(s_db, p.db + rp + jb);
+        }
+    };
+    load_row(x0);
+
     for (int i = x0; i < x1; ++i) {
         const int64_t row = (int64_t)i * ny;
         float ez_n[V], hx_o[V], hy_o[V], cb[V], ca[V], db[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) { ez_n[v] = 0.f; hx_o[v] = hy_o[v] = cb[v] = 0.f; ca[v] = 1.f; db[v] = p.db0; }
-        if (valid) {
-            if (i + 1 < nx) ldv<V>(ez_n, p.s0.ez + row + ny + jb);
-            ldv<V>(hx_o, p.s0.hx + row + jb);
-            ldv<V>(hy_o, p.s0.hy + row + jb);
-            ldv<V>(cb, p.cb + row + jb);
-            if (lossy) ldv<V>(ca, p.ca + row + jb);
-            if (mumap) ldv<V>(db, p.db + row + jb);
+        for (int v = 0; v < V; ++v) {
+            ez_n[v] = s_ezn[v]; hx_o[v] = s_hx[v]; hy_o[v] = s_hy[v];
+            cb[v] = s_cb[v]; ca[v] = s_ca[v]; db[v] = s_db[v];
         }
+        if (i + 1 < x1) load_row(i + 1);
         // Ez(i, j+1)
         float ez_r[V];
 #pragma unroll

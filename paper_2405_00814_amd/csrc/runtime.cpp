@@ -265,18 +265,18 @@ void Sim::ensure_rec(int64_t upto) {
     rec_cap = cap;
 }
 
-static void cfg_tiles(const Sim &s, int &a, int &b) {
-    a = s.kcfg.tile[0];
-    b = s.kcfg.tile[1];
-}
-
 void Sim::build_probe_tiles() {
     if (kcfg.variant != 2 || is_graph) return;
-    int a, b;
-    cfg_tiles(*this, a, b);
+    const int a = kcfg.tile[0], b = kcfg.tile[1], c3 = kcfg.tile[2];
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
-        pt_start)
+        pt_cfg[3] == c3 && pt_start)
         return;
+    if (ndim == 3) {
+        const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi}, zl[2] = {ax[2].lo, ax[2].hi};
+        wave3d_plan(nx, ny, nz, Fused3DCfg{a, b}, xl, yl, zl, plan3);
+        al.put(tl_dev);
+        tl_dev = dev_upload(al, plan3.tiles.data(), std::max<size_t>(plan3.tiles.size(), 1), st);
+    }
     int ntiles;
     std::vector<int> tile(probe_cells.size());
     if (ndim == 2) {
@@ -287,14 +287,12 @@ void Sim::build_probe_tiles() {
             tile[q] = fused2d_tile_of(nx, ny, c, i, j);
         }
     } else {
-        Fused3DCfg c{a, b};
-        ntiles = fused3d_ntiles(nx, ny, nz, c);
+        ntiles = wave3d_ngroups(nx, ny);
         for (size_t q = 0; q < probe_cells.size(); ++q) {
             const int64_t cell = probe_cells[q];
             const int i = (int)(cell / ((int64_t)ny * nz));
             const int j = (int)((cell / nz) % ny);
-            const int k = (int)(cell % nz);
-            tile[q] = fused3d_tile_of(nx, ny, nz, c, i, j, k);
+            tile[q] = wave3d_group_of(ny, i, j);
         }
     }
     std::vector<int> order(probe_cells.size());
@@ -317,6 +315,7 @@ void Sim::build_probe_tiles() {
     pt_cfg[0] = a;
     pt_cfg[1] = b;
     pt_cfg[2] = (int)probe_cells.size();
+    pt_cfg[3] = c3;
 }
 
 
@@ -337,11 +336,10 @@ void Sim::launch_step(int64_t step) {
         hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
                   "2d fused step");
     } else {
-        Fused3DCfg c{kcfg.tile[0], kcfg.tile[1]};
-        hip_check(launch_3d_fused(prob3d(cur, 1 - cur), c, pt, step, st), "3d fused step");
+        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st), "3d fused step");
     }
     cur = 1 - cur;
-    last_launches += 1;
+    last_launches += ndim == 2 ? 1 : (int64_t)plan3.l.size();
 }
 
 void Sim::zero_state() {
@@ -392,7 +390,7 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
     if (s.ndim == 2) {
-        Fused2DCfg c{s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1), 16};
+        Fused2DCfg c{s.ny % 2 == 0 ? 2 : 1, 8};
         if (fused2d_supported(s.nx, s.ny, c)) {
             k.variant = 2;
             k.tile[0] = c.V;
@@ -400,11 +398,10 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
             return 0;
         }
     } else {
-        Fused3DCfg c{4, 32};
-        if (fused3d_supported(s.nx, s.ny, s.nz, c)) {
+        Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0};
+        if (wave3d_supported(s.nx, s.ny, s.nz, c)) {
             k.variant = 2;
-            k.tile[0] = c.TJ;
-            k.tile[1] = c.TX;
+            k.tile[0] = c.V;
             return 0;
         }
     }
@@ -417,7 +414,8 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.variant == 1) return true;
     if (k.variant != 2) return false;
     if (s.ndim == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
-    return fused3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1]});
+    if (k.tile[2] != 0 || k.tile[3] != 0) return false;
+    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1]});
 }
 
 // ---------------------------------------------------------------------------
@@ -989,8 +987,8 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
     } else if (k.variant == 2) {
         fdtd_kernel_config d;
         default_variant_tiles(s, d);
-        if (k.tile[0] == 0) k.tile[0] = (s.ndim == 2) ? (s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1)) : 4;
-        if (k.tile[1] == 0) k.tile[1] = (s.ndim == 2) ? 16 : 32;
+        if (k.tile[0] == 0) k.tile[0] = d.tile[0];
+        if (s.ndim == 2 && k.tile[1] == 0) k.tile[1] = d.tile[1];
     }
     if (!config_ok(s, k)) fail(FDTD_EINVAL, "unsupported kernel configuration for this grid");
     hip_check(hipStreamSynchronize(s.st), "sync");
@@ -1049,14 +1047,16 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 if (config_ok(s, k)) cand.push_back(k);
             }
     } else {
-        for (int TJ : {1, 2, 4, 8})
-            for (int TX : {16, 32, 64, 128}) {
+        const bool zslab = s.ax[2].lo + s.ax[2].hi > 0;
+        for (int V : {1, 2, 4})
+            for (int Ve : {1, 2, 4}) {
                 fdtd_kernel_config k{};
                 k.variant = 2;
-                k.tile[0] = TJ;
-                k.tile[1] = TX;
+                k.tile[0] = V;
+                k.tile[1] = zslab ? Ve : 0;
                 k.tb = 1;
                 if (config_ok(s, k)) cand.push_back(k);
+                if (!zslab) break;
             }
     }
     {

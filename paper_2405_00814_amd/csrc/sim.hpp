@@ -93,7 +93,10 @@ struct Sim {
     // probes grouped by tile for the fused kernels
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
     int pt_ntiles = -1;
-    int pt_cfg[3] = {-1, -1, -1};
+    int pt_cfg[4] = {-1, -1, -1, -1};
+    // 3D fused: launch plan and its tile lists on the device
+    Wave3DPlan plan3;
+    int *tl_dev = nullptr;
 
     int64_t n_done = 0;
     fdtd_kernel_config kcfg{};

@@ -185,18 +185,29 @@ def test_errors_on_device_handle():
 # 3D Yee
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape,TJ,TX", [
-    ((40, 36, 30), 4, 32), ((33, 29, 70), 2, 7), ((30, 26, 20), 8, 30), ((24, 21, 64), 1, 5),
+@pytest.mark.parametrize("shape,V,Ve,npml", [
+    ((40, 36, 30), 2, 0, (6,) * 6), ((33, 29, 70), 2, 1, (5, 3, 0, 7, 4, 2)),
+    ((30, 26, 20), 4, 0, (6,) * 6), ((24, 21, 64), 4, 2, (0, 0, 0, 0, 6, 6)),
+    ((26, 23, 300), 4, 0, (6,) * 6), ((21, 19, 45), 1, 0, (6,) * 6),
+    ((44, 70, 128), 4, 0, (3, 5, 4, 6, 0, 0)), ((36, 41, 132), 2, 4, (4, 4, 7, 2, 5, 3)),
+    ((30, 37, 256), 1, 1, (5, 0, 0, 5, 8, 8)), ((28, 90, 96), 4, 4, (4, 4, 20, 20, 40, 40)),
+    ((20, 24, 96), 4, 1, (2, 2, 2, 2, 14, 3)),
 ])
-def test_yee3d_cpml_boxes(shape, TJ, TX):
-    """Zero-mean (Ricker) source: every component within 1e-4."""
-    pb = W.yee3d(shape=shape, steps=260, seed=1, nbox=10, side=(3, 12), npml=6, nprobes=5,
-                 tau_steps=8.0)
+def test_yee3d_cpml_boxes(shape, V, Ve, npml):
+    """Zero-mean (Ricker) source: every component within 1e-4.  The slab
+    widths (some asymmetric or zero) make both the slab and the interior
+    workgroups of the fused kernel run."""
+    pb = W.yee3d(shape=shape, steps=260, seed=1, nbox=10, side=(3, 12), npml=min(npml[:4]) + 2,
+                 nprobes=5, tau_steps=8.0)
+    pb.npml = tuple(npml)
+    # source at the centre of the region clear of every slab
+    pb.source.cell = tuple((npml[2 * a] + shape[a] - npml[2 * a + 1]) // 2 for a in range(3))
     pb.source.kind = W.SRC_RICKER
     pb.source.params = (1.0, 40 * pb.dt, 1.0 / (20 * pb.dt))
-    log("yee3d", shape, TJ, TX)
+    log("yee3d", shape, V, Ve, npml)
     ref, rrec = run_oracle(pb, pb.steps)
-    got, rec, cfg = run_gpu(pb, pb.steps, (2, (TJ, TX)))
+    got, rec, cfg = run_gpu(pb, pb.steps, (2, (V, Ve)))
+    assert tuple(cfg["tile"]) == (V, Ve, 0, 0)
     assert cfg["variant"] == 2
     assert_parity(got, ref, TOL, "yee3d fused %s" % (shape,))
     assert rel_l2(rec, rrec) <= TOL
@@ -205,13 +216,27 @@ def test_yee3d_cpml_boxes(shape, TJ, TX):
     assert rel_l2(rec1, rrec) <= TOL
 
 
+def test_yee3d_kernel_config_rejected():
+    from paper_2405_00814_amd._lib import FdtdError
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.yee3d(shape=(16, 16, 30), steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
+                 tau_steps=4.0)
+    s = Sim.from_problem(pb)
+    for bad in ((4,), (3,), (2, 16), (2, 4), (1, 0, 0, 5), (1, 0, 1)):
+        with pytest.raises(FdtdError):
+            s.set_kernel(2, bad)
+    s.set_kernel(2, (2,))
+    assert s.get_kernel()["tile"] == (2, 0, 0, 0)
+    s.close()
+
+
 def test_yee3d_gaussian_source_energy_norm():
     """The headline source (Gaussian, nonzero mean) leaves a static curl-free
     E; the state is compared in the energy norm, E per component."""
     pb = W.yee3d(shape=(48, 44, 40), steps=600, seed=3, nbox=12, side=(4, 14), npml=8, nprobes=6,
                  tau_steps=12.0)
     ref, rrec = run_oracle(pb, pb.steps)
-    for kernel in ((1,), (2, (4, 16)), (2, (2, 48))):
+    for kernel in ((1,), (2, (4,)), (2, (2,)), (2, (1,))):
         got, rec, _ = run_gpu(pb, pb.steps, kernel)
         e = assert_parity_energy(got, ref, pb, TOL, "yee3d gaussian %s" % (kernel,))
         log("gaussian", kernel, "energy rel-L2 %.2e" % e,
@@ -230,7 +255,7 @@ def test_yee3d_long_z_and_lossy_mu():
     pb.source.component = "ex"
     pb.probe_component = "hz"
     ref, rrec = run_oracle(pb, pb.steps)
-    for kernel in ((1,), (2, (2, 16)), (2, (4, 3))):
+    for kernel in ((1,), (2, (2,)), (2, (4,))):
         got, rec, _ = run_gpu(pb, pb.steps, kernel)
         assert_parity(got, ref, TOL, "yee3d lossy %s" % (kernel,))
         assert rel_l2(rec, rrec) <= TOL
