@@ -114,12 +114,20 @@ def bench_3d(args):
     cells = pb.cells
     rate = cells * args.steps / t
     ab = alg_bytes_implicit(cells, psi_floats_of(pb), 6, ncoef_of(pb))
-    per_launch = t / launches
-    achieved = ab * (args.steps / launches) / per_launch
+    # the same number of steps again with HIP events around every launch
+    prof = sim.step_profile(args.steps)
     ok = sim.check_finite()
     sim.close()
+    dom = max(range(len(prof)), key=lambda q: prof[q]["ms"])
+    d = prof[dom]
+    # the dominant launch runs no CPML code: fields read and written once,
+    # the coefficient maps read once
+    bpc = 8 * 6 + 4 * ncoef_of(pb)
+    assert d["cpml"] == 0, "dominant launch carries CPML code"
     return dict(pb=pb, cfg=cfg, t=t, wall=wall, launches=launches, rate=rate, bytes=ab,
-                achieved=achieved, per_launch=per_launch, finite=ok)
+                step_achieved=ab * args.steps / t, finite=ok, prof=prof, dom=dom,
+                dom_bytes=d["cells"] * bpc, dom_ms=d["ms"], dom_bpc=bpc,
+                dom_achieved=d["cells"] * bpc / (d["ms"] / 1e3))
 
 
 def bench_2d(args, steps=10000):
@@ -244,6 +252,24 @@ def cpu_baseline(target_s=15.0):
                        "CPML on 5 faces), %d steps, %.1f s" % (n, t))
 
 
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size (torch's copy kernel): the reference
+    point that scales rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps(dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes, reps=reps, ms=ms,
+                          GBps=2 * nbytes / (ms / 1e3) / 1e9)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +278,8 @@ def main():
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (the method's independent grids and batches run "
@@ -260,16 +288,24 @@ def main():
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     r = bench_3d(args)
     pb = r["pb"]
-    src3 = os.path.join(ROOT, "paper_2405_00814_amd", "csrc", "k3d.hip")
-    traffic = traffic_record("yee3d_512_fused", src3)
-    roof = dict(bound="hbm", achieved=r["achieved"] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                frac=r["achieved"] / PEAK_HBM, traffic=traffic,
-                kernel="k3d_fused", bytes_per_launch=r["bytes"],
-                bytes_per_cell_update=r["bytes"] / pb.cells,
-                avg_launch_ms=r["per_launch"] * 1e3)
+    src3 = os.path.join(ROOT, "paper_2405_00814_amd", "csrc", "k3dw.hip")
+    traffic = traffic_record("yee3d_512_interior", src3)
+    roof = dict(bound="hbm", achieved=r["dom_achieved"] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                frac=r["dom_achieved"] / PEAK_HBM, traffic=traffic,
+                kernel="k3d_cell interior launch (no CPML code)",
+                bytes_per_launch=r["dom_bytes"], bytes_per_cell_update=r["dom_bpc"],
+                cells_per_launch=r["prof"][r["dom"]]["cells"], avg_launch_ms=r["dom_ms"],
+                step=dict(launches_per_step=r["launches"] / args.steps,
+                          bytes_per_step=r["bytes"], bytes_per_cell_update=r["bytes"] / pb.cells,
+                          achieved=r["step_achieved"] / 1e9, frac=r["step_achieved"] / PEAK_HBM,
+                          launch_ms=[round(x["ms"], 4) for x in r["prof"]],
+                          launch_cells=[x["cells"] for x in r["prof"]]))
     forms = {}
     if not args.no_forms:
         log("2d ...")

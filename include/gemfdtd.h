@@ -203,6 +203,23 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out);
  * (synchronises).  *launches receives the number of kernel launches. */
 int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches);
 
+/* Per-launch timing of the step.  Advances the state by `steps` steps like
+ * fdtd_step, with a HIP event pair around every kernel launch of the 3D
+ * fused step (the interior, x/y-slab and z-end-range launches), or around
+ * the whole step for the other steppers, and writes one entry per launch
+ * (at most `max`) with the mean duration over the steps; *n receives the
+ * number of entries.  cells: cells the entry updates; cpml: 1 if the
+ * launch runs CPML code, 0 if not, -1 for a whole step; launches: kernel
+ * launches in the entry.  The events add a small gap between launches. */
+typedef struct {
+    float ms;
+    int64_t cells;
+    int32_t cpml;
+    int32_t launches;
+} fdtd_launch_stat;
+int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32_t max,
+                      int32_t *n);
+
 /* --------------------------------------------------------------------- */
 /* Batched form: many independent 2D problems of different sizes advanced  */
 /* together, one launch per time block over a packed arena, captured in a  */

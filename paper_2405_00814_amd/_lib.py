@@ -45,6 +45,10 @@ class fdtd_kernel_config(C.Structure):
     _fields_ = [("variant", C.c_int32), ("tile", C.c_int32 * 4), ("tb", C.c_int32)]
 
 
+class fdtd_launch_stat(C.Structure):
+    _fields_ = [("ms", C.c_float), ("cells", C.c_int64), ("cpml", C.c_int32), ("launches", C.c_int32)]
+
+
 class FdtdError(RuntimeError):
     def __init__(self, code, where, msg):
         super().__init__("%s failed: %s (%s)" % (where, msg, STATUS_NAMES.get(code, code)))
@@ -76,6 +80,7 @@ _SIGS = {
     "fdtd_get_kernel": (C.c_int, [P, C.POINTER(fdtd_kernel_config)]),
     "fdtd_autotune": (C.c_int, [P, i32, C.POINTER(fdtd_kernel_config)]),
     "fdtd_last_step_time": (C.c_int, [P, C.POINTER(C.c_float), i64p]),
+    "fdtd_step_profile": (C.c_int, [P, i32, C.POINTER(fdtd_launch_stat), i32, i32p]),
     "fdtd_batch_create": (C.c_int, [C.POINTER(fdtd_desc), i32, C.POINTER(P)]),
     "fdtd_batch_destroy": (C.c_int, [P]),
     "fdtd_batch_set_source": (C.c_int, [P, i32, i32p, C.c_int, f64p, f32p, i64]),

@@ -121,6 +121,7 @@ struct Wave3DLaunch {
     int kbase, klim;  // z range covered
     int nkz, njt;     // z segments per (plane, band); bands of 4*64/LZ rows
     int off, n;       // tile list entries [off, off + n) (multiple of 8)
+    int64_t cells;    // cells the launch updates
 };
 struct Wave3DPlan {
     std::vector<Wave3DLaunch> l;
@@ -128,8 +129,11 @@ struct Wave3DPlan {
 };
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl);
+// ev (optional): pl.l.size() + 1 events, recorded before each launch and
+// after the last one.
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tiles,
-                          const ProbeTiles &pt, int64_t step, hipStream_t st);
+                          const ProbeTiles &pt, int64_t step, hipStream_t st,
+                          hipEvent_t *ev = nullptr);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

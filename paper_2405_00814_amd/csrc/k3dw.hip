@@ -476,7 +476,11 @@ static void add_launch(Wave3DPlan &pl, int nx, int ny, int V, int LZ, bool pxy, 
                     ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
                 const bool outer = xs || ys;
                 if ((want == 0 && outer) || (want == 1 && !outer)) continue;
-                for (int kt = 0; kt < nkz; ++kt) pl.tiles.push_back((i * njt + jt) * nkz + kt);
+                const int rows = std::min(RB, ny - jt * RB);
+                for (int kt = 0; kt < nkz; ++kt) {
+                    pl.tiles.push_back((i * njt + jt) * nkz + kt);
+                    l.cells += (int64_t)rows * std::min(LZ * V, klim - kbase - kt * LZ * V);
+                }
             }
         }
     if (pl.tiles.size() == (size_t)l.off) return;
@@ -552,8 +556,13 @@ static void go_cell_v(const Prob3D &p, const Wave3DLaunch &l, const int *tiles, 
 }
 
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tiles, const ProbeTiles &pt,
-                          int64_t step, hipStream_t st) {
+                          int64_t step, hipStream_t st, hipEvent_t *ev) {
+    int q = 0;
     for (const Wave3DLaunch &l : pl.l) {
+        if (ev) {
+            const hipError_t e = hipEventRecord(ev[q++], st);
+            if (e != hipSuccess) return e;
+        }
         if (l.LZ == 64) {
             if (l.V == 4) go_cell_v<4, 64>(p, l, tiles, pt, step, st);
             else if (l.V == 2) go_cell_v<2, 64>(p, l, tiles, pt, step, st);
@@ -568,6 +577,10 @@ hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tile
         } else {
             return hipErrorInvalidValue;
         }
+    }
+    if (ev) {
+        const hipError_t e = hipEventRecord(ev[q], st);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

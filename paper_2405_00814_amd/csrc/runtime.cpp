@@ -336,7 +336,7 @@ void Sim::launch_step(int64_t step) {
         hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
                   "2d fused step");
     } else {
-        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st), "3d fused step");
+        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev), "3d fused step");
     }
     cur = 1 - cur;
     last_launches += ndim == 2 ? 1 : (int64_t)plan3.l.size();
@@ -824,6 +824,73 @@ int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches) {
     hip_check(hipEventSynchronize(s.ev1), "event sync");
     hip_check(hipEventElapsedTime(ms, s.ev0, s.ev1), "elapsed");
     if (launches) *launches = s.last_launches;
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32_t max, int32_t *n) {
+    GEM_TRY
+    if (!sim || !n) fail(FDTD_EINVAL, "NULL argument");
+    if (steps < 1 || steps > 100000) fail(FDTD_EINVAL, "steps must be in [1, 100000]");
+    if (max < 0 || (max > 0 && !out)) fail(FDTD_EINVAL, "bad output array");
+    Sim &s = sim->s;
+    s.ensure_source(s.n_done + steps);
+    s.ensure_rec(s.n_rec + steps);
+    s.build_probe_tiles();
+    const bool split = s.ndim == 3 && !s.is_graph && s.kcfg.variant == 2;
+    const size_t nl = split ? s.plan3.l.size() : 1;
+    // all events of all steps are recorded first; one synchronisation at the end
+    std::vector<hipEvent_t> ev((nl + 1) * (size_t)steps, nullptr);
+    struct Guard {
+        std::vector<hipEvent_t> &e;
+        Sim &s;
+        ~Guard() {
+            s.lev = nullptr;
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } guard{ev, s};
+    for (auto &e : ev) hip_check(hipEventCreate(&e), "event");
+    int64_t launches = 0;
+    for (int32_t q = 0; q < steps; ++q) {
+        hipEvent_t *e = ev.data() + (nl + 1) * (size_t)q;
+        s.last_launches = 0;
+        if (split) {
+            s.lev = e;
+        } else {
+            hip_check(hipEventRecord(e[0], s.st), "event");
+        }
+        s.launch_step(s.n_done);
+        s.lev = nullptr;
+        if (!split) hip_check(hipEventRecord(e[1], s.st), "event");
+        s.n_done += 1;
+        if (!s.probe_cells.empty()) s.n_rec += 1;
+        launches = s.last_launches;
+    }
+    hip_check(hipEventSynchronize(ev.back()), "event sync");
+    std::vector<double> acc(nl, 0.0);
+    for (int32_t q = 0; q < steps; ++q)
+        for (size_t l = 0; l < nl; ++l) {
+            float ms = 0;
+            const size_t b = (nl + 1) * (size_t)q + l;
+            hip_check(hipEventElapsedTime(&ms, ev[b], ev[b + 1]), "elapsed");
+            acc[l] += ms;
+        }
+    *n = (int32_t)nl;
+    for (size_t l = 0; l < nl && (int32_t)l < max; ++l) {
+        fdtd_launch_stat &o = out[l];
+        o.ms = (float)(acc[l] / steps);
+        if (split) {
+            const Wave3DLaunch &w = s.plan3.l[l];
+            o.cells = w.cells;
+            o.cpml = (w.pxy || w.pz) ? 1 : 0;
+            o.launches = 1;
+        } else {
+            o.cells = s.ncell;
+            o.cpml = -1;
+            o.launches = (int32_t)launches;
+        }
+    }
     return FDTD_OK;
     GEM_CATCH
 }

@@ -103,6 +103,7 @@ struct Sim {
     bool kcfg_explicit = false;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t *lev = nullptr;  // per-launch events of a profiled step (3D fused)
     bool timed = false;
     int64_t last_launches = 0;
 

@@ -279,3 +279,29 @@ def test_yee3d_tm_mode_recurrence_on_gpu():
     err = np.abs(rec[:, 2:] + rec[:, :-2] - 2 * math.cos(w) * rec[:, 1:-1]).max()
     assert err / np.abs(rec).max() < 2e-5
     s.close()
+
+
+def test_step_profile_matches_step():
+    """Per-launch profiling advances the state exactly like fdtd_step, and its
+    launches cover every cell once."""
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.yee3d(shape=(40, 44, 96), steps=30, seed=4, nbox=6, side=(3, 10), npml=6, nprobes=3,
+                 tau_steps=6.0)
+    a = Sim.from_problem(pb)
+    b = Sim.from_problem(pb)
+    a.step(7)
+    a.step(23)
+    b.step(7)
+    prof = b.step_profile(23)
+    assert sum(p["cells"] for p in prof) == pb.cells
+    assert len(prof) >= 3 and [p["cpml"] for p in prof].count(0) == 1
+    assert all(p["ms"] > 0 and p["launches"] == 1 for p in prof)
+    assert b.steps_done() == 30
+    for f in ("ex", "ey", "ez", "hx", "hy", "hz"):
+        assert np.array_equal(a.get_field(f), b.get_field(f)), f
+    assert np.array_equal(a.probe(), b.probe())
+    a.set_kernel(1)
+    prof = a.step_profile(2)
+    assert len(prof) == 1 and prof[0]["cpml"] == -1 and prof[0]["cells"] == pb.cells
+    a.close()
+    b.close()
