@@ -180,8 +180,9 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    must be 0), tile[1] = TX (x rows marched by one wavefront).
  *    3D fused: tile[0] = V (1, 2 or 4 consecutive z cells per thread;
  *    nz % V must be 0); tile[1] = the same for the z ranges next to the
- *    z CPML slabs (0 = default; nz % tile[1] must be 0); tile[2..3] must
- *    be 0.
+ *    z CPML slabs (0 = default; nz % tile[1] must be 0); tile[2] = x
+ *    planes marched by one workgroup (0 = 16, at most 4096); tile[3]
+ *    must be 0.
  * FDTD_EINVAL for unknown or unsupported combinations. */
 typedef struct {
     int32_t variant;

@@ -110,28 +110,32 @@ int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
 
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
-// Fused 3D: one workgroup covers 4 y rows x 64*V z cells of one x plane.
-// V: z cells per thread in the middle z range; Ve: in the z-slab end
-// ranges (0 = the widest of 4, 2, 1 dividing nz).
-struct Fused3DCfg { int V; int Ve; };
-// One launch of the fused 3D kernel over a list of workgroup tiles.
+// Fused 3D.  V: z cells per thread in the middle z range; Ve: in the z-slab
+// end ranges (0 = 1); TX: x planes marched by one interior workgroup
+// (0 = 16; workgroups with CPML code march max(1, TX/4).
+struct Fused3DCfg { int V; int Ve; int TX; };
+// One workgroup's tile: planes [i0, i1), rows from j0 (4*64/LZ of them),
+// z cells [ks, k1) of the segment whose lanes start at the aligned base k0.
+// i0 == i1 marks padding.
+struct Tile3 {
+    int i0, i1, j0, k0, k1, ks, pad[2];
+};
+// One launch of the fused 3D kernel over a list of tiles.
 struct Wave3DLaunch {
-    int V, LZ;        // z cells per thread, threads per z row (64, or 16/V)
-    bool pxy, pz;     // CPML code for x/y slabs, z slabs
-    int kbase, klim;  // z range covered
-    int nkz, njt;     // z segments per (plane, band); bands of 4*64/LZ rows
-    int off, n;       // tile list entries [off, off + n) (multiple of 8)
-    int64_t cells;    // cells the launch updates
+    int V, LZ;     // z cells per thread, threads per z row (64, or 16/V)
+    bool pxy, pz;  // CPML code for x/y slabs, z slabs
+    int off, n;    // tile list entries [off, off + n) (multiple of 8)
+    int64_t cells; // cells the launch updates
 };
 struct Wave3DPlan {
     std::vector<Wave3DLaunch> l;
-    std::vector<int> tiles;  // host copy of the concatenated tile lists
+    std::vector<Tile3> tiles;  // host copy of the concatenated tile lists
 };
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl);
 // ev (optional): pl.l.size() + 1 events, recorded before each launch and
 // after the last one.
-hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tiles,
+hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles,
                           const ProbeTiles &pt, int64_t step, hipStream_t st,
                           hipEvent_t *ev = nullptr);
 int wave3d_ngroups(int nx, int ny);

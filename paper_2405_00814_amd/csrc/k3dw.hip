@@ -1,19 +1,26 @@
-// Fused single-pass 3D Yee step: one V-wide z vector (V = 4 cells) per
-// thread, every thread independent (no LDS, no block barriers, no loop).
+// Fused single-pass 3D Yee step (H layer, then E layer, CPML, source and
+// probes in one kernel).  No LDS and no block barriers.
 //
-// Each thread owns cells (i, j, kb .. kb+V-1) and writes H^{n+1/2} and
-// E^{n+1} there.  The E layer of its cells needs H of the neighbours at
-// i-1, j-1 and k-1; those are recomputed from loads of the old state (the
-// rows j-1 and the plane i-1 are read again by this thread; they are the
-// neighbouring threads' own data and come from the caches).  Along z the
-// neighbours are the next/previous value in the vector or, across lanes, a
-// shuffle; the wavefront's two ends read E at z = k0+64V (lane 63) and
-// recompute Hx, Hy at z = k0-1 (lane 0).  State is double buffered (read
-// s0, write s1), so the recomputed values equal the owners' values.
+// A thread owns V consecutive z cells of one y row and marches through the
+// x planes i0 .. i1-1 of its tile.  At plane i it writes H^{n+1/2} and
+// E^{n+1} of its cells.  The E layer needs H of the neighbours at i-1, j-1
+// and k-1:
+//   i-1: the thread's own H of the previous plane, carried in registers
+//        (recomputed from the old state for the first plane of the tile);
+//   j-1: recomputed from the old state of row j-1 (that row is the
+//        neighbouring wavefront's own data and comes from the caches);
+//   k-1: the previous element of the vector, a lane shuffle, or (first
+//        active lane of a z segment) recomputed at z = ks-1.
+// The H layer needs E at i+1 (loaded once and carried to the next plane as
+// the own E), at j+1 and at k+1 (the next element, a shuffle or, for the
+// segment's last lane, a load).  State is double buffered (read s0, write
+// s1), so every recomputed value equals its owner's value bit for bit.
 //
-// Grid: one workgroup per (z segment of 64V, 4 y rows, x plane), issued so
-// that each XCD takes a contiguous range of x planes (the plane i-1 read by
-// a workgroup was just produced by its own XCD).
+// Tiles: (x range, band of 4*64/LZ y rows, z segment of LZ*V cells).  The
+// interior tiles (no CPML slab touched) run an instance without any CPML
+// code; tiles that touch an x or y slab, or a z slab, run instances with that
+// code.  The z-slab end ranges use short segments (LZ = 16/V lanes per z row)
+// so that the interior segments stay clear of them.
 #include "common.hpp"
 #include "devutil.hpp"
 
@@ -59,7 +66,7 @@ __device__ __forceinline__ float znext(const float (&x)[V], int q, float seam, b
 }
 
 // 1/(kappa dz) for the V cells of a lane: a vector load of the profile, or
-// (no z slab anywhere in the tile) the uniform value at k0.
+// (no z slab anywhere in the tile) the uniform value at an index k0 of the tile.
 template <int V, bool PZ>
 __device__ __forceinline__ void zprof(float (&r)[V], const float *t, int kb, int k0, bool ok) {
     if (PZ) {
@@ -76,35 +83,29 @@ __device__ __forceinline__ void zprof(float (&r)[V], const float *t, int kb, int
 }
 
 // MAT: 0 = Cb map only, 1 = Ca and Cb maps, 2 = Ca, Cb and Db maps.
-// PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A workgroup
-// whose cells and recomputed neighbours (plane i-1, row j-1, z = k0-1) touch
-// no x or y slab may run PXY = false, none touching a z slab PZ = false.
-// Tile ids come from a list (entries < 0 are padding) or, with no list,
-// from the block index.
+// PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A tile whose
+// cells and recomputed neighbours (plane i0-1, row j-1, z = ks-1) touch no x
+// or y slab may run PXY = false, none touching a z slab PZ = false.
 template <int V, int LZ, bool PXY, bool PZ, int MAT>
-__global__ __launch_bounds__(256) void k3d_cell(Prob3D p, int nkz, int njt, int kbase, int klim,
-                                                const int *tiles, ProbeTiles pt, int64_t step) {
+__global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, ProbeTiles pt,
+                                                 int64_t step) {
     constexpr int RW = 64 / LZ;  // y rows per wavefront
+    const Tile3 T = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    if (T.i0 >= T.i1) return;  // padding
     const int lane = threadIdx.x & 63;
     const int zlane = lane & (LZ - 1);
-    const int bl = xcd_block(blockIdx.x, gridDim.x);
-    const int L = tiles ? tiles[bl] : bl;
-    if (L < 0) return;
-    const int kt = L % nkz;
-    const int jt = (L / nkz) % njt;
-    const int i = L / (nkz * njt);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int j = LZ == 64 ? jt * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
-                           : jt * 4 * RW + (int)(threadIdx.x >> 6) * RW + lane / LZ;
-    const int k0 = kbase + kt * LZ * V, kb = k0 + zlane * V, km = k0 - 1;
-    const int kend = min(k0 + LZ * V, klim);
-    const bool ok = j < ny && kb < kend;  // segment lengths are multiples of V
-    const bool xi = i + 1 < nx, yj = j + 1 < ny, im = i >= 1, jm = j >= 1;
+    const int j = LZ == 64 ? T.j0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
+                           : T.j0 + (int)(threadIdx.x >> 6) * RW + lane / LZ;
+    // z segment: lanes from the aligned base T.k0, active on [ks, kend)
+    const int ks = T.ks, kend = T.k1, kb = T.k0 + zlane * V, km = ks - 1;
+    const bool ok = j < ny && kb >= ks && kb < kend;  // ks, kend: multiples of V
+    const bool first = kb == ks;
+    const bool yj = j + 1 < ny, jm = j >= 1;
     const bool ke = kend < nz;
-    const bool last = kb + V == kend;  // zlane LZ-1 unless the segment is cut at klim
+    const bool last = kb + V == kend;  // zlane LZ-1 unless the segment is cut short
     const unsigned sxs = (unsigned)ny * nz, sys = nz;
-    const unsigned r0 = ((unsigned)i * ny + (j < ny ? j : 0)) * nz;  // row (i, j)
-    const unsigned c = r0 + kb;
+    const int jr = j < ny ? j : 0;
     const int sy = p.y.lo + p.y.hi, sz = p.z.lo + p.z.hi;
     const float *ex0 = p.s0.f[FDTD_EX], *ey0 = p.s0.f[FDTD_EY], *ez0 = p.s0.f[FDTD_EZ];
     const float *hx0 = p.s0.f[FDTD_HX], *hy0 = p.s0.f[FDTD_HY], *hz0 = p.s0.f[FDTD_HZ];
@@ -118,317 +119,342 @@ __global__ __launch_bounds__(256) void k3d_cell(Prob3D p, int nkz, int njt, int 
         if (cond) ldv<V>(a, base + off);
         else zero(a);
     };
-    // z-slab index of cell kb+v (-1 outside, or without z slabs)
-    auto zsl = [&](int v) { return (PZ && ok) ? slab_index(p.z, kb + v) : -1; };
-
-    // x and y profiles (wave-uniform)
-    const AxP X = axp<PXY>(p.x, i), Xm = axp<PXY>(p.x, im ? i - 1 : 0);
-    const AxP Y = axp<PXY>(p.y, j < ny ? j : 0), Ym = axp<PXY>(p.y, jm && j < ny ? j - 1 : 0);
-
-    // ---- E and H at the own cells; E at (i+1), (j+1) ----
-    float ex[V], ey[V], ez[V], ey_x[V], ez_x[V], ex_y[V], ez_y[V], hxo[V], hyo[V], hzo[V];
-    float db[V], cb[V], ca[V];
-    ld(ex, ex0, c, ok);
-    ld(ey, ey0, c, ok);
-    ld(ez, ez0, c, ok);
-    ld(ey_x, ey0, c + sxs, ok && xi);
-    ld(ez_x, ez0, c + sxs, ok && xi);
-    ld(ex_y, ex0, c + sys, ok && yj);
-    ld(ez_y, ez0, c + sys, ok && yj);
-    ld(hxo, hx0, c, ok);
-    ld(hyo, hy0, c, ok);
-    ld(hzo, hz0, c, ok);
-    ld(cb, p.cb, c, ok);
+    int zsv[V];  // z-slab index of cell kb+v (-1 outside, or without z slabs)
 #pragma unroll
-    for (int v = 0; v < V; ++v) { ca[v] = 1.f; db[v] = p.db0; }
-    if (MAT >= 1 && ok) ldv<V>(ca, p.ca + c);
-    if (MAT == 2 && ok) ldv<V>(db, p.db + c);
-    const bool s63 = ok && last && ke;
-    const float ey_e = s63 ? ey0[r0 + kend] : 0.f;
-    const float ex_e = s63 ? ex0[r0 + kend] : 0.f;
-    float zkH[V], zbH[V], zcH[V];
-    zprof<V, PZ>(zkH, p.z.kH, kb, k0, ok);
-    ld(zbH, p.z.bH, kb, PZ && ok);
-    ld(zcH, p.z.cH, kb, PZ && ok);
-    // z-slab psi: the old values of a section are loaded together up front
-    // (lanes outside the slab read element 0) so that the loads overlap
-    int zsv[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) zsv[v] = zsl(v);
+    for (int v = 0; v < V; ++v) zsv[v] = (PZ && ok) ? slab_index(p.z, kb + v) : -1;
 
-    // ---- H layer at the own cells ----
-    float hx[V], hy[V], hz[V];
+    // y profiles (wave-uniform for LZ = 64)
+    const AxP Y = axp<PXY>(p.y, jr), Ym = axp<PXY>(p.y, jm && j < ny ? j - 1 : 0);
+
+    // carried between planes: E (y, z) of the current plane and H (y, z) of
+    // the previous one
+    float eyc[V], ezc[V], hyp[V], hzp[V];
     {
-        float pxy[V], pzx[V], pyx[V], pzy[V];  // x/y-slab psi (vector rows)
-        const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
-        const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
-        ld(pxy, P0[PSI_HXY], qy, iny);
-        ld(pzy, P0[PSI_HZY], qy, iny);
-        ld(pyx, P0[PSI_HYX], qx, inx);
-        ld(pzx, P0[PSI_HZX], qx, inx);
-        unsigned qz[V];
-        float oxz[V], oyz[V];
+        const int i = T.i0;
+        const unsigned r0 = ((unsigned)i * ny + jr) * nz, c = r0 + kb;
+        ld(eyc, ey0, c, ok);
+        ld(ezc, ez0, c, ok);
+        // ---- Hy, Hz at (i0-1, j) from the old state ----
+        zero(hyp);
+        zero(hzp);
+        if (i >= 1) {  // uniform over the workgroup
+            const bool o = ok;
+            const unsigned q0 = c - sxs;
+            const AxP Xm = axp<PXY>(p.x, i - 1);
+            float aex[V], aey[V], aez[V], aexy[V], ahy[V], ahz[V], adb[V];
+            ld(aex, ex0, q0, o);
+            ld(aey, ey0, q0, o);
+            ld(aez, ez0, q0, o);
+            ld(aexy, ex0, q0 + sys, o && yj);
+            ld(ahy, hy0, q0, o);
+            ld(ahz, hz0, q0, o);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
-            oxz[v] = PZ ? P0[PSI_HXZ][qz[v]] : 0.f;
-            oyz[v] = PZ ? P0[PSI_HYZ][qz[v]] : 0.f;
-        }
+            for (int v = 0; v < V; ++v) adb[v] = p.db0;
+            if (MAT == 2 && o) ldv<V>(adb, p.db + q0);
+            const float aex_e = (o && last && ke) ? ex0[r0 - sxs + kend] : 0.f;
+            float zkH[V], zbH[V], zcH[V];
+            zprof<V, PZ>(zkH, p.z.kH, kb, ks, o);
+            ld(zbH, p.z.bH, kb, PZ && o);
+            ld(zcH, p.z.cH, kb, PZ && o);
+            float pyx[V], pzx[V], pzy[V], oyz[V];
+            const bool inx = PXY && o && Xm.s >= 0, iny = PXY && o && Y.s >= 0;
+            const unsigned qx = inx ? xs3(Xm.s, j, kb, ny, nz) : 0, qy = iny ? ys3(i - 1, Y.s, kb, sy, nz) : 0;
+            ld(pyx, P0[PSI_HYX], qx, inx);
+            ld(pzx, P0[PSI_HZX], qx, inx);
+            ld(pzy, P0[PSI_HZY], qy, iny);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const float dEzy = ez_y[v] - ez[v];
-            const float dEyz = znext<V>(ey, v, ey_e, last) - ey[v];
-            const float dExz = znext<V>(ex, v, ex_e, last) - ex[v];
-            const float dEzx = ez_x[v] - ez[v];
-            const float dEyx = ey_x[v] - ey[v];
-            const float dExy = ex_y[v] - ex[v];
-            if (iny) { pxy[v] = Y.bH * pxy[v] + Y.cH * dEzy; pzy[v] = Y.bH * pzy[v] + Y.cH * dExy; }
-            if (inx) { pyx[v] = X.bH * pyx[v] + X.cH * dEzx; pzx[v] = X.bH * pzx[v] + X.cH * dEyx; }
-            float pxz = 0.f, pyz = 0.f;
-            if (zsv[v] >= 0) {
-                pxz = zbH[v] * oxz[v] + zcH[v] * dEyz;
-                pyz = zbH[v] * oyz[v] + zcH[v] * dExz;
-                P1[PSI_HXZ][qz[v]] = pxz;
-                P1[PSI_HYZ][qz[v]] = pyz;
-            }
-            hx[v] = hxo[v] - db[v] * ((Y.kH * dEzy + (iny ? pxy[v] : 0.f)) - (zkH[v] * dEyz + pxz));
-            hy[v] = hyo[v] - db[v] * ((zkH[v] * dExz + pyz) - (X.kH * dEzx + (inx ? pyx[v] : 0.f)));
-            hz[v] = hzo[v] - db[v] * ((X.kH * dEyx + (inx ? pzx[v] : 0.f)) - (Y.kH * dExy + (iny ? pzy[v] : 0.f)));
-        }
-        if (iny) { stv<V>(P1[PSI_HXY] + qy, pxy); stv<V>(P1[PSI_HZY] + qy, pzy); }
-        if (inx) { stv<V>(P1[PSI_HYX] + qx, pyx); stv<V>(P1[PSI_HZX] + qx, pzx); }
-    }
-
-    // ---- Hy, Hz at (i-1, j) ----
-    float hy_im[V], hz_im[V];
-    zero(hy_im);
-    zero(hz_im);
-    {
-        const bool o = ok && im;
-        const unsigned q0 = c - (im ? sxs : 0u);
-        float aex[V], aey[V], aez[V], aexy[V], ahy[V], ahz[V], adb[V];
-        ld(aex, ex0, q0, o);
-        ld(aey, ey0, q0, o);
-        ld(aez, ez0, q0, o);
-        ld(aexy, ex0, q0 + sys, o && yj);
-        ld(ahy, hy0, q0, o);
-        ld(ahz, hz0, q0, o);
+            for (int v = 0; v < V; ++v)
+                oyz[v] = (PZ && o) ? P0[PSI_HYZ][zsv[v] >= 0 ? zs3(i - 1, j, zsv[v], ny, sz) : 0u] : 0.f;
 #pragma unroll
-        for (int v = 0; v < V; ++v) adb[v] = p.db0;
-        if (MAT == 2 && o) ldv<V>(adb, p.db + q0);
-        const float aex_e = (o && last && ke) ? ex0[r0 - sxs + kend] : 0.f;
-        float pyx[V], pzx[V], pzy[V];
-        const bool inx = PXY && o && Xm.s >= 0, iny = PXY && o && Y.s >= 0;
-        const unsigned qx = inx ? xs3(Xm.s, j, kb, ny, nz) : 0, qy = iny ? ys3(i - 1, Y.s, kb, sy, nz) : 0;
-        ld(pyx, P0[PSI_HYX], qx, inx);
-        ld(pzx, P0[PSI_HZX], qx, inx);
-        ld(pzy, P0[PSI_HZY], qy, iny);
-        float oyz[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-            oyz[v] = (PZ && o) ? P0[PSI_HYZ][zsv[v] >= 0 ? zs3(i - 1, j, zsv[v], ny, sz) : 0u] : 0.f;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const float dExz = znext<V>(aex, v, aex_e, last) - aex[v];
-            const float dEzx = ez[v] - aez[v];
-            const float dEyx = ey[v] - aey[v];
-            const float dExy = aexy[v] - aex[v];
-            const float pyz = zsv[v] >= 0 ? zbH[v] * oyz[v] + zcH[v] * dExz : 0.f;
-            const float vyx = inx ? Xm.bH * pyx[v] + Xm.cH * dEzx : 0.f;
-            const float vzx = inx ? Xm.bH * pzx[v] + Xm.cH * dEyx : 0.f;
-            const float vzy = iny ? Y.bH * pzy[v] + Y.cH * dExy : 0.f;
-            if (o) {
-                hy_im[v] = ahy[v] - adb[v] * ((zkH[v] * dExz + pyz) - (Xm.kH * dEzx + vyx));
-                hz_im[v] = ahz[v] - adb[v] * ((Xm.kH * dEyx + vzx) - (Y.kH * dExy + vzy));
-            }
-        }
-    }
-
-    // ---- Hx, Hz at (i, j-1) ----
-    float hx_jm[V], hz_jm[V];
-    zero(hx_jm);
-    zero(hz_jm);
-    {
-        const bool o = ok && jm;
-        const unsigned q0 = c - (jm ? sys : 0u);
-        float aex[V], aey[V], aez[V], aeyx[V], ahx[V], ahz[V], adb[V];
-        ld(aex, ex0, q0, o);
-        ld(aey, ey0, q0, o);
-        ld(aez, ez0, q0, o);
-        ld(aeyx, ey0, q0 + sxs, o && xi);
-        ld(ahx, hx0, q0, o);
-        ld(ahz, hz0, q0, o);
-#pragma unroll
-        for (int v = 0; v < V; ++v) adb[v] = p.db0;
-        if (MAT == 2 && o) ldv<V>(adb, p.db + q0);
-        const float aey_e = (o && last && ke) ? ey0[r0 - sys + kend] : 0.f;
-        float pxy[V], pzy[V], pzx[V];
-        const bool iny = PXY && o && Ym.s >= 0, inx = PXY && o && X.s >= 0;
-        const unsigned qy = iny ? ys3(i, Ym.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j - 1, kb, ny, nz) : 0;
-        ld(pxy, P0[PSI_HXY], qy, iny);
-        ld(pzy, P0[PSI_HZY], qy, iny);
-        ld(pzx, P0[PSI_HZX], qx, inx);
-        float oxz[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-            oxz[v] = (PZ && o) ? P0[PSI_HXZ][zsv[v] >= 0 ? zs3(i, j - 1, zsv[v], ny, sz) : 0u] : 0.f;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const float dEzy = ez[v] - aez[v];
-            const float dEyz = znext<V>(aey, v, aey_e, last) - aey[v];
-            const float dEyx = aeyx[v] - aey[v];
-            const float dExy = ex[v] - aex[v];
-            const float pxz = zsv[v] >= 0 ? zbH[v] * oxz[v] + zcH[v] * dEyz : 0.f;
-            const float vxy = iny ? Ym.bH * pxy[v] + Ym.cH * dEzy : 0.f;
-            const float vzy = iny ? Ym.bH * pzy[v] + Ym.cH * dExy : 0.f;
-            const float vzx = inx ? X.bH * pzx[v] + X.cH * dEyx : 0.f;
-            if (o) {
-                hx_jm[v] = ahx[v] - adb[v] * ((Ym.kH * dEzy + vxy) - (zkH[v] * dEyz + pxz));
-                hz_jm[v] = ahz[v] - adb[v] * ((X.kH * dEyx + vzx) - (Ym.kH * dExy + vzy));
-            }
-        }
-    }
-
-    // ---- Hx, Hy at z = k0-1 (lane 0), then the z-1 neighbours ----
-    float hx_l = 0.f, hy_l = 0.f;
-    if (ok && zlane == 0 && km >= 0) {
-        const unsigned q0 = r0 + km;
-        const float lex = ex0[q0], ley = ey0[q0], lez = ez0[q0];
-        const float lezy = yj ? ez0[q0 + sys] : 0.f;
-        const float lezx = xi ? ez0[q0 + sxs] : 0.f;
-        const float ldb = MAT == 2 ? p.db[q0] : p.db0;
-        const float zmk = p.z.kH[km];
-        const float dEzy = lezy - lez, dEyz = ey[0] - ley;
-        const float dExz = ex[0] - lex, dEzx = lezx - lez;
-        float a = Y.kH * dEzy, b = zmk * dEyz;
-        float a2 = zmk * dExz, b2 = X.kH * dEzx;
-        if (PXY) {
-            if (Y.s >= 0) a += Y.bH * P0[PSI_HXY][ys3(i, Y.s, km, sy, nz)] + Y.cH * dEzy;
-            if (X.s >= 0) b2 += X.bH * P0[PSI_HYX][xs3(X.s, j, km, ny, nz)] + X.cH * dEzx;
-        }
-        if (PZ) {
-            const int zs = slab_index(p.z, km);
-            if (zs >= 0) {
-                const unsigned qz = zs3(i, j, zs, ny, sz);
-                const float zb = p.z.bH[km], zc = p.z.cH[km];
-                b += zb * P0[PSI_HXZ][qz] + zc * dEyz;
-                a2 += zb * P0[PSI_HYZ][qz] + zc * dExz;
-            }
-        }
-        hx_l = hx0[q0] - ldb * (a - b);
-        hy_l = hy0[q0] - ldb * (a2 - b2);
-    }
-    float hxm[V], hym[V];
-#pragma unroll
-    for (int v = 1; v < V; ++v) {
-        hxm[v] = hx[v - 1];
-        hym[v] = hy[v - 1];
-    }
-    {
-        const float s1 = __shfl_up(hx[V - 1], 1), s2 = __shfl_up(hy[V - 1], 1);
-        hxm[0] = zlane == 0 ? hx_l : s1;
-        hym[0] = zlane == 0 ? hy_l : s2;
-    }
-
-    // ---- E layer at the own cells ----
-    float exw[V], eyw[V], ezw[V];
-    {
-        float zkE[V];
-        zprof<V, PZ>(zkE, p.z.kE, kb, k0, ok);
-        float zbE[V], zcE[V], oxz[V], oyz[V];
-        unsigned qz[V];
-        ld(zbE, p.z.bE, kb, PZ && ok);
-        ld(zcE, p.z.cE, kb, PZ && ok);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
-            oxz[v] = PZ ? P0[PSI_EXZ][qz[v]] : 0.f;
-            oyz[v] = PZ ? P0[PSI_EYZ][qz[v]] : 0.f;
-        }
-        float pxy[V], pzy[V], pyx[V], pzx[V];
-        const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
-        const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
-        ld(pxy, P0[PSI_EXY], qy, iny);
-        ld(pzy, P0[PSI_EZY], qy, iny);
-        ld(pyx, P0[PSI_EYX], qx, inx);
-        ld(pzx, P0[PSI_EZX], qx, inx);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const int k = kb + v;
-            exw[v] = ex[v];
-            eyw[v] = ey[v];
-            ezw[v] = ez[v];
-            const bool inz = zsv[v] >= 0;
-            const float dHzy = hz[v] - hz_jm[v], dHyz = hy[v] - hym[v];
-            const float dHxz = hx[v] - hxm[v], dHzx = hz[v] - hz_im[v];
-            const float dHyx = hy[v] - hy_im[v], dHxy = hx[v] - hx_jm[v];
-            if (jm && k >= 1) {
-                if (iny) pxy[v] = Y.bE * pxy[v] + Y.cE * dHzy;
-                float pxz = 0.f;
-                if (inz) {
-                    pxz = zbE[v] * oxz[v] + zcE[v] * dHyz;
-                    P1[PSI_EXZ][qz[v]] = pxz;
+            for (int v = 0; v < V; ++v) {
+                const float dExz = znext<V>(aex, v, aex_e, last) - aex[v];
+                const float dEzx = ezc[v] - aez[v];
+                const float dEyx = eyc[v] - aey[v];
+                const float dExy = aexy[v] - aex[v];
+                const float pyz = zsv[v] >= 0 ? zbH[v] * oyz[v] + zcH[v] * dExz : 0.f;
+                const float vyx = inx ? Xm.bH * pyx[v] + Xm.cH * dEzx : 0.f;
+                const float vzx = inx ? Xm.bH * pzx[v] + Xm.cH * dEyx : 0.f;
+                const float vzy = iny ? Y.bH * pzy[v] + Y.cH * dExy : 0.f;
+                if (o) {
+                    hyp[v] = ahy[v] - adb[v] * ((zkH[v] * dExz + pyz) - (Xm.kH * dEzx + vyx));
+                    hzp[v] = ahz[v] - adb[v] * ((Xm.kH * dEyx + vzx) - (Y.kH * dExy + vzy));
                 }
-                const float a = Y.kE * dHzy + (iny ? pxy[v] : 0.f), b = zkE[v] * dHyz + pxz;
-                exw[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * (a - b);
-            }
-            if (im && k >= 1) {
-                if (inx) pyx[v] = X.bE * pyx[v] + X.cE * dHzx;
-                float pyz = 0.f;
-                if (inz) {
-                    pyz = zbE[v] * oyz[v] + zcE[v] * dHxz;
-                    P1[PSI_EYZ][qz[v]] = pyz;
-                }
-                const float a = zkE[v] * dHxz + pyz, b = X.kE * dHzx + (inx ? pyx[v] : 0.f);
-                eyw[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * (a - b);
-            }
-            if (im && jm) {
-                if (inx) pzx[v] = X.bE * pzx[v] + X.cE * dHyx;
-                if (iny) pzy[v] = Y.bE * pzy[v] + Y.cE * dHxy;
-                const float a = X.kE * dHyx + (inx ? pzx[v] : 0.f), b = Y.kE * dHxy + (iny ? pzy[v] : 0.f);
-                ezw[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * (a - b);
-            }
-            if ((int64_t)(c + v) == p.src_idx && ok) {
-                const float sval = step < p.src_len ? p.src_vals[step] : 0.f;
-                if (p.src_comp == FDTD_EX) exw[v] += sval;
-                else if (p.src_comp == FDTD_EY) eyw[v] += sval;
-                else ezw[v] += sval;
             }
         }
-        // psi of cells the E layer does not update keep their (zero) value
-        if (iny) { stv<V>(P1[PSI_EXY] + qy, pxy); stv<V>(P1[PSI_EZY] + qy, pzy); }
-        if (inx) { stv<V>(P1[PSI_EYX] + qx, pyx); stv<V>(P1[PSI_EZX] + qx, pzx); }
     }
-    if (ok) {
-        stv<V>(p.s1.f[FDTD_EX] + c, exw);
-        stv<V>(p.s1.f[FDTD_EY] + c, eyw);
-        stv<V>(p.s1.f[FDTD_EZ] + c, ezw);
-        stv<V>(p.s1.f[FDTD_HX] + c, hx);
-        stv<V>(p.s1.f[FDTD_HY] + c, hy);
-        stv<V>(p.s1.f[FDTD_HZ] + c, hz);
-    }
-    // ---- probes owned by this workgroup (grouped by the cell's tile) ----
-    if (pt.start == nullptr) return;
-    const int g = i * ((ny + 3) / 4) + j / 4;  // probes grouped by (x plane, 4-row band)
-    const int pbeg = pt.start[g], pend = pt.start[g + 1];
-    for (int q = pbeg; q < pend; ++q) {
-        const int64_t cell = pt.cell[q];
-        if (!ok || cell < (int64_t)c || cell >= (int64_t)c + V) continue;
-        const int v = (int)(cell - c);
-        float val = 0.f;
+
+    for (int i = T.i0; i < T.i1; ++i) {
+        const bool xi = i + 1 < nx, im = i >= 1;
+        const unsigned r0 = ((unsigned)i * ny + jr) * nz;  // row (i, j)
+        const unsigned c = r0 + kb;
+        const AxP X = axp<PXY>(p.x, i);
+
+        // ---- E and H at the own cells; E at (i+1), (j+1) ----
+        float ex[V], ey[V], ez[V], ey_x[V], ez_x[V], ex_y[V], ez_y[V], hxo[V], hyo[V], hzo[V];
+        float db[V], cb[V], ca[V];
 #pragma unroll
-        for (int w = 0; w < V; ++w) {
-            if (w != v) continue;
-            switch (p.probe_comp) {
-                case FDTD_EX: val = exw[w]; break;
-                case FDTD_EY: val = eyw[w]; break;
-                case FDTD_EZ: val = ezw[w]; break;
-                case FDTD_HX: val = hx[w]; break;
-                case FDTD_HY: val = hy[w]; break;
-                default: val = hz[w]; break;
+        for (int v = 0; v < V; ++v) { ey[v] = eyc[v]; ez[v] = ezc[v]; }
+        ld(ex, ex0, c, ok);
+        ld(ey_x, ey0, c + sxs, ok && xi);
+        ld(ez_x, ez0, c + sxs, ok && xi);
+        ld(ex_y, ex0, c + sys, ok && yj);
+        ld(ez_y, ez0, c + sys, ok && yj);
+        ld(hxo, hx0, c, ok);
+        ld(hyo, hy0, c, ok);
+        ld(hzo, hz0, c, ok);
+        ld(cb, p.cb, c, ok);
+#pragma unroll
+        for (int v = 0; v < V; ++v) { ca[v] = 1.f; db[v] = p.db0; }
+        if (MAT >= 1 && ok) ldv<V>(ca, p.ca + c);
+        if (MAT == 2 && ok) ldv<V>(db, p.db + c);
+        const bool s63 = ok && last && ke;
+        const float ey_e = s63 ? ey0[r0 + kend] : 0.f;
+        const float ex_e = s63 ? ex0[r0 + kend] : 0.f;
+        float zkH[V], zbH[V], zcH[V];
+        zprof<V, PZ>(zkH, p.z.kH, kb, ks, ok);
+        ld(zbH, p.z.bH, kb, PZ && ok);
+        ld(zcH, p.z.cH, kb, PZ && ok);
+
+        // ---- H layer at the own cells ----
+        float hx[V], hy[V], hz[V];
+        {
+            float pxy[V], pzx[V], pyx[V], pzy[V];  // x/y-slab psi (vector rows)
+            const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
+            const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
+            ld(pxy, P0[PSI_HXY], qy, iny);
+            ld(pzy, P0[PSI_HZY], qy, iny);
+            ld(pyx, P0[PSI_HYX], qx, inx);
+            ld(pzx, P0[PSI_HZX], qx, inx);
+            // z-slab psi: loaded together up front (lanes outside the slab
+            // read element 0) so that the loads overlap
+            unsigned qz[V];
+            float oxz[V], oyz[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
+                oxz[v] = PZ ? P0[PSI_HXZ][qz[v]] : 0.f;
+                oyz[v] = PZ ? P0[PSI_HYZ][qz[v]] : 0.f;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float dEzy = ez_y[v] - ez[v];
+                const float dEyz = znext<V>(ey, v, ey_e, last) - ey[v];
+                const float dExz = znext<V>(ex, v, ex_e, last) - ex[v];
+                const float dEzx = ez_x[v] - ez[v];
+                const float dEyx = ey_x[v] - ey[v];
+                const float dExy = ex_y[v] - ex[v];
+                if (iny) { pxy[v] = Y.bH * pxy[v] + Y.cH * dEzy; pzy[v] = Y.bH * pzy[v] + Y.cH * dExy; }
+                if (inx) { pyx[v] = X.bH * pyx[v] + X.cH * dEzx; pzx[v] = X.bH * pzx[v] + X.cH * dEyx; }
+                float pxz = 0.f, pyz = 0.f;
+                if (zsv[v] >= 0) {
+                    pxz = zbH[v] * oxz[v] + zcH[v] * dEyz;
+                    pyz = zbH[v] * oyz[v] + zcH[v] * dExz;
+                    P1[PSI_HXZ][qz[v]] = pxz;
+                    P1[PSI_HYZ][qz[v]] = pyz;
+                }
+                hx[v] = hxo[v] - db[v] * ((Y.kH * dEzy + (iny ? pxy[v] : 0.f)) - (zkH[v] * dEyz + pxz));
+                hy[v] = hyo[v] - db[v] * ((zkH[v] * dExz + pyz) - (X.kH * dEzx + (inx ? pyx[v] : 0.f)));
+                hz[v] = hzo[v] - db[v] * ((X.kH * dEyx + (inx ? pzx[v] : 0.f)) - (Y.kH * dExy + (iny ? pzy[v] : 0.f)));
+            }
+            if (iny) { stv<V>(P1[PSI_HXY] + qy, pxy); stv<V>(P1[PSI_HZY] + qy, pzy); }
+            if (inx) { stv<V>(P1[PSI_HYX] + qx, pyx); stv<V>(P1[PSI_HZX] + qx, pzx); }
+        }
+
+        // ---- Hx, Hz at (i, j-1) from the old state ----
+        float hx_jm[V], hz_jm[V];
+        zero(hx_jm);
+        zero(hz_jm);
+        {
+            const bool o = ok && jm;
+            const unsigned q0 = c - (jm ? sys : 0u);
+            float aex[V], aey[V], aez[V], aeyx[V], ahx[V], ahz[V], adb[V];
+            ld(aex, ex0, q0, o);
+            ld(aey, ey0, q0, o);
+            ld(aez, ez0, q0, o);
+            ld(aeyx, ey0, q0 + sxs, o && xi);
+            ld(ahx, hx0, q0, o);
+            ld(ahz, hz0, q0, o);
+#pragma unroll
+            for (int v = 0; v < V; ++v) adb[v] = p.db0;
+            if (MAT == 2 && o) ldv<V>(adb, p.db + q0);
+            const float aey_e = (o && last && ke) ? ey0[r0 - sys + kend] : 0.f;
+            float pxy[V], pzy[V], pzx[V];
+            const bool iny = PXY && o && Ym.s >= 0, inx = PXY && o && X.s >= 0;
+            const unsigned qy = iny ? ys3(i, Ym.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j - 1, kb, ny, nz) : 0;
+            ld(pxy, P0[PSI_HXY], qy, iny);
+            ld(pzy, P0[PSI_HZY], qy, iny);
+            ld(pzx, P0[PSI_HZX], qx, inx);
+            float oxz[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                oxz[v] = (PZ && o) ? P0[PSI_HXZ][zsv[v] >= 0 ? zs3(i, j - 1, zsv[v], ny, sz) : 0u] : 0.f;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float dEzy = ez[v] - aez[v];
+                const float dEyz = znext<V>(aey, v, aey_e, last) - aey[v];
+                const float dEyx = aeyx[v] - aey[v];
+                const float dExy = ex[v] - aex[v];
+                const float pxz = zsv[v] >= 0 ? zbH[v] * oxz[v] + zcH[v] * dEyz : 0.f;
+                const float vxy = iny ? Ym.bH * pxy[v] + Ym.cH * dEzy : 0.f;
+                const float vzy = iny ? Ym.bH * pzy[v] + Ym.cH * dExy : 0.f;
+                const float vzx = inx ? X.bH * pzx[v] + X.cH * dEyx : 0.f;
+                if (o) {
+                    hx_jm[v] = ahx[v] - adb[v] * ((Ym.kH * dEzy + vxy) - (zkH[v] * dEyz + pxz));
+                    hz_jm[v] = ahz[v] - adb[v] * ((X.kH * dEyx + vzx) - (Ym.kH * dExy + vzy));
+                }
             }
         }
-        p.rec[(int64_t)pt.slot[q] * p.rec_stride + (step - p.rec_base)] = val;
+
+        // ---- Hx, Hy at z = ks-1 (first active lane of the segment), then the
+        // z-1 neighbours ----
+        float hx_l = 0.f, hy_l = 0.f;
+        if (ok && first && km >= 0) {
+            const unsigned q0 = r0 + km;
+            const float lex = ex0[q0], ley = ey0[q0], lez = ez0[q0];
+            const float lezy = yj ? ez0[q0 + sys] : 0.f;
+            const float lezx = xi ? ez0[q0 + sxs] : 0.f;
+            const float ldb = MAT == 2 ? p.db[q0] : p.db0;
+            const float zmk = p.z.kH[km];
+            const float dEzy = lezy - lez, dEyz = ey[0] - ley;
+            const float dExz = ex[0] - lex, dEzx = lezx - lez;
+            float a = Y.kH * dEzy, b = zmk * dEyz;
+            float a2 = zmk * dExz, b2 = X.kH * dEzx;
+            if (PXY) {
+                if (Y.s >= 0) a += Y.bH * P0[PSI_HXY][ys3(i, Y.s, km, sy, nz)] + Y.cH * dEzy;
+                if (X.s >= 0) b2 += X.bH * P0[PSI_HYX][xs3(X.s, j, km, ny, nz)] + X.cH * dEzx;
+            }
+            if (PZ) {
+                const int zs = slab_index(p.z, km);
+                if (zs >= 0) {
+                    const unsigned qz = zs3(i, j, zs, ny, sz);
+                    const float zb = p.z.bH[km], zc = p.z.cH[km];
+                    b += zb * P0[PSI_HXZ][qz] + zc * dEyz;
+                    a2 += zb * P0[PSI_HYZ][qz] + zc * dExz;
+                }
+            }
+            hx_l = hx0[q0] - ldb * (a - b);
+            hy_l = hy0[q0] - ldb * (a2 - b2);
+        }
+        float hxm[V], hym[V];
+#pragma unroll
+        for (int v = 1; v < V; ++v) {
+            hxm[v] = hx[v - 1];
+            hym[v] = hy[v - 1];
+        }
+        {
+            const float s1 = __shfl_up(hx[V - 1], 1), s2 = __shfl_up(hy[V - 1], 1);
+            hxm[0] = first ? hx_l : s1;
+            hym[0] = first ? hy_l : s2;
+        }
+
+        // ---- E layer at the own cells ----
+        float exw[V], eyw[V], ezw[V];
+        {
+            float zkE[V], zbE[V], zcE[V], oxz[V], oyz[V];
+            unsigned qz[V];
+            zprof<V, PZ>(zkE, p.z.kE, kb, ks, ok);
+            ld(zbE, p.z.bE, kb, PZ && ok);
+            ld(zcE, p.z.cE, kb, PZ && ok);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
+                oxz[v] = PZ ? P0[PSI_EXZ][qz[v]] : 0.f;
+                oyz[v] = PZ ? P0[PSI_EYZ][qz[v]] : 0.f;
+            }
+            float pxy[V], pzy[V], pyx[V], pzx[V];
+            const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
+            const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
+            ld(pxy, P0[PSI_EXY], qy, iny);
+            ld(pzy, P0[PSI_EZY], qy, iny);
+            ld(pyx, P0[PSI_EYX], qx, inx);
+            ld(pzx, P0[PSI_EZX], qx, inx);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k = kb + v;
+                exw[v] = ex[v];
+                eyw[v] = ey[v];
+                ezw[v] = ez[v];
+                const bool inz = zsv[v] >= 0;
+                const float dHzy = hz[v] - hz_jm[v], dHyz = hy[v] - hym[v];
+                const float dHxz = hx[v] - hxm[v], dHzx = hz[v] - hzp[v];
+                const float dHyx = hy[v] - hyp[v], dHxy = hx[v] - hx_jm[v];
+                if (jm && k >= 1) {
+                    if (iny) pxy[v] = Y.bE * pxy[v] + Y.cE * dHzy;
+                    float pxz = 0.f;
+                    if (inz) {
+                        pxz = zbE[v] * oxz[v] + zcE[v] * dHyz;
+                        P1[PSI_EXZ][qz[v]] = pxz;
+                    }
+                    const float a = Y.kE * dHzy + (iny ? pxy[v] : 0.f), b = zkE[v] * dHyz + pxz;
+                    exw[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * (a - b);
+                }
+                if (im && k >= 1) {
+                    if (inx) pyx[v] = X.bE * pyx[v] + X.cE * dHzx;
+                    float pyz = 0.f;
+                    if (inz) {
+                        pyz = zbE[v] * oyz[v] + zcE[v] * dHxz;
+                        P1[PSI_EYZ][qz[v]] = pyz;
+                    }
+                    const float a = zkE[v] * dHxz + pyz, b = X.kE * dHzx + (inx ? pyx[v] : 0.f);
+                    eyw[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * (a - b);
+                }
+                if (im && jm) {
+                    if (inx) pzx[v] = X.bE * pzx[v] + X.cE * dHyx;
+                    if (iny) pzy[v] = Y.bE * pzy[v] + Y.cE * dHxy;
+                    const float a = X.kE * dHyx + (inx ? pzx[v] : 0.f), b = Y.kE * dHxy + (iny ? pzy[v] : 0.f);
+                    ezw[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * (a - b);
+                }
+                if ((int64_t)(c + v) == p.src_idx && ok) {
+                    const float sval = step < p.src_len ? p.src_vals[step] : 0.f;
+                    if (p.src_comp == FDTD_EX) exw[v] += sval;
+                    else if (p.src_comp == FDTD_EY) eyw[v] += sval;
+                    else ezw[v] += sval;
+                }
+            }
+            // psi of cells the E layer does not update keep their (zero) value
+            if (iny) { stv<V>(P1[PSI_EXY] + qy, pxy); stv<V>(P1[PSI_EZY] + qy, pzy); }
+            if (inx) { stv<V>(P1[PSI_EYX] + qx, pyx); stv<V>(P1[PSI_EZX] + qx, pzx); }
+        }
+        if (ok) {
+            stv<V>(p.s1.f[FDTD_EX] + c, exw);
+            stv<V>(p.s1.f[FDTD_EY] + c, eyw);
+            stv<V>(p.s1.f[FDTD_EZ] + c, ezw);
+            stv<V>(p.s1.f[FDTD_HX] + c, hx);
+            stv<V>(p.s1.f[FDTD_HY] + c, hy);
+            stv<V>(p.s1.f[FDTD_HZ] + c, hz);
+        }
+        // ---- probes in this plane (grouped by x plane and 4-row band) ----
+        if (pt.start != nullptr) {
+            const int g = i * ((ny + 3) / 4) + jr / 4;
+            const int pend = pt.start[g + 1];
+            for (int q = pt.start[g]; q < pend; ++q) {
+                const int64_t cell = pt.cell[q];
+                if (!ok || cell < (int64_t)c || cell >= (int64_t)c + V) continue;
+                const int v = (int)(cell - c);
+                float val = 0.f;
+#pragma unroll
+                for (int w = 0; w < V; ++w) {
+                    if (w != v) continue;
+                    switch (p.probe_comp) {
+                        case FDTD_EX: val = exw[w]; break;
+                        case FDTD_EY: val = eyw[w]; break;
+                        case FDTD_EZ: val = ezw[w]; break;
+                        case FDTD_HX: val = hx[w]; break;
+                        case FDTD_HY: val = hy[w]; break;
+                        default: val = hz[w]; break;
+                    }
+                }
+                p.rec[(int64_t)pt.slot[q] * p.rec_stride + (step - p.rec_base)] = val;
+            }
+        }
+        // carry to the next plane
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            eyc[v] = ey_x[v];
+            ezc[v] = ez_x[v];
+            hyp[v] = hy[v];
+            hzp[v] = hz[v];
+        }
     }
 }
 
@@ -440,122 +466,151 @@ bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c) {
     (void)nx; (void)ny;
     if (!(c.V == 1 || c.V == 2 || c.V == 4)) return false;
     if (!(c.Ve == 0 || c.Ve == 1 || c.Ve == 2 || c.Ve == 4)) return false;
+    if (c.TX < 0 || c.TX > 4096) return false;
     return nz % c.V == 0 && (c.Ve == 0 || nz % c.Ve == 0);
 }
 
-// Launch plan.  The tiles of one launch cover the z range [kbase, klim) in
-// segments of LZ*V cells and 4*(64/LZ) y rows.  The tile list of a launch
-// runs through the y bands in groups of 8, x planes inside a group, so that
-// the plane i-1 and the row j-1 a workgroup reads again were loaded shortly
-// before on the same XCD; each XCD takes a contiguous eighth of the list
-// (padded with -1).
-static void add_launch(Wave3DPlan &pl, int nx, int ny, int V, int LZ, bool pxy, bool pz, int kbase,
-                       int klim, const int *xlohi, const int *ylohi, int want /* 0 inner, 1 outer, 2 all */) {
-    if (klim <= kbase) return;
-    const int RB = 4 * (64 / LZ);
-    const int nkz = (klim - kbase + LZ * V - 1) / (LZ * V);
-    const int njt = (ny + RB - 1) / RB;
-    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && (i < lo || i >= n - hi); };
-    Wave3DLaunch l{};
-    l.V = V;
-    l.LZ = LZ;
-    l.pxy = pxy;
-    l.pz = pz;
-    l.kbase = kbase;
-    l.klim = klim;
-    l.nkz = nkz;
-    l.njt = njt;
-    l.off = (int)pl.tiles.size();
-    const int J = std::max(1, 32 / RB);
-    for (int jg = 0; jg < njt; jg += J)
-        for (int i = 0; i < nx; ++i) {
-            const bool xs = inslab(nx, xlohi[0], xlohi[1], i) || inslab(nx, xlohi[0], xlohi[1], i - 1);
-            for (int jt = jg; jt < std::min(jg + J, njt); ++jt) {
-                bool ys = false;
-                for (int j = jt * RB - 1; j < jt * RB + RB && j < ny; ++j)
-                    ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
-                const bool outer = xs || ys;
-                if ((want == 0 && outer) || (want == 1 && !outer)) continue;
-                const int rows = std::min(RB, ny - jt * RB);
-                for (int kt = 0; kt < nkz; ++kt) {
-                    pl.tiles.push_back((i * njt + jt) * nkz + kt);
-                    l.cells += (int64_t)rows * std::min(LZ * V, klim - kbase - kt * LZ * V);
-                }
-            }
-        }
-    if (pl.tiles.size() == (size_t)l.off) return;
-    while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(-1);
-    l.n = (int)pl.tiles.size() - l.off;
-    pl.l.push_back(l);
+namespace {
+
+struct Range {
+    int a, b;
+};
+
+// [lo, hi) cut into pieces of at most `w`
+void chunks(std::vector<Range> &out, int lo, int hi, int w) {
+    for (int a = lo; a < hi; a += w) out.push_back(Range{a, std::min(a + w, hi)});
 }
 
-// x/y: interior workgroups run without the x/y CPML code.  z: with z slabs
-// the middle range [zl, zh) (no z slab within [k0-1, kend) of any of its
-// segments) runs without the z CPML code, the two end ranges with it, in
-// short segments (4 lanes of V = 4 per z row, 16 rows per wavefront).
+// z segments of [lo, hi) on the grid of multiples of w (w cells per
+// segment, lanes below lo or from hi on idle)
+struct ZSeg {
+    int base, start, end;
+};
+void zsegs(std::vector<ZSeg> &out, int lo, int hi, int w) {
+    if (lo >= hi) return;
+    for (int b = lo / w * w; b < hi; b += w) out.push_back(ZSeg{b, std::max(b, lo), std::min(b + w, hi)});
+}
+
+}  // namespace
+
+// Launch plan.  x: the planes clear of the x slabs (a tile's plane i0-1
+// included) and the slab ends, in chunks of TX planes (TX/4 for launches
+// with CPML code, which have fewer cells per workgroup's plane and more
+// latency per plane); y: bands of 4*64/LZ rows, clear of the y slabs (row
+// j0-1 included) or not; z: with z slabs, the middle range [zl, zh) (no z
+// slab within [ks-1, k1) of any of its segments) in segments of 64V cells,
+// the ends in segments of 16 cells, both aligned to multiples of their
+// length.  Each launch's tiles run x chunk by x chunk, y bands and z
+// segments inside, so that workgroups issued together on one XCD share halo
+// rows; each XCD takes a contiguous eighth of the list (padded with empty
+// tiles).
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl) {
     pl.l.clear();
     pl.tiles.clear();
     const int V = c.V;
-    const bool anyxy = xlohi[0] + xlohi[1] + ylohi[0] + ylohi[1] > 0;
-    auto both = [&](int Vl, int LZ, bool pz, int k0, int k1) {
-        if (!anyxy) {
-            add_launch(pl, nx, ny, Vl, LZ, false, pz, k0, k1, xlohi, ylohi, 2);
-        } else {
-            add_launch(pl, nx, ny, Vl, LZ, false, pz, k0, k1, xlohi, ylohi, 0);
-            add_launch(pl, nx, ny, Vl, LZ, true, pz, k0, k1, xlohi, ylohi, 1);
-        }
+    const int TX = c.TX > 0 ? c.TX : 16, TXs = std::max(1, TX / 4);
+    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
+    const int xl = xlohi[0] == 0 ? 0 : std::min(nx, xlohi[0] + 1);
+    const int xh = std::max(xl, nx - xlohi[1]);
+    // interior launches take the (interior x, interior y band) tiles, slab
+    // launches all the others
+    auto add = [&](int Vl, int LZ, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
+        if (zseg.empty()) return;
+        const int RB = 4 * (64 / LZ);
+        const int tx = (pxy || pz) ? TXs : TX;
+        Wave3DLaunch l{};
+        l.V = Vl;
+        l.LZ = LZ;
+        l.pxy = pxy;
+        l.pz = pz;
+        l.off = (int)pl.tiles.size();
+        std::vector<Range> xr;
+        std::vector<char> xslab;
+        auto put = [&](int lo, int hi, bool sl) {
+            const size_t n0 = xr.size();
+            chunks(xr, lo, hi, tx);
+            xslab.resize(xr.size(), sl);
+            (void)n0;
+        };
+        put(0, xl, true);
+        put(xl, xh, false);
+        put(xh, nx, true);
+        for (size_t q = 0; q < xr.size(); ++q)
+            for (int j0 = 0; j0 < ny; j0 += RB) {
+                bool ys = false;
+                for (int j = j0 - 1; j < j0 + RB && j < ny; ++j) ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
+                if (pxy != (xslab[q] || ys)) continue;
+                const int rows = std::min(RB, ny - j0);
+                for (const ZSeg &z : zseg) {
+                    pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, {0, 0}});
+                    l.cells += (int64_t)(xr[q].b - xr[q].a) * rows * (z.end - z.start);
+                }
+            }
+        if (pl.tiles.size() == (size_t)l.off) return;
+        while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, {0, 0}});
+        l.n = (int)pl.tiles.size() - l.off;
+        pl.l.push_back(l);
     };
+    const bool anyxy = xlohi[0] + xlohi[1] + ylohi[0] + ylohi[1] > 0;
+    auto both = [&](int Vl, int LZ, bool pz, const std::vector<ZSeg> &zseg) {
+        add(Vl, LZ, false, pz, zseg);
+        if (anyxy) add(Vl, LZ, true, pz, zseg);
+    };
+    std::vector<ZSeg> zmid, zend;
     if (zlohi[0] + zlohi[1] == 0) {
-        both(V, 64, false, 0, nz);
+        zsegs(zmid, 0, nz, 64 * V);
+        both(V, 64, false, zmid);
         return;
     }
-    const int Ve = c.Ve ? c.Ve : (nz % 4 == 0 ? 4 : (nz % 2 == 0 ? 2 : 1)), LZe = 16 / Ve;
+    const int Ve = c.Ve ? c.Ve : 1, LZe = 16 / Ve;
     const int A = std::max(V, Ve);  // both divide nz
     const int zl = zlohi[0] == 0 ? 0 : (zlohi[0] + A) / A * A;
     const int zh = (nz - zlohi[1]) / A * A;
-    if (zl >= zh) {
-        both(V, 64, true, 0, nz);  // slabs too wide for a middle range
+    if (zl >= zh) {  // slabs too wide for a middle range
+        zsegs(zmid, 0, nz, 64 * V);
+        both(V, 64, true, zmid);
         return;
     }
-    both(V, 64, false, zl, zh);
-    both(Ve, LZe, true, 0, zl);
-    both(Ve, LZe, true, zh, nz);
+    zsegs(zmid, zl, zh, 64 * V);
+    zsegs(zend, 0, zl, LZe * Ve);
+    zsegs(zend, zh, nz, LZe * Ve);
+    both(V, 64, false, zmid);
+    both(Ve, LZe, true, zend);
 }
 
 template <int V, int LZ, bool PXY, bool PZ, int MAT>
-static void go_cell(const Prob3D &p, const Wave3DLaunch &l, const int *tiles, const ProbeTiles &pt,
-                    int64_t step, hipStream_t st) {
-    hipLaunchKernelGGL((k3d_cell<V, LZ, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(256), 0, st, p, l.nkz,
-                       l.njt, l.kbase, l.klim, tiles + l.off, pt, step);
+static void go(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
+               int64_t step, hipStream_t st) {
+    hipLaunchKernelGGL((k3d_march<V, LZ, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(256), 0, st, p,
+                       tiles + l.off, pt, step);
 }
 
 template <int V, int LZ, bool PXY, bool PZ>
-static void go_cell_m(const Prob3D &p, const Wave3DLaunch &l, const int *tiles, const ProbeTiles &pt,
-                      int64_t step, hipStream_t st) {
+static void go_m(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
+                 int64_t step, hipStream_t st) {
     const int mat = p.db ? 2 : (p.ca ? 1 : 0);
-    if (mat == 0) go_cell<V, LZ, PXY, PZ, 0>(p, l, tiles, pt, step, st);
-    else if (mat == 1) go_cell<V, LZ, PXY, PZ, 1>(p, l, tiles, pt, step, st);
-    else go_cell<V, LZ, PXY, PZ, 2>(p, l, tiles, pt, step, st);
+    if (mat == 0) go<V, LZ, PXY, PZ, 0>(p, l, tiles, pt, step, st);
+    else if (mat == 1) go<V, LZ, PXY, PZ, 1>(p, l, tiles, pt, step, st);
+    else go<V, LZ, PXY, PZ, 2>(p, l, tiles, pt, step, st);
 }
 
 template <int V, int LZ>
-static void go_cell_v(const Prob3D &p, const Wave3DLaunch &l, const int *tiles, const ProbeTiles &pt,
-                      int64_t step, hipStream_t st) {
+static void go_v(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
+                 int64_t step, hipStream_t st) {
     if constexpr (LZ != 64) {  // short segments only serve the z-slab ranges
-        if (l.pxy) go_cell_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
-        else go_cell_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
+        if (l.pxy) go_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
+        else go_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
     } else if (l.pxy) {
-        if (l.pz) go_cell_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
-        else go_cell_m<V, LZ, true, false>(p, l, tiles, pt, step, st);
+        if (l.pz) go_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
+        else go_m<V, LZ, true, false>(p, l, tiles, pt, step, st);
     } else {
-        if (l.pz) go_cell_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
-        else go_cell_m<V, LZ, false, false>(p, l, tiles, pt, step, st);
+        if (l.pz) go_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
+        else go_m<V, LZ, false, false>(p, l, tiles, pt, step, st);
     }
 }
 
-hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tiles, const ProbeTiles &pt,
+hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles, const ProbeTiles &pt,
                           int64_t step, hipStream_t st, hipEvent_t *ev) {
     int q = 0;
     for (const Wave3DLaunch &l : pl.l) {
@@ -564,16 +619,16 @@ hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const int *tile
             if (e != hipSuccess) return e;
         }
         if (l.LZ == 64) {
-            if (l.V == 4) go_cell_v<4, 64>(p, l, tiles, pt, step, st);
-            else if (l.V == 2) go_cell_v<2, 64>(p, l, tiles, pt, step, st);
-            else if (l.V == 1) go_cell_v<1, 64>(p, l, tiles, pt, step, st);
+            if (l.V == 4) go_v<4, 64>(p, l, tiles, pt, step, st);
+            else if (l.V == 2) go_v<2, 64>(p, l, tiles, pt, step, st);
+            else if (l.V == 1) go_v<1, 64>(p, l, tiles, pt, step, st);
             else return hipErrorInvalidValue;
         } else if (l.V == 4 && l.LZ == 4) {
-            go_cell_v<4, 4>(p, l, tiles, pt, step, st);
+            go_v<4, 4>(p, l, tiles, pt, step, st);
         } else if (l.V == 2 && l.LZ == 8) {
-            go_cell_v<2, 8>(p, l, tiles, pt, step, st);
+            go_v<2, 8>(p, l, tiles, pt, step, st);
         } else if (l.V == 1 && l.LZ == 16) {
-            go_cell_v<1, 16>(p, l, tiles, pt, step, st);
+            go_v<1, 16>(p, l, tiles, pt, step, st);
         } else {
             return hipErrorInvalidValue;
         }

@@ -273,9 +273,9 @@ void Sim::build_probe_tiles() {
         return;
     if (ndim == 3) {
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi}, zl[2] = {ax[2].lo, ax[2].hi};
-        wave3d_plan(nx, ny, nz, Fused3DCfg{a, b}, xl, yl, zl, plan3);
+        wave3d_plan(nx, ny, nz, Fused3DCfg{a, b, c3}, xl, yl, zl, plan3);
         al.put(tl_dev);
-        tl_dev = dev_upload(al, plan3.tiles.data(), std::max<size_t>(plan3.tiles.size(), 1), st);
+        tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
     }
     int ntiles;
     std::vector<int> tile(probe_cells.size());
@@ -398,7 +398,7 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
             return 0;
         }
     } else {
-        Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0};
+        Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0, 0};
         if (wave3d_supported(s.nx, s.ny, s.nz, c)) {
             k.variant = 2;
             k.tile[0] = c.V;
@@ -414,8 +414,8 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.variant == 1) return true;
     if (k.variant != 2) return false;
     if (s.ndim == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
-    if (k.tile[2] != 0 || k.tile[3] != 0) return false;
-    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1]});
+    if (k.tile[3] != 0) return false;
+    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1], k.tile[2]});
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,16 +1115,18 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
             }
     } else {
         const bool zslab = s.ax[2].lo + s.ax[2].hi > 0;
-        for (int V : {1, 2, 4})
-            for (int Ve : {1, 2, 4}) {
-                fdtd_kernel_config k{};
-                k.variant = 2;
-                k.tile[0] = V;
-                k.tile[1] = zslab ? Ve : 0;
-                k.tb = 1;
-                if (config_ok(s, k)) cand.push_back(k);
-                if (!zslab) break;
-            }
+        for (int TX : {8, 16, 32})
+            for (int V : {1, 2, 4})
+                for (int Ve : {1, 2, 4}) {
+                    fdtd_kernel_config k{};
+                    k.variant = 2;
+                    k.tile[0] = V;
+                    k.tile[1] = zslab ? Ve : 0;
+                    k.tile[2] = TX;
+                    k.tb = 1;
+                    if (config_ok(s, k)) cand.push_back(k);
+                    if (!zslab) break;
+                }
     }
     {
         fdtd_kernel_config k{};

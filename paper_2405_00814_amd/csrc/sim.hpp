@@ -96,7 +96,7 @@ struct Sim {
     int pt_cfg[4] = {-1, -1, -1, -1};
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
-    int *tl_dev = nullptr;
+    Tile3 *tl_dev = nullptr;
 
     int64_t n_done = 0;
     fdtd_kernel_config kcfg{};

@@ -222,7 +222,7 @@ def test_yee3d_kernel_config_rejected():
     pb = W.yee3d(shape=(16, 16, 30), steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
                  tau_steps=4.0)
     s = Sim.from_problem(pb)
-    for bad in ((4,), (3,), (2, 16), (2, 4), (1, 0, 0, 5), (1, 0, 1)):
+    for bad in ((4,), (3,), (2, 16), (2, 4), (1, 0, 0, 5), (1, 0, -1), (1, 0, 5000)):
         with pytest.raises(FdtdError):
             s.set_kernel(2, bad)
     s.set_kernel(2, (2,))
