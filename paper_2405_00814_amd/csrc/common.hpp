@@ -133,11 +133,13 @@ struct Wave3DPlan {
 };
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl);
-// ev (optional): pl.l.size() + 1 events, recorded before each launch and
-// after the last one.
+// ev (optional): pl.l.size() + 1 events, recorded on st before each launch
+// and after the last one.  side (optional, not with ev): the launches with
+// CPML code go to this stream (the caller orders it with st); the interior
+// launch is enqueued first.
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles,
                           const ProbeTiles &pt, int64_t step, hipStream_t st,
-                          hipEvent_t *ev = nullptr);
+                          hipEvent_t *ev = nullptr, hipStream_t side = nullptr);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

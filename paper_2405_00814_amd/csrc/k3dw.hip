@@ -16,7 +16,10 @@
 // segment's last lane, a load).  State is double buffered (read s0, write
 // s1), so every recomputed value equals its owner's value bit for bit.
 //
-// Tiles: (x range, band of 4*64/LZ y rows, z segment of LZ*V cells).  The
+// Tiles: (x range, band of WPB*64/LZ y rows, z segment of LZ*V cells).  Rows
+// of one workgroup exchange the values their neighbours need through LDS
+// (old Ex, Ez for the row below; new Hx, Hz for the row above), so only the
+// band's first row recomputes H at j-1 and only its last loads E at j+1.  The
 // interior tiles (no CPML slab touched) run an instance without any CPML
 // code; tiles that touch an x or y slab, or a z slab, run instances with that
 // code.  The z-slab end ranges use short segments (LZ = 16/V lanes per z row)
@@ -86,8 +89,11 @@ __device__ __forceinline__ void zprof(float (&r)[V], const float *t, int kb, int
 // PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A tile whose
 // cells and recomputed neighbours (plane i0-1, row j-1, z = ks-1) touch no x
 // or y slab may run PXY = false, none touching a z slab PZ = false.
+// wavefronts per workgroup (64 * k3d_wpb(LZ) / LZ y rows)
+constexpr int k3d_wpb(int LZ) { return LZ == 64 ? 8 : 4; }
+
 template <int V, int LZ, bool PXY, bool PZ, int MAT>
-__global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, ProbeTiles pt,
+__global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Tile3 *tiles, ProbeTiles pt,
                                                  int64_t step) {
     constexpr int RW = 64 / LZ;  // y rows per wavefront
     const Tile3 T = tiles[xcd_block(blockIdx.x, gridDim.x)];
@@ -183,6 +189,12 @@ __global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, P
         }
     }
 
+    // LDS rows: [0] Ex, [1] Ez (old), [2] Hx, [3] Hz (new) of every thread's
+    // V cells at index threadIdx.x * V; the row above is LZ threads back
+    constexpr int WPB = k3d_wpb(LZ);
+    __shared__ float sh[4][WPB * 64 * V];
+    const int tq = (int)threadIdx.x * V;
+    const bool top = (int)threadIdx.x < LZ, bot = (int)threadIdx.x >= (WPB * 64 - LZ);
     for (int i = T.i0; i < T.i1; ++i) {
         const bool xi = i + 1 < nx, im = i >= 1;
         const unsigned r0 = ((unsigned)i * ny + jr) * nz;  // row (i, j)
@@ -197,8 +209,8 @@ __global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, P
         ld(ex, ex0, c, ok);
         ld(ey_x, ey0, c + sxs, ok && xi);
         ld(ez_x, ez0, c + sxs, ok && xi);
-        ld(ex_y, ex0, c + sys, ok && yj);
-        ld(ez_y, ez0, c + sys, ok && yj);
+        ld(ex_y, ex0, c + sys, ok && yj && bot);  // other rows: from LDS below
+        ld(ez_y, ez0, c + sys, ok && yj && bot);
         ld(hxo, hx0, c, ok);
         ld(hyo, hy0, c, ok);
         ld(hzo, hz0, c, ok);
@@ -214,6 +226,13 @@ __global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, P
         zprof<V, PZ>(zkH, p.z.kH, kb, ks, ok);
         ld(zbH, p.z.bH, kb, PZ && ok);
         ld(zcH, p.z.cH, kb, PZ && ok);
+        stv<V>(&sh[0][tq], ex);
+        stv<V>(&sh[1][tq], ez);
+        __syncthreads();
+        if (!bot && ok && yj) {
+            ldv<V>(ex_y, &sh[0][tq + LZ * V]);
+            ldv<V>(ez_y, &sh[1][tq + LZ * V]);
+        }
 
         // ---- H layer at the own cells ----
         float hx[V], hy[V], hz[V];
@@ -260,12 +279,20 @@ __global__ __launch_bounds__(256) void k3d_march(Prob3D p, const Tile3 *tiles, P
             if (inx) { stv<V>(P1[PSI_HYX] + qx, pyx); stv<V>(P1[PSI_HZX] + qx, pzx); }
         }
 
-        // ---- Hx, Hz at (i, j-1) from the old state ----
+        // ---- Hx, Hz at (i, j-1): from LDS, or (first row of the band)
+        // recomputed from the old state ----
         float hx_jm[V], hz_jm[V];
         zero(hx_jm);
         zero(hz_jm);
-        {
-            const bool o = ok && jm;
+        stv<V>(&sh[2][tq], hx);
+        stv<V>(&sh[3][tq], hz);
+        __syncthreads();
+        if (!top && ok && jm) {
+            ldv<V>(hx_jm, &sh[2][tq - LZ * V]);
+            ldv<V>(hz_jm, &sh[3][tq - LZ * V]);
+        }
+        if (LZ != 64 || top) {  // wave-uniform for LZ = 64
+            const bool o = ok && jm && top;
             const unsigned q0 = c - (jm ? sys : 0u);
             float aex[V], aey[V], aez[V], aeyx[V], ahx[V], ahz[V], adb[V];
             ld(aex, ex0, q0, o);
@@ -496,7 +523,7 @@ void zsegs(std::vector<ZSeg> &out, int lo, int hi, int w) {
 // Launch plan.  x: the planes clear of the x slabs (a tile's plane i0-1
 // included) and the slab ends, in chunks of TX planes (TX/4 for launches
 // with CPML code, which have fewer cells per workgroup's plane and more
-// latency per plane); y: bands of 4*64/LZ rows, clear of the y slabs (row
+// latency per plane); y: bands of 64*k3d_wpb(LZ)/LZ rows, clear of the y slabs (row
 // j0-1 included) or not; z: with z slabs, the middle range [zl, zh) (no z
 // slab within [ks-1, k1) of any of its segments) in segments of 64V cells,
 // the ends in segments of 16 cells, both aligned to multiples of their
@@ -517,7 +544,7 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
     // launches all the others
     auto add = [&](int Vl, int LZ, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
         if (zseg.empty()) return;
-        const int RB = 4 * (64 / LZ);
+        const int RB = k3d_wpb(LZ) * (64 / LZ);
         const int tx = (pxy || pz) ? TXs : TX;
         Wave3DLaunch l{};
         l.V = Vl;
@@ -582,7 +609,7 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
 template <int V, int LZ, bool PXY, bool PZ, int MAT>
 static void go(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                int64_t step, hipStream_t st) {
-    hipLaunchKernelGGL((k3d_march<V, LZ, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(256), 0, st, p,
+    hipLaunchKernelGGL((k3d_march<V, LZ, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(64 * k3d_wpb(LZ)), 0, st, p,
                        tiles + l.off, pt, step);
 }
 
@@ -611,24 +638,34 @@ static void go_v(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, con
 }
 
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles, const ProbeTiles &pt,
-                          int64_t step, hipStream_t st, hipEvent_t *ev) {
+                          int64_t step, hipStream_t st, hipEvent_t *ev, hipStream_t side) {
+    if (ev && side) return hipErrorInvalidValue;
     int q = 0;
-    for (const Wave3DLaunch &l : pl.l) {
+    // with a side stream: the interior launch (no CPML code) first
+    std::vector<const Wave3DLaunch *> order;
+    for (const Wave3DLaunch &l : pl.l)
+        if (!side || !(l.pxy || l.pz)) order.push_back(&l);
+    if (side)
+        for (const Wave3DLaunch &l : pl.l)
+            if (l.pxy || l.pz) order.push_back(&l);
+    for (const Wave3DLaunch *lp : order) {
+        const Wave3DLaunch &l = *lp;
         if (ev) {
             const hipError_t e = hipEventRecord(ev[q++], st);
             if (e != hipSuccess) return e;
         }
+        hipStream_t s = (side && (l.pxy || l.pz)) ? side : st;
         if (l.LZ == 64) {
-            if (l.V == 4) go_v<4, 64>(p, l, tiles, pt, step, st);
-            else if (l.V == 2) go_v<2, 64>(p, l, tiles, pt, step, st);
-            else if (l.V == 1) go_v<1, 64>(p, l, tiles, pt, step, st);
+            if (l.V == 4) go_v<4, 64>(p, l, tiles, pt, step, s);
+            else if (l.V == 2) go_v<2, 64>(p, l, tiles, pt, step, s);
+            else if (l.V == 1) go_v<1, 64>(p, l, tiles, pt, step, s);
             else return hipErrorInvalidValue;
         } else if (l.V == 4 && l.LZ == 4) {
-            go_v<4, 4>(p, l, tiles, pt, step, st);
+            go_v<4, 4>(p, l, tiles, pt, step, s);
         } else if (l.V == 2 && l.LZ == 8) {
-            go_v<2, 8>(p, l, tiles, pt, step, st);
+            go_v<2, 8>(p, l, tiles, pt, step, s);
         } else if (l.V == 1 && l.LZ == 16) {
-            go_v<1, 16>(p, l, tiles, pt, step, st);
+            go_v<1, 16>(p, l, tiles, pt, step, s);
         } else {
             return hipErrorInvalidValue;
         }

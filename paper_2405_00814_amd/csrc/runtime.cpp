@@ -178,6 +178,10 @@ double source_sample(int kind, const double *par, double dt, int64_t n) {
 Sim::~Sim() {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (side) (void)hipStreamSynchronize(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     al.release_all();
 }
 
@@ -336,7 +340,28 @@ void Sim::launch_step(int64_t step) {
         hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
                   "2d fused step");
     } else {
-        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev), "3d fused step");
+        // slab launches beside the interior one unless every launch is timed
+        bool split = !lev && plan3.l.size() > 1;
+        if (split && !side) {  // on the handle's device
+            int prev = 0;
+            hip_check(hipGetDevice(&prev), "hipGetDevice");
+            hip_check(hipSetDevice(device), "hipSetDevice");
+            hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+            (void)hipSetDevice(prev);
+            hip_check(e, "side stream");
+        }
+        if (split) {
+            hip_check(hipEventRecord(ev_fork, st), "fork");
+            hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork wait");
+        }
+        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev, split ? side : nullptr),
+                  "3d fused step");
+        if (split) {
+            hip_check(hipEventRecord(ev_join, side), "join");
+            hip_check(hipStreamWaitEvent(st, ev_join, 0), "join wait");
+        }
     }
     cur = 1 - cur;
     last_launches += ndim == 2 ? 1 : (int64_t)plan3.l.size();
