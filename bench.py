@@ -120,14 +120,14 @@ def bench_3d(args):
     sim.close()
     dom = max(range(len(prof)), key=lambda q: prof[q]["ms"])
     d = prof[dom]
-    # the dominant launch runs no CPML code: fields read and written once,
-    # the coefficient maps read once
-    bpc = 8 * 6 + 4 * ncoef_of(pb)
-    assert d["cpml"] == 0, "dominant launch carries CPML code"
+    # algorithmic bytes of the dominant launch: its cells' fields read and
+    # written once, the coefficient maps read once, its psi values read and
+    # written once
+    dbytes = alg_bytes_implicit(d["cells"], d["psi"], 6, ncoef_of(pb))
     return dict(pb=pb, cfg=cfg, t=t, wall=wall, launches=launches, rate=rate, bytes=ab,
                 step_achieved=ab * args.steps / t, finite=ok, prof=prof, dom=dom,
-                dom_bytes=d["cells"] * bpc, dom_ms=d["ms"], dom_bpc=bpc,
-                dom_achieved=d["cells"] * bpc / (d["ms"] / 1e3))
+                dom_bytes=dbytes, dom_ms=d["ms"], dom_bpc=dbytes / d["cells"],
+                dom_achieved=dbytes / (d["ms"] / 1e3))
 
 
 def bench_2d(args, steps=10000):
@@ -298,9 +298,10 @@ def main():
     traffic = traffic_record("yee3d_512_interior", src3)
     roof = dict(bound="hbm", achieved=r["dom_achieved"] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                 frac=r["dom_achieved"] / PEAK_HBM, traffic=traffic,
-                kernel="k3d_cell interior launch (no CPML code)",
+                kernel="k3d_march interior launch (z-slab CPML only)",
                 bytes_per_launch=r["dom_bytes"], bytes_per_cell_update=r["dom_bpc"],
-                cells_per_launch=r["prof"][r["dom"]]["cells"], avg_launch_ms=r["dom_ms"],
+                cells_per_launch=r["prof"][r["dom"]]["cells"],
+                psi_per_launch=r["prof"][r["dom"]]["psi"], avg_launch_ms=r["dom_ms"],
                 step=dict(launches_per_step=r["launches"] / args.steps,
                           bytes_per_step=r["bytes"], bytes_per_cell_update=r["bytes"] / pb.cells,
                           achieved=r["step_achieved"] / 1e9, frac=r["step_achieved"] / PEAK_HBM,

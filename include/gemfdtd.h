@@ -179,10 +179,8 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    2D fused: tile[0] = V (1, 2 or 4 consecutive y cells per lane; ny % V
  *    must be 0), tile[1] = TX (x rows marched by one wavefront).
  *    3D fused: tile[0] = V (1, 2 or 4 consecutive z cells per thread;
- *    nz % V must be 0); tile[1] = the same for the z ranges next to the
- *    z CPML slabs (0 = default; nz % tile[1] must be 0); tile[2] = x
- *    planes marched by one workgroup (0 = 16, at most 4096); tile[3]
- *    must be 0.
+ *    nz % V must be 0); tile[2] = x planes marched by one workgroup (0 =
+ *    16, at most 4096); tile[1] and tile[3] must be 0.
  * FDTD_EINVAL for unknown or unsupported combinations. */
 typedef struct {
     int32_t variant;
@@ -206,15 +204,18 @@ int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches);
 
 /* Per-launch timing of the step.  Advances the state by `steps` steps like
  * fdtd_step, with a HIP event pair around every kernel launch of the 3D
- * fused step (the interior, x/y-slab and z-end-range launches), or around
- * the whole step for the other steppers, and writes one entry per launch
- * (at most `max`) with the mean duration over the steps; *n receives the
- * number of entries.  cells: cells the entry updates; cpml: 1 if the
- * launch runs CPML code, 0 if not, -1 for a whole step; launches: kernel
- * launches in the entry.  The events add a small gap between launches. */
+ * fused step (the interior launch and the one of the tiles that touch an x
+ * or y CPML slab), or around the whole step for the other steppers, and
+ * writes one entry per launch (at most `max`) with the mean duration over
+ * the steps; *n receives the number of entries.  cells: cells the entry
+ * updates; psi: CPML auxiliary values it updates; cpml: 0 no CPML code, 1
+ * z-slab code only, 2 x/y (and z) slab code, -1 a whole step; launches:
+ * kernel launches in the entry.  The events add a small gap between
+ * launches. */
 typedef struct {
     float ms;
     int64_t cells;
+    int64_t psi;
     int32_t cpml;
     int32_t launches;
 } fdtd_launch_stat;

@@ -110,10 +110,9 @@ int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
 
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
-// Fused 3D.  V: z cells per thread in the middle z range; Ve: in the z-slab
-// end ranges (0 = 1); TX: x planes marched by one interior workgroup
-// (0 = 16; workgroups with CPML code march max(1, TX/4).
-struct Fused3DCfg { int V; int Ve; int TX; };
+// Fused 3D.  V: z cells per thread; TX: x planes marched by one interior
+// workgroup (0 = 16; workgroups with x/y CPML code march max(1, TX/4)).
+struct Fused3DCfg { int V; int TX; };
 // One workgroup's tile: planes [i0, i1), rows from j0 (4*64/LZ of them),
 // z cells [ks, k1) of the segment whose lanes start at the aligned base k0.
 // i0 == i1 marks padding.
@@ -122,10 +121,11 @@ struct Tile3 {
 };
 // One launch of the fused 3D kernel over a list of tiles.
 struct Wave3DLaunch {
-    int V, LZ;     // z cells per thread, threads per z row (64, or 16/V)
+    int V, LZ;     // z cells per thread, threads per z row (64)
     bool pxy, pz;  // CPML code for x/y slabs, z slabs
     int off, n;    // tile list entries [off, off + n) (multiple of 8)
     int64_t cells; // cells the launch updates
+    int64_t psi;   // CPML psi values it updates
 };
 struct Wave3DPlan {
     std::vector<Wave3DLaunch> l;
@@ -134,12 +134,10 @@ struct Wave3DPlan {
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl);
 // ev (optional): pl.l.size() + 1 events, recorded on st before each launch
-// and after the last one.  side (optional, not with ev): the launches with
-// CPML code go to this stream (the caller orders it with st); the interior
-// launch is enqueued first.
+// and after the last one.
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles,
                           const ProbeTiles &pt, int64_t step, hipStream_t st,
-                          hipEvent_t *ev = nullptr, hipStream_t side = nullptr);
+                          hipEvent_t *ev = nullptr);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

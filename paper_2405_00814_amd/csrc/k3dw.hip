@@ -20,10 +20,10 @@
 // of one workgroup exchange the values their neighbours need through LDS
 // (old Ex, Ez for the row below; new Hx, Hz for the row above), so only the
 // band's first row recomputes H at j-1 and only its last loads E at j+1.  The
-// interior tiles (no CPML slab touched) run an instance without any CPML
-// code; tiles that touch an x or y slab, or a z slab, run instances with that
-// code.  The z-slab end ranges use short segments (LZ = 16/V lanes per z row)
-// so that the interior segments stay clear of them.
+// interior tiles (no x or y CPML slab touched) run an instance without the
+// x/y CPML code, the others one with it.  z-slab cells are lanes of the same
+// segments: the main formulas take the interior profile and the lanes with
+// slab cells add the CPML terms in a correction step.
 #include "common.hpp"
 #include "devutil.hpp"
 
@@ -68,23 +68,6 @@ __device__ __forceinline__ float znext(const float (&x)[V], int q, float seam, b
     return last ? seam : s;
 }
 
-// 1/(kappa dz) for the V cells of a lane: a vector load of the profile, or
-// (no z slab anywhere in the tile) the uniform value at an index k0 of the tile.
-template <int V, bool PZ>
-__device__ __forceinline__ void zprof(float (&r)[V], const float *t, int kb, int k0, bool ok) {
-    if (PZ) {
-        if (ok) ldv<V>(r, t + kb);
-        else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) r[v] = 0.f;
-        }
-    } else {
-        const float u = t[k0];
-#pragma unroll
-        for (int v = 0; v < V; ++v) r[v] = u;
-    }
-}
-
 // MAT: 0 = Cb map only, 1 = Ca and Cb maps, 2 = Ca, Cb and Db maps.
 // PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A tile whose
 // cells and recomputed neighbours (plane i0-1, row j-1, z = ks-1) touch no x
@@ -125,9 +108,30 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
         if (cond) ldv<V>(a, base + off);
         else zero(a);
     };
+    // z slabs: the main formulas use the interior 1/dz (kappa = 1 outside the
+    // slabs); cells of a lane inside a z slab then add (1/(kappa dz) - 1/dz) D
+    // and their psi term in a correction step (divergent, lanes with slab
+    // cells only)
     int zsv[V];  // z-slab index of cell kb+v (-1 outside, or without z slabs)
+    bool zany = false;
 #pragma unroll
-    for (int v = 0; v < V; ++v) zsv[v] = (PZ && ok) ? slab_index(p.z, kb + v) : -1;
+    for (int v = 0; v < V; ++v) {
+        zsv[v] = (PZ && ok) ? slab_index(p.z, kb + v) : -1;
+        zany = zany || zsv[v] >= 0;
+    }
+    const float idzH = p.z.kH[p.z.lo], idzE = p.z.kE[p.z.lo];  // index lo: first one outside
+    // the old z-slab psi a[q] of the lane's slab cells and b, c, 1/(kappa dz)
+    // of the H or E profile (elements outside the slab read a[row])
+    auto zload = [&](float (&o)[V], float (&kk)[V], float (&bb)[V], float (&cc)[V], const float *a,
+                     unsigned row, const float *kt, const float *bt, const float *ct) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            o[v] = a[row + (zsv[v] >= 0 ? zsv[v] : 0)];
+            kk[v] = kt[kb + v];
+            bb[v] = bt[kb + v];
+            cc[v] = ct[kb + v];
+        }
+    };
 
     // y profiles (wave-uniform for LZ = 64)
     const AxP Y = axp<PXY>(p.y, jr), Ym = axp<PXY>(p.y, jm && j < ny ? j - 1 : 0);
@@ -158,33 +162,36 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
             for (int v = 0; v < V; ++v) adb[v] = p.db0;
             if (MAT == 2 && o) ldv<V>(adb, p.db + q0);
             const float aex_e = (o && last && ke) ? ex0[r0 - sxs + kend] : 0.f;
-            float zkH[V], zbH[V], zcH[V];
-            zprof<V, PZ>(zkH, p.z.kH, kb, ks, o);
-            ld(zbH, p.z.bH, kb, PZ && o);
-            ld(zcH, p.z.cH, kb, PZ && o);
-            float pyx[V], pzx[V], pzy[V], oyz[V];
+            float pyx[V], pzx[V], pzy[V], dExzA[V];
             const bool inx = PXY && o && Xm.s >= 0, iny = PXY && o && Y.s >= 0;
             const unsigned qx = inx ? xs3(Xm.s, j, kb, ny, nz) : 0, qy = iny ? ys3(i - 1, Y.s, kb, sy, nz) : 0;
             ld(pyx, P0[PSI_HYX], qx, inx);
             ld(pzx, P0[PSI_HZX], qx, inx);
             ld(pzy, P0[PSI_HZY], qy, iny);
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                oyz[v] = (PZ && o) ? P0[PSI_HYZ][zsv[v] >= 0 ? zs3(i - 1, j, zsv[v], ny, sz) : 0u] : 0.f;
-#pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float dExz = znext<V>(aex, v, aex_e, last) - aex[v];
                 const float dEzx = ezc[v] - aez[v];
                 const float dEyx = eyc[v] - aey[v];
                 const float dExy = aexy[v] - aex[v];
-                const float pyz = zsv[v] >= 0 ? zbH[v] * oyz[v] + zcH[v] * dExz : 0.f;
+                dExzA[v] = dExz;
                 const float vyx = inx ? Xm.bH * pyx[v] + Xm.cH * dEzx : 0.f;
                 const float vzx = inx ? Xm.bH * pzx[v] + Xm.cH * dEyx : 0.f;
                 const float vzy = iny ? Y.bH * pzy[v] + Y.cH * dExy : 0.f;
                 if (o) {
-                    hyp[v] = ahy[v] - adb[v] * ((zkH[v] * dExz + pyz) - (Xm.kH * dEzx + vyx));
+                    hyp[v] = ahy[v] - adb[v] * ((idzH * dExz) - (Xm.kH * dEzx + vyx));
                     hzp[v] = ahz[v] - adb[v] * ((Xm.kH * dEyx + vzx) - (Y.kH * dExy + vzy));
                 }
+            }
+            if (PZ && zany) {
+                float oz[V], kh[V], bh[V], chh[V];
+                zload(oz, kh, bh, chh, P0[PSI_HYZ], zs3(i - 1, j, 0, ny, sz), p.z.kH, p.z.bH, p.z.cH);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (zsv[v] >= 0) {
+                        const float pyz = bh[v] * oz[v] + chh[v] * dExzA[v];
+                        hyp[v] -= adb[v] * ((kh[v] - idzH) * dExzA[v] + pyz);
+                    }
             }
         }
     }
@@ -222,10 +229,6 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
         const bool s63 = ok && last && ke;
         const float ey_e = s63 ? ey0[r0 + kend] : 0.f;
         const float ex_e = s63 ? ex0[r0 + kend] : 0.f;
-        float zkH[V], zbH[V], zcH[V];
-        zprof<V, PZ>(zkH, p.z.kH, kb, ks, ok);
-        ld(zbH, p.z.bH, kb, PZ && ok);
-        ld(zcH, p.z.cH, kb, PZ && ok);
         stv<V>(&sh[0][tq], ex);
         stv<V>(&sh[1][tq], ez);
         __syncthreads();
@@ -244,16 +247,7 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
             ld(pzy, P0[PSI_HZY], qy, iny);
             ld(pyx, P0[PSI_HYX], qx, inx);
             ld(pzx, P0[PSI_HZX], qx, inx);
-            // z-slab psi: loaded together up front (lanes outside the slab
-            // read element 0) so that the loads overlap
-            unsigned qz[V];
-            float oxz[V], oyz[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
-                oxz[v] = PZ ? P0[PSI_HXZ][qz[v]] : 0.f;
-                oyz[v] = PZ ? P0[PSI_HYZ][qz[v]] : 0.f;
-            }
+            float dEyzA[V], dExzA[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float dEzy = ez_y[v] - ez[v];
@@ -262,18 +256,30 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
                 const float dEzx = ez_x[v] - ez[v];
                 const float dEyx = ey_x[v] - ey[v];
                 const float dExy = ex_y[v] - ex[v];
+                dEyzA[v] = dEyz;
+                dExzA[v] = dExz;
                 if (iny) { pxy[v] = Y.bH * pxy[v] + Y.cH * dEzy; pzy[v] = Y.bH * pzy[v] + Y.cH * dExy; }
                 if (inx) { pyx[v] = X.bH * pyx[v] + X.cH * dEzx; pzx[v] = X.bH * pzx[v] + X.cH * dEyx; }
-                float pxz = 0.f, pyz = 0.f;
-                if (zsv[v] >= 0) {
-                    pxz = zbH[v] * oxz[v] + zcH[v] * dEyz;
-                    pyz = zbH[v] * oyz[v] + zcH[v] * dExz;
-                    P1[PSI_HXZ][qz[v]] = pxz;
-                    P1[PSI_HYZ][qz[v]] = pyz;
-                }
-                hx[v] = hxo[v] - db[v] * ((Y.kH * dEzy + (iny ? pxy[v] : 0.f)) - (zkH[v] * dEyz + pxz));
-                hy[v] = hyo[v] - db[v] * ((zkH[v] * dExz + pyz) - (X.kH * dEzx + (inx ? pyx[v] : 0.f)));
+                hx[v] = hxo[v] - db[v] * ((Y.kH * dEzy + (iny ? pxy[v] : 0.f)) - (idzH * dEyz));
+                hy[v] = hyo[v] - db[v] * ((idzH * dExz) - (X.kH * dEzx + (inx ? pyx[v] : 0.f)));
                 hz[v] = hzo[v] - db[v] * ((X.kH * dEyx + (inx ? pzx[v] : 0.f)) - (Y.kH * dExy + (iny ? pzy[v] : 0.f)));
+            }
+            if (PZ && zany) {
+                const unsigned row = zs3(i, j, 0, ny, sz);
+                float o1[V], o2[V], kh[V], bh[V], chh[V];
+                zload(o1, kh, bh, chh, P0[PSI_HXZ], row, p.z.kH, p.z.bH, p.z.cH);
+#pragma unroll
+                for (int v = 0; v < V; ++v) o2[v] = P0[PSI_HYZ][row + (zsv[v] >= 0 ? zsv[v] : 0)];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (zsv[v] >= 0) {
+                        const float pxz = bh[v] * o1[v] + chh[v] * dEyzA[v];
+                        const float pyz = bh[v] * o2[v] + chh[v] * dExzA[v];
+                        P1[PSI_HXZ][row + zsv[v]] = pxz;
+                        P1[PSI_HYZ][row + zsv[v]] = pyz;
+                        hx[v] += db[v] * ((kh[v] - idzH) * dEyzA[v] + pxz);
+                        hy[v] -= db[v] * ((kh[v] - idzH) * dExzA[v] + pyz);
+                    }
             }
             if (iny) { stv<V>(P1[PSI_HXY] + qy, pxy); stv<V>(P1[PSI_HZY] + qy, pzy); }
             if (inx) { stv<V>(P1[PSI_HYX] + qx, pyx); stv<V>(P1[PSI_HZX] + qx, pzx); }
@@ -311,24 +317,31 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
             ld(pxy, P0[PSI_HXY], qy, iny);
             ld(pzy, P0[PSI_HZY], qy, iny);
             ld(pzx, P0[PSI_HZX], qx, inx);
-            float oxz[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                oxz[v] = (PZ && o) ? P0[PSI_HXZ][zsv[v] >= 0 ? zs3(i, j - 1, zsv[v], ny, sz) : 0u] : 0.f;
+            float dEyzB[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float dEzy = ez[v] - aez[v];
                 const float dEyz = znext<V>(aey, v, aey_e, last) - aey[v];
                 const float dEyx = aeyx[v] - aey[v];
                 const float dExy = ex[v] - aex[v];
-                const float pxz = zsv[v] >= 0 ? zbH[v] * oxz[v] + zcH[v] * dEyz : 0.f;
+                dEyzB[v] = dEyz;
                 const float vxy = iny ? Ym.bH * pxy[v] + Ym.cH * dEzy : 0.f;
                 const float vzy = iny ? Ym.bH * pzy[v] + Ym.cH * dExy : 0.f;
                 const float vzx = inx ? X.bH * pzx[v] + X.cH * dEyx : 0.f;
                 if (o) {
-                    hx_jm[v] = ahx[v] - adb[v] * ((Ym.kH * dEzy + vxy) - (zkH[v] * dEyz + pxz));
+                    hx_jm[v] = ahx[v] - adb[v] * ((Ym.kH * dEzy + vxy) - (idzH * dEyz));
                     hz_jm[v] = ahz[v] - adb[v] * ((X.kH * dEyx + vzx) - (Ym.kH * dExy + vzy));
                 }
+            }
+            if (PZ && zany && o) {
+                float oz[V], kh[V], bh[V], chh[V];
+                zload(oz, kh, bh, chh, P0[PSI_HXZ], zs3(i, j - 1, 0, ny, sz), p.z.kH, p.z.bH, p.z.cH);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (zsv[v] >= 0) {
+                        const float pxz = bh[v] * oz[v] + chh[v] * dEyzB[v];
+                        hx_jm[v] += adb[v] * ((kh[v] - idzH) * dEyzB[v] + pxz);
+                    }
             }
         }
 
@@ -341,26 +354,24 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
             const float lezy = yj ? ez0[q0 + sys] : 0.f;
             const float lezx = xi ? ez0[q0 + sxs] : 0.f;
             const float ldb = MAT == 2 ? p.db[q0] : p.db0;
-            const float zmk = p.z.kH[km];
             const float dEzy = lezy - lez, dEyz = ey[0] - ley;
             const float dExz = ex[0] - lex, dEzx = lezx - lez;
-            float a = Y.kH * dEzy, b = zmk * dEyz;
-            float a2 = zmk * dExz, b2 = X.kH * dEzx;
+            float a = Y.kH * dEzy, b2 = X.kH * dEzx;
             if (PXY) {
                 if (Y.s >= 0) a += Y.bH * P0[PSI_HXY][ys3(i, Y.s, km, sy, nz)] + Y.cH * dEzy;
                 if (X.s >= 0) b2 += X.bH * P0[PSI_HYX][xs3(X.s, j, km, ny, nz)] + X.cH * dEzx;
             }
+            hx_l = hx0[q0] - ldb * (a - idzH * dEyz);
+            hy_l = hy0[q0] - ldb * (idzH * dExz - b2);
             if (PZ) {
                 const int zs = slab_index(p.z, km);
                 if (zs >= 0) {
                     const unsigned qz = zs3(i, j, zs, ny, sz);
-                    const float zb = p.z.bH[km], zc = p.z.cH[km];
-                    b += zb * P0[PSI_HXZ][qz] + zc * dEyz;
-                    a2 += zb * P0[PSI_HYZ][qz] + zc * dExz;
+                    const float zk = p.z.kH[km] - idzH, zb = p.z.bH[km], zc = p.z.cH[km];
+                    hx_l += ldb * (zk * dEyz + (zb * P0[PSI_HXZ][qz] + zc * dEyz));
+                    hy_l -= ldb * (zk * dExz + (zb * P0[PSI_HYZ][qz] + zc * dExz));
                 }
             }
-            hx_l = hx0[q0] - ldb * (a - b);
-            hy_l = hy0[q0] - ldb * (a2 - b2);
         }
         float hxm[V], hym[V];
 #pragma unroll
@@ -377,17 +388,7 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
         // ---- E layer at the own cells ----
         float exw[V], eyw[V], ezw[V];
         {
-            float zkE[V], zbE[V], zcE[V], oxz[V], oyz[V];
-            unsigned qz[V];
-            zprof<V, PZ>(zkE, p.z.kE, kb, ks, ok);
-            ld(zbE, p.z.bE, kb, PZ && ok);
-            ld(zcE, p.z.cE, kb, PZ && ok);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                qz[v] = zsv[v] >= 0 ? zs3(i, j, zsv[v], ny, sz) : 0u;
-                oxz[v] = PZ ? P0[PSI_EXZ][qz[v]] : 0.f;
-                oyz[v] = PZ ? P0[PSI_EYZ][qz[v]] : 0.f;
-            }
+            float dHyzA[V], dHxzA[V];
             float pxy[V], pzy[V], pyx[V], pzx[V];
             const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
             const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
@@ -401,28 +402,19 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
                 exw[v] = ex[v];
                 eyw[v] = ey[v];
                 ezw[v] = ez[v];
-                const bool inz = zsv[v] >= 0;
                 const float dHzy = hz[v] - hz_jm[v], dHyz = hy[v] - hym[v];
                 const float dHxz = hx[v] - hxm[v], dHzx = hz[v] - hzp[v];
                 const float dHyx = hy[v] - hyp[v], dHxy = hx[v] - hx_jm[v];
+                dHyzA[v] = dHyz;
+                dHxzA[v] = dHxz;
                 if (jm && k >= 1) {
                     if (iny) pxy[v] = Y.bE * pxy[v] + Y.cE * dHzy;
-                    float pxz = 0.f;
-                    if (inz) {
-                        pxz = zbE[v] * oxz[v] + zcE[v] * dHyz;
-                        P1[PSI_EXZ][qz[v]] = pxz;
-                    }
-                    const float a = Y.kE * dHzy + (iny ? pxy[v] : 0.f), b = zkE[v] * dHyz + pxz;
+                    const float a = Y.kE * dHzy + (iny ? pxy[v] : 0.f), b = idzE * dHyz;
                     exw[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * (a - b);
                 }
                 if (im && k >= 1) {
                     if (inx) pyx[v] = X.bE * pyx[v] + X.cE * dHzx;
-                    float pyz = 0.f;
-                    if (inz) {
-                        pyz = zbE[v] * oyz[v] + zcE[v] * dHxz;
-                        P1[PSI_EYZ][qz[v]] = pyz;
-                    }
-                    const float a = zkE[v] * dHxz + pyz, b = X.kE * dHzx + (inx ? pyx[v] : 0.f);
+                    const float a = idzE * dHxz, b = X.kE * dHzx + (inx ? pyx[v] : 0.f);
                     eyw[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * (a - b);
                 }
                 if (im && jm) {
@@ -431,13 +423,39 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
                     const float a = X.kE * dHyx + (inx ? pzx[v] : 0.f), b = Y.kE * dHxy + (iny ? pzy[v] : 0.f);
                     ezw[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * (a - b);
                 }
+            }
+            if (PZ && zany) {
+                // z-slab psi of Ex, Ey; cells the E layer does not update keep
+                // their (zero) value
+                const unsigned row = zs3(i, j, 0, ny, sz);
+                float o3[V], o4[V], kz[V], bz[V], cz[V];
+                zload(o3, kz, bz, cz, P0[PSI_EXZ], row, p.z.kE, p.z.bE, p.z.cE);
+#pragma unroll
+                for (int v = 0; v < V; ++v) o4[v] = P0[PSI_EYZ][row + (zsv[v] >= 0 ? zsv[v] : 0)];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (zsv[v] >= 0) {
+                        const int k = kb + v;
+                        if (jm && k >= 1) {
+                            o3[v] = bz[v] * o3[v] + cz[v] * dHyzA[v];
+                            exw[v] -= cb[v] * ((kz[v] - idzE) * dHyzA[v] + o3[v]);
+                        }
+                        if (im && k >= 1) {
+                            o4[v] = bz[v] * o4[v] + cz[v] * dHxzA[v];
+                            eyw[v] += cb[v] * ((kz[v] - idzE) * dHxzA[v] + o4[v]);
+                        }
+                        P1[PSI_EXZ][row + zsv[v]] = o3[v];
+                        P1[PSI_EYZ][row + zsv[v]] = o4[v];
+                    }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v)
                 if ((int64_t)(c + v) == p.src_idx && ok) {
                     const float sval = step < p.src_len ? p.src_vals[step] : 0.f;
                     if (p.src_comp == FDTD_EX) exw[v] += sval;
                     else if (p.src_comp == FDTD_EY) eyw[v] += sval;
                     else ezw[v] += sval;
                 }
-            }
             // psi of cells the E layer does not update keep their (zero) value
             if (iny) { stv<V>(P1[PSI_EXY] + qy, pxy); stv<V>(P1[PSI_EZY] + qy, pzy); }
             if (inx) { stv<V>(P1[PSI_EYX] + qx, pyx); stv<V>(P1[PSI_EZX] + qx, pzx); }
@@ -492,9 +510,8 @@ int wave3d_group_of(int ny, int i, int j) { return i * ((ny + 3) / 4) + j / 4; }
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c) {
     (void)nx; (void)ny;
     if (!(c.V == 1 || c.V == 2 || c.V == 4)) return false;
-    if (!(c.Ve == 0 || c.Ve == 1 || c.Ve == 2 || c.Ve == 4)) return false;
     if (c.TX < 0 || c.TX > 4096) return false;
-    return nz % c.V == 0 && (c.Ve == 0 || nz % c.Ve == 0);
+    return nz % c.V == 0;
 }
 
 namespace {
@@ -521,16 +538,15 @@ void zsegs(std::vector<ZSeg> &out, int lo, int hi, int w) {
 }  // namespace
 
 // Launch plan.  x: the planes clear of the x slabs (a tile's plane i0-1
-// included) and the slab ends, in chunks of TX planes (TX/4 for launches
-// with CPML code, which have fewer cells per workgroup's plane and more
-// latency per plane); y: bands of 64*k3d_wpb(LZ)/LZ rows, clear of the y slabs (row
-// j0-1 included) or not; z: with z slabs, the middle range [zl, zh) (no z
-// slab within [ks-1, k1) of any of its segments) in segments of 64V cells,
-// the ends in segments of 16 cells, both aligned to multiples of their
-// length.  Each launch's tiles run x chunk by x chunk, y bands and z
-// segments inside, so that workgroups issued together on one XCD share halo
-// rows; each XCD takes a contiguous eighth of the list (padded with empty
-// tiles).
+// included) and the slab ends, in chunks of TX planes (TX/4 for the launch
+// with x/y CPML code, which has fewer tiles and more latency per plane);
+// y: bands of 64*k3d_wpb(LZ)/LZ rows, clear of the y slabs (row j0-1
+// included) or not; z: segments of 64V cells (z-slab cells are handled by
+// the correction step of the PZ instances).  The interior launch takes the
+// (interior x chunk, interior y band) tiles, the slab launch all others.
+// Each launch's tiles run x chunk by x chunk, y bands and z segments
+// inside, so that workgroups issued together on one XCD share halo rows;
+// each XCD takes a contiguous eighth of the list (padded with empty tiles).
 void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
                  const int *zlohi, Wave3DPlan &pl) {
     pl.l.clear();
@@ -540,12 +556,10 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
     auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
     const int xl = xlohi[0] == 0 ? 0 : std::min(nx, xlohi[0] + 1);
     const int xh = std::max(xl, nx - xlohi[1]);
-    // interior launches take the (interior x, interior y band) tiles, slab
-    // launches all the others
     auto add = [&](int Vl, int LZ, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
         if (zseg.empty()) return;
         const int RB = k3d_wpb(LZ) * (64 / LZ);
-        const int tx = (pxy || pz) ? TXs : TX;
+        const int tx = pxy ? TXs : TX;
         Wave3DLaunch l{};
         l.V = Vl;
         l.LZ = LZ;
@@ -569,9 +583,18 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
                 for (int j = j0 - 1; j < j0 + RB && j < ny; ++j) ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
                 if (pxy != (xslab[q] || ys)) continue;
                 const int rows = std::min(RB, ny - j0);
+                const int64_t xn = xr[q].b - xr[q].a;
+                int64_t xs = 0, ysn = 0;
+                for (int i = xr[q].a; i < xr[q].b; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
+                for (int j = j0; j < j0 + rows; ++j) ysn += inslab(ny, ylohi[0], ylohi[1], j);
                 for (const ZSeg &z : zseg) {
                     pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, {0, 0}});
-                    l.cells += (int64_t)(xr[q].b - xr[q].a) * rows * (z.end - z.start);
+                    const int64_t zn = z.end - z.start;
+                    int64_t zs = 0;
+                    for (int k = z.start; k < z.end; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
+                    l.cells += xn * rows * zn;
+                    // four psi per slab a cell lies in
+                    l.psi += 4 * (xs * rows * zn + xn * ysn * zn + xn * rows * zs);
                 }
             }
         if (pl.tiles.size() == (size_t)l.off) return;
@@ -584,26 +607,9 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
         add(Vl, LZ, false, pz, zseg);
         if (anyxy) add(Vl, LZ, true, pz, zseg);
     };
-    std::vector<ZSeg> zmid, zend;
-    if (zlohi[0] + zlohi[1] == 0) {
-        zsegs(zmid, 0, nz, 64 * V);
-        both(V, 64, false, zmid);
-        return;
-    }
-    const int Ve = c.Ve ? c.Ve : 1, LZe = 16 / Ve;
-    const int A = std::max(V, Ve);  // both divide nz
-    const int zl = zlohi[0] == 0 ? 0 : (zlohi[0] + A) / A * A;
-    const int zh = (nz - zlohi[1]) / A * A;
-    if (zl >= zh) {  // slabs too wide for a middle range
-        zsegs(zmid, 0, nz, 64 * V);
-        both(V, 64, true, zmid);
-        return;
-    }
-    zsegs(zmid, zl, zh, 64 * V);
-    zsegs(zend, 0, zl, LZe * Ve);
-    zsegs(zend, zh, nz, LZe * Ve);
-    both(V, 64, false, zmid);
-    both(Ve, LZe, true, zend);
+    std::vector<ZSeg> zseg;
+    zsegs(zseg, 0, nz, 64 * V);
+    both(V, 64, zlohi[0] + zlohi[1] > 0, zseg);
 }
 
 template <int V, int LZ, bool PXY, bool PZ, int MAT>
@@ -622,53 +628,31 @@ static void go_m(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, con
     else go<V, LZ, PXY, PZ, 2>(p, l, tiles, pt, step, st);
 }
 
-template <int V, int LZ>
+template <int V>
 static void go_v(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                  int64_t step, hipStream_t st) {
-    if constexpr (LZ != 64) {  // short segments only serve the z-slab ranges
-        if (l.pxy) go_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
-        else go_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
-    } else if (l.pxy) {
-        if (l.pz) go_m<V, LZ, true, true>(p, l, tiles, pt, step, st);
-        else go_m<V, LZ, true, false>(p, l, tiles, pt, step, st);
+    if (l.pxy) {
+        if (l.pz) go_m<V, 64, true, true>(p, l, tiles, pt, step, st);
+        else go_m<V, 64, true, false>(p, l, tiles, pt, step, st);
     } else {
-        if (l.pz) go_m<V, LZ, false, true>(p, l, tiles, pt, step, st);
-        else go_m<V, LZ, false, false>(p, l, tiles, pt, step, st);
+        if (l.pz) go_m<V, 64, false, true>(p, l, tiles, pt, step, st);
+        else go_m<V, 64, false, false>(p, l, tiles, pt, step, st);
     }
 }
 
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles, const ProbeTiles &pt,
-                          int64_t step, hipStream_t st, hipEvent_t *ev, hipStream_t side) {
-    if (ev && side) return hipErrorInvalidValue;
+                          int64_t step, hipStream_t st, hipEvent_t *ev) {
     int q = 0;
-    // with a side stream: the interior launch (no CPML code) first
-    std::vector<const Wave3DLaunch *> order;
-    for (const Wave3DLaunch &l : pl.l)
-        if (!side || !(l.pxy || l.pz)) order.push_back(&l);
-    if (side)
-        for (const Wave3DLaunch &l : pl.l)
-            if (l.pxy || l.pz) order.push_back(&l);
-    for (const Wave3DLaunch *lp : order) {
-        const Wave3DLaunch &l = *lp;
+    for (const Wave3DLaunch &l : pl.l) {
         if (ev) {
             const hipError_t e = hipEventRecord(ev[q++], st);
             if (e != hipSuccess) return e;
         }
-        hipStream_t s = (side && (l.pxy || l.pz)) ? side : st;
-        if (l.LZ == 64) {
-            if (l.V == 4) go_v<4, 64>(p, l, tiles, pt, step, s);
-            else if (l.V == 2) go_v<2, 64>(p, l, tiles, pt, step, s);
-            else if (l.V == 1) go_v<1, 64>(p, l, tiles, pt, step, s);
-            else return hipErrorInvalidValue;
-        } else if (l.V == 4 && l.LZ == 4) {
-            go_v<4, 4>(p, l, tiles, pt, step, s);
-        } else if (l.V == 2 && l.LZ == 8) {
-            go_v<2, 8>(p, l, tiles, pt, step, s);
-        } else if (l.V == 1 && l.LZ == 16) {
-            go_v<1, 16>(p, l, tiles, pt, step, s);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        if (l.LZ != 64) return hipErrorInvalidValue;
+        if (l.V == 4) go_v<4>(p, l, tiles, pt, step, st);
+        else if (l.V == 2) go_v<2>(p, l, tiles, pt, step, st);
+        else if (l.V == 1) go_v<1>(p, l, tiles, pt, step, st);
+        else return hipErrorInvalidValue;
     }
     if (ev) {
         const hipError_t e = hipEventRecord(ev[q], st);

@@ -178,10 +178,6 @@ double source_sample(int kind, const double *par, double dt, int64_t n) {
 Sim::~Sim() {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    if (side) (void)hipStreamSynchronize(side);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
     al.release_all();
 }
 
@@ -277,7 +273,7 @@ void Sim::build_probe_tiles() {
         return;
     if (ndim == 3) {
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi}, zl[2] = {ax[2].lo, ax[2].hi};
-        wave3d_plan(nx, ny, nz, Fused3DCfg{a, b, c3}, xl, yl, zl, plan3);
+        wave3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, xl, yl, zl, plan3);
         al.put(tl_dev);
         tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
     }
@@ -340,28 +336,7 @@ void Sim::launch_step(int64_t step) {
         hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
                   "2d fused step");
     } else {
-        // slab launches beside the interior one unless every launch is timed
-        bool split = !lev && plan3.l.size() > 1;
-        if (split && !side) {  // on the handle's device
-            int prev = 0;
-            hip_check(hipGetDevice(&prev), "hipGetDevice");
-            hip_check(hipSetDevice(device), "hipSetDevice");
-            hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
-            (void)hipSetDevice(prev);
-            hip_check(e, "side stream");
-        }
-        if (split) {
-            hip_check(hipEventRecord(ev_fork, st), "fork");
-            hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork wait");
-        }
-        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev, split ? side : nullptr),
-                  "3d fused step");
-        if (split) {
-            hip_check(hipEventRecord(ev_join, side), "join");
-            hip_check(hipStreamWaitEvent(st, ev_join, 0), "join wait");
-        }
+        hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev), "3d fused step");
     }
     cur = 1 - cur;
     last_launches += ndim == 2 ? 1 : (int64_t)plan3.l.size();
@@ -423,7 +398,7 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
             return 0;
         }
     } else {
-        Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0, 0};
+        Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0};
         if (wave3d_supported(s.nx, s.ny, s.nz, c)) {
             k.variant = 2;
             k.tile[0] = c.V;
@@ -439,8 +414,8 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.variant == 1) return true;
     if (k.variant != 2) return false;
     if (s.ndim == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
-    if (k.tile[3] != 0) return false;
-    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[1], k.tile[2]});
+    if (k.tile[1] != 0 || k.tile[3] != 0) return false;
+    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]});
 }
 
 // ---------------------------------------------------------------------------
@@ -908,10 +883,13 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
         if (split) {
             const Wave3DLaunch &w = s.plan3.l[l];
             o.cells = w.cells;
-            o.cpml = (w.pxy || w.pz) ? 1 : 0;
+            o.psi = w.psi;
+            o.cpml = w.pxy ? 2 : (w.pz ? 1 : 0);
             o.launches = 1;
         } else {
             o.cells = s.ncell;
+            o.psi = 0;
+            for (int a = 0; a < NPSI3; ++a) o.psi += s.psi_len[a];
             o.cpml = -1;
             o.launches = (int32_t)launches;
         }
@@ -1130,7 +1108,7 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     std::vector<fdtd_kernel_config> cand;
     if (s.ndim == 2) {
         for (int V : {1, 2, 4})
-            for (int TX : {8, 16, 32, 64}) {
+            for (int TX : {4, 8, 16, 32}) {
                 fdtd_kernel_config k{};
                 k.variant = 2;
                 k.tile[0] = V;
@@ -1139,19 +1117,15 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 if (config_ok(s, k)) cand.push_back(k);
             }
     } else {
-        const bool zslab = s.ax[2].lo + s.ax[2].hi > 0;
         for (int TX : {8, 16, 32})
-            for (int V : {1, 2, 4})
-                for (int Ve : {1, 2, 4}) {
-                    fdtd_kernel_config k{};
-                    k.variant = 2;
-                    k.tile[0] = V;
-                    k.tile[1] = zslab ? Ve : 0;
-                    k.tile[2] = TX;
-                    k.tb = 1;
-                    if (config_ok(s, k)) cand.push_back(k);
-                    if (!zslab) break;
-                }
+            for (int V : {1, 2, 4}) {
+                fdtd_kernel_config k{};
+                k.variant = 2;
+                k.tile[0] = V;
+                k.tile[2] = TX;
+                k.tb = 1;
+                if (config_ok(s, k)) cand.push_back(k);
+            }
     }
     {
         fdtd_kernel_config k{};

@@ -104,10 +104,6 @@ struct Sim {
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t *lev = nullptr;  // per-launch events of a profiled step (3D fused)
-    // 3D fused: the CPML-slab launches run on a side stream next to the
-    // interior launch (fork/join through two events each step)
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool timed = false;
     int64_t last_launches = 0;
 

@@ -185,15 +185,15 @@ def test_errors_on_device_handle():
 # 3D Yee
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape,V,Ve,npml", [
-    ((40, 36, 30), 2, 0, (6,) * 6), ((33, 29, 70), 2, 1, (5, 3, 0, 7, 4, 2)),
-    ((30, 26, 20), 4, 0, (6,) * 6), ((24, 21, 64), 4, 2, (0, 0, 0, 0, 6, 6)),
+@pytest.mark.parametrize("shape,V,TX,npml", [
+    ((40, 36, 30), 2, 0, (6,) * 6), ((33, 29, 70), 2, 5, (5, 3, 0, 7, 4, 2)),
+    ((30, 26, 20), 4, 0, (6,) * 6), ((24, 21, 64), 4, 3, (0, 0, 0, 0, 6, 6)),
     ((26, 23, 300), 4, 0, (6,) * 6), ((21, 19, 45), 1, 0, (6,) * 6),
-    ((44, 70, 128), 4, 0, (3, 5, 4, 6, 0, 0)), ((36, 41, 132), 2, 4, (4, 4, 7, 2, 5, 3)),
-    ((30, 37, 256), 1, 1, (5, 0, 0, 5, 8, 8)), ((28, 90, 96), 4, 4, (4, 4, 20, 20, 40, 40)),
-    ((20, 24, 96), 4, 1, (2, 2, 2, 2, 14, 3)),
+    ((44, 70, 128), 4, 0, (3, 5, 4, 6, 0, 0)), ((36, 41, 132), 2, 8, (4, 4, 7, 2, 5, 3)),
+    ((30, 37, 256), 1, 1, (5, 0, 0, 5, 8, 8)), ((28, 90, 96), 4, 64, (4, 4, 20, 20, 40, 40)),
+    ((20, 24, 96), 4, 2, (2, 2, 2, 2, 14, 3)),
 ])
-def test_yee3d_cpml_boxes(shape, V, Ve, npml):
+def test_yee3d_cpml_boxes(shape, V, TX, npml):
     """Zero-mean (Ricker) source: every component within 1e-4.  The slab
     widths (some asymmetric or zero) make both the slab and the interior
     workgroups of the fused kernel run."""
@@ -204,10 +204,10 @@ def test_yee3d_cpml_boxes(shape, V, Ve, npml):
     pb.source.cell = tuple((npml[2 * a] + shape[a] - npml[2 * a + 1]) // 2 for a in range(3))
     pb.source.kind = W.SRC_RICKER
     pb.source.params = (1.0, 40 * pb.dt, 1.0 / (20 * pb.dt))
-    log("yee3d", shape, V, Ve, npml)
+    log("yee3d", shape, V, TX, npml)
     ref, rrec = run_oracle(pb, pb.steps)
-    got, rec, cfg = run_gpu(pb, pb.steps, (2, (V, Ve)))
-    assert tuple(cfg["tile"]) == (V, Ve, 0, 0)
+    got, rec, cfg = run_gpu(pb, pb.steps, (2, (V, 0, TX)))
+    assert tuple(cfg["tile"]) == (V, 0, TX, 0)
     assert cfg["variant"] == 2
     assert_parity(got, ref, TOL, "yee3d fused %s" % (shape,))
     assert rel_l2(rec, rrec) <= TOL
@@ -294,7 +294,11 @@ def test_step_profile_matches_step():
     b.step(7)
     prof = b.step_profile(23)
     assert sum(p["cells"] for p in prof) == pb.cells
-    assert len(prof) >= 3 and [p["cpml"] for p in prof].count(0) == 1
+    # interior launch (z-slab code) and x/y-slab launch; every psi value once
+    assert [p["cpml"] for p in prof] == [1, 2]
+    sx, sy, sz = 12, 12, 12
+    nx, ny, nz = pb.shape
+    assert sum(p["psi"] for p in prof) == 4 * (sx * ny * nz + nx * sy * nz + nx * ny * sz)
     assert all(p["ms"] > 0 and p["launches"] == 1 for p in prof)
     assert b.steps_done() == 30
     for f in ("ex", "ey", "ez", "hx", "hy", "hz"):
@@ -303,5 +307,6 @@ def test_step_profile_matches_step():
     a.set_kernel(1)
     prof = a.step_profile(2)
     assert len(prof) == 1 and prof[0]["cpml"] == -1 and prof[0]["cells"] == pb.cells
+    assert prof[0]["psi"] == 4 * (sx * ny * nz + nx * sy * nz + nx * ny * sz)
     a.close()
     b.close()
