@@ -113,7 +113,7 @@ hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
 // Fused 3D.  V: z cells per thread; TX: x planes marched by one interior
 // workgroup (0 = 16; workgroups with x/y CPML code march max(1, TX/4)).
 struct Fused3DCfg { int V; int TX; };
-// One workgroup's tile: planes [i0, i1), rows from j0 (4*64/LZ of them),
+// One workgroup's tile: planes [i0, i1), rows from j0 (one per wavefront),
 // z cells [ks, k1) of the segment whose lanes start at the aligned base k0.
 // i0 == i1 marks padding.
 struct Tile3 {
@@ -121,7 +121,7 @@ struct Tile3 {
 };
 // One launch of the fused 3D kernel over a list of tiles.
 struct Wave3DLaunch {
-    int V, LZ;     // z cells per thread, threads per z row (64)
+    int V, wpb;    // z cells per thread; wavefronts (y rows) per workgroup
     bool pxy, pz;  // CPML code for x/y slabs, z slabs
     int off, n;    // tile list entries [off, off + n) (multiple of 8)
     int64_t cells; // cells the launch updates

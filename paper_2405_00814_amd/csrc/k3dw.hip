@@ -16,7 +16,7 @@
 // segment's last lane, a load).  State is double buffered (read s0, write
 // s1), so every recomputed value equals its owner's value bit for bit.
 //
-// Tiles: (x range, band of WPB*64/LZ y rows, z segment of LZ*V cells).  Rows
+// Tiles: (x range, band of WPB y rows, z segment of 64*V cells).  Rows
 // of one workgroup exchange the values their neighbours need through LDS
 // (old Ex, Ez for the row below; new Hx, Hz for the row above), so only the
 // band's first row recomputes H at j-1 and only its last loads E at j+1.  The
@@ -72,27 +72,24 @@ __device__ __forceinline__ float znext(const float (&x)[V], int q, float seam, b
 // PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A tile whose
 // cells and recomputed neighbours (plane i0-1, row j-1, z = ks-1) touch no x
 // or y slab may run PXY = false, none touching a z slab PZ = false.
-// wavefronts per workgroup (64 * k3d_wpb(LZ) / LZ y rows)
-constexpr int k3d_wpb(int LZ) { return LZ == 64 ? 8 : 4; }
-
-template <int V, int LZ, bool PXY, bool PZ, int MAT>
-__global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Tile3 *tiles, ProbeTiles pt,
+// WPB: wavefronts per workgroup, one y row each
+template <int V, int WPB, bool PXY, bool PZ, int MAT>
+__global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *tiles, ProbeTiles pt,
                                                  int64_t step) {
-    constexpr int RW = 64 / LZ;  // y rows per wavefront
+    constexpr int LZ = 64;  // lanes per z row
     const Tile3 T = tiles[xcd_block(blockIdx.x, gridDim.x)];
     if (T.i0 >= T.i1) return;  // padding
     const int lane = threadIdx.x & 63;
-    const int zlane = lane & (LZ - 1);
+    const int zlane = lane;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int j = LZ == 64 ? T.j0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
-                           : T.j0 + (int)(threadIdx.x >> 6) * RW + lane / LZ;
+    const int j = T.j0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     // z segment: lanes from the aligned base T.k0, active on [ks, kend)
     const int ks = T.ks, kend = T.k1, kb = T.k0 + zlane * V, km = ks - 1;
     const bool ok = j < ny && kb >= ks && kb < kend;  // ks, kend: multiples of V
     const bool first = kb == ks;
     const bool yj = j + 1 < ny, jm = j >= 1;
     const bool ke = kend < nz;
-    const bool last = kb + V == kend;  // zlane LZ-1 unless the segment is cut short
+    const bool last = kb + V == kend;  // lane 63 unless the segment is cut short
     const unsigned sxs = (unsigned)ny * nz, sys = nz;
     const int jr = j < ny ? j : 0;
     const int sy = p.y.lo + p.y.hi, sz = p.z.lo + p.z.hi;
@@ -133,7 +130,7 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
         }
     };
 
-    // y profiles (wave-uniform for LZ = 64)
+    // y profiles (wave-uniform)
     const AxP Y = axp<PXY>(p.y, jr), Ym = axp<PXY>(p.y, jm && j < ny ? j - 1 : 0);
 
     // carried between planes: E (y, z) of the current plane and H (y, z) of
@@ -198,7 +195,6 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
 
     // LDS rows: [0] Ex, [1] Ez (old), [2] Hx, [3] Hz (new) of every thread's
     // V cells at index threadIdx.x * V; the row above is LZ threads back
-    constexpr int WPB = k3d_wpb(LZ);
     __shared__ float sh[4][WPB * 64 * V];
     const int tq = (int)threadIdx.x * V;
     const bool top = (int)threadIdx.x < LZ, bot = (int)threadIdx.x >= (WPB * 64 - LZ);
@@ -297,7 +293,7 @@ __global__ __launch_bounds__(64 * k3d_wpb(LZ)) void k3d_march(Prob3D p, const Ti
             ldv<V>(hx_jm, &sh[2][tq - LZ * V]);
             ldv<V>(hz_jm, &sh[3][tq - LZ * V]);
         }
-        if (LZ != 64 || top) {  // wave-uniform for LZ = 64
+        if (top) {  // wave-uniform
             const bool o = ok && jm && top;
             const unsigned q0 = c - (jm ? sys : 0u);
             float aex[V], aey[V], aez[V], aeyx[V], ahx[V], ahz[V], adb[V];
@@ -540,7 +536,7 @@ void zsegs(std::vector<ZSeg> &out, int lo, int hi, int w) {
 // Launch plan.  x: the planes clear of the x slabs (a tile's plane i0-1
 // included) and the slab ends, in chunks of TX planes (TX/4 for the launch
 // with x/y CPML code, which has fewer tiles and more latency per plane);
-// y: bands of 64*k3d_wpb(LZ)/LZ rows, clear of the y slabs (row j0-1
+// y: bands of WPB rows (8 interior, 4 slab), clear of the y slabs (row j0-1
 // included) or not; z: segments of 64V cells (z-slab cells are handled by
 // the correction step of the PZ instances).  The interior launch takes the
 // (interior x chunk, interior y band) tiles, the slab launch all others.
@@ -556,13 +552,13 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
     auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
     const int xl = xlohi[0] == 0 ? 0 : std::min(nx, xlohi[0] + 1);
     const int xh = std::max(xl, nx - xlohi[1]);
-    auto add = [&](int Vl, int LZ, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
+    auto add = [&](int Vl, int wpb, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
         if (zseg.empty()) return;
-        const int RB = k3d_wpb(LZ) * (64 / LZ);
+        const int RB = wpb;
         const int tx = pxy ? TXs : TX;
         Wave3DLaunch l{};
         l.V = Vl;
-        l.LZ = LZ;
+        l.wpb = wpb;
         l.pxy = pxy;
         l.pz = pz;
         l.off = (int)pl.tiles.size();
@@ -577,24 +573,28 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
         put(0, xl, true);
         put(xl, xh, false);
         put(xh, nx, true);
+        // y rows are classified in groups of 8 (the interior band height);
+        // the slab launch splits its groups into bands of RB rows
         for (size_t q = 0; q < xr.size(); ++q)
-            for (int j0 = 0; j0 < ny; j0 += RB) {
+            for (int g0 = 0; g0 < ny; g0 += 8) {
                 bool ys = false;
-                for (int j = j0 - 1; j < j0 + RB && j < ny; ++j) ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
+                for (int j = g0 - 1; j < g0 + 8 && j < ny; ++j) ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
                 if (pxy != (xslab[q] || ys)) continue;
-                const int rows = std::min(RB, ny - j0);
-                const int64_t xn = xr[q].b - xr[q].a;
-                int64_t xs = 0, ysn = 0;
-                for (int i = xr[q].a; i < xr[q].b; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
-                for (int j = j0; j < j0 + rows; ++j) ysn += inslab(ny, ylohi[0], ylohi[1], j);
-                for (const ZSeg &z : zseg) {
-                    pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, {0, 0}});
-                    const int64_t zn = z.end - z.start;
-                    int64_t zs = 0;
-                    for (int k = z.start; k < z.end; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
-                    l.cells += xn * rows * zn;
-                    // four psi per slab a cell lies in
-                    l.psi += 4 * (xs * rows * zn + xn * ysn * zn + xn * rows * zs);
+                for (int j0 = g0; j0 < std::min(g0 + 8, ny); j0 += RB) {
+                    const int rows = std::min(RB, ny - j0);
+                    const int64_t xn = xr[q].b - xr[q].a;
+                    int64_t xs = 0, ysn = 0;
+                    for (int i = xr[q].a; i < xr[q].b; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
+                    for (int j = j0; j < j0 + rows; ++j) ysn += inslab(ny, ylohi[0], ylohi[1], j);
+                    for (const ZSeg &z : zseg) {
+                        pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, {0, 0}});
+                        const int64_t zn = z.end - z.start;
+                        int64_t zs = 0;
+                        for (int k = z.start; k < z.end; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
+                        l.cells += xn * rows * zn;
+                        // four psi per slab a cell lies in
+                        l.psi += 4 * (xs * rows * zn + xn * ysn * zn + xn * rows * zs);
+                    }
                 }
             }
         if (pl.tiles.size() == (size_t)l.off) return;
@@ -603,40 +603,43 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
         pl.l.push_back(l);
     };
     const bool anyxy = xlohi[0] + xlohi[1] + ylohi[0] + ylohi[1] > 0;
-    auto both = [&](int Vl, int LZ, bool pz, const std::vector<ZSeg> &zseg) {
-        add(Vl, LZ, false, pz, zseg);
-        if (anyxy) add(Vl, LZ, true, pz, zseg);
+    // slab workgroups: 4 rows (fewer registers per wave are left, so smaller
+    // workgroups keep more of them resident)
+    auto both = [&](int Vl, bool pz, const std::vector<ZSeg> &zseg) {
+        add(Vl, 8, false, pz, zseg);
+        if (anyxy) add(Vl, 4, true, pz, zseg);
     };
     std::vector<ZSeg> zseg;
     zsegs(zseg, 0, nz, 64 * V);
-    both(V, 64, zlohi[0] + zlohi[1] > 0, zseg);
+    both(V, zlohi[0] + zlohi[1] > 0, zseg);
 }
 
-template <int V, int LZ, bool PXY, bool PZ, int MAT>
+template <int V, int WPB, bool PXY, bool PZ, int MAT>
 static void go(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                int64_t step, hipStream_t st) {
-    hipLaunchKernelGGL((k3d_march<V, LZ, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(64 * k3d_wpb(LZ)), 0, st, p,
+    hipLaunchKernelGGL((k3d_march<V, WPB, PXY, PZ, MAT>), dim3((unsigned)l.n), dim3(64 * WPB), 0, st, p,
                        tiles + l.off, pt, step);
 }
 
-template <int V, int LZ, bool PXY, bool PZ>
+template <int V, int WPB, bool PXY, bool PZ>
 static void go_m(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                  int64_t step, hipStream_t st) {
     const int mat = p.db ? 2 : (p.ca ? 1 : 0);
-    if (mat == 0) go<V, LZ, PXY, PZ, 0>(p, l, tiles, pt, step, st);
-    else if (mat == 1) go<V, LZ, PXY, PZ, 1>(p, l, tiles, pt, step, st);
-    else go<V, LZ, PXY, PZ, 2>(p, l, tiles, pt, step, st);
+    if (mat == 0) go<V, WPB, PXY, PZ, 0>(p, l, tiles, pt, step, st);
+    else if (mat == 1) go<V, WPB, PXY, PZ, 1>(p, l, tiles, pt, step, st);
+    else go<V, WPB, PXY, PZ, 2>(p, l, tiles, pt, step, st);
 }
 
+// interior launches: 8-row workgroups; x/y-slab launches: 4-row ones
 template <int V>
 static void go_v(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                  int64_t step, hipStream_t st) {
     if (l.pxy) {
-        if (l.pz) go_m<V, 64, true, true>(p, l, tiles, pt, step, st);
-        else go_m<V, 64, true, false>(p, l, tiles, pt, step, st);
+        if (l.pz) go_m<V, 4, true, true>(p, l, tiles, pt, step, st);
+        else go_m<V, 4, true, false>(p, l, tiles, pt, step, st);
     } else {
-        if (l.pz) go_m<V, 64, false, true>(p, l, tiles, pt, step, st);
-        else go_m<V, 64, false, false>(p, l, tiles, pt, step, st);
+        if (l.pz) go_m<V, 8, false, true>(p, l, tiles, pt, step, st);
+        else go_m<V, 8, false, false>(p, l, tiles, pt, step, st);
     }
 }
 
@@ -648,7 +651,7 @@ hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *ti
             const hipError_t e = hipEventRecord(ev[q++], st);
             if (e != hipSuccess) return e;
         }
-        if (l.LZ != 64) return hipErrorInvalidValue;
+        if (l.wpb != (l.pxy ? 4 : 8)) return hipErrorInvalidValue;
         if (l.V == 4) go_v<4>(p, l, tiles, pt, step, st);
         else if (l.V == 2) go_v<2>(p, l, tiles, pt, step, st);
         else if (l.V == 1) go_v<1>(p, l, tiles, pt, step, st);
