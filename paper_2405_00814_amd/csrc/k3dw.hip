@@ -225,6 +225,19 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
         const bool s63 = ok && last && ke;
         const float ey_e = s63 ? ey0[r0 + kend] : 0.f;
         const float ex_e = s63 ? ex0[r0 + kend] : 0.f;
+        // old z-slab psi of the lane's slab cells, issued with the field loads
+        float zo[4][V];
+        const unsigned zrow = zs3(i, j, 0, ny, sz);
+        if (PZ && zany) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const unsigned q = zrow + (zsv[v] >= 0 ? zsv[v] : 0);
+                zo[0][v] = P0[PSI_HXZ][q];
+                zo[1][v] = P0[PSI_HYZ][q];
+                zo[2][v] = P0[PSI_EXZ][q];
+                zo[3][v] = P0[PSI_EYZ][q];
+            }
+        }
         stv<V>(&sh[0][tq], ex);
         stv<V>(&sh[1][tq], ez);
         __syncthreads();
@@ -261,20 +274,17 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
                 hz[v] = hzo[v] - db[v] * ((X.kH * dEyx + (inx ? pzx[v] : 0.f)) - (Y.kH * dExy + (iny ? pzy[v] : 0.f)));
             }
             if (PZ && zany) {
-                const unsigned row = zs3(i, j, 0, ny, sz);
-                float o1[V], o2[V], kh[V], bh[V], chh[V];
-                zload(o1, kh, bh, chh, P0[PSI_HXZ], row, p.z.kH, p.z.bH, p.z.cH);
-#pragma unroll
-                for (int v = 0; v < V; ++v) o2[v] = P0[PSI_HYZ][row + (zsv[v] >= 0 ? zsv[v] : 0)];
+                const unsigned row = zrow;
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (zsv[v] >= 0) {
-                        const float pxz = bh[v] * o1[v] + chh[v] * dEyzA[v];
-                        const float pyz = bh[v] * o2[v] + chh[v] * dExzA[v];
+                        const float kh = p.z.kH[kb + v], bh = p.z.bH[kb + v], chh = p.z.cH[kb + v];
+                        const float pxz = bh * zo[0][v] + chh * dEyzA[v];
+                        const float pyz = bh * zo[1][v] + chh * dExzA[v];
                         P1[PSI_HXZ][row + zsv[v]] = pxz;
                         P1[PSI_HYZ][row + zsv[v]] = pyz;
-                        hx[v] += db[v] * ((kh[v] - idzH) * dEyzA[v] + pxz);
-                        hy[v] -= db[v] * ((kh[v] - idzH) * dExzA[v] + pyz);
+                        hx[v] += db[v] * ((kh - idzH) * dEyzA[v] + pxz);
+                        hy[v] -= db[v] * ((kh - idzH) * dExzA[v] + pyz);
                     }
             }
             if (iny) { stv<V>(P1[PSI_HXY] + qy, pxy); stv<V>(P1[PSI_HZY] + qy, pzy); }
@@ -423,25 +433,23 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
             if (PZ && zany) {
                 // z-slab psi of Ex, Ey; cells the E layer does not update keep
                 // their (zero) value
-                const unsigned row = zs3(i, j, 0, ny, sz);
-                float o3[V], o4[V], kz[V], bz[V], cz[V];
-                zload(o3, kz, bz, cz, P0[PSI_EXZ], row, p.z.kE, p.z.bE, p.z.cE);
-#pragma unroll
-                for (int v = 0; v < V; ++v) o4[v] = P0[PSI_EYZ][row + (zsv[v] >= 0 ? zsv[v] : 0)];
+                const unsigned row = zrow;
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (zsv[v] >= 0) {
                         const int k = kb + v;
+                        const float kz = p.z.kE[k], bz = p.z.bE[k], cz = p.z.cE[k];
+                        float o3 = zo[2][v], o4 = zo[3][v];
                         if (jm && k >= 1) {
-                            o3[v] = bz[v] * o3[v] + cz[v] * dHyzA[v];
-                            exw[v] -= cb[v] * ((kz[v] - idzE) * dHyzA[v] + o3[v]);
+                            o3 = bz * o3 + cz * dHyzA[v];
+                            exw[v] -= cb[v] * ((kz - idzE) * dHyzA[v] + o3);
                         }
                         if (im && k >= 1) {
-                            o4[v] = bz[v] * o4[v] + cz[v] * dHxzA[v];
-                            eyw[v] += cb[v] * ((kz[v] - idzE) * dHxzA[v] + o4[v]);
+                            o4 = bz * o4 + cz * dHxzA[v];
+                            eyw[v] += cb[v] * ((kz - idzE) * dHxzA[v] + o4);
                         }
-                        P1[PSI_EXZ][row + zsv[v]] = o3[v];
-                        P1[PSI_EYZ][row + zsv[v]] = o4[v];
+                        P1[PSI_EXZ][row + zsv[v]] = o3;
+                        P1[PSI_EYZ][row + zsv[v]] = o4;
                     }
             }
 #pragma unroll
