@@ -238,6 +238,14 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
                 zo[3][v] = P0[PSI_EYZ][q];
             }
         }
+        // x/y-slab psi of H (vector rows), also issued before the barrier
+        float pxy[V], pzx[V], pyx[V], pzy[V];
+        const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
+        const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
+        ld(pxy, P0[PSI_HXY], qy, iny);
+        ld(pzy, P0[PSI_HZY], qy, iny);
+        ld(pyx, P0[PSI_HYX], qx, inx);
+        ld(pzx, P0[PSI_HZX], qx, inx);
         stv<V>(&sh[0][tq], ex);
         stv<V>(&sh[1][tq], ez);
         __syncthreads();
@@ -249,13 +257,6 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
         // ---- H layer at the own cells ----
         float hx[V], hy[V], hz[V];
         {
-            float pxy[V], pzx[V], pyx[V], pzy[V];  // x/y-slab psi (vector rows)
-            const bool iny = PXY && ok && Y.s >= 0, inx = PXY && ok && X.s >= 0;
-            const unsigned qy = iny ? ys3(i, Y.s, kb, sy, nz) : 0, qx = inx ? xs3(X.s, j, kb, ny, nz) : 0;
-            ld(pxy, P0[PSI_HXY], qy, iny);
-            ld(pzy, P0[PSI_HZY], qy, iny);
-            ld(pyx, P0[PSI_HYX], qx, inx);
-            ld(pzx, P0[PSI_HZX], qx, inx);
             float dEyzA[V], dExzA[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
