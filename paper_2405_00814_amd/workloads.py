@@ -15,8 +15,8 @@ out of the absorbing layer.  All randomness is numpy PCG64 with an explicit
 seed.
 
 The time step comes from a Courant number S: dt = S * min(dx) / c0.  The
-spatial step of the dielectric scenes follows the paper's "20 points per
-shortest wavelength" rule (Sec. V-B), with the shortest wavelength taken at
+spatial step of the dielectric scenes follows the paper's sampling rule of
+twenty cells per shortest wavelength (Sec. V-B), with that wavelength taken at
 three times the Ricker peak frequency in the densest medium.
 """
 from __future__ import annotations
@@ -107,7 +107,7 @@ def courant_dt(S: float, dx: Sequence[float]) -> float:
 
 
 def dx_for_ricker(f_peak: float, eps_max: float, ppw: int = 20) -> float:
-    """Spatial step from 'ppw points per shortest wavelength', shortest
+    """Spatial step giving ppw cells per shortest wavelength, shortest
     wavelength at 3 * f_peak in the densest medium."""
     return C0 / (3.0 * f_peak * math.sqrt(eps_max) * ppw)
 
