@@ -78,7 +78,7 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
             s.kcfg = fdtd_kernel_config{};
             s.kcfg.variant = 2;
             s.kcfg.tile[0] = s.ny % 2 == 0 ? 2 : 1;
-            s.kcfg.tile[1] = 8;
+            s.kcfg.tile[1] = 4;
             s.kcfg.tb = 1;
         }
         s.pt_ntiles = -1;
@@ -184,8 +184,9 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
             s.n_rec = k0;
             for (int64_t k = k0; k < k1; ++k) {
                 const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
+                const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
                 hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
-                                          cap_br + (k - k0) * nd),
+                                          cap_br + (k - k0) * nd, s.split2d() ? &sp : nullptr),
                           "recompute");
                 s.cur = 1 - s.cur;
                 s.n_done += 1;

@@ -2,12 +2,13 @@
 //
 // Every problem keeps its own double-buffered state and coefficient tables
 // (a Sim).  Problems are grouped by the vector width their row length
-// allows (4, 2 or 1 float per lane); each group has one flat list of
-// wavefront tiles over all of its problems, so one launch per group advances
-// every problem by one step, with the load spread evenly over the tiles
-// whatever the mix of sizes.  Launches read the step number from a device
-// counter, which lets a captured HIP graph of GRAPH_STEPS steps be replayed
-// for any step range.
+// allows (2 floats per lane for even rows, 1 for odd ones); each group has one
+// flat list of wavefront tiles over all of its problems, interior tiles first
+// and CPML-slab tiles after them, so two launches per group (without and with
+// the CPML code) advance every problem by one step, with the load spread
+// evenly over the tiles whatever the mix of sizes.  Launches read the step
+// number from a device counter, which lets a captured HIP graph of
+// GRAPH_STEPS steps be replayed for any step range.
 #include <algorithm>
 #include <memory>
 
@@ -21,7 +22,9 @@ struct BatchGroup {
     BatchTile *tiles = nullptr;
     int ntiles = 0;
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
-    std::vector<int> tile_base;  // first tile of each problem of the group
+    std::vector<int> tile_base;  // first tile of each problem of the group (problem order)
+    std::vector<int> pos;        // problem-order tile -> place in the launch list
+    int n_inner = 0;             // list: interior tiles, then slab tiles
 };
 
 }  // namespace gem
@@ -75,7 +78,8 @@ static void batch_build_probes(fdtd_batch &b) {
             Fused2DCfg c{g.V, g.TX};
             for (size_t p = 0; p < s.probe_cells.size(); ++p) {
                 const int i = (int)(s.probe_cells[p] / s.ny), j = (int)(s.probe_cells[p] % s.ny);
-                ent.push_back({g.tile_base[qi] + fused2d_tile_of(s.nx, s.ny, c, i, j), (int)cells_all.size()});
+                ent.push_back({g.pos[(size_t)(g.tile_base[qi] + fused2d_tile_of(s.nx, s.ny, c, i, j))],
+                               (int)cells_all.size()});
                 cells_all.push_back((int)s.probe_cells[p]);
                 slots_all.push_back((int)p);
             }
@@ -142,7 +146,11 @@ static void batch_sync_probs(fdtd_batch &b) {
 static void batch_launch_one(fdtd_batch &b, int parity, int k, hipStream_t st) {
     for (auto &g : b.groups) {
         ProbeTiles pt{g.pt_start, g.pt_cell, g.pt_slot};
-        hip_check(launch_batch_step(b.probs_dev[parity], g.tiles, g.ntiles, pt, g.V, g.TX, b.step_base, k, st),
+        hip_check(launch_batch_step(b.probs_dev[parity], g.tiles, 0, g.n_inner, false, pt, g.V, g.TX,
+                                    b.step_base, k, st),
+                  "batch step");
+        hip_check(launch_batch_step(b.probs_dev[parity], g.tiles, g.n_inner, g.ntiles - g.n_inner, true, pt,
+                                    g.V, g.TX, b.step_base, k, st),
                   "batch step");
     }
 }
@@ -193,14 +201,16 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
             init_sim(*b->sims.back(), &d);
         }
         // groups by vector width
-        for (int V : {4, 2, 1}) {
+        // groups by vector width: 2 for even rows, 1 for odd ones (the
+        // 4-wide instance holds too many registers for the CPML tiles)
+        for (int V : {2, 1}) {
             BatchGroup g;
             g.V = V;
-            g.TX = 16;
+            g.TX = 8;
             std::vector<BatchTile> tiles;
             for (int q = 0; q < n; ++q) {
                 const Sim &s = *b->sims[(size_t)q];
-                const int vq = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
+                const int vq = s.ny % 2 == 0 ? 2 : 1;
                 if (vq != V) continue;
                 g.probs.push_back(q);
                 g.tile_base.push_back((int)tiles.size());
@@ -210,6 +220,27 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
                     for (int sy = 0; sy < nsy; ++sy) tiles.push_back(BatchTile{q, cx, sy});
             }
             if (g.probs.empty()) continue;
+            // interior tiles (no CPML code) first, then the slab tiles; pos
+            // maps a tile's place in problem order to its place in the list
+            {
+                std::vector<BatchTile> inner, outer;
+                std::vector<int> where(tiles.size());
+                for (size_t t = 0; t < tiles.size(); ++t) {
+                    const Sim &s = *b->sims[(size_t)tiles[t].prob];
+                    const int xl[2] = {s.ax[0].lo, s.ax[0].hi}, yl[2] = {s.ax[1].lo, s.ax[1].hi};
+                    const int nsy = (s.ny + 64 * V - 1) / (64 * V);
+                    const int tid = tiles[t].cx * nsy + tiles[t].sy;
+                    const bool in = fused2d_interior(s.nx, s.ny, Fused2DCfg{V, g.TX}, xl, yl, tid);
+                    where[t] = in ? (int)inner.size() : -1 - (int)outer.size();
+                    (in ? inner : outer).push_back(tiles[t]);
+                }
+                g.n_inner = (int)inner.size();
+                g.pos.resize(tiles.size());
+                for (size_t t = 0; t < tiles.size(); ++t)
+                    g.pos[t] = where[t] >= 0 ? where[t] : g.n_inner + (-1 - where[t]);
+                tiles = inner;
+                tiles.insert(tiles.end(), outer.begin(), outer.end());
+            }
             g.ntiles = (int)tiles.size();
             g.tiles = (BatchTile *)b->al.get(tiles.size() * sizeof(BatchTile));
             hip_check(hipMemcpyAsync(g.tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
@@ -279,7 +310,8 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n) {
         b->last_launches = 0;
         hip_check(hipEventRecord(b->ev0, b->st), "event");
         int64_t k = 0;
-        const int64_t ng = (int64_t)b->groups.size();
+        int64_t ng = 0;  // launches per step
+        for (const auto &g : b->groups) ng += (g.n_inner > 0) + (g.ntiles > g.n_inner);
         // align to an even step so that graph replays start on buffer set 0
         while (k < n && ((b->n_done + k) & 1)) {
             batch_launch_one(*b, (int)((b->n_done + k) & 1), (int)k, b->st);

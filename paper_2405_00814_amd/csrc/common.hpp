@@ -102,9 +102,20 @@ struct ProbeTiles {
 // ---------------------------------------------------------------------------
 hipError_t launch_2d_ref(const Prob2D &p, int64_t step, hipStream_t st);
 struct Fused2DCfg { int V; int TX; };
+// Tile ids of the fused 2D kernel split into those clear of the CPML slabs
+// and the rest (device arrays).
+struct TileSplit2D {
+    const int *inner;
+    int n_inner;
+    const int *outer;
+    int n_outer;
+};
+// split (optional): launch the interior tiles without the CPML code and the
+// slab tiles with it; nullptr: one launch over all tiles.
 hipError_t launch_2d_fused(const Prob2D &p, const Fused2DCfg &c, const ProbeTiles &pt,
                            int64_t step, hipStream_t st, const int *design, float *cap_ez,
-                           float *cap_br);
+                           float *cap_br, const TileSplit2D *split = nullptr);
+bool fused2d_interior(int nx, int ny, const Fused2DCfg &c, const int *xlohi, const int *ylohi, int t);
 int fused2d_ntiles(int nx, int ny, const Fused2DCfg &c);
 int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
@@ -156,9 +167,10 @@ hipError_t launch_node_source_probe(float *x, int64_t src_node, const float *src
 
 // Batched 2D: one launch advances every problem by one step.
 struct BatchTile { int prob; int cx; int sy; };
-hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, int ntiles,
-                             const ProbeTiles &pt, int V, int TX, const int64_t *step_base, int k,
-                             hipStream_t st);
+// tiles [t0, t0 + ntiles) of a group's list; pml: they touch a CPML slab
+hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, int t0, int ntiles,
+                             bool pml, const ProbeTiles &pt, int V, int TX, const int64_t *step_base,
+                             int k, hipStream_t st);
 hipError_t launch_advance(int64_t *step_base, int64_t by, hipStream_t st);
 
 // Adjoint 2D kernels (see adjoint.hip).

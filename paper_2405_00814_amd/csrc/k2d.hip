@@ -7,6 +7,8 @@
 // self weight Ca = A-/A+ and curl weight Cb = dt/(A+ eps).  CPML auxiliary
 // values ride along in the boundary slabs.  The soft source is added after
 // the E layer; probes sample Ez afterwards.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace gem {
@@ -363,11 +365,13 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
 }
 
 template <int V, bool PML, bool CAPTURE>
+// list: tile ids of this launch (nullptr: tiles 0 .. ntiles-1)
 __global__ __launch_bounds__(256) void k2d_fused(Prob2D p, int TX, int nsy, int ntiles,
-                                                 ProbeTiles pt, int64_t step,
+                                                 const int *list, ProbeTiles pt, int64_t step,
                                                  int4 design, float *cap_ez, float *cap_br) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (t >= ntiles) return;  // whole wavefront leaves; no block barriers below
+    const int tw = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (tw >= ntiles) return;  // whole wavefront leaves; no block barriers below
+    const int t = list ? list[tw] : tw;
     const int cx = t / nsy, sy = t - cx * nsy;
     fused2d_tile<V, PML, CAPTURE>(p, TX, cx, sy, pt, pt.start[t], pt.start[t + 1], step, design,
                                   cap_ez, cap_br);
@@ -376,16 +380,18 @@ __global__ __launch_bounds__(256) void k2d_fused(Prob2D p, int TX, int nsy, int 
 // Batched: the tile list spans many independent problems; the step index is
 // read from device memory (base + k) so that a captured graph of launches can
 // be replayed at any step.
-template <int V>
+// tiles [t0, t0 + ntiles) of a group's list; PML: the slab tiles
+template <int V, bool PML>
 __global__ __launch_bounds__(256) void k2d_batch(const Prob2D *__restrict__ probs,
-                                                 const BatchTile *__restrict__ tiles, int ntiles,
+                                                 const BatchTile *__restrict__ tiles, int t0, int ntiles,
                                                  ProbeTiles pt, int TX,
                                                  const int64_t *__restrict__ step_base, int k) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (t >= ntiles) return;
+    const int tw = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (tw >= ntiles) return;
+    const int t = t0 + tw;
     const BatchTile bt = tiles[t];
     const int64_t step = *step_base + k;
-    fused2d_tile<V, true, false>(probs[bt.prob], TX, bt.cx, bt.sy, pt, pt.start[t],
+    fused2d_tile<V, PML, false>(probs[bt.prob], TX, bt.cx, bt.sy, pt, pt.start[t],
                                  pt.start[t + 1], step, make_int4(0, 0, 0, 0), nullptr, nullptr);
 }
 
@@ -396,17 +402,23 @@ __global__ void k_advance(int64_t *step_base, int64_t by) {
     if (t == 0) step_base[t] += by;
 }
 
-hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, int ntiles,
-                             const ProbeTiles &pt, int V, int TX, const int64_t *step_base, int k,
-                             hipStream_t st) {
+hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, int t0, int ntiles,
+                             bool pml, const ProbeTiles &pt, int V, int TX, const int64_t *step_base,
+                             int k, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((ntiles + 3) / 4);
+    const dim3 g((unsigned)((ntiles + 3) / 4)), b(256);
+#define GEM_B(VV)                                                                                     \
+    do {                                                                                              \
+        if (pml) hipLaunchKernelGGL((k2d_batch<VV, true>), g, b, 0, st, probs_dev, tiles, t0, ntiles, pt, TX, step_base, k); \
+        else hipLaunchKernelGGL((k2d_batch<VV, false>), g, b, 0, st, probs_dev, tiles, t0, ntiles, pt, TX, step_base, k); \
+    } while (0)
     switch (V) {
-        case 1: hipLaunchKernelGGL(k2d_batch<1>, dim3(nb), dim3(256), 0, st, probs_dev, tiles, ntiles, pt, TX, step_base, k); break;
-        case 2: hipLaunchKernelGGL(k2d_batch<2>, dim3(nb), dim3(256), 0, st, probs_dev, tiles, ntiles, pt, TX, step_base, k); break;
-        case 4: hipLaunchKernelGGL(k2d_batch<4>, dim3(nb), dim3(256), 0, st, probs_dev, tiles, ntiles, pt, TX, step_base, k); break;
+        case 1: GEM_B(1); break;
+        case 2: GEM_B(2); break;
+        case 4: GEM_B(4); break;
         default: return hipErrorInvalidValue;
     }
+#undef GEM_B
     return hipGetLastError();
 }
 
@@ -433,30 +445,42 @@ bool fused2d_supported(int nx, int ny, const Fused2DCfg &c) {
 }
 
 template <int V, bool PML, bool CAP>
-static void go2d(const Prob2D &p, const Fused2DCfg &c, const ProbeTiles &pt, int64_t step,
-                 hipStream_t st, int4 d, float *ce, float *cbr) {
+static void go2d(const Prob2D &p, const Fused2DCfg &c, const int *list, int ntiles, const ProbeTiles &pt,
+                 int64_t step, hipStream_t st, int4 d, float *ce, float *cbr) {
+    if (ntiles <= 0) return;
     const int nsy = (p.ny + 64 * V - 1) / (64 * V);
-    const int ntiles = fused2d_ntiles(p.nx, p.ny, c);
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
-    hipLaunchKernelGGL((k2d_fused<V, PML, CAP>), dim3(nb), dim3(256), 0, st, p, c.TX, nsy,
-                       ntiles, pt, step, d, ce, cbr);
+    hipLaunchKernelGGL((k2d_fused<V, PML, CAP>), dim3(nb), dim3(256), 0, st, p, c.TX, nsy, ntiles, list,
+                       pt, step, d, ce, cbr);
 }
 
 hipError_t launch_2d_fused(const Prob2D &p, const Fused2DCfg &c, const ProbeTiles &pt,
                            int64_t step, hipStream_t st, const int *design, float *cap_ez,
-                           float *cap_br) {
+                           float *cap_br, const TileSplit2D *split) {
     const bool pml = (p.x.lo + p.x.hi + p.y.lo + p.y.hi) > 0;
     const bool cap = design != nullptr;
     const int4 d = cap ? make_int4(design[0], design[1], design[2], design[3]) : make_int4(0, 0, 0, 0);
-#define GEM_GO(VV)                                                              \
-    do {                                                                        \
-        if (pml) {                                                              \
-            if (cap) go2d<VV, true, true>(p, c, pt, step, st, d, cap_ez, cap_br);  \
-            else go2d<VV, true, false>(p, c, pt, step, st, d, cap_ez, cap_br);     \
-        } else {                                                                \
-            if (cap) go2d<VV, false, true>(p, c, pt, step, st, d, cap_ez, cap_br); \
-            else go2d<VV, false, false>(p, c, pt, step, st, d, cap_ez, cap_br);    \
-        }                                                                       \
+    // with CPML and a split: the interior tiles without the CPML code, then
+    // the slab tiles with it
+    const bool two = pml && split != nullptr;
+    const int all = fused2d_ntiles(p.nx, p.ny, c);
+#define GEM_GO(VV)                                                                                 \
+    do {                                                                                           \
+        if (two) {                                                                                 \
+            if (cap) {                                                                             \
+                go2d<VV, false, true>(p, c, split->inner, split->n_inner, pt, step, st, d, cap_ez, cap_br); \
+                go2d<VV, true, true>(p, c, split->outer, split->n_outer, pt, step, st, d, cap_ez, cap_br);  \
+            } else {                                                                               \
+                go2d<VV, false, false>(p, c, split->inner, split->n_inner, pt, step, st, d, cap_ez, cap_br); \
+                go2d<VV, true, false>(p, c, split->outer, split->n_outer, pt, step, st, d, cap_ez, cap_br);  \
+            }                                                                                      \
+        } else if (pml) {                                                                          \
+            if (cap) go2d<VV, true, true>(p, c, nullptr, all, pt, step, st, d, cap_ez, cap_br);    \
+            else go2d<VV, true, false>(p, c, nullptr, all, pt, step, st, d, cap_ez, cap_br);       \
+        } else {                                                                                   \
+            if (cap) go2d<VV, false, true>(p, c, nullptr, all, pt, step, st, d, cap_ez, cap_br);   \
+            else go2d<VV, false, false>(p, c, nullptr, all, pt, step, st, d, cap_ez, cap_br);      \
+        }                                                                                          \
     } while (0)
     switch (c.V) {
         case 1: GEM_GO(1); break;
@@ -466,6 +490,20 @@ hipError_t launch_2d_fused(const Prob2D &p, const Fused2DCfg &c, const ProbeTile
     }
 #undef GEM_GO
     return hipGetLastError();
+}
+
+// Tiles clear of every CPML slab: rows [x0-1, x1) outside the x slabs and
+// columns [y0-1, y0+64V) outside the y slabs (row x0-1 and column y0-1 are
+// recomputed by the tile).
+bool fused2d_interior(int nx, int ny, const Fused2DCfg &c, const int *xlohi, const int *ylohi, int t) {
+    const int nsy = (ny + 64 * c.V - 1) / (64 * c.V);
+    const int cx = t / nsy, sy = t - cx * nsy;
+    const int x0 = cx * c.TX, x1 = std::min(x0 + c.TX, nx);
+    const int y0 = sy * 64 * c.V, y1 = std::min(y0 + 64 * c.V, ny);
+    auto clear = [](int n, int lo, int hi, int a, int b) {  // [a, b) outside both slabs
+        return std::max(a, 0) >= lo && b <= n - hi;
+    };
+    return clear(nx, xlohi[0], xlohi[1], x0 - 1, x1) && clear(ny, ylohi[0], ylohi[1], y0 - 1, y1);
 }
 
 // ---------------------------------------------------------------------------

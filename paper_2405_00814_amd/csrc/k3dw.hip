@@ -14,7 +14,8 @@
 // The H layer needs E at i+1 (loaded once and carried to the next plane as
 // the own E), at j+1 and at k+1 (the next element, a shuffle or, for the
 // segment's last lane, a load).  State is double buffered (read s0, write
-// s1), so every recomputed value equals its owner's value bit for bit.
+// s1), so every recomputed value equals its owner's value (up to the
+// rounding of the same arithmetic written in another place).
 //
 // Tiles: (x range, band of WPB y rows, z segment of 64*V cells).  Rows
 // of one workgroup exchange the values their neighbours need through LDS

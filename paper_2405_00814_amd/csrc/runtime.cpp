@@ -271,6 +271,18 @@ void Sim::build_probe_tiles() {
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
         pt_cfg[3] == c3 && pt_start)
         return;
+    if (ndim == 2) {
+        const Fused2DCfg c{a, b};
+        const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
+        const int nt = fused2d_ntiles(nx, ny, c);
+        std::vector<int> ids, outer;
+        for (int t = 0; t < nt; ++t) (fused2d_interior(nx, ny, c, xl, yl, t) ? ids : outer).push_back(t);
+        tl2_inner = (int)ids.size();
+        tl2_outer = (int)outer.size();
+        ids.insert(ids.end(), outer.begin(), outer.end());
+        al.put(tl2_dev);
+        tl2_dev = dev_upload(al, ids.data(), std::max<size_t>(ids.size(), 1), st);
+    }
     if (ndim == 3) {
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi}, zl[2] = {ax[2].lo, ax[2].hi};
         wave3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, xl, yl, zl, plan3);
@@ -333,13 +345,20 @@ void Sim::launch_step(int64_t step) {
     ProbeTiles pt{pt_start, pt_cell, pt_slot};
     if (ndim == 2) {
         Fused2DCfg c{kcfg.tile[0], kcfg.tile[1]};
-        hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr),
+        const TileSplit2D sp{tl2_dev, tl2_inner, tl2_dev + tl2_inner, tl2_outer};
+        hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr,
+                                  split2d() ? &sp : nullptr),
                   "2d fused step");
     } else {
         hip_check(launch_3d_wave(prob3d(cur, 1 - cur), plan3, tl_dev, pt, step, st, lev), "3d fused step");
     }
     cur = 1 - cur;
-    last_launches += ndim == 2 ? 1 : (int64_t)plan3.l.size();
+    if (ndim == 3) {
+        last_launches += (int64_t)plan3.l.size();
+    } else {
+        const bool pml = ax[0].lo + ax[0].hi + ax[1].lo + ax[1].hi > 0;
+        last_launches += (pml && split2d()) ? (tl2_inner > 0) + (tl2_outer > 0) : 1;
+    }
 }
 
 void Sim::zero_state() {
@@ -390,7 +409,7 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
     if (s.ndim == 2) {
-        Fused2DCfg c{s.ny % 2 == 0 ? 2 : 1, 8};
+        Fused2DCfg c{s.ny % 2 == 0 ? 2 : 1, 4};
         if (fused2d_supported(s.nx, s.ny, c)) {
             k.variant = 2;
             k.tile[0] = c.V;

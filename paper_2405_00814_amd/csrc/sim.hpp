@@ -94,6 +94,13 @@ struct Sim {
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
     int pt_ntiles = -1;
     int pt_cfg[4] = {-1, -1, -1, -1};
+    // 2D fused: tile ids clear of the CPML slabs, then the others.  Large
+    // grids launch the two lists separately (the interior without the CPML
+    // code); small grids take one launch, where a second launch's fixed cost
+    // outweighs the gain.
+    int *tl2_dev = nullptr;
+    int tl2_inner = 0, tl2_outer = 0;
+    bool split2d() const { return (int64_t)nx * ny >= (int64_t)4 << 20; }
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
     Tile3 *tl_dev = nullptr;

@@ -1,6 +1,6 @@
 """GPU parity of the explicit-graph (CSR) form, the batched form and the
 adjoint, against the FP64 oracle (and, where the arithmetic is the same,
-against the plain stepper bit for bit)."""
+against the plain stepper up to FP32 rounding order)."""
 import numpy as np
 import pytest
 
@@ -77,13 +77,14 @@ def test_batch_matches_single_and_oracle():
         got = {k: b.get_field(q, k) for k in ("ez", "hx", "hy")}
         rec = b.probe(q)
         single, srec, _ = run_gpu(pb, n)
+        # the batch runs its interior tiles without the CPML code while a small
+        # single grid runs every tile with it: equal up to FP32 rounding order
         for k in got:
-            assert np.array_equal(got[k], single[k]), (q, k)
-        assert np.array_equal(rec, srec)
-        if q < 3:
-            ref, rrec = run_oracle(pb, n)
-            assert_parity(got, ref, TOL, "batch[%d]" % q)
-            assert rel_l2(rec, rrec) <= TOL
+            assert rel_l2(got[k], single[k]) <= 1e-5, (q, k, rel_l2(got[k], single[k]))
+        assert rel_l2(rec, srec) <= 1e-5
+        ref, rrec = run_oracle(pb, n)
+        assert_parity(got, ref, TOL, "batch[%d]" % q)
+        assert rel_l2(rec, rrec) <= TOL
     assert b.cells() == sum(p.cells for p in probs)
     ms, launches = b.last_step_time()
     assert ms > 0 and launches > 0
