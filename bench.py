@@ -238,10 +238,11 @@ def cpu_baseline(target_s=15.0):
     o = O.Oracle3D(sub, pb.dx, pb.dt, pb.eps_r[:48], None, None, (12, 0, 12, 12, 12, 12), pb.cpml)
     o.set_source((20, 256, 256), pb.source.kind, pb.source.params)
     o.set_probes([(30, 100, 100)])
+    o.run(2)  # warm-up (thread start, first touch)
     t0 = time.perf_counter()
-    o.run(2)
+    o.run(4)
     t1 = time.perf_counter() - t0
-    n = max(2, int(target_s / max(t1 / 2, 1e-3)))
+    n = max(2, int(target_s / max(t1 / 4, 1e-3)))
     t0 = time.perf_counter()
     o.run(n)
     t = time.perf_counter() - t0
