@@ -174,13 +174,21 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
 /* Kernel selection for the implicit-graph stepper.
  *  variant: 0 = auto (autotuned or default), 1 = two-pass reference
  *           (separate H and E kernels, in place), 2 = fused single pass
- *           (one kernel per step, double-buffered state).
+ *           (one kernel per step, double-buffered state), 3 = (3D only)
+ *           two leapfrog steps per pass over memory: tiles whose
+ *           dependency cone stays clear of the x and y CPML slabs advance
+ *           two steps in one kernel (state n+1 never leaves the chip); the
+ *           rest takes two fused single steps through a third state set
+ *           (allocated on first use, 24 B per cell plus the CPML auxiliary
+ *           values).  An odd remainder of fdtd_step's n is one single step.
  *  tile[0..3]: variant-specific tile sizes (0 = default); tb reserved (1).
  *    2D fused: tile[0] = V (1, 2 or 4 consecutive y cells per lane; ny % V
  *    must be 0), tile[1] = TX (x rows marched by one wavefront).
  *    3D fused: tile[0] = V (1, 2 or 4 consecutive z cells per thread;
  *    nz % V must be 0); tile[2] = x planes marched by one workgroup (0 =
  *    16, at most 4096); tile[1] and tile[3] must be 0.
+ *    3D two-step: as 3D fused with V = 4; also nz <= 512 and at most 64
+ *    z-CPML cells in all.
  * FDTD_EINVAL for unknown or unsupported combinations. */
 typedef struct {
     int32_t variant;
@@ -205,19 +213,24 @@ int fdtd_last_step_time(fdtd_sim *sim, float *ms, int64_t *launches);
 /* Per-launch timing of the step.  Advances the state by `steps` steps like
  * fdtd_step, with a HIP event pair around every kernel launch of the 3D
  * fused step (the interior launch and the one of the tiles that touch an x
- * or y CPML slab), or around the whole step for the other steppers, and
+ * or y CPML slab; with the two-step pass: the first single-step launches,
+ * the two-step launch, the second single-step launches, each step pair
+ * timed as one unit), or around the whole step for the other steppers, and
  * writes one entry per launch (at most `max`) with the mean duration over
- * the steps; *n receives the number of entries.  cells: cells the entry
+ * the units (steps, or step pairs; an odd last step of a two-step run is
+ * not timed); *n receives the number of entries.  cells: cells the entry
  * updates; psi: CPML auxiliary values it updates; cpml: 0 no CPML code, 1
  * z-slab code only, 2 x/y (and z) slab code, -1 a whole step; launches:
- * kernel launches in the entry.  The events add a small gap between
- * launches. */
+ * kernel launches in the entry; steps: leapfrog steps the entry advances
+ * its cells by (1, or 2 for the two-step launch).  The events add a small
+ * gap between launches. */
 typedef struct {
     float ms;
     int64_t cells;
     int64_t psi;
     int32_t cpml;
     int32_t launches;
+    int32_t steps;
 } fdtd_launch_stat;
 int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32_t max,
                       int32_t *n);

@@ -47,7 +47,7 @@ class fdtd_kernel_config(C.Structure):
 
 class fdtd_launch_stat(C.Structure):
     _fields_ = [("ms", C.c_float), ("cells", C.c_int64), ("psi", C.c_int64), ("cpml", C.c_int32),
-                ("launches", C.c_int32)]
+                ("launches", C.c_int32), ("steps", C.c_int32)]
 
 
 class FdtdError(RuntimeError):

@@ -124,11 +124,12 @@ hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
 // Fused 3D.  V: z cells per thread; TX: x planes marched by one interior
 // workgroup (0 = 16; workgroups with x/y CPML code march max(1, TX/4)).
 struct Fused3DCfg { int V; int TX; };
-// One workgroup's tile: planes [i0, i1), rows from j0 (one per wavefront),
-// z cells [ks, k1) of the segment whose lanes start at the aligned base k0.
+// One workgroup's tile: planes [i0, i1), rows j0 .. j0+nrows-1 (one per
+// wavefront, nrows <= wavefronts per workgroup, j0 + nrows <= ny), z cells
+// [ks, k1) of the segment whose lanes start at the aligned base k0.
 // i0 == i1 marks padding.
 struct Tile3 {
-    int i0, i1, j0, k0, k1, ks, pad[2];
+    int i0, i1, j0, k0, k1, ks, nrows, rec;  // rec: 1 = record probes in this tile
 };
 // One launch of the fused 3D kernel over a list of tiles.
 struct Wave3DLaunch {
@@ -149,6 +150,27 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
 hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *tiles,
                           const ProbeTiles &pt, int64_t step, hipStream_t st,
                           hipEvent_t *ev = nullptr);
+// Two steps per pass (temporal blocking).  A tile: planes [i0, i1), rows
+// j0 .. j0+nrows-1, full z; i0 == i1 marks padding.
+struct TileTB {
+    int i0, i1, j0, nrows;
+};
+bool two3d_supported(int nx, int ny, int nz, int sz);
+int two3d_rows(int nz, bool pz, int mat);  // mat: 0 Cb, 1 Ca+Cb, 2 Ca+Cb+Db maps
+// records probes at steps `step` and `step`+1 of cells it owns
+hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                         hipStream_t st);
+// Plan of a two-step pass: the interior tiles run the two-step kernel; the
+// rest (S, tiles whose cone touches an x or y slab) runs two single steps:
+// pass1 over S and its one-cell rim M (state n -> a third state set, probes
+// recorded in S only), pass2 over S (third set -> state n+2).
+struct TwoPlan {
+    std::vector<TileTB> tb;  // padded to a multiple of 8
+    int64_t tb_cells = 0, tb_psi = 0;
+    Wave3DPlan pass1, pass2;
+};
+void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int *xlohi, const int *ylohi,
+                const int *zlohi, TwoPlan &pl);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

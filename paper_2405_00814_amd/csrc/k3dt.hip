@@ -1,0 +1,682 @@
+// Two leapfrog steps per pass over HBM (temporal blocking) for the interior
+// of the 3D grid: state n is read once, state n+2 written once, state n+1
+// lives in registers and LDS only.
+//
+// A workgroup holds R+2 y rows (its R rows plus one halo row above and one
+// below) of full z length (RZ wavefronts of 64 lanes x V cells per row) and
+// marches through the x planes of its tile.  At plane i it computes step 1
+// (H^{n+1/2}, E^{n+1}) of all its rows at plane i, then step 2 (H^{n+3/2},
+// E^{n+2}) of its own rows at plane i-1, which needs step 1 at planes i-1
+// and i only:
+//   x: step-1 values of plane i-1 are carried in registers; the tile starts
+//      one plane early and recomputes H^{n+1/2} (y, z) of the plane before;
+//   y: rows exchange through LDS; the halo rows give step 1 of the rows
+//      next to the band (the upper one recomputes H^{n+1/2} of the row above
+//      it from state n, the lower one loads E^n of the row below);
+//   z: the lane shuffle and, between wavefronts of a row, LDS seam values;
+//      the row is whole, so no z halo.
+// Step-1 values of the halo rows and planes are recomputed by every tile
+// that needs them, identically, so tiles stay independent (no grid barrier).
+// z-slab CPML: correction of the slab lanes as in the single-step kernel;
+// their step-1 psi values wait in LDS (indexed by slab cell) until step 2.
+// Tiles whose dependency cone (planes i0-2 .. i1, rows j0-2 .. j0+R) touches
+// an x or y CPML slab are advanced by two single steps instead.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "devutil.hpp"
+#include "k3dcell.hpp"
+
+namespace gem {
+
+constexpr int kTwoZMax = 64;  // largest z-slab thickness (both ends) of the two-step kernel
+
+template <int V, int RZ, int R, bool PZ, int MAT>
+__global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const TileTB *tiles, ProbeTiles pt,
+                                                           int64_t step) {
+    constexpr int NR = R + 2;            // rows held: halo, R own, halo
+    constexpr int NT = 64 * RZ * NR;     // threads
+    constexpr int SEG = 64 * V;          // z cells per wavefront
+    constexpr int ROW = RZ * SEG;        // LDS floats per row
+    const TileTB T = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    if (T.i0 >= T.i1) return;  // padding
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int seg = w % RZ, rr = w / RZ;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int j = T.j0 - 1 + rr;
+    const bool top = rr == 0, bot = rr == T.nrows + 1;
+    const bool own = rr >= 1 && rr <= T.nrows;
+    const bool rok = rr <= T.nrows + 1 && j >= 0 && j < ny;
+    const int kb = seg * SEG + lane * V;
+    const bool ok = rok && kb < nz;  // nz % V == 0
+    const int segend = min((seg + 1) * SEG, nz);
+    const bool last = kb + V == segend, seamnext = segend < nz;
+    const bool yj = j + 1 < ny, jm = j >= 1;
+    const unsigned sxs = (unsigned)ny * nz, sys = nz;
+    const int jr = rok ? j : 0;
+    const int sz = p.z.lo + p.z.hi;
+    const float *ex0 = p.s0.f[FDTD_EX], *ey0 = p.s0.f[FDTD_EY], *ez0 = p.s0.f[FDTD_EZ];
+    const float *hx0 = p.s0.f[FDTD_HX], *hy0 = p.s0.f[FDTD_HY], *hz0 = p.s0.f[FDTD_HZ];
+    float *const *P0 = p.s0.psi;
+    float *const *P1 = p.s1.psi;
+    const int tq = (int)threadIdx.x * V;
+    // the tile's x and y profiles are the interior ones (no slab in the cone)
+    const float ikx = p.x.kH[p.x.lo], iky = p.y.kH[p.y.lo], jkx = p.x.kE[p.x.lo], jky = p.y.kE[p.y.lo];
+    const float idzH = p.z.kH[p.z.lo], idzE = p.z.kE[p.z.lo];
+
+    __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
+    __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
+    __shared__ float Zs[PZ ? 2 : 1][PZ ? NR : 1][PZ ? kTwoZMax : 1][4];  // step-1 z psi
+    // z-slab profile per slab cell (kH - idzH, bH, cH, kE - idzE, bE, cE) and
+    // the state-n z psi (Hx-z, Hy-z, Ex-z, Ey-z) of the current plane for
+    // rows j0-2 .. j0+R, row stride sz: loaded with the plane's fields and
+    // read from LDS, so no slab lane waits on a dependent global load
+    constexpr int NZR = NR + 1;
+    __shared__ float ZT[PZ ? 6 : 1][PZ ? kTwoZMax : 1];
+    __shared__ float ZP[PZ ? 4 : 1][PZ ? NZR * kTwoZMax : 1];
+
+    int zsv[V];
+    bool zany = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        zsv[v] = (PZ && ok) ? slab_index(p.z, kb + v) : -1;
+        zany = zany || zsv[v] >= 0;
+    }
+
+    auto zero = [](float (&a)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) a[v] = 0.f;
+    };
+    auto ld = [&](float (&a)[V], const float *base, unsigned off, bool cond) {
+        if (cond) ldv<V>(a, base + off);
+        else zero(a);
+    };
+    auto prv = [&](const float (&x)[V], int q, float seam) {
+        if (q > 0) return x[q - 1];
+        const float s = __shfl_up(x[V - 1], 1);
+        return lane == 0 ? seam : s;
+    };
+    // H from E: own, +x, +y, +z seam; the z differences are kept for the
+    // slab correction
+    auto hstep = [&](float (&hx)[V], float (&hy)[V], float (&hz)[V], const float (&db)[V], const float (&ex)[V],
+                     const float (&ey)[V], const float (&ez)[V], const float (&eyx)[V], const float (&ezx)[V],
+                     const float (&exy)[V], const float (&ezy)[V], float exs, float eys, float (&dyz)[V],
+                     float (&dxz)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const float dEzy = ezy[v] - ez[v];
+            const float dEyz = znext<V>(ey, v, eys, last) - ey[v];
+            const float dExz = znext<V>(ex, v, exs, last) - ex[v];
+            const float dEzx = ezx[v] - ez[v], dEyx = eyx[v] - ey[v], dExy = exy[v] - ex[v];
+            dyz[v] = dEyz;
+            dxz[v] = dExz;
+            hx[v] = hx[v] - db[v] * ((iky * dEzy) - (idzH * dEyz));
+            hy[v] = hy[v] - db[v] * ((idzH * dExz) - (ikx * dEzx));
+            hz[v] = hz[v] - db[v] * ((ikx * dEyx) - (iky * dExy));
+        }
+    };
+    // z-slab correction of H (psi in o1 = Hx-z, o2 = Hy-z: old in, new out)
+    auto hfix = [&](float (&hx)[V], float (&hy)[V], const float (&db)[V], const float (&dyz)[V],
+                    const float (&dxz)[V], float (&o1)[V], float (&o2)[V], bool fx, bool fy) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (zsv[v] >= 0) {
+                const int s = zsv[v];
+                const float kh = ZT[0][PZ ? s : 0], bh = ZT[1][PZ ? s : 0], ch = ZT[2][PZ ? s : 0];
+                o1[v] = bh * o1[v] + ch * dyz[v];
+                o2[v] = bh * o2[v] + ch * dxz[v];
+                if (fx) hx[v] += db[v] * (kh * dyz[v] + o1[v]);
+                if (fy) hy[v] -= db[v] * (kh * dxz[v] + o2[v]);
+            }
+    };
+    // E from H: own, -x, -y, -z seam (ex/ey/ez old in, new out)
+    auto estep = [&](float (&ex)[V], float (&ey)[V], float (&ez)[V], const float (&ca)[V], const float (&cb)[V],
+                     const float (&hx)[V], const float (&hy)[V], const float (&hz)[V], const float (&hyp)[V],
+                     const float (&hzp)[V], const float (&hxj)[V], const float (&hzj)[V], float hxs, float hys,
+                     bool im, float (&dyz)[V], float (&dxz)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            dyz[v] = hy[v] - prv(hy, v, hys);
+            dxz[v] = hx[v] - prv(hx, v, hxs);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int k = kb + v;
+            const float dHzy = hz[v] - hzj[v], dHzx = hz[v] - hzp[v];
+            const float dHyx = hy[v] - hyp[v], dHxy = hx[v] - hxj[v];
+            if (jm && k >= 1) ex[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * ((jky * dHzy) - (idzE * dyz[v]));
+            if (im && k >= 1) ey[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * ((idzE * dxz[v]) - (jkx * dHzx));
+            if (im && jm) ez[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * ((jkx * dHyx) - (jky * dHxy));
+        }
+    };
+    // z-slab correction of E (o3 = Ex-z, o4 = Ey-z); cells not updated keep psi
+    auto efix = [&](float (&ex)[V], float (&ey)[V], const float (&cb)[V], const float (&dyz)[V],
+                    const float (&dxz)[V], float (&o3)[V], float (&o4)[V], bool im) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (zsv[v] >= 0) {
+                const int k = kb + v;
+                const int s = zsv[v];
+                const float ke = ZT[3][PZ ? s : 0], be = ZT[4][PZ ? s : 0], ce = ZT[5][PZ ? s : 0];
+                if (jm && k >= 1) {
+                    o3[v] = be * o3[v] + ce * dyz[v];
+                    ex[v] -= cb[v] * (ke * dyz[v] + o3[v]);
+                }
+                if (im && k >= 1) {
+                    o4[v] = be * o4[v] + ce * dxz[v];
+                    ey[v] += cb[v] * (ke * dxz[v] + o4[v]);
+                }
+            }
+    };
+    // psi of the thread's slab cells from the LDS copy (component cc, row
+    // index r = j - (j0 - 2))
+    auto zlds = [&](float (&o)[V], int cc, int r) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = ZP[PZ ? cc : 0][PZ ? r * sz + (zsv[v] >= 0 ? zsv[v] : 0) : 0];
+    };
+    auto zload = [&](float (&o)[V], const float *a, unsigned row) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = a[row + (zsv[v] >= 0 ? zsv[v] : 0)];
+    };
+    // The element is picked by selects, never by an index computed at run
+    // time: a computed index into a register array moves the array to
+    // scratch memory for the whole kernel.
+    auto add_source = [&](unsigned c, int64_t n, float (&ex)[V], float (&ey)[V], float (&ez)[V]) {
+        const int64_t d = p.src_idx - (int64_t)c;
+        if (!ok || d < 0 || d >= V) return;
+        const float sval = n < p.src_len ? p.src_vals[n] : 0.f;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool at = d == v;
+            ex[v] = (at && p.src_comp == FDTD_EX) ? ex[v] + sval : ex[v];
+            ey[v] = (at && p.src_comp == FDTD_EY) ? ey[v] + sval : ey[v];
+            ez[v] = (at && p.src_comp == FDTD_EZ) ? ez[v] + sval : ez[v];
+        }
+    };
+    auto record = [&](int i, unsigned c, int64_t n, const float (&ex)[V], const float (&ey)[V], const float (&ez)[V],
+                      const float (&hx)[V], const float (&hy)[V], const float (&hz)[V]) {
+        if (pt.start == nullptr || !ok) return;
+        const int g = i * ((ny + 3) / 4) + jr / 4;
+        const int pend = pt.start[g + 1];
+        for (int q = pt.start[g]; q < pend; ++q) {
+            const int64_t cell = pt.cell[q];
+            if (cell < (int64_t)c || cell >= (int64_t)c + V) continue;
+            const int v = (int)(cell - c);
+            const int pc = p.probe_comp;
+            float val = 0.f;
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const float x = pc == FDTD_EX ? ex[u] : pc == FDTD_EY ? ey[u] : pc == FDTD_EZ ? ez[u]
+                              : pc == FDTD_HX ? hx[u] : pc == FDTD_HY ? hy[u] : hz[u];
+                val = u == v ? x : val;
+            }
+            p.rec[(int64_t)pt.slot[q] * p.rec_stride + (n - p.rec_base)] = val;
+        }
+    };
+    auto coef = [&](float (&cb)[V], float (&ca)[V], float (&db)[V], unsigned c, bool cond) {
+        ld(cb, p.cb, c, cond);
+#pragma unroll
+        for (int v = 0; v < V; ++v) { ca[v] = 1.f; db[v] = p.db0; }
+        if (MAT >= 1 && cond) ldv<V>(ca, p.ca + c);
+        if (MAT == 2 && cond) ldv<V>(db, p.db + c);
+    };
+
+    const int ia = T.i0 > 0 ? T.i0 - 1 : 0;
+    if (PZ) {
+        for (int k = (int)threadIdx.x; k < nz; k += NT) {
+            const int s = slab_index(p.z, k);
+            if (s >= 0) {
+                ZT[0][PZ ? s : 0] = p.z.kH[k] - idzH;
+                ZT[1][PZ ? s : 0] = p.z.bH[k];
+                ZT[2][PZ ? s : 0] = p.z.cH[k];
+                ZT[3][PZ ? s : 0] = p.z.kE[k] - idzE;
+                ZT[4][PZ ? s : 0] = p.z.bE[k];
+                ZT[5][PZ ? s : 0] = p.z.cE[k];
+            }
+        }
+        __syncthreads();
+    }
+    // carried between planes
+    float eyc[V], ezc[V];             // E^n at plane i
+    float hx1p[V], hy1p[V], hz1p[V];  // H^{n+1/2} at plane i-1
+    float ex1p[V], ey1p[V], ez1p[V];  // E^{n+1} at plane i-1
+    float hy2p[V], hz2p[V];           // H^{n+3/2} at plane i-2
+    float cbp[V], cap[V], dbp[V];     // coefficients at plane i-1
+    zero(hx1p); zero(hy1p); zero(hz1p); zero(ex1p); zero(ey1p); zero(ez1p); zero(hy2p); zero(hz2p);
+#pragma unroll
+    for (int v = 0; v < V; ++v) { cbp[v] = 0.f; cap[v] = 1.f; dbp[v] = p.db0; }
+    {
+        const unsigned c = ((unsigned)ia * ny + jr) * nz + kb;
+        ld(eyc, ey0, c, ok);
+        ld(ezc, ez0, c, ok);
+        if (ia >= 1) {  // H^{n+1/2} (y, z) at plane ia-1 from state n
+            const unsigned q0 = c - sxs;
+            float aex[V], aey[V], aez[V], aexy[V], ahx[V], ahy[V], ahz[V], ab[V], aa[V], adb[V], dyz[V], dxz[V];
+            ld(aex, ex0, q0, ok);
+            ld(aey, ey0, q0, ok);
+            ld(aez, ez0, q0, ok);
+            ld(aexy, ex0, q0 + sys, ok && yj);
+            zero(ahx);
+            ld(ahy, hy0, q0, ok);
+            ld(ahz, hz0, q0, ok);
+            coef(ab, aa, adb, q0, ok);
+            const unsigned rq = ((unsigned)(ia - 1) * ny + jr) * nz;
+            const bool sn = ok && last && seamnext;
+            const float exs = sn ? ex0[rq + segend] : 0.f, eys = sn ? ey0[rq + segend] : 0.f;
+            float zz[V];
+            zero(zz);
+            hstep(ahx, ahy, ahz, adb, aex, aey, aez, eyc, ezc, aexy, zz, exs, eys, dyz, dxz);
+            if (PZ && zany) {
+                float o1[V], o2[V];
+                zload(o1, P0[PSI_HXZ], zs3(ia - 1, j, 0, ny, sz));
+                zload(o2, P0[PSI_HYZ], zs3(ia - 1, j, 0, ny, sz));
+                hfix(ahx, ahy, adb, dyz, dxz, o1, o2, false, true);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) { hy1p[v] = ahy[v]; hz1p[v] = ahz[v]; }
+        }
+    }
+    float ex1y[V], ez1y[V];  // E^{n+1} at (i-1, j+1)
+    float e1s[2] = {0.f, 0.f};
+    zero(ex1y);
+    zero(ez1y);
+
+    const int iend = min(T.i1, nx);
+    for (int i = ia; i <= iend; ++i) {
+        const bool pa = i < nx;
+        const bool xi = i + 1 < nx, im = i >= 1;
+        const unsigned r0 = ((unsigned)(pa ? i : 0) * ny + jr) * nz, c = r0 + kb;
+        const bool la = pa && ok;
+        // ---- state-n z psi of plane i (rows j0-2 .. j0+R): issued now,
+        //      written to LDS before the first barrier ----
+        constexpr int NZL = PZ ? (NZR * kTwoZMax + NT - 1) / NT : 1;
+        float zpre[4][NZL];
+        const int zrows = NZR * sz;
+        const int64_t zg0 = ((int64_t)(pa ? i : 0) * ny + (T.j0 - 2)) * sz;
+        if (PZ) {
+#pragma unroll
+            for (int u = 0; u < NZL; ++u) {
+                const int q = (int)threadIdx.x + u * NT;
+                const int64_t g = (int64_t)(T.j0 - 2) * sz + q;  // offset inside plane i
+                const bool in = pa && q < zrows && g >= 0 && g < (int64_t)ny * sz;
+                zpre[0][u] = in ? P0[PSI_HXZ][zg0 + q] : 0.f;
+                zpre[1][u] = in ? P0[PSI_HYZ][zg0 + q] : 0.f;
+                zpre[2][u] = in ? P0[PSI_EXZ][zg0 + q] : 0.f;
+                zpre[3][u] = in ? P0[PSI_EYZ][zg0 + q] : 0.f;
+            }
+        }
+        // ---- E^{n+1} at plane i-1 of the row below and the z seam ----
+        if (i > ia && rr <= T.nrows) {
+            ldv<V>(ex1y, &L1x[tq + ROW]);
+            ldv<V>(ez1y, &L1z[tq + ROW]);
+            if (seg + 1 < RZ) {
+                e1s[0] = Se1[rr][seg + 1][0];
+                e1s[1] = Se1[rr][seg + 1][1];
+            }
+        }
+        // ---- step 1 at plane i ----
+        float ex[V], ey[V], ez[V], eyx[V], ezx[V], exy[V], ezy[V], hx[V], hy[V], hz[V], cb[V], ca[V], db[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) { ey[v] = eyc[v]; ez[v] = ezc[v]; }
+        ld(ex, ex0, c, la);
+        ld(eyx, ey0, c + sxs, la && xi);
+        ld(ezx, ez0, c + sxs, la && xi);
+        ld(exy, ex0, c + sys, la && yj && bot);
+        ld(ezy, ez0, c + sys, la && yj && bot);
+        ld(hx, hx0, c, la);
+        ld(hy, hy0, c, la);
+        ld(hz, hz0, c, la);
+        coef(cb, ca, db, c, la);
+        stv<V>(&LEx[tq], ex);
+        stv<V>(&LEz[tq], ez);
+        if (lane == 0) { Se0[rr][seg][0] = ex[0]; Se0[rr][seg][1] = ey[0]; }
+        if (PZ) {
+#pragma unroll
+            for (int u = 0; u < NZL; ++u) {
+                const int q = (int)threadIdx.x + u * NT;
+                if (q < zrows) {
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) ZP[PZ ? cc : 0][PZ ? q : 0] = zpre[cc][u];
+                }
+            }
+        }
+        __syncthreads();
+        if (!bot && la && yj) {
+            ldv<V>(exy, &LEx[tq + ROW]);
+            ldv<V>(ezy, &LEz[tq + ROW]);
+        }
+        const bool sn = last && seamnext;
+        const float exs0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][0] : 0.f;
+        const float eys0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][1] : 0.f;
+        float dyz[V], dxz[V];
+        hstep(hx, hy, hz, db, ex, ey, ez, eyx, ezx, exy, ezy, exs0, eys0, dyz, dxz);
+        if (PZ && zany && la) {  // z-slab psi of step 1: state n in, n+1 to the stash
+            float o1[V], o2[V];
+            zlds(o1, 0, rr + 1);
+            zlds(o2, 1, rr + 1);
+            hfix(hx, hy, db, dyz, dxz, o1, o2, true, true);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (zsv[v] >= 0) {
+                    float *z = Zs[PZ ? (i & 1) : 0][PZ ? rr : 0][PZ ? zsv[v] : 0];
+                    z[0] = o1[v]; z[1] = o2[v];
+                }
+        }
+        stv<V>(&LHx[tq], hx);
+        stv<V>(&LHz[tq], hz);
+        if (lane == 63) { Sh1[rr][seg][0] = hx[V - 1]; Sh1[rr][seg][1] = hy[V - 1]; }
+        __syncthreads();
+        float hxj[V], hzj[V];
+        zero(hxj);
+        zero(hzj);
+        if (!top) {
+            if (la && jm) {
+                ldv<V>(hxj, &LHx[tq - ROW]);
+                ldv<V>(hzj, &LHz[tq - ROW]);
+            }
+        } else if (pa && rok && jm) {  // H^{n+1/2} (x, z) at (i, j-1) from state n (wave-uniform)
+            const unsigned q0 = c - sys;
+            float aex[V], aey[V], aez[V], aeyx[V], ahx[V], ahy[V], ahz[V], ab[V], aa[V], adb[V], zz[V], d1[V], d2[V];
+            ld(aex, ex0, q0, ok);
+            ld(aey, ey0, q0, ok);
+            ld(aez, ez0, q0, ok);
+            ld(aeyx, ey0, q0 + sxs, ok && xi);
+            ld(ahx, hx0, q0, ok);
+            zero(ahy);
+            ld(ahz, hz0, q0, ok);
+            coef(ab, aa, adb, q0, ok);
+            const bool snj = ok && last && seamnext;
+            const float eys = snj ? ey0[r0 - sys + segend] : 0.f, exs = snj ? ex0[r0 - sys + segend] : 0.f;
+            zero(zz);
+            hstep(ahx, ahy, ahz, adb, aex, aey, aez, aeyx, zz, ex, ez, exs, eys, d1, d2);
+            if (PZ && zany) {
+                float q1[V], q2[V];
+                zlds(q1, 0, rr);
+                zero(q2);
+                hfix(ahx, ahy, adb, d1, d2, q1, q2, true, false);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) { hxj[v] = ahx[v]; hzj[v] = ahz[v]; }
+        }
+        const float hxs1 = (lane == 0 && seg > 0) ? Sh1[rr][seg > 0 ? seg - 1 : 0][0] : 0.f;
+        const float hys1 = (lane == 0 && seg > 0) ? Sh1[rr][seg > 0 ? seg - 1 : 0][1] : 0.f;
+        float ex1[V], ey1[V], ez1[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) { ex1[v] = ex[v]; ey1[v] = ey[v]; ez1[v] = ez[v]; }
+        estep(ex1, ey1, ez1, ca, cb, hx, hy, hz, hy1p, hz1p, hxj, hzj, hxs1, hys1, im, dyz, dxz);
+        if (PZ && zany && la) {
+            float o3[V], o4[V];
+            zlds(o3, 2, rr + 1);
+            zlds(o4, 3, rr + 1);
+            efix(ex1, ey1, cb, dyz, dxz, o3, o4, im);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (zsv[v] >= 0) {
+                    float *z = Zs[PZ ? (i & 1) : 0][PZ ? rr : 0][PZ ? zsv[v] : 0];
+                    z[2] = o3[v]; z[3] = o4[v];
+                }
+        }
+        add_source(c, step, ex1, ey1, ez1);
+        if (!la) { zero(ex1); zero(ey1); zero(ez1); zero(hx); zero(hy); zero(hz); }
+        if (own && la && i >= T.i0 && i < T.i1) record(i, c, step, ex1, ey1, ez1, hx, hy, hz);
+        stv<V>(&L1x[tq], ex1);
+        stv<V>(&L1z[tq], ez1);
+        if (lane == 0) { Se1[rr][seg][0] = ex1[0]; Se1[rr][seg][1] = ey1[0]; }
+
+        // ---- step 2 at plane ib = i-1 (H on the halo row above too) ----
+        const int ib = i - 1;
+        const bool pb = ib >= ia && rr <= T.nrows && rok;  // wave-uniform
+        const bool wb = own && rok && ib >= T.i0;          // E too, and stored
+        const unsigned cq = ((unsigned)(pb ? ib : 0) * ny + jr) * nz + kb;
+        const unsigned zrb = zs3(pb ? ib : 0, jr, 0, ny, sz);
+        float hx2[V], hy2[V], hz2[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) { hx2[v] = hx1p[v]; hy2[v] = hy1p[v]; hz2[v] = hz1p[v]; }
+        // step-1 z psi of plane ib from the stash (component c)
+        auto zstash = [&](float (&o)[V], int cc) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) o[v] = Zs[PZ ? (ib & 1) : 0][PZ ? rr : 0][PZ ? (zsv[v] >= 0 ? zsv[v] : 0) : 0][cc];
+        };
+        if (pb) {  // wave-uniform
+            const bool sn2 = last && seamnext;
+            const float exs = sn2 ? e1s[0] : 0.f, eys = sn2 ? e1s[1] : 0.f;
+            hstep(hx2, hy2, hz2, dbp, ex1p, ey1p, ez1p, ey1, ez1, ex1y, ez1y, exs, eys, dyz, dxz);
+            if (PZ && zany) {
+                float p1[V], p2[V];
+                zstash(p1, 0);
+                zstash(p2, 1);
+                hfix(hx2, hy2, dbp, dyz, dxz, p1, p2, true, true);
+                if (wb) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        if (zsv[v] >= 0) {
+                            P1[PSI_HXZ][zrb + zsv[v]] = p1[v];
+                            P1[PSI_HYZ][zrb + zsv[v]] = p2[v];
+                        }
+                }
+            }
+        }
+        __syncthreads();  // step-1 LDS reads of this plane are done
+        stv<V>(&LHx[tq], hx2);
+        stv<V>(&LHz[tq], hz2);
+        if (lane == 63) { Sh2[rr][seg][0] = hx2[V - 1]; Sh2[rr][seg][1] = hy2[V - 1]; }
+        __syncthreads();
+        if (wb) {  // wave-uniform
+            float hxj2[V], hzj2[V];
+            zero(hxj2);
+            zero(hzj2);
+            if (jm) {
+                ldv<V>(hxj2, &LHx[tq - ROW]);
+                ldv<V>(hzj2, &LHz[tq - ROW]);
+            }
+            const float hxs2 = (lane == 0 && seg > 0) ? Sh2[rr][seg > 0 ? seg - 1 : 0][0] : 0.f;
+            const float hys2 = (lane == 0 && seg > 0) ? Sh2[rr][seg > 0 ? seg - 1 : 0][1] : 0.f;
+            float e2x[V], e2y[V], e2z[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) { e2x[v] = ex1p[v]; e2y[v] = ey1p[v]; e2z[v] = ez1p[v]; }
+            estep(e2x, e2y, e2z, cap, cbp, hx2, hy2, hz2, hy2p, hz2p, hxj2, hzj2, hxs2, hys2, ib >= 1, dyz, dxz);
+            if (PZ && zany) {  // zany implies ok
+                float p3[V], p4[V];
+                zstash(p3, 2);
+                zstash(p4, 3);
+                efix(e2x, e2y, cbp, dyz, dxz, p3, p4, ib >= 1);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (zsv[v] >= 0) {
+                        P1[PSI_EXZ][zrb + zsv[v]] = p3[v];
+                        P1[PSI_EYZ][zrb + zsv[v]] = p4[v];
+                    }
+            }
+            add_source(cq, step + 1, e2x, e2y, e2z);
+            record(ib, cq, step + 1, e2x, e2y, e2z, hx2, hy2, hz2);
+            if (ok) {
+                stv<V>(p.s1.f[FDTD_EX] + cq, e2x);
+                stv<V>(p.s1.f[FDTD_EY] + cq, e2y);
+                stv<V>(p.s1.f[FDTD_EZ] + cq, e2z);
+                stv<V>(p.s1.f[FDTD_HX] + cq, hx2);
+                stv<V>(p.s1.f[FDTD_HY] + cq, hy2);
+                stv<V>(p.s1.f[FDTD_HZ] + cq, hz2);
+            }
+        }
+        // ---- carry ----
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            eyc[v] = eyx[v];
+            ezc[v] = ezx[v];
+            hx1p[v] = hx[v]; hy1p[v] = hy[v]; hz1p[v] = hz[v];
+            ex1p[v] = ex1[v]; ey1p[v] = ey1[v]; ez1p[v] = ez1[v];
+            hy2p[v] = hy2[v]; hz2p[v] = hz2[v];
+            cbp[v] = cb[v]; cap[v] = ca[v]; dbp[v] = db[v];
+        }
+    }
+}
+
+bool two3d_supported(int nx, int ny, int nz, int sz) {
+    (void)nx; (void)ny;
+    return nz % 4 == 0 && nz <= 2 * 64 * 4 && sz <= kTwoZMax;
+}
+
+// Rows per band of the two-step kernel (its workgroup holds two halo rows
+// more, RZ wavefronts per row).  The instances with z-slab CPML or a Db map
+// need more registers: 12 wavefronts (168 VGPRs) instead of 16 (128).
+constexpr int two_waves(bool pz, int mat) { return (pz || mat == 2) ? 12 : 16; }
+int two3d_rows(int nz, bool pz, int mat) {
+    const int rz = nz <= 64 * 4 ? 1 : 2;
+    return two_waves(pz, mat) / rz - 2;
+}
+
+namespace {
+
+// single-step tiles covering the marked (plane, row) cells of a mask (1 =
+// record probes, 2 = do not), full z: per plane, runs of rows with one mark
+// in pieces of at most 4 rows; consecutive planes with the same pieces merge
+// into x ranges of at most tx planes.
+void mask_tiles(const std::vector<unsigned char> &m, int nx, int ny, int nz, int V, int tx, bool pz,
+                const int *xlohi, const int *ylohi, const int *zlohi, Wave3DPlan &pl) {
+    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
+    struct Piece {
+        int j0, n, rec;
+        bool operator==(const Piece &o) const { return j0 == o.j0 && n == o.n && rec == o.rec; }
+    };
+    auto pieces_of = [&](int i) {
+        std::vector<Piece> ps;
+        int j = 0;
+        while (j < ny) {
+            const unsigned char mk = m[(size_t)i * ny + j];
+            if (!mk) { ++j; continue; }
+            int e = j;
+            while (e < ny && m[(size_t)i * ny + e] == mk) ++e;
+            for (int a = j; a < e; a += 4) ps.push_back(Piece{a, std::min(4, e - a), mk == 1 ? 1 : 0});
+            j = e;
+        }
+        return ps;
+    };
+    Wave3DLaunch l{};
+    l.V = V;
+    l.wpb = 4;
+    l.pxy = true;
+    l.pz = pz;
+    l.off = (int)pl.tiles.size();
+    const int seg = 64 * V;
+    int i = 0;
+    while (i < nx) {
+        const std::vector<Piece> ps = pieces_of(i);
+        int e = i + 1;
+        while (e < nx && e - i < tx && pieces_of(e) == ps) ++e;
+        int64_t xs = 0;
+        for (int a = i; a < e; ++a) xs += inslab(nx, xlohi[0], xlohi[1], a);
+        for (const Piece &pc : ps) {
+            int64_t ysn = 0;
+            for (int b = pc.j0; b < pc.j0 + pc.n; ++b) ysn += inslab(ny, ylohi[0], ylohi[1], b);
+            for (int k0 = 0; k0 < nz; k0 += seg) {
+                const int k1 = std::min(k0 + seg, nz);
+                int64_t zs = 0;
+                for (int k = k0; k < k1; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
+                pl.tiles.push_back(Tile3{i, e, pc.j0, k0, k1, k0, pc.n, pc.rec});
+                const int64_t xn = e - i, zn = k1 - k0;
+                l.cells += xn * pc.n * zn;
+                l.psi += 4 * (xs * pc.n * zn + xn * ysn * zn + xn * pc.n * zs);
+            }
+        }
+        i = e;
+    }
+    if (pl.tiles.size() == (size_t)l.off) return;
+    while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, 0, 0});
+    l.n = (int)pl.tiles.size() - l.off;
+    pl.l.push_back(l);
+}
+
+}  // namespace
+
+void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int *xlohi, const int *ylohi,
+                const int *zlohi, TwoPlan &pl) {
+    pl.tb.clear();
+    pl.tb_cells = pl.tb_psi = 0;
+    pl.pass1.l.clear();
+    pl.pass1.tiles.clear();
+    pl.pass2.l.clear();
+    pl.pass2.tiles.clear();
+    const int TX = c.TX > 0 ? c.TX : 16, R = two3d_rows(nz, zlohi[0] + zlohi[1] > 0, mat);
+    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
+    auto clear = [&](int n, int lo, int hi, int a, int b) {  // no slab cell in [a, b]
+        for (int q = std::max(a, 0); q <= std::min(b, n - 1); ++q)
+            if (inslab(n, lo, hi, q)) return false;
+        return true;
+    };
+    int64_t zs = 0;
+    for (int k = 0; k < nz; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
+    std::vector<unsigned char> inner((size_t)nx * ny, 0);
+    // two-step tiles, x chunk by x chunk, bands inside, over the planes and
+    // rows whose cone is clear: [lo + 2, n - hi - 1) of an axis with slabs
+    auto range = [](int n, int lo, int hi, int &a, int &b) {
+        a = lo > 0 ? lo + 2 : 0;
+        b = hi > 0 ? n - hi - 1 : n;
+    };
+    int xa, xb, ya, yb;
+    range(nx, xlohi[0], xlohi[1], xa, xb);
+    range(ny, ylohi[0], ylohi[1], ya, yb);
+    for (int i0 = xa; i0 < xb; i0 += TX) {
+        const int i1 = std::min(i0 + TX, xb);
+        if (!clear(nx, xlohi[0], xlohi[1], i0 - 2, i1)) continue;
+        for (int j0 = ya; j0 < yb; j0 += R) {
+            const int nr = std::min(R, yb - j0);
+            if (!clear(ny, ylohi[0], ylohi[1], j0 - 2, j0 + nr)) continue;
+            pl.tb.push_back(TileTB{i0, i1, j0, nr});
+            pl.tb_cells += (int64_t)(i1 - i0) * nr * nz;
+            pl.tb_psi += 4 * (int64_t)(i1 - i0) * nr * zs;
+            for (int i = i0; i < i1; ++i)
+                for (int j = j0; j < j0 + nr; ++j) inner[(size_t)i * ny + j] = 1;
+        }
+    }
+    while (pl.tb.size() % 8) pl.tb.push_back(TileTB{0, 0, 0, 0});
+    // S: everything else (marked 1); M: its one-cell rim in x and y (marked 2)
+    std::vector<unsigned char> s1((size_t)nx * ny, 0), s2((size_t)nx * ny, 0);
+    for (size_t q = 0; q < s1.size(); ++q) s1[q] = s2[q] = inner[q] ? 0 : 1;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            if (!inner[(size_t)i * ny + j]) continue;
+            bool near = false;
+            for (int a = i - 1; a <= i + 1; ++a)
+                for (int b = j - 1; b <= j + 1; ++b)
+                    if (a >= 0 && a < nx && b >= 0 && b < ny && !inner[(size_t)a * ny + b]) near = true;
+            if (near) s1[(size_t)i * ny + j] = 2;
+        }
+    const int txs = std::max(1, TX / 4);
+    const bool pz = zlohi[0] + zlohi[1] > 0;
+    mask_tiles(s1, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass1);
+    mask_tiles(s2, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass2);
+}
+
+template <int RZ, bool PZ, int MAT>
+static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step, hipStream_t st) {
+    constexpr int W = two_waves(PZ, MAT), R = W / RZ - 2;
+    hipLaunchKernelGGL((k3d_two<4, RZ, R, PZ, MAT>), dim3((unsigned)n), dim3(64 * W), 0, st, p, tiles, pt, step);
+}
+
+template <int RZ, bool PZ>
+static void go_two_m(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                     hipStream_t st) {
+    const int mat = p.db ? 2 : (p.ca ? 1 : 0);
+    if (mat == 0) go_two<RZ, PZ, 0>(p, tiles, n, pt, step, st);
+    else if (mat == 1) go_two<RZ, PZ, 1>(p, tiles, n, pt, step, st);
+    else go_two<RZ, PZ, 2>(p, tiles, n, pt, step, st);
+}
+
+hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!two3d_supported(p.nx, p.ny, p.nz, p.z.lo + p.z.hi)) return hipErrorInvalidValue;
+    const bool pz = p.z.lo + p.z.hi > 0;
+    if (p.nz <= 64 * 4) {
+        if (pz) go_two_m<1, true>(p, tiles, n, pt, step, st);
+        else go_two_m<1, false>(p, tiles, n, pt, step, st);
+    } else {
+        if (pz) go_two_m<2, true>(p, tiles, n, pt, step, st);
+        else go_two_m<2, false>(p, tiles, n, pt, step, st);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gem

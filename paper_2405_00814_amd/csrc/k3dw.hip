@@ -27,47 +27,9 @@
 // slab cells add the CPML terms in a correction step.
 #include "common.hpp"
 #include "devutil.hpp"
+#include "k3dcell.hpp"
 
 namespace gem {
-
-__device__ __forceinline__ unsigned xs3(int ii, int j, int k, int ny, int nz) {
-    return ((unsigned)ii * ny + j) * nz + k;
-}
-__device__ __forceinline__ unsigned ys3(int i, int jj, int k, int sy, int nz) {
-    return ((unsigned)i * sy + jj) * nz + k;
-}
-__device__ __forceinline__ unsigned zs3(int i, int j, int kk, int ny, int sz) {
-    return ((unsigned)i * ny + j) * sz + kk;
-}
-
-// Profile of one axis at one index (b, c of the CPML recursion; 1/(kappa d)).
-// For x and y the index is uniform over a wavefront, so these are scalar loads.
-struct AxP {
-    float kH, kE, bH, cH, bE, cE;
-    int s;  // slab index or -1
-};
-template <bool PML>
-__device__ __forceinline__ AxP axp(const AxisDev &a, int i) {
-    AxP r;
-    r.kH = a.kH[i];
-    r.kE = a.kE[i];
-    r.s = PML ? slab_index(a, i) : -1;
-    r.bH = r.cH = r.bE = r.cE = 0.f;
-    if (PML && r.s >= 0) {
-        r.bH = a.bH[i]; r.cH = a.cH[i];
-        r.bE = a.bE[i]; r.cE = a.cE[i];
-    }
-    return r;
-}
-
-// value at z+1 of element q of a lane's vector: the next element, or the
-// next lane's first element, or (the segment's last lane) the seam value
-template <int V>
-__device__ __forceinline__ float znext(const float (&x)[V], int q, float seam, bool last) {
-    if (q + 1 < V) return x[q + 1];
-    const float s = __shfl_down(x[0], 1);
-    return last ? seam : s;
-}
 
 // MAT: 0 = Cb map only, 1 = Ca and Cb maps, 2 = Ca, Cb and Db maps.
 // PXY: CPML code for the x and y slabs; PZ: for the z slabs.  A tile whose
@@ -83,16 +45,17 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
     const int lane = threadIdx.x & 63;
     const int zlane = lane;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int j = T.j0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const int rw = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // row of the band
+    const int j = T.j0 + rw;  // wave-uniform
     // z segment: lanes from the aligned base T.k0, active on [ks, kend)
     const int ks = T.ks, kend = T.k1, kb = T.k0 + zlane * V, km = ks - 1;
-    const bool ok = j < ny && kb >= ks && kb < kend;  // ks, kend: multiples of V
+    const bool ok = rw < T.nrows && kb >= ks && kb < kend;  // ks, kend: multiples of V
     const bool first = kb == ks;
     const bool yj = j + 1 < ny, jm = j >= 1;
     const bool ke = kend < nz;
     const bool last = kb + V == kend;  // lane 63 unless the segment is cut short
     const unsigned sxs = (unsigned)ny * nz, sys = nz;
-    const int jr = j < ny ? j : 0;
+    const int jr = rw < T.nrows ? j : T.j0;
     const int sy = p.y.lo + p.y.hi, sz = p.z.lo + p.z.hi;
     const float *ex0 = p.s0.f[FDTD_EX], *ey0 = p.s0.f[FDTD_EY], *ez0 = p.s0.f[FDTD_EZ];
     const float *hx0 = p.s0.f[FDTD_HX], *hy0 = p.s0.f[FDTD_HY], *hz0 = p.s0.f[FDTD_HZ];
@@ -198,7 +161,7 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
     // V cells at index threadIdx.x * V; the row above is LZ threads back
     __shared__ float sh[4][WPB * 64 * V];
     const int tq = (int)threadIdx.x * V;
-    const bool top = (int)threadIdx.x < LZ, bot = (int)threadIdx.x >= (WPB * 64 - LZ);
+    const bool top = rw == 0, bot = rw == T.nrows - 1;  // first and last row of the band
     for (int i = T.i0; i < T.i1; ++i) {
         const bool xi = i + 1 < nx, im = i >= 1;
         const unsigned r0 = ((unsigned)i * ny + jr) * nz;  // row (i, j)
@@ -475,7 +438,7 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
             stv<V>(p.s1.f[FDTD_HZ] + c, hz);
         }
         // ---- probes in this plane (grouped by x plane and 4-row band) ----
-        if (pt.start != nullptr) {
+        if (pt.start != nullptr && T.rec) {
             const int g = i * ((ny + 3) / 4) + jr / 4;
             const int pend = pt.start[g + 1];
             for (int q = pt.start[g]; q < pend; ++q) {
@@ -597,7 +560,7 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
                     for (int i = xr[q].a; i < xr[q].b; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
                     for (int j = j0; j < j0 + rows; ++j) ysn += inslab(ny, ylohi[0], ylohi[1], j);
                     for (const ZSeg &z : zseg) {
-                        pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, {0, 0}});
+                        pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, rows, 1});
                         const int64_t zn = z.end - z.start;
                         int64_t zs = 0;
                         for (int k = z.start; k < z.end; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
@@ -608,7 +571,7 @@ void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, 
                 }
             }
         if (pl.tiles.size() == (size_t)l.off) return;
-        while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, {0, 0}});
+        while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, 0, 0});
         l.n = (int)pl.tiles.size() - l.off;
         pl.l.push_back(l);
     };

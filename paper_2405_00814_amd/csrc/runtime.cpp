@@ -266,10 +266,12 @@ void Sim::ensure_rec(int64_t upto) {
 }
 
 void Sim::build_probe_tiles() {
-    if (kcfg.variant != 2 || is_graph) return;
+    if (kcfg.variant < 2 || is_graph) return;
     const int a = kcfg.tile[0], b = kcfg.tile[1], c3 = kcfg.tile[2];
+    const int mat = mumap ? 2 : (lossy ? 1 : 0);
+    const int vm = kcfg.variant * 4 + mat;
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
-        pt_cfg[3] == c3 && pt_start)
+        pt_cfg[3] == c3 && pt_cfg[4] == vm && pt_start)
         return;
     if (ndim == 2) {
         const Fused2DCfg c{a, b};
@@ -288,6 +290,19 @@ void Sim::build_probe_tiles() {
         wave3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, xl, yl, zl, plan3);
         al.put(tl_dev);
         tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
+        if (kcfg.variant == 3) {
+            two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, xl, yl, zl, plan2);
+            plan2_rows = two3d_rows(nz, zl[0] + zl[1] > 0, mat);
+            al.put(tb_dev);
+            al.put(p1_dev);
+            al.put(p2_dev);
+            tb_dev = plan2.tb.empty() ? nullptr : dev_upload(al, plan2.tb.data(), plan2.tb.size(), st);
+            p1_dev = plan2.pass1.tiles.empty() ? nullptr
+                                               : dev_upload(al, plan2.pass1.tiles.data(), plan2.pass1.tiles.size(), st);
+            p2_dev = plan2.pass2.tiles.empty() ? nullptr
+                                               : dev_upload(al, plan2.pass2.tiles.data(), plan2.pass2.tiles.size(), st);
+            alloc_set(2);
+        }
     }
     int ntiles;
     std::vector<int> tile(probe_cells.size());
@@ -328,6 +343,7 @@ void Sim::build_probe_tiles() {
     pt_cfg[1] = b;
     pt_cfg[2] = (int)probe_cells.size();
     pt_cfg[3] = c3;
+    pt_cfg[4] = vm;
 }
 
 
@@ -361,8 +377,60 @@ void Sim::launch_step(int64_t step) {
     }
 }
 
+void Sim::alloc_set(int set) {
+    if (f[set][FDTD_EZ]) return;
+    const size_t n = (size_t)ncell;
+    if (ndim == 2) {
+        for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) f[set][c] = (float *)al.get(n * 4);
+    } else {
+        for (int c = 0; c < 6; ++c) f[set][c] = (float *)al.get(n * 4);
+    }
+    for (int a = 0; a < NPSI3; ++a)
+        if (psi_len[a] > 0) psi[set][a] = (float *)al.get((size_t)psi_len[a] * 4);
+}
+
+// Two steps n -> n+2 from set cur into set 1-cur: x/y-slab cells S and
+// their rim M take a single step into set 2 (pass1), the interior tiles two
+// steps at once, then S its second single step from set 2 (pass2).  The
+// three writes are disjoint in their target cells; pass2 reads set 2 only
+// where pass1 wrote it.  ev (optional): pass1.l.size() + pass2.l.size() + 2
+// events, one before every launch and one after the last.
+void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
+    const int A = cur, B = 1 - cur, C = 2;
+    const ProbeTiles pt{pt_start, pt_cell, pt_slot};
+    const size_t n1 = plan2.pass1.l.size();
+    const Prob3D pab = prob3d(A, B);
+    if (two3d_rows(nz, pab.z.lo + pab.z.hi > 0, pab.db ? 2 : (pab.ca ? 1 : 0)) != plan2_rows)
+        fail(FDTD_ESTATE, "two-step plan out of date");
+    hip_check(launch_3d_wave(prob3d(A, C), plan2.pass1, p1_dev, pt, step, st, ev), "3d pass1");
+    hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), pt, step, st), "3d two-step");
+    hip_check(launch_3d_wave(prob3d(C, B), plan2.pass2, p2_dev, pt, step + 1, st, ev ? ev + n1 + 1 : nullptr),
+              "3d pass2");
+    cur = B;
+    last_launches += (int64_t)(n1 + plan2.pass2.l.size()) + (plan2.tb.empty() ? 0 : 1);
+}
+
+// n steps: pairs through the two-step pass where it is selected, single
+// steps otherwise
+void Sim::advance(int64_t n) {
+    const bool two = kcfg.variant == 3 && ndim == 3 && !is_graph;
+    const int64_t inc = probe_cells.empty() ? 0 : 1;
+    int64_t q = 0;
+    if (two)
+        for (; q + 2 <= n; q += 2) {
+            launch_pair(n_done);
+            n_done += 2;
+            n_rec += 2 * inc;
+        }
+    for (; q < n; ++q) {
+        launch_step(n_done);
+        n_done += 1;
+        n_rec += inc;
+    }
+}
+
 void Sim::zero_state() {
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < 3; ++s) {
         for (int c = 0; c < 6; ++c)
             if (f[s][c]) hip_check(hipMemsetAsync(f[s][c], 0, (size_t)ncell * 4, st), "memset");
         for (int a = 0; a < NPSI3; ++a)
@@ -405,6 +473,9 @@ void Sim::refold(int64_t c0, int64_t c1) {
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
+// smallest 3D grid (cells) on which the default takes two steps per pass
+constexpr int64_t kTwoStepMinCells = (int64_t)1 << 23;
+
 static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
@@ -419,7 +490,11 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     } else {
         Fused3DCfg c{s.nz % 4 == 0 ? 4 : (s.nz % 2 == 0 ? 2 : 1), 0};
         if (wave3d_supported(s.nx, s.ny, s.nz, c)) {
-            k.variant = 2;
+            // two steps per pass on grids large enough for its interior
+            // tiles to dominate; single steps otherwise
+            const bool two = c.V == 4 && s.ncell >= kTwoStepMinCells &&
+                             two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo + s.ax[2].hi);
+            k.variant = two ? 3 : 2;
             k.tile[0] = c.V;
             return 0;
         }
@@ -431,10 +506,11 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
 static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.tb != 0 && k.tb != 1) return false;
     if (k.variant == 1) return true;
-    if (k.variant != 2) return false;
-    if (s.ndim == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
+    if (k.variant != 2 && k.variant != 3) return false;
+    if (s.ndim == 2) return k.variant == 2 && fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
     if (k.tile[1] != 0 || k.tile[3] != 0) return false;
-    return wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]});
+    if (!wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]})) return false;
+    return k.variant == 2 || (k.tile[0] == 4 && two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo + s.ax[2].hi));
 }
 
 // ---------------------------------------------------------------------------
@@ -541,15 +617,7 @@ void init_sim(Sim &s, const fdtd_desc *d) {
         const int64_t len[NPSI3] = {Y, Z, Z, X, X, Y, Y, Z, Z, X, X, Y};
         for (int a = 0; a < NPSI3; ++a) s.psi_len[a] = len[a];
     }
-    for (int set = 0; set < 2; ++set) {
-        if (s.ndim == 2) {
-            for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) s.f[set][c] = (float *)s.al.get(n * 4);
-        } else {
-            for (int c = 0; c < 6; ++c) s.f[set][c] = (float *)s.al.get(n * 4);
-        }
-        for (int a = 0; a < NPSI3; ++a)
-            if (s.psi_len[a] > 0) s.psi[set][a] = (float *)s.al.get((size_t)s.psi_len[a] * 4);
-    }
+    for (int set = 0; set < 2; ++set) s.alloc_set(set);
     hip_check(hipEventCreate(&s.ev0), "event");
     hip_check(hipEventCreate(&s.ev1), "event");
     default_variant_tiles(s, s.kcfg);
@@ -824,11 +892,7 @@ int fdtd_step(fdtd_sim *sim, int64_t n) {
     s.build_probe_tiles();
     s.last_launches = 0;
     hip_check(hipEventRecord(s.ev0, s.st), "event");
-    for (int64_t q = 0; q < n; ++q) {
-        s.launch_step(s.n_done);
-        s.n_done += 1;
-        if (!s.probe_cells.empty()) s.n_rec += 1;
-    }
+    s.advance(n);
     hip_check(hipEventRecord(s.ev1, s.st), "event");
     s.timed = true;
     return FDTD_OK;
@@ -856,10 +920,15 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
     s.ensure_source(s.n_done + steps);
     s.ensure_rec(s.n_rec + steps);
     s.build_probe_tiles();
-    const bool split = s.ndim == 3 && !s.is_graph && s.kcfg.variant == 2;
-    const size_t nl = split ? s.plan3.l.size() : 1;
-    // all events of all steps are recorded first; one synchronisation at the end
-    std::vector<hipEvent_t> ev((nl + 1) * (size_t)steps, nullptr);
+    const bool fused3 = s.ndim == 3 && !s.is_graph && s.kcfg.variant >= 2;
+    const bool two = fused3 && s.kcfg.variant == 3 && steps >= 2;
+    // one timed unit: a step, or a pair of steps for the two-step pass
+    const int32_t per = two ? 2 : 1;
+    const int32_t units = steps / per;
+    const size_t nl = two ? s.plan2.pass1.l.size() + 1 + s.plan2.pass2.l.size()
+                          : (fused3 ? s.plan3.l.size() : 1);
+    // all events of all units are recorded first; one synchronisation at the end
+    std::vector<hipEvent_t> ev((nl + 1) * (size_t)units, nullptr);
     struct Guard {
         std::vector<hipEvent_t> &e;
         Sim &s;
@@ -870,25 +939,28 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
         }
     } guard{ev, s};
     for (auto &e : ev) hip_check(hipEventCreate(&e), "event");
+    const int64_t inc = s.probe_cells.empty() ? 0 : 1;
     int64_t launches = 0;
-    for (int32_t q = 0; q < steps; ++q) {
+    for (int32_t q = 0; q < units; ++q) {
         hipEvent_t *e = ev.data() + (nl + 1) * (size_t)q;
         s.last_launches = 0;
-        if (split) {
-            s.lev = e;
+        if (two) {
+            s.launch_pair(s.n_done, e);
         } else {
-            hip_check(hipEventRecord(e[0], s.st), "event");
+            if (fused3) s.lev = e;
+            else hip_check(hipEventRecord(e[0], s.st), "event");
+            s.launch_step(s.n_done);
+            s.lev = nullptr;
+            if (!fused3) hip_check(hipEventRecord(e[1], s.st), "event");
         }
-        s.launch_step(s.n_done);
-        s.lev = nullptr;
-        if (!split) hip_check(hipEventRecord(e[1], s.st), "event");
-        s.n_done += 1;
-        if (!s.probe_cells.empty()) s.n_rec += 1;
+        s.n_done += per;
+        s.n_rec += per * inc;
         launches = s.last_launches;
     }
+    for (int32_t q = units * per; q < steps; ++q) s.advance(1);
     hip_check(hipEventSynchronize(ev.back()), "event sync");
     std::vector<double> acc(nl, 0.0);
-    for (int32_t q = 0; q < steps; ++q)
+    for (int32_t q = 0; q < units; ++q)
         for (size_t l = 0; l < nl; ++l) {
             float ms = 0;
             const size_t b = (nl + 1) * (size_t)q + l;
@@ -896,21 +968,38 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
             acc[l] += ms;
         }
     *n = (int32_t)nl;
+    auto slab = [&](fdtd_launch_stat &o, const Wave3DLaunch &w) {
+        o.cells = w.cells;
+        o.psi = w.psi;
+        o.cpml = w.pxy ? 2 : (w.pz ? 1 : 0);
+        o.launches = 1;
+        o.steps = 1;
+    };
     for (size_t l = 0; l < nl && (int32_t)l < max; ++l) {
         fdtd_launch_stat &o = out[l];
-        o.ms = (float)(acc[l] / steps);
-        if (split) {
-            const Wave3DLaunch &w = s.plan3.l[l];
-            o.cells = w.cells;
-            o.psi = w.psi;
-            o.cpml = w.pxy ? 2 : (w.pz ? 1 : 0);
-            o.launches = 1;
+        o.ms = (float)(acc[l] / units);
+        const size_t n1 = s.plan2.pass1.l.size();
+        if (two) {
+            if (l < n1) {
+                slab(o, s.plan2.pass1.l[l]);
+            } else if (l == n1) {
+                o.cells = s.plan2.tb_cells;
+                o.psi = s.plan2.tb_psi;
+                o.cpml = s.ax[2].lo + s.ax[2].hi > 0 ? 1 : 0;
+                o.launches = s.plan2.tb.empty() ? 0 : 1;
+                o.steps = 2;
+            } else {
+                slab(o, s.plan2.pass2.l[l - n1 - 1]);
+            }
+        } else if (fused3) {
+            slab(o, s.plan3.l[l]);
         } else {
             o.cells = s.ncell;
             o.psi = 0;
             for (int a = 0; a < NPSI3; ++a) o.psi += s.psi_len[a];
             o.cpml = -1;
             o.launches = (int32_t)launches;
+            o.steps = 1;
         }
     }
     return FDTD_OK;
@@ -1073,7 +1162,7 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
     if (k.tb == 0) k.tb = 1;
     if (k.variant == 0) {
         default_variant_tiles(s, k);
-    } else if (k.variant == 2) {
+    } else if (k.variant == 2 || k.variant == 3) {
         fdtd_kernel_config d;
         default_variant_tiles(s, d);
         if (k.tile[0] == 0) k.tile[0] = d.tile[0];
@@ -1104,7 +1193,8 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     if (!sim) fail(FDTD_EINVAL, "sim is NULL");
     Sim &s = sim->s;
     if (s.is_graph) fail(FDTD_EINVAL, "autotune applies to the implicit-graph stepper");
-    if (trial_steps < 1) trial_steps = 1;
+    if (trial_steps < 2) trial_steps = 2;
+    trial_steps += trial_steps % 2;  // whole pairs for the two-step pass
     const std::string key = tune_key(s);
     const char *path = std::getenv("GEMFDTD_TUNE_CACHE");
     std::map<std::string, std::vector<int>> cache;
@@ -1145,6 +1235,14 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 k.tb = 1;
                 if (config_ok(s, k)) cand.push_back(k);
             }
+        for (int TX : {8, 16, 32}) {
+            fdtd_kernel_config k{};
+            k.variant = 3;
+            k.tile[0] = 4;
+            k.tile[2] = TX;
+            k.tb = 1;
+            if (config_ok(s, k)) cand.push_back(k);
+        }
     }
     {
         fdtd_kernel_config k{};
@@ -1180,9 +1278,11 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
         s.kcfg = k;
         s.pt_ntiles = -1;
         s.build_probe_tiles();
-        s.launch_step(s.n_done);  // warm-up
+        s.n_done = n_done0;
+        s.n_rec = n_rec0;
+        s.advance(2);  // warm-up
         hip_check(hipEventRecord(s.ev0, s.st), "event");
-        for (int q = 0; q < trial_steps; ++q) s.launch_step(s.n_done + 1 + q);
+        s.advance(trial_steps);
         hip_check(hipEventRecord(s.ev1, s.st), "event");
         hip_check(hipEventSynchronize(s.ev1), "sync");
         float ms = 0;

@@ -66,9 +66,11 @@ struct Sim {
     AxisHost axh[3];
     AxisDev ax[3]{};
 
-    // double-buffered state: fields[set][comp], psi[set][a]
-    float *f[2][6] = {};
-    float *psi[2][NPSI3] = {};
+    // double-buffered state: fields[set][comp], psi[set][a]; set 2 is
+    // allocated for the two-step pass only (state n+1 of the cells that the
+    // two-step kernel does not cover)
+    float *f[3][6] = {};
+    float *psi[3][NPSI3] = {};
     int64_t psi_len[NPSI3] = {};
     int cur = 0;
 
@@ -93,7 +95,7 @@ struct Sim {
     // probes grouped by tile for the fused kernels
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
     int pt_ntiles = -1;
-    int pt_cfg[4] = {-1, -1, -1, -1};
+    int pt_cfg[5] = {-1, -1, -1, -1, -1};
     // 2D fused: tile ids clear of the CPML slabs, then the others.  Large
     // grids launch the two lists separately (the interior without the CPML
     // code); small grids take one launch, where a second launch's fixed cost
@@ -104,6 +106,11 @@ struct Sim {
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
     Tile3 *tl_dev = nullptr;
+    // 3D two steps per pass (variant 3): its plan and tile lists
+    TwoPlan plan2;
+    TileTB *tb_dev = nullptr;
+    Tile3 *p1_dev = nullptr, *p2_dev = nullptr;
+    int plan2_rows = 0;
 
     int64_t n_done = 0;
     fdtd_kernel_config kcfg{};
@@ -146,6 +153,9 @@ struct Sim {
     void ensure_rec(int64_t upto);
     void build_probe_tiles();
     void launch_step(int64_t step);
+    void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
+    void advance(int64_t n);
+    void alloc_set(int set);
     void zero_state();
     void refold(int64_t c0, int64_t c1);
 };

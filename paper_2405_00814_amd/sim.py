@@ -237,12 +237,13 @@ class Sim:
 
     def step_profile(self, steps=1):
         """Advance `steps` steps with per-launch HIP events; list of dicts
-        (ms, cells, psi, cpml, launches) with the mean duration of each launch."""
+        (ms, cells, psi, cpml, launches, steps) with the mean duration of each
+        launch per step (per step pair for the two-step pass)."""
         arr = (L.fdtd_launch_stat * 64)()
         n = C.c_int32()
         L.call("fdtd_step_profile", self.h, int(steps), arr, 64, C.byref(n))
         return [dict(ms=arr[q].ms, cells=arr[q].cells, psi=arr[q].psi, cpml=arr[q].cpml,
-                     launches=arr[q].launches)
+                     launches=arr[q].launches, steps=arr[q].steps)
                 for q in range(min(n.value, 64))]
 
     def adjoint_eps(self, T, window, design, ckpt_interval=0, grad=None):

@@ -1,0 +1,154 @@
+"""GPU parity of the 3D two-steps-per-pass stepper (kernel variant 3):
+interior tiles advance two leapfrog steps in one kernel, the tiles near the x
+and y CPML slabs two single steps through a third state set.  Bar: every
+field component and the probe series within relative L2 1e-4 of the FP64
+oracle, and the single-step fused stepper's result within 1e-5."""
+import numpy as np
+import pytest
+
+from paper_2405_00814_amd import workloads as W
+
+from helpers import assert_parity, log, rel_l2, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _problem(shape, npml, steps, seed=1, src=None):
+    pb = W.yee3d(shape=shape, steps=steps, seed=seed, nbox=10, side=(3, 12),
+                 npml=min(npml[:4]) + 2, nprobes=6, tau_steps=8.0)
+    pb.npml = tuple(npml)
+    if src is None:
+        src = tuple((npml[2 * a] + shape[a] - npml[2 * a + 1]) // 2 for a in range(3))
+    pb.source.cell = src
+    pb.source.kind = W.SRC_RICKER
+    pb.source.params = (1.0, 40 * pb.dt, 1.0 / (20 * pb.dt))
+    return pb
+
+
+# nz <= 256 runs one wavefront per row, 256 < nz <= 512 two; shapes with and
+# without z slabs, asymmetric and zero-width x/y slabs, TX from 1 to 32
+CASES = [
+    ((40, 44, 96), (4,) * 6, 0, 121),
+    ((36, 50, 128), (4, 3, 5, 4, 0, 0), 5, 120),
+    ((30, 34, 64), (0, 0, 0, 0, 6, 6), 8, 97),
+    ((26, 30, 300), (4, 4, 4, 4, 6, 5), 0, 80),
+    ((22, 28, 512), (3, 3, 3, 3, 0, 0), 32, 60),
+    ((34, 40, 260), (0, 5, 6, 0, 2, 30), 1, 90),
+    ((24, 60, 44), (5, 5, 5, 5, 3, 3), 3, 110),
+]
+
+
+@pytest.mark.parametrize("shape,npml,TX,steps", CASES)
+def test_two_step_cpml_boxes(shape, npml, TX, steps):
+    pb = _problem(shape, npml, steps)
+    log("two-step", shape, npml, TX, steps)
+    ref, rrec = run_oracle(pb, steps)
+    got, rec, cfg = run_gpu(pb, steps, (3, (4, 0, TX)))
+    assert cfg["variant"] == 3 and tuple(cfg["tile"]) == (4, 0, TX, 0)
+    assert_parity(got, ref, TOL, "two-step %s" % (shape,))
+    assert rel_l2(rec, rrec) <= TOL
+    one, rec1, _ = run_gpu(pb, steps, (2, (4, 0, TX)))
+    for k in got:
+        assert rel_l2(got[k], one[k]) <= 1e-5, k
+    assert rel_l2(rec, rec1) <= 1e-5
+
+
+@pytest.mark.parametrize("mat", ["lossy", "lossy_mu"])
+def test_two_step_materials(mat):
+    """Ca map (sigma > 0) and Db map (mu_r map): the kernels with more
+    coefficient streams and fewer rows per workgroup."""
+    for shape, npml in (((30, 36, 120), (4,) * 6), ((20, 30, 280), (3, 3, 4, 4, 0, 0))):
+        pb = _problem(shape, npml, 90, seed=5)
+        rng = np.random.default_rng(11)
+        pb.sigma = rng.uniform(0, 0.05, pb.shape).astype(np.float32)
+        if mat == "lossy_mu":
+            pb.mu_r = rng.uniform(1, 2, pb.shape).astype(np.float32)
+        pb.source.component = "ey"
+        pb.probe_component = "hx"
+        log("two-step", mat, shape, npml)
+        ref, rrec = run_oracle(pb, pb.steps)
+        got, rec, _ = run_gpu(pb, pb.steps, (3, (4,)))
+        assert_parity(got, ref, TOL, "two-step %s %s" % (mat, shape))
+        assert rel_l2(rec, rrec) <= TOL
+
+
+def test_two_step_sources_and_probes_everywhere():
+    """Source in the band next to a y slab (single-step part) and probes in
+    the two-step part, its rim and the slab part; stepping in odd chunks."""
+    shape, npml = (32, 40, 96), (4,) * 6
+    pb = _problem(shape, npml, 75, src=(16, 5, 48))
+    pb.probes = np.array([(16, 20, 48), (5, 20, 30), (6, 20, 31), (7, 7, 7), (2, 2, 90),
+                          (20, 5, 47), (9, 13, 60), (25, 30, 3)], dtype=np.int32)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for chunks in (1, 3, 7):
+        got, rec, _ = run_gpu(pb, pb.steps, (3, (4, 0, 6)), chunks=chunks)
+        log("chunks", chunks, {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
+        assert_parity(got, ref, TOL, "two-step chunks %d" % chunks)
+        assert rel_l2(rec, rrec) <= TOL
+
+
+def test_two_step_profile_matches_step():
+    from paper_2405_00814_amd.sim import Sim
+    pb = _problem((40, 44, 96), (6,) * 6, 30)
+    a = Sim.from_problem(pb)
+    b = Sim.from_problem(pb)
+    for s in (a, b):
+        s.set_kernel(3, (4,))
+    a.step(7)
+    a.step(23)
+    b.step(7)
+    prof = b.step_profile(23)
+    assert b.steps_done() == 30
+    two = [p for p in prof if p["steps"] == 2]
+    assert len(two) == 1 and two[0]["cpml"] == 1 and two[0]["cells"] > 0
+    k = prof.index(two[0])
+    # pass2 and the two-step launch cover every cell once; pass1 covers
+    # pass2's cells and a rim
+    assert two[0]["cells"] + sum(p["cells"] for p in prof[k + 1:]) == pb.cells
+    assert sum(p["cells"] for p in prof[:k]) > sum(p["cells"] for p in prof[k + 1:])
+    assert all(p["ms"] > 0 for p in prof)
+    for f in ("ex", "ey", "ez", "hx", "hy", "hz"):
+        assert np.array_equal(a.get_field(f), b.get_field(f)), f
+    assert np.array_equal(a.probe(), b.probe())
+    a.close()
+    b.close()
+
+
+def test_two_step_config_rules():
+    from paper_2405_00814_amd._lib import FdtdError
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.yee3d(shape=(16, 16, 30), steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
+                 tau_steps=4.0)
+    s = Sim.from_problem(pb)
+    with pytest.raises(FdtdError):  # nz % 4 != 0
+        s.set_kernel(3, (2,))
+    s.close()
+    for shape, npml in (((16, 16, 516), (3,) * 6), ((16, 16, 160), (3, 3, 3, 3, 40, 30))):
+        pb = W.yee3d(shape=shape, steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
+                     tau_steps=4.0)
+        pb.npml = npml
+        s = Sim.from_problem(pb)
+        with pytest.raises(FdtdError):
+            s.set_kernel(3, (4,))
+        s.close()
+    pb = W.yee3d(shape=(16, 16, 32), steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
+                 tau_steps=4.0)
+    s = Sim.from_problem(pb)
+    for bad in ((2,), (1,), (4, 4)):
+        with pytest.raises(FdtdError):
+            s.set_kernel(3, bad)
+    s.set_kernel(3, (4, 0, 8))
+    assert s.get_kernel()["variant"] == 3
+    s.close()
+
+
+def test_two_step_default_on_large_grid():
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.yee3d(shape=(200, 200, 256), steps=4, seed=0, nbox=20, side=(4, 30), npml=12,
+                 nprobes=4, tau_steps=4.0)
+    s = Sim.from_problem(pb)
+    assert s.get_kernel()["variant"] == 3
+    s.step(4)
+    assert s.check_finite()
+    s.close()
