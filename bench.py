@@ -120,14 +120,18 @@ def bench_3d(args):
     sim.close()
     dom = max(range(len(prof)), key=lambda q: prof[q]["ms"])
     d = prof[dom]
-    # algorithmic bytes of the dominant launch: its cells' fields read and
-    # written once, the coefficient maps read once, its psi values read and
-    # written once
-    dbytes = alg_bytes_implicit(d["cells"], d["psi"], 6, ncoef_of(pb))
+    # algorithmic bytes per cell-update of the dominant launch: its cells'
+    # fields read and written once, the coefficient maps read once, its psi
+    # values read and written once.  A launch that advances its cells by two
+    # steps processes two cell-updates per cell; the bytes it must move at
+    # least are those of one pass (state n in, state n+2 out).
+    pass_bytes = alg_bytes_implicit(d["cells"], d["psi"], 6, ncoef_of(pb))
+    k = d.get("steps", 1)
     return dict(pb=pb, cfg=cfg, t=t, wall=wall, launches=launches, rate=rate, bytes=ab,
                 step_achieved=ab * args.steps / t, finite=ok, prof=prof, dom=dom,
-                dom_bytes=dbytes, dom_ms=d["ms"], dom_bpc=dbytes / d["cells"],
-                dom_achieved=dbytes / (d["ms"] / 1e3))
+                dom_steps=k, dom_pass_bytes=pass_bytes, dom_bytes=k * pass_bytes,
+                dom_ms=d["ms"], dom_bpc=pass_bytes / d["cells"],
+                dom_achieved=k * pass_bytes / (d["ms"] / 1e3))
 
 
 def bench_2d(args, steps=10000):
@@ -295,19 +299,26 @@ def main():
 
     r = bench_3d(args)
     pb = r["pb"]
-    src3 = os.path.join(ROOT, "paper_2405_00814_amd", "csrc", "k3dw.hip")
-    traffic = traffic_record("yee3d_512_interior", src3)
+    two = r["dom_steps"] == 2
+    src3 = os.path.join(ROOT, "paper_2405_00814_amd", "csrc", "k3dt.hip" if two else "k3dw.hip")
+    traffic = traffic_record("yee3d_512_two" if two else "yee3d_512_interior", src3)
+    dcells = r["prof"][r["dom"]]["cells"]
     roof = dict(bound="hbm", achieved=r["dom_achieved"] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                 frac=r["dom_achieved"] / PEAK_HBM, traffic=traffic,
-                kernel="k3d_march interior launch (z-slab CPML only)",
+                kernel=("k3d_two launch (interior tiles, two steps per pass, z-slab CPML)" if two
+                        else "k3d_march interior launch (z-slab CPML only)"),
                 bytes_per_launch=r["dom_bytes"], bytes_per_cell_update=r["dom_bpc"],
-                cells_per_launch=r["prof"][r["dom"]]["cells"],
+                steps_per_launch=r["dom_steps"], cells_per_launch=dcells,
+                cell_updates_per_launch=r["dom_steps"] * dcells,
                 psi_per_launch=r["prof"][r["dom"]]["psi"], avg_launch_ms=r["dom_ms"],
+                min_bytes_per_launch=r["dom_pass_bytes"],
+                pass_frac=r["dom_pass_bytes"] / (r["dom_ms"] / 1e3) / PEAK_HBM,
                 step=dict(launches_per_step=r["launches"] / args.steps,
                           bytes_per_step=r["bytes"], bytes_per_cell_update=r["bytes"] / pb.cells,
                           achieved=r["step_achieved"] / 1e9, frac=r["step_achieved"] / PEAK_HBM,
                           launch_ms=[round(x["ms"], 4) for x in r["prof"]],
-                          launch_cells=[x["cells"] for x in r["prof"]]))
+                          launch_cells=[x["cells"] for x in r["prof"]],
+                          launch_steps=[x["steps"] for x in r["prof"]]))
     forms = {}
     if not args.no_forms:
         log("2d ...")

@@ -68,22 +68,39 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
 
     __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
     __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
-    __shared__ float Zs[PZ ? 2 : 1][PZ ? NR : 1][PZ ? kTwoZMax : 1][4];  // step-1 z psi
-    // z-slab profile per slab cell (kH - idzH, bH, cH, kE - idzE, bE, cE) and
-    // the state-n z psi (Hx-z, Hy-z, Ex-z, Ey-z) of the current plane for
-    // rows j0-2 .. j0+R, row stride sz: loaded with the plane's fields and
-    // read from LDS, so no slab lane waits on a dependent global load
+    // z-slab data in LDS, ZW entries per row: entry e holds cell k = e below
+    // LO4 (the low slab's size rounded up to a multiple of 4) and k = HB4 +
+    // e - LO4 from LO4 on (HB4: start of the high slab rounded down), so a
+    // lane's V cells are V aligned consecutive entries; entries of cells
+    // outside the slabs are padding (profile 0, psi 0: the correction is
+    // then exactly zero).
+    //   ZT: profile (kH - idzH, bH, cH, kE - idzE, bE, cE)
+    //   ZP: state-n psi (Hx-z, Hy-z, Ex-z, Ey-z) of the current plane, rows
+    //       j0-2 .. j0+R, copied from memory with the plane's fields
+    //   Zs: step-1 psi of the last two planes (by plane parity) for step 2
+    //   ZQ: step-2 psi of the own rows, written to memory coalesced after
+    //       the next barrier
+    constexpr int ZW = kTwoZMax + 8;
     constexpr int NZR = NR + 1;
-    __shared__ float ZT[PZ ? 6 : 1][PZ ? kTwoZMax : 1];
-    __shared__ float ZP[PZ ? 4 : 1][PZ ? NZR * kTwoZMax : 1];
-
-    int zsv[V];
-    bool zany = false;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        zsv[v] = (PZ && ok) ? slab_index(p.z, kb + v) : -1;
-        zany = zany || zsv[v] >= 0;
-    }
+    __shared__ __align__(16) float ZT[PZ ? 6 : 1][PZ ? ZW : 4];
+    __shared__ __align__(16) float ZP[PZ ? 4 : 1][PZ ? NZR * ZW : 4];
+    __shared__ __align__(16) float Zs[PZ ? 2 : 1][PZ ? NR : 1][PZ ? 4 : 1][PZ ? ZW : 4];
+    __shared__ __align__(16) float ZQ[PZ ? 4 : 1][PZ ? R * ZW : 4];
+    const int zlo = p.z.lo, zhi = p.z.hi;
+    const int LO4 = (zlo + 3) & ~3, HB4 = (nz - zhi) & ~3;
+    const bool zany = PZ && ok && (kb < LO4 || kb >= HB4);
+    const int zl = PZ ? (kb < LO4 ? kb : LO4 + kb - HB4) : 0;
+    // entry e: its cell's slab index s (the psi arrays' z index); true if the
+    // cell lies in a slab
+    auto zent = [&](int e, int &zs) {
+        if (e < LO4) {
+            zs = e;
+            return e < zlo;
+        }
+        const int k = HB4 + e - LO4;
+        zs = zlo + (k - (nz - zhi));
+        return k >= nz - zhi && k < nz;
+    };
 
     auto zero = [](float (&a)[V]) {
 #pragma unroll
@@ -121,15 +138,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     auto hfix = [&](float (&hx)[V], float (&hy)[V], const float (&db)[V], const float (&dyz)[V],
                     const float (&dxz)[V], float (&o1)[V], float (&o2)[V], bool fx, bool fy) {
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            if (zsv[v] >= 0) {
-                const int s = zsv[v];
-                const float kh = ZT[0][PZ ? s : 0], bh = ZT[1][PZ ? s : 0], ch = ZT[2][PZ ? s : 0];
-                o1[v] = bh * o1[v] + ch * dyz[v];
-                o2[v] = bh * o2[v] + ch * dxz[v];
-                if (fx) hx[v] += db[v] * (kh * dyz[v] + o1[v]);
-                if (fy) hy[v] -= db[v] * (kh * dxz[v] + o2[v]);
-            }
+        for (int v = 0; v < V; ++v) {
+            const float kh = ZT[0][zl + v], bh = ZT[PZ ? 1 : 0][zl + v], ch = ZT[PZ ? 2 : 0][zl + v];
+            o1[v] = bh * o1[v] + ch * dyz[v];
+            o2[v] = bh * o2[v] + ch * dxz[v];
+            if (fx) hx[v] += db[v] * (kh * dyz[v] + o1[v]);
+            if (fy) hy[v] -= db[v] * (kh * dxz[v] + o2[v]);
+        }
     };
     // E from H: own, -x, -y, -z seam (ex/ey/ez old in, new out)
     auto estep = [&](float (&ex)[V], float (&ey)[V], float (&ez)[V], const float (&ca)[V], const float (&cb)[V],
@@ -155,30 +170,47 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     auto efix = [&](float (&ex)[V], float (&ey)[V], const float (&cb)[V], const float (&dyz)[V],
                     const float (&dxz)[V], float (&o3)[V], float (&o4)[V], bool im) {
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            if (zsv[v] >= 0) {
-                const int k = kb + v;
-                const int s = zsv[v];
-                const float ke = ZT[3][PZ ? s : 0], be = ZT[4][PZ ? s : 0], ce = ZT[5][PZ ? s : 0];
-                if (jm && k >= 1) {
-                    o3[v] = be * o3[v] + ce * dyz[v];
-                    ex[v] -= cb[v] * (ke * dyz[v] + o3[v]);
-                }
-                if (im && k >= 1) {
-                    o4[v] = be * o4[v] + ce * dxz[v];
-                    ey[v] += cb[v] * (ke * dxz[v] + o4[v]);
-                }
+        for (int v = 0; v < V; ++v) {
+            const float ke = ZT[PZ ? 3 : 0][zl + v], be = ZT[PZ ? 4 : 0][zl + v], ce = ZT[PZ ? 5 : 0][zl + v];
+            const bool kk = kb + v >= 1;
+            if (jm && kk) {
+                o3[v] = be * o3[v] + ce * dyz[v];
+                ex[v] -= cb[v] * (ke * dyz[v] + o3[v]);
             }
+            if (im && kk) {
+                o4[v] = be * o4[v] + ce * dxz[v];
+                ey[v] += cb[v] * (ke * dxz[v] + o4[v]);
+            }
+        }
     };
-    // psi of the thread's slab cells from the LDS copy (component cc, row
-    // index r = j - (j0 - 2))
-    auto zlds = [&](float (&o)[V], int cc, int r) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = ZP[PZ ? cc : 0][PZ ? r * sz + (zsv[v] >= 0 ? zsv[v] : 0) : 0];
-    };
+    // psi of the thread's cells from the LDS copy (component cc, row index
+    // r = j - (j0 - 2))
+    auto zlds = [&](float (&o)[V], int cc, int r) { ldv<V>(o, &ZP[PZ ? cc : 0][PZ ? r * ZW + zl : 0]); };
+    // from memory (tile start only): padding cells read as 0
     auto zload = [&](float (&o)[V], const float *a, unsigned row) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = a[row + (zsv[v] >= 0 ? zsv[v] : 0)];
+        for (int v = 0; v < V; ++v) {
+            const int q = slab_index(p.z, kb + v);
+            o[v] = q >= 0 ? a[row + q] : 0.f;
+        }
+    };
+    // step-1 stash and step-2 output of the thread's cells
+    auto zstash_w = [&](int par, int cc, const float (&o)[V]) { stv<V>(&Zs[PZ ? par : 0][PZ ? rr : 0][PZ ? cc : 0][zl], o); };
+    auto zstash_r = [&](float (&o)[V], int par, int cc) { ldv<V>(o, &Zs[PZ ? par : 0][PZ ? rr : 0][PZ ? cc : 0][zl]); };
+    auto zout = [&](int cc, const float (&o)[V]) { stv<V>(&ZQ[PZ ? cc : 0][PZ ? (rr - 1) * ZW + zl : 0], o); };
+    // coalesced copy of the step-2 psi of plane ib (own rows) to memory
+    auto zflush = [&](int ib) {
+        for (int q = (int)threadIdx.x; q < R * ZW; q += NT) {
+            const int r = q / ZW, e = q - r * ZW;
+            int zs;
+            if (zent(e, zs) && r < T.nrows) {
+                const unsigned g = zs3(ib, T.j0 + r, zs, ny, sz);
+                P1[PSI_HXZ][g] = ZQ[0][q];
+                P1[PSI_HYZ][g] = ZQ[PZ ? 1 : 0][q];
+                P1[PSI_EXZ][g] = ZQ[PZ ? 2 : 0][q];
+                P1[PSI_EYZ][g] = ZQ[PZ ? 3 : 0][q];
+            }
+        }
     };
     // The element is picked by selects, never by an index computed at run
     // time: a computed index into a register array moves the array to
@@ -224,18 +256,20 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     };
 
     const int ia = T.i0 > 0 ? T.i0 - 1 : 0;
-    if (PZ) {
-        for (int k = (int)threadIdx.x; k < nz; k += NT) {
-            const int s = slab_index(p.z, k);
-            if (s >= 0) {
-                ZT[0][PZ ? s : 0] = p.z.kH[k] - idzH;
-                ZT[1][PZ ? s : 0] = p.z.bH[k];
-                ZT[2][PZ ? s : 0] = p.z.cH[k];
-                ZT[3][PZ ? s : 0] = p.z.kE[k] - idzE;
-                ZT[4][PZ ? s : 0] = p.z.bE[k];
-                ZT[5][PZ ? s : 0] = p.z.cE[k];
+    if (PZ) {  // profile table; psi copy zeroed (its padding stays zero)
+        for (int q = (int)threadIdx.x; q < 6 * ZW; q += NT) {
+            const int c = q / ZW, e = q - c * ZW;
+            int zs;
+            const bool real = zent(e, zs);
+            const int k = e < LO4 ? e : HB4 + e - LO4;
+            float v = 0.f;
+            if (real) {
+                v = c == 0 ? p.z.kH[k] - idzH : c == 1 ? p.z.bH[k] : c == 2 ? p.z.cH[k]
+                  : c == 3 ? p.z.kE[k] - idzE : c == 4 ? p.z.bE[k] : p.z.cE[k];
             }
+            ZT[PZ ? c : 0][e] = v;
         }
+        for (int q = (int)threadIdx.x; q < 4 * NZR * ZW; q += NT) (&ZP[0][0])[q] = 0.f;
         __syncthreads();
     }
     // carried between planes
@@ -291,20 +325,24 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const bool la = pa && ok;
         // ---- state-n z psi of plane i (rows j0-2 .. j0+R): issued now,
         //      written to LDS before the first barrier ----
-        constexpr int NZL = PZ ? (NZR * kTwoZMax + NT - 1) / NT : 1;
+        constexpr int NZQ = NZR * ZW;  // entries per component
+        constexpr int NZL = PZ ? (NZQ + NT - 1) / NT : 1;
         float zpre[4][NZL];
-        const int zrows = NZR * sz;
-        const int64_t zg0 = ((int64_t)(pa ? i : 0) * ny + (T.j0 - 2)) * sz;
+        bool zin[NZL];
         if (PZ) {
 #pragma unroll
             for (int u = 0; u < NZL; ++u) {
                 const int q = (int)threadIdx.x + u * NT;
-                const int64_t g = (int64_t)(T.j0 - 2) * sz + q;  // offset inside plane i
-                const bool in = pa && q < zrows && g >= 0 && g < (int64_t)ny * sz;
-                zpre[0][u] = in ? P0[PSI_HXZ][zg0 + q] : 0.f;
-                zpre[1][u] = in ? P0[PSI_HYZ][zg0 + q] : 0.f;
-                zpre[2][u] = in ? P0[PSI_EXZ][zg0 + q] : 0.f;
-                zpre[3][u] = in ? P0[PSI_EYZ][zg0 + q] : 0.f;
+                const int row = q / ZW, e = q - row * ZW;
+                const int jj = T.j0 - 2 + row;
+                int zs = 0;
+                zin[u] = q < NZQ && zent(e, zs) && jj >= 0 && jj < ny;
+                const unsigned g = zs3(pa ? i : 0, zin[u] ? jj : 0, zin[u] ? zs : 0, ny, sz);
+                const bool in = zin[u] && pa;
+                zpre[0][u] = in ? P0[PSI_HXZ][g] : 0.f;
+                zpre[1][u] = in ? P0[PSI_HYZ][g] : 0.f;
+                zpre[2][u] = in ? P0[PSI_EXZ][g] : 0.f;
+                zpre[3][u] = in ? P0[PSI_EYZ][g] : 0.f;
             }
         }
         // ---- E^{n+1} at plane i-1 of the row below and the z seam ----
@@ -334,15 +372,15 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         if (lane == 0) { Se0[rr][seg][0] = ex[0]; Se0[rr][seg][1] = ey[0]; }
         if (PZ) {
 #pragma unroll
-            for (int u = 0; u < NZL; ++u) {
-                const int q = (int)threadIdx.x + u * NT;
-                if (q < zrows) {
+            for (int u = 0; u < NZL; ++u)
+                if (zin[u]) {
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) ZP[PZ ? cc : 0][PZ ? q : 0] = zpre[cc][u];
+                    for (int cc = 0; cc < 4; ++cc) ZP[PZ ? cc : 0][(int)threadIdx.x + u * NT] = zpre[cc][u];
                 }
-            }
         }
         __syncthreads();
+        // step-2 psi of plane i-2 (written to LDS last iteration) to memory
+        if (PZ && i - 2 >= T.i0) zflush(i - 2);
         if (!bot && la && yj) {
             ldv<V>(exy, &LEx[tq + ROW]);
             ldv<V>(ezy, &LEz[tq + ROW]);
@@ -357,12 +395,8 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             zlds(o1, 0, rr + 1);
             zlds(o2, 1, rr + 1);
             hfix(hx, hy, db, dyz, dxz, o1, o2, true, true);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (zsv[v] >= 0) {
-                    float *z = Zs[PZ ? (i & 1) : 0][PZ ? rr : 0][PZ ? zsv[v] : 0];
-                    z[0] = o1[v]; z[1] = o2[v];
-                }
+            zstash_w(i & 1, 0, o1);
+            zstash_w(i & 1, 1, o2);
         }
         stv<V>(&LHx[tq], hx);
         stv<V>(&LHz[tq], hz);
@@ -411,12 +445,8 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             zlds(o3, 2, rr + 1);
             zlds(o4, 3, rr + 1);
             efix(ex1, ey1, cb, dyz, dxz, o3, o4, im);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (zsv[v] >= 0) {
-                    float *z = Zs[PZ ? (i & 1) : 0][PZ ? rr : 0][PZ ? zsv[v] : 0];
-                    z[2] = o3[v]; z[3] = o4[v];
-                }
+            zstash_w(i & 1, 2, o3);
+            zstash_w(i & 1, 3, o4);
         }
         add_source(c, step, ex1, ey1, ez1);
         if (!la) { zero(ex1); zero(ey1); zero(ez1); zero(hx); zero(hy); zero(hz); }
@@ -430,31 +460,21 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const bool pb = ib >= ia && rr <= T.nrows && rok;  // wave-uniform
         const bool wb = own && rok && ib >= T.i0;          // E too, and stored
         const unsigned cq = ((unsigned)(pb ? ib : 0) * ny + jr) * nz + kb;
-        const unsigned zrb = zs3(pb ? ib : 0, jr, 0, ny, sz);
         float hx2[V], hy2[V], hz2[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) { hx2[v] = hx1p[v]; hy2[v] = hy1p[v]; hz2[v] = hz1p[v]; }
-        // step-1 z psi of plane ib from the stash (component c)
-        auto zstash = [&](float (&o)[V], int cc) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) o[v] = Zs[PZ ? (ib & 1) : 0][PZ ? rr : 0][PZ ? (zsv[v] >= 0 ? zsv[v] : 0) : 0][cc];
-        };
         if (pb) {  // wave-uniform
             const bool sn2 = last && seamnext;
             const float exs = sn2 ? e1s[0] : 0.f, eys = sn2 ? e1s[1] : 0.f;
             hstep(hx2, hy2, hz2, dbp, ex1p, ey1p, ez1p, ey1, ez1, ex1y, ez1y, exs, eys, dyz, dxz);
             if (PZ && zany) {
                 float p1[V], p2[V];
-                zstash(p1, 0);
-                zstash(p2, 1);
+                zstash_r(p1, ib & 1, 0);
+                zstash_r(p2, ib & 1, 1);
                 hfix(hx2, hy2, dbp, dyz, dxz, p1, p2, true, true);
                 if (wb) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        if (zsv[v] >= 0) {
-                            P1[PSI_HXZ][zrb + zsv[v]] = p1[v];
-                            P1[PSI_HYZ][zrb + zsv[v]] = p2[v];
-                        }
+                    zout(0, p1);
+                    zout(1, p2);
                 }
             }
         }
@@ -479,15 +499,11 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             estep(e2x, e2y, e2z, cap, cbp, hx2, hy2, hz2, hy2p, hz2p, hxj2, hzj2, hxs2, hys2, ib >= 1, dyz, dxz);
             if (PZ && zany) {  // zany implies ok
                 float p3[V], p4[V];
-                zstash(p3, 2);
-                zstash(p4, 3);
+                zstash_r(p3, ib & 1, 2);
+                zstash_r(p4, ib & 1, 3);
                 efix(e2x, e2y, cbp, dyz, dxz, p3, p4, ib >= 1);
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    if (zsv[v] >= 0) {
-                        P1[PSI_EXZ][zrb + zsv[v]] = p3[v];
-                        P1[PSI_EYZ][zrb + zsv[v]] = p4[v];
-                    }
+                zout(2, p3);
+                zout(3, p4);
             }
             add_source(cq, step + 1, e2x, e2y, e2z);
             record(ib, cq, step + 1, e2x, e2y, e2z, hx2, hy2, hz2);
@@ -510,6 +526,10 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             hy2p[v] = hy2[v]; hz2p[v] = hz2[v];
             cbp[v] = cb[v]; cap[v] = ca[v]; dbp[v] = db[v];
         }
+    }
+    if (PZ && iend - 1 >= T.i0) {
+        __syncthreads();
+        zflush(iend - 1);
     }
 }
 
