@@ -174,8 +174,8 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
 /* Kernel selection for the implicit-graph stepper.
  *  variant: 0 = auto (autotuned or default), 1 = two-pass reference
  *           (separate H and E kernels, in place), 2 = fused single pass
- *           (one kernel per step, double-buffered state), 3 = (3D only)
- *           two leapfrog steps per pass over memory: tiles whose
+ *           (one kernel per step, double-buffered state), 3 = several
+ *           leapfrog steps per pass over memory.  3D: tiles whose
  *           dependency cone stays clear of the x and y CPML slabs advance
  *           two steps in one kernel (state n+1 never leaves the chip); the
  *           rest takes two fused single steps through a third state set
@@ -187,8 +187,15 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    3D fused: tile[0] = V (1, 2 or 4 consecutive z cells per thread;
  *    nz % V must be 0); tile[2] = x planes marched by one workgroup (0 =
  *    16, at most 4096); tile[1] and tile[3] must be 0.
- *    3D two-step: as 3D fused with V = 4; also nz <= 512 and at most 64
- *    z-CPML cells in all.
+ *    3D two-step: as 3D fused with V = 4; also nz <= 512, at most 64
+ *    z-CPML cells in all, and no 4-cell z group holding cells of both z
+ *    slabs.
+ *    2D multi-step (variant 3 on a 2D grid): tile[0] = V (2 or 4; ny % V
+ *    must be 0), tile[1] = TX (rows per tile, 1..65536; 0 = 32), tile[2] =
+ *    TB (leapfrog steps per pass: 2 or 4); tile[3] must be 0.  Each
+ *    wavefront advances its rows and columns TB steps, recomputing the
+ *    neighbouring rows and columns it needs; an n not divisible by TB ends
+ *    with single steps.
  * FDTD_EINVAL for unknown or unsupported combinations. */
 typedef struct {
     int32_t variant;

@@ -116,6 +116,28 @@ hipError_t launch_2d_fused(const Prob2D &p, const Fused2DCfg &c, const ProbeTile
                            int64_t step, hipStream_t st, const int *design, float *cap_ez,
                            float *cap_br, const TileSplit2D *split = nullptr);
 bool fused2d_interior(int nx, int ny, const Fused2DCfg &c, const int *xlohi, const int *ylohi, int t);
+
+// 2D, TB steps per pass (temporal blocking).  A tile is one wavefront: rows
+// [i0, i1) and columns [ja, ja + tb2d_own(V, TB)) (clipped to ny) of problem
+// `prob`; the lanes at each side recompute the neighbouring columns.
+struct Tile2T {
+    int prob, i0, i1, ja;
+};
+constexpr int tb2d_halo(int V, int TB) { return (TB + V - 1) / V; }
+constexpr int tb2d_own(int V, int TB) { return (64 - 2 * tb2d_halo(V, TB)) * V; }
+bool tb2d_supported(int ny, int V, int TB, int TX);
+// Tiles of one problem: rows in chunks of TX, strips of tb2d_own(V, TB)
+// columns; `inner` takes the tiles whose dependency cone (rows i0-TB ..
+// i1+TB-1, the strip's loaded columns) is clear of the CPML slabs, `outer`
+// the others.  Ordered row chunk by row chunk.
+void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi, const int *ylohi,
+               std::vector<Tile2T> &inner, std::vector<Tile2T> &outer);
+// probs_dev: nullptr for one problem p (tiles' prob ignored), else the
+// device array the tiles index (step = *step_base + step).  mat: 0 Cb, 1
+// Ca and Cb, 2 Ca, Cb and Db maps (null maps of a problem read as uniform).
+hipError_t launch_2d_tb(const Prob2D &p, const Prob2D *probs_dev, const Tile2T *tiles, int ntiles, bool pml,
+                        int mat, const ProbeTiles &pt, int V, int TB, const int64_t *step_base, int64_t step,
+                        hipStream_t st);
 int fused2d_ntiles(int nx, int ny, const Fused2DCfg &c);
 int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
@@ -155,7 +177,17 @@ hipError_t launch_3d_wave(const Prob3D &p, const Wave3DPlan &pl, const Tile3 *ti
 struct TileTB {
     int i0, i1, j0, nrows;
 };
-bool two3d_supported(int nx, int ny, int nz, int sz);
+// z-slab cells (both ends together) the two-step kernel handles at most
+constexpr int kTwoZMax = 64;
+// Wavefronts per workgroup of the two-step kernel.  The instances with
+// z-slab CPML or a Db map need more registers: 12 wavefronts (168 VGPRs)
+// instead of 16 (128).
+constexpr int two_waves(bool pz, int mat) { return (pz || mat == 2) ? 12 : 16; }
+// nz % 4 == 0, nz <= 512, zlo + zhi <= kTwoZMax, and no 4-cell group holds
+// cells of both z slabs
+bool two3d_supported(int nx, int ny, int nz, int zlo, int zhi);
+// rows per band (the workgroup holds two halo rows more, RZ wavefronts per
+// row)
 int two3d_rows(int nz, bool pz, int mat);  // mat: 0 Cb, 1 Ca+Cb, 2 Ca+Cb+Db maps
 // records probes at steps `step` and `step`+1 of cells it owns
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,

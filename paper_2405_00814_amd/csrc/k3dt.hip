@@ -30,8 +30,6 @@
 
 namespace gem {
 
-constexpr int kTwoZMax = 64;  // largest z-slab thickness (both ends) of the two-step kernel
-
 template <int V, int RZ, int R, bool PZ, int MAT>
 __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const TileTB *tiles, ProbeTiles pt,
                                                            int64_t step) {
@@ -533,142 +531,6 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     }
 }
 
-bool two3d_supported(int nx, int ny, int nz, int sz) {
-    (void)nx; (void)ny;
-    return nz % 4 == 0 && nz <= 2 * 64 * 4 && sz <= kTwoZMax;
-}
-
-// Rows per band of the two-step kernel (its workgroup holds two halo rows
-// more, RZ wavefronts per row).  The instances with z-slab CPML or a Db map
-// need more registers: 12 wavefronts (168 VGPRs) instead of 16 (128).
-constexpr int two_waves(bool pz, int mat) { return (pz || mat == 2) ? 12 : 16; }
-int two3d_rows(int nz, bool pz, int mat) {
-    const int rz = nz <= 64 * 4 ? 1 : 2;
-    return two_waves(pz, mat) / rz - 2;
-}
-
-namespace {
-
-// single-step tiles covering the marked (plane, row) cells of a mask (1 =
-// record probes, 2 = do not), full z: per plane, runs of rows with one mark
-// in pieces of at most 4 rows; consecutive planes with the same pieces merge
-// into x ranges of at most tx planes.
-void mask_tiles(const std::vector<unsigned char> &m, int nx, int ny, int nz, int V, int tx, bool pz,
-                const int *xlohi, const int *ylohi, const int *zlohi, Wave3DPlan &pl) {
-    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
-    struct Piece {
-        int j0, n, rec;
-        bool operator==(const Piece &o) const { return j0 == o.j0 && n == o.n && rec == o.rec; }
-    };
-    auto pieces_of = [&](int i) {
-        std::vector<Piece> ps;
-        int j = 0;
-        while (j < ny) {
-            const unsigned char mk = m[(size_t)i * ny + j];
-            if (!mk) { ++j; continue; }
-            int e = j;
-            while (e < ny && m[(size_t)i * ny + e] == mk) ++e;
-            for (int a = j; a < e; a += 4) ps.push_back(Piece{a, std::min(4, e - a), mk == 1 ? 1 : 0});
-            j = e;
-        }
-        return ps;
-    };
-    Wave3DLaunch l{};
-    l.V = V;
-    l.wpb = 4;
-    l.pxy = true;
-    l.pz = pz;
-    l.off = (int)pl.tiles.size();
-    const int seg = 64 * V;
-    int i = 0;
-    while (i < nx) {
-        const std::vector<Piece> ps = pieces_of(i);
-        int e = i + 1;
-        while (e < nx && e - i < tx && pieces_of(e) == ps) ++e;
-        int64_t xs = 0;
-        for (int a = i; a < e; ++a) xs += inslab(nx, xlohi[0], xlohi[1], a);
-        for (const Piece &pc : ps) {
-            int64_t ysn = 0;
-            for (int b = pc.j0; b < pc.j0 + pc.n; ++b) ysn += inslab(ny, ylohi[0], ylohi[1], b);
-            for (int k0 = 0; k0 < nz; k0 += seg) {
-                const int k1 = std::min(k0 + seg, nz);
-                int64_t zs = 0;
-                for (int k = k0; k < k1; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
-                pl.tiles.push_back(Tile3{i, e, pc.j0, k0, k1, k0, pc.n, pc.rec});
-                const int64_t xn = e - i, zn = k1 - k0;
-                l.cells += xn * pc.n * zn;
-                l.psi += 4 * (xs * pc.n * zn + xn * ysn * zn + xn * pc.n * zs);
-            }
-        }
-        i = e;
-    }
-    if (pl.tiles.size() == (size_t)l.off) return;
-    while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, 0, 0});
-    l.n = (int)pl.tiles.size() - l.off;
-    pl.l.push_back(l);
-}
-
-}  // namespace
-
-void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int *xlohi, const int *ylohi,
-                const int *zlohi, TwoPlan &pl) {
-    pl.tb.clear();
-    pl.tb_cells = pl.tb_psi = 0;
-    pl.pass1.l.clear();
-    pl.pass1.tiles.clear();
-    pl.pass2.l.clear();
-    pl.pass2.tiles.clear();
-    const int TX = c.TX > 0 ? c.TX : 16, R = two3d_rows(nz, zlohi[0] + zlohi[1] > 0, mat);
-    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
-    auto clear = [&](int n, int lo, int hi, int a, int b) {  // no slab cell in [a, b]
-        for (int q = std::max(a, 0); q <= std::min(b, n - 1); ++q)
-            if (inslab(n, lo, hi, q)) return false;
-        return true;
-    };
-    int64_t zs = 0;
-    for (int k = 0; k < nz; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
-    std::vector<unsigned char> inner((size_t)nx * ny, 0);
-    // two-step tiles, x chunk by x chunk, bands inside, over the planes and
-    // rows whose cone is clear: [lo + 2, n - hi - 1) of an axis with slabs
-    auto range = [](int n, int lo, int hi, int &a, int &b) {
-        a = lo > 0 ? lo + 2 : 0;
-        b = hi > 0 ? n - hi - 1 : n;
-    };
-    int xa, xb, ya, yb;
-    range(nx, xlohi[0], xlohi[1], xa, xb);
-    range(ny, ylohi[0], ylohi[1], ya, yb);
-    for (int i0 = xa; i0 < xb; i0 += TX) {
-        const int i1 = std::min(i0 + TX, xb);
-        if (!clear(nx, xlohi[0], xlohi[1], i0 - 2, i1)) continue;
-        for (int j0 = ya; j0 < yb; j0 += R) {
-            const int nr = std::min(R, yb - j0);
-            if (!clear(ny, ylohi[0], ylohi[1], j0 - 2, j0 + nr)) continue;
-            pl.tb.push_back(TileTB{i0, i1, j0, nr});
-            pl.tb_cells += (int64_t)(i1 - i0) * nr * nz;
-            pl.tb_psi += 4 * (int64_t)(i1 - i0) * nr * zs;
-            for (int i = i0; i < i1; ++i)
-                for (int j = j0; j < j0 + nr; ++j) inner[(size_t)i * ny + j] = 1;
-        }
-    }
-    while (pl.tb.size() % 8) pl.tb.push_back(TileTB{0, 0, 0, 0});
-    // S: everything else (marked 1); M: its one-cell rim in x and y (marked 2)
-    std::vector<unsigned char> s1((size_t)nx * ny, 0), s2((size_t)nx * ny, 0);
-    for (size_t q = 0; q < s1.size(); ++q) s1[q] = s2[q] = inner[q] ? 0 : 1;
-    for (int i = 0; i < nx; ++i)
-        for (int j = 0; j < ny; ++j) {
-            if (!inner[(size_t)i * ny + j]) continue;
-            bool near = false;
-            for (int a = i - 1; a <= i + 1; ++a)
-                for (int b = j - 1; b <= j + 1; ++b)
-                    if (a >= 0 && a < nx && b >= 0 && b < ny && !inner[(size_t)a * ny + b]) near = true;
-            if (near) s1[(size_t)i * ny + j] = 2;
-        }
-    const int txs = std::max(1, TX / 4);
-    const bool pz = zlohi[0] + zlohi[1] > 0;
-    mask_tiles(s1, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass1);
-    mask_tiles(s2, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass2);
-}
-
 template <int RZ, bool PZ, int MAT>
 static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step, hipStream_t st) {
     constexpr int W = two_waves(PZ, MAT), R = W / RZ - 2;
@@ -687,7 +549,7 @@ static void go_two_m(const Prob3D &p, const TileTB *tiles, int n, const ProbeTil
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
                          hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (!two3d_supported(p.nx, p.ny, p.nz, p.z.lo + p.z.hi)) return hipErrorInvalidValue;
+    if (!two3d_supported(p.nx, p.ny, p.nz, p.z.lo, p.z.hi)) return hipErrorInvalidValue;
     const bool pz = p.z.lo + p.z.hi > 0;
     if (p.nz <= 64 * 4) {
         if (pz) go_two_m<1, true>(p, tiles, n, pt, step, st);

@@ -472,121 +472,6 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
     }
 }
 
-// Probes are grouped by (x plane, 4-row band).
-int wave3d_ngroups(int nx, int ny) { return nx * ((ny + 3) / 4); }
-int wave3d_group_of(int ny, int i, int j) { return i * ((ny + 3) / 4) + j / 4; }
-
-bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c) {
-    (void)nx; (void)ny;
-    if (!(c.V == 1 || c.V == 2 || c.V == 4)) return false;
-    if (c.TX < 0 || c.TX > 4096) return false;
-    return nz % c.V == 0;
-}
-
-namespace {
-
-struct Range {
-    int a, b;
-};
-
-// [lo, hi) cut into pieces of at most `w`
-void chunks(std::vector<Range> &out, int lo, int hi, int w) {
-    for (int a = lo; a < hi; a += w) out.push_back(Range{a, std::min(a + w, hi)});
-}
-
-// z segments of [lo, hi) on the grid of multiples of w (w cells per
-// segment, lanes below lo or from hi on idle)
-struct ZSeg {
-    int base, start, end;
-};
-void zsegs(std::vector<ZSeg> &out, int lo, int hi, int w) {
-    if (lo >= hi) return;
-    for (int b = lo / w * w; b < hi; b += w) out.push_back(ZSeg{b, std::max(b, lo), std::min(b + w, hi)});
-}
-
-}  // namespace
-
-// Launch plan.  x: the planes clear of the x slabs (a tile's plane i0-1
-// included) and the slab ends, in chunks of TX planes (TX/4 for the launch
-// with x/y CPML code, which has fewer tiles and more latency per plane);
-// y: bands of WPB rows (8 interior, 4 slab), clear of the y slabs (row j0-1
-// included) or not; z: segments of 64V cells (z-slab cells are handled by
-// the correction step of the PZ instances).  The interior launch takes the
-// (interior x chunk, interior y band) tiles, the slab launch all others.
-// Each launch's tiles run x chunk by x chunk, y bands and z segments
-// inside, so that workgroups issued together on one XCD share halo rows;
-// each XCD takes a contiguous eighth of the list (padded with empty tiles).
-void wave3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, const int *xlohi, const int *ylohi,
-                 const int *zlohi, Wave3DPlan &pl) {
-    pl.l.clear();
-    pl.tiles.clear();
-    const int V = c.V;
-    const int TX = c.TX > 0 ? c.TX : 16, TXs = std::max(1, TX / 4);
-    auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
-    const int xl = xlohi[0] == 0 ? 0 : std::min(nx, xlohi[0] + 1);
-    const int xh = std::max(xl, nx - xlohi[1]);
-    auto add = [&](int Vl, int wpb, bool pxy, bool pz, const std::vector<ZSeg> &zseg) {
-        if (zseg.empty()) return;
-        const int RB = wpb;
-        const int tx = pxy ? TXs : TX;
-        Wave3DLaunch l{};
-        l.V = Vl;
-        l.wpb = wpb;
-        l.pxy = pxy;
-        l.pz = pz;
-        l.off = (int)pl.tiles.size();
-        std::vector<Range> xr;
-        std::vector<char> xslab;
-        auto put = [&](int lo, int hi, bool sl) {
-            const size_t n0 = xr.size();
-            chunks(xr, lo, hi, tx);
-            xslab.resize(xr.size(), sl);
-            (void)n0;
-        };
-        put(0, xl, true);
-        put(xl, xh, false);
-        put(xh, nx, true);
-        // y rows are classified in groups of 8 (the interior band height);
-        // the slab launch splits its groups into bands of RB rows
-        for (size_t q = 0; q < xr.size(); ++q)
-            for (int g0 = 0; g0 < ny; g0 += 8) {
-                bool ys = false;
-                for (int j = g0 - 1; j < g0 + 8 && j < ny; ++j) ys = ys || inslab(ny, ylohi[0], ylohi[1], j);
-                if (pxy != (xslab[q] || ys)) continue;
-                for (int j0 = g0; j0 < std::min(g0 + 8, ny); j0 += RB) {
-                    const int rows = std::min(RB, ny - j0);
-                    const int64_t xn = xr[q].b - xr[q].a;
-                    int64_t xs = 0, ysn = 0;
-                    for (int i = xr[q].a; i < xr[q].b; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
-                    for (int j = j0; j < j0 + rows; ++j) ysn += inslab(ny, ylohi[0], ylohi[1], j);
-                    for (const ZSeg &z : zseg) {
-                        pl.tiles.push_back(Tile3{xr[q].a, xr[q].b, j0, z.base, z.end, z.start, rows, 1});
-                        const int64_t zn = z.end - z.start;
-                        int64_t zs = 0;
-                        for (int k = z.start; k < z.end; ++k) zs += inslab(nz, zlohi[0], zlohi[1], k);
-                        l.cells += xn * rows * zn;
-                        // four psi per slab a cell lies in
-                        l.psi += 4 * (xs * rows * zn + xn * ysn * zn + xn * rows * zs);
-                    }
-                }
-            }
-        if (pl.tiles.size() == (size_t)l.off) return;
-        while ((pl.tiles.size() - (size_t)l.off) % 8) pl.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, 0, 0});
-        l.n = (int)pl.tiles.size() - l.off;
-        pl.l.push_back(l);
-    };
-    const bool anyxy = xlohi[0] + xlohi[1] + ylohi[0] + ylohi[1] > 0;
-    // slab workgroups: 4 rows (fewer registers per wave are left, so smaller
-    // workgroups keep more of them resident)
-    auto both = [&](int Vl, bool pz, const std::vector<ZSeg> &zseg) {
-        add(Vl, 8, false, pz, zseg);
-        if (anyxy) add(Vl, 4, true, pz, zseg);
-    };
-    std::vector<ZSeg> zseg;
-    zsegs(zseg, 0, nz, 64 * V);
-    both(V, zlohi[0] + zlohi[1] > 0, zseg);
-}
-
 template <int V, int WPB, bool PXY, bool PZ, int MAT>
 static void go(const Prob3D &p, const Wave3DLaunch &l, const Tile3 *tiles, const ProbeTiles &pt,
                int64_t step, hipStream_t st) {

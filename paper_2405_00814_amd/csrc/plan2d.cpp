@@ -1,0 +1,35 @@
+// Host-side tile plan of the 2D multi-step kernel (pure integer work).
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gem {
+
+bool tb2d_supported(int ny, int V, int TB, int TX) {
+    if (!(V == 2 || V == 4) || !(TB == 2 || TB == 4)) return false;
+    if (TX < 1 || TX > 65536) return false;
+    return ny % V == 0;
+}
+
+void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi, const int *ylohi,
+               std::vector<Tile2T> &inner, std::vector<Tile2T> &outer) {
+    const int ow = tb2d_own(V, TB), hw = tb2d_halo(V, TB) * V;
+    auto clear = [](int n, int lo, int hi, int a, int b) {  // no slab index in [a, b)
+        a = std::max(a, 0);
+        b = std::min(b, n);
+        for (int q = a; q < b; ++q)
+            if (q < lo || q >= n - hi) return false;
+        return true;
+    };
+    for (int i0 = 0; i0 < nx; i0 += TX) {
+        const int i1 = std::min(i0 + TX, nx);
+        const bool xc = clear(nx, xlohi[0], xlohi[1], i0 - TB, i1 + TB);
+        for (int ja = 0; ja < ny; ja += ow) {
+            const bool yc = clear(ny, ylohi[0], ylohi[1], ja - hw, ja - hw + 64 * V);
+            (xc && yc ? inner : outer).push_back(Tile2T{prob, i0, i1, ja});
+        }
+    }
+}
+
+}  // namespace gem

@@ -268,13 +268,13 @@ void Sim::ensure_rec(int64_t upto) {
 void Sim::build_probe_tiles() {
     if (kcfg.variant < 2 || is_graph) return;
     const int a = kcfg.tile[0], b = kcfg.tile[1], c3 = kcfg.tile[2];
-    const int mat = mumap ? 2 : (lossy ? 1 : 0);
+    const int mat = this->mat();
     const int vm = kcfg.variant * 4 + mat;
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
         pt_cfg[3] == c3 && pt_cfg[4] == vm && pt_start)
         return;
     if (ndim == 2) {
-        const Fused2DCfg c{a, b};
+        const Fused2DCfg c = single2d();
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
         const int nt = fused2d_ntiles(nx, ny, c);
         std::vector<int> ids, outer;
@@ -307,7 +307,7 @@ void Sim::build_probe_tiles() {
     int ntiles;
     std::vector<int> tile(probe_cells.size());
     if (ndim == 2) {
-        Fused2DCfg c{a, b};
+        const Fused2DCfg c = single2d();
         ntiles = fused2d_ntiles(nx, ny, c);
         for (size_t q = 0; q < probe_cells.size(); ++q) {
             const int i = (int)(probe_cells[q] / ny), j = (int)(probe_cells[q] % ny);
@@ -344,6 +344,61 @@ void Sim::build_probe_tiles() {
     pt_cfg[2] = (int)probe_cells.size();
     pt_cfg[3] = c3;
     pt_cfg[4] = vm;
+    if (ndim == 2 && kcfg.variant == 3) {
+        const int V = kcfg.tile[0], TX = kcfg.tile[1], TB = kcfg.tile[2];
+        const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
+        std::vector<Tile2T> in, out;
+        tb2d_plan(0, nx, ny, V, TB, TX, xl, yl, in, out);
+        tb2_inner = (int)in.size();
+        tb2_outer = (int)out.size();
+        in.insert(in.end(), out.begin(), out.end());
+        al.put(tb2_dev);
+        tb2_dev = dev_upload(al, in.data(), std::max<size_t>(in.size(), 1), st);
+        // probe groups by position in the list
+        const int ow = tb2d_own(V, TB), nstrip = (ny + ow - 1) / ow;
+        std::vector<int> pos((size_t)((nx + TX - 1) / TX) * nstrip, -1);
+        for (size_t q = 0; q < in.size(); ++q) pos[(size_t)(in[q].i0 / TX) * nstrip + in[q].ja / ow] = (int)q;
+        std::vector<int> tl(probe_cells.size());
+        for (size_t q = 0; q < probe_cells.size(); ++q) {
+            const int i = (int)(probe_cells[q] / ny), j = (int)(probe_cells[q] % ny);
+            tl[q] = pos[(size_t)(i / TX) * nstrip + j / ow];
+        }
+        std::vector<int> ord(probe_cells.size());
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int)q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return tl[u] < tl[v]; });
+        std::vector<int> st2(in.size() + 1, 0), ce(ord.size()), sl(ord.size());
+        for (size_t q = 0; q < ord.size(); ++q) {
+            ce[q] = (int)probe_cells[ord[q]];
+            sl[q] = ord[q];
+            st2[(size_t)tl[ord[q]] + 1]++;
+        }
+        for (size_t t = 0; t < in.size(); ++t) st2[t + 1] += st2[t];
+        al.put(pt2_start);
+        al.put(pt2_cell);
+        al.put(pt2_slot);
+        pt2_start = dev_upload(al, st2.data(), st2.size(), st);
+        pt2_cell = dev_upload(al, ce.data(), std::max<size_t>(ce.size(), 1), st);
+        pt2_slot = dev_upload(al, sl.data(), std::max<size_t>(sl.size(), 1), st);
+    }
+}
+
+Fused2DCfg Sim::single2d() const {
+    if (kcfg.variant == 2) return Fused2DCfg{kcfg.tile[0], kcfg.tile[1]};
+    return Fused2DCfg{ny % 2 == 0 ? 2 : 1, 4};
+}
+
+// TB steps of the 2D grid in one pass: interior tiles without the CPML code,
+// then the tiles near a slab with it
+void Sim::launch_tb2d(int64_t step) {
+    const int V = kcfg.tile[0], TB = kcfg.tile[2];
+    const Prob2D p = prob2d(cur, 1 - cur);
+    const ProbeTiles pt{pt2_start, pt2_cell, pt2_slot};
+    const ProbeTiles po{pt2_start + tb2_inner, pt2_cell, pt2_slot};
+    hip_check(launch_2d_tb(p, nullptr, tb2_dev, tb2_inner, false, mat(), pt, V, TB, nullptr, step, st), "2d multi-step");
+    hip_check(launch_2d_tb(p, nullptr, tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB, nullptr, step, st),
+              "2d multi-step (cpml)");
+    cur = 1 - cur;
+    last_launches += (tb2_inner > 0) + (tb2_outer > 0);
 }
 
 
@@ -360,7 +415,7 @@ void Sim::launch_step(int64_t step) {
     }
     ProbeTiles pt{pt_start, pt_cell, pt_slot};
     if (ndim == 2) {
-        Fused2DCfg c{kcfg.tile[0], kcfg.tile[1]};
+        const Fused2DCfg c = single2d();
         const TileSplit2D sp{tl2_dev, tl2_inner, tl2_dev + tl2_inner, tl2_outer};
         hip_check(launch_2d_fused(prob2d(cur, 1 - cur), c, pt, step, st, nullptr, nullptr, nullptr,
                                   split2d() ? &sp : nullptr),
@@ -414,6 +469,7 @@ void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
 // steps otherwise
 void Sim::advance(int64_t n) {
     const bool two = kcfg.variant == 3 && ndim == 3 && !is_graph;
+    const bool tb2 = kcfg.variant == 3 && ndim == 2 && !is_graph;
     const int64_t inc = probe_cells.empty() ? 0 : 1;
     int64_t q = 0;
     if (two)
@@ -422,6 +478,14 @@ void Sim::advance(int64_t n) {
             n_done += 2;
             n_rec += 2 * inc;
         }
+    if (tb2) {
+        const int TB = kcfg.tile[2];
+        for (; q + TB <= n; q += TB) {
+            launch_tb2d(n_done);
+            n_done += TB;
+            n_rec += TB * inc;
+        }
+    }
     for (; q < n; ++q) {
         launch_step(n_done);
         n_done += 1;
@@ -473,6 +537,8 @@ void Sim::refold(int64_t c0, int64_t c1) {
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
+// rows per tile of the 2D multi-step kernel
+constexpr int kTB2DefaultTX = 32;
 // smallest 3D grid (cells) on which the default takes two steps per pass
 constexpr int64_t kTwoStepMinCells = (int64_t)1 << 23;
 
@@ -493,7 +559,7 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
             // two steps per pass on grids large enough for its interior
             // tiles to dominate; single steps otherwise
             const bool two = c.V == 4 && s.ncell >= kTwoStepMinCells &&
-                             two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo + s.ax[2].hi);
+                             two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo, s.ax[2].hi);
             k.variant = two ? 3 : 2;
             k.tile[0] = c.V;
             return 0;
@@ -507,10 +573,14 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.tb != 0 && k.tb != 1) return false;
     if (k.variant == 1) return true;
     if (k.variant != 2 && k.variant != 3) return false;
-    if (s.ndim == 2) return k.variant == 2 && fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
+    if (s.ndim == 2) {
+        if (k.variant == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
+        return k.tile[3] == 0 && tb2d_supported(s.ny, k.tile[0], k.tile[2], k.tile[1]) &&
+               fused2d_supported(s.nx, s.ny, Fused2DCfg{s.ny % 2 == 0 ? 2 : 1, 4});
+    }
     if (k.tile[1] != 0 || k.tile[3] != 0) return false;
     if (!wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]})) return false;
-    return k.variant == 2 || (k.tile[0] == 4 && two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo + s.ax[2].hi));
+    return k.variant == 2 || (k.tile[0] == 4 && two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo, s.ax[2].hi));
 }
 
 // ---------------------------------------------------------------------------
@@ -922,8 +992,10 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
     s.build_probe_tiles();
     const bool fused3 = s.ndim == 3 && !s.is_graph && s.kcfg.variant >= 2;
     const bool two = fused3 && s.kcfg.variant == 3 && steps >= 2;
-    // one timed unit: a step, or a pair of steps for the two-step pass
-    const int32_t per = two ? 2 : 1;
+    const bool tb2 = s.ndim == 2 && !s.is_graph && s.kcfg.variant == 3 && steps >= s.kcfg.tile[2];
+    // one timed unit: a step, a pair of steps for the 3D two-step pass, or
+    // the TB steps of the 2D multi-step pass
+    const int32_t per = two ? 2 : (tb2 ? s.kcfg.tile[2] : 1);
     const int32_t units = steps / per;
     const size_t nl = two ? s.plan2.pass1.l.size() + 1 + s.plan2.pass2.l.size()
                           : (fused3 ? s.plan3.l.size() : 1);
@@ -946,6 +1018,10 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
         s.last_launches = 0;
         if (two) {
             s.launch_pair(s.n_done, e);
+        } else if (tb2) {
+            hip_check(hipEventRecord(e[0], s.st), "event");
+            s.launch_tb2d(s.n_done);
+            hip_check(hipEventRecord(e[1], s.st), "event");
         } else {
             if (fused3) s.lev = e;
             else hip_check(hipEventRecord(e[0], s.st), "event");
@@ -999,7 +1075,7 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
             for (int a = 0; a < NPSI3; ++a) o.psi += s.psi_len[a];
             o.cpml = -1;
             o.launches = (int32_t)launches;
-            o.steps = 1;
+            o.steps = per;
         }
     }
     return FDTD_OK;
@@ -1162,6 +1238,10 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
     if (k.tb == 0) k.tb = 1;
     if (k.variant == 0) {
         default_variant_tiles(s, k);
+    } else if (s.ndim == 2 && k.variant == 3) {
+        if (k.tile[0] == 0) k.tile[0] = s.ny % 4 == 0 ? 4 : 2;
+        if (k.tile[1] == 0) k.tile[1] = kTB2DefaultTX;
+        if (k.tile[2] == 0) k.tile[2] = 2;
     } else if (k.variant == 2 || k.variant == 3) {
         fdtd_kernel_config d;
         default_variant_tiles(s, d);
@@ -1194,7 +1274,7 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     Sim &s = sim->s;
     if (s.is_graph) fail(FDTD_EINVAL, "autotune applies to the implicit-graph stepper");
     if (trial_steps < 2) trial_steps = 2;
-    trial_steps += trial_steps % 2;  // whole pairs for the two-step pass
+    trial_steps = (trial_steps + 3) / 4 * 4;  // whole passes of the multi-step kernels
     const std::string key = tune_key(s);
     const char *path = std::getenv("GEMFDTD_TUNE_CACHE");
     std::map<std::string, std::vector<int>> cache;
@@ -1225,6 +1305,17 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 k.tb = 1;
                 if (config_ok(s, k)) cand.push_back(k);
             }
+        for (int V : {2, 4})
+            for (int TB : {2, 4})
+                for (int TX : {16, 32, 64}) {
+                    fdtd_kernel_config k{};
+                    k.variant = 3;
+                    k.tile[0] = V;
+                    k.tile[1] = TX;
+                    k.tile[2] = TB;
+                    k.tb = 1;
+                    if (config_ok(s, k)) cand.push_back(k);
+                }
     } else {
         for (int TX : {8, 16, 32})
             for (int V : {1, 2, 4}) {
@@ -1272,15 +1363,15 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     const fdtd_kernel_config k0 = s.kcfg;
     float best = 1e30f;
     fdtd_kernel_config bestk = k0;
-    s.ensure_source(s.n_done + 2 * trial_steps + 2);
-    s.ensure_rec(s.n_rec + 2 * trial_steps + 2);
+    s.ensure_source(s.n_done + trial_steps + 4);
+    s.ensure_rec(s.n_rec + trial_steps + 4);
     for (auto &k : cand) {
         s.kcfg = k;
         s.pt_ntiles = -1;
         s.build_probe_tiles();
         s.n_done = n_done0;
         s.n_rec = n_rec0;
-        s.advance(2);  // warm-up
+        s.advance(4);  // warm-up
         hip_check(hipEventRecord(s.ev0, s.st), "event");
         s.advance(trial_steps);
         hip_check(hipEventRecord(s.ev1, s.st), "event");

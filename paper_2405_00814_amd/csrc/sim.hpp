@@ -103,6 +103,15 @@ struct Sim {
     int *tl2_dev = nullptr;
     int tl2_inner = 0, tl2_outer = 0;
     bool split2d() const { return (int64_t)nx * ny >= (int64_t)4 << 20; }
+    // single-step 2D configuration (variant 2's tiles; the default one for
+    // the remainder steps of variant 3)
+    Fused2DCfg single2d() const;
+    // 2D, TB steps per pass (variant 3: tile[0] = V, tile[1] = TX, tile[2] =
+    // TB): tiles clear of the slabs, then the others, and their probe groups
+    Tile2T *tb2_dev = nullptr;
+    int tb2_inner = 0, tb2_outer = 0;
+    int *pt2_start = nullptr, *pt2_cell = nullptr, *pt2_slot = nullptr;
+    int mat() const { return mumap ? 2 : (lossy ? 1 : 0); }
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
     Tile3 *tl_dev = nullptr;
@@ -154,6 +163,7 @@ struct Sim {
     void build_probe_tiles();
     void launch_step(int64_t step);
     void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
+    void launch_tb2d(int64_t step);
     void advance(int64_t n);
     void alloc_set(int set);
     void zero_state();

@@ -124,7 +124,10 @@ def test_two_step_config_rules():
     with pytest.raises(FdtdError):  # nz % 4 != 0
         s.set_kernel(3, (2,))
     s.close()
-    for shape, npml in (((16, 16, 516), (3,) * 6), ((16, 16, 160), (3, 3, 3, 3, 40, 30))):
+    # nz > 512; more than 64 z-slab cells; a 4-cell z group with cells of
+    # both z slabs
+    for shape, npml in (((16, 16, 516), (3,) * 6), ((16, 16, 160), (3, 3, 3, 3, 40, 30)),
+                        ((16, 16, 16), (3, 3, 3, 3, 9, 6))):
         pb = W.yee3d(shape=shape, steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
                      tau_steps=4.0)
         pb.npml = npml
