@@ -2,14 +2,17 @@
 //
 // Every problem keeps its own double-buffered state and coefficient tables
 // (a Sim).  Problems are grouped by the vector width their row length
-// allows (2 floats per lane for even rows, 1 for odd ones); each group has one
-// flat list of wavefront tiles over all of its problems, interior tiles first
-// and CPML-slab tiles after them, so two launches per group (without and with
-// the CPML code) advance every problem by one step, with the load spread
-// evenly over the tiles whatever the mix of sizes.  Launches read the step
-// number from a device counter, which lets a captured HIP graph of
-// GRAPH_STEPS steps be replayed for any step range.
+// allows; each group has one flat list of wavefront tiles over all of its
+// problems, interior tiles first and CPML-slab tiles after them, so two
+// launches per group (without and with the CPML code) advance every problem,
+// with the load spread evenly over the tiles whatever the mix of sizes.
+// The main path is the multi-step kernel (TB steps per pass, groups of
+// vector width 4, 2 and 1); single-step groups (width 2 and 1) take the
+// remainder steps and align the buffer parity.  Launches read the step
+// number from a device counter, which lets a captured HIP graph of passes be
+// replayed for any step range.
 #include <algorithm>
+#include <map>
 #include <memory>
 
 #include "sim.hpp"
@@ -27,6 +30,17 @@ struct BatchGroup {
     int n_inner = 0;             // list: interior tiles, then slab tiles
 };
 
+// Multi-step group: the problems whose row length the vector width divides.
+struct TBGroup {
+    int V = 4, TB = 4, TX = 16, mat = 0;
+    std::vector<int> probs;
+    Tile2T *tiles = nullptr;
+    int ntiles = 0, n_inner = 0;
+    int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
+    std::vector<int> pos_base;  // per problem of the group: first entry in pos
+    std::vector<int> pos;       // (problem, row chunk, strip) -> place in the list
+};
+
 }  // namespace gem
 
 struct fdtd_batch {
@@ -36,6 +50,9 @@ struct fdtd_batch {
     hipStream_t cap_st = nullptr;
     gem::DevAlloc al;
     std::vector<gem::BatchGroup> groups;
+    std::vector<gem::TBGroup> tbg;
+    int tb = 4;   // steps per multi-step pass (1: single steps only)
+    int cur = 0;  // buffer set holding the current state
     gem::Prob2D *probs_dev[2] = {nullptr, nullptr};
     std::vector<const void *> probs_key[2];
     int64_t *step_base = nullptr;
@@ -80,6 +97,43 @@ static void batch_build_probes(fdtd_batch &b) {
                 const int i = (int)(s.probe_cells[p] / s.ny), j = (int)(s.probe_cells[p] % s.ny);
                 ent.push_back({g.pos[(size_t)(g.tile_base[qi] + fused2d_tile_of(s.nx, s.ny, c, i, j))],
                                (int)cells_all.size()});
+                cells_all.push_back((int)s.probe_cells[p]);
+                slots_all.push_back((int)p);
+            }
+        }
+        std::stable_sort(ent.begin(), ent.end());
+        std::vector<int> start((size_t)g.ntiles + 1, 0);
+        for (auto &e : ent) {
+            start[(size_t)e.first + 1]++;
+            cell.push_back(cells_all[(size_t)e.second]);
+            slot.push_back(slots_all[(size_t)e.second]);
+        }
+        for (int t = 0; t < g.ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
+        if (cell.empty()) {
+            cell.push_back(0);
+            slot.push_back(0);
+        }
+        b.al.put(g.pt_start);
+        b.al.put(g.pt_cell);
+        b.al.put(g.pt_slot);
+        g.pt_start = (int *)b.al.get(start.size() * 4);
+        g.pt_cell = (int *)b.al.get(cell.size() * 4);
+        g.pt_slot = (int *)b.al.get(slot.size() * 4);
+        hip_check(hipMemcpyAsync(g.pt_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipMemcpyAsync(g.pt_cell, cell.data(), cell.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipMemcpyAsync(g.pt_slot, slot.data(), slot.size() * 4, hipMemcpyHostToDevice, b.st), "upload");
+        hip_check(hipStreamSynchronize(b.st), "sync");
+    }
+    for (auto &g : b.tbg) {
+        std::vector<std::pair<int, int>> ent;  // (tile, index)
+        std::vector<int> cells_all, slots_all, cell, slot;
+        const int ow = tb2d_own(g.V, g.TB);
+        for (size_t qi = 0; qi < g.probs.size(); ++qi) {
+            const Sim &s = *b.sims[(size_t)g.probs[qi]];
+            const int nstrip = (s.ny + ow - 1) / ow;
+            for (size_t p = 0; p < s.probe_cells.size(); ++p) {
+                const int i = (int)(s.probe_cells[p] / s.ny), j = (int)(s.probe_cells[p] % s.ny);
+                ent.push_back({g.pos[(size_t)(g.pos_base[qi] + (i / g.TX) * nstrip + j / ow)], (int)cells_all.size()});
                 cells_all.push_back((int)s.probe_cells[p]);
                 slots_all.push_back((int)p);
             }
@@ -155,11 +209,32 @@ static void batch_launch_one(fdtd_batch &b, int parity, int k, hipStream_t st) {
     }
 }
 
+// one multi-step pass (b.tb steps) of every problem, reading set `parity`
+static void batch_launch_pass(fdtd_batch &b, int parity, int k, hipStream_t st) {
+    const Prob2D none{};
+    for (auto &g : b.tbg) {
+        const ProbeTiles pt{g.pt_start, g.pt_cell, g.pt_slot};
+        const ProbeTiles po{g.pt_start + g.n_inner, g.pt_cell, g.pt_slot};
+        hip_check(launch_2d_tb(none, b.probs_dev[parity], g.tiles, g.n_inner, false, g.mat, pt, g.V, g.TB,
+                               b.step_base, k, st),
+                  "batch pass");
+        hip_check(launch_2d_tb(none, b.probs_dev[parity], g.tiles + g.n_inner, g.ntiles - g.n_inner, true, g.mat,
+                               po, g.V, g.TB, b.step_base, k, st),
+                  "batch pass");
+    }
+}
+
+// graph_steps steps from buffer set 0: passes of b.tb steps (an even number
+// of them), or single steps
 static void batch_capture(fdtd_batch &b) {
     if (b.exec) return;
     if (!b.cap_st) hip_check(hipStreamCreateWithFlags(&b.cap_st, hipStreamNonBlocking), "stream");
     hip_check(hipStreamBeginCapture(b.cap_st, hipStreamCaptureModeRelaxed), "begin capture");
-    for (int k = 0; k < b.graph_steps; ++k) batch_launch_one(b, k & 1, k, b.cap_st);
+    if (b.tb > 1) {
+        for (int k = 0; k < b.graph_steps / b.tb; ++k) batch_launch_pass(b, k & 1, k * b.tb, b.cap_st);
+    } else {
+        for (int k = 0; k < b.graph_steps; ++k) batch_launch_one(b, k & 1, k, b.cap_st);
+    }
     hip_check(launch_advance(b.step_base, b.graph_steps, b.cap_st), "advance");
     hip_check(hipStreamEndCapture(b.cap_st, &b.graph), "end capture");
     hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "instantiate");
@@ -248,6 +323,50 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
             hip_check(hipStreamSynchronize(b->st), "sync");
             b->groups.push_back(g);
         }
+        // multi-step groups: vector width 4, 2 or 1 by row length
+        for (int V : {4, 2, 1}) {
+            TBGroup g;
+            g.V = V;
+            g.TB = b->tb;
+            std::vector<Tile2T> in, out, all;
+            for (int q = 0; q < n; ++q) {
+                const Sim &s = *b->sims[(size_t)q];
+                const int vq = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
+                if (vq != V) continue;
+                if (!tb2d_supported(s.ny, V, g.TB, g.TX)) fail(FDTD_EINVAL, "multi-step configuration");
+                g.probs.push_back(q);
+                g.mat = std::max(g.mat, s.mat());
+                g.pos_base.push_back((int)all.size());
+                std::vector<Tile2T> a, c;
+                const int xl[2] = {s.ax[0].lo, s.ax[0].hi}, yl[2] = {s.ax[1].lo, s.ax[1].hi};
+                tb2d_plan(q, s.nx, s.ny, V, g.TB, g.TX, xl, yl, a, c);
+                // problem-order list (row chunk by row chunk, strips inside)
+                const int ow = tb2d_own(V, g.TB), nstrip = (s.ny + ow - 1) / ow;
+                std::vector<Tile2T> po((size_t)((s.nx + g.TX - 1) / g.TX) * nstrip);
+                for (const auto &t : a) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
+                for (const auto &t : c) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
+                for (const auto &t : po) all.push_back(t);
+                in.insert(in.end(), a.begin(), a.end());
+                out.insert(out.end(), c.begin(), c.end());
+            }
+            if (g.probs.empty()) continue;
+            // place of each problem-order tile in the launch list
+            g.n_inner = (int)in.size();
+            g.ntiles = (int)(in.size() + out.size());
+            {
+                std::map<std::pair<int, std::pair<int, int>>, int> at;
+                for (size_t t = 0; t < in.size(); ++t) at[{in[t].prob, {in[t].i0, in[t].ja}}] = (int)t;
+                for (size_t t = 0; t < out.size(); ++t) at[{out[t].prob, {out[t].i0, out[t].ja}}] = g.n_inner + (int)t;
+                g.pos.resize(all.size());
+                for (size_t t = 0; t < all.size(); ++t) g.pos[t] = at[{all[t].prob, {all[t].i0, all[t].ja}}];
+            }
+            in.insert(in.end(), out.begin(), out.end());
+            g.tiles = (Tile2T *)b->al.get(in.size() * sizeof(Tile2T));
+            hip_check(hipMemcpyAsync(g.tiles, in.data(), in.size() * sizeof(Tile2T), hipMemcpyHostToDevice, b->st),
+                      "upload");
+            hip_check(hipStreamSynchronize(b->st), "sync");
+            b->tbg.push_back(g);
+        }
         b->step_base = (int64_t *)b->al.get(sizeof(int64_t));
         hip_check(hipEventCreate(&b->ev0), "event");
         hip_check(hipEventCreate(&b->ev1), "event");
@@ -309,25 +428,36 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n) {
         hip_check(hipStreamSynchronize(b->st), "sync");
         b->last_launches = 0;
         hip_check(hipEventRecord(b->ev0, b->st), "event");
-        int64_t k = 0;
-        int64_t ng = 0;  // launches per step
+        int64_t ng = 0, np = 0;  // launches per single step, per pass
         for (const auto &g : b->groups) ng += (g.n_inner > 0) + (g.ntiles > g.n_inner);
-        // align to an even step so that graph replays start on buffer set 0
-        while (k < n && ((b->n_done + k) & 1)) {
-            batch_launch_one(*b, (int)((b->n_done + k) & 1), (int)k, b->st);
+        for (const auto &g : b->tbg) np += (g.n_inner > 0) + (g.ntiles > g.n_inner);
+        const int tb = b->tb;
+        int64_t k = 0;
+        // graph replays start on buffer set 0
+        if (n > 0 && b->cur == 1) {
+            batch_launch_one(*b, 1, 0, b->st);
+            b->cur = 0;
             b->last_launches += ng;
-            ++k;
+            k = 1;
         }
         if (k > 0) hip_check(launch_advance(b->step_base, k, b->st), "advance");
         const int64_t reps = b->use_graph ? (n - k) / b->graph_steps : 0;
         if (reps > 0) {
             batch_capture(*b);
             for (int64_t r = 0; r < reps; ++r) hip_check(hipGraphLaunch(b->exec, b->st), "graph launch");
-            b->last_launches += reps * (b->graph_steps * ng + 1);
+            b->last_launches += reps * ((tb > 1 ? (b->graph_steps / tb) * np : b->graph_steps * ng) + 1);
         }
         const int64_t k2 = k + reps * b->graph_steps;
-        for (int64_t q = k2; q < n; ++q) {
-            batch_launch_one(*b, (int)((b->n_done + q) & 1), (int)(q - k2), b->st);
+        int64_t q = k2;
+        if (tb > 1)
+            for (; q + tb <= n; q += tb) {
+                batch_launch_pass(*b, b->cur, (int)(q - k2), b->st);
+                b->cur ^= 1;
+                b->last_launches += np;
+            }
+        for (; q < n; ++q) {
+            batch_launch_one(*b, b->cur, (int)(q - k2), b->st);
+            b->cur ^= 1;
             b->last_launches += ng;
         }
         hip_check(hipEventRecord(b->ev1, b->st), "event");
@@ -336,7 +466,7 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n) {
         for (auto &sp : b->sims) {
             sp->n_done = b->n_done;
             if (!sp->probe_cells.empty()) sp->n_rec += n;
-            sp->cur = (int)(b->n_done & 1);
+            sp->cur = b->cur;
         }
         return FDTD_OK;
     } catch (...) {

@@ -290,7 +290,9 @@ hipError_t launch_2d_tb(const Prob2D &p, const Prob2D *probs_dev, const Tile2T *
     if (ntiles <= 0) return hipSuccess;
     if (!probs_dev && p.ny % V != 0) return hipErrorInvalidValue;
     if (mat < 0 || mat > 2) return hipErrorInvalidValue;
-    if (V == 2 && TB == 2) go_tb_m<2, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
+    if (V == 1 && TB == 2) go_tb_m<1, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
+    else if (V == 1 && TB == 4) go_tb_m<1, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
+    else if (V == 2 && TB == 2) go_tb_m<2, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
     else if (V == 2 && TB == 4) go_tb_m<2, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
     else if (V == 4 && TB == 2) go_tb_m<4, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
     else if (V == 4 && TB == 4) go_tb_m<4, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);

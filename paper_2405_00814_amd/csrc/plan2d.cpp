@@ -7,7 +7,7 @@
 namespace gem {
 
 bool tb2d_supported(int ny, int V, int TB, int TX) {
-    if (!(V == 2 || V == 4) || !(TB == 2 || TB == 4)) return false;
+    if (!(V == 1 || V == 2 || V == 4) || !(TB == 2 || TB == 4)) return false;
     if (TX < 1 || TX > 65536) return false;
     return ny % V == 0;
 }

@@ -537,8 +537,10 @@ void Sim::refold(int64_t c0, int64_t c1) {
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
-// rows per tile of the 2D multi-step kernel
-constexpr int kTB2DefaultTX = 32;
+// rows per tile of the 2D multi-step kernel, and the smallest 2D grid
+// (cells) on which the default takes it
+constexpr int kTB2DefaultTX = 8;
+constexpr int64_t kTB2MinCells = (int64_t)1 << 21;
 // smallest 3D grid (cells) on which the default takes two steps per pass
 constexpr int64_t kTwoStepMinCells = (int64_t)1 << 23;
 
@@ -546,6 +548,16 @@ static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
     if (s.ndim == 2) {
+        // several steps per pass on grids large enough to fill the chip
+        // with short tiles; single steps otherwise
+        const int vt = s.ny % 2 == 0 ? 2 : 1;
+        if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, kTB2DefaultTX)) {
+            k.variant = 3;
+            k.tile[0] = vt;
+            k.tile[1] = kTB2DefaultTX;
+            k.tile[2] = 4;
+            return 0;
+        }
         Fused2DCfg c{s.ny % 2 == 0 ? 2 : 1, 4};
         if (fused2d_supported(s.nx, s.ny, c)) {
             k.variant = 2;
@@ -1239,7 +1251,7 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
     if (k.variant == 0) {
         default_variant_tiles(s, k);
     } else if (s.ndim == 2 && k.variant == 3) {
-        if (k.tile[0] == 0) k.tile[0] = s.ny % 4 == 0 ? 4 : 2;
+        if (k.tile[0] == 0) k.tile[0] = s.ny % 2 == 0 ? 2 : 1;
         if (k.tile[1] == 0) k.tile[1] = kTB2DefaultTX;
         if (k.tile[2] == 0) k.tile[2] = 2;
     } else if (k.variant == 2 || k.variant == 3) {
@@ -1305,9 +1317,9 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 k.tb = 1;
                 if (config_ok(s, k)) cand.push_back(k);
             }
-        for (int V : {2, 4})
+        for (int V : {1, 2, 4})
             for (int TB : {2, 4})
-                for (int TX : {16, 32, 64}) {
+                for (int TX : {4, 8, 16}) {
                     fdtd_kernel_config k{};
                     k.variant = 3;
                     k.tile[0] = V;

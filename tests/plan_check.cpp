@@ -7,8 +7,12 @@
 //    rows j0-2 .. j0+nrows) clear of the x/y slabs; two-step tiles and the
 //    second pass cover every cell exactly once; the first pass covers every
 //    cell of the second pass and every (x, y) neighbour of one, once, with
-//    probes recorded exactly on the second pass's cells.
+//    probes recorded exactly on the second pass's cells;
+//  * 2D multi-step plan: the tiles' own rows and columns cover the grid
+//    once; interior tiles' cones (TB rows and the halo lanes' columns around
+//    them) clear of the slabs.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
@@ -96,6 +100,34 @@ int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl
         }
     return 0;
 }
+// 2D multi-step plan: own columns [ja, ja + own) and rows [i0, i1) of the
+// tiles cover the grid once; interior tiles' cones clear of the slabs
+int check2d(int nx, int ny, int V, int TB, int TX, const int *xl, const int *yl) {
+    std::vector<Tile2T> in, out;
+    tb2d_plan(7, nx, ny, V, TB, TX, xl, yl, in, out);
+    std::vector<int> cov((size_t)nx * ny, 0);
+    const int ow = tb2d_own(V, TB), hw = tb2d_halo(V, TB) * V;
+    for (int pass = 0; pass < 2; ++pass)
+        for (const Tile2T &t : pass ? out : in) {
+            if (t.prob != 7 || t.i0 < 0 || t.i1 > nx || t.i0 >= t.i1 || t.i1 - t.i0 > TX || t.ja < 0 || t.ja >= ny ||
+                t.ja % V) {
+                printf("bad 2d tile\n");
+                return 1;
+            }
+            if (pass == 0) {
+                for (int i = t.i0 - TB; i < t.i1 + TB; ++i)
+                    if (inslab(nx, xl[0], xl[1], i)) { printf("2d interior cone touches x slab\n"); return 1; }
+                for (int j = t.ja - hw; j < t.ja - hw + 64 * V; ++j)
+                    if (inslab(ny, yl[0], yl[1], j)) { printf("2d interior cone touches y slab\n"); return 1; }
+            }
+            for (int i = t.i0; i < t.i1; ++i)
+                for (int j = t.ja; j < std::min(ny, t.ja + ow); ++j) cov[(size_t)i * ny + j]++;
+        }
+    for (int c : cov)
+        if (c != 1) { printf("2d coverage %d\n", c); return 1; }
+    return 0;
+}
+
 int main() {
     int bad = 0, n = 0;
     // two-step support rule: nz % 4, nz <= 512, at most 64 slab cells, no
@@ -128,6 +160,17 @@ int main() {
         r = check2(nx, ny, nz2, TX, mat, s, s + 2, s + 4);
         if (r) printf("  two case nx %d ny %d nz %d TX %d mat %d s %d %d %d %d %d %d\n", nx, ny, nz2, TX, mat, s[0], s[1], s[2], s[3], s[4], s[5]);
         bad += r; ++n;
+    }
+    for (int t = 0; t < 2000; ++t) {
+        const int V = 1 << (rand() % 3), TB = rand() % 2 ? 2 : 4;
+        const int nx = 1 + rand() % 300, ny = V * (1 + rand() % 200), TX = 1 + rand() % 40;
+        int s[4];
+        for (int q = 0; q < 4; ++q) s[q] = rand() % 3 == 0 ? 0 : rand() % 20;
+        if (s[0] + s[1] >= nx) s[0] = s[1] = 0;
+        if (s[2] + s[3] >= ny) s[2] = s[3] = 0;
+        const int r = check2d(nx, ny, V, TB, TX, s, s + 2);
+        if (r) printf("  2d case nx %d ny %d V %d TB %d TX %d s %d %d %d %d\n", nx, ny, V, TB, TX, s[0], s[1], s[2], s[3]);
+        bad += r;
     }
     printf("%d / %d bad\n", bad, n);
     return bad != 0;

@@ -70,8 +70,9 @@ def test_batch_matches_single_and_oracle():
     log("batch shapes", shapes)
     assert len({s[1] % 4 for s in shapes}) >= 2      # several vector widths
     b = Batch(probs)
-    b.step(37)      # odd start: aligns, then graph replays
-    b.step(150)
+    b.step(3)       # single steps only (fewer than one multi-step pass)
+    b.step(34)      # starts on the other buffer set: one aligning step, passes, a single step
+    b.step(150)     # graph replays of passes, then passes and single steps
     n = 187
     for q, pb in enumerate(probs):
         got = {k: b.get_field(q, k) for k in ("ez", "hx", "hy")}

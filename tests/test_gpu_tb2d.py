@@ -95,7 +95,7 @@ def test_tb2d_profile_and_rules():
     for f in ("ez", "hx", "hy"):
         assert np.array_equal(a.get_field(f), b.get_field(f)), f
     assert np.array_equal(a.probe(), b.probe())
-    for bad in ((3, (4, 16, 3)), (3, (8, 16, 2)), (3, (1, 16, 2)), (3, (4, 16, 2, 1))):
+    for bad in ((3, (4, 16, 3)), (3, (8, 16, 2)), (3, (3, 16, 2)), (3, (4, 16, 2, 1))):
         with pytest.raises(FdtdError):
             a.set_kernel(*bad)
     a.close()

@@ -1,6 +1,7 @@
-"""Host logic: the 3D launch plans (single-step and two-steps-per-pass) cover
-every cell as the kernels require.  Builds tests/plan_check.cpp with the
-library's plan source (host code only) and runs it on random grids."""
+"""Host logic: the launch plans (3D single-step and two-steps-per-pass, 2D
+multi-step) cover every cell as the kernels require.  Builds
+tests/plan_check.cpp with the library's plan sources (host code only) and
+runs it on random grids."""
 import os
 import shutil
 import subprocess
@@ -18,7 +19,7 @@ def test_plan_coverage(tmp_path):
     exe = str(tmp_path / "plan_check")
     cmd = [HIPCC, "-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I",
            os.path.join(ROOT, "include"), os.path.join(HERE, "plan_check.cpp"),
-           os.path.join(CSRC, "plan3d.cpp"), "-o", exe]
+           os.path.join(CSRC, "plan3d.cpp"), os.path.join(CSRC, "plan2d.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
