@@ -141,11 +141,16 @@ def bench_2d(args, steps=10000):
     sim = Sim.from_problem(pb)
     t, wall, launches = timed_steps(sim, steps, 20)
     ab = alg_bytes_implicit(pb.cells, psi_floats_of(pb), 3, ncoef_of(pb))
+    k = sim.get_kernel()
+    tb = k["tile"][2] if k["variant"] == 3 else 1
+    # hbm_frac: algorithmic bytes per cell-update x cell-updates/s; a pass of
+    # tb steps moves one step's bytes, so pass_frac is the memory-side view
     out = dict(workload="dielectric2d_4096x4096_cpml16_200rects", steps=steps,
-               kernel=sim.get_kernel(), gcells_per_s=pb.cells * steps / t / 1e9,
+               kernel=k, steps_per_pass=tb, gcells_per_s=pb.cells * steps / t / 1e9,
                bytes_per_cell_update=ab / pb.cells,
                achieved_GBps=ab * steps / t / 1e9,
-               hbm_frac=ab * steps / t / PEAK_HBM)
+               hbm_frac=ab * steps / t / PEAK_HBM,
+               pass_frac=ab * steps / tb / t / PEAK_HBM)
     sim.close()
     # explicit graph form on the same grid
     g = Sim.from_problem(pb, graph=True)
@@ -203,8 +208,8 @@ def bench_batch(args, steps=500):
         s.close()
     ab = sum(alg_bytes_implicit(p.cells, psi_floats_of(p), 3, ncoef_of(p)) for p in probs)
     return dict(workload="batch2d_256_problems_sides_256_2048_cpml16", problems=len(probs),
-                cells=cells, steps=steps, gcells_per_s=cells * steps / tb / 1e9,
-                hbm_frac=ab * steps / tb / PEAK_HBM,
+                cells=cells, steps=steps, steps_per_pass=4, gcells_per_s=cells * steps / tb / 1e9,
+                hbm_frac=ab * steps / tb / PEAK_HBM, pass_frac=ab * steps / 4 / tb / PEAK_HBM,
                 plain_sequential_gcells_per_s=cells * steps / tp / 1e9,
                 speedup_vs_plain=tp / tb, launches=lb, finite=bool(ok))
 

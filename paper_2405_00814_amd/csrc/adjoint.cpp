@@ -71,13 +71,16 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         const int64_t nd = (int64_t)(i1 - i0) * (j1 - j0);
         const int64_t P = (int64_t)s.probe_cells.size();
 
-        // the recompute captures design values from the fused kernel
+        // the recompute captures design values from the fused single-step
+        // kernel; the adjoint step takes the same tiles.  Unless chosen
+        // explicitly: one column per lane below 4M cells (more wavefronts
+        // for the chip), else two.
         saved = s.kcfg;
         restore_cfg = true;
-        if (s.kcfg.variant != 2) {
+        if (s.kcfg.variant != 2 || !s.kcfg_explicit) {
             s.kcfg = fdtd_kernel_config{};
             s.kcfg.variant = 2;
-            s.kcfg.tile[0] = s.ny % 2 == 0 ? 2 : 1;
+            s.kcfg.tile[0] = (s.ncell >= ((int64_t)4 << 20) && s.ny % 2 == 0) ? 2 : 1;
             s.kcfg.tile[1] = 4;
             s.kcfg.tb = 1;
         }
@@ -117,20 +120,19 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
                 const double v = rec[(size_t)(p * T + m - 1)];
                 loss += v * v;
             }
-        // ---- adjoint buffers ----
-        Adj2D a{};
+        // ---- adjoint buffers (double buffered, zero-filled) ----
+        Adj2D a[2]{};
         const size_t cb = (size_t)s.ncell * 4;
-        a.ez = (float *)get(cb);
-        a.hx = (float *)get(cb);
-        a.hy = (float *)get(cb);
-        a.gx = (float *)get(cb);
-        a.gy = (float *)get(cb);
-        a.ex = (float *)get(cb);
-        a.ey = (float *)get(cb);
-        a.psi_hx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[0]) * 4);
-        a.psi_hy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[1]) * 4);
-        a.psi_ezx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[2]) * 4);
-        a.psi_ezy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[3]) * 4);
+        for (Adj2D &x : a) {
+            x.ez = (float *)get(cb);
+            x.hx = (float *)get(cb);
+            x.hy = (float *)get(cb);
+            x.psi_hx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[0]) * 4);
+            x.psi_hy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[1]) * 4);
+            x.psi_ezx = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[2]) * 4);
+            x.psi_ezy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[3]) * 4);
+        }
+        int acur = 0;
         double *grad = (double *)get((size_t)nd * 8);
         float *cap_ez = (float *)get((size_t)(L * nd) * 4);
         float *cap_br = (float *)get((size_t)(L * nd) * 4);
@@ -151,24 +153,24 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         float *dcb = (float *)get((size_t)nd * 4);
         hip_check(hipMemcpyAsync(dca, hdca.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipMemcpyAsync(dcb, hdcb.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
-        // probes grouped per block of 256 cells (for the loss seed)
-        const int64_t nb = (s.ncell + 255) / 256;
-        std::vector<int> pst((size_t)nb + 1, 0), pcell, pslot;
+        // probed cells (sorted) and their probe entries, for the loss seed
+        std::vector<int> ust, pcell, pslot;
         {
             std::vector<std::pair<int64_t, int>> e;
             for (int64_t p = 0; p < P; ++p) e.push_back({s.probe_cells[(size_t)p], (int)p});
             std::sort(e.begin(), e.end());
-            for (auto &x : e) {
-                pst[(size_t)(x.first / 256) + 1]++;
-                pcell.push_back((int)x.first);
-                pslot.push_back(x.second);
+            for (size_t q = 0; q < e.size(); ++q) {
+                if (q == 0 || e[q].first != e[q - 1].first) ust.push_back((int)q);
+                pcell.push_back((int)e[q].first);
+                pslot.push_back(e[q].second);
             }
-            for (int64_t b = 0; b < nb; ++b) pst[(size_t)b + 1] += pst[(size_t)b];
+            ust.push_back((int)e.size());
         }
-        int *d_pst = (int *)get(pst.size() * 4);
+        const int nu = (int)ust.size() - 1;
+        int *d_ust = (int *)get(ust.size() * 4);
         int *d_pcell = (int *)get(pcell.size() * 4);
         int *d_pslot = (int *)get(pslot.size() * 4);
-        hip_check(hipMemcpyAsync(d_pst, pst.data(), pst.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(d_ust, ust.data(), ust.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipMemcpyAsync(d_pcell, pcell.data(), pcell.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipMemcpyAsync(d_pslot, pslot.data(), pslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipStreamSynchronize(s.st), "sync");
@@ -195,10 +197,11 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
             const Prob2D p = s.prob2d(0, 0);
             for (int64_t k = k1 - 1; k >= k0; --k) {
                 const int seed = (k + 1 > n0 && k + 1 <= n1) ? 1 : 0;
-                hip_check(launch_adj2d(p, a, k, dbox, cap_ez + (k - k0) * nd, cap_br + (k - k0) * nd,
-                                       dca, dcb, grad, seed, d_pst, d_pcell, d_pslot, s.rec_dev,
-                                       s.rec_cap, s.st),
+                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], k, dbox, cap_ez + (k - k0) * nd,
+                                             cap_br + (k - k0) * nd, dca, dcb, grad, seed, d_ust, d_pcell,
+                                             d_pslot, nu, s.rec_dev, s.rec_cap, fc.V, fc.TX, s.st),
                           "adjoint step");
+                acur = 1 - acur;
             }
         }
         hip_check(launch_grad_to_float(grad, grad_dev, nd, s.st), "gradient");
@@ -209,7 +212,7 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         s.n_rec = T;
         hip_check(hipEventRecord(s.ev1, s.st), "event");
         s.timed = true;
-        s.last_launches = T * 2 + T * 3;
+        s.last_launches = T * 3 + (n1 - n0);
         hip_check(hipStreamSynchronize(s.st), "sync");
         for (void *p : tmp) s.al.put(p);
         tmp.clear();

@@ -227,17 +227,21 @@ hipError_t launch_batch_step(const Prob2D *probs_dev, const BatchTile *tiles, in
                              int k, hipStream_t st);
 hipError_t launch_advance(int64_t *step_base, int64_t by, hipStream_t st);
 
-// Adjoint 2D kernels (see adjoint.hip).
+// Adjoint state of the 2D step (kadj.hip).
 struct Adj2D {
     float *ez, *hx, *hy, *psi_hx, *psi_hy, *psi_ezx, *psi_ezy;
-    float *gx, *gy, *ex, *ey;   // full-grid temporaries
 };
-hipError_t launch_adj2d(const Prob2D &p, const Adj2D &a, int64_t k, const int *design,
-                        const float *cap_ez, const float *cap_br, const float *dca,
-                        const float *dcb, double *grad, int seed_on, const int *pb_start,
-                        const int *pb_cell, const int *pb_slot, const float *rec,
-                        int64_t rec_stride, hipStream_t st);
 hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st);
+// One adjoint step in one pass: reads the adjoint state l0 (step k+1; the
+// probe seed of step k+1 is added to l0.ez first when seed_on: nu probed
+// cells, probe entries [seed_start[u], seed_start[u+1]) at cell u), writes l1
+// (step k), accumulates the gradient at the design cells.  Tiles of TX rows
+// by 64*V columns; ny % V == 0.
+hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, int64_t k, const int *design,
+                              const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
+                              double *grad, int seed_on, const int *seed_start, const int *seed_cell,
+                              const int *seed_slot, int nu, const float *rec, int64_t rec_stride, int V, int TX,
+                              hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Errors

@@ -1,13 +1,12 @@
 // Discrete adjoint of the 2D TMz step (transposed message passing run
 // backward in time).  One backward step applies the transpose of the E
-// layer, then the transpose of the H layer, to the adjoint state
-// (lEz, lHx, lHy and the adjoint CPML values), as three in-place gather
-// kernels:
-//   A: per cell, E layer^T pointwise: probe-loss seed, u = Cb*a,
-//      gx/gy temporaries, adjoint psi_E, gradient, lEz <- Ca*a
-//   B: per cell, gather gx/gy into lHx/lHy, then H layer^T pointwise:
-//      ex/ey temporaries and adjoint psi_H
-//   C: per cell, gather ex/ey into lEz
+// layer, then the transpose of the H layer, to the adjoint state (lEz, lHx,
+// lHy and the adjoint CPML values), in three phases per cell:
+//   A: E layer^T pointwise: u = Cb*a (a = lEz with the probe-loss seed),
+//      messages gx, gy to the H nodes, adjoint psi_E, gradient, lEz <- Ca*a
+//   B: gather gx/gy into lHx/lHy, then H layer^T pointwise: messages ex, ey
+//      to the E nodes and adjoint psi_H
+//   C: gather ex/ey into lEz
 // (E layer^T: each E node sends Cb-weighted messages back to the H nodes it
 // gathered from; H layer^T likewise back to the E nodes.)  The 1/d factors
 // are folded in the axis tables exactly as in the forward kernels.
@@ -15,145 +14,304 @@
 
 namespace gem {
 
-struct AdjArgs {
-    Prob2D p;          // forward problem (coefficients, axis tables)
-    Adj2D a;
-    int4 design;       // [i0,i1) x [j0,j1)
-    const float *cap_ez;   // Ez^k at design cells (before the E layer of step k)
-    const float *cap_br;   // bracket of the E layer of step k at design cells
-    const float *dca, *dcb;
+// ---------------------------------------------------------------------------
+// Fused adjoint step: the three phases above in one pass over memory, by the
+// forward kernel's tiling (a wavefront marches TX rows of a 64*V column
+// strip).  Double buffered: the adjoint state of step k+1 is read from L0,
+// that of step k written to L1.  At row i the wavefront has phase A of rows i
+// (carried) and i+1, phase B of rows i-1 (carried) and i, and writes row i.
+// The strip's edge columns take their neighbours' values by recomputation:
+// phase A's gx at column y0+64V (right of the strip, lane 63) and phase B's
+// ey at column y0-1 (left, lane 0).  The probe-loss seed is added to L0 by a
+// separate launch first.
+// ---------------------------------------------------------------------------
+struct AdjFArgs {
+    Prob2D p;
+    Adj2D l0, l1;      // adjoint state read (step k+1) and written (step k)
+    int4 design;
+    const float *cap_ez, *cap_br, *dca, *dcb;
     double *grad;
-    // probe-loss seed: lEz[probe] += 2 * Ez^{k+1}[probe] when k+1 in (n0, n1]
-    int seed_on;
-    const int *pb_start;   // per block of 256 cells: probe entries
-    const int *pb_cell;
-    const int *pb_slot;
-    const float *rec;      // forward probe record [np][rec_stride]
-    int64_t rec_stride;
-    int64_t k;
 };
 
-__global__ __launch_bounds__(256) void k_adj_a(AdjArgs A) {
+template <int V>
+__device__ __forceinline__ void ldva(float (&r)[V], const float *p) {
+    if constexpr (V == 4) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
+    } else if constexpr (V == 2) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        r[0] = t.x; r[1] = t.y;
+    } else {
+        r[0] = *p;
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void stva(float *p, const float (&r)[V]) {
+    if constexpr (V == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(r[0], r[1], r[2], r[3]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<float2 *>(p) = make_float2(r[0], r[1]);
+    } else {
+        *p = r[0];
+    }
+}
+
+template <int V, bool PML>
+__global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, int ntiles) {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int tw = ((nb % 8 == 0) ? (b % 8) * (nb / 8) + (b / 8) : b) * 4 + (int)(threadIdx.x >> 6);
+    if (tw >= ntiles) return;  // whole wavefront leaves; no barriers below
     const Prob2D &p = A.p;
-    const int64_t n = (int64_t)p.nx * p.ny;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    const int ny = p.ny;
-    const int i = (int)(c / ny), j = (int)(c - (int64_t)i * ny);
-    float a = A.a.ez[c];
-    if (A.seed_on) {
-        const int b0 = A.pb_start[blockIdx.x], b1 = A.pb_start[blockIdx.x + 1];
-        for (int q = b0; q < b1; ++q)
-            if (A.pb_cell[q] == c) a += 2.f * A.rec[(int64_t)A.pb_slot[q] * A.rec_stride + A.k];
+    const Adj2D &L0 = A.l0, &L1 = A.l1;
+    const int lane = threadIdx.x & 63;
+    const int nx = p.nx, ny = p.ny;
+    const int cx = tw / nsy, sy = tw - cx * nsy;
+    const int x0 = cx * TX, x1 = min(x0 + TX, nx);
+    const int y0 = sy * 64 * V, jb = y0 + lane * V, jend = y0 + 64 * V, jm = y0 - 1;
+    const bool valid = jb < ny;  // ny % V == 0
+    const int syw = p.y.lo + p.y.hi;
+    const int dw = A.design.w - A.design.z;
+
+    float kEy[V], bEy[V], cEy[V], kHy[V], bHy[V], cHy[V];
+    int jj[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int j = valid ? jb + v : 0;
+        kEy[v] = p.y.kE[j]; kHy[v] = p.y.kH[j];
+        bEy[v] = p.y.bE[j]; cEy[v] = p.y.cE[j];
+        bHy[v] = p.y.bH[j]; cHy[v] = p.y.cH[j];
+        jj[v] = (PML && valid) ? slab_index(p.y, j) : -1;
     }
-    float gx = 0.f, gy = 0.f;
-    if (i >= 1 && j >= 1) {
-        const float u = p.cb[c] * a;
-        const int ii = slab_index(p.x, i), jj = slab_index(p.y, j);
-        const int sy = p.y.lo + p.y.hi;
-        float px = u, py = -u;
-        if (ii >= 0) {
-            float *q = A.a.psi_ezx + (int64_t)ii * ny + j;
-            px += *q;
-            *q = p.x.bE[i] * px;
+    auto zero = [](float (&a)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) a[v] = 0.f;
+    };
+    // phase A of row i (own columns): gx, gy messages, Ca-weighted adjoint
+    // Ez; writes the new E-type psi and the gradient when `write`
+    auto phaseA = [&](int i, float (&gx)[V], float (&gy)[V], float (&aca)[V], bool write) {
+        zero(gx); zero(gy); zero(aca);
+        if (i < 0 || i >= nx || !valid) return;
+        const int64_t row = (int64_t)i * ny;
+        float a[V], cb[V], ca[V];
+        ldva<V>(a, L0.ez + row + jb);
+        ldva<V>(cb, p.cb + row + jb);
+        if (p.ca) ldva<V>(ca, p.ca + row + jb);
+        else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) ca[v] = 1.f;
         }
-        if (jj >= 0) {
-            float *q = A.a.psi_ezy + (int64_t)i * sy + jj;
-            py += *q;
-            *q = p.y.bE[j] * py;
+        const int ii = PML ? slab_index(p.x, i) : -1;
+        const float kEx = p.x.kE[i], bEx = p.x.bE[i], cEx = p.x.cE[i];
+        float px_o[V], px_n[V];
+        if (PML && ii >= 0) ldva<V>(px_o, L0.psi_ezx + (int64_t)ii * ny + jb);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int j = jb + v;
+            aca[v] = a[v];
+            if (PML && ii >= 0) px_n[v] = px_o[v];
+            if (i >= 1 && j >= 1) {
+                const float u = cb[v] * a[v];
+                float px = u, py = -u;
+                if (PML && ii >= 0) {
+                    px += px_o[v];
+                    px_n[v] = bEx * px;
+                }
+                if (PML && jj[v] >= 0) {
+                    const int64_t q = (int64_t)i * syw + jj[v];
+                    py += L0.psi_ezy[q];
+                    if (write) L1.psi_ezy[q] = bEy[v] * py;
+                }
+                gy[v] = u * kEx + cEx * px;
+                gx[v] = -u * kEy[v] + cEy[v] * py;
+                if (write && i >= A.design.x && i < A.design.y && j >= A.design.z && j < A.design.w) {
+                    const int64_t q = (int64_t)(i - A.design.x) * dw + (j - A.design.z);
+                    A.grad[q] += (double)a[v] * ((double)A.dca[q] * A.cap_ez[q] + (double)A.dcb[q] * A.cap_br[q]);
+                }
+                aca[v] = a[v] * ca[v];
+            } else if (PML && jj[v] >= 0 && write) {
+                const int64_t q = (int64_t)i * syw + jj[v];
+                L1.psi_ezy[q] = L0.psi_ezy[q];
+            }
         }
-        gy = u * p.x.kE[i] + p.x.cE[i] * px;
-        gx = -u * p.y.kE[j] + p.y.cE[j] * py;
-        if (i >= A.design.x && i < A.design.y && j >= A.design.z && j < A.design.w) {
-            const int64_t q = (int64_t)(i - A.design.x) * (A.design.w - A.design.z) + (j - A.design.z);
-            A.grad[q] += (double)a * ((double)A.dca[q] * A.cap_ez[q] + (double)A.dcb[q] * A.cap_br[q]);
+        if (PML && ii >= 0 && write) stva<V>(L1.psi_ezx + (int64_t)ii * ny + jb, px_n);
+    };
+    // phase A's gx of one column (edge recompute, no writes)
+    auto edge_gx = [&](int i, int j) {
+        if (i < 1 || i >= nx || j < 1 || j >= ny) return 0.f;
+        const int64_t c = (int64_t)i * ny + j;
+        const float u = p.cb[c] * L0.ez[c];
+        float py = -u;
+        const int q = PML ? slab_index(p.y, j) : -1;
+        if (PML && q >= 0) py += L0.psi_ezy[(int64_t)i * syw + q];
+        return -u * p.y.kE[j] + p.y.cE[j] * py;
+    };
+
+    // prologue: A of row x0, ex of row x0-1
+    float gx_c[V], gy_c[V], aca_c[V], ex_p[V];
+    phaseA(x0, gx_c, gy_c, aca_c, true);
+    zero(ex_p);
+    if (x0 >= 1 && valid) {
+        const int i = x0 - 1;
+        const int64_t row = (int64_t)i * ny;
+        float gxm[V], gym[V], acam[V], hy[V], db[V];
+        phaseA(i, gxm, gym, acam, false);
+        ldva<V>(hy, L0.hy + row + jb);
+        if (p.db) ldva<V>(db, p.db + row + jb);
+        else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) db[v] = p.db0;
         }
-        a *= p.ca ? p.ca[c] : 1.f;
+        const int ii = PML ? slab_index(p.x, i) : -1;
+        float py_o[V];
+        if (PML && ii >= 0) ldva<V>(py_o, L0.psi_hy + (int64_t)ii * ny + jb);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const float h = hy[v] + gym[v] - gy_c[v];
+            float wy = db[v] * h;
+            if (PML && ii >= 0) wy += py_o[v];
+            ex_p[v] = db[v] * h * p.x.kH[i] + p.x.cH[i] * wy;
+        }
     }
-    A.a.gx[c] = gx;
-    A.a.gy[c] = gy;
-    A.a.ez[c] = a;
-}
 
-__global__ __launch_bounds__(256) void k_adj_b(AdjArgs A) {
-    const Prob2D &p = A.p;
-    const int64_t n = (int64_t)p.nx * p.ny;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    const int ny = p.ny;
-    const int i = (int)(c / ny), j = (int)(c - (int64_t)i * ny);
-    float hy = A.a.hy[c] + A.a.gy[c] - ((i + 1 < p.nx) ? A.a.gy[c + ny] : 0.f);
-    float hx = A.a.hx[c] + A.a.gx[c] - ((j + 1 < ny) ? A.a.gx[c + 1] : 0.f);
-    const float db = p.db ? p.db[c] : p.db0;
-    const int ii = slab_index(p.x, i), jj = slab_index(p.y, j);
-    const int sy = p.y.lo + p.y.hi;
-    // Hx: forward Hx -= Db (kH dEy + psi), psi <- b psi + c dEy
-    float wx = -db * hx;
-    if (jj >= 0) {
-        float *q = A.a.psi_hx + (int64_t)i * sy + jj;
-        wx += *q;
-        *q = p.y.bH[j] * wx;
+    for (int i = x0; i < x1; ++i) {
+        const int64_t row = (int64_t)i * ny;
+        float gx_n[V], gy_n[V], aca_n[V];
+        phaseA(i + 1, gx_n, gy_n, aca_n, i + 1 < x1);
+        // gx at j+1
+        float gxr[V];
+#pragma unroll
+        for (int v = 0; v + 1 < V; ++v) gxr[v] = gx_c[v + 1];
+        float sh = __shfl_down(gx_c[0], 1);
+        if (lane == 63) sh = edge_gx(i, jend);
+        gxr[V - 1] = sh;
+        // ---- phase B (H layer transposed) ----
+        float hx[V], hy[V], db[V], ex[V], ey[V];
+        zero(hx); zero(hy); zero(ex); zero(ey);
+#pragma unroll
+        for (int v = 0; v < V; ++v) db[v] = p.db0;
+        const int ii = PML ? slab_index(p.x, i) : -1;
+        if (valid) {
+            ldva<V>(hx, L0.hx + row + jb);
+            ldva<V>(hy, L0.hy + row + jb);
+            if (p.db) ldva<V>(db, p.db + row + jb);
+            float py_o[V], py_n[V];
+            if (PML && ii >= 0) ldva<V>(py_o, L0.psi_hy + (int64_t)ii * ny + jb);
+            const float kHx = p.x.kH[i], bHx = p.x.bH[i], cHx = p.x.cH[i];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                hy[v] = hy[v] + gy_c[v] - gy_n[v];
+                hx[v] = hx[v] + gx_c[v] - gxr[v];
+                float wx = -db[v] * hx[v];
+                if (PML && jj[v] >= 0) {
+                    const int64_t q = (int64_t)i * syw + jj[v];
+                    wx += L0.psi_hx[q];
+                    L1.psi_hx[q] = bHy[v] * wx;
+                }
+                ey[v] = -db[v] * hx[v] * kHy[v] + cHy[v] * wx;
+                float wy = db[v] * hy[v];
+                if (PML && ii >= 0) {
+                    wy += py_o[v];
+                    py_n[v] = bHx * wy;
+                }
+                ex[v] = db[v] * hy[v] * kHx + cHx * wy;
+            }
+            stva<V>(L1.hx + row + jb, hx);
+            stva<V>(L1.hy + row + jb, hy);
+            if (PML && ii >= 0) stva<V>(L1.psi_hy + (int64_t)ii * ny + jb, py_n);
+        }
+        // ey at j-1
+        float eyl[V];
+#pragma unroll
+        for (int v = 1; v < V; ++v) eyl[v] = ey[v - 1];
+        float shl = __shfl_up(ey[V - 1], 1);
+        if (lane == 0) {
+            shl = 0.f;
+            if (jm >= 0) {
+                const int64_t c = row + jm;
+                const float dbm = p.db ? p.db[c] : p.db0;
+                const float h = L0.hx[c] + edge_gx(i, jm) - gx_c[0];
+                float wx = -dbm * h;
+                const int q = PML ? slab_index(p.y, jm) : -1;
+                if (PML && q >= 0) wx += L0.psi_hx[(int64_t)i * syw + q];
+                shl = -dbm * h * p.y.kH[jm] + p.y.cH[jm] * wx;
+            }
+        }
+        eyl[0] = shl;
+        // ---- phase C (gather into adjoint Ez) ----
+        if (valid) {
+            float ez[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                float w = aca_c[v] - ey[v] - ex[v];
+                if (jb + v >= 1) w += eyl[v];
+                if (i >= 1) w += ex_p[v];
+                ez[v] = w;
+            }
+            stva<V>(L1.ez + row + jb, ez);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            gx_c[v] = gx_n[v]; gy_c[v] = gy_n[v]; aca_c[v] = aca_n[v]; ex_p[v] = ex[v];
+        }
     }
-    const float ey = -db * hx * p.y.kH[j] + p.y.cH[j] * wx;
-    // Hy: forward Hy += Db (kH dEx + psi)
-    float wy = db * hy;
-    if (ii >= 0) {
-        float *q = A.a.psi_hy + (int64_t)ii * ny + j;
-        wy += *q;
-        *q = p.x.bH[i] * wy;
-    }
-    const float ex = db * hy * p.x.kH[i] + p.x.cH[i] * wy;
-    A.a.hx[c] = hx;
-    A.a.hy[c] = hy;
-    A.a.ex[c] = ex;
-    A.a.ey[c] = ey;
 }
 
-__global__ __launch_bounds__(256) void k_adj_c(AdjArgs A) {
-    const Prob2D &p = A.p;
-    const int64_t n = (int64_t)p.nx * p.ny;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    const int ny = p.ny;
-    const int i = (int)(c / ny), j = (int)(c - (int64_t)i * ny);
-    float v = A.a.ez[c] - A.a.ey[c] - A.a.ex[c];
-    if (j >= 1) v += A.a.ey[c - 1];
-    if (i >= 1) v += A.a.ex[c - ny];
-    A.a.ez[c] = v;
+// probe-loss seed: lEz[probe] += 2 * Ez^{k+1}[probe]; one thread per probed
+// cell (entries sorted by cell, [start[u], start[u+1]) share cell u), so
+// probes sharing a cell add up in order
+__global__ void k_adj_seed(float *ez, const int *start, const int *cell, const int *slot, int nu,
+                           const float *rec, int64_t rec_stride, int64_t k) {
+    const int u = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (u >= nu) return;
+    const int q0 = start[u], q1 = start[u + 1];
+    const int c = cell[q0];
+    float v = ez[c];
+    for (int q = q0; q < q1; ++q) v += 2.f * rec[(int64_t)slot[q] * rec_stride + k];
+    ez[c] = v;
 }
 
-__global__ void k_grad_to_float(const double *g, float *out, int64_t n) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) out[q] = (float)g[q];
-}
-
-hipError_t launch_adj2d(const Prob2D &p, const Adj2D &a, int64_t k, const int *design,
-                        const float *cap_ez, const float *cap_br, const float *dca,
-                        const float *dcb, double *grad, int seed_on, const int *pb_start,
-                        const int *pb_cell, const int *pb_slot, const float *rec,
-                        int64_t rec_stride, hipStream_t st) {
-    AdjArgs A;
+hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, int64_t k, const int *design,
+                              const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
+                              double *grad, int seed_on, const int *seed_start, const int *seed_cell,
+                              const int *seed_slot, int nu, const float *rec, int64_t rec_stride, int V, int TX,
+                              hipStream_t st) {
+    if (p.ny % V != 0 || TX < 1) return hipErrorInvalidValue;
+    if (seed_on && nu > 0)
+        hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((nu + 63) / 64)), dim3(64), 0, st, l0.ez, seed_start,
+                           seed_cell, seed_slot, nu, rec, rec_stride, k);
+    AdjFArgs A;
     A.p = p;
-    A.a = a;
+    A.l0 = l0;
+    A.l1 = l1;
     A.design = make_int4(design[0], design[1], design[2], design[3]);
     A.cap_ez = cap_ez;
     A.cap_br = cap_br;
     A.dca = dca;
     A.dcb = dcb;
     A.grad = grad;
-    A.seed_on = seed_on;
-    A.pb_start = pb_start;
-    A.pb_cell = pb_cell;
-    A.pb_slot = pb_slot;
-    A.rec = rec;
-    A.rec_stride = rec_stride;
-    A.k = k;
-    const int64_t n = (int64_t)p.nx * p.ny;
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_adj_a, dim3(nb), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_adj_b, dim3(nb), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_adj_c, dim3(nb), dim3(256), 0, st, A);
+    const int nsy = (p.ny + 64 * V - 1) / (64 * V), ncx = (p.nx + TX - 1) / TX;
+    const int nt = nsy * ncx;
+    const dim3 g((unsigned)((nt + 3) / 4)), b(256);
+    const bool pml = p.x.lo + p.x.hi + p.y.lo + p.y.hi > 0;
+#define GEM_A(VV)                                                                                   \
+    do {                                                                                            \
+        if (pml) hipLaunchKernelGGL((k_adj_fused<VV, true>), g, b, 0, st, A, TX, nsy, nt);        \
+        else hipLaunchKernelGGL((k_adj_fused<VV, false>), g, b, 0, st, A, TX, nsy, nt);           \
+    } while (0)
+    switch (V) {
+        case 1: GEM_A(1); break;
+        case 2: GEM_A(2); break;
+        case 4: GEM_A(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GEM_A
     return hipGetLastError();
+}
+
+__global__ void k_grad_to_float(const double *g, float *out, int64_t n) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = (float)g[q];
 }
 
 hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st) {
