@@ -191,8 +191,8 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    z-CPML cells in all, and no 4-cell z group holding cells of both z
  *    slabs.
  *    2D multi-step (variant 3 on a 2D grid): tile[0] = V (1, 2 or 4; ny % V
- *    must be 0), tile[1] = TX (rows per tile, 1..65536; 0 = 8), tile[2] =
- *    TB (leapfrog steps per pass: 2 or 4); tile[3] must be 0.  Each
+ *    must be 0; 0 = 1), tile[1] = TX (rows per tile, 1..65536; 0 = 4), tile[2] =
+ *    TB (leapfrog steps per pass: 2 or 4; 0 = 4); tile[3] must be 0.  Each
  *    wavefront advances its rows and columns TB steps, recomputing the
  *    neighbouring rows and columns it needs; an n not divisible by TB ends
  *    with single steps.

@@ -71,19 +71,17 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         const int64_t nd = (int64_t)(i1 - i0) * (j1 - j0);
         const int64_t P = (int64_t)s.probe_cells.size();
 
-        // the recompute captures design values from the fused single-step
-        // kernel; the adjoint step takes the same tiles.  Unless chosen
-        // explicitly: one column per lane below 4M cells (more wavefronts
-        // for the chip), else two.
+        // forward and recompute: the chosen fused configuration (variant 2
+        // or 3; else the grid's default), the recompute capturing the design
+        // cells.  The adjoint step: one column per lane below 4M cells (more
+        // wavefronts for the chip), else two.
         saved = s.kcfg;
         restore_cfg = true;
-        if (s.kcfg.variant != 2 || !s.kcfg_explicit) {
-            s.kcfg = fdtd_kernel_config{};
-            s.kcfg.variant = 2;
-            s.kcfg.tile[0] = (s.ncell >= ((int64_t)4 << 20) && s.ny % 2 == 0) ? 2 : 1;
-            s.kcfg.tile[1] = 4;
-            s.kcfg.tb = 1;
-        }
+        if ((s.kcfg.variant != 2 && s.kcfg.variant != 3) || !s.kcfg_explicit) default_variant_tiles(s, s.kcfg);
+        if (s.kcfg.variant != 2 && s.kcfg.variant != 3) fail(FDTD_EINVAL, "no fused 2D kernel for this grid");
+        const bool multi = s.kcfg.variant == 3;
+        const int TB = multi ? s.kcfg.tile[2] : 1;
+        const Fused2DCfg ac{(s.ncell >= ((int64_t)4 << 20) && s.ny % 2 == 0) ? 2 : 1, 4};
         s.pt_ntiles = -1;
         s.build_probe_tiles();
         s.zero_state();
@@ -102,10 +100,18 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         for (int64_t g = 0; g < nseg; ++g) {
             copy_state(s, s.cur, ck + g * S, true);
             const int64_t k1 = std::min(T, (g + 1) * L);
-            for (int64_t k = g * L; k < k1; ++k) {
-                s.launch_step(k);
-                s.n_done += 1;
-                s.n_rec += 1;
+            for (int64_t k = g * L; k < k1;) {
+                if (multi && k + TB <= k1) {
+                    s.launch_tb2d(k);
+                    k += TB;
+                    s.n_done += TB;
+                    s.n_rec += TB;
+                } else {
+                    s.launch_step(k);
+                    k += 1;
+                    s.n_done += 1;
+                    s.n_rec += 1;
+                }
             }
         }
         copy_state(s, s.cur, fin, true);
@@ -173,18 +179,52 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         hip_check(hipMemcpyAsync(d_ust, ust.data(), ust.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipMemcpyAsync(d_pcell, pcell.data(), pcell.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         hip_check(hipMemcpyAsync(d_pslot, pslot.data(), pslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        // the same entries grouped by tile of the adjoint kernel
+        const int nsy = (s.ny + 62 * ac.V - 1) / (62 * ac.V), ncx = (s.nx + ac.TX - 1) / ac.TX;
+        std::vector<int> tst((size_t)nsy * ncx + 1, 0), tcell, tslot;
+        {
+            std::vector<std::pair<int, int>> e;  // (tile, entry)
+            for (size_t q = 0; q < pcell.size(); ++q) {
+                const int i = pcell[q] / s.ny, j = pcell[q] % s.ny;
+                e.push_back({(i / ac.TX) * nsy + j / (62 * ac.V), (int)q});
+            }
+            std::stable_sort(e.begin(), e.end(), [](const std::pair<int, int> &u, const std::pair<int, int> &v) {
+                return u.first < v.first;
+            });
+            for (auto &x : e) {
+                tst[(size_t)x.first + 1]++;
+                tcell.push_back(pcell[(size_t)x.second]);
+                tslot.push_back(pslot[(size_t)x.second]);
+            }
+            for (size_t t = 0; t + 1 < tst.size(); ++t) tst[t + 1] += tst[t];
+        }
+        int *d_tst = (int *)get(tst.size() * 4);
+        int *d_tcell = (int *)get(std::max<size_t>(1, tcell.size()) * 4);
+        int *d_tslot = (int *)get(std::max<size_t>(1, tslot.size()) * 4);
+        hip_check(hipMemcpyAsync(d_tst, tst.data(), tst.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(d_tcell, tcell.data(), tcell.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        hip_check(hipMemcpyAsync(d_tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
+        const ProbeTiles apt{d_tst, d_tcell, d_tslot};
         hip_check(hipStreamSynchronize(s.st), "sync");
         // ---- backward over segments ----
         const int dbox[4] = {i0, i1, j0, j1};
         ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
-        Fused2DCfg fc{s.kcfg.tile[0], s.kcfg.tile[1]};
+        const Fused2DCfg fc = s.single2d();
         for (int64_t g = nseg - 1; g >= 0; --g) {
             const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
             copy_state(s, 0, ck + g * S, false);
             s.cur = 0;
             s.n_done = k0;
             s.n_rec = k0;
-            for (int64_t k = k0; k < k1; ++k) {
+            const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
+            for (int64_t k = k0; k < k1;) {
+                if (multi && k + TB <= k1) {
+                    s.launch_tb2d(k, &cap);
+                    k += TB;
+                    s.n_done += TB;
+                    s.n_rec += TB;
+                    continue;
+                }
                 const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
                 const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
                 hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
@@ -193,13 +233,20 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
                 s.cur = 1 - s.cur;
                 s.n_done += 1;
                 s.n_rec += 1;
+                k += 1;
             }
             const Prob2D p = s.prob2d(0, 0);
             for (int64_t k = k1 - 1; k >= k0; --k) {
-                const int seed = (k + 1 > n0 && k + 1 <= n1) ? 1 : 0;
-                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], k, dbox, cap_ez + (k - k0) * nd,
-                                             cap_br + (k - k0) * nd, dca, dcb, grad, seed, d_ust, d_pcell,
-                                             d_pslot, nu, s.rec_dev, s.rec_cap, fc.V, fc.TX, s.st),
+                // the first step's input is seeded here, every later one by
+                // the step that writes it
+                if (k == T - 1 && T > n0 && T <= n1)
+                    hip_check(launch_adj2d_seed(a[acur].ez, d_ust, d_pcell, d_pslot, nu, s.rec_dev, s.rec_cap, T - 1,
+                                                s.st),
+                              "adjoint seed");
+                const int seed_out = (k > n0 && k <= n1) ? 1 : 0;
+                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cap_ez + (k - k0) * nd,
+                                             cap_br + (k - k0) * nd, dca, dcb, grad, seed_out, apt, s.rec_dev,
+                                             s.rec_cap, k - 1, ac.V, ac.TX, s.st),
                           "adjoint step");
                 acur = 1 - acur;
             }
@@ -212,7 +259,7 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         s.n_rec = T;
         hip_check(hipEventRecord(s.ev1, s.st), "event");
         s.timed = true;
-        s.last_launches = T * 3 + (n1 - n0);
+        s.last_launches = T * 3 + 1;
         hip_check(hipStreamSynchronize(s.st), "sync");
         for (void *p : tmp) s.al.put(p);
         tmp.clear();

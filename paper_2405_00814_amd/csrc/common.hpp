@@ -132,12 +132,22 @@ bool tb2d_supported(int ny, int V, int TB, int TX);
 // the others.  Ordered row chunk by row chunk.
 void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi, const int *ylohi,
                std::vector<Tile2T> &inner, std::vector<Tile2T> &outer);
+// Capture of the design cells for the adjoint: for every step n of the
+// pass, at cell (i, j) of the box design = [x, y) x [z, w), Ez before the E
+// layer goes to ez[(n - k0) * nd + q] and the E layer's bracket to br[...],
+// q = (i - x) * (w - z) + (j - z).
+struct CapArgs {
+    int4 design;
+    float *ez, *br;
+    int64_t k0, nd;
+};
 // probs_dev: nullptr for one problem p (tiles' prob ignored), else the
 // device array the tiles index (step = *step_base + step).  mat: 0 Cb, 1
 // Ca and Cb, 2 Ca, Cb and Db maps (null maps of a problem read as uniform).
+// capture: one problem only (nullptr: none).
 hipError_t launch_2d_tb(const Prob2D &p, const Prob2D *probs_dev, const Tile2T *tiles, int ntiles, bool pml,
                         int mat, const ProbeTiles &pt, int V, int TB, const int64_t *step_base, int64_t step,
-                        hipStream_t st);
+                        hipStream_t st, const CapArgs *capture = nullptr);
 int fused2d_ntiles(int nx, int ny, const Fused2DCfg &c);
 int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
@@ -232,16 +242,20 @@ struct Adj2D {
     float *ez, *hx, *hy, *psi_hx, *psi_hy, *psi_ezx, *psi_ezy;
 };
 hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st);
-// One adjoint step in one pass: reads the adjoint state l0 (step k+1; the
-// probe seed of step k+1 is added to l0.ez first when seed_on: nu probed
-// cells, probe entries [seed_start[u], seed_start[u+1]) at cell u), writes l1
-// (step k), accumulates the gradient at the design cells.  Tiles of TX rows
-// by 64*V columns; ny % V == 0.
-hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, int64_t k, const int *design,
+// One adjoint step in one pass: reads the adjoint state l0 (step k+1),
+// writes l1 (step k), accumulates the gradient at the design cells.  When
+// seed_out, the probe-loss seed of the next step is added to the written
+// Ez: l1.ez[probe] += 2 * rec[slot][seed_k] (pt: probes grouped by tile in
+// tile order, tile = (i / TX) * nsy + j / (62 V), entries of one cell
+// consecutive).  Tiles of TX rows by 62*V columns; ny % V == 0.
+hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
                               const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
-                              double *grad, int seed_on, const int *seed_start, const int *seed_cell,
-                              const int *seed_slot, int nu, const float *rec, int64_t rec_stride, int V, int TX,
-                              hipStream_t st);
+                              double *grad, int seed_out, const ProbeTiles &pt, const float *rec, int64_t rec_stride,
+                              int64_t seed_k, int V, int TX, hipStream_t st);
+// The seed of the first adjoint step: ez[cell u] += 2 * rec[slot][k] over
+// the probe entries [start[u], start[u+1]) of the nu probed cells.
+hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_cell, const int *seed_slot, int nu,
+                             const float *rec, int64_t rec_stride, int64_t k, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Errors

@@ -36,7 +36,8 @@ struct Row2 {
 template <int V, int TB, bool PML, int MAT, bool BATCH>
 __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restrict__ probs,
                                               const Tile2T *__restrict__ tiles, int ntiles, ProbeTiles pt,
-                                              const int64_t *__restrict__ step_base, int64_t step0) {
+                                              const int64_t *__restrict__ step_base, int64_t step0,
+                                              CapArgs cap) {
     constexpr int HL = (TB + V - 1) / V;  // halo lanes per side
     constexpr int OW = (64 - 2 * HL) * V;  // own columns per strip
     const int tw = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
@@ -174,6 +175,10 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
 #pragma unroll
             for (int v = 1; v < V; ++v) hl[v] = out.hx[v - 1];
             hl[0] = __shfl_up(out.hx[V - 1], 1);
+            const bool mine = own && i >= T.i0 && i < T.i1;
+            // design-cell capture (single problem): Ez before the E layer
+            // and the E layer's bracket, per step
+            const bool capi = !BATCH && cap.ez != nullptr && mine && i >= cap.design.x && i < cap.design.y;
             // ---- E layer ----
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -195,6 +200,12 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                         ty += out.pezy[v];
                     }
                     out.e[v] = (MAT >= 1 ? a.ca[v] * a.e[v] : a.e[v]) + a.cb[v] * (tx - ty);
+                    if (capi && j >= cap.design.z && j < cap.design.w) {
+                        const int64_t q = (step + k - cap.k0) * cap.nd + (int64_t)(i - cap.design.x) *
+                                          (cap.design.w - cap.design.z) + (j - cap.design.z);
+                        cap.ez[q] = a.e[v];
+                        cap.br[q] = tx - ty;
+                    }
                 }
                 if ((int64_t)i * ny + j == p.src_idx) out.e[v] += sval[k];
             }
@@ -208,7 +219,6 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                 out.cb[v] = a.cb[v]; out.ca[v] = a.ca[v]; out.db[v] = a.db[v];
                 hyp[k][v] = out.hy[v];
             }
-            const bool mine = own && i >= T.i0 && i < T.i1;
             // probes of this tile, state n+k+1
             if (mine && pt.start != nullptr) {
                 const int pend = pt.start[tw + 1];
@@ -260,18 +270,21 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
 
 template <int V, int TB, bool PML, int MAT>
 static void go_tb(const Prob2D &p, const Prob2D *probs, const Tile2T *tiles, int n, const ProbeTiles &pt,
-                  const int64_t *step_base, int64_t step, hipStream_t st) {
+                  const int64_t *step_base, int64_t step, const CapArgs &cap, hipStream_t st) {
     const dim3 g((unsigned)((n + 3) / 4)), b(256);
     if (probs)
-        hipLaunchKernelGGL((k2d_tb<V, TB, PML, MAT, true>), g, b, 0, st, p, probs, tiles, n, pt, step_base, step);
+        hipLaunchKernelGGL((k2d_tb<V, TB, PML, MAT, true>), g, b, 0, st, p, probs, tiles, n, pt, step_base, step,
+                           cap);
     else
-        hipLaunchKernelGGL((k2d_tb<V, TB, PML, MAT, false>), g, b, 0, st, p, probs, tiles, n, pt, step_base, step);
+        hipLaunchKernelGGL((k2d_tb<V, TB, PML, MAT, false>), g, b, 0, st, p, probs, tiles, n, pt, step_base, step,
+                           cap);
 }
 
 template <int V, int TB>
 static void go_tb_m(const Prob2D &p, const Prob2D *probs, const Tile2T *tiles, int n, bool pml, int mat,
-                    const ProbeTiles &pt, const int64_t *step_base, int64_t step, hipStream_t st) {
-#define GEM_TB(PM, MA) go_tb<V, TB, PM, MA>(p, probs, tiles, n, pt, step_base, step, st)
+                    const ProbeTiles &pt, const int64_t *step_base, int64_t step, const CapArgs &cap,
+                    hipStream_t st) {
+#define GEM_TB(PM, MA) go_tb<V, TB, PM, MA>(p, probs, tiles, n, pt, step_base, step, cap, st)
     if (pml) {
         if (mat == 0) GEM_TB(true, 0);
         else if (mat == 1) GEM_TB(true, 1);
@@ -286,16 +299,19 @@ static void go_tb_m(const Prob2D &p, const Prob2D *probs, const Tile2T *tiles, i
 
 hipError_t launch_2d_tb(const Prob2D &p, const Prob2D *probs_dev, const Tile2T *tiles, int ntiles, bool pml,
                         int mat, const ProbeTiles &pt, int V, int TB, const int64_t *step_base, int64_t step,
-                        hipStream_t st) {
+                        hipStream_t st, const CapArgs *capture) {
     if (ntiles <= 0) return hipSuccess;
+    if (capture && probs_dev) return hipErrorInvalidValue;
+    CapArgs cap{};
+    if (capture) cap = *capture;
     if (!probs_dev && p.ny % V != 0) return hipErrorInvalidValue;
     if (mat < 0 || mat > 2) return hipErrorInvalidValue;
-    if (V == 1 && TB == 2) go_tb_m<1, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
-    else if (V == 1 && TB == 4) go_tb_m<1, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
-    else if (V == 2 && TB == 2) go_tb_m<2, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
-    else if (V == 2 && TB == 4) go_tb_m<2, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
-    else if (V == 4 && TB == 2) go_tb_m<4, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
-    else if (V == 4 && TB == 4) go_tb_m<4, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, st);
+    if (V == 1 && TB == 2) go_tb_m<1, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
+    else if (V == 1 && TB == 4) go_tb_m<1, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
+    else if (V == 2 && TB == 2) go_tb_m<2, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
+    else if (V == 2 && TB == 4) go_tb_m<2, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
+    else if (V == 4 && TB == 2) go_tb_m<4, 2>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
+    else if (V == 4 && TB == 4) go_tb_m<4, 4>(p, probs_dev, tiles, ntiles, pml, mat, pt, step_base, step, cap, st);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

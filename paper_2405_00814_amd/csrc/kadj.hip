@@ -21,9 +21,11 @@ namespace gem {
 // that of step k written to L1.  At row i the wavefront has phase A of rows i
 // (carried) and i+1, phase B of rows i-1 (carried) and i, and writes row i.
 // The strip's edge columns take their neighbours' values by recomputation:
-// phase A's gx at column y0+64V (right of the strip, lane 63) and phase B's
-// ey at column y0-1 (left, lane 0).  The probe-loss seed is added to L0 by a
-// separate launch first.
+// lanes 0 and 63 hold the neighbouring strips' edge columns and recompute
+// them (phase B needs phase A's gx at j+1, phase C phase B's ey at j-1), so
+// a strip owns the 62*V columns of lanes 1..62 and no lane waits on a
+// scalar recompute.  The probe-loss seed of the next step is added to the
+// written adjoint Ez by the cell's owner.
 // ---------------------------------------------------------------------------
 struct AdjFArgs {
     Prob2D p;
@@ -31,6 +33,13 @@ struct AdjFArgs {
     int4 design;
     const float *cap_ez, *cap_br, *dca, *dcb;
     double *grad;
+    // probe-loss seed of the next step, added to the written adjoint Ez:
+    // l1.ez[probe] += 2 * rec[slot][seed_k] (probes grouped by tile, entries
+    // of one cell consecutive)
+    int seed_out;
+    ProbeTiles pt;
+    const float *rec;
+    int64_t rec_stride, seed_k;
 };
 
 template <int V>
@@ -68,8 +77,9 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
     const int nx = p.nx, ny = p.ny;
     const int cx = tw / nsy, sy = tw - cx * nsy;
     const int x0 = cx * TX, x1 = min(x0 + TX, nx);
-    const int y0 = sy * 64 * V, jb = y0 + lane * V, jend = y0 + 64 * V, jm = y0 - 1;
-    const bool valid = jb < ny;  // ny % V == 0
+    const int jb = sy * 62 * V - V + lane * V;       // lane 0: the column group left of the strip
+    const bool valid = jb >= 0 && jb < ny;           // ny % V == 0
+    const bool own = valid && lane >= 1 && lane <= 62;
     const int syw = p.y.lo + p.y.hi;
     const int dw = A.design.w - A.design.z;
 
@@ -89,7 +99,8 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
     };
     // phase A of row i (own columns): gx, gy messages, Ca-weighted adjoint
     // Ez; writes the new E-type psi and the gradient when `write`
-    auto phaseA = [&](int i, float (&gx)[V], float (&gy)[V], float (&aca)[V], bool write) {
+    auto phaseA = [&](int i, float (&gx)[V], float (&gy)[V], float (&aca)[V], bool wr) {
+        const bool write = wr && own;
         zero(gx); zero(gy); zero(aca);
         if (i < 0 || i >= nx || !valid) return;
         const int64_t row = (int64_t)i * ny;
@@ -136,17 +147,6 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
         }
         if (PML && ii >= 0 && write) stva<V>(L1.psi_ezx + (int64_t)ii * ny + jb, px_n);
     };
-    // phase A's gx of one column (edge recompute, no writes)
-    auto edge_gx = [&](int i, int j) {
-        if (i < 1 || i >= nx || j < 1 || j >= ny) return 0.f;
-        const int64_t c = (int64_t)i * ny + j;
-        const float u = p.cb[c] * L0.ez[c];
-        float py = -u;
-        const int q = PML ? slab_index(p.y, j) : -1;
-        if (PML && q >= 0) py += L0.psi_ezy[(int64_t)i * syw + q];
-        return -u * p.y.kE[j] + p.y.cE[j] * py;
-    };
-
     // prologue: A of row x0, ex of row x0-1
     float gx_c[V], gy_c[V], aca_c[V], ex_p[V];
     phaseA(x0, gx_c, gy_c, aca_c, true);
@@ -182,9 +182,7 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
         float gxr[V];
 #pragma unroll
         for (int v = 0; v + 1 < V; ++v) gxr[v] = gx_c[v + 1];
-        float sh = __shfl_down(gx_c[0], 1);
-        if (lane == 63) sh = edge_gx(i, jend);
-        gxr[V - 1] = sh;
+        gxr[V - 1] = __shfl_down(gx_c[0], 1);  // lane 63: not needed
         // ---- phase B (H layer transposed) ----
         float hx[V], hy[V], db[V], ex[V], ey[V];
         zero(hx); zero(hy); zero(ex); zero(ey);
@@ -206,7 +204,7 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 if (PML && jj[v] >= 0) {
                     const int64_t q = (int64_t)i * syw + jj[v];
                     wx += L0.psi_hx[q];
-                    L1.psi_hx[q] = bHy[v] * wx;
+                    if (own) L1.psi_hx[q] = bHy[v] * wx;
                 }
                 ey[v] = -db[v] * hx[v] * kHy[v] + cHy[v] * wx;
                 float wy = db[v] * hy[v];
@@ -216,30 +214,19 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 }
                 ex[v] = db[v] * hy[v] * kHx + cHx * wy;
             }
-            stva<V>(L1.hx + row + jb, hx);
-            stva<V>(L1.hy + row + jb, hy);
-            if (PML && ii >= 0) stva<V>(L1.psi_hy + (int64_t)ii * ny + jb, py_n);
+            if (own) {
+                stva<V>(L1.hx + row + jb, hx);
+                stva<V>(L1.hy + row + jb, hy);
+                if (PML && ii >= 0) stva<V>(L1.psi_hy + (int64_t)ii * ny + jb, py_n);
+            }
         }
         // ey at j-1
         float eyl[V];
 #pragma unroll
         for (int v = 1; v < V; ++v) eyl[v] = ey[v - 1];
-        float shl = __shfl_up(ey[V - 1], 1);
-        if (lane == 0) {
-            shl = 0.f;
-            if (jm >= 0) {
-                const int64_t c = row + jm;
-                const float dbm = p.db ? p.db[c] : p.db0;
-                const float h = L0.hx[c] + edge_gx(i, jm) - gx_c[0];
-                float wx = -dbm * h;
-                const int q = PML ? slab_index(p.y, jm) : -1;
-                if (PML && q >= 0) wx += L0.psi_hx[(int64_t)i * syw + q];
-                shl = -dbm * h * p.y.kH[jm] + p.y.cH[jm] * wx;
-            }
-        }
-        eyl[0] = shl;
+        eyl[0] = __shfl_up(ey[V - 1], 1);  // lane 0: not needed
         // ---- phase C (gather into adjoint Ez) ----
-        if (valid) {
+        if (own) {
             float ez[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -247,6 +234,17 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 if (jb + v >= 1) w += eyl[v];
                 if (i >= 1) w += ex_p[v];
                 ez[v] = w;
+            }
+            if (A.seed_out) {
+                const int q1 = A.pt.start[tw + 1];
+                for (int q = A.pt.start[tw]; q < q1; ++q) {
+                    const int c = A.pt.cell[q];
+                    const int pi = c / ny, pj = c - pi * ny;
+                    if (pi != i) continue;
+                    const float add = 2.f * A.rec[(int64_t)A.pt.slot[q] * A.rec_stride + A.seed_k];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) ez[v] = pj == jb + v ? ez[v] + add : ez[v];
+                }
             }
             stva<V>(L1.ez + row + jb, ez);
         }
@@ -271,16 +269,25 @@ __global__ void k_adj_seed(float *ez, const int *start, const int *cell, const i
     ez[c] = v;
 }
 
-hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, int64_t k, const int *design,
+hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_cell, const int *seed_slot, int nu,
+                             const float *rec, int64_t rec_stride, int64_t k, hipStream_t st) {
+    if (nu <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((nu + 63) / 64)), dim3(64), 0, st, ez, seed_start, seed_cell,
+                       seed_slot, nu, rec, rec_stride, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
                               const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
-                              double *grad, int seed_on, const int *seed_start, const int *seed_cell,
-                              const int *seed_slot, int nu, const float *rec, int64_t rec_stride, int V, int TX,
-                              hipStream_t st) {
+                              double *grad, int seed_out, const ProbeTiles &pt, const float *rec, int64_t rec_stride,
+                              int64_t seed_k, int V, int TX, hipStream_t st) {
     if (p.ny % V != 0 || TX < 1) return hipErrorInvalidValue;
-    if (seed_on && nu > 0)
-        hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((nu + 63) / 64)), dim3(64), 0, st, l0.ez, seed_start,
-                           seed_cell, seed_slot, nu, rec, rec_stride, k);
     AdjFArgs A;
+    A.seed_out = seed_out;
+    A.pt = pt;
+    A.rec = rec;
+    A.rec_stride = rec_stride;
+    A.seed_k = seed_k;
     A.p = p;
     A.l0 = l0;
     A.l1 = l1;
@@ -290,7 +297,7 @@ hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1,
     A.dca = dca;
     A.dcb = dcb;
     A.grad = grad;
-    const int nsy = (p.ny + 64 * V - 1) / (64 * V), ncx = (p.nx + TX - 1) / TX;
+    const int nsy = (p.ny + 62 * V - 1) / (62 * V), ncx = (p.nx + TX - 1) / TX;
     const int nt = nsy * ncx;
     const dim3 g((unsigned)((nt + 3) / 4)), b(256);
     const bool pml = p.x.lo + p.x.hi + p.y.lo + p.y.hi > 0;

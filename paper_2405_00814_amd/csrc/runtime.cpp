@@ -384,18 +384,20 @@ void Sim::build_probe_tiles() {
 
 Fused2DCfg Sim::single2d() const {
     if (kcfg.variant == 2) return Fused2DCfg{kcfg.tile[0], kcfg.tile[1]};
-    return Fused2DCfg{ny % 2 == 0 ? 2 : 1, 4};
+    return default_single2d(nx, ny);
 }
 
 // TB steps of the 2D grid in one pass: interior tiles without the CPML code,
 // then the tiles near a slab with it
-void Sim::launch_tb2d(int64_t step) {
+void Sim::launch_tb2d(int64_t step, const CapArgs *cap) {
     const int V = kcfg.tile[0], TB = kcfg.tile[2];
     const Prob2D p = prob2d(cur, 1 - cur);
     const ProbeTiles pt{pt2_start, pt2_cell, pt2_slot};
     const ProbeTiles po{pt2_start + tb2_inner, pt2_cell, pt2_slot};
-    hip_check(launch_2d_tb(p, nullptr, tb2_dev, tb2_inner, false, mat(), pt, V, TB, nullptr, step, st), "2d multi-step");
-    hip_check(launch_2d_tb(p, nullptr, tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB, nullptr, step, st),
+    hip_check(launch_2d_tb(p, nullptr, tb2_dev, tb2_inner, false, mat(), pt, V, TB, nullptr, step, st, cap),
+              "2d multi-step");
+    hip_check(launch_2d_tb(p, nullptr, tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB, nullptr, step, st,
+                           cap),
               "2d multi-step (cpml)");
     cur = 1 - cur;
     last_launches += (tb2_inner > 0) + (tb2_outer > 0);
@@ -537,28 +539,35 @@ void Sim::refold(int64_t c0, int64_t c1) {
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
-// rows per tile of the 2D multi-step kernel, and the smallest 2D grid
-// (cells) on which the default takes it
-constexpr int kTB2DefaultTX = 8;
-constexpr int64_t kTB2MinCells = (int64_t)1 << 21;
+// 2D defaults (measured on MI355X over grids of 256^2 .. 4096^2): single
+// steps below 2M cells, four steps per pass from there on; one column per
+// lane and short tiles below 8M cells (more wavefronts), two columns and
+// longer tiles above.
+constexpr int64_t kTB2MinCells = (int64_t)2 << 20;
+constexpr int64_t kWide2DCells = (int64_t)8 << 20;
+constexpr int kTB2DefaultTX = 4;
 // smallest 3D grid (cells) on which the default takes two steps per pass
 constexpr int64_t kTwoStepMinCells = (int64_t)1 << 23;
 
-static int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
+Fused2DCfg default_single2d(int nx, int ny) {
+    const bool wide = (int64_t)nx * ny >= kWide2DCells && ny % 2 == 0;
+    return wide ? Fused2DCfg{2, 4} : Fused2DCfg{1, 2};
+}
+
+int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
     if (s.ndim == 2) {
-        // several steps per pass on grids large enough to fill the chip
-        // with short tiles; single steps otherwise
-        const int vt = s.ny % 2 == 0 ? 2 : 1;
-        if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, kTB2DefaultTX)) {
+        const bool wide = s.ncell >= kWide2DCells && s.ny % 2 == 0;
+        const int vt = wide ? 2 : 1, tx = wide ? 8 : kTB2DefaultTX;
+        if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, tx)) {
             k.variant = 3;
             k.tile[0] = vt;
-            k.tile[1] = kTB2DefaultTX;
+            k.tile[1] = tx;
             k.tile[2] = 4;
             return 0;
         }
-        Fused2DCfg c{s.ny % 2 == 0 ? 2 : 1, 4};
+        const Fused2DCfg c = default_single2d(s.nx, s.ny);
         if (fused2d_supported(s.nx, s.ny, c)) {
             k.variant = 2;
             k.tile[0] = c.V;
@@ -588,7 +597,7 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (s.ndim == 2) {
         if (k.variant == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
         return k.tile[3] == 0 && tb2d_supported(s.ny, k.tile[0], k.tile[2], k.tile[1]) &&
-               fused2d_supported(s.nx, s.ny, Fused2DCfg{s.ny % 2 == 0 ? 2 : 1, 4});
+               fused2d_supported(s.nx, s.ny, default_single2d(s.nx, s.ny));
     }
     if (k.tile[1] != 0 || k.tile[3] != 0) return false;
     if (!wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]})) return false;
@@ -1251,9 +1260,9 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
     if (k.variant == 0) {
         default_variant_tiles(s, k);
     } else if (s.ndim == 2 && k.variant == 3) {
-        if (k.tile[0] == 0) k.tile[0] = s.ny % 2 == 0 ? 2 : 1;
+        if (k.tile[0] == 0) k.tile[0] = 1;
         if (k.tile[1] == 0) k.tile[1] = kTB2DefaultTX;
-        if (k.tile[2] == 0) k.tile[2] = 2;
+        if (k.tile[2] == 0) k.tile[2] = 4;
     } else if (k.variant == 2 || k.variant == 3) {
         fdtd_kernel_config d;
         default_variant_tiles(s, d);

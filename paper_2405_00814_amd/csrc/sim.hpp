@@ -163,7 +163,7 @@ struct Sim {
     void build_probe_tiles();
     void launch_step(int64_t step);
     void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
-    void launch_tb2d(int64_t step);
+    void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);
     void advance(int64_t n);
     void alloc_set(int set);
     void zero_state();
@@ -177,6 +177,11 @@ void graph_refold(Sim &s);
 void graph_set_source_probes(Sim &s);
 void graph_get_field(Sim &s, int comp, float *host);
 void graph_set_field(Sim &s, int comp, const float *host);
+
+// default single-step 2D tiles for a grid, and the default kernel
+// configuration of a simulation (runtime.cpp)
+Fused2DCfg default_single2d(int nx, int ny);
+int default_variant_tiles(const Sim &s, fdtd_kernel_config &k);
 
 // creation helpers (runtime.cpp)
 void validate_desc(const fdtd_desc *d);

@@ -123,6 +123,30 @@ def test_adjoint_matches_oracle(ckpt, lossy):
     s.close()
 
 
+@pytest.mark.parametrize("kernel,ckpt,lossy", [((3, (1, 4, 4)), 0, False), ((3, (2, 3, 2)), 17, True),
+                                               ((3, (1, 16, 4)), 30, False), ((2, (2, 8)), 0, True)])
+def test_adjoint_kernel_configs(kernel, ckpt, lossy):
+    """Forward and recompute through the multi-step passes (segments of 17
+    and 30 steps end with single steps) and explicit single-step tiles: the
+    same loss and gradient as the oracle."""
+    from oracle import oracle as O
+    from paper_2405_00814_amd.sim import Sim
+    pb = _adjoint_case(n=72, lossy=lossy)
+    o = O.for_problem(pb)
+    loss_ref, grad_ref = o.loss_and_grad(pb.steps, pb.window, pb.design)
+    s = Sim.from_problem(pb)
+    s.set_kernel(*kernel)
+    loss, grad = s.adjoint_eps(pb.steps, pb.window, pb.design, ckpt)
+    g = grad.cpu().numpy().reshape(grad_ref.shape)
+    log("adjoint", kernel, ckpt, "loss", loss, loss_ref, "grad rel", rel_l2(g, grad_ref))
+    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
+    assert rel_l2(g, grad_ref) <= 1e-3
+    assert s.get_kernel()["variant"] == kernel[0]
+    ref, _ = run_oracle(pb, pb.steps)
+    assert_parity({k: s.get_field(k) for k in ("ez", "hx", "hy")}, ref, TOL, "after adjoint")
+    s.close()
+
+
 def test_adjoint_gradient_vs_fd_fp64():
     """FP32 GPU gradient against FP64 central finite differences of the
     oracle forward on a few seeded design cells."""
