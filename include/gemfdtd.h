@@ -258,6 +258,13 @@ int fdtd_batch_set_source(fdtd_batch *b, int32_t problem, const int32_t *ijk, in
 int fdtd_batch_set_probes(fdtd_batch *b, int32_t problem, const int32_t *ijk, int32_t n);
 /* Enqueue n steps of every problem. */
 int fdtd_batch_step(fdtd_batch *b, int64_t n);
+/* Kernel configuration of the batch: tb leapfrog steps per pass (1, 2 or
+ * 4; 1 = single steps only), tx rows per wavefront tile (1..65536), vmax
+ * the widest vector of columns per lane (1, 2 or 4; each problem takes the
+ * widest its row length allows).  Default 4, 16, 2.  Synchronises; the
+ * state is kept.  FDTD_EINVAL for other values (the configuration is then
+ * unchanged). */
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax);
 int fdtd_batch_probe(fdtd_batch *b, int32_t problem, float *out, int64_t cap,
                      int64_t *n_recorded);
 int fdtd_batch_get_field(fdtd_batch *b, int32_t problem, int component, void *dst,

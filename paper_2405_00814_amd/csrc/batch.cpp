@@ -6,8 +6,9 @@
 // problems, interior tiles first and CPML-slab tiles after them, so two
 // launches per group (without and with the CPML code) advance every problem,
 // with the load spread evenly over the tiles whatever the mix of sizes.
-// The main path is the multi-step kernel (TB steps per pass, groups of
-// vector width 4, 2 and 1); single-step groups (width 2 and 1) take the
+// The main path is the multi-step kernel (TB = 4 steps per pass, groups of
+// vector width 2 and 1 by default: the 4-wide instance with the CPML code
+// holds twice the registers); single-step groups (width 2 and 1) take the
 // remainder steps and align the buffer parity.  Launches read the step
 // number from a device counter, which lets a captured HIP graph of passes be
 // replayed for any step range.
@@ -52,6 +53,7 @@ struct fdtd_batch {
     std::vector<gem::BatchGroup> groups;
     std::vector<gem::TBGroup> tbg;
     int tb = 4;   // steps per multi-step pass (1: single steps only)
+    int tb_tx = 16, tb_vmax = 2;
     int cur = 0;  // buffer set holding the current state
     gem::Prob2D *probs_dev[2] = {nullptr, nullptr};
     std::vector<const void *> probs_key[2];
@@ -197,6 +199,65 @@ static void batch_sync_probs(fdtd_batch &b) {
     }
 }
 
+// multi-step groups: vector width 4, 2 or 1 by row length (at most
+// tb_vmax); none when tb == 1
+static void batch_build_tb(fdtd_batch &b) {
+    for (auto &g : b.tbg) {
+        b.al.put(g.tiles);
+        b.al.put(g.pt_start);
+        b.al.put(g.pt_cell);
+        b.al.put(g.pt_slot);
+    }
+    b.tbg.clear();
+    if (b.tb <= 1) return;
+    const int n = (int)b.sims.size();
+    for (int V : {4, 2, 1}) {
+        if (V > b.tb_vmax) continue;
+        TBGroup g;
+        g.V = V;
+        g.TB = b.tb;
+        g.TX = b.tb_tx;
+        std::vector<Tile2T> in, out, all;
+        for (int q = 0; q < n; ++q) {
+            const Sim &s = *b.sims[(size_t)q];
+            const int vq = (s.ny % 4 == 0 && b.tb_vmax >= 4) ? 4 : ((s.ny % 2 == 0 && b.tb_vmax >= 2) ? 2 : 1);
+            if (vq != V) continue;
+            if (!tb2d_supported(s.ny, V, g.TB, g.TX)) fail(FDTD_EINVAL, "multi-step configuration");
+            g.probs.push_back(q);
+            g.mat = std::max(g.mat, s.mat());
+            g.pos_base.push_back((int)all.size());
+            std::vector<Tile2T> a, c;
+            const int xl[2] = {s.ax[0].lo, s.ax[0].hi}, yl[2] = {s.ax[1].lo, s.ax[1].hi};
+            tb2d_plan(q, s.nx, s.ny, V, g.TB, g.TX, xl, yl, a, c);
+            // problem-order list (row chunk by row chunk, strips inside)
+            const int ow = tb2d_own(V, g.TB), nstrip = (s.ny + ow - 1) / ow;
+            std::vector<Tile2T> po((size_t)((s.nx + g.TX - 1) / g.TX) * nstrip);
+            for (const auto &t : a) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
+            for (const auto &t : c) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
+            for (const auto &t : po) all.push_back(t);
+            in.insert(in.end(), a.begin(), a.end());
+            out.insert(out.end(), c.begin(), c.end());
+        }
+        if (g.probs.empty()) continue;
+        // place of each problem-order tile in the launch list
+        g.n_inner = (int)in.size();
+        g.ntiles = (int)(in.size() + out.size());
+        {
+            std::map<std::pair<int, std::pair<int, int>>, int> at;
+            for (size_t t = 0; t < in.size(); ++t) at[{in[t].prob, {in[t].i0, in[t].ja}}] = (int)t;
+            for (size_t t = 0; t < out.size(); ++t) at[{out[t].prob, {out[t].i0, out[t].ja}}] = g.n_inner + (int)t;
+            g.pos.resize(all.size());
+            for (size_t t = 0; t < all.size(); ++t) g.pos[t] = at[{all[t].prob, {all[t].i0, all[t].ja}}];
+        }
+        in.insert(in.end(), out.begin(), out.end());
+        g.tiles = (Tile2T *)b.al.get(in.size() * sizeof(Tile2T));
+        hip_check(hipMemcpyAsync(g.tiles, in.data(), in.size() * sizeof(Tile2T), hipMemcpyHostToDevice, b.st),
+                  "upload");
+        hip_check(hipStreamSynchronize(b.st), "sync");
+        b.tbg.push_back(g);
+    }
+}
+
 static void batch_launch_one(fdtd_batch &b, int parity, int k, hipStream_t st) {
     for (auto &g : b.groups) {
         ProbeTiles pt{g.pt_start, g.pt_cell, g.pt_slot};
@@ -323,50 +384,7 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
             hip_check(hipStreamSynchronize(b->st), "sync");
             b->groups.push_back(g);
         }
-        // multi-step groups: vector width 4, 2 or 1 by row length
-        for (int V : {4, 2, 1}) {
-            TBGroup g;
-            g.V = V;
-            g.TB = b->tb;
-            std::vector<Tile2T> in, out, all;
-            for (int q = 0; q < n; ++q) {
-                const Sim &s = *b->sims[(size_t)q];
-                const int vq = s.ny % 4 == 0 ? 4 : (s.ny % 2 == 0 ? 2 : 1);
-                if (vq != V) continue;
-                if (!tb2d_supported(s.ny, V, g.TB, g.TX)) fail(FDTD_EINVAL, "multi-step configuration");
-                g.probs.push_back(q);
-                g.mat = std::max(g.mat, s.mat());
-                g.pos_base.push_back((int)all.size());
-                std::vector<Tile2T> a, c;
-                const int xl[2] = {s.ax[0].lo, s.ax[0].hi}, yl[2] = {s.ax[1].lo, s.ax[1].hi};
-                tb2d_plan(q, s.nx, s.ny, V, g.TB, g.TX, xl, yl, a, c);
-                // problem-order list (row chunk by row chunk, strips inside)
-                const int ow = tb2d_own(V, g.TB), nstrip = (s.ny + ow - 1) / ow;
-                std::vector<Tile2T> po((size_t)((s.nx + g.TX - 1) / g.TX) * nstrip);
-                for (const auto &t : a) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
-                for (const auto &t : c) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
-                for (const auto &t : po) all.push_back(t);
-                in.insert(in.end(), a.begin(), a.end());
-                out.insert(out.end(), c.begin(), c.end());
-            }
-            if (g.probs.empty()) continue;
-            // place of each problem-order tile in the launch list
-            g.n_inner = (int)in.size();
-            g.ntiles = (int)(in.size() + out.size());
-            {
-                std::map<std::pair<int, std::pair<int, int>>, int> at;
-                for (size_t t = 0; t < in.size(); ++t) at[{in[t].prob, {in[t].i0, in[t].ja}}] = (int)t;
-                for (size_t t = 0; t < out.size(); ++t) at[{out[t].prob, {out[t].i0, out[t].ja}}] = g.n_inner + (int)t;
-                g.pos.resize(all.size());
-                for (size_t t = 0; t < all.size(); ++t) g.pos[t] = at[{all[t].prob, {all[t].i0, all[t].ja}}];
-            }
-            in.insert(in.end(), out.begin(), out.end());
-            g.tiles = (Tile2T *)b->al.get(in.size() * sizeof(Tile2T));
-            hip_check(hipMemcpyAsync(g.tiles, in.data(), in.size() * sizeof(Tile2T), hipMemcpyHostToDevice, b->st),
-                      "upload");
-            hip_check(hipStreamSynchronize(b->st), "sync");
-            b->tbg.push_back(g);
-        }
+        batch_build_tb(*b);
         b->step_base = (int64_t *)b->al.get(sizeof(int64_t));
         hip_check(hipEventCreate(&b->ev0), "event");
         hip_check(hipEventCreate(&b->ev1), "event");
@@ -378,6 +396,34 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
         const int rc = gem::status_of_current_exception();
         delete b;
         return rc;
+    }
+}
+
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax) {
+    try {
+        if (!b) fail(FDTD_EINVAL, "batch is NULL");
+        if (!(tb == 1 || tb == 2 || tb == 4) || tx < 1 || tx > 65536 || !(vmax == 1 || vmax == 2 || vmax == 4))
+            fail(FDTD_EINVAL, "unsupported batch kernel configuration");
+        hip_check(hipStreamSynchronize(b->st), "sync");
+        const int otb = b->tb, otx = b->tb_tx, ov = b->tb_vmax;
+        b->tb = tb;
+        b->tb_tx = tx;
+        b->tb_vmax = vmax;
+        try {
+            batch_build_tb(*b);
+        } catch (...) {
+            b->tb = otb;
+            b->tb_tx = otx;
+            b->tb_vmax = ov;
+            batch_build_tb(*b);
+            batch_build_probes(*b);
+            throw;
+        }
+        batch_build_probes(*b);
+        set_error("");
+        return FDTD_OK;
+    } catch (...) {
+        return gem::status_of_current_exception();
     }
 }
 

@@ -308,6 +308,10 @@ class Batch:
     def step(self, n):
         L.call("fdtd_batch_step", self.h, int(n))
 
+    def set_kernel(self, tb=4, tx=16, vmax=2):
+        """Steps per pass (1, 2, 4), rows per tile, widest column vector."""
+        L.call("fdtd_batch_set_kernel", self.h, int(tb), int(tx), int(vmax))
+
     def probe(self, q):
         n = C.c_int64()
         L.call("fdtd_batch_probe", self.h, int(q), None, 0, C.byref(n))

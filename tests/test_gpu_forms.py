@@ -92,6 +92,31 @@ def test_batch_matches_single_and_oracle():
     b.close()
 
 
+@pytest.mark.parametrize("cfg", [(1, 16, 4), (2, 5, 2), (4, 1, 1), (4, 40, 4)])
+def test_batch_kernel_configs(cfg):
+    """Single steps only, two steps per pass with two-column vectors, one-row
+    tiles, long tiles: the same fields as the single-problem stepper."""
+    from paper_2405_00814_amd.sim import Batch
+    probs = W.batch2d(count=5, steps=0, seed=7, side=(66, 150), nprobes=2, rect_side=(8, 30),
+                      rect_density=40.0 / 4096)
+    b = Batch(probs)
+    b.set_kernel(*cfg)
+    b.step(9)
+    b.step(70)
+    n = 79
+    for q, pb in enumerate(probs):
+        single, srec, _ = run_gpu(pb, n)
+        for k in single:
+            assert rel_l2(b.get_field(q, k), single[k]) <= 1e-5, (cfg, q, k)
+        assert rel_l2(b.probe(q), srec) <= 1e-5
+    from paper_2405_00814_amd._lib import FdtdError
+    for bad in ((3, 16, 4), (4, 0, 4), (4, 16, 3)):
+        with pytest.raises(FdtdError):
+            b.set_kernel(*bad)
+    b.step(4)  # still usable after a rejected configuration
+    b.close()
+
+
 # ---------------------------------------------------------------------------
 # Adjoint
 # ---------------------------------------------------------------------------
