@@ -192,7 +192,8 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    slabs.
  *    2D multi-step (variant 3 on a 2D grid): tile[0] = V (1, 2 or 4; ny % V
  *    must be 0; 0 = 1), tile[1] = TX (rows per tile, 1..65536; 0 = 4), tile[2] =
- *    TB (leapfrog steps per pass: 2 or 4; 0 = 4); tile[3] must be 0.  Each
+ *    TB (leapfrog steps per pass: 2 or 4; 0 = 4), tile[3] = rows per tile
+ *    of the tiles near a CPML slab (0 = TX; at most 65536).  Each
  *    wavefront advances its rows and columns TB steps, recomputing the
  *    neighbouring rows and columns it needs; an n not divisible by TB ends
  *    with single steps.
@@ -261,10 +262,11 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n);
 /* Kernel configuration of the batch: tb leapfrog steps per pass (1, 2 or
  * 4; 1 = single steps only), tx rows per wavefront tile (1..65536), vmax
  * the widest vector of columns per lane (1, 2 or 4; each problem takes the
- * widest its row length allows).  Default 4, 16, 2.  Synchronises; the
- * state is kept.  FDTD_EINVAL for other values (the configuration is then
+ * widest its row length allows), txo rows per tile of the tiles near a
+ * CPML slab (0 = tx).  Default 4, 16, 2, 0.  Synchronises; the state is
+ * kept.  FDTD_EINVAL for other values (the configuration is then
  * unchanged). */
-int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax);
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax, int32_t txo);
 int fdtd_batch_probe(fdtd_batch *b, int32_t problem, float *out, int64_t cap,
                      int64_t *n_recorded);
 int fdtd_batch_get_field(fdtd_batch *b, int32_t problem, int component, void *dst,

@@ -87,7 +87,7 @@ _SIGS = {
     "fdtd_batch_set_source": (C.c_int, [P, i32, i32p, C.c_int, f64p, f32p, i64]),
     "fdtd_batch_set_probes": (C.c_int, [P, i32, i32p, i32]),
     "fdtd_batch_step": (C.c_int, [P, i64]),
-    "fdtd_batch_set_kernel": (C.c_int, [P, i32, i32, i32]),
+    "fdtd_batch_set_kernel": (C.c_int, [P, i32, i32, i32, i32]),
     "fdtd_batch_probe": (C.c_int, [P, i32, f32p, i64, i64p]),
     "fdtd_batch_get_field": (C.c_int, [P, i32, C.c_int, P, C.c_int]),
     "fdtd_batch_last_step_time": (C.c_int, [P, C.POINTER(C.c_float), i64p]),

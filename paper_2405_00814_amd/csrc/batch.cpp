@@ -39,7 +39,8 @@ struct TBGroup {
     int ntiles = 0, n_inner = 0;
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
     std::vector<int> pos_base;  // per problem of the group: first entry in pos
-    std::vector<int> pos;       // (problem, row chunk, strip) -> place in the list
+    std::vector<int> pos;       // (problem, row, strip) -> place in the launch list of the
+                                // tile starting there, -1 where none starts
 };
 
 }  // namespace gem
@@ -54,6 +55,7 @@ struct fdtd_batch {
     std::vector<gem::TBGroup> tbg;
     int tb = 4;   // steps per multi-step pass (1: single steps only)
     int tb_tx = 16, tb_vmax = 2;
+    int tb_txo = 0;  // rows per tile with the CPML code (0: tb_tx)
     int cur = 0;  // buffer set holding the current state
     gem::Prob2D *probs_dev[2] = {nullptr, nullptr};
     std::vector<const void *> probs_key[2];
@@ -135,7 +137,10 @@ static void batch_build_probes(fdtd_batch &b) {
             const int nstrip = (s.ny + ow - 1) / ow;
             for (size_t p = 0; p < s.probe_cells.size(); ++p) {
                 const int i = (int)(s.probe_cells[p] / s.ny), j = (int)(s.probe_cells[p] % s.ny);
-                ent.push_back({g.pos[(size_t)(g.pos_base[qi] + (i / g.TX) * nstrip + j / ow)], (int)cells_all.size()});
+                // the tile that starts at or last before row i
+                int r = i;
+                while (g.pos[(size_t)(g.pos_base[qi] + r * nstrip + j / ow)] < 0) --r;
+                ent.push_back({g.pos[(size_t)(g.pos_base[qi] + r * nstrip + j / ow)], (int)cells_all.size()});
                 cells_all.push_back((int)s.probe_cells[p]);
                 slots_all.push_back((int)p);
             }
@@ -228,12 +233,12 @@ static void batch_build_tb(fdtd_batch &b) {
             g.pos_base.push_back((int)all.size());
             std::vector<Tile2T> a, c;
             const int xl[2] = {s.ax[0].lo, s.ax[0].hi}, yl[2] = {s.ax[1].lo, s.ax[1].hi};
-            tb2d_plan(q, s.nx, s.ny, V, g.TB, g.TX, xl, yl, a, c);
-            // problem-order list (row chunk by row chunk, strips inside)
+            tb2d_plan(q, s.nx, s.ny, V, g.TB, g.TX, b.tb_txo, xl, yl, a, c);
+            // problem-order list by (row, strip) of each tile's first row
             const int ow = tb2d_own(V, g.TB), nstrip = (s.ny + ow - 1) / ow;
-            std::vector<Tile2T> po((size_t)((s.nx + g.TX - 1) / g.TX) * nstrip);
-            for (const auto &t : a) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
-            for (const auto &t : c) po[(size_t)(t.i0 / g.TX) * nstrip + t.ja / ow] = t;
+            std::vector<Tile2T> po((size_t)s.nx * nstrip, Tile2T{-1, 0, 0, 0});
+            for (const auto &t : a) po[(size_t)t.i0 * nstrip + t.ja / ow] = t;
+            for (const auto &t : c) po[(size_t)t.i0 * nstrip + t.ja / ow] = t;
             for (const auto &t : po) all.push_back(t);
             in.insert(in.end(), a.begin(), a.end());
             out.insert(out.end(), c.begin(), c.end());
@@ -247,7 +252,8 @@ static void batch_build_tb(fdtd_batch &b) {
             for (size_t t = 0; t < in.size(); ++t) at[{in[t].prob, {in[t].i0, in[t].ja}}] = (int)t;
             for (size_t t = 0; t < out.size(); ++t) at[{out[t].prob, {out[t].i0, out[t].ja}}] = g.n_inner + (int)t;
             g.pos.resize(all.size());
-            for (size_t t = 0; t < all.size(); ++t) g.pos[t] = at[{all[t].prob, {all[t].i0, all[t].ja}}];
+            for (size_t t = 0; t < all.size(); ++t)
+                g.pos[t] = all[t].prob < 0 ? -1 : at[{all[t].prob, {all[t].i0, all[t].ja}}];
         }
         in.insert(in.end(), out.begin(), out.end());
         g.tiles = (Tile2T *)b.al.get(in.size() * sizeof(Tile2T));
@@ -399,22 +405,25 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
     }
 }
 
-int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax) {
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax, int32_t txo) {
     try {
         if (!b) fail(FDTD_EINVAL, "batch is NULL");
-        if (!(tb == 1 || tb == 2 || tb == 4) || tx < 1 || tx > 65536 || !(vmax == 1 || vmax == 2 || vmax == 4))
+        if (!(tb == 1 || tb == 2 || tb == 4) || tx < 1 || tx > 65536 || !(vmax == 1 || vmax == 2 || vmax == 4) ||
+            txo < 0 || txo > 65536)
             fail(FDTD_EINVAL, "unsupported batch kernel configuration");
         hip_check(hipStreamSynchronize(b->st), "sync");
-        const int otb = b->tb, otx = b->tb_tx, ov = b->tb_vmax;
+        const int otb = b->tb, otx = b->tb_tx, ov = b->tb_vmax, oo = b->tb_txo;
         b->tb = tb;
         b->tb_tx = tx;
         b->tb_vmax = vmax;
+        b->tb_txo = txo;
         try {
             batch_build_tb(*b);
         } catch (...) {
             b->tb = otb;
             b->tb_tx = otx;
             b->tb_vmax = ov;
+            b->tb_txo = oo;
             batch_build_tb(*b);
             batch_build_probes(*b);
             throw;

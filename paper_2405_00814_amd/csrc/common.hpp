@@ -129,8 +129,9 @@ bool tb2d_supported(int ny, int V, int TB, int TX);
 // Tiles of one problem: rows in chunks of TX, strips of tb2d_own(V, TB)
 // columns; `inner` takes the tiles whose dependency cone (rows i0-TB ..
 // i1+TB-1, the strip's loaded columns) is clear of the CPML slabs, `outer`
-// the others.  Ordered row chunk by row chunk.
-void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi, const int *ylohi,
+// the others, cut into pieces of TXo rows (< 1: TX).  Ordered row chunk by
+// row chunk.
+void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, int TXo, const int *xlohi, const int *ylohi,
                std::vector<Tile2T> &inner, std::vector<Tile2T> &outer);
 // Capture of the design cells for the adjoint: for every step n of the
 // pass, at cell (i, j) of the box design = [x, y) x [z, w), Ez before the E

@@ -12,8 +12,9 @@ bool tb2d_supported(int ny, int V, int TB, int TX) {
     return ny % V == 0;
 }
 
-void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi, const int *ylohi,
+void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, int TXo, const int *xlohi, const int *ylohi,
                std::vector<Tile2T> &inner, std::vector<Tile2T> &outer) {
+    if (TXo < 1) TXo = TX;
     const int ow = tb2d_own(V, TB), hw = tb2d_halo(V, TB) * V;
     auto clear = [](int n, int lo, int hi, int a, int b) {  // no slab index in [a, b)
         a = std::max(a, 0);
@@ -27,7 +28,12 @@ void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, const int *xlohi
         const bool xc = clear(nx, xlohi[0], xlohi[1], i0 - TB, i1 + TB);
         for (int ja = 0; ja < ny; ja += ow) {
             const bool yc = clear(ny, ylohi[0], ylohi[1], ja - hw, ja - hw + 64 * V);
-            (xc && yc ? inner : outer).push_back(Tile2T{prob, i0, i1, ja});
+            if (xc && yc) {
+                inner.push_back(Tile2T{prob, i0, i1, ja});
+            } else {
+                // tiles with the CPML code in pieces of TXo rows
+                for (int a = i0; a < i1; a += TXo) outer.push_back(Tile2T{prob, a, std::min(a + TXo, i1), ja});
+            }
         }
     }
 }

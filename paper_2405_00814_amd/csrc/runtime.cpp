@@ -348,20 +348,23 @@ void Sim::build_probe_tiles() {
         const int V = kcfg.tile[0], TX = kcfg.tile[1], TB = kcfg.tile[2];
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
         std::vector<Tile2T> in, out;
-        tb2d_plan(0, nx, ny, V, TB, TX, xl, yl, in, out);
+        tb2d_plan(0, nx, ny, V, TB, TX, kcfg.tile[3], xl, yl, in, out);
         tb2_inner = (int)in.size();
         tb2_outer = (int)out.size();
         in.insert(in.end(), out.begin(), out.end());
         al.put(tb2_dev);
         tb2_dev = dev_upload(al, in.data(), std::max<size_t>(in.size(), 1), st);
-        // probe groups by position in the list
+        // probe groups by position in the list: the tile starting at or
+        // last before the probe's row in its strip
         const int ow = tb2d_own(V, TB), nstrip = (ny + ow - 1) / ow;
-        std::vector<int> pos((size_t)((nx + TX - 1) / TX) * nstrip, -1);
-        for (size_t q = 0; q < in.size(); ++q) pos[(size_t)(in[q].i0 / TX) * nstrip + in[q].ja / ow] = (int)q;
+        std::vector<int> pos((size_t)nx * nstrip, -1);
+        for (size_t q = 0; q < in.size(); ++q) pos[(size_t)in[q].i0 * nstrip + in[q].ja / ow] = (int)q;
         std::vector<int> tl(probe_cells.size());
         for (size_t q = 0; q < probe_cells.size(); ++q) {
-            const int i = (int)(probe_cells[q] / ny), j = (int)(probe_cells[q] % ny);
-            tl[q] = pos[(size_t)(i / TX) * nstrip + j / ow];
+            int i = (int)(probe_cells[q] / ny);
+            const int j = (int)(probe_cells[q] % ny);
+            while (pos[(size_t)i * nstrip + j / ow] < 0) --i;
+            tl[q] = pos[(size_t)i * nstrip + j / ow];
         }
         std::vector<int> ord(probe_cells.size());
         for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int)q;
@@ -596,7 +599,7 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.variant != 2 && k.variant != 3) return false;
     if (s.ndim == 2) {
         if (k.variant == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
-        return k.tile[3] == 0 && tb2d_supported(s.ny, k.tile[0], k.tile[2], k.tile[1]) &&
+        return k.tile[3] >= 0 && k.tile[3] <= 65536 && tb2d_supported(s.ny, k.tile[0], k.tile[2], k.tile[1]) &&
                fused2d_supported(s.nx, s.ny, default_single2d(s.nx, s.ny));
     }
     if (k.tile[1] != 0 || k.tile[3] != 0) return false;

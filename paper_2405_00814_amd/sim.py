@@ -308,9 +308,10 @@ class Batch:
     def step(self, n):
         L.call("fdtd_batch_step", self.h, int(n))
 
-    def set_kernel(self, tb=4, tx=16, vmax=2):
-        """Steps per pass (1, 2, 4), rows per tile, widest column vector."""
-        L.call("fdtd_batch_set_kernel", self.h, int(tb), int(tx), int(vmax))
+    def set_kernel(self, tb=4, tx=16, vmax=2, txo=0):
+        """Steps per pass (1, 2, 4), rows per tile, widest column vector,
+        rows per tile near a CPML slab (0: tx)."""
+        L.call("fdtd_batch_set_kernel", self.h, int(tb), int(tx), int(vmax), int(txo))
 
     def probe(self, q):
         n = C.c_int64()

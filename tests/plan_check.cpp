@@ -102,14 +102,15 @@ int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl
 }
 // 2D multi-step plan: own columns [ja, ja + own) and rows [i0, i1) of the
 // tiles cover the grid once; interior tiles' cones clear of the slabs
-int check2d(int nx, int ny, int V, int TB, int TX, const int *xl, const int *yl) {
+int check2d(int nx, int ny, int V, int TB, int TX, int TXo, const int *xl, const int *yl) {
     std::vector<Tile2T> in, out;
-    tb2d_plan(7, nx, ny, V, TB, TX, xl, yl, in, out);
+    tb2d_plan(7, nx, ny, V, TB, TX, TXo, xl, yl, in, out);
     std::vector<int> cov((size_t)nx * ny, 0);
     const int ow = tb2d_own(V, TB), hw = tb2d_halo(V, TB) * V;
     for (int pass = 0; pass < 2; ++pass)
         for (const Tile2T &t : pass ? out : in) {
-            if (t.prob != 7 || t.i0 < 0 || t.i1 > nx || t.i0 >= t.i1 || t.i1 - t.i0 > TX || t.ja < 0 || t.ja >= ny ||
+            if (t.prob != 7 || t.i0 < 0 || t.i1 > nx || t.i0 >= t.i1 || t.i1 - t.i0 > (pass && TXo > 0 ? TXo : TX) ||
+                t.ja < 0 || t.ja >= ny ||
                 t.ja % V) {
                 printf("bad 2d tile\n");
                 return 1;
@@ -168,8 +169,9 @@ int main() {
         for (int q = 0; q < 4; ++q) s[q] = rand() % 3 == 0 ? 0 : rand() % 20;
         if (s[0] + s[1] >= nx) s[0] = s[1] = 0;
         if (s[2] + s[3] >= ny) s[2] = s[3] = 0;
-        const int r = check2d(nx, ny, V, TB, TX, s, s + 2);
-        if (r) printf("  2d case nx %d ny %d V %d TB %d TX %d s %d %d %d %d\n", nx, ny, V, TB, TX, s[0], s[1], s[2], s[3]);
+        const int TXo = rand() % 3 == 0 ? 0 : 1 + rand() % 10;
+        const int r = check2d(nx, ny, V, TB, TX, TXo, s, s + 2);
+        if (r) printf("  2d case nx %d ny %d V %d TB %d TX %d TXo %d s %d %d %d %d\n", nx, ny, V, TB, TX, TXo, s[0], s[1], s[2], s[3]);
         bad += r;
     }
     printf("%d / %d bad\n", bad, n);

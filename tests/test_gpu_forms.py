@@ -92,10 +92,11 @@ def test_batch_matches_single_and_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("cfg", [(1, 16, 4), (2, 5, 2), (4, 1, 1), (4, 40, 4)])
+@pytest.mark.parametrize("cfg", [(1, 16, 4, 0), (2, 5, 2, 3), (4, 1, 1, 0), (4, 40, 4, 2)])
 def test_batch_kernel_configs(cfg):
-    """Single steps only, two steps per pass with two-column vectors, one-row
-    tiles, long tiles: the same fields as the single-problem stepper."""
+    """Single steps only, two steps per pass with two-column vectors and
+    3-row tiles near the slabs, one-row tiles, long tiles: the same fields as
+    the single-problem stepper."""
     from paper_2405_00814_amd.sim import Batch
     probs = W.batch2d(count=5, steps=0, seed=7, side=(66, 150), nprobes=2, rect_side=(8, 30),
                       rect_density=40.0 / 4096)
@@ -110,7 +111,7 @@ def test_batch_kernel_configs(cfg):
             assert rel_l2(b.get_field(q, k), single[k]) <= 1e-5, (cfg, q, k)
         assert rel_l2(b.probe(q), srec) <= 1e-5
     from paper_2405_00814_amd._lib import FdtdError
-    for bad in ((3, 16, 4), (4, 0, 4), (4, 16, 3)):
+    for bad in ((3, 16, 4), (4, 0, 4), (4, 16, 3), (4, 16, 2, -1)):
         with pytest.raises(FdtdError):
             b.set_kernel(*bad)
     b.step(4)  # still usable after a rejected configuration

@@ -47,7 +47,7 @@ def test_tb2d_mu_map_kappa_alpha_asymmetric():
     pb.mu_r = np.random.default_rng(5).uniform(1.0, 2.5, pb.shape).astype(np.float32)
     pb.npml = (4, 12, 0, 9)
     ref, rrec = run_oracle(pb, pb.steps)
-    for kernel in ((3, (2, 8, 2)), (3, (4, 5, 4)), (3, (2, 64, 4))):
+    for kernel in ((3, (2, 8, 2)), (3, (4, 5, 4)), (3, (2, 64, 4, 3))):
         got, rec, _ = run_gpu(pb, pb.steps, kernel)
         assert_parity(got, ref, TOL, "tb2d mu %s" % (kernel,))
         assert rel_l2(rec, rrec) <= TOL
@@ -95,7 +95,7 @@ def test_tb2d_profile_and_rules():
     for f in ("ez", "hx", "hy"):
         assert np.array_equal(a.get_field(f), b.get_field(f)), f
     assert np.array_equal(a.probe(), b.probe())
-    for bad in ((3, (4, 16, 3)), (3, (8, 16, 2)), (3, (3, 16, 2)), (3, (4, 16, 2, 1))):
+    for bad in ((3, (4, 16, 3)), (3, (8, 16, 2)), (3, (3, 16, 2)), (3, (4, 16, 2, -1))):
         with pytest.raises(FdtdError):
             a.set_kernel(*bad)
     a.close()
