@@ -175,12 +175,16 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *  variant: 0 = auto (autotuned or default), 1 = two-pass reference
  *           (separate H and E kernels, in place), 2 = fused single pass
  *           (one kernel per step, double-buffered state), 3 = several
- *           leapfrog steps per pass over memory.  3D: tiles whose
- *           dependency cone stays clear of the x and y CPML slabs advance
- *           two steps in one kernel (state n+1 never leaves the chip); the
- *           rest takes two fused single steps through a third state set
- *           (allocated on first use, 24 B per cell plus the CPML auxiliary
- *           values).  An odd remainder of fdtd_step's n is one single step.
+ *           leapfrog steps per pass over memory.  3D: every tile
+ *           advances two steps in one kernel (state n+1 never leaves the
+ *           chip, the x/y-CPML auxiliary values of step n+1 excepted: they
+ *           pass through a third state set, allocated on first use, 24 B
+ *           per cell plus the CPML auxiliary values); tiles whose
+ *           dependency cone stays clear of the x and y CPML slabs run a
+ *           kernel without x/y-CPML code.  With tile[1] = 1 the tiles near
+ *           the x/y slabs take two fused single steps through the third
+ *           set instead.  An odd remainder of fdtd_step's n is one single
+ *           step.
  *  tile[0..3]: variant-specific tile sizes (0 = default); tb reserved (1).
  *    2D fused: tile[0] = V (1, 2 or 4 consecutive y cells per lane; ny % V
  *    must be 0), tile[1] = TX (x rows marched by one wavefront).
@@ -189,7 +193,9 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    16, at most 4096); tile[1] and tile[3] must be 0.
  *    3D two-step: as 3D fused with V = 4; also nz <= 512, at most 64
  *    z-CPML cells in all, and no 4-cell z group holding cells of both z
- *    slabs.
+ *    slabs; tile[1] = 0 (tiles near the x/y slabs in the two-step kernel)
+ *    or 1 (as two single steps); tile[3] = x planes per tile over the
+ *    x-CPML ends (0 = tile[2]'s value, at most 4096).
  *    2D multi-step (variant 3 on a 2D grid): tile[0] = V (1, 2 or 4; ny % V
  *    must be 0; 0 = 1), tile[1] = TX (rows per tile, 1..65536; 0 = 4), tile[2] =
  *    TB (leapfrog steps per pass: 2 or 4; 0 = 4), tile[3] = rows per tile

@@ -193,27 +193,35 @@ constexpr int kTwoZMax = 64;
 // Wavefronts per workgroup of the two-step kernel.  The instances with
 // z-slab CPML or a Db map need more registers: 12 wavefronts (168 VGPRs)
 // instead of 16 (128).
-constexpr int two_waves(bool pz, int mat) { return (pz || mat == 2) ? 12 : 16; }
+constexpr int two_waves(bool pz, int mat, bool pxy = false) { return (pz || mat == 2 || pxy) ? 12 : 16; }
 // nz % 4 == 0, nz <= 512, zlo + zhi <= kTwoZMax, and no 4-cell group holds
 // cells of both z slabs
 bool two3d_supported(int nx, int ny, int nz, int zlo, int zhi);
 // rows per band (the workgroup holds two halo rows more, RZ wavefronts per
 // row)
-int two3d_rows(int nz, bool pz, int mat);  // mat: 0 Cb, 1 Ca+Cb, 2 Ca+Cb+Db maps
-// records probes at steps `step` and `step`+1 of cells it owns
+int two3d_rows(int nz, bool pz, int mat, bool pxy);  // mat: 0 Cb, 1 Ca+Cb, 2 Ca+Cb+Db maps
+// records probes at steps `step` and `step`+1 of cells it owns.  mid:
+// nullptr for tiles whose cone is clear of the x/y slabs; else the state
+// set whose x/y-slab psi arrays hold the step-1 psi (any tiles).
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                         hipStream_t st);
-// Plan of a two-step pass: the interior tiles run the two-step kernel; the
-// rest (S, tiles whose cone touches an x or y slab) runs two single steps:
-// pass1 over S and its one-cell rim M (state n -> a third state set, probes
-// recorded in S only), pass2 over S (third set -> state n+2).
+                         hipStream_t st, const State3D *mid = nullptr);
+// Plan of a two-step pass.  The interior tiles (cone clear of the x/y
+// slabs) run the two-step kernel without x/y-slab code.  The rest, S:
+//   slab_tb: tiles of the two-step kernel with x/y-slab code (tbo: x chunks
+//     of txo planes, 0 = TX, over the x-slab ends), which keep the step-1
+//     psi in a third state set;
+//   else two single steps: pass1 over S and its one-cell rim M (state n ->
+//     the third state set, probes recorded in S only), pass2 over S (third
+//     set -> state n+2).
 struct TwoPlan {
-    std::vector<TileTB> tb;  // padded to a multiple of 8
-    int64_t tb_cells = 0, tb_psi = 0;
+    bool slab_tb = false;
+    int rows = 0, rows_o = 0;  // rows per band: tb, tbo
+    std::vector<TileTB> tb, tbo;  // each padded to a multiple of 8
+    int64_t tb_cells = 0, tb_psi = 0, tbo_cells = 0, tbo_psi = 0;
     Wave3DPlan pass1, pass2;
 };
-void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int *xlohi, const int *ylohi,
-                const int *zlohi, TwoPlan &pl);
+void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_tb, int txo, const int *xlohi,
+                const int *ylohi, const int *zlohi, TwoPlan &pl);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

@@ -1,6 +1,6 @@
-// Two leapfrog steps per pass over HBM (temporal blocking) for the interior
-// of the 3D grid: state n is read once, state n+2 written once, state n+1
-// lives in registers and LDS only.
+// Two leapfrog steps per pass over HBM (temporal blocking) for the 3D grid:
+// state n is read once, state n+2 written once, state n+1 lives in
+// registers and LDS only (its x/y-slab psi excepted, see below).
 //
 // A workgroup holds R+2 y rows (its R rows plus one halo row above and one
 // below) of full z length (RZ wavefronts of 64 lanes x V cells per row) and
@@ -19,8 +19,12 @@
 // that needs them, identically, so tiles stay independent (no grid barrier).
 // z-slab CPML: correction of the slab lanes as in the single-step kernel;
 // their step-1 psi values wait in LDS (indexed by slab cell) until step 2.
-// Tiles whose dependency cone (planes i0-2 .. i1, rows j0-2 .. j0+R) touches
-// an x or y CPML slab are advanced by two single steps instead.
+// x/y-slab CPML (instances with PXY, for the tiles whose dependency cone,
+// planes i0-2 .. i1 and rows j0-2 .. j0+R, touches an x or y slab; the
+// others run without that code): the plane's and the row's profiles are
+// wave-uniform scalars; the step-1 psi of a slab cell goes to the psi
+// arrays of a third state set (the same thread reads it back at the next
+// plane; a halo row's value, written by two tiles, is the same in both).
 #include <algorithm>
 #include <vector>
 
@@ -30,9 +34,9 @@
 
 namespace gem {
 
-template <int V, int RZ, int R, bool PZ, int MAT>
+template <int V, int RZ, int R, bool PZ, bool PXY, int MAT>
 __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const TileTB *tiles, ProbeTiles pt,
-                                                           int64_t step) {
+                                                           int64_t step, State3D mid) {
     constexpr int NR = R + 2;            // rows held: halo, R own, halo
     constexpr int NT = 64 * RZ * NR;     // threads
     constexpr int SEG = 64 * V;          // z cells per wavefront
@@ -59,10 +63,18 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     const float *hx0 = p.s0.f[FDTD_HX], *hy0 = p.s0.f[FDTD_HY], *hz0 = p.s0.f[FDTD_HZ];
     float *const *P0 = p.s0.psi;
     float *const *P1 = p.s1.psi;
+    float *const *PM = mid.psi;  // x/y-slab psi of state n+1 (PXY)
+    const int sy = p.y.lo + p.y.hi;
     const int tq = (int)threadIdx.x * V;
-    // the tile's x and y profiles are the interior ones (no slab in the cone)
+    // x and y profiles: without x/y-slab code the interior ones (no slab in
+    // the cone), else those of the plane and the row
     const float ikx = p.x.kH[p.x.lo], iky = p.y.kH[p.y.lo], jkx = p.x.kE[p.x.lo], jky = p.y.kE[p.y.lo];
     const float idzH = p.z.kH[p.z.lo], idzE = p.z.kE[p.z.lo];
+    auto prof = [&](const AxisDev &a, int q, float kh, float ke) {
+        if constexpr (PXY) return axp<true>(a, q);
+        else return AxP{kh, ke, 0.f, 0.f, 0.f, 0.f, -1};
+    };
+    const AxP Y = prof(p.y, jr, iky, jky);                             // row j
 
     __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
     __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
@@ -114,11 +126,14 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         return lane == 0 ? seam : s;
     };
     // H from E: own, +x, +y, +z seam; the z differences are kept for the
-    // slab correction
+    // slab correction.  Xa, Ya: profiles of the cells' plane and row.  With
+    // x/y-slab code, q holds the psi of the slabs the cells lie in (old in,
+    // new out): q[0] Hx-y, q[1] Hz-y (y slab: iny), q[2] Hy-x, q[3] Hz-x
+    // (x slab: inx).
     auto hstep = [&](float (&hx)[V], float (&hy)[V], float (&hz)[V], const float (&db)[V], const float (&ex)[V],
                      const float (&ey)[V], const float (&ez)[V], const float (&eyx)[V], const float (&ezx)[V],
                      const float (&exy)[V], const float (&ezy)[V], float exs, float eys, float (&dyz)[V],
-                     float (&dxz)[V]) {
+                     float (&dxz)[V], const AxP &Xa, const AxP &Ya, bool inx, bool iny, float (&q)[4][V]) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const float dEzy = ezy[v] - ez[v];
@@ -127,9 +142,22 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             const float dEzx = ezx[v] - ez[v], dEyx = eyx[v] - ey[v], dExy = exy[v] - ex[v];
             dyz[v] = dEyz;
             dxz[v] = dExz;
-            hx[v] = hx[v] - db[v] * ((iky * dEzy) - (idzH * dEyz));
-            hy[v] = hy[v] - db[v] * ((idzH * dExz) - (ikx * dEzx));
-            hz[v] = hz[v] - db[v] * ((ikx * dEyx) - (iky * dExy));
+            float ty = Ya.kH * dEzy, tzy = Ya.kH * dExy, tx = Xa.kH * dEzx, tzx = Xa.kH * dEyx;
+            if (PXY && iny) {
+                q[0][v] = Ya.bH * q[0][v] + Ya.cH * dEzy;
+                q[1][v] = Ya.bH * q[1][v] + Ya.cH * dExy;
+                ty += q[0][v];
+                tzy += q[1][v];
+            }
+            if (PXY && inx) {
+                q[2][v] = Xa.bH * q[2][v] + Xa.cH * dEzx;
+                q[3][v] = Xa.bH * q[3][v] + Xa.cH * dEyx;
+                tx += q[2][v];
+                tzx += q[3][v];
+            }
+            hx[v] = hx[v] - db[v] * (ty - (idzH * dEyz));
+            hy[v] = hy[v] - db[v] * ((idzH * dExz) - tx);
+            hz[v] = hz[v] - db[v] * (tzx - tzy);
         }
     };
     // z-slab correction of H (psi in o1 = Hx-z, o2 = Hy-z: old in, new out)
@@ -144,11 +172,14 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             if (fy) hy[v] -= db[v] * (kh * dxz[v] + o2[v]);
         }
     };
-    // E from H: own, -x, -y, -z seam (ex/ey/ez old in, new out)
+    // E from H: own, -x, -y, -z seam (ex/ey/ez old in, new out).  With
+    // x/y-slab code, q: q[0] Ex-y, q[1] Ez-y (y slab), q[2] Ey-x, q[3] Ez-x
+    // (x slab); the psi of a cell the E layer does not update stays.
     auto estep = [&](float (&ex)[V], float (&ey)[V], float (&ez)[V], const float (&ca)[V], const float (&cb)[V],
                      const float (&hx)[V], const float (&hy)[V], const float (&hz)[V], const float (&hyp)[V],
                      const float (&hzp)[V], const float (&hxj)[V], const float (&hzj)[V], float hxs, float hys,
-                     bool im, float (&dyz)[V], float (&dxz)[V]) {
+                     bool im, float (&dyz)[V], float (&dxz)[V], const AxP &Xa, const AxP &Ya, bool inx, bool iny,
+                     float (&q)[4][V]) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             dyz[v] = hy[v] - prv(hy, v, hys);
@@ -159,9 +190,44 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             const int k = kb + v;
             const float dHzy = hz[v] - hzj[v], dHzx = hz[v] - hzp[v];
             const float dHyx = hy[v] - hyp[v], dHxy = hx[v] - hxj[v];
-            if (jm && k >= 1) ex[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * ((jky * dHzy) - (idzE * dyz[v]));
-            if (im && k >= 1) ey[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * ((idzE * dxz[v]) - (jkx * dHzx));
-            if (im && jm) ez[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * ((jkx * dHyx) - (jky * dHxy));
+            const bool ux = jm && k >= 1, uy = im && k >= 1, uz = im && jm;
+            float ty = Ya.kE * dHzy, tx = Xa.kE * dHzx, tzx = Xa.kE * dHyx, tzy = Ya.kE * dHxy;
+            if (PXY && iny) {
+                if (ux) q[0][v] = Ya.bE * q[0][v] + Ya.cE * dHzy;
+                if (uz) q[1][v] = Ya.bE * q[1][v] + Ya.cE * dHxy;
+                ty += q[0][v];
+                tzy += q[1][v];
+            }
+            if (PXY && inx) {
+                if (uy) q[2][v] = Xa.bE * q[2][v] + Xa.cE * dHzx;
+                if (uz) q[3][v] = Xa.bE * q[3][v] + Xa.cE * dHyx;
+                tx += q[2][v];
+                tzx += q[3][v];
+            }
+            if (ux) ex[v] = (MAT >= 1 ? ca[v] * ex[v] : ex[v]) + cb[v] * (ty - (idzE * dyz[v]));
+            if (uy) ey[v] = (MAT >= 1 ? ca[v] * ey[v] : ey[v]) + cb[v] * ((idzE * dxz[v]) - tx);
+            if (uz) ez[v] = (MAT >= 1 ? ca[v] * ez[v] : ez[v]) + cb[v] * (tzx - tzy);
+        }
+    };
+    // x/y-slab psi of the thread's cells: q[0], q[1] from the y-slab arrays
+    // a, b at qy (if iny), q[2], q[3] from the x-slab arrays c, d at qx (if
+    // inx), else zero; and the reverse
+    auto qload = [&](float (&q)[4][V], float *const *S, int a, int b, int c, int d, unsigned qy, bool iny,
+                     unsigned qx, bool inx) {
+        ld(q[0], S[a], qy, iny);
+        ld(q[1], S[b], qy, iny);
+        ld(q[2], S[c], qx, inx);
+        ld(q[3], S[d], qx, inx);
+    };
+    auto qstore = [&](const float (&q)[4][V], float *const *S, int a, int b, int c, int d, unsigned qy, bool iny,
+                      unsigned qx, bool inx) {
+        if (iny) {
+            stv<V>(S[a] + qy, q[0]);
+            stv<V>(S[b] + qy, q[1]);
+        }
+        if (inx) {
+            stv<V>(S[c] + qx, q[2]);
+            stv<V>(S[d] + qx, q[3]);
         }
     };
     // z-slab correction of E (o3 = Ex-z, o4 = Ey-z); cells not updated keep psi
@@ -299,7 +365,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             const float exs = sn ? ex0[rq + segend] : 0.f, eys = sn ? ey0[rq + segend] : 0.f;
             float zz[V];
             zero(zz);
-            hstep(ahx, ahy, ahz, adb, aex, aey, aez, eyc, ezc, aexy, zz, exs, eys, dyz, dxz);
+            const AxP Xq = prof(p.x, ia - 1, ikx, jkx);
+            float qa[4][V];  // Hx-y unused (Hx is not needed)
+            const bool inx = PXY && ok && Xq.s >= 0, iny = PXY && ok && Y.s >= 0;
+            if (PXY)
+                qload(qa, P0, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, iny ? ys3(ia - 1, Y.s, kb, sy, nz) : 0, iny,
+                      inx ? xs3(Xq.s, j, kb, ny, nz) : 0, inx);
+            hstep(ahx, ahy, ahz, adb, aex, aey, aez, eyc, ezc, aexy, zz, exs, eys, dyz, dxz, Xq, Y, inx, iny, qa);
             if (PZ && zany) {
                 float o1[V], o2[V];
                 zload(o1, P0[PSI_HXZ], zs3(ia - 1, j, 0, ny, sz));
@@ -321,6 +393,9 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const bool xi = i + 1 < nx, im = i >= 1;
         const unsigned r0 = ((unsigned)(pa ? i : 0) * ny + jr) * nz, c = r0 + kb;
         const bool la = pa && ok;
+        const AxP X = prof(p.x, pa ? i : 0, ikx, jkx);
+        const bool inx1 = PXY && la && X.s >= 0, iny1 = PXY && la && Y.s >= 0;
+        const unsigned qx1 = inx1 ? xs3(X.s, j, kb, ny, nz) : 0, qy1 = iny1 ? ys3(i, Y.s, kb, sy, nz) : 0;
         // ---- state-n z psi of plane i (rows j0-2 .. j0+R): issued now,
         //      written to LDS before the first barrier ----
         constexpr int NZQ = NZR * ZW;  // entries per component
@@ -387,7 +462,11 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const float exs0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][0] : 0.f;
         const float eys0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][1] : 0.f;
         float dyz[V], dxz[V];
-        hstep(hx, hy, hz, db, ex, ey, ez, eyx, ezx, exy, ezy, exs0, eys0, dyz, dxz);
+        float q1[4][V];  // x/y-slab psi of H at (i, j): state n in, n+1 out
+        if (PXY) qload(q1, P0, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy1, iny1, qx1, inx1);
+        hstep(hx, hy, hz, db, ex, ey, ez, eyx, ezx, exy, ezy, exs0, eys0, dyz, dxz, X, Y, inx1, iny1, q1);
+        // step 2 reads them at plane i (rows up to the last own one)
+        if (PXY && rr <= T.nrows && i < iend) qstore(q1, PM, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy1, iny1, qx1, inx1);
         if (PZ && zany && la) {  // z-slab psi of step 1: state n in, n+1 to the stash
             float o1[V], o2[V];
             zlds(o1, 0, rr + 1);
@@ -422,7 +501,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             const bool snj = ok && last && seamnext;
             const float eys = snj ? ey0[r0 - sys + segend] : 0.f, exs = snj ? ex0[r0 - sys + segend] : 0.f;
             zero(zz);
-            hstep(ahx, ahy, ahz, adb, aex, aey, aez, aeyx, zz, ex, ez, exs, eys, d1, d2);
+            float qa[4][V];  // Hy-x unused (Hy is not needed)
+            const AxP Ym = prof(p.y, j - 1, iky, jky);
+            const bool inx = PXY && ok && X.s >= 0, iny = PXY && ok && Ym.s >= 0;
+            if (PXY)
+                qload(qa, P0, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, iny ? ys3(i, Ym.s, kb, sy, nz) : 0, iny,
+                      inx ? xs3(X.s, j - 1, kb, ny, nz) : 0, inx);
+            hstep(ahx, ahy, ahz, adb, aex, aey, aez, aeyx, zz, ex, ez, exs, eys, d1, d2, X, Ym, inx, iny, qa);
             if (PZ && zany) {
                 float q1[V], q2[V];
                 zlds(q1, 0, rr);
@@ -437,7 +522,11 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         float ex1[V], ey1[V], ez1[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) { ex1[v] = ex[v]; ey1[v] = ey[v]; ez1[v] = ez[v]; }
-        estep(ex1, ey1, ez1, ca, cb, hx, hy, hz, hy1p, hz1p, hxj, hzj, hxs1, hys1, im, dyz, dxz);
+        float e1q[4][V];  // x/y-slab psi of E at (i, j): state n in, n+1 out
+        if (PXY) qload(e1q, P0, PSI_EXY, PSI_EZY, PSI_EYX, PSI_EZX, qy1, iny1, qx1, inx1);
+        estep(ex1, ey1, ez1, ca, cb, hx, hy, hz, hy1p, hz1p, hxj, hzj, hxs1, hys1, im, dyz, dxz, X, Y, inx1, iny1, e1q);
+        if (PXY && own && i >= T.i0 && i < iend)  // step 2 of the own rows reads them at plane i
+            qstore(e1q, PM, PSI_EXY, PSI_EZY, PSI_EYX, PSI_EZX, qy1, iny1, qx1, inx1);
         if (PZ && zany && la) {
             float o3[V], o4[V];
             zlds(o3, 2, rr + 1);
@@ -458,13 +547,19 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const bool pb = ib >= ia && rr <= T.nrows && rok;  // wave-uniform
         const bool wb = own && rok && ib >= T.i0;          // E too, and stored
         const unsigned cq = ((unsigned)(pb ? ib : 0) * ny + jr) * nz + kb;
+        const AxP Xp = prof(p.x, pb ? ib : 0, ikx, jkx);
+        const bool inx2 = PXY && pb && ok && Xp.s >= 0, iny2 = PXY && pb && ok && Y.s >= 0;
+        const unsigned qx2 = inx2 ? xs3(Xp.s, j, kb, ny, nz) : 0, qy2 = iny2 ? ys3(ib, Y.s, kb, sy, nz) : 0;
         float hx2[V], hy2[V], hz2[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) { hx2[v] = hx1p[v]; hy2[v] = hy1p[v]; hz2[v] = hz1p[v]; }
         if (pb) {  // wave-uniform
             const bool sn2 = last && seamnext;
             const float exs = sn2 ? e1s[0] : 0.f, eys = sn2 ? e1s[1] : 0.f;
-            hstep(hx2, hy2, hz2, dbp, ex1p, ey1p, ez1p, ey1, ez1, ex1y, ez1y, exs, eys, dyz, dxz);
+            float q2[4][V];  // x/y-slab psi of H at (ib, j): n+1 in, n+2 out
+            if (PXY) qload(q2, PM, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy2, iny2, qx2, inx2);
+            hstep(hx2, hy2, hz2, dbp, ex1p, ey1p, ez1p, ey1, ez1, ex1y, ez1y, exs, eys, dyz, dxz, Xp, Y, inx2, iny2, q2);
+            if (PXY && wb) qstore(q2, P1, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy2, iny2, qx2, inx2);
             if (PZ && zany) {
                 float p1[V], p2[V];
                 zstash_r(p1, ib & 1, 0);
@@ -494,7 +589,11 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             float e2x[V], e2y[V], e2z[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) { e2x[v] = ex1p[v]; e2y[v] = ey1p[v]; e2z[v] = ez1p[v]; }
-            estep(e2x, e2y, e2z, cap, cbp, hx2, hy2, hz2, hy2p, hz2p, hxj2, hzj2, hxs2, hys2, ib >= 1, dyz, dxz);
+            float e2q[4][V];  // x/y-slab psi of E at (ib, j): n+1 in, n+2 out
+            if (PXY) qload(e2q, PM, PSI_EXY, PSI_EZY, PSI_EYX, PSI_EZX, qy2, iny2, qx2, inx2);
+            estep(e2x, e2y, e2z, cap, cbp, hx2, hy2, hz2, hy2p, hz2p, hxj2, hzj2, hxs2, hys2, ib >= 1, dyz, dxz, Xp, Y,
+                  inx2, iny2, e2q);
+            if (PXY) qstore(e2q, P1, PSI_EXY, PSI_EZY, PSI_EYX, PSI_EZX, qy2, iny2, qx2, inx2);
             if (PZ && zany) {  // zany implies ok
                 float p3[V], p4[V];
                 zstash_r(p3, ib & 1, 2);
@@ -531,33 +630,50 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     }
 }
 
-template <int RZ, bool PZ, int MAT>
-static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step, hipStream_t st) {
-    constexpr int W = two_waves(PZ, MAT), R = W / RZ - 2;
-    hipLaunchKernelGGL((k3d_two<4, RZ, R, PZ, MAT>), dim3((unsigned)n), dim3(64 * W), 0, st, p, tiles, pt, step);
+template <int RZ, bool PZ, bool PXY, int MAT>
+static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                   const State3D &mid, hipStream_t st) {
+    constexpr int W = two_waves(PZ, MAT, PXY), R = W / RZ - 2;
+    hipLaunchKernelGGL((k3d_two<4, RZ, R, PZ, PXY, MAT>), dim3((unsigned)n), dim3(64 * W), 0, st, p, tiles, pt, step,
+                       mid);
 }
 
-template <int RZ, bool PZ>
+template <int RZ, bool PZ, bool PXY>
 static void go_two_m(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                     hipStream_t st) {
+                     const State3D &mid, hipStream_t st) {
     const int mat = p.db ? 2 : (p.ca ? 1 : 0);
-    if (mat == 0) go_two<RZ, PZ, 0>(p, tiles, n, pt, step, st);
-    else if (mat == 1) go_two<RZ, PZ, 1>(p, tiles, n, pt, step, st);
-    else go_two<RZ, PZ, 2>(p, tiles, n, pt, step, st);
+    if (mat == 0) go_two<RZ, PZ, PXY, 0>(p, tiles, n, pt, step, mid, st);
+    else if (mat == 1) go_two<RZ, PZ, PXY, 1>(p, tiles, n, pt, step, mid, st);
+    else go_two<RZ, PZ, PXY, 2>(p, tiles, n, pt, step, mid, st);
+}
+
+template <int RZ>
+static void go_two_c(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                     const State3D *mid, hipStream_t st) {
+    const bool pz = p.z.lo + p.z.hi > 0;
+    if (mid) {
+        if (pz) go_two_m<RZ, true, true>(p, tiles, n, pt, step, *mid, st);
+        else go_two_m<RZ, false, true>(p, tiles, n, pt, step, *mid, st);
+    } else {
+        const State3D none{};
+        if (pz) go_two_m<RZ, true, false>(p, tiles, n, pt, step, none, st);
+        else go_two_m<RZ, false, false>(p, tiles, n, pt, step, none, st);
+    }
 }
 
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                         hipStream_t st) {
+                         hipStream_t st, const State3D *mid) {
     if (n <= 0) return hipSuccess;
     if (!two3d_supported(p.nx, p.ny, p.nz, p.z.lo, p.z.hi)) return hipErrorInvalidValue;
-    const bool pz = p.z.lo + p.z.hi > 0;
-    if (p.nz <= 64 * 4) {
-        if (pz) go_two_m<1, true>(p, tiles, n, pt, step, st);
-        else go_two_m<1, false>(p, tiles, n, pt, step, st);
-    } else {
-        if (pz) go_two_m<2, true>(p, tiles, n, pt, step, st);
-        else go_two_m<2, false>(p, tiles, n, pt, step, st);
+    if (mid && p.x.lo + p.x.hi + p.y.lo + p.y.hi > 0) {
+        // the slab psi arrays of the middle state must exist
+        for (int a : {PSI_HXY, PSI_HZY, PSI_EXY, PSI_EZY})
+            if (p.y.lo + p.y.hi > 0 && !mid->psi[a]) return hipErrorInvalidValue;
+        for (int a : {PSI_HYX, PSI_HZX, PSI_EYX, PSI_EZX})
+            if (p.x.lo + p.x.hi > 0 && !mid->psi[a]) return hipErrorInvalidValue;
     }
+    if (p.nz <= 64 * 4) go_two_c<1>(p, tiles, n, pt, step, mid, st);
+    else go_two_c<2>(p, tiles, n, pt, step, mid, st);
     return hipGetLastError();
 }
 

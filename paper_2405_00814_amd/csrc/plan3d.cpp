@@ -2,6 +2,7 @@
 // covers (single-step fused kernel, two-steps-per-pass kernel and its two
 // single-step passes).  Pure integer work, no device code.
 #include <algorithm>
+#include <stdexcept>
 #include <vector>
 
 #include "common.hpp"
@@ -130,9 +131,9 @@ bool two3d_supported(int nx, int ny, int nz, int zlo, int zhi) {
     return ((zlo + 3) & ~3) <= ((nz - zhi) & ~3);
 }
 
-int two3d_rows(int nz, bool pz, int mat) {
+int two3d_rows(int nz, bool pz, int mat, bool pxy) {
     const int rz = nz <= 64 * 4 ? 1 : 2;
-    return two_waves(pz, mat) / rz - 2;
+    return two_waves(pz, mat, pxy) / rz - 2;
 }
 
 namespace {
@@ -198,15 +199,20 @@ void mask_tiles(const std::vector<unsigned char> &m, int nx, int ny, int nz, int
 
 }  // namespace
 
-void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int *xlohi, const int *ylohi,
-                const int *zlohi, TwoPlan &pl) {
+void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_tb, int txo, const int *xlohi,
+                const int *ylohi, const int *zlohi, TwoPlan &pl) {
     pl.tb.clear();
-    pl.tb_cells = pl.tb_psi = 0;
+    pl.tbo.clear();
+    pl.tb_cells = pl.tb_psi = pl.tbo_cells = pl.tbo_psi = 0;
     pl.pass1.l.clear();
     pl.pass1.tiles.clear();
     pl.pass2.l.clear();
     pl.pass2.tiles.clear();
-    const int TX = c.TX > 0 ? c.TX : 16, R = two3d_rows(nz, zlohi[0] + zlohi[1] > 0, mat);
+    const bool pz = zlohi[0] + zlohi[1] > 0;
+    const int TX = c.TX > 0 ? c.TX : 16, R = two3d_rows(nz, pz, mat, false);
+    pl.slab_tb = slab_tb;
+    pl.rows = R;
+    pl.rows_o = two3d_rows(nz, pz, mat, true);
     auto inslab = [](int n, int lo, int hi, int i) { return i >= 0 && i < n && (i < lo || i >= n - hi); };
     auto clear = [&](int n, int lo, int hi, int a, int b) {  // no slab cell in [a, b]
         for (int q = std::max(a, 0); q <= std::min(b, n - 1); ++q)
@@ -219,12 +225,61 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int 
     // two-step tiles, x chunk by x chunk, bands inside, over the planes and
     // rows whose cone is clear: [lo + 2, n - hi - 1) of an axis with slabs
     auto range = [](int n, int lo, int hi, int &a, int &b) {
-        a = lo > 0 ? lo + 2 : 0;
-        b = hi > 0 ? n - hi - 1 : n;
+        a = std::min(lo > 0 ? lo + 2 : 0, n);
+        b = std::max(hi > 0 ? n - hi - 1 : n, a);
     };
     int xa, xb, ya, yb;
     range(nx, xlohi[0], xlohi[1], xa, xb);
     range(ny, ylohi[0], ylohi[1], ya, yb);
+    if (slab_tb) {
+        // every cell in two-step tiles: x pieces [0, xa) and [xb, nx) in
+        // chunks of TXo planes, [xa, xb) in chunks of TX; bands of rows_o
+        // rows over the x-slab pieces and over [0, ya), [yb, ny) of the
+        // others (the launch with x/y-slab code), bands of R rows over
+        // [ya, yb) of the others (the launch without)
+        const int TXo = txo > 0 ? txo : TX, Ro = pl.rows_o;
+        std::vector<Range> xr;
+        std::vector<char> xin;
+        chunks(xr, 0, xa, TXo);
+        xin.resize(xr.size(), 0);
+        chunks(xr, xa, xb, TX);
+        xin.resize(xr.size(), 1);
+        chunks(xr, xb, nx, TXo);
+        xin.resize(xr.size(), 0);
+        for (size_t q = 0; q < xr.size(); ++q) {
+            const int i0 = xr[q].a, i1 = xr[q].b;
+            int64_t xs = 0;
+            for (int i = i0; i < i1; ++i) xs += inslab(nx, xlohi[0], xlohi[1], i);
+            auto band = [&](int a, int b, int r, bool in) {
+                for (int j0 = a; j0 < b; j0 += r) {
+                    const int nr = std::min(r, b - j0);
+                    if (in) {
+                        if (!clear(nx, xlohi[0], xlohi[1], i0 - 2, i1) || !clear(ny, ylohi[0], ylohi[1], j0 - 2, j0 + nr))
+                            throw std::logic_error("two-step plan: interior tile touches a slab");
+                        pl.tb.push_back(TileTB{i0, i1, j0, nr});
+                        pl.tb_cells += (int64_t)(i1 - i0) * nr * nz;
+                        pl.tb_psi += 4 * (int64_t)(i1 - i0) * nr * zs;
+                    } else {
+                        int64_t ysn = 0;
+                        for (int jj = j0; jj < j0 + nr; ++jj) ysn += inslab(ny, ylohi[0], ylohi[1], jj);
+                        pl.tbo.push_back(TileTB{i0, i1, j0, nr});
+                        pl.tbo_cells += (int64_t)(i1 - i0) * nr * nz;
+                        pl.tbo_psi += 4 * (xs * nr * nz + (int64_t)(i1 - i0) * ysn * nz + (int64_t)(i1 - i0) * nr * zs);
+                    }
+                }
+            };
+            if (!xin[q]) {
+                band(0, ny, Ro, false);
+            } else {
+                band(0, ya, Ro, false);
+                band(ya, yb, R, true);
+                band(yb, ny, Ro, false);
+            }
+        }
+        while (pl.tb.size() % 8) pl.tb.push_back(TileTB{0, 0, 0, 0});
+        while (pl.tbo.size() % 8) pl.tbo.push_back(TileTB{0, 0, 0, 0});
+        return;
+    }
     for (int i0 = xa; i0 < xb; i0 += TX) {
         const int i1 = std::min(i0 + TX, xb);
         if (!clear(nx, xlohi[0], xlohi[1], i0 - 2, i1)) continue;
@@ -252,7 +307,6 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, const int 
             if (near) s1[(size_t)i * ny + j] = 2;
         }
     const int txs = std::max(1, TX / 4);
-    const bool pz = zlohi[0] + zlohi[1] > 0;
     mask_tiles(s1, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass1);
     mask_tiles(s2, nx, ny, nz, c.V, txs, pz, xlohi, ylohi, zlohi, pl.pass2);
 }

@@ -271,7 +271,7 @@ void Sim::build_probe_tiles() {
     const int mat = this->mat();
     const int vm = kcfg.variant * 4 + mat;
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
-        pt_cfg[3] == c3 && pt_cfg[4] == vm && pt_start)
+        pt_cfg[3] == c3 && pt_cfg[4] == vm && pt_cfg[5] == kcfg.tile[3] && pt_start)
         return;
     if (ndim == 2) {
         const Fused2DCfg c = single2d();
@@ -291,12 +291,14 @@ void Sim::build_probe_tiles() {
         al.put(tl_dev);
         tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
         if (kcfg.variant == 3) {
-            two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, xl, yl, zl, plan2);
-            plan2_rows = two3d_rows(nz, zl[0] + zl[1] > 0, mat);
+            two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, b == 0, kcfg.tile[3], xl, yl, zl, plan2);
+            plan2_mat = mat;
             al.put(tb_dev);
+            al.put(tbo_dev);
             al.put(p1_dev);
             al.put(p2_dev);
             tb_dev = plan2.tb.empty() ? nullptr : dev_upload(al, plan2.tb.data(), plan2.tb.size(), st);
+            tbo_dev = plan2.tbo.empty() ? nullptr : dev_upload(al, plan2.tbo.data(), plan2.tbo.size(), st);
             p1_dev = plan2.pass1.tiles.empty() ? nullptr
                                                : dev_upload(al, plan2.pass1.tiles.data(), plan2.pass1.tiles.size(), st);
             p2_dev = plan2.pass2.tiles.empty() ? nullptr
@@ -344,6 +346,7 @@ void Sim::build_probe_tiles() {
     pt_cfg[2] = (int)probe_cells.size();
     pt_cfg[3] = c3;
     pt_cfg[4] = vm;
+    pt_cfg[5] = kcfg.tile[3];
     if (ndim == 2 && kcfg.variant == 3) {
         const int V = kcfg.tile[0], TX = kcfg.tile[1], TB = kcfg.tile[2];
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
@@ -449,19 +452,36 @@ void Sim::alloc_set(int set) {
         if (psi_len[a] > 0) psi[set][a] = (float *)al.get((size_t)psi_len[a] * 4);
 }
 
-// Two steps n -> n+2 from set cur into set 1-cur: x/y-slab cells S and
-// their rim M take a single step into set 2 (pass1), the interior tiles two
-// steps at once, then S its second single step from set 2 (pass2).  The
-// three writes are disjoint in their target cells; pass2 reads set 2 only
-// where pass1 wrote it.  ev (optional): pass1.l.size() + pass2.l.size() + 2
-// events, one before every launch and one after the last.
+// Two steps n -> n+2 from set cur into set 1-cur.  Slab tiles in the
+// two-step kernel: the tiles near the x/y slabs (their step-1 psi kept in
+// set 2), then the interior tiles, both reading set cur only.  Else the
+// x/y-slab cells S and their rim M take a single step into set 2 (pass1),
+// the interior tiles two steps at once, then S its second single step from
+// set 2 (pass2).  The writes to set 1-cur are disjoint in their target
+// cells; pass2 reads set 2 only where pass1 wrote it.  ev (optional):
+// pair_launches() + 1 events, one before every launch and one after the
+// last.
+size_t Sim::pair_launches() const {
+    return plan2.slab_tb ? 2 : plan2.pass1.l.size() + 1 + plan2.pass2.l.size();
+}
+
 void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
     const int A = cur, B = 1 - cur, C = 2;
     const ProbeTiles pt{pt_start, pt_cell, pt_slot};
     const size_t n1 = plan2.pass1.l.size();
     const Prob3D pab = prob3d(A, B);
-    if (two3d_rows(nz, pab.z.lo + pab.z.hi > 0, pab.db ? 2 : (pab.ca ? 1 : 0)) != plan2_rows)
-        fail(FDTD_ESTATE, "two-step plan out of date");
+    if ((pab.db ? 2 : (pab.ca ? 1 : 0)) != plan2_mat) fail(FDTD_ESTATE, "two-step plan out of date");
+    if (plan2.slab_tb) {
+        const State3D mid = prob3d(C, C).s1;
+        if (ev) hip_check(hipEventRecord(ev[0], st), "event");
+        hip_check(launch_3d_two(pab, tbo_dev, (int)plan2.tbo.size(), pt, step, st, &mid), "3d two-step (slabs)");
+        if (ev) hip_check(hipEventRecord(ev[1], st), "event");
+        hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), pt, step, st), "3d two-step");
+        if (ev) hip_check(hipEventRecord(ev[2], st), "event");
+        cur = B;
+        last_launches += (plan2.tbo.empty() ? 0 : 1) + (plan2.tb.empty() ? 0 : 1);
+        return;
+    }
     hip_check(launch_3d_wave(prob3d(A, C), plan2.pass1, p1_dev, pt, step, st, ev), "3d pass1");
     hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), pt, step, st), "3d two-step");
     hip_check(launch_3d_wave(prob3d(C, B), plan2.pass2, p2_dev, pt, step + 1, st, ev ? ev + n1 + 1 : nullptr),
@@ -602,7 +622,8 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
         return k.tile[3] >= 0 && k.tile[3] <= 65536 && tb2d_supported(s.ny, k.tile[0], k.tile[2], k.tile[1]) &&
                fused2d_supported(s.nx, s.ny, default_single2d(s.nx, s.ny));
     }
-    if (k.tile[1] != 0 || k.tile[3] != 0) return false;
+    if (k.variant == 2 && (k.tile[1] != 0 || k.tile[3] != 0)) return false;
+    if (k.variant == 3 && (k.tile[1] < 0 || k.tile[1] > 1 || k.tile[3] < 0 || k.tile[3] > 4096)) return false;
     if (!wave3d_supported(s.nx, s.ny, s.nz, Fused3DCfg{k.tile[0], k.tile[2]})) return false;
     return k.variant == 2 || (k.tile[0] == 4 && two3d_supported(s.nx, s.ny, s.nz, s.ax[2].lo, s.ax[2].hi));
 }
@@ -1021,8 +1042,7 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
     // the TB steps of the 2D multi-step pass
     const int32_t per = two ? 2 : (tb2 ? s.kcfg.tile[2] : 1);
     const int32_t units = steps / per;
-    const size_t nl = two ? s.plan2.pass1.l.size() + 1 + s.plan2.pass2.l.size()
-                          : (fused3 ? s.plan3.l.size() : 1);
+    const size_t nl = two ? s.pair_launches() : (fused3 ? s.plan3.l.size() : 1);
     // all events of all units are recorded first; one synchronisation at the end
     std::vector<hipEvent_t> ev((nl + 1) * (size_t)units, nullptr);
     struct Guard {
@@ -1079,13 +1099,21 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
         fdtd_launch_stat &o = out[l];
         o.ms = (float)(acc[l] / units);
         const size_t n1 = s.plan2.pass1.l.size();
-        if (two) {
+        const bool zc = s.ax[2].lo + s.ax[2].hi > 0;
+        if (two && s.plan2.slab_tb) {
+            const bool o1 = l == 0;
+            o.cells = o1 ? s.plan2.tbo_cells : s.plan2.tb_cells;
+            o.psi = o1 ? s.plan2.tbo_psi : s.plan2.tb_psi;
+            o.cpml = o1 ? 2 : (zc ? 1 : 0);
+            o.launches = (o1 ? s.plan2.tbo.empty() : s.plan2.tb.empty()) ? 0 : 1;
+            o.steps = 2;
+        } else if (two) {
             if (l < n1) {
                 slab(o, s.plan2.pass1.l[l]);
             } else if (l == n1) {
                 o.cells = s.plan2.tb_cells;
                 o.psi = s.plan2.tb_psi;
-                o.cpml = s.ax[2].lo + s.ax[2].hi > 0 ? 1 : 0;
+                o.cpml = zc ? 1 : 0;
                 o.launches = s.plan2.tb.empty() ? 0 : 1;
                 o.steps = 2;
             } else {
@@ -1350,14 +1378,16 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 k.tb = 1;
                 if (config_ok(s, k)) cand.push_back(k);
             }
-        for (int TX : {8, 16, 32}) {
-            fdtd_kernel_config k{};
-            k.variant = 3;
-            k.tile[0] = 4;
-            k.tile[2] = TX;
-            k.tb = 1;
-            if (config_ok(s, k)) cand.push_back(k);
-        }
+        for (int sp : {0, 1})
+            for (int TX : {8, 16, 32}) {
+                fdtd_kernel_config k{};
+                k.variant = 3;
+                k.tile[0] = 4;
+                k.tile[1] = sp;
+                k.tile[2] = TX;
+                k.tb = 1;
+                if (config_ok(s, k)) cand.push_back(k);
+            }
     }
     {
         fdtd_kernel_config k{};

@@ -95,7 +95,7 @@ struct Sim {
     // probes grouped by tile for the fused kernels
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
     int pt_ntiles = -1;
-    int pt_cfg[5] = {-1, -1, -1, -1, -1};
+    int pt_cfg[6] = {-1, -1, -1, -1, -1, -1};
     // 2D fused: tile ids clear of the CPML slabs, then the others.  Large
     // grids launch the two lists separately (the interior without the CPML
     // code); small grids take one launch, where a second launch's fixed cost
@@ -117,9 +117,9 @@ struct Sim {
     Tile3 *tl_dev = nullptr;
     // 3D two steps per pass (variant 3): its plan and tile lists
     TwoPlan plan2;
-    TileTB *tb_dev = nullptr;
+    TileTB *tb_dev = nullptr, *tbo_dev = nullptr;
     Tile3 *p1_dev = nullptr, *p2_dev = nullptr;
-    int plan2_rows = 0;
+    int plan2_mat = -1;
 
     int64_t n_done = 0;
     fdtd_kernel_config kcfg{};
@@ -163,6 +163,7 @@ struct Sim {
     void build_probe_tiles();
     void launch_step(int64_t step);
     void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
+    size_t pair_launches() const;
     void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);
     void advance(int64_t n);
     void alloc_set(int set);

@@ -62,8 +62,9 @@ int check1(int nx, int ny, int nz, int V, int TX, const int *xl, const int *yl, 
 }
 int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl, const int *zl) {
     TwoPlan pl;
-    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, xl, yl, zl, pl);
-    const int R = two3d_rows(nz, zl[0] + zl[1] > 0, mat);
+    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, false, 0, xl, yl, zl, pl);
+    const int R = two3d_rows(nz, zl[0] + zl[1] > 0, mat, false);
+    if (pl.slab_tb || pl.rows != R || !pl.tbo.empty()) { printf("two-pass plan fields\n"); return 1; }
     std::vector<int> own((size_t)nx * ny, 0);
     if (pl.tb.size() % 8) { printf("tb not mult of 8\n"); return 1; }
     int64_t tbc = 0;
@@ -98,6 +99,55 @@ int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl
                 if (c1[c] && r1[c] != (o == 0 ? 1 : 0)) { printf("pass1 rec wrong\n"); return 1; }
             }
         }
+    return 0;
+}
+// two-step plan with the slab tiles in the two-step kernel: the interior
+// list's tiles have a cone clear of the x/y slabs and at most R rows, the
+// slab list's at most rows_o rows and txo planes (TX inside [lo+2, n-hi-1));
+// together they own every (i, j) once; no single-step passes
+int check2s(int nx, int ny, int nz, int TX, int txo, int mat, const int *xl, const int *yl, const int *zl) {
+    TwoPlan pl;
+    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, true, txo, xl, yl, zl, pl);
+    const bool pz = zl[0] + zl[1] > 0;
+    const int R = two3d_rows(nz, pz, mat, false), Ro = two3d_rows(nz, pz, mat, true);
+    const int tx = TX > 0 ? TX : 16, txs = txo > 0 ? txo : tx;
+    if (!pl.slab_tb || pl.rows != R || pl.rows_o != Ro || !pl.pass1.l.empty() || !pl.pass2.l.empty()) {
+        printf("slab plan fields\n");
+        return 1;
+    }
+    if (pl.tb.size() % 8 || pl.tbo.size() % 8) { printf("slab plan lists not mult of 8\n"); return 1; }
+    std::vector<int> own((size_t)nx * ny, 0);
+    int64_t zs = 0;
+    for (int k = 0; k < nz; ++k) zs += inslab(nz, zl[0], zl[1], k);
+    for (int list = 0; list < 2; ++list) {
+        int64_t cells = 0, psi = 0;
+        for (const TileTB &T : list ? pl.tbo : pl.tb) {
+            if (T.i0 >= T.i1) continue;
+            if (T.i0 < 0 || T.i1 > nx || T.j0 < 0 || T.nrows < 1 || T.j0 + T.nrows > ny ||
+                T.nrows > (list ? Ro : R) || T.i1 - T.i0 > std::max(tx, txs)) {
+                printf("bad slab-plan tile list %d\n", list);
+                return 1;
+            }
+            if (list == 0) {
+                for (int i = T.i0 - 2; i <= T.i1; ++i)
+                    if (inslab(nx, xl[0], xl[1], i)) { printf("interior cone touches x slab\n"); return 1; }
+                for (int j = T.j0 - 2; j <= T.j0 + T.nrows; ++j)
+                    if (inslab(ny, yl[0], yl[1], j)) { printf("interior cone touches y slab\n"); return 1; }
+            }
+            for (int i = T.i0; i < T.i1; ++i)
+                for (int j = T.j0; j < T.j0 + T.nrows; ++j) {
+                    own[(size_t)i * ny + j]++;
+                    cells += nz;
+                    psi += 4 * ((inslab(nx, xl[0], xl[1], i) + inslab(ny, yl[0], yl[1], j)) * (int64_t)nz + zs);
+                }
+        }
+        if (cells != (list ? pl.tbo_cells : pl.tb_cells) || psi != (list ? pl.tbo_psi : pl.tb_psi)) {
+            printf("slab plan counts list %d\n", list);
+            return 1;
+        }
+    }
+    for (int o : own)
+        if (o != 1) { printf("slab plan coverage %d\n", o); return 1; }
     return 0;
 }
 // 2D multi-step plan: own columns [ja, ja + own) and rows [i0, i1) of the
@@ -160,6 +210,10 @@ int main() {
         const int mat = rand() % 3;
         r = check2(nx, ny, nz2, TX, mat, s, s + 2, s + 4);
         if (r) printf("  two case nx %d ny %d nz %d TX %d mat %d s %d %d %d %d %d %d\n", nx, ny, nz2, TX, mat, s[0], s[1], s[2], s[3], s[4], s[5]);
+        bad += r; ++n;
+        const int txo = rand() % 3 == 0 ? 0 : 1 + rand() % 20;
+        r = check2s(nx, ny, nz2, TX, txo, mat, s, s + 2, s + 4);
+        if (r) printf("  slab-tb case nx %d ny %d nz %d TX %d txo %d mat %d s %d %d %d %d %d %d\n", nx, ny, nz2, TX, txo, mat, s[0], s[1], s[2], s[3], s[4], s[5]);
         bad += r; ++n;
     }
     for (int t = 0; t < 2000; ++t) {

@@ -1,8 +1,10 @@
 """GPU parity of the 3D two-steps-per-pass stepper (kernel variant 3):
-interior tiles advance two leapfrog steps in one kernel, the tiles near the x
-and y CPML slabs two single steps through a third state set.  Bar: every
-field component and the probe series within relative L2 1e-4 of the FP64
-oracle, and the single-step fused stepper's result within 1e-5."""
+interior tiles advance two leapfrog steps in one kernel; the tiles near the
+x and y CPML slabs either do too, in the kernel with x/y-slab code (tile[1]
+= 0, their step-1 psi through a third state set), or take two single steps
+through the third set (tile[1] = 1).  Bar: every field component and the
+probe series within relative L2 1e-4 of the FP64 oracle, and the
+single-step fused stepper's result within 1e-5."""
 import numpy as np
 import pytest
 
@@ -39,19 +41,24 @@ CASES = [
 ]
 
 
+# (slab mode, x planes per tile over the x-slab ends)
+MODES = [(0, 0), (0, 3), (1, 0)]
+
+
 @pytest.mark.parametrize("shape,npml,TX,steps", CASES)
 def test_two_step_cpml_boxes(shape, npml, TX, steps):
     pb = _problem(shape, npml, steps)
-    log("two-step", shape, npml, TX, steps)
     ref, rrec = run_oracle(pb, steps)
-    got, rec, cfg = run_gpu(pb, steps, (3, (4, 0, TX)))
-    assert cfg["variant"] == 3 and tuple(cfg["tile"]) == (4, 0, TX, 0)
-    assert_parity(got, ref, TOL, "two-step %s" % (shape,))
-    assert rel_l2(rec, rrec) <= TOL
     one, rec1, _ = run_gpu(pb, steps, (2, (4, 0, TX)))
-    for k in got:
-        assert rel_l2(got[k], one[k]) <= 1e-5, k
-    assert rel_l2(rec, rec1) <= 1e-5
+    for sp, txo in MODES:
+        log("two-step", shape, npml, TX, steps, "slab mode", sp, "txo", txo)
+        got, rec, cfg = run_gpu(pb, steps, (3, (4, sp, TX, txo)))
+        assert cfg["variant"] == 3 and tuple(cfg["tile"]) == (4, sp, TX, txo)
+        assert_parity(got, ref, TOL, "two-step %s mode %d/%d" % (shape, sp, txo))
+        assert rel_l2(rec, rrec) <= TOL
+        for k in got:
+            assert rel_l2(got[k], one[k]) <= 1e-5, (k, sp, txo)
+        assert rel_l2(rec, rec1) <= 1e-5
 
 
 @pytest.mark.parametrize("mat", ["lossy", "lossy_mu"])
@@ -66,47 +73,55 @@ def test_two_step_materials(mat):
             pb.mu_r = rng.uniform(1, 2, pb.shape).astype(np.float32)
         pb.source.component = "ey"
         pb.probe_component = "hx"
-        log("two-step", mat, shape, npml)
         ref, rrec = run_oracle(pb, pb.steps)
-        got, rec, _ = run_gpu(pb, pb.steps, (3, (4,)))
-        assert_parity(got, ref, TOL, "two-step %s %s" % (mat, shape))
-        assert rel_l2(rec, rrec) <= TOL
+        for sp in (0, 1):
+            log("two-step", mat, shape, npml, "slab mode", sp)
+            got, rec, _ = run_gpu(pb, pb.steps, (3, (4, sp)))
+            assert_parity(got, ref, TOL, "two-step %s %s mode %d" % (mat, shape, sp))
+            assert rel_l2(rec, rrec) <= TOL
 
 
 def test_two_step_sources_and_probes_everywhere():
-    """Source in the band next to a y slab (single-step part) and probes in
-    the two-step part, its rim and the slab part; stepping in odd chunks."""
+    """Source in the band next to a y slab (slab tiles) and probes in the
+    interior tiles, next to them and in the slabs; stepping in odd chunks."""
     shape, npml = (32, 40, 96), (4,) * 6
     pb = _problem(shape, npml, 75, src=(16, 5, 48))
     pb.probes = np.array([(16, 20, 48), (5, 20, 30), (6, 20, 31), (7, 7, 7), (2, 2, 90),
                           (20, 5, 47), (9, 13, 60), (25, 30, 3)], dtype=np.int32)
     ref, rrec = run_oracle(pb, pb.steps)
-    for chunks in (1, 3, 7):
-        got, rec, _ = run_gpu(pb, pb.steps, (3, (4, 0, 6)), chunks=chunks)
-        log("chunks", chunks, {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
-        assert_parity(got, ref, TOL, "two-step chunks %d" % chunks)
-        assert rel_l2(rec, rrec) <= TOL
+    for sp in (0, 1):
+        for chunks in (1, 3, 7):
+            got, rec, _ = run_gpu(pb, pb.steps, (3, (4, sp, 6)), chunks=chunks)
+            log("slab mode", sp, "chunks", chunks, {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
+            assert_parity(got, ref, TOL, "two-step mode %d chunks %d" % (sp, chunks))
+            assert rel_l2(rec, rrec) <= TOL
 
 
-def test_two_step_profile_matches_step():
+@pytest.mark.parametrize("sp", [0, 1])
+def test_two_step_profile_matches_step(sp):
     from paper_2405_00814_amd.sim import Sim
     pb = _problem((40, 44, 96), (6,) * 6, 30)
     a = Sim.from_problem(pb)
     b = Sim.from_problem(pb)
     for s in (a, b):
-        s.set_kernel(3, (4,))
+        s.set_kernel(3, (4, sp))
     a.step(7)
     a.step(23)
     b.step(7)
     prof = b.step_profile(23)
     assert b.steps_done() == 30
     two = [p for p in prof if p["steps"] == 2]
-    assert len(two) == 1 and two[0]["cpml"] == 1 and two[0]["cells"] > 0
-    k = prof.index(two[0])
-    # pass2 and the two-step launch cover every cell once; pass1 covers
-    # pass2's cells and a rim
-    assert two[0]["cells"] + sum(p["cells"] for p in prof[k + 1:]) == pb.cells
-    assert sum(p["cells"] for p in prof[:k]) > sum(p["cells"] for p in prof[k + 1:])
+    if sp == 0:
+        # slab tiles (x/y-slab code), then interior tiles: every cell once
+        assert [p["cpml"] for p in prof] == [2, 1] and len(two) == 2
+        assert sum(p["cells"] for p in prof) == pb.cells and min(p["cells"] for p in prof) > 0
+    else:
+        assert len(two) == 1 and two[0]["cpml"] == 1 and two[0]["cells"] > 0
+        k = prof.index(two[0])
+        # pass2 and the two-step launch cover every cell once; pass1 covers
+        # pass2's cells and a rim
+        assert two[0]["cells"] + sum(p["cells"] for p in prof[k + 1:]) == pb.cells
+        assert sum(p["cells"] for p in prof[:k]) > sum(p["cells"] for p in prof[k + 1:])
     assert all(p["ms"] > 0 for p in prof)
     for f in ("ex", "ey", "ez", "hx", "hy", "hz"):
         assert np.array_equal(a.get_field(f), b.get_field(f)), f
@@ -138,11 +153,12 @@ def test_two_step_config_rules():
     pb = W.yee3d(shape=(16, 16, 32), steps=10, seed=0, nbox=2, side=(2, 4), npml=3, nprobes=1,
                  tau_steps=4.0)
     s = Sim.from_problem(pb)
-    for bad in ((2,), (1,), (4, 4)):
+    for bad in ((2,), (1,), (4, 4), (4, 2), (4, -1), (4, 0, 8, -1), (4, 1, 8, 5000)):
         with pytest.raises(FdtdError):
             s.set_kernel(3, bad)
-    s.set_kernel(3, (4, 0, 8))
-    assert s.get_kernel()["variant"] == 3
+    for good in ((4, 0, 8), (4, 1, 8), (4, 0, 8, 4096), (4, 1, 0, 3)):
+        s.set_kernel(3, good)
+        assert s.get_kernel()["variant"] == 3 and tuple(s.get_kernel()["tile"]) == good + (0,) * (4 - len(good))
     s.close()
 
 

@@ -24,4 +24,4 @@ def test_plan_coverage(tmp_path):
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:]
-    assert "0 / 6000 bad" in r.stdout
+    assert "0 / 9000 bad" in r.stdout
