@@ -117,9 +117,7 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         copy_state(s, s.cur, fin, true);
         // ---- loss ----
         std::vector<float> rec((size_t)(P * T));
-        hip_check(hipMemcpy2DAsync(rec.data(), T * 4, s.rec_dev, s.rec_cap * 4, T * 4, P,
-                                   hipMemcpyDeviceToHost, s.st), "record copy");
-        hip_check(hipStreamSynchronize(s.st), "sync");
+        s.records_to_host(rec.data(), T, T);
         double loss = 0.0;
         for (int64_t p = 0; p < P; ++p)
             for (int64_t m = n0 + 1; m <= n1; ++m) {

@@ -440,6 +440,10 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         ld(hy, hy0, c, la);
         ld(hz, hz0, c, la);
         coef(cb, ca, db, c, la);
+        // x/y-slab psi of H at (i, j), state n in, n+1 out: issued with the
+        // field loads (those of E are issued right before use: registers)
+        float q1[4][V];
+        if (PXY) qload(q1, P0, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy1, iny1, qx1, inx1);
         stv<V>(&LEx[tq], ex);
         stv<V>(&LEz[tq], ez);
         if (lane == 0) { Se0[rr][seg][0] = ex[0]; Se0[rr][seg][1] = ey[0]; }
@@ -462,8 +466,6 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         const float exs0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][0] : 0.f;
         const float eys0 = sn ? Se0[rr][seg + (seg + 1 < RZ)][1] : 0.f;
         float dyz[V], dxz[V];
-        float q1[4][V];  // x/y-slab psi of H at (i, j): state n in, n+1 out
-        if (PXY) qload(q1, P0, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy1, iny1, qx1, inx1);
         hstep(hx, hy, hz, db, ex, ey, ez, eyx, ezx, exy, ezy, exs0, eys0, dyz, dxz, X, Y, inx1, iny1, q1);
         // step 2 reads them at plane i (rows up to the last own one)
         if (PXY && rr <= T.nrows && i < iend) qstore(q1, PM, PSI_HXY, PSI_HZY, PSI_HYX, PSI_HZX, qy1, iny1, qx1, inx1);

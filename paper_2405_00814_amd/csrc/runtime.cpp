@@ -265,6 +265,32 @@ void Sim::ensure_rec(int64_t upto) {
     rec_cap = cap;
 }
 
+// The first m records of every probe to host memory, row p at out + p * ld
+// (synchronous).  A 2D device-to-host copy into pageable memory has read
+// back zeros under a profiler's kernel tracing (rocprofv3), so the rows are
+// gathered on the device into one block first and leave by 1D copies.
+void Sim::records_to_host(float *out, int64_t ld, int64_t m) {
+    const int64_t P = (int64_t)probe_cells.size();
+    if (P > 0 && m > 0) {
+        float *tmp = (float *)al.get((size_t)(P * m) * sizeof(float));
+        hip_check(hipMemcpy2DAsync(tmp, m * sizeof(float), rec_dev, rec_cap * sizeof(float), m * sizeof(float), P,
+                                   hipMemcpyDeviceToDevice, st),
+                  "record gather");
+        if (ld == m) {
+            hip_check(hipMemcpyAsync(out, tmp, (size_t)(P * m) * sizeof(float), hipMemcpyDeviceToHost, st),
+                      "record copy");
+        } else {
+            for (int64_t q = 0; q < P; ++q)
+                hip_check(hipMemcpyAsync(out + q * ld, tmp + q * m, (size_t)m * sizeof(float), hipMemcpyDeviceToHost,
+                                         st),
+                          "record copy");
+        }
+        hip_check(hipStreamSynchronize(st), "sync");
+        al.put(tmp);
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+}
+
 void Sim::build_probe_tiles() {
     if (kcfg.variant < 2 || is_graph) return;
     const int a = kcfg.tile[0], b = kcfg.tile[1], c3 = kcfg.tile[2];
@@ -1141,12 +1167,7 @@ int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded) {
     if (n_recorded) *n_recorded = s.n_rec;
     if (!out || s.probe_cells.empty()) return FDTD_OK;
     if (cap < 0) fail(FDTD_EINVAL, "cap must be >= 0");
-    const int64_t m = std::min(cap, s.n_rec);
-    if (m > 0)
-        hip_check(hipMemcpy2DAsync(out, cap * sizeof(float), s.rec_dev, s.rec_cap * sizeof(float),
-                                   m * sizeof(float), s.probe_cells.size(), hipMemcpyDeviceToHost, s.st),
-                  "probe copy");
-    hip_check(hipStreamSynchronize(s.st), "sync");
+    s.records_to_host(out, cap, std::min(cap, s.n_rec));
     return FDTD_OK;
     GEM_CATCH
 }

@@ -164,6 +164,7 @@ struct Sim {
     void launch_step(int64_t step);
     void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
     size_t pair_launches() const;
+    void records_to_host(float *out, int64_t ld, int64_t m);
     void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);
     void advance(int64_t n);
     void alloc_set(int set);
