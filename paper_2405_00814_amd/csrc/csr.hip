@@ -1,29 +1,59 @@
 // Explicit-graph form: one CSR gather per layer (Prop. 2: h_l = sum over the
 // neighbourhood of w * h).  Rows are the nodes a layer updates; weights are
-// the fixed coefficients.  Gather only (each row written by one thread), so
-// results are deterministic.
+// the fixed coefficients.  Gather only (each row written by one thread, its
+// edges summed in order), so results are deterministic.
 #include "common.hpp"
 
 namespace gem {
+
+// One wavefront per 64 consecutive rows.  Its edge range [rowptr[r0],
+// rowptr[r0 + 64]) is staged in LDS by coalesced loads; each lane then sums
+// its row from LDS in edge order (a segment longer than the staging space
+// reads memory directly, same order).
+constexpr int kCsrCap = 512;  // staged edges per wavefront
 
 __global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowptr,
                                                    const int *__restrict__ col,
                                                    const float *__restrict__ w,
                                                    const int *__restrict__ dst, const float *x,
                                                    float *y, int nrows) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    const int b = rowptr[r], e = rowptr[r + 1];
+    __shared__ int sc[4][kCsrCap];
+    __shared__ float sw[4][kCsrCap];
+    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int r0 = ((int)blockIdx.x * 4 + wv) * 64;
+    const int r = r0 + lane;
+    const bool live = r0 < nrows;  // wave-uniform
+    int b0 = 0, n = 0, b = 0, e = 0;
+    if (live) {
+        const int rl = min(r0 + 64, nrows);
+        b0 = rowptr[r0];
+        n = rowptr[rl] - b0;
+        if (r < nrows) {
+            b = rowptr[r];
+            e = rowptr[r + 1];
+        }
+        if (n <= kCsrCap)
+            for (int q = lane; q < n; q += 64) {
+                sc[wv][q] = col[b0 + q];
+                sw[wv][q] = w[b0 + q];
+            }
+    }
+    __syncthreads();
+    if (!live || r >= nrows) return;
     float acc = 0.f;
-    for (int q = b; q < e; ++q) acc += w[q] * x[col[q]];
+    if (n <= kCsrCap) {
+        for (int q = b - b0; q < e - b0; ++q) acc += sw[wv][q] * x[sc[wv][q]];
+    } else {
+        for (int q = b; q < e; ++q) acc += w[q] * x[col[q]];
+    }
     y[dst[r]] = acc;
 }
 
 hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w, const int *dst,
                             const float *x, float *y, int nrows, hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_csr_layer, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
-                       rowptr, col, w, dst, x, y, nrows);
+    const unsigned nb = (unsigned)((nrows + 255) / 256);
+    hipLaunchKernelGGL(k_csr_layer, dim3(nb), dim3(256), 0, st, rowptr, col, w, dst, x, y, nrows);
     return hipGetLastError();
 }
 
