@@ -194,8 +194,11 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    3D two-step: as 3D fused with V = 4; also nz <= 512, at most 64
  *    z-CPML cells in all, and no 4-cell z group holding cells of both z
  *    slabs; tile[1] = 0 (tiles near the x/y slabs in the two-step kernel)
- *    or 1 (as two single steps); tile[3] = x planes per tile over the
- *    x-CPML ends (0 = tile[2]'s value, at most 4096).
+ *    or 1 (as two single steps); tile[2] = x planes per interior tile (0:
+ *    with tile[1] = 0, the length whose tile list a model of the
+ *    device's dispatch finishes first, 16 .. 128; with tile[1] = 1, 16);
+ *    tile[3] = x planes per tile of the tiles near the x/y slabs (0 = 16,
+ *    at most 4096).
  *    2D multi-step (variant 3 on a 2D grid): tile[0] = V (1, 2 or 4; ny % V
  *    must be 0; 0 = 1), tile[1] = TX (rows per tile, 1..65536; 0 = 4), tile[2] =
  *    TB (leapfrog steps per pass: 2 or 4; 0 = 4), tile[3] = rows per tile

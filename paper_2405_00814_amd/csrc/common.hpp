@@ -208,20 +208,24 @@ hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const Prob
 // Plan of a two-step pass.  The interior tiles (cone clear of the x/y
 // slabs) run the two-step kernel without x/y-slab code.  The rest, S:
 //   slab_tb: tiles of the two-step kernel with x/y-slab code (tbo: x chunks
-//     of txo planes, 0 = TX, over the x-slab ends), which keep the step-1
-//     psi in a third state set;
+//     of txo planes, 0 = 16), which keep the step-1 psi in a third state
+//     set; the interior list is ordered in 8 equal parts, one per XCD;
 //   else two single steps: pass1 over S and its one-cell rim M (state n ->
 //     the third state set, probes recorded in S only), pass2 over S (third
 //     set -> state n+2).
 struct TwoPlan {
     bool slab_tb = false;
     int rows = 0, rows_o = 0;  // rows per band: tb, tbo
+    int tx = 0;                // x planes per interior tile
     std::vector<TileTB> tb, tbo;  // each padded to a multiple of 8
     int64_t tb_cells = 0, tb_psi = 0, tbo_cells = 0, tbo_psi = 0;
     Wave3DPlan pass1, pass2;
 };
-void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_tb, int txo, const int *xlohi,
-                const int *ylohi, const int *zlohi, TwoPlan &pl);
+// c.TX = 0: slab_tb takes two3d_auto_tx's chunk for the interior tiles
+// (cus: compute units of the device), the other mode 16.
+void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_tb, int txo, int cus,
+                const int *xlohi, const int *ylohi, const int *zlohi, TwoPlan &pl);
+int two3d_auto_tx(int nxi, int nbands, int cus);
 int wave3d_ngroups(int nx, int ny);
 int wave3d_group_of(int ny, int i, int j);
 bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);

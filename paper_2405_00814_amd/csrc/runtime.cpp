@@ -317,7 +317,7 @@ void Sim::build_probe_tiles() {
         al.put(tl_dev);
         tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
         if (kcfg.variant == 3) {
-            two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, b == 0, kcfg.tile[3], xl, yl, zl, plan2);
+            two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, b == 0, kcfg.tile[3], cus, xl, yl, zl, plan2);
             plan2_mat = mat;
             al.put(tb_dev);
             al.put(tbo_dev);
@@ -718,6 +718,7 @@ void init_sim(Sim &s, const fdtd_desc *d) {
     s.cpml = d->cpml;
     s.st = (hipStream_t)d->stream;
     hip_check(hipGetDevice(&s.device), "hipGetDevice");
+    hip_check(hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, s.device), "device attribute");
     s.al.st = s.st;
     if (d->allocator) {
         if (!d->allocator->alloc || !d->allocator->free) fail(FDTD_EINVAL, "allocator callbacks missing");
@@ -1400,7 +1401,7 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
                 if (config_ok(s, k)) cand.push_back(k);
             }
         for (int sp : {0, 1})
-            for (int TX : {8, 16, 32}) {
+            for (int TX : {0, 16, 32, 64}) {
                 fdtd_kernel_config k{};
                 k.variant = 3;
                 k.tile[0] = 4;

@@ -53,6 +53,7 @@ struct Sim {
     double dx = 0, dy = 0, dz = 0, dt = 0;
     hipStream_t st = nullptr;
     int device = 0;
+    int cus = 256;  // compute units of the device
     DevAlloc al;
 
     // host copies of the maps (for refolding)

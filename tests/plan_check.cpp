@@ -62,7 +62,7 @@ int check1(int nx, int ny, int nz, int V, int TX, const int *xl, const int *yl, 
 }
 int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl, const int *zl) {
     TwoPlan pl;
-    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, false, 0, xl, yl, zl, pl);
+    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, false, 0, 256, xl, yl, zl, pl);
     const int R = two3d_rows(nz, zl[0] + zl[1] > 0, mat, false);
     if (pl.slab_tb || pl.rows != R || !pl.tbo.empty()) { printf("two-pass plan fields\n"); return 1; }
     std::vector<int> own((size_t)nx * ny, 0);
@@ -107,10 +107,12 @@ int check2(int nx, int ny, int nz, int TX, int mat, const int *xl, const int *yl
 // together they own every (i, j) once; no single-step passes
 int check2s(int nx, int ny, int nz, int TX, int txo, int mat, const int *xl, const int *yl, const int *zl) {
     TwoPlan pl;
-    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, true, txo, xl, yl, zl, pl);
+    two3d_plan(nx, ny, nz, Fused3DCfg{4, TX}, mat, true, txo, 256, xl, yl, zl, pl);
     const bool pz = zl[0] + zl[1] > 0;
     const int R = two3d_rows(nz, pz, mat, false), Ro = two3d_rows(nz, pz, mat, true);
-    const int tx = TX > 0 ? TX : 16, txs = txo > 0 ? txo : tx;
+    const int tx = TX > 0 ? TX : pl.tx, txs = txo > 0 ? txo : 16;
+    if (TX > 0 && pl.tx != TX) { printf("slab plan tx\n"); return 1; }
+    if (TX == 0 && (pl.tx < 16 || pl.tx > 128)) { printf("auto tx %d\n", pl.tx); return 1; }
     if (!pl.slab_tb || pl.rows != R || pl.rows_o != Ro || !pl.pass1.l.empty() || !pl.pass2.l.empty()) {
         printf("slab plan fields\n");
         return 1;
