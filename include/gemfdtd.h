@@ -60,13 +60,19 @@ enum {
 /* Field components. */
 enum { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
 
-/* Source waveforms g(t) (the paper names Gaussian-type point sources,
- * Sec. V-A and V-B, without a formula; these are the forms used here):
+/* Source waveforms g(t) (the paper names Gaussian, sinusoidal and
+ * modulated Gaussian sources, Sec. V-A and V-B, without formulas; these are
+ * the forms used here).  The field gets amp * g(t):
  *  GAUSSIAN params {amp, t0, tau}: g = exp(-((t - t0)/tau)^2)
  *  RICKER   params {amp, t0, f}:   g = (1 - 2a) exp(-a), a = (pi f (t - t0))^2
  *  TABLE    g[n] given for the steps 0..n_table-1 (sample n is added at the
- *           end of step n, i.e. at time (n+1) dt), zero afterwards; amp = 1. */
-enum { FDTD_SRC_GAUSSIAN = 0, FDTD_SRC_RICKER = 1, FDTD_SRC_TABLE = 2 };
+ *           end of step n, i.e. at time (n+1) dt), zero afterwards; amp = 1.
+ *  SINE     params {amp, f, t_ramp}: g = r(t) sin(2 pi f t), with the
+ *           turn-on r = sin^2(pi t / (2 t_ramp)) for t < t_ramp, else 1
+ *           (t_ramp = 0: no ramp)
+ *  MODGAUSS params {amp, t0, tau, f}: g = exp(-((t - t0)/tau)^2)
+ *           sin(2 pi f (t - t0)) (four parameters) */
+enum { FDTD_SRC_GAUSSIAN = 0, FDTD_SRC_RICKER = 1, FDTD_SRC_TABLE = 2, FDTD_SRC_SINE = 3, FDTD_SRC_MODGAUSS = 4 };
 
 /* Optional device allocator.  alloc returns NULL on failure.  The library
  * frees every block it allocated in fdtd_destroy / fdtd_batch_destroy. */
@@ -128,7 +134,8 @@ int fdtd_create_graph(const fdtd_desc *desc, fdtd_sim **out);
 int fdtd_destroy(fdtd_sim *sim);
 
 /* Point source on an E component (FDTD_EZ for ndim 2) at cell ijk[0..ndim).
- * params as in the FDTD_SRC_* comment (3 doubles; ignored for TABLE).
+ * params as in the FDTD_SRC_* comment (3 doubles, 4 for MODGAUSS;
+ * ignored for TABLE).
  * A new call replaces the previous source; kind < 0 removes it.  The cell
  * must not be on a PEC wall plane of that component.  FDTD_EINVAL. */
 int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind,

@@ -128,9 +128,15 @@ void orc_cpml_axis(int n, int d_lo, int d_hi, double delta, double dt, double m,
     }
 }
 
-/* Source samples out[k] = amp * g((n0 + k + 1) dt), k in [0, count).
+/* Source samples out[k] = amp * g((n0 + k + 1) dt), k in [0, count).  The
+ * paper names Gaussian, sinusoidal and modulated Gaussian sources (Sec. V-A,
+ * V-B) without formulas; these are the readings taken:
  * kind 0 (Gaussian): params {amp, t0, tau}, g = exp(-((t - t0)/tau)^2)
- * kind 1 (Ricker):   params {amp, t0, f},   g = (1 - 2 a) exp(-a), a = (pi f (t - t0))^2 */
+ * kind 1 (Ricker):   params {amp, t0, f},   g = (1 - 2 a) exp(-a), a = (pi f (t - t0))^2
+ * kind 3 (sine):     params {amp, f, T},    g = w(t) sin(2 pi f t), where the
+ *                    turn-on w rises as sin^2(pi t / 2T) up to t = T, then 1
+ * kind 4 (modulated Gaussian): params {amp, t0, tau, f},
+ *                    g = exp(-((t - t0)/tau)^2) sin(2 pi f (t - t0)) */
 void orc_source(int kind, const double *params, double dt, long n0, long count,
                 double *out)
 {
@@ -140,10 +146,21 @@ void orc_source(int kind, const double *params, double dt, long n0, long count,
         if (kind == 0) {
             double u = (t - params[1]) / params[2];
             v = exp(-u * u);
-        } else {
+        } else if (kind == 1) {
             double a = ORC_PI * params[2] * (t - params[1]);
             a = a * a;
             v = (1.0 - 2.0 * a) * exp(-a);
+        } else if (kind == 3) {
+            double w = 1.0;
+            if (t < params[2]) {
+                double h = sin(ORC_PI * t / (2.0 * params[2]));
+                w = h * h;
+            }
+            v = w * sin(2.0 * ORC_PI * params[1] * t);
+        } else {
+            double s = t - params[1];
+            double u = s / params[2];
+            v = exp(-u * u) * sin(2.0 * ORC_PI * params[3] * s);
         }
         out[k] = params[0] * v;
     }

@@ -158,6 +158,8 @@ AxisDev upload_axis(DevAlloc &al, const AxisHost &h, hipStream_t st) {
     return a;
 }
 
+int src_nparams(int kind) { return kind == FDTD_SRC_MODGAUSS ? 4 : (kind == FDTD_SRC_TABLE ? 0 : 3); }
+
 double source_sample(int kind, const double *par, double dt, int64_t n) {
     const double t = (double)(n + 1) * dt;
     if (kind == FDTD_SRC_GAUSSIAN) {
@@ -168,6 +170,18 @@ double source_sample(int kind, const double *par, double dt, int64_t n) {
         double a = kPi * par[2] * (t - par[1]);
         a *= a;
         return par[0] * (1.0 - 2.0 * a) * std::exp(-a);
+    }
+    if (kind == FDTD_SRC_SINE) {
+        double r = 1.0;
+        if (t < par[2]) {
+            const double q = std::sin(0.5 * kPi * t / par[2]);
+            r = q * q;
+        }
+        return par[0] * r * std::sin(2.0 * kPi * par[1] * t);
+    }
+    if (kind == FDTD_SRC_MODGAUSS) {
+        const double u = (t - par[1]) / par[2];
+        return par[0] * std::exp(-u * u) * std::sin(2.0 * kPi * par[3] * (t - par[1]));
     }
     return 0.0;
 }
@@ -955,12 +969,17 @@ int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, 
         if (!table || n_table < 0) fail(FDTD_EINVAL, "table source needs table and n_table >= 0");
         for (int64_t n = 0; n < n_table; ++n)
             if (!std::isfinite(table[n])) fail(FDTD_EINVAL, "non-finite source table value");
-    } else if (kind == FDTD_SRC_GAUSSIAN || kind == FDTD_SRC_RICKER) {
+    } else if (kind == FDTD_SRC_GAUSSIAN || kind == FDTD_SRC_RICKER || kind == FDTD_SRC_SINE ||
+               kind == FDTD_SRC_MODGAUSS) {
         if (!params) fail(FDTD_EINVAL, "params is NULL");
-        for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < src_nparams(kind); ++q)
             if (!std::isfinite(params[q])) fail(FDTD_EINVAL, "non-finite source parameter");
-        if (kind == FDTD_SRC_GAUSSIAN && !(params[2] > 0)) fail(FDTD_EINVAL, "Gaussian tau must be > 0");
+        if ((kind == FDTD_SRC_GAUSSIAN || kind == FDTD_SRC_MODGAUSS) && !(params[2] > 0))
+            fail(FDTD_EINVAL, "Gaussian tau must be > 0");
         if (kind == FDTD_SRC_RICKER && !(params[2] > 0)) fail(FDTD_EINVAL, "Ricker frequency must be > 0");
+        if (kind == FDTD_SRC_SINE && (!(params[1] > 0) || !(params[2] >= 0)))
+            fail(FDTD_EINVAL, "sine needs f > 0 and t_ramp >= 0");
+        if (kind == FDTD_SRC_MODGAUSS && !(params[3] >= 0)) fail(FDTD_EINVAL, "modulation frequency must be >= 0");
     } else {
         fail(FDTD_EINVAL, "unknown source kind");
     }
@@ -977,7 +996,7 @@ int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, 
         s.src_len = n_table;
         hip_check(hipStreamSynchronize(s.st), "sync");
     } else {
-        for (int q = 0; q < 3; ++q) s.src_par[q] = params[q];
+        for (int q = 0; q < 4; ++q) s.src_par[q] = q < src_nparams(kind) ? params[q] : 0.0;
         s.ensure_source(std::max<int64_t>(s.n_done + 1, 1));
         hip_check(hipStreamSynchronize(s.st), "sync");
     }

@@ -45,6 +45,8 @@ AxisDev upload_axis(DevAlloc &al, const AxisHost &h, hipStream_t st);
 
 // Source waveform sample for step n (added at the end of step n, t = (n+1) dt).
 double source_sample(int kind, const double *par, double dt, int64_t n);
+// parameters a kind reads (FDTD_SRC_*)
+int src_nparams(int kind);
 
 struct Sim {
     int ndim = 2;
@@ -79,7 +81,7 @@ struct Sim {
     int src_comp = FDTD_EZ;
     int64_t src_idx = -1;
     int src_kind = -1;
-    double src_par[3] = {0, 0, 0};
+    double src_par[4] = {0, 0, 0, 0};
     std::vector<float> src_table;   // TABLE kind
     float *src_dev = nullptr;
     int64_t src_cap = 0;            // entries on the device

@@ -144,7 +144,7 @@ class Sim:
 
     def set_source(self, comp, cell, kind, params=(0.0, 0.0, 0.0), table=None):
         ijk = (C.c_int32 * 3)(*[int(v) for v in cell] + [0] * (3 - len(cell)))
-        par = (C.c_double * 3)(*[float(v) for v in params])
+        par = (C.c_double * 4)(*[float(v) for v in params])
         tp, nt = None, 0
         if table is not None:
             self._table = np.ascontiguousarray(np.asarray(table, np.float32))
@@ -296,7 +296,7 @@ class Batch:
 
     def set_source(self, q, cell, kind, params):
         ijk = (C.c_int32 * 3)(*[int(v) for v in cell] + [0])
-        par = (C.c_double * 3)(*[float(v) for v in params])
+        par = (C.c_double * 4)(*[float(v) for v in params])
         L.call("fdtd_batch_set_source", self.h, int(q), ijk, int(kind), par, None, 0)
 
     def set_probes(self, q, cells):

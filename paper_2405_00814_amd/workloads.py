@@ -31,6 +31,8 @@ C0 = 299792458.0  # speed of light in vacuum, m/s (exact, SI)
 
 SRC_GAUSSIAN = 0
 SRC_RICKER = 1
+SRC_SINE = 3
+SRC_MODGAUSS = 4
 
 
 @dataclasses.dataclass
@@ -39,6 +41,8 @@ class Source:
 
     kind: SRC_GAUSSIAN with params (amp, t0, tau), g = exp(-((t - t0)/tau)^2)
           SRC_RICKER   with params (amp, t0, f),   g = (1 - 2 pi^2 f^2 s^2) exp(-pi^2 f^2 s^2), s = t - t0
+          SRC_SINE     with params (amp, f, T),    g = w(t) sin(2 pi f t), turn-on w = sin^2(pi t / 2T) for t < T
+          SRC_MODGAUSS with params (amp, t0, tau, f), g = exp(-((t - t0)/tau)^2) sin(2 pi f (t - t0))
     """
     cell: Tuple[int, ...]
     kind: int

@@ -310,3 +310,31 @@ def test_step_profile_matches_step():
     assert prof[0]["psi"] == 4 * (sx * ny * nz + nx * sy * nz + nx * ny * sz)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("kind", ["sine", "modgauss"])
+def test_sine_and_modulated_gaussian_sources(kind):
+    """The sinusoidal (with its turn-on) and modulated-Gaussian sources in
+    2D and 3D, through the single-step and the multi-step kernels."""
+    pb = W.dielectric2d(120, ny=104, steps=420, seed=6, nrect=6, side=(8, 30), npml=10, nprobes=4)
+    if kind == "sine":
+        pb.source.kind, pb.source.params = W.SRC_SINE, (1.0, 1.2e9, 0.8e-9)
+    else:
+        pb.source.kind, pb.source.params = W.SRC_MODGAUSS, (1.0, 1.0e-9, 0.3e-9, 1.5e9)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in ((2, (1, 4)), (3, (1, 4, 4)), (3, (2, 8, 2))):
+        got, rec, _ = run_gpu(pb, pb.steps, kernel)
+        assert_parity(got, ref, TOL, "2d %s %s" % (kind, kernel))
+        assert rel_l2(rec, rrec) <= TOL
+    pb3 = W.yee3d(shape=(36, 34, 48), steps=200, seed=4, nbox=8, side=(3, 10), npml=6, nprobes=4,
+                  tau_steps=8.0)
+    if kind == "sine":
+        pb3.source.kind, pb3.source.params = W.SRC_SINE, (1.0, 30e9, 0.1e-9)
+        pb3.source.component = "ey"
+    else:
+        pb3.source.kind, pb3.source.params = W.SRC_MODGAUSS, (1.0, 0.15e-9, 0.05e-9, 30e9)
+    ref, rrec = run_oracle(pb3, pb3.steps)
+    for kernel in ((2, (4,)), (3, (4,))):
+        got, rec, _ = run_gpu(pb3, pb3.steps, kernel)
+        assert_parity(got, ref, TOL, "3d %s %s" % (kind, kernel))
+        assert rel_l2(rec, rrec) <= TOL

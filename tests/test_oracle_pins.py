@@ -396,6 +396,56 @@ def test_source_closed_forms(orc):
     assert abs(r.min() + 2 * math.exp(-1.5)) < 1e-6
 
 
+def _spectral_peak(g, dt, fmax):
+    """Frequency of the largest |DFT| bin below fmax (zero-padded 8x)."""
+    n = 8 * len(g)
+    spec = np.abs(np.fft.rfft(g, n))
+    fr = np.fft.rfftfreq(n, dt)
+    spec[fr > fmax] = 0
+    return fr[int(np.argmax(spec))], fr[1]
+
+
+def test_source_sine_and_modulated_gaussian(orc):
+    """The sinusoidal and modulated-Gaussian sources (named by the paper
+    without formulas): properties of the readings, not their formulas."""
+    dt, f, T, amp = 1e-12, 1e9, 3e-9, 1.5
+    n = 24000
+    g = orc.source_samples(3, (amp, f, T), dt, 0, n)
+    t = (np.arange(n) + 1) * dt
+    late = t >= T
+    # after the turn-on: a sine of amplitude amp and frequency f, zero at the
+    # half periods and +-amp at the quarter periods
+    k = np.arange(7, 23)
+    z = np.rint(k / (2 * f) / dt).astype(int) - 1
+    assert np.abs(g[z]).max() < 1e-12
+    q = np.rint((k + 0.25) / f / dt).astype(int) - 1
+    assert np.allclose(np.abs(g[q]), amp, rtol=0, atol=1e-12)
+    assert np.abs(g).max() <= amp * (1 + 1e-15)
+    # the turn-on starts from zero with zero slope of its envelope: the first
+    # period is far below a bare sine's, and the envelope grows monotonically
+    assert np.abs(g[:1000]).max() < 0.2 * amp
+    peaks = [np.abs(g[int(a / dt):int((a + 1 / f) / dt)]).max() for a in np.arange(0, T, 1 / f)]
+    assert all(b >= a for a, b in zip(peaks, peaks[1:]))
+    fp, df = _spectral_peak(g[late], dt, 5 * f)
+    assert abs(fp - f) <= df
+    # without a ramp (T = 0) it is the bare sine from the first sample
+    g0 = orc.source_samples(3, (1.0, f, 0.0), dt, 0, 100)
+    assert abs(g0[0] - math.sin(2 * math.pi * f * dt)) < 1e-15
+
+    # modulated Gaussian: odd about t0, zero there, under its Gaussian
+    # envelope, spectrum centred on the carrier
+    t0, tau, fc, a2 = 2e-9, 0.5e-9, 3e9, 2.0
+    m = orc.source_samples(4, (a2, t0, tau, fc), dt, 0, 4000)
+    c = int(round(t0 / dt)) - 1  # the sample at t0
+    assert abs(m[c]) < 1e-12
+    s_ = np.arange(1, 1500)
+    assert np.abs(m[c + s_] + m[c - s_]).max() < 1e-12
+    env = a2 * np.exp(-(((np.arange(4000) + 1) * dt - t0) / tau) ** 2)
+    assert np.all(np.abs(m) <= env * (1 + 1e-12) + 1e-300)
+    fp, df = _spectral_peak(m, dt, 10 * fc)
+    assert abs(fp - fc) <= 2 * df
+
+
 # ---------------------------------------------------------------------------
 # Adjoint: exact transpose and finite differences
 # ---------------------------------------------------------------------------
