@@ -141,6 +141,16 @@ int fdtd_destroy(fdtd_sim *sim);
 int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind,
                     const double *params, const float *table, int64_t n_table);
 
+/* Soft source on every cell of the box [lo, hi) (lo, hi: ndim int32 each,
+ * host), all with the same waveform: a line source when one extent exceeds
+ * 1 (the paper uses line sources in Sec. V-B without a formula), a plane or
+ * volume source otherwise.  Same kinds, parameters and rules as
+ * fdtd_set_source (which is this call with hi = lo + 1); the box must lie in
+ * the grid, be non-empty and avoid the PEC walls of the component.
+ * FDTD_EINVAL. */
+int fdtd_set_source_box(fdtd_sim *sim, int component, const int32_t *lo, const int32_t *hi, int kind,
+                        const double *params, const float *table, int64_t n_table);
+
 /* Probe cells (ijk: n*ndim int32, host) sampled on `component` after every
  * step.  Replaces earlier probes and clears the record.  n <= 4096. */
 int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n);

@@ -229,12 +229,13 @@ void orc2d_e_layer(const orc2d_t *s, double *curl)
 
 /*
  * Run nsteps leapfrog steps.  Step k (0-based within this call):
- *   H layer, E layer, Ez[src] += src_vals[k], rec[p*rec_stride + k] = Ez[probe p].
+ *   H layer, E layer, Ez[c] += src_vals[k] for each of the nsrc source cells
+ *   c, rec[p*rec_stride + k] = Ez[probe p].
  * If design != NULL ({i0,i1,j0,j1}), the Ez value before the E layer and
  * the bracket of the E layer at every design cell are stored per step in
  * traj_ez / traj_br ([nsteps][(i1-i0)*(j1-j0)]) for the adjoint.
  */
-void orc2d_run(const orc2d_t *s, long nsteps, long src_idx, const double *src_vals,
+void orc2d_run(const orc2d_t *s, long nsteps, long nsrc, const long *src_cells, const double *src_vals,
                int np, const long *probe_idx, double *rec, long rec_stride,
                const int *design, double *traj_ez, double *traj_br)
 {
@@ -257,7 +258,7 @@ void orc2d_run(const orc2d_t *s, long nsteps, long src_idx, const double *src_va
                 for (int j = design[2]; j < design[3]; ++j)
                     traj_br[k * nd + q++] = curl[(long)i * ny + j];
         }
-        if (src_idx >= 0 && src_vals) s->ez[src_idx] += src_vals[k];
+        for (long q = 0; q < nsrc && src_vals; ++q) s->ez[src_cells[q]] += src_vals[k];
         for (int p = 0; p < np; ++p) rec[(long)p * rec_stride + k] = s->ez[probe_idx[p]];
     }
     free(curl);
@@ -480,14 +481,14 @@ void orc3d_e_layer(const orc3d_t *s)
 
 /* Run nsteps 3D steps; src_field / probe_field point at one of the six
  * component arrays of s (the soft source and probes act on that component). */
-void orc3d_run(const orc3d_t *s, long nsteps, double *src_field, long src_idx,
+void orc3d_run(const orc3d_t *s, long nsteps, double *src_field, long nsrc, const long *src_cells,
                const double *src_vals, const double *probe_field, int np,
                const long *probe_idx, double *rec, long rec_stride)
 {
     for (long k = 0; k < nsteps; ++k) {
         orc3d_h_layer(s);
         orc3d_e_layer(s);
-        if (src_field && src_idx >= 0 && src_vals) src_field[src_idx] += src_vals[k];
+        for (long q = 0; q < nsrc && src_field && src_vals; ++q) src_field[src_cells[q]] += src_vals[k];
         for (int p = 0; p < np; ++p) rec[(long)p * rec_stride + k] = probe_field[probe_idx[p]];
     }
 }

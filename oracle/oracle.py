@@ -78,7 +78,7 @@ def lib():
             L.orc_source.argtypes = [C.c_int, DP, C.c_double, C.c_long, C.c_long, DP]
             L.orc2d_h_layer.argtypes = [C.POINTER(_O2)]
             L.orc2d_e_layer.argtypes = [C.POINTER(_O2), DP]
-            L.orc2d_run.argtypes = [C.POINTER(_O2), C.c_long, C.c_long, DP, C.c_int, LP, DP,
+            L.orc2d_run.argtypes = [C.POINTER(_O2), C.c_long, C.c_long, LP, DP, C.c_int, LP, DP,
                                     C.c_long, IP, DP, DP]
             L.orc2d_adj_step.argtypes = [C.POINTER(_O2), C.POINTER(_A2)]
             L.orc2d_adjoint.argtypes = [C.POINTER(_O2), C.POINTER(_A2), C.c_long, C.c_int, LP,
@@ -86,7 +86,7 @@ def lib():
                                         C.c_double, DP]
             L.orc3d_h_layer.argtypes = [C.POINTER(_O3)]
             L.orc3d_e_layer.argtypes = [C.POINTER(_O3)]
-            L.orc3d_run.argtypes = [C.POINTER(_O3), C.c_long, DP, C.c_long, DP, DP, C.c_int,
+            L.orc3d_run.argtypes = [C.POINTER(_O3), C.c_long, DP, C.c_long, LP, DP, DP, C.c_int,
                                     LP, DP, C.c_long]
             _lib = L
     return _lib
@@ -162,7 +162,7 @@ class Oracle2D:
     def from_problem(cls, pb):
         o = cls(pb.shape, pb.dx, pb.dt, pb.eps_r, pb.sigma, pb.mu_r, pb.npml, pb.cpml)
         if pb.source is not None:
-            o.set_source(pb.source.cell, pb.source.kind, pb.source.params)
+            o.set_source(pb.source.cell, pb.source.kind, pb.source.params, hi=getattr(pb.source, "hi", None))
         o.set_probes(pb.probes)
         return o
 
@@ -177,8 +177,11 @@ class Oracle2D:
         self._keep = s
         return s
 
-    def set_source(self, cell, kind, params):
-        self.src = (int(cell[0]) * self.shape[1] + int(cell[1]), int(kind), tuple(params))
+    def set_source(self, cell, kind, params, hi=None):
+        """Soft Ez source at cell, or on every cell of the box [cell, hi)."""
+        hi = tuple(hi) if hi is not None else (cell[0] + 1, cell[1] + 1)
+        cells = [i * self.shape[1] + j for i in range(cell[0], hi[0]) for j in range(cell[1], hi[1])]
+        self.src = (np.array(cells, np.int64), int(kind), tuple(params))
 
     def set_probes(self, cells):
         cells = np.asarray(cells, np.int64).reshape(-1, 2)
@@ -190,10 +193,11 @@ class Oracle2D:
         s = self._struct()
         P = len(self.probes)
         rec = np.zeros((P, nsteps), np.float64)
-        src_idx, vals = -1, None
+        cells, vals = np.zeros(1, np.int64), None
         if self.src is not None:
-            src_idx = self.src[0]
+            cells = self.src[0]
             vals = source_samples(self.src[1], self.src[2], self.dt, self.n, nsteps)
+        nsrc = len(cells) if self.src is not None else 0
         dz = tz = tb = None
         if design is not None:
             dz = (C.c_int * 4)(*design)
@@ -201,7 +205,7 @@ class Oracle2D:
             tz = np.zeros((nsteps, nd), np.float64)
             tb = np.zeros((nsteps, nd), np.float64)
         pr = self.probes if P else np.zeros(1, np.int64)
-        lib().orc2d_run(C.byref(s), nsteps, src_idx, _p(vals), P, pr.ctypes.data_as(LP),
+        lib().orc2d_run(C.byref(s), nsteps, nsrc, cells.ctypes.data_as(LP), _p(vals), P, pr.ctypes.data_as(LP),
                         _p(rec), nsteps, dz, _p(tz), _p(tb))
         self.n += nsteps
         self.rec.append(rec)
@@ -301,7 +305,8 @@ class Oracle3D:
     def from_problem(cls, pb):
         o = cls(pb.shape, pb.dx, pb.dt, pb.eps_r, pb.sigma, pb.mu_r, pb.npml, pb.cpml)
         if pb.source is not None:
-            o.set_source(pb.source.cell, pb.source.kind, pb.source.params, pb.source.component)
+            o.set_source(pb.source.cell, pb.source.kind, pb.source.params, pb.source.component,
+                         hi=getattr(pb.source, "hi", None))
         o.set_probes(pb.probes, pb.probe_component)
         return o
 
@@ -320,8 +325,13 @@ class Oracle3D:
         self._keep = s
         return s
 
-    def set_source(self, cell, kind, params, component="ez"):
-        self.src = (self._lin(cell), int(kind), tuple(params), component)
+    def set_source(self, cell, kind, params, component="ez", hi=None):
+        """Soft source on `component` at cell, or on every cell of the box
+        [cell, hi)."""
+        hi = tuple(hi) if hi is not None else tuple(int(c) + 1 for c in cell)
+        cells = [self._lin((i, j, k)) for i in range(cell[0], hi[0]) for j in range(cell[1], hi[1])
+                 for k in range(cell[2], hi[2])]
+        self.src = (np.array(cells, np.int64), int(kind), tuple(params), component)
 
     def set_probes(self, cells, component="ez"):
         cells = np.asarray(cells, np.int64).reshape(-1, 3)
@@ -332,13 +342,14 @@ class Oracle3D:
         s = self._struct()
         P = len(self.probes)
         rec = np.zeros((P, nsteps), np.float64)
-        sf, src_idx, vals = None, -1, None
+        sf, cells, vals = None, np.zeros(1, np.int64), None
         if self.src is not None:
-            src_idx = self.src[0]
+            cells = self.src[0]
             sf = _p(getattr(self, self.src[3]))
             vals = source_samples(self.src[1], self.src[2], self.dt, self.n, nsteps)
+        nsrc = len(cells) if self.src is not None else 0
         pr = self.probes if P else np.zeros(1, np.int64)
-        lib().orc3d_run(C.byref(s), nsteps, sf, src_idx, _p(vals),
+        lib().orc3d_run(C.byref(s), nsteps, sf, nsrc, cells.ctypes.data_as(LP), _p(vals),
                         _p(getattr(self, self.probe_comp)), P, pr.ctypes.data_as(LP),
                         _p(rec), nsteps)
         self.n += nsteps

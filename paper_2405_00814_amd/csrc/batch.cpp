@@ -194,6 +194,7 @@ static void batch_sync_probs(fdtd_batch &b) {
             key.push_back((const void *)(intptr_t)h[q].src_len);
             key.push_back((const void *)(intptr_t)h[q].rec_base);
             key.push_back((const void *)(intptr_t)h[q].src_idx);
+            for (int c = 0; c < 4; ++c) key.push_back((const void *)(intptr_t)h[q].src_box[c]);
             key.push_back((const void *)(intptr_t)h[q].np);
         }
         if (b.probs_dev[par] && key == b.probs_key[par]) continue;

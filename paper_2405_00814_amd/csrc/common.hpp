@@ -51,7 +51,8 @@ struct Prob2D {
     AxisDev x, y;
     State2D s0;        // state read (n)
     State2D s1;        // state written (n+1); equal to s0 for in-place kernels
-    int64_t src_idx;   // -1 => none
+    int64_t src_idx;   // -1 => none; else the source box's first cell
+    int src_box[6];    // source cells [b0, b1) x [b2, b3) (x [b4, b5) = [0, 1))
     const float *src_vals;  // device table, indexed by absolute step
     int64_t src_len;
     int np;
@@ -78,7 +79,8 @@ struct Prob3D {
     float db0;
     AxisDev x, y, z;
     State3D s0, s1;
-    int64_t src_idx;
+    int64_t src_idx;   // -1 => none; else the source box's first cell
+    int src_box[6];    // source cells [b0, b1) x [b2, b3) x [b4, b5)
     int src_comp;
     const float *src_vals;
     int64_t src_len;
@@ -89,6 +91,12 @@ struct Prob3D {
     int64_t rec_stride;
     int64_t rec_base;
 };
+
+// Cell (i, j, k) lies in the source box b (2D: k = 0, b4 = 0, b5 = 1).
+__host__ __device__ inline bool in_src(const int *b, int i, int j, int k) {
+    return (unsigned)(i - b[0]) < (unsigned)(b[1] - b[0]) && (unsigned)(j - b[2]) < (unsigned)(b[3] - b[2]) &&
+           (unsigned)(k - b[4]) < (unsigned)(b[5] - b[4]);
+}
 
 // Probes grouped by tile: tile t owns sorted entries [start[t], start[t+1]).
 struct ProbeTiles {
@@ -237,7 +245,7 @@ hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,
                             const int *dst, const float *x, float *y, int nrows,
                             hipStream_t st);
 // Soft source and probes on a node vector.
-hipError_t launch_node_source_probe(float *x, int64_t src_node, const float *src_vals,
+hipError_t launch_node_source_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                     int64_t src_len, int64_t step, int np,
                                     const int *probe_node, float *rec, int64_t rec_stride,
                                     int64_t rec_index, hipStream_t st);

@@ -57,22 +57,23 @@ hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w, c
     return hipGetLastError();
 }
 
-// Soft source on one node, then probe samples (one block).
-__global__ void k_node_src_probe(float *x, int64_t src_node, const float *src_vals,
+// Soft source on its nodes, then probe samples (one block).
+__global__ void k_node_src_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                  int64_t src_len, int64_t step, int np, const int *probe_node,
                                  float *rec, int64_t rec_stride, int64_t rec_index) {
-    if (threadIdx.x == 0 && src_node >= 0 && step < src_len) x[src_node] += src_vals[step];
+    if (step < src_len)
+        for (int q = threadIdx.x; q < nsrc; q += blockDim.x) x[src_nodes[q]] += src_vals[step];
     __syncthreads();
     for (int q = threadIdx.x; q < np; q += blockDim.x)
         rec[(int64_t)q * rec_stride + rec_index] = x[probe_node[q]];
 }
 
-hipError_t launch_node_source_probe(float *x, int64_t src_node, const float *src_vals,
+hipError_t launch_node_source_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                     int64_t src_len, int64_t step, int np,
                                     const int *probe_node, float *rec, int64_t rec_stride,
                                     int64_t rec_index, hipStream_t st) {
-    if (src_node < 0 && np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_node_src_probe, dim3(1), dim3(64), 0, st, x, src_node, src_vals, src_len,
+    if (nsrc <= 0 && np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_src_probe, dim3(1), dim3(256), 0, st, x, src_nodes, nsrc, src_vals, src_len,
                        step, np, probe_node, rec, rec_stride, rec_index);
     return hipGetLastError();
 }

@@ -209,7 +209,18 @@ void graph_refold(Sim &s) { build_graph(s); }
 
 void graph_set_source_probes(Sim &s) {
     Sim::Graph &g = s.g;
-    g.src_node = s.src_idx >= 0 ? g.ez_node[(size_t)s.src_idx] : -1;
+    s.al.put(g.src_nodes);
+    g.src_nodes = nullptr;
+    g.nsrc = 0;
+    if (s.src_idx >= 0) {
+        std::vector<int> sn;
+        for (int i = s.src_box[0]; i < s.src_box[1]; ++i)
+            for (int j = s.src_box[2]; j < s.src_box[3]; ++j) sn.push_back((int)g.ez_node[(size_t)i * s.ny + j]);
+        int64_t dummy = 0;
+        g.src_nodes = up(s.al, sn, s.st, dummy);
+        g.nsrc = (int)sn.size();
+        hip_check(hipStreamSynchronize(s.st), "sync");
+    }
     s.al.put(g.probe_node);
     g.probe_node = nullptr;
     if (!s.probe_cells.empty()) {
@@ -227,11 +238,11 @@ void graph_step(Sim &s, int64_t step) {
         hip_check(launch_csr_layer(L->rowptr, L->col, L->w, L->dst, g.x, g.x, L->nrows, s.st), "csr layer");
         s.last_launches += 1;
     }
-    hip_check(launch_node_source_probe(g.x, g.src_node, s.src_dev, s.src_len, step,
+    hip_check(launch_node_source_probe(g.x, g.src_nodes, g.nsrc, s.src_dev, s.src_len, step,
                                        (int)s.probe_cells.size(), g.probe_node, s.rec_dev, s.rec_cap,
                                        step - (s.n_done - s.n_rec), s.st),
               "source/probe");
-    if (g.src_node >= 0 || !s.probe_cells.empty()) s.last_launches += 1;
+    if (g.nsrc > 0 || !s.probe_cells.empty()) s.last_launches += 1;
 }
 
 static int64_t node_of(const Sim &s, int comp, int i, int j) {

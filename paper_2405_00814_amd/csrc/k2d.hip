@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k2d_ref_e(Prob2D p, int64_t step) {
         const float ca = p.ca ? p.ca[c] : 1.f;
         e = ca * e + p.cb[c] * (tx - ty);
     }
-    if (c == p.src_idx && step < p.src_len) e += p.src_vals[step];
+    if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0) && step < p.src_len) e += p.src_vals[step];
     p.s0.ez[c] = e;
 }
 
@@ -338,7 +338,7 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
                     cap_br[q] = br;
                 }
             }
-            if (row + j == p.src_idx) ez_w[v] += sval;
+            if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0)) ez_w[v] += sval;
         }
         if (valid) {
             stv<V>(p.s1.hx + row + jb, hx_n);

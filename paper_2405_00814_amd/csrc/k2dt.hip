@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                         cap.br[q] = tx - ty;
                     }
                 }
-                if ((int64_t)i * ny + j == p.src_idx) out.e[v] += sval[k];
+                if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0)) out.e[v] += sval[k];
             }
             // outside the grid: the ghost values are zero
             if (!rv || !valid) {

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k3d_ref_e(Prob3D p, int64_t step) {
         if (jj >= 0) b += cpml_upd(ps[PSI_EZY], ps[PSI_EZY], ys_idx(i, jj, k, sy, nz), p.y.bE[j], p.y.cE[j], dHxy);
         f[FDTD_EZ][c] = ca * f[FDTD_EZ][c] + cb * (a - b);
     }
-    if (c == p.src_idx && step < p.src_len) f[p.src_comp][c] += p.src_vals[step];
+    if (p.src_idx >= 0 && in_src(p.src_box, i, j, k) && step < p.src_len) f[p.src_comp][c] += p.src_vals[step];
 }
 
 __global__ void k_probe_3d(Prob3D p, int64_t step) {

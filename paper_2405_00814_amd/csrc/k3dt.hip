@@ -279,13 +279,15 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     // The element is picked by selects, never by an index computed at run
     // time: a computed index into a register array moves the array to
     // scratch memory for the whole kernel.
-    auto add_source = [&](unsigned c, int64_t n, float (&ex)[V], float (&ey)[V], float (&ez)[V]) {
-        const int64_t d = p.src_idx - (int64_t)c;
-        if (!ok || d < 0 || d >= V) return;
+    auto add_source = [&](int i, int64_t n, float (&ex)[V], float (&ey)[V], float (&ez)[V]) {
+        const int *b = p.src_box;
+        if (p.src_idx < 0 || !ok || (unsigned)(i - b[0]) >= (unsigned)(b[1] - b[0]) ||
+            (unsigned)(j - b[2]) >= (unsigned)(b[3] - b[2]))
+            return;
         const float sval = n < p.src_len ? p.src_vals[n] : 0.f;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const bool at = d == v;
+            const bool at = (unsigned)(kb + v - b[4]) < (unsigned)(b[5] - b[4]);
             ex[v] = (at && p.src_comp == FDTD_EX) ? ex[v] + sval : ex[v];
             ey[v] = (at && p.src_comp == FDTD_EY) ? ey[v] + sval : ey[v];
             ez[v] = (at && p.src_comp == FDTD_EZ) ? ez[v] + sval : ez[v];
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             zstash_w(i & 1, 2, o3);
             zstash_w(i & 1, 3, o4);
         }
-        add_source(c, step, ex1, ey1, ez1);
+        add_source(i, step, ex1, ey1, ez1);
         if (!la) { zero(ex1); zero(ey1); zero(ez1); zero(hx); zero(hy); zero(hz); }
         if (own && la && i >= T.i0 && i < T.i1) record(i, c, step, ex1, ey1, ez1, hx, hy, hz);
         stv<V>(&L1x[tq], ex1);
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
                 zout(2, p3);
                 zout(3, p4);
             }
-            add_source(cq, step + 1, e2x, e2y, e2z);
+            add_source(ib, step + 1, e2x, e2y, e2z);
             record(ib, cq, step + 1, e2x, e2y, e2z, hx2, hy2, hz2);
             if (ok) {
                 stv<V>(p.s1.f[FDTD_EX] + cq, e2x);

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
             }
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if ((int64_t)(c + v) == p.src_idx && ok) {
+                if (p.src_idx >= 0 && ok && in_src(p.src_box, i, j, kb + v)) {
                     const float sval = step < p.src_len ? p.src_vals[step] : 0.f;
                     if (p.src_comp == FDTD_EX) exw[v] += sval;
                     else if (p.src_comp == FDTD_EY) eyw[v] += sval;

@@ -208,6 +208,7 @@ Prob2D Sim::prob2d(int si, int so) const {
     p.s0 = State2D{f[si][FDTD_EZ], f[si][FDTD_HX], f[si][FDTD_HY], psi[si][0], psi[si][1], psi[si][2], psi[si][3]};
     p.s1 = State2D{f[so][FDTD_EZ], f[so][FDTD_HX], f[so][FDTD_HY], psi[so][0], psi[so][1], psi[so][2], psi[so][3]};
     p.src_idx = src_idx;
+    for (int q = 0; q < 6; ++q) p.src_box[q] = src_box[q];
     p.src_vals = src_dev;
     p.src_len = src_len;
     p.np = (int)probe_cells.size();
@@ -240,6 +241,7 @@ Prob3D Sim::prob3d(int si, int so) const {
         p.s1.psi[a] = psi[so][a];
     }
     p.src_idx = src_idx;
+    for (int q = 0; q < 6; ++q) p.src_box[q] = src_box[q];
     p.src_comp = src_comp;
     p.src_vals = src_dev;
     p.src_len = src_len;
@@ -949,6 +951,14 @@ static bool comp_ok(const Sim &s, int comp) {
 
 int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, const double *params,
                     const float *table, int64_t n_table) {
+    if (kind < 0 || !ijk) return fdtd_set_source_box(sim, component, ijk, ijk, kind, params, table, n_table);
+    int32_t hi[3] = {ijk[0] + 1, ijk[1] + 1, 1};
+    if (sim && sim->s.ndim == 3) hi[2] = ijk[2] + 1;
+    return fdtd_set_source_box(sim, component, ijk, hi, kind, params, table, n_table);
+}
+
+int fdtd_set_source_box(fdtd_sim *sim, int component, const int32_t *lo, const int32_t *hi, int kind,
+                        const double *params, const float *table, int64_t n_table) {
     GEM_TRY
     if (!sim) fail(FDTD_EINVAL, "sim is NULL");
     Sim &s = sim->s;
@@ -958,13 +968,21 @@ int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, 
         if (s.is_graph) graph_set_source_probes(s);
         return FDTD_OK;
     }
-    if (!ijk) fail(FDTD_EINVAL, "ijk is NULL");
+    if (!lo || !hi) fail(FDTD_EINVAL, "lo or hi is NULL");
     if (component < FDTD_EX || component > FDTD_EZ || (s.ndim == 2 && component != FDTD_EZ))
         fail(FDTD_EINVAL, "source component must be an E component present in the grid");
-    const int64_t c = lin_cell(s, ijk);
-    if (c < 0) fail(FDTD_EINVAL, "source cell outside the grid");
-    int cc[3] = {ijk[0], ijk[1], s.ndim == 3 ? ijk[2] : 1};
-    if (on_wall(s, component, cc)) fail(FDTD_EINVAL, "source cell lies on a PEC wall of that component");
+    const int n3[3] = {s.nx, s.ny, s.ndim == 3 ? s.nz : 1};
+    int box[6] = {0, 1, 0, 1, 0, 1};
+    for (int a = 0; a < s.ndim; ++a) {
+        if (lo[a] < 0 || hi[a] > n3[a] || lo[a] >= hi[a]) fail(FDTD_EINVAL, "source box empty or outside the grid");
+        box[2 * a] = lo[a];
+        box[2 * a + 1] = hi[a];
+    }
+    const int64_t c = lin_cell(s, lo);
+    // the PEC walls of an E component are low planes: the box avoids them if
+    // its low corner does
+    int cc[3] = {lo[0], lo[1], s.ndim == 3 ? lo[2] : 1};
+    if (on_wall(s, component, cc)) fail(FDTD_EINVAL, "source box touches a PEC wall of that component");
     if (kind == FDTD_SRC_TABLE) {
         if (!table || n_table < 0) fail(FDTD_EINVAL, "table source needs table and n_table >= 0");
         for (int64_t n = 0; n < n_table; ++n)
@@ -988,6 +1006,7 @@ int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind, 
     s.src_cap = s.src_len = 0;
     s.src_comp = component;
     s.src_idx = c;
+    for (int q = 0; q < 6; ++q) s.src_box[q] = box[q];
     s.src_kind = kind;
     if (kind == FDTD_SRC_TABLE) {
         s.src_table.assign(table, table + n_table);

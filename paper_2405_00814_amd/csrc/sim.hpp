@@ -79,7 +79,8 @@ struct Sim {
 
     // source
     int src_comp = FDTD_EZ;
-    int64_t src_idx = -1;
+    int64_t src_idx = -1;                 // first cell of the source box (-1: none)
+    int src_box[6] = {0, 0, 0, 0, 0, 0};  // [lo, hi) per axis (2D: z = [0, 1))
     int src_kind = -1;
     double src_par[4] = {0, 0, 0, 0};
     std::vector<float> src_table;   // TABLE kind
@@ -146,7 +147,8 @@ struct Sim {
             int64_t nnz = 0;
         } h_aux, h_main, e_aux, e_main;
         std::vector<int64_t> ez_node;     // node of Ez(i,j) (host)
-        int64_t src_node = -1;
+        int *src_nodes = nullptr;  // device: the source box's Ez nodes
+        int nsrc = 0;
         int *probe_node = nullptr;
         int64_t bytes = 0;
     } g;

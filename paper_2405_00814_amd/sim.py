@@ -121,7 +121,9 @@ class Sim:
     def from_problem(cls, pb, graph=False, **kw):
         s = cls(pb.shape, pb.dx, pb.dt, pb.eps_r, pb.mu_r, pb.sigma, pb.npml, pb.cpml,
                 graph=graph, **kw)
-        if pb.source is not None:
+        if pb.source is not None and pb.source.hi is not None:
+            s.set_source_box(pb.source.component, pb.source.cell, pb.source.hi, pb.source.kind, pb.source.params)
+        elif pb.source is not None:
             s.set_source(pb.source.component, pb.source.cell, pb.source.kind, pb.source.params)
         if len(pb.probes):
             s.set_probes(pb.probe_component, pb.probes)
@@ -151,6 +153,19 @@ class Sim:
             tp = self._table.ctypes.data_as(C.POINTER(C.c_float))
             nt = self._table.size
         L.call("fdtd_set_source", self.h, _comp(comp), ijk, int(kind), par, tp, nt)
+
+    def set_source_box(self, comp, lo, hi, kind, params=(0.0, 0.0, 0.0), table=None):
+        """Soft source on every cell of [lo, hi) (a line source when one
+        extent exceeds 1)."""
+        a = (C.c_int32 * 3)(*[int(v) for v in lo] + [0] * (3 - len(lo)))
+        b = (C.c_int32 * 3)(*[int(v) for v in hi] + [1] * (3 - len(hi)))
+        par = (C.c_double * 4)(*[float(v) for v in params])
+        tp, nt = None, 0
+        if table is not None:
+            self._table = np.ascontiguousarray(np.asarray(table, np.float32))
+            tp = self._table.ctypes.data_as(C.POINTER(C.c_float))
+            nt = self._table.size
+        L.call("fdtd_set_source_box", self.h, _comp(comp), a, b, int(kind), par, tp, nt)
 
     def clear_source(self):
         L.call("fdtd_set_source", self.h, L.FDTD_EZ, None, -1, None, None, 0)

@@ -37,7 +37,9 @@ SRC_MODGAUSS = 4
 
 @dataclasses.dataclass
 class Source:
-    """A soft point source: Ez[cell] += amp * g((n+1) dt) after each E update.
+    """A soft source: E[cell] += amp * g((n+1) dt) after each E update; with
+    hi set, on every cell of the box [cell, hi) (a line source when one
+    extent exceeds 1).
 
     kind: SRC_GAUSSIAN with params (amp, t0, tau), g = exp(-((t - t0)/tau)^2)
           SRC_RICKER   with params (amp, t0, f),   g = (1 - 2 pi^2 f^2 s^2) exp(-pi^2 f^2 s^2), s = t - t0
@@ -46,8 +48,9 @@ class Source:
     """
     cell: Tuple[int, ...]
     kind: int
-    params: Tuple[float, float, float]
+    params: Tuple[float, ...]
     component: str = "ez"
+    hi: Optional[Tuple[int, ...]] = None
 
 
 @dataclasses.dataclass

@@ -446,6 +446,41 @@ def test_source_sine_and_modulated_gaussian(orc):
     assert abs(fp - fc) <= 2 * df
 
 
+def test_line_source_is_superposition_of_point_sources(orc):
+    """A box (line) source drives every cell of the box with the same
+    waveform: by linearity its fields equal the sum of the runs with one
+    point source per cell."""
+    pb = W.dielectric2d(40, ny=36, steps=60, seed=2, nrect=3, side=(4, 10), npml=5, nprobes=2)
+    lo, hi = (12, 9), (13, 17)
+    o = orc.Oracle2D.from_problem(pb)
+    o.set_source(lo, pb.source.kind, pb.source.params, hi=hi)
+    o.run(60)
+    acc = {f: np.zeros(pb.shape) for f in ("ez", "hx", "hy")}
+    for j in range(lo[1], hi[1]):
+        q = orc.Oracle2D.from_problem(pb)
+        q.set_source((lo[0], j), pb.source.kind, pb.source.params)
+        q.run(60)
+        for f in acc:
+            acc[f] += getattr(q, f)
+    for f in acc:
+        assert _rel(getattr(o, f), acc[f]) < 1e-12, f
+    pb3 = W.yee3d(shape=(14, 12, 16), steps=30, seed=1, nbox=2, side=(2, 4), npml=3, nprobes=1, tau_steps=4.0)
+    lo3, hi3 = (5, 4, 6), (7, 5, 10)
+    o = orc.Oracle3D.from_problem(pb3)
+    o.set_source(lo3, pb3.source.kind, pb3.source.params, "ey", hi=hi3)
+    o.run(30)
+    acc = {f: np.zeros(pb3.shape) for f in ("ex", "ey", "ez", "hx", "hy", "hz")}
+    for i in range(lo3[0], hi3[0]):
+        for k in range(lo3[2], hi3[2]):
+            q = orc.Oracle3D.from_problem(pb3)
+            q.set_source((i, 4, k), pb3.source.kind, pb3.source.params, "ey")
+            q.run(30)
+            for f in acc:
+                acc[f] += getattr(q, f)
+    for f in acc:
+        assert _rel(getattr(o, f), acc[f]) < 1e-12, f
+
+
 # ---------------------------------------------------------------------------
 # Adjoint: exact transpose and finite differences
 # ---------------------------------------------------------------------------
