@@ -162,6 +162,19 @@ def bench_2d(args, steps=10000):
                              achieved_GBps=gbytes * gs / tg / 1e9,
                              hbm_frac=gbytes * gs / tg / PEAK_HBM, launches_per_step=lg / gs)
     g.close()
+    # frequency-domain monitor: Ez on the central 2048^2 box at 4 frequencies
+    # (single steps while it is set), against single steps without it
+    ms = 400
+    m = Sim.from_problem(pb)
+    m.set_kernel(2, (2, 4))
+    tp, _, _ = timed_steps(m, ms, 5)
+    m.set_dft("ez", (1024, 1024), (3072, 3072), [0.5e9, 1.0e9, 1.5e9, 2.0e9])
+    tm, _, _ = timed_steps(m, ms, 5)
+    m.close()
+    out["dft_monitor"] = dict(steps=ms, box_cells=2048 * 2048, frequencies=4,
+                              single_step_gcells_per_s=pb.cells * ms / tp / 1e9,
+                              with_monitor_gcells_per_s=pb.cells * ms / tm / 1e9,
+                              monitor_us_per_step=(tm - tp) / ms * 1e6)
     return out
 
 

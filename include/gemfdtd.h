@@ -151,6 +151,27 @@ int fdtd_set_source(fdtd_sim *sim, int component, const int32_t *ijk, int kind,
 int fdtd_set_source_box(fdtd_sim *sim, int component, const int32_t *lo, const int32_t *hi, int kind,
                         const double *params, const float *table, int64_t n_table);
 
+/* Frequency-domain monitor (the paper motivates frequency-domain responses,
+ * Sec. I, without a formulation): running discrete Fourier transform of
+ * `component` on every cell of the box [lo, hi) (ndim int32 each, host) at
+ * the nf frequencies freqs (Hz, >= 0, host): after every step n, from this
+ * call on,
+ *   X_q[c] += F^{n+1}[c] exp(-2 pi i f_q t_n) dt,
+ * t_n = (n+1) dt for an E component and (n+1/2) dt for an H component (the
+ * sample's time on the leapfrog grid), summed in FP64.  nf in [0, 16]; a
+ * call replaces the monitor (nf = 0 removes it).  While a monitor is set,
+ * fdtd_step advances one step per pass (the multi-step kernels do not keep
+ * the intermediate steps), and fdtd_step_profile, fdtd_autotune and
+ * fdtd_adjoint_eps return FDTD_ESTATE; fdtd_reset zeroes the sums.
+ * FDTD_EINVAL for a bad box, component or frequency. */
+int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t *hi, int32_t nf,
+                 const double *freqs);
+
+/* The monitor's sums: re, im host arrays [nf][box cells] (cells in the
+ * box's row-major order, last axis fastest); nsteps (optional) = steps
+ * summed.  re = im = NULL: only nsteps.  FDTD_ESTATE without a monitor. */
+int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps);
+
 /* Probe cells (ijk: n*ndim int32, host) sampled on `component` after every
  * step.  Replaces earlier probes and clears the record.  n <= 4096. */
 int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n);

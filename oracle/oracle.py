@@ -157,6 +157,7 @@ class Oracle2D:
         self.probes = np.zeros((0,), np.int64)
         self.n = 0
         self.rec = []
+        self.dft = None
 
     @classmethod
     def from_problem(cls, pb):
@@ -183,6 +184,9 @@ class Oracle2D:
         cells = [i * self.shape[1] + j for i in range(cell[0], hi[0]) for j in range(cell[1], hi[1])]
         self.src = (np.array(cells, np.int64), int(kind), tuple(params))
 
+    def set_dft(self, comp, lo, hi, freqs):
+        _set_dft(self, comp, lo, hi, freqs)
+
     def set_probes(self, cells):
         cells = np.asarray(cells, np.int64).reshape(-1, 2)
         self.probes = np.ascontiguousarray(cells[:, 0] * self.shape[1] + cells[:, 1])
@@ -190,6 +194,8 @@ class Oracle2D:
     def run(self, nsteps, design=None):
         """Advance nsteps; returns probe samples [P, nsteps] and, with a
         design box, the per-step (Ez before E layer, bracket) trajectories."""
+        if self.dft is not None and design is None and nsteps > 1:
+            return np.concatenate([self.run(1) for _ in range(nsteps)], axis=1)
         s = self._struct()
         P = len(self.probes)
         rec = np.zeros((P, nsteps), np.float64)
@@ -209,6 +215,8 @@ class Oracle2D:
                         _p(rec), nsteps, dz, _p(tz), _p(tb))
         self.n += nsteps
         self.rec.append(rec)
+        if self.dft is not None:
+            _dft_sample(self, nsteps)
         if design is not None:
             return rec, tz, tb
         return rec
@@ -300,6 +308,7 @@ class Oracle3D:
         self.probe_comp = "ez"
         self.n = 0
         self.rec = []
+        self.dft = None
 
     @classmethod
     def from_problem(cls, pb):
@@ -333,12 +342,17 @@ class Oracle3D:
                  for k in range(cell[2], hi[2])]
         self.src = (np.array(cells, np.int64), int(kind), tuple(params), component)
 
+    def set_dft(self, comp, lo, hi, freqs):
+        _set_dft(self, comp, lo, hi, freqs)
+
     def set_probes(self, cells, component="ez"):
         cells = np.asarray(cells, np.int64).reshape(-1, 3)
         self.probes = np.ascontiguousarray(np.array([self._lin(c) for c in cells], np.int64))
         self.probe_comp = component
 
     def run(self, nsteps):
+        if self.dft is not None and nsteps > 1:
+            return np.concatenate([self.run(1) for _ in range(nsteps)], axis=1)
         s = self._struct()
         P = len(self.probes)
         rec = np.zeros((P, nsteps), np.float64)
@@ -354,6 +368,8 @@ class Oracle3D:
                         _p(rec), nsteps)
         self.n += nsteps
         self.rec.append(rec)
+        if self.dft is not None:
+            _dft_sample(self, nsteps)
         return rec
 
     def h_layer(self):
@@ -373,6 +389,29 @@ class Oracle3D:
     def set_state(self, st):
         for n, v in st.items():
             getattr(self, n)[...] = v
+
+
+def _set_dft(o, comp, lo, hi, freqs):
+    """Frequency-domain monitor (the paper motivates frequency-domain
+    responses, Sec. I; no formulation given): the discrete Fourier sum
+    X_q = sum_n F^{n+1}[box] exp(-2 pi i f_q t_n) dt over the steps run from
+    now on, t_n = (n+1) dt for E and (n+1/2) dt for H (the sample's time on
+    the leapfrog grid)."""
+    box = tuple(slice(int(a), int(b)) for a, b in zip(lo, hi))
+    o.dft = dict(comp=comp, box=box, f=np.asarray(freqs, np.float64),
+                 X=np.zeros((len(freqs),) + tuple(b.stop - b.start for b in box), np.complex128), n=0)
+
+
+def _dft_sample(o, nsteps):
+    # called after exactly one step (run steps one by one while a monitor is set)
+    assert nsteps == 1
+    d = o.dft
+    step = o.n - 1
+    t = (step + (0.5 if d["comp"].startswith("h") else 1.0)) * o.dt
+    v = getattr(o, d["comp"])[d["box"]]
+    for q, f in enumerate(d["f"]):
+        d["X"][q] += v * np.exp(-2j * np.pi * f * t) * o.dt
+    d["n"] += 1
 
 
 def for_problem(pb):

@@ -240,6 +240,16 @@ bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);
 
 hipError_t launch_nonfinite(const float *a, int64_t n, int *flag, hipStream_t st);
 
+// Frequency-domain monitor (dft.hip): acc[2q][c] += f[idx[c]] re[q],
+// acc[2q+1][c] += f[idx[c]] im[q] for the nf <= kDftMaxFreq frequencies (acc
+// rows of npts doubles).
+constexpr int kDftMaxFreq = 16;
+struct DftPhase {
+    double re[kDftMaxFreq], im[kDftMaxFreq];
+};
+hipError_t launch_dft(const float *f, const int64_t *idx, int64_t npts, int nf, const DftPhase &ph, double *acc,
+                      hipStream_t st);
+
 // CSR layer: y[dst[r]] = sum_{e in row r} w[e] * x[col[e]] for r < nrows.
 hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,
                             const int *dst, const float *x, float *y, int nrows,

@@ -252,6 +252,8 @@ static int64_t node_of(const Sim &s, int comp, int i, int j) {
     return 2LL * i + (int64_t)nx * (3LL * j + 1);
 }
 
+int64_t graph_node(const Sim &s, int comp, int i, int j) { return node_of(s, comp, i, j); }
+
 void graph_get_field(Sim &s, int comp, float *host) {
     std::vector<float> x((size_t)s.g.nnodes);
     hip_check(hipMemcpyAsync(x.data(), s.g.x, x.size() * 4, hipMemcpyDeviceToHost, s.st), "copy");

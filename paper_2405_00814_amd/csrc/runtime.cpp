@@ -452,6 +452,23 @@ void Sim::launch_tb2d(int64_t step, const CapArgs *cap) {
 }
 
 
+// After step `step` (state step+1): the monitor's sums gain the field
+// sample times exp(-2 pi i f t) dt, t = (step+1) dt for E and (step+1/2) dt
+// for H (the sample's time on the leapfrog grid).
+void Sim::dft_accumulate(int64_t step) {
+    DftPhase ph{};
+    const double t = ((double)step + (dft.comp >= FDTD_HX ? 0.5 : 1.0)) * dt;
+    for (int q = 0; q < dft.nf; ++q) {
+        const double a = 2.0 * kPi * dft.f[q] * t;
+        ph.re[q] = std::cos(a) * dt;
+        ph.im[q] = -std::sin(a) * dt;
+    }
+    const float *fld = is_graph ? g.x : f[cur][dft.comp];
+    hip_check(launch_dft(fld, dft.idx, dft.npts, dft.nf, ph, dft.acc, st), "dft");
+    dft.nacc += 1;
+    last_launches += 1;
+}
+
 void Sim::launch_step(int64_t step) {
     if (is_graph) {
         graph_step(*this, step);
@@ -535,8 +552,10 @@ void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
 // n steps: pairs through the two-step pass where it is selected, single
 // steps otherwise
 void Sim::advance(int64_t n) {
-    const bool two = kcfg.variant == 3 && ndim == 3 && !is_graph;
-    const bool tb2 = kcfg.variant == 3 && ndim == 2 && !is_graph;
+    // a frequency-domain monitor needs every step's field: single steps
+    const bool mon = dft.comp >= 0;
+    const bool two = kcfg.variant == 3 && ndim == 3 && !is_graph && !mon;
+    const bool tb2 = kcfg.variant == 3 && ndim == 2 && !is_graph && !mon;
     const int64_t inc = probe_cells.empty() ? 0 : 1;
     int64_t q = 0;
     if (two)
@@ -555,6 +574,7 @@ void Sim::advance(int64_t n) {
     }
     for (; q < n; ++q) {
         launch_step(n_done);
+        if (mon) dft_accumulate(n_done);
         n_done += 1;
         n_rec += inc;
     }
@@ -568,6 +588,8 @@ void Sim::zero_state() {
             if (psi[s][a]) hip_check(hipMemsetAsync(psi[s][a], 0, (size_t)psi_len[a] * 4, st), "memset");
     }
     if (is_graph && g.x) hip_check(hipMemsetAsync(g.x, 0, (size_t)g.nnodes * 4, st), "memset");
+    if (dft.acc) hip_check(hipMemsetAsync(dft.acc, 0, (size_t)(2 * dft.nf * dft.npts) * 8, st), "memset");
+    dft.nacc = 0;
     cur = 0;
     n_done = 0;
     n_rec = 0;
@@ -1097,6 +1119,7 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
     if (steps < 1 || steps > 100000) fail(FDTD_EINVAL, "steps must be in [1, 100000]");
     if (max < 0 || (max > 0 && !out)) fail(FDTD_EINVAL, "bad output array");
     Sim &s = sim->s;
+    if (s.dft.comp >= 0) fail(FDTD_ESTATE, "remove the frequency-domain monitor before profiling");
     s.ensure_source(s.n_done + steps);
     s.ensure_rec(s.n_rec + steps);
     s.build_probe_tiles();
@@ -1211,6 +1234,65 @@ int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded) {
     GEM_CATCH
 }
 
+
+int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t *hi, int32_t nf,
+                 const double *freqs) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    if (nf < 0 || nf > kDftMaxFreq) fail(FDTD_EINVAL, "nf must be in [0, 16]");
+    if (nf > 0) {
+        if (!lo || !hi || !freqs) fail(FDTD_EINVAL, "NULL argument");
+        if (!comp_ok(s, component)) fail(FDTD_EINVAL, "component not present in this grid");
+        const int n3[3] = {s.nx, s.ny, s.ndim == 3 ? s.nz : 1};
+        for (int a = 0; a < s.ndim; ++a)
+            if (lo[a] < 0 || hi[a] > n3[a] || lo[a] >= hi[a]) fail(FDTD_EINVAL, "monitor box empty or outside the grid");
+        for (int q = 0; q < nf; ++q)
+            if (!std::isfinite(freqs[q]) || freqs[q] < 0) fail(FDTD_EINVAL, "frequencies must be finite and >= 0");
+    }
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    s.al.put(s.dft.idx);
+    s.al.put(s.dft.acc);
+    s.dft = Sim::Dft{};
+    if (nf == 0) return FDTD_OK;
+    Sim::Dft &d = s.dft;
+    d.comp = component;
+    d.nf = nf;
+    for (int q = 0; q < nf; ++q) d.f[q] = freqs[q];
+    const int b[6] = {lo[0], hi[0], lo[1], hi[1], s.ndim == 3 ? lo[2] : 0, s.ndim == 3 ? hi[2] : 1};
+    for (int q = 0; q < 6; ++q) d.box[q] = b[q];
+    std::vector<int64_t> idx;
+    for (int i = b[0]; i < b[1]; ++i)
+        for (int j = b[2]; j < b[3]; ++j)
+            for (int k = b[4]; k < b[5]; ++k)
+                idx.push_back(s.is_graph ? graph_node(s, component, i, j) : ((int64_t)i * s.ny + j) * s.nz + k);
+    d.npts = (int64_t)idx.size();
+    d.idx = dev_upload(s.al, idx.data(), idx.size(), s.st);
+    d.acc = (double *)s.al.get((size_t)(2 * nf * d.npts) * 8);  // zero-filled
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps) {
+    GEM_TRY
+    if (!sim) fail(FDTD_EINVAL, "sim is NULL");
+    Sim &s = sim->s;
+    const Sim::Dft &d = s.dft;
+    if (d.comp < 0) fail(FDTD_ESTATE, "no frequency-domain monitor set");
+    if (nsteps) *nsteps = d.nacc;
+    if (!re && !im) return FDTD_OK;
+    if (!re || !im) fail(FDTD_EINVAL, "re and im must both be given");
+    std::vector<double> h((size_t)(2 * d.nf * d.npts));
+    hip_check(hipMemcpyAsync(h.data(), d.acc, h.size() * 8, hipMemcpyDeviceToHost, s.st), "dft copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    for (int q = 0; q < d.nf; ++q) {
+        std::memcpy(re + (size_t)q * d.npts, h.data() + (size_t)(2 * q) * d.npts, (size_t)d.npts * 8);
+        std::memcpy(im + (size_t)q * d.npts, h.data() + (size_t)(2 * q + 1) * d.npts, (size_t)d.npts * 8);
+    }
+    return FDTD_OK;
+    GEM_CATCH
+}
 
 int fdtd_get_field(fdtd_sim *sim, int component, void *dst, int dst_on_device) {
     GEM_TRY
@@ -1385,6 +1467,7 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     if (!sim) fail(FDTD_EINVAL, "sim is NULL");
     Sim &s = sim->s;
     if (s.is_graph) fail(FDTD_EINVAL, "autotune applies to the implicit-graph stepper");
+    if (s.dft.comp >= 0) fail(FDTD_ESTATE, "remove the frequency-domain monitor before autotuning");
     if (trial_steps < 2) trial_steps = 2;
     trial_steps = (trial_steps + 3) / 4 * 4;  // whole passes of the multi-step kernels
     const std::string key = tune_key(s);

@@ -169,6 +169,17 @@ struct Sim {
     void launch_step(int64_t step);
     void launch_pair(int64_t step, hipEvent_t *ev = nullptr);
     size_t pair_launches() const;
+
+    // frequency-domain monitor (comp < 0: none)
+    struct Dft {
+        int comp = -1, nf = 0;
+        int box[6] = {0, 0, 0, 0, 0, 0};
+        double f[kDftMaxFreq] = {};
+        int64_t npts = 0, nacc = 0;
+        int64_t *idx = nullptr;  // device: field-array index of each cell
+        double *acc = nullptr;   // device: [2 nf][npts]
+    } dft;
+    void dft_accumulate(int64_t step);
     void records_to_host(float *out, int64_t ld, int64_t m);
     void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);
     void advance(int64_t n);
@@ -182,6 +193,8 @@ void build_graph(Sim &s);
 void graph_step(Sim &s, int64_t step);
 void graph_refold(Sim &s);
 void graph_set_source_probes(Sim &s);
+// node of component comp at cell (i, j) in the graph's node vector
+int64_t graph_node(const Sim &s, int comp, int i, int j);
 void graph_get_field(Sim &s, int comp, float *host);
 void graph_set_field(Sim &s, int comp, const float *host);
 

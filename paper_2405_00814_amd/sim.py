@@ -167,6 +167,28 @@ class Sim:
             nt = self._table.size
         L.call("fdtd_set_source_box", self.h, _comp(comp), a, b, int(kind), par, tp, nt)
 
+    def set_dft(self, comp, lo, hi, freqs):
+        """Frequency-domain monitor of `comp` on the box [lo, hi) at freqs
+        (Hz); an empty freqs removes it."""
+        a = (C.c_int32 * 3)(*[int(v) for v in lo] + [0] * (3 - len(lo)))
+        b = (C.c_int32 * 3)(*[int(v) for v in hi] + [1] * (3 - len(hi)))
+        fr = (C.c_double * max(1, len(freqs)))(*[float(v) for v in freqs])
+        L.call("fdtd_set_dft", self.h, _comp(comp), a, b, len(freqs), fr)
+        self._dft = (tuple(int(h) - int(l) for l, h in zip(lo, hi)), len(freqs))
+
+    def get_dft(self):
+        """(X, nsteps): X complex128 [nf, *box shape]."""
+        shape, nf = getattr(self, "_dft", ((0,), 0))
+        if nf == 0:  # no monitor: the library reports it
+            L.call("fdtd_get_dft", self.h, None, None, None)
+        n = int(np.prod(shape))
+        re = np.zeros(nf * n, np.float64)
+        im = np.zeros(nf * n, np.float64)
+        ns = C.c_int64()
+        L.call("fdtd_get_dft", self.h, re.ctypes.data_as(C.POINTER(C.c_double)),
+               im.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ns))
+        return (re + 1j * im).reshape((nf,) + shape), ns.value
+
     def clear_source(self):
         L.call("fdtd_set_source", self.h, L.FDTD_EZ, None, -1, None, None, 0)
 

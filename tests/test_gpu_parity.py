@@ -374,3 +374,78 @@ def test_line_and_box_sources():
             e = assert_parity_energy(got, ref, pb3, TOL, "3d box %s %s %s" % (comp, lo, kernel))
             log("box", comp, kernel, "energy %.1e" % e, {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
             assert rel_l2(rec, rrec) <= TOL
+
+
+def test_dft_monitor():
+    """Frequency-domain monitor (running DFT) of an E and an H component in
+    2D (the multi-step default, which drops to single steps, and the graph
+    form) and 3D, against the oracle's FP64 sums."""
+    from paper_2405_00814_amd.sim import Sim
+    from oracle import oracle as O
+    pb = W.dielectric2d(120, ny=104, steps=360, seed=6, nrect=6, side=(8, 30), npml=10, nprobes=4)
+    freqs = [0.5e9, 1.0e9, 1.7e9]
+    for comp, lo, hi in (("ez", (20, 15), (90, 70)), ("hy", (0, 0), (120, 104))):
+        o = O.for_problem(pb)
+        o.set_dft(comp, lo, hi, freqs)
+        o.run(pb.steps)
+        ref = o.dft["X"]
+        for kernel, graph in (((3, (1, 4, 4)), False), (None, True), ((2, (1, 4)), False)):
+            s = Sim.from_problem(pb, graph=graph)
+            if kernel is not None:
+                s.set_kernel(*kernel)
+            s.set_dft(comp, lo, hi, freqs)
+            s.step(100)
+            s.step(pb.steps - 100)
+            X, n = s.get_dft()
+            assert n == pb.steps
+            e = float(np.linalg.norm(X - ref) / np.linalg.norm(ref))
+            log("dft 2d", comp, kernel, graph, "%.2e" % e)
+            assert e <= TOL, (comp, kernel, graph, e)
+            s.close()
+    pb3 = W.yee3d(shape=(36, 34, 48), steps=160, seed=4, nbox=8, side=(3, 10), npml=6, nprobes=4,
+                  tau_steps=8.0)
+    pb3.source.kind, pb3.source.params = W.SRC_RICKER, (1.0, 40 * pb3.dt, 1.0 / (20 * pb3.dt))
+    f3 = [1.0 / (20 * pb3.dt), 1.0 / (40 * pb3.dt)]
+    for comp, lo, hi in (("ey", (4, 5, 6), (30, 29, 40)), ("hz", (10, 10, 0), (26, 24, 48))):
+        o = O.for_problem(pb3)
+        o.set_dft(comp, lo, hi, f3)
+        o.run(pb3.steps)
+        s = Sim.from_problem(pb3)
+        s.set_kernel(3, (4,))
+        s.set_dft(comp, lo, hi, f3)
+        s.step(pb3.steps)
+        X, n = s.get_dft()
+        e = float(np.linalg.norm(X - o.dft["X"]) / np.linalg.norm(o.dft["X"]))
+        log("dft 3d", comp, "%.2e" % e)
+        assert n == pb3.steps and e <= TOL
+        s.close()
+
+
+def test_dft_monitor_rules():
+    from paper_2405_00814_amd._lib import FdtdError
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.dielectric2d(64, ny=48, steps=20, seed=1, nrect=2, side=(4, 10), npml=6, nprobes=1)
+    s = Sim.from_problem(pb)
+    with pytest.raises(FdtdError):
+        s.get_dft()                                    # none set
+    for lo, hi, fr in (((0, 0), (65, 10), [1e9]), ((5, 5), (5, 9), [1e9]), ((0, 0), (4, 4), [-1.0]),
+                       ((0, 0), (4, 4), [1e9] * 17)):
+        with pytest.raises(FdtdError):
+            s.set_dft("ez", lo, hi, fr)
+    s.set_field("ez", np.random.default_rng(0).standard_normal(pb.shape).astype(np.float32))
+    s.set_dft("ez", (2, 2), (30, 20), [1e9, 2e9])
+    s.step(10)
+    X, n = s.get_dft()
+    assert n == 10 and X.shape == (2, 28, 18) and np.abs(X).max() > 0
+    with pytest.raises(FdtdError):
+        s.step_profile(4)
+    with pytest.raises(FdtdError):
+        s.autotune(4)
+    s.reset()
+    X, n = s.get_dft()
+    assert n == 0 and np.abs(X).max() == 0
+    s.set_dft("ez", (2, 2), (30, 20), [])              # removed
+    with pytest.raises(FdtdError):
+        s.get_dft()
+    s.step_profile(4)
+    s.close()

@@ -117,6 +117,41 @@ def test_cavity_recurrence_2d(orc, mn):
         assert bad > 1e-9
 
 
+def test_dft_monitor_closed_form_cavity_mode(orc):
+    """Frequency-domain monitor against a closed form: started from a
+    discrete TM_mn eigenmode with H = 0, a lossless PEC cavity gives
+    Ez^k = mode * s_k with s_k = cos(k w dt) + (cos(w dt) - 1)/sin(w dt)
+    sin(k w dt) (the recurrence s_{k+1} = 2 cos(w dt) s_k - s_{k-1} from
+    s_0 = 1, s_1 = 2 cos(w dt) - 1), so the monitor's sum is
+    mode * dt * sum_k s_k exp(-2 pi i f k dt) (E sampled at t = k dt)."""
+    nx, ny, h = 40, 30, 1e-3
+    dt = 0.9 / math.sqrt(2) * h / C0
+    m, n = 2, 1
+    o = orc.Oracle2D((nx, ny), (h, h), dt)
+    i = np.arange(nx)[:, None]
+    j = np.arange(ny)[None, :]
+    mode = np.sin(m * math.pi * i / nx) * np.sin(n * math.pi * j / ny)
+    o.ez[...] = mode
+    wdt = _omega_dt((C0 * dt) ** 2, [(nx, h), (ny, h)], (m, n))
+    N = 400
+    freqs = [wdt / (2 * math.pi * dt), 0.7 * wdt / (2 * math.pi * dt), 1.3e9, 0.0]
+    lo, hi = (5, 3), (31, 22)
+    o.set_dft("ez", lo, hi, freqs)
+    o.run(N)
+    k = np.arange(1, N + 1)
+    c, s_ = math.cos(wdt), math.sin(wdt)
+    sk = np.cos(k * wdt) + (c - 1) / s_ * np.sin(k * wdt)
+    box = mode[lo[0]:hi[0], lo[1]:hi[1]]
+    assert o.dft["n"] == N
+    for q, f in enumerate(freqs):
+        expect = np.sum(sk * np.exp(-2j * np.pi * f * k * dt)) * dt * box
+        got = o.dft["X"][q]
+        assert np.abs(got - expect).max() <= 1e-10 * np.abs(expect).max(), f
+    # the resonance: the bin at the mode's frequency dominates the others
+    mags = [np.abs(o.dft["X"][q]).max() for q in range(len(freqs))]
+    assert mags[0] > 5 * max(mags[1:])
+
+
 def test_cavity_recurrence_lossy_2d(orc):
     """Homogeneous lossy medium: a mode obeys
     e^{n+1} = (1 + Ca - Cb Db L) e^n - Ca e^{n-1}, with Ca = A-/A+ and
