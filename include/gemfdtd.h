@@ -95,6 +95,16 @@ typedef struct {
 typedef struct {
     int32_t npml[6];
     double m, sigma_max, kappa_max, alpha_max, m_alpha;
+    /* 0: the CPML above.  1 (ndim 2 only): the paper's split-field PML
+     * (Sec. III-C, Eq. 10-13 in TMz form): in the layer cells Ez = Ezx +
+     * Ezy with eps dEzx/dt + sigma_x Ezx = dHy/dx, eps dEzy/dt + sigma_y Ezy
+     * = -dHx/dy, and mu dHx/dt + sm_y Hx = -dEz/dy, mu dHy/dt + sm_x Hy =
+     * dEz/dx, with the magnetic conductivity sm matched (sm / mu0 = sigma /
+     * eps0), sigma graded as above (kappa_max and alpha_max unused),
+     * discretised with the semi-implicit averaging of Eq. 7-9.  The layer
+     * cells must be vacuum (eps_r = mu_r = 1, sigma = 0).  Kernel variant 1
+     * and the explicit graph (4 nodes per cell) only. */
+    int32_t split;
 } fdtd_cpml;
 
 /* Problem description (the paper's problem statement, Sec. III: grid and

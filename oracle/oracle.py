@@ -415,4 +415,7 @@ def _dft_sample(o, nsteps):
 
 
 def for_problem(pb):
+    if pb.ndim == 2 and (pb.cpml or {}).get("split", 0):
+        from .split import Oracle2DSplit
+        return Oracle2DSplit.from_problem(pb)
     return (Oracle2D if pb.ndim == 2 else Oracle3D).from_problem(pb)

@@ -30,7 +30,8 @@ class fdtd_allocator(C.Structure):
 
 class fdtd_cpml(C.Structure):
     _fields_ = [("npml", C.c_int32 * 6), ("m", C.c_double), ("sigma_max", C.c_double),
-                ("kappa_max", C.c_double), ("alpha_max", C.c_double), ("m_alpha", C.c_double)]
+                ("kappa_max", C.c_double), ("alpha_max", C.c_double), ("m_alpha", C.c_double),
+                ("split", C.c_int32)]
 
 
 class fdtd_desc(C.Structure):

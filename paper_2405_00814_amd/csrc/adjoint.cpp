@@ -61,6 +61,7 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         sp = &s;
         if (s.ndim != 2 || s.is_graph) fail(FDTD_EINVAL, "the adjoint supports the 2D implicit stepper");
         if (s.dft.comp >= 0) fail(FDTD_ESTATE, "remove the frequency-domain monitor before the adjoint");
+        if (s.split) fail(FDTD_EINVAL, "the adjoint supports the CPML only");
         if (T < 1 || n0 < 0 || n1 < n0 || n1 > T) fail(FDTD_EINVAL, "need T >= 1 and 0 <= n0 <= n1 <= T");
         const int i0 = design[0], i1 = design[1], j0 = design[2], j1 = design[3];
         if (i0 < 0 || i1 > s.nx || j0 < 0 || j1 > s.ny || i0 >= i1 || j0 >= j1)

@@ -327,6 +327,8 @@ int fdtd_batch_create(const fdtd_desc *descs, int32_t n, fdtd_batch **out) {
     fdtd_batch *b = nullptr;
     try {
         if (!descs || n < 1) fail(FDTD_EINVAL, "need at least one problem");
+        for (int32_t q = 0; q < n; ++q)
+            if (descs[q].cpml.split != 0) fail(FDTD_EINVAL, "the batch takes the CPML only");
         b = new fdtd_batch();
         b->st = (hipStream_t)descs[0].stream;
         b->al.st = b->st;

@@ -51,6 +51,12 @@ struct Prob2D {
     AxisDev x, y;
     State2D s0;        // state read (n)
     State2D s1;        // state written (n+1); equal to s0 for in-place kernels
+    // Split-field (Berenger) PML instead of the CPML (reference kernels
+    // only): Ezy of every cell (Ez holds Ezx + Ezy), nullptr for the CPML.
+    // The axis tables then hold k = 1/d, b = (1 - s)/(1 + s) and
+    // c = 1/(1 + s), s = sigma dt / (2 eps0) at the E (i) and H (i + 1/2)
+    // positions.
+    float *ezy;
     int64_t src_idx;   // -1 => none; else the source box's first cell
     int src_box[6];    // source cells [b0, b1) x [b2, b3) (x [b4, b5) = [0, 1))
     const float *src_vals;  // device table, indexed by absolute step
@@ -257,7 +263,7 @@ hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,
 // Soft source and probes on a node vector.
 hipError_t launch_node_source_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                     int64_t src_len, int64_t step, int np,
-                                    const int *probe_node, float *rec, int64_t rec_stride,
+                                    const int *probe_node, const int *probe_node2, float *rec, int64_t rec_stride,
                                     int64_t rec_index, hipStream_t st);
 
 // Batched 2D: one launch advances every problem by one step.

@@ -60,21 +60,21 @@ hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w, c
 // Soft source on its nodes, then probe samples (one block).
 __global__ void k_node_src_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                  int64_t src_len, int64_t step, int np, const int *probe_node,
-                                 float *rec, int64_t rec_stride, int64_t rec_index) {
+                                 const int *probe_node2, float *rec, int64_t rec_stride, int64_t rec_index) {
     if (step < src_len)
         for (int q = threadIdx.x; q < nsrc; q += blockDim.x) x[src_nodes[q]] += src_vals[step];
     __syncthreads();
     for (int q = threadIdx.x; q < np; q += blockDim.x)
-        rec[(int64_t)q * rec_stride + rec_index] = x[probe_node[q]];
+        rec[(int64_t)q * rec_stride + rec_index] = x[probe_node[q]] + (probe_node2 ? x[probe_node2[q]] : 0.f);
 }
 
 hipError_t launch_node_source_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                     int64_t src_len, int64_t step, int np,
-                                    const int *probe_node, float *rec, int64_t rec_stride,
+                                    const int *probe_node, const int *probe_node2, float *rec, int64_t rec_stride,
                                     int64_t rec_index, hipStream_t st) {
     if (nsrc <= 0 && np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_node_src_probe, dim3(1), dim3(256), 0, st, x, src_nodes, nsrc, src_vals, src_len,
-                       step, np, probe_node, rec, rec_stride, rec_index);
+                       step, np, probe_node, probe_node2, rec, rec_stride, rec_index);
     return hipGetLastError();
 }
 

@@ -55,7 +55,114 @@ static void free_layer(Sim &s, Sim::Graph::Layer &L) {
     L = Sim::Graph::Layer{};
 }
 
+// The graph of the split-field PML (Sec. IV, the 4 Nx Nz-node form, in the
+// TMz relabelling): nodes Hx u = i + 4 j nx, Hy q = 3i + nx(4j + 1), Ezx
+// tx = q + 1, Ezy tz = q + 2 for every cell, so the layer cells need no
+// other layout.  H nodes gather both Ez parts of their two E neighbours,
+// Ezx gathers Hy(i, j), Hy(i-1, j) and Ezy gathers Hx(i, j), Hx(i, j-1)
+// (the k-offset of the printed neighbourhood of Eyz read as the j-offset,
+// as the update equations require).  Weights: the per-axis split tables
+// (self b, curl scale c, 1/d) times the cell's Ca (self) or Cb, Db (curl):
+// in the interior b = c = 1, in the vacuum layer Ca = 1.
+static void build_graph_split(Sim &s) {
+    const int nx = s.nx, ny = s.ny;
+    auto u = [&](int i, int j) -> int64_t { return (int64_t)i + 4LL * j * nx; };
+    auto q = [&](int i, int j) -> int64_t { return 3LL * i + (int64_t)nx * (4LL * j + 1); };
+    auto tx = [&](int i, int j) { return q(i, j) + 1; };
+    auto tz = [&](int i, int j) { return q(i, j) + 2; };
+    const int64_t nnodes = 4LL * nx * ny;
+    if (nnodes >= ((int64_t)1 << 31)) fail(FDTD_EINVAL, "graph too large for 32-bit node indices");
+    const AxisHost &X = s.axh[0], &Y = s.axh[1];
+    auto cell = [&](int i, int j) { return (int64_t)i * ny + j; };
+    auto eps = [&](int64_t c) { return kEps0 * (s.eps_r.empty() ? 1.0 : s.eps_r[(size_t)c]); };
+    auto sh = [&](int64_t c) { return (s.sigma.empty() ? 0.0 : s.sigma[(size_t)c]) * s.dt / (2.0 * eps(c)); };
+    auto cb_of = [&](int64_t c) { return (s.dt / eps(c)) / (1.0 + sh(c)); };
+    auto ca_of = [&](int64_t c) { return (1.0 - sh(c)) / (1.0 + sh(c)); };
+    auto db_of = [&](int64_t c) { return s.dt / (kMu0 * (s.mu_r.empty() ? 1.0 : s.mu_r[(size_t)c])); };
+    RowBuilder hm, em;
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {  // Hx: -Db c_H,y (Ez(i, j+1) - Ez(i, j)) / dy
+            const double w = db_of(cell(i, j)) * (double)Y.cH[j] * (double)Y.kH[j];
+            hm.edge(u(i, j), Y.bH[j]);
+            hm.edge(tx(i, j), w);
+            hm.edge(tz(i, j), w);
+            if (j + 1 < ny) {
+                hm.edge(tx(i, j + 1), -w);
+                hm.edge(tz(i, j + 1), -w);
+            }
+            hm.end_row(u(i, j));
+        }
+        for (int i = 0; i < nx; ++i) {  // Hy: +Db c_H,x (Ez(i+1, j) - Ez(i, j)) / dx
+            const double w = db_of(cell(i, j)) * (double)X.cH[i] * (double)X.kH[i];
+            hm.edge(q(i, j), X.bH[i]);
+            hm.edge(tx(i, j), -w);
+            hm.edge(tz(i, j), -w);
+            if (i + 1 < nx) {
+                hm.edge(tx(i + 1, j), w);
+                hm.edge(tz(i + 1, j), w);
+            }
+            hm.end_row(q(i, j));
+        }
+    }
+    for (int j = 1; j < ny; ++j)
+        for (int i = 1; i < nx; ++i) {
+            const int64_t c = cell(i, j);
+            const double ca = ca_of(c), cb = cb_of(c);
+            const double wx = cb * (double)X.cE[i] * (double)X.kE[i], wy = cb * (double)Y.cE[j] * (double)Y.kE[j];
+            em.edge(tx(i, j), ca * (double)X.bE[i]);
+            em.edge(q(i, j), wx);
+            em.edge(q(i - 1, j), -wx);
+            em.end_row(tx(i, j));
+            em.edge(tz(i, j), ca * (double)Y.bE[j]);
+            em.edge(u(i, j), -wy);
+            em.edge(u(i, j - 1), wy);
+            em.end_row(tz(i, j));
+        }
+    Sim::Graph &g = s.g;
+    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) free_layer(s, *L);
+    g.bytes = 0;
+    auto put = [&](Sim::Graph::Layer &L, RowBuilder &b) {
+        L.nrows = (int)b.dst.size();
+        L.nnz = (int64_t)b.col.size();
+        L.rowptr = up(s.al, b.rowptr, s.st, g.bytes);
+        L.col = up(s.al, b.col, s.st, g.bytes);
+        L.dst = up(s.al, b.dst, s.st, g.bytes);
+        L.w = up(s.al, b.w, s.st, g.bytes);
+        hip_check(hipStreamSynchronize(s.st), "sync");
+        b = RowBuilder{};
+    };
+    put(g.h_main, hm);
+    put(g.e_main, em);
+    g.nmain = nnodes;
+    g.nnodes = nnodes;
+    if (!g.x) g.x = (float *)s.al.get((size_t)nnodes * 4);
+    g.ez_node.resize((size_t)nx * ny);
+    g.ez_node2.resize((size_t)nx * ny);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            g.ez_node[(size_t)cell(i, j)] = tx(i, j);
+            g.ez_node2[(size_t)cell(i, j)] = tz(i, j);
+        }
+    for (int set = 0; set < 2; ++set) {
+        for (int c = 0; c < 6; ++c) {
+            s.al.put(s.f[set][c]);
+            s.f[set][c] = nullptr;
+        }
+        for (int a = 0; a < NPSI3; ++a) {
+            s.al.put(s.psi[set][a]);
+            s.psi[set][a] = nullptr;
+        }
+    }
+    s.al.put(s.ezy);
+    s.ezy = nullptr;
+    hip_check(hipStreamSynchronize(s.st), "sync");
+}
+
 void build_graph(Sim &s) {
+    if (s.split) {
+        build_graph_split(s);
+        return;
+    }
     const int nx = s.nx, ny = s.ny;
     auto t = [&](int i, int j) -> int64_t { return 2LL * i + 1 + (int64_t)nx * (3LL * j + 1); };
     auto u = [&](int i, int j) -> int64_t { return (int64_t)i + 3LL * j * nx; };
@@ -222,12 +329,17 @@ void graph_set_source_probes(Sim &s) {
         hip_check(hipStreamSynchronize(s.st), "sync");
     }
     s.al.put(g.probe_node);
-    g.probe_node = nullptr;
+    s.al.put(g.probe_node2);
+    g.probe_node = g.probe_node2 = nullptr;
     if (!s.probe_cells.empty()) {
-        std::vector<int> pn(s.probe_cells.size());
+        std::vector<int> pn(s.probe_cells.size()), pn2(s.probe_cells.size());
         for (size_t p = 0; p < pn.size(); ++p) pn[p] = (int)g.ez_node[(size_t)s.probe_cells[p]];
         int64_t dummy = 0;
         g.probe_node = up(s.al, pn, s.st, dummy);
+        if (!g.ez_node2.empty()) {  // split field: Ez = Ezx + Ezy
+            for (size_t p = 0; p < pn.size(); ++p) pn2[p] = (int)g.ez_node2[(size_t)s.probe_cells[p]];
+            g.probe_node2 = up(s.al, pn2, s.st, dummy);
+        }
         hip_check(hipStreamSynchronize(s.st), "sync");
     }
 }
@@ -239,7 +351,7 @@ void graph_step(Sim &s, int64_t step) {
         s.last_launches += 1;
     }
     hip_check(launch_node_source_probe(g.x, g.src_nodes, g.nsrc, s.src_dev, s.src_len, step,
-                                       (int)s.probe_cells.size(), g.probe_node, s.rec_dev, s.rec_cap,
+                                       (int)s.probe_cells.size(), g.probe_node, g.probe_node2, s.rec_dev, s.rec_cap,
                                        step - (s.n_done - s.n_rec), s.st),
               "source/probe");
     if (g.nsrc > 0 || !s.probe_cells.empty()) s.last_launches += 1;
@@ -247,6 +359,10 @@ void graph_step(Sim &s, int64_t step) {
 
 static int64_t node_of(const Sim &s, int comp, int i, int j) {
     const int nx = s.nx;
+    if (s.split) {  // Ez: its Ezx node (Ezy is the node after it)
+        if (comp == FDTD_HX) return (int64_t)i + 4LL * j * nx;
+        return 3LL * i + (int64_t)nx * (4LL * j + 1) + (comp == FDTD_EZ ? 1 : 0);
+    }
     if (comp == FDTD_EZ) return 2LL * i + 1 + (int64_t)nx * (3LL * j + 1);
     if (comp == FDTD_HX) return (int64_t)i + 3LL * j * nx;
     return 2LL * i + (int64_t)nx * (3LL * j + 1);
@@ -258,16 +374,25 @@ void graph_get_field(Sim &s, int comp, float *host) {
     std::vector<float> x((size_t)s.g.nnodes);
     hip_check(hipMemcpyAsync(x.data(), s.g.x, x.size() * 4, hipMemcpyDeviceToHost, s.st), "copy");
     hip_check(hipStreamSynchronize(s.st), "sync");
+    const bool two = s.split && comp == FDTD_EZ;  // Ez = Ezx + Ezy
     for (int i = 0; i < s.nx; ++i)
-        for (int j = 0; j < s.ny; ++j) host[(size_t)i * s.ny + j] = x[(size_t)node_of(s, comp, i, j)];
+        for (int j = 0; j < s.ny; ++j) {
+            const size_t n0 = (size_t)node_of(s, comp, i, j);
+            host[(size_t)i * s.ny + j] = two ? x[n0] + x[n0 + 1] : x[n0];
+        }
 }
 
 void graph_set_field(Sim &s, int comp, const float *host) {
     std::vector<float> x((size_t)s.g.nnodes);
     hip_check(hipMemcpyAsync(x.data(), s.g.x, x.size() * 4, hipMemcpyDeviceToHost, s.st), "copy");
     hip_check(hipStreamSynchronize(s.st), "sync");
+    const bool two = s.split && comp == FDTD_EZ;  // a set Ez is all Ezx
     for (int i = 0; i < s.nx; ++i)
-        for (int j = 0; j < s.ny; ++j) x[(size_t)node_of(s, comp, i, j)] = host[(size_t)i * s.ny + j];
+        for (int j = 0; j < s.ny; ++j) {
+            const size_t n0 = (size_t)node_of(s, comp, i, j);
+            x[n0] = host[(size_t)i * s.ny + j];
+            if (two) x[n0 + 1] = 0.f;
+        }
     hip_check(hipMemcpyAsync(s.g.x, x.data(), x.size() * 4, hipMemcpyHostToDevice, s.st), "copy");
     hip_check(hipStreamSynchronize(s.st), "sync");
 }

@@ -26,6 +26,11 @@ __global__ __launch_bounds__(256) void k2d_ref_h(Prob2D p) {
     const float ey1 = (j + 1 < ny) ? p.s0.ez[c + 1] : 0.f;
     const float ex1 = (i + 1 < p.nx) ? p.s0.ez[c + ny] : 0.f;
     const float db = p.db ? p.db[c] : p.db0;
+    if (p.ezy) {  // split-field PML: sigma* along the difference's axis
+        p.s0.hx[c] = p.y.bH[j] * p.s0.hx[c] - db * p.y.cH[j] * p.y.kH[j] * (ey1 - e0);
+        p.s0.hy[c] = p.x.bH[i] * p.s0.hy[c] + db * p.x.cH[i] * p.x.kH[i] * (ex1 - e0);
+        return;
+    }
     const float dEy = ey1 - e0;
     float ty = dEy * p.y.kH[j];
     const int jj = slab_index(p.y, j);
@@ -59,6 +64,18 @@ __global__ __launch_bounds__(256) void k2d_ref_e(Prob2D p, int64_t step) {
     if (i >= 1 && j >= 1) {
         const float dHy = p.s0.hy[c] - p.s0.hy[c - ny];
         const float dHx = p.s0.hx[c] - p.s0.hx[c - 1];
+        if (p.ezy && (slab_index(p.x, i) >= 0 || slab_index(p.y, j) >= 0)) {
+            // split-field PML cell (vacuum): Ezx = Ez - Ezy and Ezy decay
+            // with sigma_x and sigma_y
+            const float zy = p.ezy[c];
+            const float nx_ = p.x.bE[i] * (e - zy) + p.cb[c] * p.x.cE[i] * p.x.kE[i] * dHy;
+            const float ny_ = p.y.bE[j] * zy - p.cb[c] * p.y.cE[j] * p.y.kE[j] * dHx;
+            p.ezy[c] = ny_;
+            e = nx_ + ny_;
+            if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0) && step < p.src_len) e += p.src_vals[step];
+            p.s0.ez[c] = e;
+            return;
+        }
         float tx = dHy * p.x.kE[i];
         float ty = dHx * p.y.kE[j];
         const int ii = slab_index(p.x, i);

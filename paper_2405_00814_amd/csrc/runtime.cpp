@@ -144,6 +144,37 @@ AxisHost build_axis(int n, int lo, int hi, double d, double dt, const fdtd_cpml 
     return A;
 }
 
+// Tables of the split-field PML (same grading and positions as the CPML):
+// k = 1/d, b = (1 - s)/(1 + s), c = 1/(1 + s), s = sigma dt / (2 eps0) (the
+// magnetic layer at the H positions matched, sigma*/mu0 = sigma/eps0).
+AxisHost build_axis_split(int n, int lo, int hi, double d, double dt, const fdtd_cpml &cp) {
+    AxisHost A;
+    A.n = n;
+    A.lo = lo;
+    A.hi = hi;
+    const double eta0 = std::sqrt(kMu0 / kEps0);
+    const double m = cp.m;
+    const double smax = cp.sigma_max > 0 ? cp.sigma_max : 0.8 * (m + 1.0) / (eta0 * d);
+    for (int half = 0; half < 2; ++half) {
+        std::vector<float> &K = half ? A.kH : A.kE;
+        std::vector<float> &B = half ? A.bH : A.bE;
+        std::vector<float> &Cc = half ? A.cH : A.cE;
+        K.assign(n, (float)(1.0 / d));
+        B.resize(n);
+        Cc.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const double x = i + (half ? 0.5 : 0.0);
+            double rho = 0.0;
+            if (lo > 0 && x < lo) rho = (lo - x) / lo;
+            if (hi > 0 && x > n - hi) rho = std::max(rho, (x - (n - hi)) / hi);
+            const double s = smax * std::pow(rho, m) * dt / (2.0 * kEps0);
+            B[i] = (float)((1.0 - s) / (1.0 + s));
+            Cc[i] = (float)(1.0 / (1.0 + s));
+        }
+    }
+    return A;
+}
+
 AxisDev upload_axis(DevAlloc &al, const AxisHost &h, hipStream_t st) {
     AxisDev a{};
     a.n = h.n;
@@ -206,6 +237,7 @@ Prob2D Sim::prob2d(int si, int so) const {
     p.x = ax[0];
     p.y = ax[1];
     p.s0 = State2D{f[si][FDTD_EZ], f[si][FDTD_HX], f[si][FDTD_HY], psi[si][0], psi[si][1], psi[si][2], psi[si][3]};
+    p.ezy = split ? ezy : nullptr;
     p.s1 = State2D{f[so][FDTD_EZ], f[so][FDTD_HX], f[so][FDTD_HY], psi[so][0], psi[so][1], psi[so][2], psi[so][3]};
     p.src_idx = src_idx;
     for (int q = 0; q < 6; ++q) p.src_box[q] = src_box[q];
@@ -580,6 +612,20 @@ void Sim::advance(int64_t n) {
     }
 }
 
+// The split-field PML's layer cells must be vacuum (their tables assume
+// eps0, mu0, no loss).
+void Sim::split_check() const {
+    const int xlo = ax[0].lo, xhi = ax[0].hi, ylo = ax[1].lo, yhi = ax[1].hi;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            if (!(i < xlo || i >= nx - xhi || j < ylo || j >= ny - yhi)) continue;
+            const size_t c = (size_t)i * ny + j;
+            if ((!eps_r.empty() && eps_r[c] != 1.f) || (!mu_r.empty() && mu_r[c] != 1.f) ||
+                (!sigma.empty() && sigma[c] != 0.f))
+                fail(FDTD_EINVAL, "the split-field PML needs vacuum in its layer cells");
+        }
+}
+
 void Sim::zero_state() {
     for (int s = 0; s < 3; ++s) {
         for (int c = 0; c < 6; ++c)
@@ -590,6 +636,7 @@ void Sim::zero_state() {
     if (is_graph && g.x) hip_check(hipMemsetAsync(g.x, 0, (size_t)g.nnodes * 4, st), "memset");
     if (dft.acc) hip_check(hipMemsetAsync(dft.acc, 0, (size_t)(2 * dft.nf * dft.npts) * 8, st), "memset");
     dft.nacc = 0;
+    if (ezy) hip_check(hipMemsetAsync(ezy, 0, (size_t)ncell * 4, st), "memset");
     cur = 0;
     n_done = 0;
     n_rec = 0;
@@ -644,6 +691,10 @@ Fused2DCfg default_single2d(int nx, int ny) {
 int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     k = fdtd_kernel_config{};
     k.tb = 1;
+    if (s.split) {  // the split-field PML runs in the reference kernels only
+        k.variant = 1;
+        return 0;
+    }
     if (s.ndim == 2) {
         const bool wide = s.ncell >= kWide2DCells && s.ny % 2 == 0;
         const int vt = wide ? 2 : 1, tx = wide ? 8 : kTB2DefaultTX;
@@ -680,6 +731,7 @@ int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
 static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.tb != 0 && k.tb != 1) return false;
     if (k.variant == 1) return true;
+    if (s.split) return false;
     if (k.variant != 2 && k.variant != 3) return false;
     if (s.ndim == 2) {
         if (k.variant == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
@@ -737,6 +789,8 @@ void validate_desc(const fdtd_desc *d) {
         !(c.alpha_max >= 0) || !std::isfinite(c.alpha_max) || !(c.m_alpha >= 0) ||
         !std::isfinite(c.m_alpha) || !std::isfinite(c.sigma_max))
         fail(FDTD_EINVAL, "invalid CPML parameters");
+    if (c.split != 0 && c.split != 1) fail(FDTD_EINVAL, "cpml.split must be 0 or 1");
+    if (c.split == 1 && d->ndim != 2) fail(FDTD_EINVAL, "the split-field PML is 2D only");
     check_map(d->eps_r, ncell, 1.0, "eps_r");
     check_map(d->mu_r, ncell, 1.0, "mu_r");
     check_map(d->sigma, ncell, 0.0, "sigma");
@@ -754,6 +808,7 @@ void init_sim(Sim &s, const fdtd_desc *d) {
     s.dz = d->ndim == 3 ? d->dz : 1.0;
     s.dt = d->dt;
     s.cpml = d->cpml;
+    s.split = d->cpml.split == 1;
     s.st = (hipStream_t)d->stream;
     hip_check(hipGetDevice(&s.device), "hipGetDevice");
     hip_check(hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, s.device), "device attribute");
@@ -781,7 +836,8 @@ void init_sim(Sim &s, const fdtd_desc *d) {
         if (a == 2 && s.ndim == 2) {
             s.axh[a] = build_axis(1, 0, 0, 1.0, s.dt, s.cpml);
         } else {
-            s.axh[a] = build_axis(nn[a], s.cpml.npml[2 * a], s.cpml.npml[2 * a + 1], dd[a], s.dt, s.cpml);
+            s.axh[a] = s.split ? build_axis_split(nn[a], s.cpml.npml[2 * a], s.cpml.npml[2 * a + 1], dd[a], s.dt, s.cpml)
+                               : build_axis(nn[a], s.cpml.npml[2 * a], s.cpml.npml[2 * a + 1], dd[a], s.dt, s.cpml);
         }
         s.ax[a] = upload_axis(s.al, s.axh[a], s.st);
     }
@@ -798,6 +854,10 @@ void init_sim(Sim &s, const fdtd_desc *d) {
         for (int a = 0; a < NPSI3; ++a) s.psi_len[a] = len[a];
     }
     for (int set = 0; set < 2; ++set) s.alloc_set(set);
+    if (s.split) {
+        s.split_check();
+        s.ezy = (float *)s.al.get(n * 4);
+    }
     hip_check(hipEventCreate(&s.ev0), "event");
     hip_check(hipEventCreate(&s.ev1), "event");
     default_variant_tiles(s, s.kcfg);
@@ -1244,6 +1304,8 @@ int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t 
     if (nf > 0) {
         if (!lo || !hi || !freqs) fail(FDTD_EINVAL, "NULL argument");
         if (!comp_ok(s, component)) fail(FDTD_EINVAL, "component not present in this grid");
+        if (s.is_graph && s.split && component == FDTD_EZ)
+            fail(FDTD_EINVAL, "the split-field graph holds Ez in two nodes: monitor Hx or Hy");
         const int n3[3] = {s.nx, s.ny, s.ndim == 3 ? s.nz : 1};
         for (int a = 0; a < s.ndim; ++a)
             if (lo[a] < 0 || hi[a] > n3[a] || lo[a] >= hi[a]) fail(FDTD_EINVAL, "monitor box empty or outside the grid");
@@ -1339,6 +1401,8 @@ int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_dev
     hip_check(hipMemcpyAsync(s.f[s.cur][component], src, bytes,
                              src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s.st),
               "copy");
+    // split-field PML: a set Ez is all Ezx
+    if (s.split && component == FDTD_EZ) hip_check(hipMemsetAsync(s.ezy, 0, bytes, s.st), "memset");
     hip_check(hipStreamSynchronize(s.st), "sync");
     return FDTD_OK;
     GEM_CATCH
@@ -1404,6 +1468,15 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi, const
     const int64_t bn = (int64_t)(h[0] - l[0]) * (h[1] - l[1]) * (h[2] - l[2]);
     check_map(eps_r, bn, 1.0, "eps_r");
     if (sigma) check_map(sigma, bn, 0.0, "sigma");
+    if (s.split) {  // the split-field PML's layer stays vacuum
+        int64_t q2 = 0;
+        for (int i = l[0]; i < h[0]; ++i)
+            for (int j = l[1]; j < h[1]; ++j, ++q2) {
+                const bool layer = i < s.ax[0].lo || i >= s.nx - s.ax[0].hi || j < s.ax[1].lo || j >= s.ny - s.ax[1].hi;
+                if (layer && (eps_r[q2] != 1.f || (sigma && sigma[q2] != 0.f)))
+                    fail(FDTD_EINVAL, "the split-field PML needs vacuum in its layer cells");
+            }
+    }
     hip_check(hipStreamSynchronize(s.st), "sync");
     if (s.eps_r.empty()) s.eps_r.assign((size_t)s.ncell, 1.0f);
     if (sigma && s.sigma.empty()) s.sigma.assign((size_t)s.ncell, 0.0f);

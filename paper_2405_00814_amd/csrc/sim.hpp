@@ -56,6 +56,8 @@ struct Sim {
     hipStream_t st = nullptr;
     int device = 0;
     int cus = 256;  // compute units of the device
+    bool split = false;      // split-field PML (2D) instead of the CPML
+    float *ezy = nullptr;    // its Ezy of every cell (device)
     DevAlloc al;
 
     // host copies of the maps (for refolding)
@@ -146,10 +148,12 @@ struct Sim {
             float *w = nullptr;
             int64_t nnz = 0;
         } h_aux, h_main, e_aux, e_main;
-        std::vector<int64_t> ez_node;     // node of Ez(i,j) (host)
+        std::vector<int64_t> ez_node;     // node of Ez(i,j) (host; split field: of Ezx)
+        std::vector<int64_t> ez_node2;    // split field: node of Ezy(i,j), else empty
         int *src_nodes = nullptr;  // device: the source box's Ez nodes
         int nsrc = 0;
         int *probe_node = nullptr;
+        int *probe_node2 = nullptr;  // split field: the Ezy node of each probe
         int64_t bytes = 0;
     } g;
 
@@ -181,6 +185,7 @@ struct Sim {
     } dft;
     void dft_accumulate(int64_t step);
     void records_to_host(float *out, int64_t ld, int64_t m);
+    void split_check() const;
     void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);
     void advance(int64_t n);
     void alloc_set(int set);

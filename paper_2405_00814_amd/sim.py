@@ -92,11 +92,12 @@ def make_desc(shape, dx, dt, eps_r=None, mu_r=None, sigma=None, npml=None, cpml=
     d.mu_r = keep[1].ctypes.data_as(fp) if keep[1] is not None else fp()
     d.sigma = keep[2].ctypes.data_as(fp) if keep[2] is not None else fp()
     np6 = list(npml or ()) + [0] * 6
-    cp = dict(m=3.0, sigma_max=0.0, kappa_max=1.0, alpha_max=0.0, m_alpha=1.0)
+    cp = dict(m=3.0, sigma_max=0.0, kappa_max=1.0, alpha_max=0.0, m_alpha=1.0, split=0)
     cp.update(cpml or {})
     d.cpml.npml = (C.c_int32 * 6)(*[int(v) for v in np6[:6]])
     d.cpml.m, d.cpml.sigma_max = cp["m"], cp["sigma_max"]
     d.cpml.kappa_max, d.cpml.alpha_max, d.cpml.m_alpha = cp["kappa_max"], cp["alpha_max"], cp["m_alpha"]
+    d.cpml.split = int(cp["split"])
     d.stream = current_stream() if stream is None else stream
     if allocator:
         d.allocator = C.pointer(torch_allocator())
