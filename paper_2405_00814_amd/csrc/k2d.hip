@@ -178,6 +178,10 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
     const int syw = p.y.lo + p.y.hi;
     const bool lossy = p.ca != nullptr;
     const bool mumap = p.db != nullptr;
+    // the source box, read once (the batched tiles read p from memory): an
+    // empty box without a source
+    const bool hs = p.src_idx >= 0;
+    const int si0 = hs ? p.src_box[0] : 0, si1 = hs ? p.src_box[1] : 0, sj0 = p.src_box[2], sj1 = p.src_box[3];
 
     float kHy[V], kEy[V], bHy[V], cHy[V], bEy[V], cEy[V];
     int jj[V];
@@ -355,7 +359,8 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
                     cap_br[q] = br;
                 }
             }
-            if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0)) ez_w[v] += sval;
+            if ((unsigned)(i - si0) < (unsigned)(si1 - si0) && (unsigned)(j - sj0) < (unsigned)(sj1 - sj0))
+                ez_w[v] += sval;
         }
         if (valid) {
             stv<V>(p.s1.hx + row + jb, hx_n);

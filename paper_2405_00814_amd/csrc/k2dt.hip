@@ -75,6 +75,10 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
     float sval[TB];
 #pragma unroll
     for (int k = 0; k < TB; ++k) sval[k] = (p.src_idx >= 0 && step + k < p.src_len) ? p.src_vals[step + k] : 0.f;
+    // the source box, read once (the batched instances read p from memory):
+    // an empty box without a source
+    const bool hs = p.src_idx >= 0;
+    const int si0 = hs ? p.src_box[0] : 0, si1 = hs ? p.src_box[1] : 0, sj0 = p.src_box[2], sj1 = p.src_box[3];
 
     auto zero = [](float (&a)[V]) {
 #pragma unroll
@@ -236,7 +240,8 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                         cap.br[q] = tx - ty;
                     }
                 }
-                if (p.src_idx >= 0 && in_src(p.src_box, i, j, 0)) out.e[v] += sval[k];
+                if ((unsigned)(i - si0) < (unsigned)(si1 - si0) && (unsigned)(j - sj0) < (unsigned)(sj1 - sj0))
+                    out.e[v] += sval[k];
             }
             // outside the grid: the ghost values are zero
             if (!rv || !valid) {
