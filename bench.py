@@ -175,6 +175,20 @@ def bench_2d(args, steps=10000):
                               single_step_gcells_per_s=pb.cells * ms / tp / 1e9,
                               with_monitor_gcells_per_s=pb.cells * ms / tm / 1e9,
                               monitor_us_per_step=(tm - tp) / ms * 1e6)
+    # the paper's split-field PML (two-pass reference kernels), against the
+    # CPML through the same kernels, and its 4-node explicit graph
+    import dataclasses
+    ps = dataclasses.replace(pb, cpml=dict(pb.cpml, split=1))
+    rates = {}
+    for name, prob, graph in (("cpml_reference", pb, False), ("split_reference", ps, False),
+                              ("split_graph", ps, True)):
+        r = Sim.from_problem(prob, graph=graph)
+        if not graph:
+            r.set_kernel(1)
+        tr, _, _ = timed_steps(r, 200, 5)
+        rates[name + "_gcells_per_s"] = pb.cells * 200 / tr / 1e9
+        r.close()
+    out["split_pml"] = rates
     return out
 
 
