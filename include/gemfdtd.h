@@ -349,6 +349,15 @@ int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
                      const int32_t *design, int32_t ckpt_interval, double *loss_out,
                      float *grad_dev);
 
+/* The same adjoint run with the gradients with respect to eps_r and to the
+ * conductivity sigma on the design box (the learnable-components direction
+ * the paper points to, Sec. I: every per-cell edge weight of the E layer
+ * depends on both).  grad_eps_dev, grad_sigma_dev: device float32
+ * [(i1-i0)*(j1-j0)], either may be NULL (not both).  fdtd_adjoint_eps is
+ * this call with grad_sigma_dev = NULL.  dL/d sigma is per S/m. */
+int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
+                 int32_t ckpt_interval, double *loss_out, float *grad_eps_dev, float *grad_sigma_dev);
+
 /* Thread-local text of the calling thread's last failure ("" if none). */
 const char *fdtd_last_error(void);
 

@@ -97,6 +97,7 @@ _SIGS = {
     "fdtd_batch_last_step_time": (C.c_int, [P, C.POINTER(C.c_float), i64p]),
     "fdtd_batch_cells": (C.c_int, [P, i64p]),
     "fdtd_adjoint_eps": (C.c_int, [P, i64, i64, i64, i32p, i32, f64p, f32p]),
+    "fdtd_adjoint": (C.c_int, [P, i64, i64, i64, i32p, i32, f64p, f32p, f32p]),
     "fdtd_last_error": (C.c_char_p, []),
     "fdtd_version": (C.c_char_p, []),
 }

@@ -1,14 +1,16 @@
-// Gradient of a probe-energy loss with respect to eps_r by the discrete
-// adjoint, with checkpointing.
+// Gradient of a probe-energy loss with respect to eps_r (and sigma) by the
+// discrete adjoint, with checkpointing.
 //
 // Forward: T steps from the zero state with a full-state checkpoint every L
 // steps.  Backward, newest segment first: restore the checkpoint, recompute
 // the segment with the same kernel (bitwise the same states) while keeping,
 // at every design cell and step, Ez before the E layer and the E-layer
 // bracket; then run the segment's adjoint steps backward.  The gradient of
-// E^{k+1} = Ca E^k + Cb * bracket with respect to eps_r at a design cell is
-// dCa * E^k + dCb * bracket, weighted by the adjoint of E^{k+1}; it is
-// accumulated in double.
+// E^{k+1} = Ca E^k + Cb * bracket with respect to a parameter of Ca and Cb
+// at a design cell is dCa * E^k + dCb * bracket, weighted by the adjoint of
+// E^{k+1}: the adjoint steps sum a * E^k and a * bracket per cell in
+// double, and the gradients with respect to eps_r and sigma combine these
+// sums with the coefficients' derivatives at the end.
 #include <algorithm>
 #include <cmath>
 
@@ -51,12 +53,21 @@ using namespace gem;
 extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
                                 const int32_t *design, int32_t ckpt_interval, double *loss_out,
                                 float *grad_dev) {
+    if (!grad_dev) {
+        set_error("NULL argument");
+        return FDTD_EINVAL;
+    }
+    return fdtd_adjoint(sim, T, n0, n1, design, ckpt_interval, loss_out, grad_dev, nullptr);
+}
+
+extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
+                            int32_t ckpt_interval, double *loss_out, float *grad_eps_dev, float *grad_sigma_dev) {
     std::vector<void *> tmp;
     Sim *sp = nullptr;
     fdtd_kernel_config saved{};
     bool restore_cfg = false;
     try {
-        if (!sim || !design || !grad_dev) fail(FDTD_EINVAL, "NULL argument");
+        if (!sim || !design || (!grad_eps_dev && !grad_sigma_dev)) fail(FDTD_EINVAL, "NULL argument");
         Sim &s = sim->s;
         sp = &s;
         if (s.ndim != 2 || s.is_graph) fail(FDTD_EINVAL, "the adjoint supports the 2D implicit stepper");
@@ -139,11 +150,15 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
             x.psi_ezy = (float *)get((size_t)std::max<int64_t>(1, s.psi_len[3]) * 4);
         }
         int acur = 0;
-        double *grad = (double *)get((size_t)nd * 8);
+        double *sez = (double *)get((size_t)nd * 8);  // zero-filled
+        double *sbr = (double *)get((size_t)nd * 8);
         float *cap_ez = (float *)get((size_t)(L * nd) * 4);
         float *cap_br = (float *)get((size_t)(L * nd) * 4);
-        // coefficient derivatives at the design cells (double, rounded once)
-        std::vector<float> hdca((size_t)nd), hdcb((size_t)nd);
+        // derivatives of Ca = (e - h)/(e + h) and Cb = dt/(e + h), e = eps0
+        // eps_r, h = sigma dt / 2, at the design cells (FP64):
+        //   d/d eps_r: dCa = 2 eps0 h / (e + h)^2,  dCb = -eps0 dt / (e + h)^2
+        //   d/d sigma: dCa = -dt e / (e + h)^2,     dCb = -dt^2 / (2 (e + h)^2)
+        std::vector<double> hd((size_t)(4 * nd));
         for (int i = i0; i < i1; ++i)
             for (int j = j0; j < j1; ++j) {
                 const int64_t c = (int64_t)i * s.ny + j;
@@ -152,13 +167,13 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
                 const double sg = s.sigma.empty() ? 0.0 : s.sigma[(size_t)c];
                 const double e = kEps0 * er, h = 0.5 * sg * s.dt;
                 const double den = (e + h) * (e + h);
-                hdca[(size_t)q] = (float)(kEps0 * 2.0 * h / den);
-                hdcb[(size_t)q] = (float)(-kEps0 * s.dt / den);
+                hd[(size_t)q] = kEps0 * 2.0 * h / den;
+                hd[(size_t)(nd + q)] = -kEps0 * s.dt / den;
+                hd[(size_t)(2 * nd + q)] = -s.dt * e / den;
+                hd[(size_t)(3 * nd + q)] = -0.5 * s.dt * s.dt / den;
             }
-        float *dca = (float *)get((size_t)nd * 4);
-        float *dcb = (float *)get((size_t)nd * 4);
-        hip_check(hipMemcpyAsync(dca, hdca.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
-        hip_check(hipMemcpyAsync(dcb, hdcb.data(), (size_t)nd * 4, hipMemcpyHostToDevice, s.st), "upload");
+        double *dcoef = (double *)get((size_t)(4 * nd) * 8);
+        hip_check(hipMemcpyAsync(dcoef, hd.data(), (size_t)(4 * nd) * 8, hipMemcpyHostToDevice, s.st), "upload");
         // probed cells (sorted) and their probe entries, for the loss seed
         std::vector<int> ust, pcell, pslot;
         {
@@ -245,13 +260,17 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
                               "adjoint seed");
                 const int seed_out = (k > n0 && k <= n1) ? 1 : 0;
                 hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cap_ez + (k - k0) * nd,
-                                             cap_br + (k - k0) * nd, dca, dcb, grad, seed_out, apt, s.rec_dev,
+                                             cap_br + (k - k0) * nd, sez, sbr, seed_out, apt, s.rec_dev,
                                              s.rec_cap, k - 1, ac.V, ac.TX, s.st),
                           "adjoint step");
                 acur = 1 - acur;
             }
         }
-        hip_check(launch_grad_to_float(grad, grad_dev, nd, s.st), "gradient");
+        if (grad_eps_dev)
+            hip_check(launch_grad_combine(sez, sbr, dcoef, dcoef + nd, grad_eps_dev, nd, s.st), "gradient");
+        if (grad_sigma_dev)
+            hip_check(launch_grad_combine(sez, sbr, dcoef + 2 * nd, dcoef + 3 * nd, grad_sigma_dev, nd, s.st),
+                      "gradient");
         // leave the forward state after T steps
         copy_state(s, 0, fin, false);
         s.cur = 0;

@@ -278,17 +278,21 @@ hipError_t launch_advance(int64_t *step_base, int64_t by, hipStream_t st);
 struct Adj2D {
     float *ez, *hx, *hy, *psi_hx, *psi_hy, *psi_ezx, *psi_ezy;
 };
-hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st);
+// out = dca sez + dcb sbr (the gradient with respect to the parameter whose
+// Ca and Cb derivatives are dca, dcb), rounded to float
+hipError_t launch_grad_combine(const double *sez, const double *sbr, const double *dca, const double *dcb, float *out,
+                               int64_t n, hipStream_t st);
 // One adjoint step in one pass: reads the adjoint state l0 (step k+1),
-// writes l1 (step k), accumulates the gradient at the design cells.  When
-// seed_out, the probe-loss seed of the next step is added to the written
-// Ez: l1.ez[probe] += 2 * rec[slot][seed_k] (pt: probes grouped by tile in
-// tile order, tile = (i / TX) * nsy + j / (62 V), entries of one cell
+// writes l1 (step k), accumulates at the design cells sez += a Ez^k and
+// sbr += a bracket (a: the adjoint Ez of step k+1).  When seed_out, the
+// probe-loss seed of the next step is added to the written Ez:
+// l1.ez[probe] += 2 * rec[slot][seed_k] (pt: probes grouped by tile in tile
+// order, tile = (i / TX) * nsy + j / (62 V), entries of one cell
 // consecutive).  Tiles of TX rows by 62*V columns; ny % V == 0.
 hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
-                              const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
-                              double *grad, int seed_out, const ProbeTiles &pt, const float *rec, int64_t rec_stride,
-                              int64_t seed_k, int V, int TX, hipStream_t st);
+                              const float *cap_ez, const float *cap_br, double *sez, double *sbr, int seed_out,
+                              const ProbeTiles &pt, const float *rec, int64_t rec_stride, int64_t seed_k, int V,
+                              int TX, hipStream_t st);
 // The seed of the first adjoint step: ez[cell u] += 2 * rec[slot][k] over
 // the probe entries [start[u], start[u+1]) of the nu probed cells.
 hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_cell, const int *seed_slot, int nu,

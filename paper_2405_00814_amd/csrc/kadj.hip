@@ -31,8 +31,11 @@ struct AdjFArgs {
     Prob2D p;
     Adj2D l0, l1;      // adjoint state read (step k+1) and written (step k)
     int4 design;
-    const float *cap_ez, *cap_br, *dca, *dcb;
-    double *grad;
+    const float *cap_ez, *cap_br;
+    // per design cell: sez += a Ez^n, sbr += a bracket (the gradients with
+    // respect to any per-cell parameter of Ca and Cb follow from these two
+    // sums and the coefficients' derivatives)
+    double *sez, *sbr;
     // probe-loss seed of the next step, added to the written adjoint Ez:
     // l1.ez[probe] += 2 * rec[slot][seed_k] (probes grouped by tile, entries
     // of one cell consecutive)
@@ -137,7 +140,8 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 gx[v] = -u * kEy[v] + cEy[v] * py;
                 if (write && i >= A.design.x && i < A.design.y && j >= A.design.z && j < A.design.w) {
                     const int64_t q = (int64_t)(i - A.design.x) * dw + (j - A.design.z);
-                    A.grad[q] += (double)a[v] * ((double)A.dca[q] * A.cap_ez[q] + (double)A.dcb[q] * A.cap_br[q]);
+                    A.sez[q] += (double)a[v] * A.cap_ez[q];
+                    A.sbr[q] += (double)a[v] * A.cap_br[q];
                 }
                 aca[v] = a[v] * ca[v];
             } else if (PML && jj[v] >= 0 && write) {
@@ -278,9 +282,9 @@ hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_c
 }
 
 hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
-                              const float *cap_ez, const float *cap_br, const float *dca, const float *dcb,
-                              double *grad, int seed_out, const ProbeTiles &pt, const float *rec, int64_t rec_stride,
-                              int64_t seed_k, int V, int TX, hipStream_t st) {
+                              const float *cap_ez, const float *cap_br, double *sez, double *sbr, int seed_out,
+                              const ProbeTiles &pt, const float *rec, int64_t rec_stride, int64_t seed_k, int V,
+                              int TX, hipStream_t st) {
     if (p.ny % V != 0 || TX < 1) return hipErrorInvalidValue;
     AdjFArgs A;
     A.seed_out = seed_out;
@@ -294,9 +298,8 @@ hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1,
     A.design = make_int4(design[0], design[1], design[2], design[3]);
     A.cap_ez = cap_ez;
     A.cap_br = cap_br;
-    A.dca = dca;
-    A.dcb = dcb;
-    A.grad = grad;
+    A.sez = sez;
+    A.sbr = sbr;
     const int nsy = (p.ny + 62 * V - 1) / (62 * V), ncx = (p.nx + TX - 1) / TX;
     const int nt = nsy * ncx;
     const dim3 g((unsigned)((nt + 3) / 4)), b(256);
@@ -316,14 +319,17 @@ hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1,
     return hipGetLastError();
 }
 
-__global__ void k_grad_to_float(const double *g, float *out, int64_t n) {
+__global__ void k_grad_combine(const double *sez, const double *sbr, const double *dca, const double *dcb,
+                               float *out, int64_t n) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) out[q] = (float)g[q];
+    if (q < n) out[q] = (float)(dca[q] * sez[q] + dcb[q] * sbr[q]);
 }
 
-hipError_t launch_grad_to_float(const double *g, float *out, int64_t n, hipStream_t st) {
+hipError_t launch_grad_combine(const double *sez, const double *sbr, const double *dca, const double *dcb, float *out,
+                               int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, out, n);
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sez, sbr, dca, dcb, out,
+                       n);
     return hipGetLastError();
 }
 

@@ -297,6 +297,22 @@ class Sim:
                int(ckpt_interval), C.byref(loss), C.cast(C.c_void_p(grad.data_ptr()), C.POINTER(C.c_float)))
         return loss.value, grad
 
+    def adjoint_grads(self, T, window, design, ckpt_interval=0):
+        """Loss and its gradients with respect to eps_r and sigma (per S/m)
+        on the design box, from one adjoint run: (loss, g_eps, g_sigma) with
+        torch float32 CUDA tensors of the box size."""
+        torch = _torch()
+        i0, i1, j0, j1 = design
+        n = (i1 - i0) * (j1 - j0)
+        ge = torch.empty(n, dtype=torch.float32, device="cuda")
+        gs = torch.empty(n, dtype=torch.float32, device="cuda")
+        d = (C.c_int32 * 4)(*[int(v) for v in design])
+        loss = C.c_double()
+        fp = C.POINTER(C.c_float)
+        L.call("fdtd_adjoint", self.h, int(T), int(window[0]), int(window[1]), d, int(ckpt_interval),
+               C.byref(loss), C.cast(C.c_void_p(ge.data_ptr()), fp), C.cast(C.c_void_p(gs.data_ptr()), fp))
+        return loss.value, ge, gs
+
 
 class Batch:
     """Many independent 2D problems advanced together."""

@@ -218,3 +218,46 @@ def test_autograd_function():
     assert abs(L.item() - loss_ref) <= 1e-4 * loss_ref
     assert rel_l2(eps.grad.cpu().numpy(), grad_ref) <= 1e-3
     s.close()
+
+
+@pytest.mark.parametrize("lossy", [False, True])
+def test_adjoint_sigma_gradient_vs_fd_fp64(lossy):
+    """Gradients with respect to eps_r and sigma from one adjoint run, each
+    against FP64 central finite differences of the oracle forward on seeded
+    design cells (sigma = 0 in the box, and sigma > 0); the eps_r gradient
+    equals fdtd_adjoint_eps's."""
+    from oracle import oracle as O
+    from paper_2405_00814_amd.sim import Sim
+    pb = _adjoint_case(n=56, T=260, design=(20, 30, 22, 32), lossy=lossy)
+    s = Sim.from_problem(pb)
+    loss, ge, gs = s.adjoint_grads(pb.steps, pb.window, pb.design)
+    ge = ge.cpu().numpy().reshape(10, 10)
+    gs = gs.cpu().numpy().reshape(10, 10)
+    s.reset()
+    loss1, g1 = s.adjoint_eps(pb.steps, pb.window, pb.design)
+    assert np.array_equal(g1.cpu().numpy().reshape(10, 10), ge) and loss1 == loss
+    s.close()
+    sig0 = np.zeros(pb.shape) if pb.sigma is None else pb.sigma.astype(np.float64)
+
+    def oloss(eps, sig):
+        o = O.Oracle2D(pb.shape, pb.dx, pb.dt, eps, sig, None, pb.npml)
+        o.set_source(pb.source.cell, pb.source.kind, pb.source.params)
+        o.set_probes(pb.probes)
+        r = o.run(pb.steps)
+        return np.sum(r[:, pb.window[0]:pb.window[1]] ** 2)
+
+    rng = np.random.default_rng(9)
+    fd, gg = [], []
+    for _ in range(4):
+        c = (int(rng.integers(20, 30)), int(rng.integers(22, 32)))
+        h = 1e-4
+        vals = []
+        for sgn in (+1, -1):
+            sig = sig0.copy()
+            sig[c] += sgn * h
+            vals.append(oloss(pb.eps_r.astype(np.float64), sig))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        gg.append(gs[c[0] - 20, c[1] - 22])
+    fd, gg = np.array(fd), np.array(gg)
+    log("sigma fd", fd, "gpu", gg)
+    assert np.linalg.norm(gg - fd) <= 1e-3 * np.linalg.norm(fd)
