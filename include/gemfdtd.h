@@ -253,7 +253,10 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *    of the tiles near a CPML slab (0 = TX; at most 65536).  Each
  *    wavefront advances its rows and columns TB steps, recomputing the
  *    neighbouring rows and columns it needs; an n not divisible by TB ends
- *    with single steps.
+ *    with single steps.  The tiles near a slab run on a second stream of
+ *    the library, forked from and joined back to the simulation's stream
+ *    within each pass.  The default chunk depends on the grid (16-32 rows
+ *    where the interior tiles then fill the device once, else 4 or 8).
  * FDTD_EINVAL for unknown or unsupported combinations. */
 typedef struct {
     int32_t variant;

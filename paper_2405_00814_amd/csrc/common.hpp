@@ -147,6 +147,9 @@ bool tb2d_supported(int ny, int V, int TB, int TX);
 // row chunk.
 void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, int TXo, const int *xlohi, const int *ylohi,
                std::vector<Tile2T> &inner, std::vector<Tile2T> &outer);
+// Default row chunk TX of the four-step pass at strip width V on `cus`
+// compute units (see plan2d.cpp).
+int tb2d_default_tx(int nx, int ny, int V, int cus);
 // Capture of the design cells for the adjoint: for every step n of the
 // pass, at cell (i, j) of the box design = [x, y) x [z, w), Ez before the E
 // layer goes to ez[(n - k0) * nd + q] and the E layer's bracket to br[...],

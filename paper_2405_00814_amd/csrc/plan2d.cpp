@@ -12,6 +12,26 @@ bool tb2d_supported(int ny, int V, int TB, int TX) {
     return ny % V == 0;
 }
 
+// The default row chunk.  Measured on 2048^2 - 6400^2 dielectric grids
+// (four steps per pass, CPML tiles on a second stream): at V = 2 the pass is
+// fastest when all interior workgroups (four strips each) are resident at
+// once, 4-5 per CU at the kernel's register use, with chunks as long as
+// that allows (fewer recomputed rows); grids too large for one round run
+// best with short chunks of 8 rows.  At V = 1 (lighter registers) the
+// longest chunk that still gives 4 workgroups per CU wins.
+int tb2d_default_tx(int nx, int ny, int V, int cus) {
+    const int own = tb2d_own(V, 4);
+    auto wgs = [&](int tx) { return (int64_t)((nx + tx - 1) / tx) * ((ny + own - 1) / own) / 4; };
+    if (V == 2) {
+        for (int tx : {32, 16})
+            if (wgs(tx) >= 4 * (int64_t)cus && wgs(tx) <= 5 * (int64_t)cus) return tx;
+        return 8;
+    }
+    for (int tx : {16, 8})
+        if (wgs(tx) >= 4 * (int64_t)cus) return tx;
+    return 4;
+}
+
 void tb2d_plan(int prob, int nx, int ny, int V, int TB, int TX, int TXo, const int *xlohi, const int *ylohi,
                std::vector<Tile2T> &inner, std::vector<Tile2T> &outer) {
     if (TXo < 1) TXo = TX;

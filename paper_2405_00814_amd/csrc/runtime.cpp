@@ -223,6 +223,9 @@ double source_sample(int kind, const double *par, double dt, int64_t n) {
 Sim::~Sim() {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (evf) (void)hipEventDestroy(evf);
+    if (evj) (void)hipEventDestroy(evj);
+    if (side) (void)hipStreamDestroy(side);
     al.release_all();
 }
 
@@ -467,18 +470,30 @@ Fused2DCfg Sim::single2d() const {
     return default_single2d(nx, ny);
 }
 
-// TB steps of the 2D grid in one pass: interior tiles without the CPML code,
-// then the tiles near a slab with it
+// TB steps of the 2D grid in one pass: interior tiles without the CPML code
+// on `st` and, at the same time, the tiles near a slab with it on the second
+// stream.  The two sets read state n and write state n+TB of disjoint cells
+// (own columns and rows; probe slots and design-cell captures of their own
+// tiles), so they run concurrently: the few CPML tiles, long dependent chains
+// of row loads, fill the CUs beside the interior tiles instead of running
+// after them on an almost empty device.  `st` waits for both.
 void Sim::launch_tb2d(int64_t step, const CapArgs *cap) {
     const int V = kcfg.tile[0], TB = kcfg.tile[2];
     const Prob2D p = prob2d(cur, 1 - cur);
     const ProbeTiles pt{pt2_start, pt2_cell, pt2_slot};
     const ProbeTiles po{pt2_start + tb2_inner, pt2_cell, pt2_slot};
+    const bool fork = tb2_inner > 0 && tb2_outer > 0;
+    if (fork) {
+        hip_check(hipEventRecord(evf, st), "event");
+        hip_check(hipStreamWaitEvent(side, evf, 0), "stream wait");
+    }
+    hip_check(launch_2d_tb(p, nullptr, tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB, nullptr, step,
+                           fork ? side : st, cap),
+              "2d multi-step (cpml)");
+    if (fork) hip_check(hipEventRecord(evj, side), "event");
     hip_check(launch_2d_tb(p, nullptr, tb2_dev, tb2_inner, false, mat(), pt, V, TB, nullptr, step, st, cap),
               "2d multi-step");
-    hip_check(launch_2d_tb(p, nullptr, tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB, nullptr, step, st,
-                           cap),
-              "2d multi-step (cpml)");
+    if (fork) hip_check(hipStreamWaitEvent(st, evj, 0), "stream wait");
     cur = 1 - cur;
     last_launches += (tb2_inner > 0) + (tb2_outer > 0);
 }
@@ -697,12 +712,13 @@ int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
     }
     if (s.ndim == 2) {
         const bool wide = s.ncell >= kWide2DCells && s.ny % 2 == 0;
-        const int vt = wide ? 2 : 1, tx = wide ? 8 : kTB2DefaultTX;
+        const int vt = wide ? 2 : 1, tx = tb2d_default_tx(s.nx, s.ny, vt, s.cus);
         if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, tx)) {
             k.variant = 3;
             k.tile[0] = vt;
             k.tile[1] = tx;
             k.tile[2] = 4;
+            k.tile[3] = tx >= 16 ? tx / 4 : 0;  // CPML tiles in quarters of long chunks
             return 0;
         }
         const Fused2DCfg c = default_single2d(s.nx, s.ny);
@@ -860,6 +876,9 @@ void init_sim(Sim &s, const fdtd_desc *d) {
     }
     hip_check(hipEventCreate(&s.ev0), "event");
     hip_check(hipEventCreate(&s.ev1), "event");
+    hip_check(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking), "stream");
+    hip_check(hipEventCreateWithFlags(&s.evf, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&s.evj, hipEventDisableTiming), "event");
     default_variant_tiles(s, s.kcfg);
     hip_check(hipStreamSynchronize(s.st), "sync");
 }
@@ -1575,15 +1594,18 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
             }
         for (int V : {1, 2, 4})
             for (int TB : {2, 4})
-                for (int TX : {4, 8, 16}) {
-                    fdtd_kernel_config k{};
-                    k.variant = 3;
-                    k.tile[0] = V;
-                    k.tile[1] = TX;
-                    k.tile[2] = TB;
-                    k.tb = 1;
-                    if (config_ok(s, k)) cand.push_back(k);
-                }
+                for (int TX : {4, 8, 16, 32})
+                    for (int TXo : {0, TX / 4}) {  // CPML tiles: whole chunks or quarters
+                        if (TXo == TX / 4 && TX < 16) continue;
+                        fdtd_kernel_config k{};
+                        k.variant = 3;
+                        k.tile[0] = V;
+                        k.tile[1] = TX;
+                        k.tile[2] = TB;
+                        k.tile[3] = TXo;
+                        k.tb = 1;
+                        if (config_ok(s, k)) cand.push_back(k);
+                    }
     } else {
         for (int TX : {8, 16, 32})
             for (int V : {1, 2, 4}) {

@@ -132,6 +132,10 @@ struct Sim {
     bool kcfg_explicit = false;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // second stream of the 2D multi-step pass (its CPML tiles) and the
+    // events that fork it from and join it to `st`
+    hipStream_t side = nullptr;
+    hipEvent_t evf = nullptr, evj = nullptr;
     hipEvent_t *lev = nullptr;  // per-launch events of a profiled step (3D fused)
     bool timed = false;
     int64_t last_launches = 0;

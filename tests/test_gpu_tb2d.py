@@ -69,6 +69,23 @@ def test_tb2d_chunks_sources_probes_at_edges():
         assert rel_l2(rec, rrec) <= TOL
 
 
+def test_tb2d_cpml_tiles_on_second_stream():
+    """The CPML tiles (quarter chunks) run beside the interior tiles on a
+    second stream: parity, and the same bits on a second run."""
+    pb = W.dielectric2d(700, ny=600, steps=301, seed=7, nrect=10, side=(8, 48), npml=16, nprobes=5)
+    ref, rrec = run_oracle(pb, pb.steps)
+    for kernel in ((3, (2, 32, 4, 8)), (3, (1, 16, 4, 4))):
+        runs = [run_gpu(pb, pb.steps, kernel) for _ in range(2)]
+        got, rec, cfg = runs[0]
+        assert cfg["tile"] == kernel[1]
+        log("tb2d second stream", kernel, {k: "%.1e" % rel_l2(got[k], ref[k]) for k in ref})
+        assert_parity(got, ref, TOL, "tb2d second stream %s" % (kernel,))
+        assert rel_l2(rec, rrec) <= TOL
+        for k in got:
+            assert np.array_equal(got[k], runs[1][0][k]), k
+        assert np.array_equal(rec, runs[1][1])
+
+
 def test_tb2d_cavity_full_config():
     pb = W.cavity2d(128, steps=1000, seed=0)
     ref, rrec = run_oracle(pb, pb.steps)
