@@ -18,7 +18,7 @@ bool tb2d_supported(int ny, int V, int TB, int TX) {
 // once, 4-5 per CU at the kernel's register use, with chunks as long as
 // that allows (fewer recomputed rows); grids too large for one round run
 // best with short chunks of 8 rows.  At V = 1 (lighter registers) the
-// longest chunk that still gives 4 workgroups per CU wins.
+// longest chunk that still gives 2 workgroups per CU wins.
 int tb2d_default_tx(int nx, int ny, int V, int cus) {
     const int own = tb2d_own(V, 4);
     auto wgs = [&](int tx) { return (int64_t)((nx + tx - 1) / tx) * ((ny + own - 1) / own) / 4; };
@@ -28,7 +28,7 @@ int tb2d_default_tx(int nx, int ny, int V, int cus) {
         return 8;
     }
     for (int tx : {16, 8})
-        if (wgs(tx) >= 4 * (int64_t)cus) return tx;
+        if (wgs(tx) >= 2 * (int64_t)cus) return tx;
     return 4;
 }
 

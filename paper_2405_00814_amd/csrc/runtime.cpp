@@ -688,11 +688,11 @@ void Sim::refold(int64_t c0, int64_t c1) {
     hip_check(hipStreamSynchronize(st), "sync");
 }
 
-// 2D defaults (measured on MI355X over grids of 256^2 .. 4096^2): single
-// steps below 2M cells, four steps per pass from there on; one column per
-// lane and short tiles below 8M cells (more wavefronts), two columns and
-// longer tiles above.
-constexpr int64_t kTB2MinCells = (int64_t)2 << 20;
+// 2D defaults (measured on MI355X over grids of 256^2 .. 6400^2): single
+// steps below 1.5M cells, four steps per pass from there on; one column per
+// lane below 8M cells, two columns above; the row chunk from
+// tb2d_default_tx.
+constexpr int64_t kTB2MinCells = (int64_t)3 << 19;
 constexpr int64_t kWide2DCells = (int64_t)8 << 20;
 constexpr int kTB2DefaultTX = 4;
 // smallest 3D grid (cells) on which the default takes two steps per pass
