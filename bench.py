@@ -256,10 +256,17 @@ def bench_adjoint(args):
     loss, grad = s.adjoint_eps(pb.steps, pb.window, pb.design, 0)
     ta, _ = s.last_step_time()
     g = grad.cpu().numpy()
+    # the same run holding the design values of all T steps (no recompute:
+    # 8 B per design cell and step, 2.1 GB here)
+    s.reset()
+    loss_f, grad_f = s.adjoint_eps(pb.steps, pb.window, pb.design, pb.steps)
+    tn, _ = s.last_step_time()
+    same = bool(loss_f == loss and torch.equal(grad_f, grad))
     s.close()
     return dict(workload="adjoint2d_1024x1024_design_256x256_T4000", steps=pb.steps,
                 forward_ms=tf, adjoint_ms=ta, adjoint_over_forward=ta / tf,
                 checkpoint_interval=int(math.ceil(math.sqrt(pb.steps))),
+                no_recompute_ms=tn, no_recompute_over_forward=tn / tf, no_recompute_same_bits=same,
                 loss=loss, grad_finite=bool(np.isfinite(g).all()))
 
 

@@ -344,7 +344,11 @@ int fdtd_batch_cells(const fdtd_batch *b, int64_t *cells);
  * design = {i0, i1, j0, j1} (ndim 2) by the discrete adjoint: the
  * transposed E and H layers run backward in time.  The forward pass keeps a
  * full-state checkpoint every `ckpt_interval` steps (<= 0 => ceil(sqrt T))
- * and recomputes each segment before its adjoint sweep.
+ * and recomputes each segment but the last before its adjoint sweep (the
+ * forward pass keeps the last segment's design-cell values).  Device
+ * memory: the checkpoints plus 8 B per design cell and step of one
+ * segment; ckpt_interval >= T runs no recompute and holds the values of
+ * all T steps.
  * loss_out (host, may be NULL); grad_dev: device float32
  * [(i1-i0)*(j1-j0)], written.  On return the handle holds the forward state
  * after T steps and the probe record of the forward run. */

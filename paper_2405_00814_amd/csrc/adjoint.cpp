@@ -2,10 +2,13 @@
 // discrete adjoint, with checkpointing.
 //
 // Forward: T steps from the zero state with a full-state checkpoint every L
-// steps.  Backward, newest segment first: restore the checkpoint, recompute
-// the segment with the same kernel (bitwise the same states) while keeping,
-// at every design cell and step, Ez before the E layer and the E-layer
-// bracket; then run the segment's adjoint steps backward.  The gradient of
+// steps; the last segment already keeps, at every design cell and step, Ez
+// before the E layer and the E-layer bracket.  Backward, newest segment
+// first: run the segment's adjoint steps backward on what was kept; for
+// every older segment first restore its checkpoint and recompute it with
+// the same kernels (bitwise the same states), keeping the same values.
+// With L >= T the forward pass is the only one (the design values of all
+// T steps are held: 8 B per design cell and step).  The gradient of
 // E^{k+1} = Ca E^k + Cb * bracket with respect to a parameter of Ca and Cb
 // at a design cell is dCa * E^k + dCb * bracket, weighted by the adjoint of
 // E^{k+1}: the adjoint steps sum a * E^k and a * bracket per cell in
@@ -106,25 +109,49 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
             return p;
         };
         const int64_t S = state_floats(s);
-        float *ck = (float *)get((size_t)(nseg * S) * 4);
+        float *ck = (float *)get((size_t)(std::max<int64_t>(1, nseg - 1) * S) * 4);
         float *fin = (float *)get((size_t)S * 4);
-        hip_check(hipEventRecord(s.ev0, s.st), "event");
-        // ---- forward with checkpoints ----
-        for (int64_t g = 0; g < nseg; ++g) {
-            copy_state(s, s.cur, ck + g * S, true);
-            const int64_t k1 = std::min(T, (g + 1) * L);
-            for (int64_t k = g * L; k < k1;) {
+        float *cap_ez = (float *)get((size_t)(L * nd) * 4);
+        float *cap_br = (float *)get((size_t)(L * nd) * 4);
+        const int dbox[4] = {i0, i1, j0, j1};
+        ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
+        const Fused2DCfg fc = s.single2d();
+        // steps [k0, k1) from the current state; with `cap`, keeping the
+        // design values of each step at (step - k0) * nd
+        auto run = [&](int64_t k0, int64_t k1, const CapArgs *cap) {
+            for (int64_t k = k0; k < k1;) {
                 if (multi && k + TB <= k1) {
-                    s.launch_tb2d(k);
+                    s.launch_tb2d(k, cap);
                     k += TB;
                     s.n_done += TB;
                     s.n_rec += TB;
+                    continue;
+                }
+                if (cap) {
+                    const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
+                    const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
+                    hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
+                                              cap_br + (k - k0) * nd, s.split2d() ? &sp : nullptr),
+                              "forward step");
+                    s.cur = 1 - s.cur;
                 } else {
                     s.launch_step(k);
-                    k += 1;
-                    s.n_done += 1;
-                    s.n_rec += 1;
                 }
+                s.n_done += 1;
+                s.n_rec += 1;
+                k += 1;
+            }
+        };
+        hip_check(hipEventRecord(s.ev0, s.st), "event");
+        // ---- forward: checkpoints, then the last segment with its design values ----
+        for (int64_t g = 0; g < nseg; ++g) {
+            const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
+            if (g + 1 < nseg) {
+                copy_state(s, s.cur, ck + g * S, true);
+                run(k0, k1, nullptr);
+            } else {
+                const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
+                run(k0, k1, &cap);
             }
         }
         copy_state(s, s.cur, fin, true);
@@ -152,8 +179,6 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
         int acur = 0;
         double *sez = (double *)get((size_t)nd * 8);  // zero-filled
         double *sbr = (double *)get((size_t)nd * 8);
-        float *cap_ez = (float *)get((size_t)(L * nd) * 4);
-        float *cap_br = (float *)get((size_t)(L * nd) * 4);
         // derivatives of Ca = (e - h)/(e + h) and Cb = dt/(e + h), e = eps0
         // eps_r, h = sigma dt / 2, at the design cells (FP64):
         //   d/d eps_r: dCa = 2 eps0 h / (e + h)^2,  dCb = -eps0 dt / (e + h)^2
@@ -221,34 +246,16 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
         hip_check(hipMemcpyAsync(d_tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         const ProbeTiles apt{d_tst, d_tcell, d_tslot};
         hip_check(hipStreamSynchronize(s.st), "sync");
-        // ---- backward over segments ----
-        const int dbox[4] = {i0, i1, j0, j1};
-        ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
-        const Fused2DCfg fc = s.single2d();
+        // ---- backward over segments (the last one kept by the forward) ----
         for (int64_t g = nseg - 1; g >= 0; --g) {
             const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
-            copy_state(s, 0, ck + g * S, false);
-            s.cur = 0;
-            s.n_done = k0;
-            s.n_rec = k0;
-            const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
-            for (int64_t k = k0; k < k1;) {
-                if (multi && k + TB <= k1) {
-                    s.launch_tb2d(k, &cap);
-                    k += TB;
-                    s.n_done += TB;
-                    s.n_rec += TB;
-                    continue;
-                }
-                const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
-                const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
-                hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
-                                          cap_br + (k - k0) * nd, s.split2d() ? &sp : nullptr),
-                          "recompute");
-                s.cur = 1 - s.cur;
-                s.n_done += 1;
-                s.n_rec += 1;
-                k += 1;
+            if (g + 1 < nseg) {
+                copy_state(s, 0, ck + g * S, false);
+                s.cur = 0;
+                s.n_done = k0;
+                s.n_rec = k0;
+                const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
+                run(k0, k1, &cap);
             }
             const Prob2D p = s.prob2d(0, 0);
             for (int64_t k = k1 - 1; k >= k0; --k) {

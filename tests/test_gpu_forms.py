@@ -149,6 +149,40 @@ def test_adjoint_matches_oracle(ckpt, lossy):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", [None, (3, (1, 4, 4)), (3, (2, 3, 2)), (2, (2, 8))])
+def test_adjoint_checkpoint_intervals_same_bits(kernel):
+    """The recomputed segments repeat the forward pass bit for bit, so with
+    single steps the checkpoint interval (the last segment kept by the
+    forward, every other one recomputed; T and above: no recompute) changes
+    no bit of the loss, the gradients or the state left behind.  With
+    multi-step passes the interval regroups the steps into passes and
+    single steps (last bits of a contracted multiply-add may differ): the
+    same values within 1e-5."""
+    from paper_2405_00814_amd.sim import Sim
+    pb = _adjoint_case(n=72, T=203, lossy=True)
+    out = []
+    for ckpt in (0, 1, 7, 64, pb.steps, pb.steps + 5):
+        s = Sim.from_problem(pb)
+        if kernel is not None:
+            s.set_kernel(*kernel)
+        loss, ge, gs = s.adjoint_grads(pb.steps, pb.window, pb.design, ckpt)
+        out.append((ckpt, loss, ge.cpu().numpy(), gs.cpu().numpy(), s.get_field("ez"), s.probe()))
+        s.close()
+    c0, l0, e0, s0, z0, r0 = out[0]
+    assert np.isfinite(e0).all() and np.abs(e0).max() > 0 and np.abs(s0).max() > 0
+    bits = kernel is None or kernel[0] == 2
+    for c, l, e, sg, z, r in out[1:]:
+        log("ckpt", c, "loss", l, l0, "grad", rel_l2(e, e0), rel_l2(sg, s0))
+        if bits:
+            assert l == l0, c
+            assert np.array_equal(e, e0) and np.array_equal(sg, s0), c
+            assert np.array_equal(z, z0) and np.array_equal(r, r0), c
+        else:
+            assert abs(l - l0) <= 1e-6 * abs(l0), c
+            assert rel_l2(e, e0) <= 1e-5 and rel_l2(sg, s0) <= 1e-5, c
+            assert rel_l2(z, z0) <= 1e-5 and rel_l2(r, r0) <= 1e-5, c
+
+
 @pytest.mark.parametrize("kernel,ckpt,lossy", [((3, (1, 4, 4)), 0, False), ((3, (2, 3, 2)), 17, True),
                                                ((3, (1, 16, 4)), 30, False), ((2, (2, 8)), 0, True)])
 def test_adjoint_kernel_configs(kernel, ckpt, lossy):
