@@ -182,6 +182,20 @@ int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t 
  * summed.  re = im = NULL: only nsteps.  FDTD_ESTATE without a monitor. */
 int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps);
 
+/* Specific absorption rate (W/kg) from the monitor's sums, the monitored E
+ * component's share: sar[q][c] = sigma_c |X_qc|^2 / (2 rho_c norm_q^2),
+ * X_qc = re + i im of fdtd_get_dft, sigma_c the cell's conductivity (S/m,
+ * the material map), rho_c its mass density.  The time-averaged power per
+ * unit mass that a time-harmonic field of complex amplitude X deposits
+ * (the paper estimates SAR in layered tissue, Sec. V-B); dividing the
+ * transient's sums by the source spectrum |S(f_q)| (norm_q) gives it per
+ * unit source amplitude.  rho: host float [box cells] (finite, > 0), box
+ * order as fdtd_get_dft; norm: host double [nf] (finite, > 0) or NULL
+ * (all 1); sar: host float [nf][box cells], written.  Synchronises.
+ * FDTD_ESTATE without a monitor; FDTD_EINVAL for a monitor on an H
+ * component or a bad rho or norm. */
+int fdtd_dft_sar(fdtd_sim *sim, const float *rho, const double *norm, float *sar);
+
 /* Probe cells (ijk: n*ndim int32, host) sampled on `component` after every
  * step.  Replaces earlier probes and clears the record.  n <= 4096. */
 int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n);

@@ -414,6 +414,20 @@ def _dft_sample(o, nsteps):
     d["n"] += 1
 
 
+def sar(X, sigma, rho, norm=None):
+    """Specific absorption rate (W/kg) of a time-harmonic field whose complex
+    amplitude at frequency q is X[q] (the paper estimates SAR in layered
+    tissue, Sec. V-B, without stating the formula): the time-averaged Joule
+    power per unit mass, sigma |X|^2 / (2 rho), with X divided by norm[q]
+    (the source spectrum, for a per-unit-source result; None: 1).  sigma and
+    rho have the shape of one X[q]."""
+    X = np.asarray(X, np.complex128)
+    n = np.ones(X.shape[0]) if norm is None else np.asarray(norm, np.float64)
+    n = n.reshape((-1,) + (1,) * (X.ndim - 1))
+    a2 = X.real ** 2 + X.imag ** 2
+    return np.asarray(sigma, np.float64)[None] * a2 / (2.0 * np.asarray(rho, np.float64)[None] * n ** 2)
+
+
 def for_problem(pb):
     if pb.ndim == 2 and (pb.cpml or {}).get("split", 0):
         from .split import Oracle2DSplit

@@ -72,6 +72,7 @@ _SIGS = {
     "fdtd_set_source_box": (C.c_int, [P, C.c_int, i32p, i32p, C.c_int, f64p, f32p, i64]),
     "fdtd_set_dft": (C.c_int, [P, C.c_int, i32p, i32p, C.c_int, f64p]),
     "fdtd_get_dft": (C.c_int, [P, f64p, f64p, C.POINTER(C.c_int64)]),
+    "fdtd_dft_sar": (C.c_int, [P, f32p, f64p, f32p]),
     "fdtd_set_probes": (C.c_int, [P, C.c_int, i32p, i32]),
     "fdtd_step": (C.c_int, [P, i64]),
     "fdtd_probe": (C.c_int, [P, f32p, i64, i64p]),

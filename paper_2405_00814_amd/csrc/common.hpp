@@ -258,6 +258,13 @@ struct DftPhase {
 };
 hipError_t launch_dft(const float *f, const int64_t *idx, int64_t npts, int nf, const DftPhase &ph, double *acc,
                       hipStream_t st);
+// Specific absorption rate from a monitor's sums: out[q][c] = sig[c] |X_qc|^2
+// * inv2n2[q] / rho[c] (inv2n2 = 1 / (2 norm_q^2)), in FP64, stored FP32.
+struct SarScale {
+    double inv2n2[kDftMaxFreq];
+};
+hipError_t launch_sar(const double *acc, int64_t npts, int nf, const float *sig, const float *rho,
+                      const SarScale &sc, float *out, hipStream_t st);
 
 // CSR layer: y[dst[r]] = sum_{e in row r} w[e] * x[col[e]] for r < nrows.
 hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,

@@ -26,4 +26,29 @@ hipError_t launch_dft(const float *f, const int64_t *idx, int64_t npts, int nf, 
     return hipGetLastError();
 }
 
+// The monitored E component's share of the specific absorption rate: the
+// time-averaged power a time-harmonic field of complex amplitude X deposits
+// per unit mass is sigma |X|^2 / (2 rho).  One thread per cell, all
+// frequencies.
+__global__ __launch_bounds__(256) void k_sar(const double *__restrict__ acc, int64_t npts, int nf,
+                                             const float *__restrict__ sig, const float *__restrict__ rho,
+                                             SarScale sc, float *__restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= npts) return;
+    const double w = (double)sig[c] / (double)rho[c];
+    for (int q = 0; q < nf; ++q) {
+        const double re = acc[(2 * q) * npts + c], im = acc[(2 * q + 1) * npts + c];
+        out[(int64_t)q * npts + c] = (float)(w * (re * re + im * im) * sc.inv2n2[q]);
+    }
+}
+
+hipError_t launch_sar(const double *acc, int64_t npts, int nf, const float *sig, const float *rho,
+                      const SarScale &sc, float *out, hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    if (nf < 1 || nf > kDftMaxFreq) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sar, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, acc, npts, nf, sig, rho, sc,
+                       out);
+    return hipGetLastError();
+}
+
 }  // namespace gem

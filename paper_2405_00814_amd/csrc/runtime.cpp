@@ -1375,6 +1375,49 @@ int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps) {
     GEM_CATCH
 }
 
+int fdtd_dft_sar(fdtd_sim *sim, const float *rho, const double *norm, float *sar) {
+    GEM_TRY
+    if (!sim || !rho || !sar) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    const Sim::Dft &d = s.dft;
+    if (d.comp < 0) fail(FDTD_ESTATE, "no frequency-domain monitor set");
+    if (d.comp != FDTD_EX && d.comp != FDTD_EY && d.comp != FDTD_EZ)
+        fail(FDTD_EINVAL, "the absorption rate needs a monitor on an E component");
+    SarScale sc{};
+    for (int q = 0; q < d.nf; ++q) {
+        const double n = norm ? norm[q] : 1.0;
+        if (!std::isfinite(n) || n <= 0) fail(FDTD_EINVAL, "norm must be finite and > 0");
+        sc.inv2n2[q] = 0.5 / (n * n);
+    }
+    std::vector<float> sg((size_t)d.npts, 0.f);
+    int64_t c = 0;
+    for (int i = d.box[0]; i < d.box[1]; ++i)
+        for (int j = d.box[2]; j < d.box[3]; ++j)
+            for (int k = d.box[4]; k < d.box[5]; ++k, ++c) {
+                if (!std::isfinite(rho[c]) || rho[c] <= 0) fail(FDTD_EINVAL, "rho must be finite and > 0");
+                if (!s.sigma.empty()) sg[(size_t)c] = s.sigma[(size_t)(((int64_t)i * s.ny + j) * s.nz + k)];
+            }
+    const size_t nb = (size_t)d.npts * 4;
+    float *dsg = (float *)s.al.get(nb), *drho = (float *)s.al.get(nb), *dout = (float *)s.al.get(nb * d.nf);
+    struct Put {
+        Sim &s;
+        void *a, *b, *c;
+        ~Put() {
+            (void)hipStreamSynchronize(s.st);
+            s.al.put(a);
+            s.al.put(b);
+            s.al.put(c);
+        }
+    } put{s, dsg, drho, dout};
+    hip_check(hipMemcpyAsync(dsg, sg.data(), nb, hipMemcpyHostToDevice, s.st), "upload");
+    hip_check(hipMemcpyAsync(drho, rho, nb, hipMemcpyHostToDevice, s.st), "upload");
+    hip_check(launch_sar(d.acc, d.npts, d.nf, dsg, drho, sc, dout, s.st), "sar");
+    hip_check(hipMemcpyAsync(sar, dout, nb * d.nf, hipMemcpyDeviceToHost, s.st), "copy");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
 int fdtd_get_field(fdtd_sim *sim, int component, void *dst, int dst_on_device) {
     GEM_TRY
     if (!sim || !dst) fail(FDTD_EINVAL, "NULL argument");

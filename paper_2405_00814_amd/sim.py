@@ -190,6 +190,25 @@ class Sim:
                im.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ns))
         return (re + 1j * im).reshape((nf,) + shape), ns.value
 
+    def dft_sar(self, rho, norm=None):
+        """Specific absorption rate (W/kg) from the monitor's sums, float32
+        [nf, *box shape]: sigma |X|^2 / (2 rho norm^2); rho over the box
+        (kg/m^3), norm per frequency (None: 1)."""
+        shape, nf = getattr(self, "_dft", ((0,), 0))
+        if nf == 0:  # no monitor: the library reports it
+            one = np.ones(1, np.float32)
+            L.call("fdtd_dft_sar", self.h, one.ctypes.data_as(C.POINTER(C.c_float)), None,
+                   one.ctypes.data_as(C.POINTER(C.c_float)))
+        n = int(np.prod(shape))
+        r = np.ascontiguousarray(np.asarray(rho, np.float32).reshape(-1))
+        if r.size != n:
+            raise ValueError("rho must have one value per monitored cell")
+        out = np.zeros(max(1, nf * n), np.float32)
+        nm = None if norm is None else (C.c_double * nf)(*[float(v) for v in norm])
+        L.call("fdtd_dft_sar", self.h, r.ctypes.data_as(C.POINTER(C.c_float)), nm,
+               out.ctypes.data_as(C.POINTER(C.c_float)))
+        return out[:nf * n].reshape((nf,) + shape)
+
     def clear_source(self):
         L.call("fdtd_set_source", self.h, L.FDTD_EZ, None, -1, None, None, 0)
 

@@ -73,6 +73,7 @@ class Problem:
     window: Optional[Tuple[int, int]] = None              # loss window (n0, n1]
     cpml: dict = dataclasses.field(default_factory=lambda: dict(
         m=3.0, sigma_max=0.0, kappa_max=1.0, alpha_max=0.0, m_alpha=1.0))
+    rho: Optional[np.ndarray] = None  # mass density (kg/m^3), for absorption rates
 
     @property
     def cells(self) -> int:
@@ -250,6 +251,48 @@ def adjoint2d(n: int = 1024, steps: int = 4000, seed: int = 0,
                       dtype=np.int32)
     return Problem("adjoint2d_%dx%d" % shape, 2, shape, dx, dt, steps, pml, eps,
                    None, None, src, probes, design=design, window=(steps // 2, steps))
+
+
+def layered2d(n: int = 400, steps: int = 4000, seed: int = 0, ny: Optional[int] = None,
+              npml: int = 12, f0: float = 6.8e9, nprobes: int = 4) -> Problem:
+    """2D TMz layered lossy medium of the shape of the paper's tissue case
+    (Sec. V-B: air over a thin, a thick and a semi-infinite layer, a pulsed
+    point source above the first layer, 20 cells per shortest wavelength,
+    Courant number 0.95).  The layer properties are synthetic draws from
+    broad tissue-like ranges, not measured data: thin layer eps_r U[25, 45],
+    sigma U[1, 5] S/m; thick layer eps_r U[3, 8], sigma U[0.05, 0.5];
+    last layer eps_r U[35, 55], sigma U[2, 8]; density U[900, 1150] kg/m^3
+    per layer (air: 1.2).  Layers run along x (rows): air to 30 % of the
+    rows, the thin layer 4 %, the thick one 30 %, the last to the end.
+    Source: modulated Gaussian at f0 (tau = 1/f0, t0 = 4 tau), 8 % of the
+    rows above the first layer, mid column; probes on that column."""
+    rng = np.random.default_rng(seed)
+    ny = n if ny is None else ny
+    shape = (n, ny)
+    pml = (npml,) * 4
+    props = [(1.0, 0.0, 1.2),
+             (float(rng.uniform(25, 45)), float(rng.uniform(1, 5)), float(rng.uniform(900, 1150))),
+             (float(rng.uniform(3, 8)), float(rng.uniform(0.05, 0.5)), float(rng.uniform(900, 1150))),
+             (float(rng.uniform(35, 55)), float(rng.uniform(2, 8)), float(rng.uniform(900, 1150)))]
+    edges = [0, int(0.30 * n), int(0.34 * n), int(0.64 * n), n]
+    eps = np.ones(shape, np.float32)
+    sig = np.zeros(shape, np.float32)
+    rho = np.ones(shape, np.float32)
+    for (er, sg, rh), a, b in zip(props, edges[:-1], edges[1:]):
+        eps[a:b] = er
+        sig[a:b] = sg
+        rho[a:b] = rh
+    h = C0 / (f0 * math.sqrt(max(p[0] for p in props)) * 20)
+    dx = (h, h)
+    dt = courant_dt(0.95 / math.sqrt(2.0), dx)
+    tau = 1.0 / f0
+    src = Source((max(npml + 1, edges[1] - int(0.08 * n)), ny // 2), SRC_MODGAUSS, (1.0, 4 * tau, tau, f0))
+    rows = np.linspace(edges[1] + 1, n - npml - 2, nprobes).astype(np.int32)
+    probes = np.array([(int(r), ny // 2) for r in rows], dtype=np.int32)
+    pb = Problem("layered2d_%dx%d" % shape, 2, shape, dx, dt, steps, pml, eps, sig, None, src, probes)
+    pb.rho = rho
+    pb.cpml = dict(m=3.0, sigma_max=0.0, kappa_max=1.0, alpha_max=0.0, m_alpha=1.0)
+    return pb
 
 
 def freespace2d(n: int, steps: int = 1024, npml: int = 16) -> Problem:

@@ -451,6 +451,50 @@ def test_dft_monitor_rules():
     s.close()
 
 
+def test_sar_layered():
+    """Absorption rate in the layered lossy case (the paper's tissue setup,
+    Sec. V-B, with synthetic layer properties) from the GPU monitor against
+    the oracle's, sigma |X|^2 / (2 rho norm^2) per frequency, without and
+    with a source-spectrum norm; zero in the lossless air rows; the rules."""
+    from paper_2405_00814_amd._lib import FdtdError
+    from paper_2405_00814_amd.sim import Sim
+    from oracle import oracle as O
+    pb = W.layered2d(160, ny=120, steps=600, seed=2)
+    f0 = pb.source.params[3]
+    freqs = [0.6 * f0, f0, 1.4 * f0]
+    lo, hi = (30, 20), (140, 100)
+    box = (slice(lo[0], hi[0]), slice(lo[1], hi[1]))
+    o = O.for_problem(pb)
+    o.set_dft("ez", lo, hi, freqs)
+    o.run(pb.steps)
+    air = pb.sigma[box] == 0
+    assert air.any() and (~air).any()
+    for kernel in (None, (2, (1, 4)), (1,)):
+        s = Sim.from_problem(pb)
+        if kernel is not None:
+            s.set_kernel(*kernel)
+        s.set_dft("ez", lo, hi, freqs)
+        s.step(pb.steps)
+        for nm in (None, [2.0, 0.5, 3.0]):
+            got = s.dft_sar(pb.rho[box], nm)
+            ref = O.sar(o.dft["X"], pb.sigma[box], pb.rho[box], nm)
+            e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            log("sar", kernel, nm, "rel-L2 %.2e" % e, "max %.3e" % ref.max())
+            assert e <= TOL, (kernel, nm, e)
+            assert np.all(got[:, air] == 0) and got.max() > 0
+        with pytest.raises(FdtdError):
+            s.dft_sar(np.zeros_like(pb.rho[box]))            # rho must be > 0
+        with pytest.raises(FdtdError):
+            s.dft_sar(pb.rho[box], [1.0, -1.0, 1.0])         # norm must be > 0
+        s.set_dft("hx", lo, hi, freqs)
+        with pytest.raises(FdtdError):
+            s.dft_sar(pb.rho[box])                            # an H monitor
+        s.set_dft("ez", lo, hi, [])
+        with pytest.raises(FdtdError):
+            s.dft_sar(np.zeros(0, np.float32))                # no monitor
+        s.close()
+
+
 def test_split_field_pml():
     """The paper's split-field PML (Sec. III-C): the reference kernels and the
     4-nodes-per-cell explicit graph against the split-field oracle; the

@@ -152,6 +152,37 @@ def test_dft_monitor_closed_form_cavity_mode(orc):
     assert mags[0] > 5 * max(mags[1:])
 
 
+def test_sar_parseval_joule_energy(orc):
+    """Absorption rate from the monitor's sums against the Joule energy
+    counted in the time domain (Parseval): over N steps with the N frequencies
+    f_k = k / (N dt), sum_n sigma E_n^2 dt = (2 rho / (N dt)) sum_k SAR_k at
+    every cell, since sum_k |X_k|^2 = N dt^2 sum_n E_n^2 for X_k = dt sum_n
+    E_n exp(-2 pi i f_k t_n).  The layers vary along x only, so a transposed
+    cell index, a dropped 1/2, rho or dt fails it."""
+    pb = W.layered2d(56, ny=40, steps=48, seed=3, npml=6)
+    N = pb.steps
+    o = orc.for_problem(pb)
+    o.set_source(pb.source.cell, pb.source.kind, pb.source.params)
+    lo, hi = (10, 4), (50, 36)
+    box = (slice(lo[0], hi[0]), slice(lo[1], hi[1]))
+    o.set_dft("ez", lo, hi, [k / (N * pb.dt) for k in range(N)])
+    sig = pb.sigma[box].astype(np.float64)
+    rho = pb.rho[box].astype(np.float64)
+    joule = np.zeros(sig.shape)
+    for _ in range(N):
+        o.run(1)
+        joule += sig * o.ez[box] ** 2 * pb.dt
+    sar = orc.sar(o.dft["X"], sig, rho)
+    freq = 2.0 * rho / (N * pb.dt) * sar.sum(axis=0)
+    assert np.abs(joule).max() > 0 and (sig == 0).any() and (sig > 0).any()
+    assert np.abs(freq - joule).max() <= 1e-9 * np.abs(joule).max()
+    # the balance is sensitive: sigma of the mirrored rows (a wrong index)
+    # or without the 1/2 it fails
+    bad = 2.0 * rho / (N * pb.dt) * orc.sar(o.dft["X"], sig[::-1], rho).sum(axis=0)
+    assert np.abs(bad - joule).max() > 1e-3 * np.abs(joule).max()
+    assert np.abs(2.0 * freq - joule).max() > 1e-3 * np.abs(joule).max()
+
+
 def test_cavity_recurrence_lossy_2d(orc):
     """Homogeneous lossy medium: a mode obeys
     e^{n+1} = (1 + Ca - Cb Db L) e^n - Ca e^{n-1}, with Ca = A-/A+ and
