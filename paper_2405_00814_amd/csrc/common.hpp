@@ -249,15 +249,26 @@ bool wave3d_supported(int nx, int ny, int nz, const Fused3DCfg &c);
 
 hipError_t launch_nonfinite(const float *a, int64_t n, int *flag, hipStream_t st);
 
-// Frequency-domain monitor (dft.hip): acc[2q][c] += f[idx[c]] re[q],
-// acc[2q+1][c] += f[idx[c]] im[q] for the nf <= kDftMaxFreq frequencies (acc
-// rows of npts doubles).
+// Frequency-domain monitor (dft.hip).  After each step launch_dft_gather
+// copies the monitored cells' samples into one row of a ring of kDftBatch
+// rows (cells of the box of a row-major grid, or through an index list);
+// launch_dft_flush then adds, for the nk <= kDftBatch buffered steps,
+// sum_k row_k[c] re[k][q] to acc[2q][c] and sum_k row_k[c] im[k][q] to
+// acc[2q+1][c] (nf <= kDftMaxFreq frequencies, acc rows of npts doubles).
 constexpr int kDftMaxFreq = 16;
-struct DftPhase {
-    double re[kDftMaxFreq], im[kDftMaxFreq];
+constexpr int kDftBatch = 8;
+struct DftPhases {
+    double re[kDftBatch][kDftMaxFreq], im[kDftBatch][kDftMaxFreq];
 };
-hipError_t launch_dft(const float *f, const int64_t *idx, int64_t npts, int nf, const DftPhase &ph, double *acc,
-                      hipStream_t st);
+struct DftBox {
+    int i0, j0, k0;  // box origin
+    int nj, nk;      // box extents along y and z
+    int ny, nz;      // grid extents along y and z
+};
+hipError_t launch_dft_gather(const float *f, const int64_t *idx, const DftBox &box, int64_t npts, float *row,
+                             hipStream_t st);
+hipError_t launch_dft_flush(const float *ring, int64_t npts, int nk, int nf, const DftPhases &ph, double *acc,
+                            hipStream_t st);
 // Specific absorption rate from a monitor's sums: out[q][c] = sig[c] |X_qc|^2
 // * inv2n2[q] / rho[c] (inv2n2 = 1 / (2 norm_q^2)), in FP64, stored FP32.
 struct SarScale {

@@ -1,28 +1,63 @@
 // Frequency-domain monitor: running discrete Fourier transform of one field
-// component at a list of cells, fed after every step (the paper motivates
-// frequency-domain responses, Sec. I, without a formulation).  One thread per
-// cell; the step's phase factors arrive by value, so the kernel reads the
-// field once and updates its FP64 sums.
+// component at a box of cells, fed after every step (the paper motivates
+// frequency-domain responses, Sec. I, without a formulation).  The FP64 sums
+// cost 16 B of reads and writes per frequency and update, so the samples of
+// kDftBatch steps are first gathered into a ring (8 B per cell and step:
+// one read, one write) and the sums updated once per batch with the
+// buffered steps' phase factors, passed by value: per cell and step about
+// 4 + 32 nf / kDftBatch bytes instead of 4 + 32 nf.  One thread per cell.
 #include "common.hpp"
 
 namespace gem {
 
-__global__ __launch_bounds__(256) void k_dft(const float *__restrict__ f, const int64_t *__restrict__ idx,
-                                             int64_t npts, int nf, DftPhase ph, double *__restrict__ acc) {
+__global__ __launch_bounds__(256) void k_dft_gather(const float *__restrict__ f, const int64_t *__restrict__ idx,
+                                                    DftBox b, int64_t npts, float *__restrict__ row) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= npts) return;
-    const double v = f[idx[c]];
+    int64_t g;
+    if (idx) {
+        g = idx[c];
+    } else {
+        const int64_t k = c % b.nk, r = c / b.nk;
+        const int64_t j = r % b.nj, i = r / b.nj;
+        g = ((b.i0 + i) * b.ny + (b.j0 + j)) * b.nz + (b.k0 + k);
+    }
+    row[c] = f[g];
+}
+
+__global__ __launch_bounds__(256) void k_dft_flush(const float *__restrict__ ring, int64_t npts, int nk, int nf,
+                                                   DftPhases ph, double *__restrict__ acc) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= npts) return;
+    double v[kDftBatch];
+#pragma unroll
+    for (int k = 0; k < kDftBatch; ++k) v[k] = k < nk ? (double)ring[k * npts + c] : 0.0;
     for (int q = 0; q < nf; ++q) {
-        acc[(2 * q) * npts + c] += v * ph.re[q];
-        acc[(2 * q + 1) * npts + c] += v * ph.im[q];
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int k = 0; k < kDftBatch; ++k) {
+            re += v[k] * ph.re[k][q];
+            im += v[k] * ph.im[k][q];
+        }
+        acc[(2 * q) * npts + c] += re;
+        acc[(2 * q + 1) * npts + c] += im;
     }
 }
 
-hipError_t launch_dft(const float *f, const int64_t *idx, int64_t npts, int nf, const DftPhase &ph, double *acc,
-                      hipStream_t st) {
+hipError_t launch_dft_gather(const float *f, const int64_t *idx, const DftBox &box, int64_t npts, float *row,
+                             hipStream_t st) {
     if (npts <= 0) return hipSuccess;
-    if (nf < 1 || nf > kDftMaxFreq) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dft, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, f, idx, npts, nf, ph, acc);
+    if (!idx && (box.nj < 1 || box.nk < 1)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dft_gather, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, f, idx, box, npts, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_flush(const float *ring, int64_t npts, int nk, int nf, const DftPhases &ph, double *acc,
+                            hipStream_t st) {
+    if (npts <= 0 || nk == 0) return hipSuccess;
+    if (nf < 1 || nf > kDftMaxFreq || nk < 0 || nk > kDftBatch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dft_flush, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, ring, npts, nk, nf, ph,
+                       acc);
     return hipGetLastError();
 }
 

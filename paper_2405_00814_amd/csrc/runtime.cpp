@@ -502,18 +502,33 @@ void Sim::launch_tb2d(int64_t step, const CapArgs *cap) {
 // After step `step` (state step+1): the monitor's sums gain the field
 // sample times exp(-2 pi i f t) dt, t = (step+1) dt for E and (step+1/2) dt
 // for H (the sample's time on the leapfrog grid).
+// The sample goes to the next row of the ring with its phase factors; a
+// full ring is summed.
 void Sim::dft_accumulate(int64_t step) {
-    DftPhase ph{};
+    const int r = dft.nbuf;
     const double t = ((double)step + (dft.comp >= FDTD_HX ? 0.5 : 1.0)) * dt;
     for (int q = 0; q < dft.nf; ++q) {
         const double a = 2.0 * kPi * dft.f[q] * t;
-        ph.re[q] = std::cos(a) * dt;
-        ph.im[q] = -std::sin(a) * dt;
+        dft.pend.re[r][q] = std::cos(a) * dt;
+        dft.pend.im[r][q] = -std::sin(a) * dt;
     }
     const float *fld = is_graph ? g.x : f[cur][dft.comp];
-    hip_check(launch_dft(fld, dft.idx, dft.npts, dft.nf, ph, dft.acc, st), "dft");
+    const DftBox box{dft.box[0], dft.box[2], dft.box[4], dft.box[3] - dft.box[2], dft.box[5] - dft.box[4], ny, nz};
+    hip_check(launch_dft_gather(fld, dft.idx, box, dft.npts, dft.ring + (int64_t)r * dft.npts, st), "dft");
+    dft.nbuf = r + 1;
     dft.nacc += 1;
     last_launches += 1;
+    if (dft.nbuf == kDftBatch) {
+        dft_flush();
+        last_launches += 1;
+    }
+}
+
+// Sum the buffered samples into the monitor's FP64 sums.
+void Sim::dft_flush() {
+    if (dft.comp < 0 || dft.nbuf == 0) return;
+    hip_check(launch_dft_flush(dft.ring, dft.npts, dft.nbuf, dft.nf, dft.pend, dft.acc, st), "dft sums");
+    dft.nbuf = 0;
 }
 
 void Sim::launch_step(int64_t step) {
@@ -651,6 +666,7 @@ void Sim::zero_state() {
     if (is_graph && g.x) hip_check(hipMemsetAsync(g.x, 0, (size_t)g.nnodes * 4, st), "memset");
     if (dft.acc) hip_check(hipMemsetAsync(dft.acc, 0, (size_t)(2 * dft.nf * dft.npts) * 8, st), "memset");
     dft.nacc = 0;
+    dft.nbuf = 0;
     if (ezy) hip_check(hipMemsetAsync(ezy, 0, (size_t)ncell * 4, st), "memset");
     cur = 0;
     n_done = 0;
@@ -1334,6 +1350,7 @@ int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t 
     hip_check(hipStreamSynchronize(s.st), "sync");
     s.al.put(s.dft.idx);
     s.al.put(s.dft.acc);
+    s.al.put(s.dft.ring);
     s.dft = Sim::Dft{};
     if (nf == 0) return FDTD_OK;
     Sim::Dft &d = s.dft;
@@ -1342,14 +1359,15 @@ int fdtd_set_dft(fdtd_sim *sim, int component, const int32_t *lo, const int32_t 
     for (int q = 0; q < nf; ++q) d.f[q] = freqs[q];
     const int b[6] = {lo[0], hi[0], lo[1], hi[1], s.ndim == 3 ? lo[2] : 0, s.ndim == 3 ? hi[2] : 1};
     for (int q = 0; q < 6; ++q) d.box[q] = b[q];
-    std::vector<int64_t> idx;
-    for (int i = b[0]; i < b[1]; ++i)
-        for (int j = b[2]; j < b[3]; ++j)
-            for (int k = b[4]; k < b[5]; ++k)
-                idx.push_back(s.is_graph ? graph_node(s, component, i, j) : ((int64_t)i * s.ny + j) * s.nz + k);
-    d.npts = (int64_t)idx.size();
-    d.idx = dev_upload(s.al, idx.data(), idx.size(), s.st);
+    d.npts = (int64_t)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]);
+    if (s.is_graph) {  // the graph's node order is not the box's: an index list
+        std::vector<int64_t> idx;
+        for (int i = b[0]; i < b[1]; ++i)
+            for (int j = b[2]; j < b[3]; ++j) idx.push_back(graph_node(s, component, i, j));
+        d.idx = dev_upload(s.al, idx.data(), idx.size(), s.st);
+    }
     d.acc = (double *)s.al.get((size_t)(2 * nf * d.npts) * 8);  // zero-filled
+    d.ring = (float *)s.al.get((size_t)(kDftBatch * d.npts) * 4);
     hip_check(hipStreamSynchronize(s.st), "sync");
     return FDTD_OK;
     GEM_CATCH
@@ -1364,6 +1382,7 @@ int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps) {
     if (nsteps) *nsteps = d.nacc;
     if (!re && !im) return FDTD_OK;
     if (!re || !im) fail(FDTD_EINVAL, "re and im must both be given");
+    s.dft_flush();
     std::vector<double> h((size_t)(2 * d.nf * d.npts));
     hip_check(hipMemcpyAsync(h.data(), d.acc, h.size() * 8, hipMemcpyDeviceToHost, s.st), "dft copy");
     hip_check(hipStreamSynchronize(s.st), "sync");
@@ -1397,6 +1416,7 @@ int fdtd_dft_sar(fdtd_sim *sim, const float *rho, const double *norm, float *sar
                 if (!std::isfinite(rho[c]) || rho[c] <= 0) fail(FDTD_EINVAL, "rho must be finite and > 0");
                 if (!s.sigma.empty()) sg[(size_t)c] = s.sigma[(size_t)(((int64_t)i * s.ny + j) * s.nz + k)];
             }
+    s.dft_flush();
     const size_t nb = (size_t)d.npts * 4;
     float *dsg = (float *)s.al.get(nb), *drho = (float *)s.al.get(nb), *dout = (float *)s.al.get(nb * d.nf);
     struct Put {

@@ -184,10 +184,14 @@ struct Sim {
         int box[6] = {0, 0, 0, 0, 0, 0};
         double f[kDftMaxFreq] = {};
         int64_t npts = 0, nacc = 0;
-        int64_t *idx = nullptr;  // device: field-array index of each cell
+        int64_t *idx = nullptr;  // device: node index of each cell (graph form; else the box)
         double *acc = nullptr;   // device: [2 nf][npts]
+        float *ring = nullptr;   // device: [kDftBatch][npts] samples not yet summed
+        int nbuf = 0;            // rows of the ring in use
+        DftPhases pend{};        // their phase factors
     } dft;
     void dft_accumulate(int64_t step);
+    void dft_flush();
     void records_to_host(float *out, int64_t ld, int64_t m);
     void split_check() const;
     void launch_tb2d(int64_t step, const CapArgs *cap = nullptr);

@@ -449,6 +449,22 @@ def test_dft_monitor_rules():
         s.get_dft()
     s.step_profile(4)
     s.close()
+    # samples are summed in batches of steps: reading the sums between
+    # uneven chunks (partial batches) gives the sums of one run
+    st0 = np.random.default_rng(1).standard_normal(pb.shape).astype(np.float32)
+    out = []
+    for chunks in ((37,), (5, 13, 19), (1, 7, 8, 21)):
+        s = Sim.from_problem(pb)
+        s.set_field("ez", st0)
+        s.set_dft("hy", (1, 3), (40, 44), [0.7e9, 3e9, 0.0])
+        for c in chunks:
+            s.step(c)
+            X, n = s.get_dft()
+        assert n == 37
+        out.append(X)
+        s.close()
+    for X in out[1:]:
+        assert np.abs(X - out[0]).max() <= 1e-12 * np.abs(out[0]).max()
 
 
 def test_sar_layered():
