@@ -10,7 +10,7 @@
 //    probes recorded exactly on the second pass's cells;
 //  * 2D multi-step plan: the tiles' own rows and columns cover the grid
 //    once; interior tiles' cones (TB rows and the halo lanes' columns around
-//    them) clear of the slabs.
+//    them) clear of the slabs; the default row chunk at measured grids.
 #include <cstdio>
 #include <algorithm>
 #include <cstdlib>
@@ -191,6 +191,16 @@ int main() {
     for (const auto &c : sup)
         if (two3d_supported(8, 8, c.nz, c.lo, c.hi) != c.ok) {
             printf("two3d_supported(%d, %d, %d) wrong\n", c.nz, c.lo, c.hi);
+            ++bad;
+        }
+    // default row chunk of the 2D four-step pass on 256 CUs, at the grids it
+    // was measured on (V = 2: the chunk whose interior workgroups number 4-5
+    // per CU, else 8; V = 1: the longest with 2 per CU, else 4)
+    const struct { int n, V, tx; } dtx[] = {
+        {4096, 2, 32}, {3072, 2, 16}, {6400, 2, 8}, {2048, 2, 8}, {2048, 1, 16}, {1448, 1, 16}, {1024, 1, 8}, {256, 1, 4}};
+    for (const auto &c : dtx)
+        if (tb2d_default_tx(c.n, c.n, c.V, 256) != c.tx) {
+            printf("tb2d_default_tx(%d, V %d) = %d, expected %d\n", c.n, c.V, tb2d_default_tx(c.n, c.n, c.V, 256), c.tx);
             ++bad;
         }
     srand(1);
