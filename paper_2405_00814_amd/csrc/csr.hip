@@ -9,7 +9,10 @@ namespace gem {
 // One wavefront per 64 consecutive rows.  Its edge range [rowptr[r0],
 // rowptr[r0 + 64]) is staged in LDS by coalesced loads; each lane then sums
 // its row from LDS in edge order (a segment longer than the staging space
-// reads memory directly, same order).
+// reads memory directly, same order).  A row of at most 8 edges (every row
+// of the FDTD graphs) issues all its gathers before the first product, so
+// they are in flight together instead of one per loop trip (4096^2 TMz
+// graph: 24.6 -> 29.1 Gcell/s); the sum keeps the edge order.
 constexpr int kCsrCap = 512;  // staged edges per wavefront
 
 __global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowptr,
@@ -41,8 +44,19 @@ __global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowpt
     __syncthreads();
     if (!live || r >= nrows) return;
     float acc = 0.f;
-    if (n <= kCsrCap) {
-        for (int q = b - b0; q < e - b0; ++q) acc += sw[wv][q] * x[sc[wv][q]];
+    if (n <= kCsrCap && e - b <= 8) {
+        const int q0 = b - b0, len = e - b;
+        float wq[8], xq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            wq[u] = u < len ? sw[wv][q0 + u] : 0.f;
+            xq[u] = u < len ? x[sc[wv][q0 + u]] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u < len) acc += wq[u] * xq[u];
+    } else if (n <= kCsrCap) {
+        for (int q = b - b0; q < e - b0; ++q) acc += sw[wv][q] * x[sc[wv][q]];  // longer rows (none in the graphs built here)
     } else {
         for (int q = b; q < e; ++q) acc += w[q] * x[col[q]];
     }
