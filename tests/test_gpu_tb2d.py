@@ -86,6 +86,29 @@ def test_tb2d_cpml_tiles_on_second_stream():
         assert np.array_equal(rec, runs[1][1])
 
 
+def test_tb2d_forked_pass_on_a_torch_stream():
+    """The second stream forks from and joins to the simulation's stream,
+    whichever it is: on a non-default torch stream the forked passes, in
+    uneven chunks, give the bits of the default stream."""
+    import torch
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.dielectric2d(700, ny=600, steps=201, seed=8, nrect=10, side=(8, 48), npml=16, nprobes=5)
+    kernel = (3, (2, 32, 4, 8))
+    got, rec, _ = run_gpu(pb, pb.steps, kernel)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = Sim.from_problem(pb)
+        s.set_kernel(*kernel)
+        for c in (60, 141):
+            s.step(c)
+        f = {k: s.get_field(k) for k in got}
+        r = s.probe()
+        s.close()
+    for k in got:
+        assert np.array_equal(f[k], got[k]), k
+    assert np.array_equal(r, rec)
+
+
 def test_tb2d_cavity_full_config():
     pb = W.cavity2d(128, steps=1000, seed=0)
     ref, rrec = run_oracle(pb, pb.steps)
