@@ -76,6 +76,7 @@ _SIGS = {
     "fdtd_set_probes": (C.c_int, [P, C.c_int, i32p, i32]),
     "fdtd_step": (C.c_int, [P, i64]),
     "fdtd_probe": (C.c_int, [P, f32p, i64, i64p]),
+    "fdtd_probe_noalloc": (C.c_int, [P, f32p, i64, i64p]),
     "fdtd_get_field": (C.c_int, [P, C.c_int, P, C.c_int]),
     "fdtd_set_field": (C.c_int, [P, C.c_int, P, C.c_int]),
     "fdtd_reset": (C.c_int, [P]),
@@ -120,10 +121,19 @@ def open_library(path: str):
 
 
 def load():
-    """The process-wide library handle (raises if it has not been built)."""
+    """The process-wide library handle (raises if it has not been built).
+
+    torch is imported first when it is installed: the library and torch then
+    share torch's HIP runtime, whichever of the two the caller touches first
+    (with the library loaded first, torch's device initialisation afterwards
+    left the library's HIP calls without a device)."""
     global _L
     with _lock:
         if _L is None:
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             _L = open_library(LIBPATH)
     return _L
 
