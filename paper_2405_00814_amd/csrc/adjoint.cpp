@@ -82,7 +82,9 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
             fail(FDTD_EINVAL, "invalid design box");
         if (s.probe_cells.empty() || s.probe_comp != FDTD_EZ)
             fail(FDTD_EINVAL, "the loss needs Ez probes (fdtd_set_probes)");
-        const int64_t L = ckpt_interval > 0 ? ckpt_interval : (int64_t)std::ceil(std::sqrt((double)T));
+        // an interval beyond T is one segment of T steps
+        const int64_t L = std::min<int64_t>(T, ckpt_interval > 0 ? ckpt_interval
+                                                                 : (int64_t)std::ceil(std::sqrt((double)T)));
         const int64_t nseg = (T + L - 1) / L;
         const int64_t nd = (int64_t)(i1 - i0) * (j1 - j0);
         const int64_t P = (int64_t)s.probe_cells.size();

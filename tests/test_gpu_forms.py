@@ -161,7 +161,9 @@ def test_adjoint_checkpoint_intervals_same_bits(kernel):
     from paper_2405_00814_amd.sim import Sim
     pb = _adjoint_case(n=72, T=203, lossy=True)
     out = []
-    for ckpt in (0, 1, 7, 64, pb.steps, pb.steps + 5):
+    # 2**31 - 1: an interval far beyond T is clamped to one segment of T
+    # steps (no oversized design buffers)
+    for ckpt in (0, 1, 7, 64, pb.steps, pb.steps + 5, 2 ** 31 - 1):
         s = Sim.from_problem(pb)
         if kernel is not None:
             s.set_kernel(*kernel)
