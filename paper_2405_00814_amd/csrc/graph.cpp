@@ -27,6 +27,8 @@ struct RowBuilder {
     std::vector<int> rowptr{0}, col, dst;
     std::vector<float> w;
     void edge(int64_t c, double v) {
+        // row pointers are int32: a layer holds fewer than 2^31 nonzeros
+        if (col.size() >= (size_t)INT32_MAX) fail(FDTD_EINVAL, "graph layer has 2^31 or more nonzeros");
         col.push_back((int)c);
         w.push_back((float)v);
     }
@@ -156,6 +158,20 @@ static void build_graph_split(Sim &s) {
     s.al.put(s.ezy);
     s.ezy = nullptr;
     hip_check(hipStreamSynchronize(s.st), "sync");
+}
+
+// Nonzeros of the largest layer of the explicit graph of an nx x ny grid
+// with sx / sy CPML cells across the x / y slabs (both faces together), an
+// upper bound for the E layer and exact for the H layer's field rows, which
+// are the largest: non-split, Hx gathers itself, Ez(i,j), Ez(i,j+1) below
+// the last row and its psi in a y slab, Hy likewise along x; split, each H
+// node gathers both Ez parts of its two E neighbours.
+int64_t graph_layer_nnz_max(int nx, int ny, int sx, int sy, bool split) {
+    const int64_t N = (int64_t)nx * ny;
+    const int64_t h = split ? 6 * N + 2LL * nx * (ny - 1) + 2LL * ny * (nx - 1)
+                            : 4 * N + (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1) + (int64_t)nx * sy + (int64_t)ny * sx;
+    const int64_t e = (split ? 6 : 7) * N;
+    return std::max(h, e);
 }
 
 void build_graph(Sim &s) {

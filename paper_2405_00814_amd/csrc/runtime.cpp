@@ -1019,6 +1019,18 @@ int fdtd_create_graph(const fdtd_desc *desc, fdtd_sim **out) {
     fdtd_sim *h = nullptr;
     GEM_TRY
     if (desc && desc->ndim != 2) fail(FDTD_EINVAL, "the explicit graph form supports ndim 2 only");
+    validate_desc(desc);
+    {
+        // size check before any device work: node and nonzero counts of the
+        // graph fit its int32 indices
+        const int sx = desc->cpml.npml[0] + desc->cpml.npml[1], sy = desc->cpml.npml[2] + desc->cpml.npml[3];
+        const int64_t N = (int64_t)desc->nx * desc->ny;
+        const bool split = desc->cpml.split == 1;
+        const int64_t nodes = split ? 4 * N : 3 * N + 2LL * desc->nx * sy + 2LL * desc->ny * sx;
+        if (nodes >= ((int64_t)1 << 31)) fail(FDTD_EINVAL, "graph too large for 32-bit node indices");
+        if (graph_layer_nnz_max(desc->nx, desc->ny, sx, sy, split) >= (int64_t)INT32_MAX)
+            fail(FDTD_EINVAL, "graph too large: a layer would hold 2^31 or more nonzeros (int32 row pointers)");
+    }
     h = new fdtd_sim();
     init_sim(h->s, desc);
     h->s.is_graph = true;

@@ -210,6 +210,8 @@ void graph_set_source_probes(Sim &s);
 int64_t graph_node(const Sim &s, int comp, int i, int j);
 void graph_get_field(Sim &s, int comp, float *host);
 void graph_set_field(Sim &s, int comp, const float *host);
+// nonzeros of the largest layer (graph.cpp); the row pointers are int32
+int64_t graph_layer_nnz_max(int nx, int ny, int sx, int sy, bool split);
 
 // default single-step 2D tiles for a grid, and the default kernel
 // configuration of a simulation (runtime.cpp)

@@ -84,3 +84,26 @@ def test_null_arguments():
     assert L.fdtd_destroy(None) == 0
     assert L.fdtd_step(None, 1) == -1
     assert L.fdtd_probe(None, None, 0, None) == -1
+
+
+@pytest.mark.parametrize("n,npml,split", [(19000, 16, 0), (15000, 16, 1)])
+def test_graph_size_guard(n, npml, split):
+    """The explicit graph's row pointers and columns are int32: a grid whose
+    largest layer would hold 2^31 or more nonzeros (19000^2 cells: about 6
+    per cell in the H layer; split-field 15000^2: about 10) is refused with
+    FDTD_EINVAL before any device work or host-side graph construction,
+    although its node count fits."""
+    from paper_2405_00814_amd import _lib
+    from paper_2405_00814_amd.sim import make_desc
+    h = 1e-3
+    dt = 0.9 / math.sqrt(2) * h / 299792458.0
+    cells = n * n
+    assert (4 if split else 3) * cells < 2 ** 31  # nodes fit
+    d, keep = make_desc((n, n), (h, h), dt, npml=(npml,) * 4, cpml=dict(split=split), stream=0,
+                        allocator=False)
+    out = C.c_void_p()
+    L = _lib.load()
+    rc = L.fdtd_create_graph(C.byref(d), C.byref(out))
+    assert rc == -1 and not out.value
+    assert b"nonzeros" in L.fdtd_last_error()
+
