@@ -208,6 +208,19 @@ int fdtd_step(fdtd_sim *sim, int64_t n);
  * the probes were set.  Synchronises.  out may be NULL to query. */
 int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
 
+/* fdtd_probe for callers that cannot allocate device memory (code running
+ * while other streams capture a HIP graph, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, result and synchronisation as
+ * fdtd_probe, but the records are packed in a fixed device array of the
+ * library (16 MiB per device, held until the process ends) instead of a
+ * block allocated per call, and no device memory is allocated or freed.
+ * Limit: probes x min(cap, recorded) <= 4194304 floats, else FDTD_EINVAL
+ * (nothing copied; read in several calls or use fdtd_probe).  All calls on
+ * one device share that array: calls that overlap on one device (from
+ * several threads, or on several streams) race and must be serialised by
+ * the caller. */
+int fdtd_probe_noalloc(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
+
 /* Copy one component (nx*ny*nz float32, same layout as the maps) to dst.
  * dst_on_device != 0: dst is device memory, the copy is enqueued on the
  * stream; else host memory and the call synchronises. */

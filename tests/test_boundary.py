@@ -107,3 +107,8 @@ def test_graph_size_guard(n, npml, split):
     assert rc == -1 and not out.value
     assert b"nonzeros" in L.fdtd_last_error()
 
+
+def test_noalloc_probe_rejects_null():
+    from paper_2405_00814_amd import _lib
+    L = _lib.load()
+    assert L.fdtd_probe_noalloc(None, None, 0, None) == -1
