@@ -184,6 +184,12 @@ typedef struct {
 #define P_BH(p, n, i) ((p)[3 * (n) + (i)])
 #define P_CH(p, n, i) ((p)[4 * (n) + (i)])
 #define P_KH(p, n, i) ((p)[5 * (n) + (i)])
+/* The CPML auxiliary value psi of a difference along an axis exists only in
+ * that axis's absorbing layer: elsewhere b = 1 and c = 0, so a psi that
+ * starts at zero stays zero and adds nothing.  The updates below touch psi
+ * only where the profile is not (b, c) = (1, 0) and use 0 elsewhere. */
+#define IN_LAYER_E(p, n, i) (P_BE(p, n, i) != 1.0 || P_CE(p, n, i) != 0.0)
+#define IN_LAYER_H(p, n, i) (P_BH(p, n, i) != 1.0 || P_CH(p, n, i) != 0.0)
 
 /* H layer: messages from the E nodes to Hx, Hy (Eq. 8-9, TMz form). */
 void orc2d_h_layer(const orc2d_t *s)
@@ -198,10 +204,17 @@ void orc2d_h_layer(const orc2d_t *s)
             double ex1 = (i + 1 < nx) ? s->ez[c + ny] : 0.0;
             double dey = (ey1 - e0) / s->dy;
             double dex = (ex1 - e0) / s->dx;
-            s->psi_hx[c] = P_BH(s->prof_y, ny, j) * s->psi_hx[c] + P_CH(s->prof_y, ny, j) * dey;
-            s->hx[c] -= s->db[c] * (dey * P_KH(s->prof_y, ny, j) + s->psi_hx[c]);
-            s->psi_hy[c] = P_BH(s->prof_x, nx, i) * s->psi_hy[c] + P_CH(s->prof_x, nx, i) * dex;
-            s->hy[c] += s->db[c] * (dex * P_KH(s->prof_x, nx, i) + s->psi_hy[c]);
+            double phx = 0.0, phy = 0.0; /* psi outside the absorbing layer: 0 */
+            if (IN_LAYER_H(s->prof_y, ny, j)) {
+                s->psi_hx[c] = P_BH(s->prof_y, ny, j) * s->psi_hx[c] + P_CH(s->prof_y, ny, j) * dey;
+                phx = s->psi_hx[c];
+            }
+            s->hx[c] -= s->db[c] * (dey * P_KH(s->prof_y, ny, j) + phx);
+            if (IN_LAYER_H(s->prof_x, nx, i)) {
+                s->psi_hy[c] = P_BH(s->prof_x, nx, i) * s->psi_hy[c] + P_CH(s->prof_x, nx, i) * dex;
+                phy = s->psi_hy[c];
+            }
+            s->hy[c] += s->db[c] * (dex * P_KH(s->prof_x, nx, i) + phy);
         }
     }
 }
@@ -217,10 +230,17 @@ void orc2d_e_layer(const orc2d_t *s, double *curl)
             long c = (long)i * ny + j;
             double dhy = (s->hy[c] - s->hy[c - ny]) / s->dx;
             double dhx = (s->hx[c] - s->hx[c - 1]) / s->dy;
-            s->psi_ezx[c] = P_BE(s->prof_x, nx, i) * s->psi_ezx[c] + P_CE(s->prof_x, nx, i) * dhy;
-            s->psi_ezy[c] = P_BE(s->prof_y, ny, j) * s->psi_ezy[c] + P_CE(s->prof_y, ny, j) * dhx;
+            double pex = 0.0, pey = 0.0; /* psi outside the absorbing layer: 0 */
+            if (IN_LAYER_E(s->prof_x, nx, i)) {
+                s->psi_ezx[c] = P_BE(s->prof_x, nx, i) * s->psi_ezx[c] + P_CE(s->prof_x, nx, i) * dhy;
+                pex = s->psi_ezx[c];
+            }
+            if (IN_LAYER_E(s->prof_y, ny, j)) {
+                s->psi_ezy[c] = P_BE(s->prof_y, ny, j) * s->psi_ezy[c] + P_CE(s->prof_y, ny, j) * dhx;
+                pey = s->psi_ezy[c];
+            }
             double br = dhy * P_KE(s->prof_x, nx, i) - dhx * P_KE(s->prof_y, ny, j)
-                      + s->psi_ezx[c] - s->psi_ezy[c];
+                      + pex - pey;
             if (curl) curl[c] = br;
             s->ez[c] = s->ca[c] * s->ez[c] + s->cb[c] * br;
         }
@@ -407,7 +427,9 @@ void orc3d_h_layer(const orc3d_t *s)
     const double *px = s->prof_x, *py = s->prof_y, *pz = s->prof_z;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nx; ++i) {
+        const int lx = IN_LAYER_H(px, nx, i);
         for (int j = 0; j < ny; ++j) {
+            const int ly = IN_LAYER_H(py, ny, j);
             for (int k = 0; k < nz; ++k) {
                 long c = i * sx + j * sy + k;
                 double ex0 = s->ex[c], ey0 = s->ey[c], ez0 = s->ez[c];
@@ -420,18 +442,32 @@ void orc3d_h_layer(const orc3d_t *s)
                 double dezdy = (ez_y - ez0) / s->dy, deydz = (ey_z - ey0) / s->dz;
                 double dexdz = (ex_z - ex0) / s->dz, dezdx = (ez_x - ez0) / s->dx;
                 double deydx = (ey_x - ey0) / s->dx, dexdy = (ex_y - ex0) / s->dy;
-                s->psi_hxy[c] = P_BH(py, ny, j) * s->psi_hxy[c] + P_CH(py, ny, j) * dezdy;
-                s->psi_hxz[c] = P_BH(pz, nz, k) * s->psi_hxz[c] + P_CH(pz, nz, k) * deydz;
-                s->hx[c] -= s->db[c] * (dezdy * P_KH(py, ny, j) + s->psi_hxy[c]
-                                        - deydz * P_KH(pz, nz, k) - s->psi_hxz[c]);
-                s->psi_hyz[c] = P_BH(pz, nz, k) * s->psi_hyz[c] + P_CH(pz, nz, k) * dexdz;
-                s->psi_hyx[c] = P_BH(px, nx, i) * s->psi_hyx[c] + P_CH(px, nx, i) * dezdx;
-                s->hy[c] -= s->db[c] * (dexdz * P_KH(pz, nz, k) + s->psi_hyz[c]
-                                        - dezdx * P_KH(px, nx, i) - s->psi_hyx[c]);
-                s->psi_hzx[c] = P_BH(px, nx, i) * s->psi_hzx[c] + P_CH(px, nx, i) * deydx;
-                s->psi_hzy[c] = P_BH(py, ny, j) * s->psi_hzy[c] + P_CH(py, ny, j) * dexdy;
-                s->hz[c] -= s->db[c] * (deydx * P_KH(px, nx, i) + s->psi_hzx[c]
-                                        - dexdy * P_KH(py, ny, j) - s->psi_hzy[c]);
+                /* psi outside the absorbing layer of its axis: 0 */
+                double pxy = 0.0, pxz = 0.0, pyz = 0.0, pyx = 0.0, pzx = 0.0, pzy = 0.0;
+                if (lx) {
+                    s->psi_hyx[c] = P_BH(px, nx, i) * s->psi_hyx[c] + P_CH(px, nx, i) * dezdx;
+                    s->psi_hzx[c] = P_BH(px, nx, i) * s->psi_hzx[c] + P_CH(px, nx, i) * deydx;
+                    pyx = s->psi_hyx[c];
+                    pzx = s->psi_hzx[c];
+                }
+                if (ly) {
+                    s->psi_hxy[c] = P_BH(py, ny, j) * s->psi_hxy[c] + P_CH(py, ny, j) * dezdy;
+                    s->psi_hzy[c] = P_BH(py, ny, j) * s->psi_hzy[c] + P_CH(py, ny, j) * dexdy;
+                    pxy = s->psi_hxy[c];
+                    pzy = s->psi_hzy[c];
+                }
+                if (IN_LAYER_H(pz, nz, k)) {
+                    s->psi_hxz[c] = P_BH(pz, nz, k) * s->psi_hxz[c] + P_CH(pz, nz, k) * deydz;
+                    s->psi_hyz[c] = P_BH(pz, nz, k) * s->psi_hyz[c] + P_CH(pz, nz, k) * dexdz;
+                    pxz = s->psi_hxz[c];
+                    pyz = s->psi_hyz[c];
+                }
+                s->hx[c] -= s->db[c] * (dezdy * P_KH(py, ny, j) + pxy
+                                        - deydz * P_KH(pz, nz, k) - pxz);
+                s->hy[c] -= s->db[c] * (dexdz * P_KH(pz, nz, k) + pyz
+                                        - dezdx * P_KH(px, nx, i) - pyx);
+                s->hz[c] -= s->db[c] * (deydx * P_KH(px, nx, i) + pzx
+                                        - dexdy * P_KH(py, ny, j) - pzy);
             }
         }
     }
@@ -444,35 +480,60 @@ void orc3d_e_layer(const orc3d_t *s)
     const double *px = s->prof_x, *py = s->prof_y, *pz = s->prof_z;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nx; ++i) {
+        const int lx = IN_LAYER_E(px, nx, i);
         for (int j = 0; j < ny; ++j) {
+            const int ly = IN_LAYER_E(py, ny, j);
             for (int k = 0; k < nz; ++k) {
                 long c = i * sx + j * sy + k;
+                const int lz = IN_LAYER_E(pz, nz, k);
+                /* psi outside the absorbing layer of its axis: 0 */
                 if (j >= 1 && k >= 1) {
                     double dhzdy = (s->hz[c] - s->hz[c - sy]) / s->dy;
                     double dhydz = (s->hy[c] - s->hy[c - 1]) / s->dz;
-                    s->psi_exy[c] = P_BE(py, ny, j) * s->psi_exy[c] + P_CE(py, ny, j) * dhzdy;
-                    s->psi_exz[c] = P_BE(pz, nz, k) * s->psi_exz[c] + P_CE(pz, nz, k) * dhydz;
+                    double qy = 0.0, qz = 0.0;
+                    if (ly) {
+                        s->psi_exy[c] = P_BE(py, ny, j) * s->psi_exy[c] + P_CE(py, ny, j) * dhzdy;
+                        qy = s->psi_exy[c];
+                    }
+                    if (lz) {
+                        s->psi_exz[c] = P_BE(pz, nz, k) * s->psi_exz[c] + P_CE(pz, nz, k) * dhydz;
+                        qz = s->psi_exz[c];
+                    }
                     s->ex[c] = s->ca[c] * s->ex[c]
-                             + s->cb[c] * (dhzdy * P_KE(py, ny, j) + s->psi_exy[c]
-                                           - dhydz * P_KE(pz, nz, k) - s->psi_exz[c]);
+                             + s->cb[c] * (dhzdy * P_KE(py, ny, j) + qy
+                                           - dhydz * P_KE(pz, nz, k) - qz);
                 }
                 if (i >= 1 && k >= 1) {
                     double dhxdz = (s->hx[c] - s->hx[c - 1]) / s->dz;
                     double dhzdx = (s->hz[c] - s->hz[c - sx]) / s->dx;
-                    s->psi_eyz[c] = P_BE(pz, nz, k) * s->psi_eyz[c] + P_CE(pz, nz, k) * dhxdz;
-                    s->psi_eyx[c] = P_BE(px, nx, i) * s->psi_eyx[c] + P_CE(px, nx, i) * dhzdx;
+                    double qz = 0.0, qx = 0.0;
+                    if (lz) {
+                        s->psi_eyz[c] = P_BE(pz, nz, k) * s->psi_eyz[c] + P_CE(pz, nz, k) * dhxdz;
+                        qz = s->psi_eyz[c];
+                    }
+                    if (lx) {
+                        s->psi_eyx[c] = P_BE(px, nx, i) * s->psi_eyx[c] + P_CE(px, nx, i) * dhzdx;
+                        qx = s->psi_eyx[c];
+                    }
                     s->ey[c] = s->ca[c] * s->ey[c]
-                             + s->cb[c] * (dhxdz * P_KE(pz, nz, k) + s->psi_eyz[c]
-                                           - dhzdx * P_KE(px, nx, i) - s->psi_eyx[c]);
+                             + s->cb[c] * (dhxdz * P_KE(pz, nz, k) + qz
+                                           - dhzdx * P_KE(px, nx, i) - qx);
                 }
                 if (i >= 1 && j >= 1) {
                     double dhydx = (s->hy[c] - s->hy[c - sx]) / s->dx;
                     double dhxdy = (s->hx[c] - s->hx[c - sy]) / s->dy;
-                    s->psi_ezx[c] = P_BE(px, nx, i) * s->psi_ezx[c] + P_CE(px, nx, i) * dhydx;
-                    s->psi_ezy[c] = P_BE(py, ny, j) * s->psi_ezy[c] + P_CE(py, ny, j) * dhxdy;
+                    double qx = 0.0, qy = 0.0;
+                    if (lx) {
+                        s->psi_ezx[c] = P_BE(px, nx, i) * s->psi_ezx[c] + P_CE(px, nx, i) * dhydx;
+                        qx = s->psi_ezx[c];
+                    }
+                    if (ly) {
+                        s->psi_ezy[c] = P_BE(py, ny, j) * s->psi_ezy[c] + P_CE(py, ny, j) * dhxdy;
+                        qy = s->psi_ezy[c];
+                    }
                     s->ez[c] = s->ca[c] * s->ez[c]
-                             + s->cb[c] * (dhydx * P_KE(px, nx, i) + s->psi_ezx[c]
-                                           - dhxdy * P_KE(py, ny, j) - s->psi_ezy[c]);
+                             + s->cb[c] * (dhydx * P_KE(px, nx, i) + qx
+                                           - dhxdy * P_KE(py, ny, j) - qy);
                 }
             }
         }

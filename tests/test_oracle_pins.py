@@ -24,6 +24,26 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def _random_state(o, rng):
+    """Random fields everywhere; each CPML psi value only inside the
+    absorbing layer of its difference axis (elsewhere it does not exist and
+    is zero), sampled at the E (integer) or H (half-integer) position."""
+    st = {n: rng.standard_normal(o.shape) for n in o.fields}
+    axes = "xyz"[:len(o.shape)]
+    named = {"psi_hx": ("h", "y"), "psi_hy": ("h", "x"), "psi_ezx": ("e", "x"), "psi_ezy": ("e", "y")}
+    for n in o.psis:
+        kind, axis = named[n] if len(o.shape) == 2 else (n[4], n[-1])
+        p = getattr(o, "prof_" + axis)
+        m = len(p) // 6
+        b, c = (p[3 * m:4 * m], p[4 * m:5 * m]) if kind == "h" else (p[:m], p[m:2 * m])
+        shape = [1] * len(o.shape)
+        shape[axes.index(axis)] = -1
+        inl = ((b != 1.0) | (c != 0.0)).reshape(shape)
+        assert inl.any()
+        st[n] = rng.standard_normal(o.shape) * inl
+    return st
+
+
 # ---------------------------------------------------------------------------
 # Prop. 1/2: dense graph form == stencil form
 # ---------------------------------------------------------------------------
@@ -34,7 +54,7 @@ def test_graph_equals_stencil_2d(orc):
     o = orc.Oracle2D(pb.shape, pb.dx, pb.dt, pb.eps_r, pb.sigma, None, pb.npml,
                      dict(kappa_max=2.0, alpha_max=0.05))
     rng = np.random.default_rng(1)
-    st = {n: rng.standard_normal(pb.shape) for n in o.fields + o.psis}
+    st = _random_state(o, rng)
     o.set_state(st)
     o.set_source(pb.source.cell, pb.source.kind, pb.source.params)
     g = brute.Graph2D(o)
@@ -58,7 +78,7 @@ def test_graph_equals_stencil_3d(orc):
     o = orc.Oracle3D(pb.shape, pb.dx, pb.dt, pb.eps_r, sig, mu, pb.npml,
                      dict(kappa_max=2.0, alpha_max=0.05))
     rng = np.random.default_rng(3)
-    st = {n: rng.standard_normal(pb.shape) for n in o.fields + o.psis}
+    st = _random_state(o, rng)
     o.set_state(st)
     g = brute.Graph3D(o)
     h = g.pack(st)
@@ -613,8 +633,8 @@ def test_adjoint_step_is_exact_transpose(orc):
 def test_adjoint_dot_product_50_steps(orc):
     pb, o, _ = _adj_problem(orc)
     rng = np.random.default_rng(1)
-    x = {n: rng.standard_normal(pb.shape) for n in o.fields + o.psis}
-    y = {n: rng.standard_normal(pb.shape) for n in o.fields + o.psis}
+    x = _random_state(o, rng)
+    y = _random_state(o, rng)
     o.src = None
     o.set_state(x)
     o.run(50)
