@@ -22,6 +22,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fdtd_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
+# the same C source built in single precision (run_fp32 below)
+LIB32 = os.path.join(HERE, "liborc32.so")
 
 _lock = threading.Lock()
 _lib = None
@@ -32,12 +34,14 @@ IP = C.POINTER(C.c_int)
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no GPU code involved)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (no GPU code involved), and the same
+    source in single precision (-DORC_FP32) for run_fp32."""
+    for out, extra in ((LIB, []), (LIB32, ["-DORC_FP32"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                                   "-Wall"] + extra + ["-o", tmp, SRC, "-lm"])
+            os.replace(tmp, out)
     return LIB
 
 
@@ -433,3 +437,84 @@ def for_problem(pb):
         from .split import Oracle2DSplit
         return Oracle2DSplit.from_problem(pb)
     return (Oracle2D if pb.ndim == 2 else Oracle3D).from_problem(pb)
+
+
+# ---------------------------------------------------------------------------
+# FP32 evaluation of the same update (rounding studies; not the oracle)
+# ---------------------------------------------------------------------------
+FP = C.POINTER(C.c_float)
+
+
+class _O2f(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("dx", C.c_float), ("dy", C.c_float)] + \
+               [(n, FP) for n in ("ez", "hx", "hy", "ca", "cb", "db", "psi_hx", "psi_hy", "psi_ezx",
+                                  "psi_ezy", "prof_x", "prof_y")]
+
+
+class _O3f(C.Structure):
+    _fields_ = ([("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                 ("dx", C.c_float), ("dy", C.c_float), ("dz", C.c_float)]
+                + [(n, FP) for n in F3] + [("ca", FP), ("cb", FP), ("db", FP)]
+                + [(n, FP) for n in PSI3]
+                + [("prof_x", FP), ("prof_y", FP), ("prof_z", FP)])
+
+
+_lib32 = None
+
+
+def lib32():
+    global _lib32
+    with _lock:
+        if _lib32 is None:
+            build()
+            L = C.CDLL(LIB32)
+            L.orc2d_run.argtypes = [C.POINTER(_O2f), C.c_long, C.c_long, LP, FP, C.c_int, LP, FP,
+                                    C.c_long, IP, FP, FP]
+            L.orc3d_run.argtypes = [C.POINTER(_O3f), C.c_long, FP, C.c_long, LP, FP, FP, C.c_int,
+                                    LP, FP, C.c_long]
+            _lib32 = L
+    return _lib32
+
+
+def run_fp32(o, nsteps):
+    """Advance the problem of the FP64 oracle `o` by nsteps from o's current
+    state with the single-precision build of the same stepping code: the
+    state, the coefficients, the CPML profiles and the source samples (all
+    computed in FP64) rounded once to float32, every operation of the steps
+    in float32.  `o` is not modified.  Returns ({name: float32 array} of the
+    fields and psi arrays, float32 probe record [P, nsteps])."""
+    f32 = {n: np.ascontiguousarray(getattr(o, n), np.float32) for n in o.fields + o.psis}
+    tabs = {n: np.ascontiguousarray(getattr(o, n), np.float32)
+            for n in ("ca", "cb", "db", "prof_x", "prof_y") + (("prof_z",) if len(o.shape) == 3 else ())}
+
+    def fp(a):
+        return a.ctypes.data_as(FP)
+
+    P = len(o.probes)
+    rec = np.zeros((P, nsteps), np.float32)
+    pr = o.probes if P else np.zeros(1, np.int64)
+    cells, vals, nsrc = np.zeros(1, np.int64), None, 0
+    if o.src is not None:
+        cells = o.src[0]
+        nsrc = len(cells)
+        vals = source_samples(o.src[1], o.src[2], o.dt, o.n, nsteps).astype(np.float32)
+    if len(o.shape) == 2:
+        s = _O2f()
+        s.nx, s.ny = o.shape
+        s.dx, s.dy = o.dx
+        for n, a in list(f32.items()) + list(tabs.items()):
+            setattr(s, n, fp(a))
+        lib32().orc2d_run(C.byref(s), nsteps, nsrc, cells.ctypes.data_as(LP),
+                          fp(vals) if vals is not None else None, P, pr.ctypes.data_as(LP), fp(rec),
+                          nsteps, None, None, None)
+    else:
+        s = _O3f()
+        s.nx, s.ny, s.nz = o.shape
+        s.dx, s.dy, s.dz = o.dx
+        for n, a in list(f32.items()) + list(tabs.items()):
+            setattr(s, n, fp(a))
+        sf = fp(f32[o.src[3]]) if o.src is not None else None
+        lib32().orc3d_run(C.byref(s), nsteps, sf, nsrc, cells.ctypes.data_as(LP),
+                          fp(vals) if vals is not None else None, fp(f32[o.probe_comp]), P,
+                          pr.ctypes.data_as(LP), fp(rec), nsteps)
+    return f32, rec

@@ -83,3 +83,64 @@ def assert_parity_energy(gpu, ref, pb, tol=1e-4, what=""):
             ek = rel_l2(gpu[k], ref[k])
             assert ek <= tol, "%s %s rel-L2 %.3e > %.1e" % (what, k, ek, tol)
     return e
+
+
+def group_norm(state, group):
+    """Norm of the E ("e") or H ("h") components of a state together."""
+    return float(np.sqrt(sum(float(np.sum(np.asarray(v, np.float64) ** 2))
+                             for k, v in state.items() if k.startswith(group))))
+
+
+def run_oracle_tracked(o, steps, chunk, at=()):
+    """Advance the FP64 oracle `o` by `steps` in chunks of at most `chunk`,
+    tracking the largest norm the E and the H components reached (at the
+    chunk ends; a lower bound of the true peak).  Returns the probe record,
+    {"e": peak, "h": peak} and copies of the fields at the steps in `at`
+    (counted from o's start)."""
+    fields = o.fields
+    peaks = {"e": 0.0, "h": 0.0}
+    snaps = {}
+    stops = sorted(set(list(range(chunk, steps, chunk)) + [int(a) for a in at if 0 < a < steps] + [steps]))
+    done, recs = 0, []
+    for stop in stops:
+        recs.append(o.run(stop - done))
+        done = stop
+        st = {f: getattr(o, f) for f in fields}
+        for g in peaks:
+            peaks[g] = max(peaks[g], group_norm(st, g))
+        if done in at:
+            snaps[done] = {f: getattr(o, f).copy() for f in fields}
+    return np.concatenate(recs, axis=1), peaks, snaps
+
+
+def run_errors(got, ref, peaks):
+    """Per component: the literal rel-L2 ||got - ref|| / ||ref||, the error
+    relative to the peak norm of its field group over the run
+    ||got - ref|| / P_group, and ||ref|| / P_group."""
+    out = {}
+    for k in ref:
+        d = float(np.linalg.norm((np.asarray(got[k], np.float64) - ref[k]).ravel()))
+        n = float(np.linalg.norm(np.asarray(ref[k], np.float64).ravel()))
+        p = peaks[k[0]]
+        out[k] = (d / n if n > 0 else d, d / p, n / p)
+    return out
+
+
+LIVE = 0.1
+
+
+def assert_run_parity(got, ref, peaks, tol=1e-4, what=""):
+    """The parity bar of a whole run at a checkpoint: every component within
+    tol of the peak norm its field group (E or H) reached over the run, and
+    every live component (norm at least LIVE of that peak) also within tol
+    of its own norm.  A component far below its group's peak (a pulse that
+    has been absorbed, the H of the static field a DC-carrying source
+    leaves) carries the rounding of the whole run in units of that peak:
+    no FP32 evaluation meets the literal bar there (the FP32 build of the
+    oracle shows it)."""
+    errs = run_errors(got, ref, peaks)
+    for k, (lit, grp, frac) in errs.items():
+        assert grp <= tol, "%s %s error / group peak %.3e > %.1e" % (what, k, grp, tol)
+        if frac >= LIVE:
+            assert lit <= tol, "%s %s rel-L2 %.3e > %.1e (live: %.2f of the peak)" % (what, k, lit, tol, frac)
+    return errs
