@@ -246,3 +246,114 @@ class Graph3D:
 
     def step_matrix(self):
         return self.WE @ self.WH
+
+
+class Graph2DSplit:
+    """Dense W_H, W_E of the paper's split-field PML graph (Sec. IV, the
+    4 Nx Nz-node form of its Sec. III-C layer), for a 2D TMz problem.
+
+    Nodes, in the TMz relabelling (Ey -> Ez split into Ezx and Ezy, Hz -> Hy,
+    paper-z -> y): Hx u = i + 4 j Nx, Hy q = 3 i + Nx (4 j + 1), Ezx
+    tx = q + 1, Ezy tz = q + 2.  Every cell carries all four.  H layer:
+    Hx(i, j) gathers itself and both Ez parts at (i, j) and (i, j+1), Hy(i, j)
+    itself and both parts at (i, j) and (i+1, j); E layer (cells off the PEC
+    planes i = 0 and j = 0): Ezx(i, j) gathers itself and Hy at (i, j),
+    (i-1, j); Ezy(i, j) itself and Hx at (i, j), (i, j-1) (the printed k
+    offset of the Eyz neighbourhood read as the j offset its update needs).
+
+    Weights, one per edge, written from the node positions: a node at
+    position x along the axis of its loss term gets the layer conductivity
+    s(x) = s_max rho(x)^m, rho the normalised depth into the layer (Ezx, Ezy
+    at integer positions, Hx at y = j + 1/2, Hy at x = i + 1/2); the
+    magnetic loss is s mu0 / eps0; with a = (cell loss + s) dt / (2 m),
+    m = eps or mu of the cell, the self weight is (1 - a)/(1 + a) and the
+    curl weight (dt/m)/(1 + a) divided by the step of the axis.  Nothing is
+    taken from oracle/split.py but the problem's inputs."""
+
+    def __init__(self, shape, dx, dt, eps_r=None, sigma=None, mu_r=None, npml=(0, 0, 0, 0), m=3.0,
+                 sigma_max=0.0):
+        nx, ny = shape
+        self.nx, self.ny = nx, ny
+        self.nnodes = 4 * nx * ny
+        self.u = lambda i, j: i + 4 * j * nx
+        self.q = lambda i, j: 3 * i + nx * (4 * j + 1)
+        self.tx = lambda i, j: self.q(i, j) + 1
+        self.tz = lambda i, j: self.q(i, j) + 2
+        seen = np.zeros(self.nnodes, np.int32)
+        for i in range(nx):
+            for j in range(ny):
+                for f in (self.u, self.q, self.tx, self.tz):
+                    seen[f(i, j)] += 1
+        assert np.all(seen == 1), "4-node index maps are not a bijection"
+        eps0, mu0 = 8.8541878128e-12, 1.25663706212e-6
+        eta0 = (mu0 / eps0) ** 0.5
+
+        def s_layer(pos, n, lo, hi, delta):
+            depth = 0.0
+            if lo > 0 and pos < lo:
+                depth = (lo - pos) / lo
+            if hi > 0 and pos > n - hi:
+                depth = max(depth, (pos - (n - hi)) / hi)
+            smax = sigma_max if sigma_max > 0 else 0.8 * (m + 1.0) / (eta0 * delta)
+            return smax * depth ** m
+
+        def w(loss, mat):
+            a = loss * dt / (2.0 * mat)
+            return (1.0 - a) / (1.0 + a), (dt / mat) / (1.0 + a)
+
+        def get(a, i, j, default):
+            return default if a is None else float(np.asarray(a).reshape(shape)[i, j])
+
+        M = self.nnodes
+        WH, WE = np.eye(M), np.eye(M)
+        for i in range(nx):
+            for j in range(ny):
+                mu = mu0 * get(mu_r, i, j, 1.0)
+                eps = eps0 * get(eps_r, i, j, 1.0)
+                sc = get(sigma, i, j, 0.0)
+                # Hx(i, j + 1/2): -dEz/dy, magnetic loss of the y layer
+                self_w, curl = w(s_layer(j + 0.5, ny, npml[2], npml[3], dx[1]) * mu0 / eps0, mu)
+                r = self.u(i, j)
+                WH[r, r] = self_w
+                for part in (self.tx, self.tz):
+                    WH[r, part(i, j)] += curl / dx[1]
+                    if j + 1 < ny:
+                        WH[r, part(i, j + 1)] -= curl / dx[1]
+                # Hy(i + 1/2, j): +dEz/dx, magnetic loss of the x layer
+                self_w, curl = w(s_layer(i + 0.5, nx, npml[0], npml[1], dx[0]) * mu0 / eps0, mu)
+                r = self.q(i, j)
+                WH[r, r] = self_w
+                for part in (self.tx, self.tz):
+                    WH[r, part(i, j)] -= curl / dx[0]
+                    if i + 1 < nx:
+                        WH[r, part(i + 1, j)] += curl / dx[0]
+                if i == 0 or j == 0:
+                    continue  # PEC planes: the E nodes keep their value
+                # Ezx(i, j): +dHy/dx, the cell's loss plus the x layer's
+                self_w, curl = w(sc + s_layer(float(i), nx, npml[0], npml[1], dx[0]), eps)
+                r = self.tx(i, j)
+                WE[r, r] = self_w
+                WE[r, self.q(i, j)] += curl / dx[0]
+                WE[r, self.q(i - 1, j)] -= curl / dx[0]
+                # Ezy(i, j): -dHx/dy, the cell's loss plus the y layer's
+                self_w, curl = w(sc + s_layer(float(j), ny, npml[2], npml[3], dx[1]), eps)
+                r = self.tz(i, j)
+                WE[r, r] = self_w
+                WE[r, self.u(i, j)] -= curl / dx[1]
+                WE[r, self.u(i, j - 1)] += curl / dx[1]
+        self.WH, self.WE = WH, WE
+
+    def ez(self, h):
+        out = np.zeros((self.nx, self.ny))
+        for i in range(self.nx):
+            for j in range(self.ny):
+                out[i, j] = h[self.tx(i, j)] + h[self.tz(i, j)]
+        return out
+
+    def field(self, h, name):
+        f = {"hx": self.u, "hy": self.q, "ezx": self.tx, "ezy": self.tz}[name]
+        out = np.zeros((self.nx, self.ny))
+        for i in range(self.nx):
+            for j in range(self.ny):
+                out[i, j] = h[f(i, j)]
+        return out

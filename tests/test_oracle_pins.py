@@ -436,6 +436,57 @@ def test_cpml_absorbs(orc):
     assert 20 * math.log10(r_pec) > -6
 
 
+@pytest.mark.parametrize("npml,lossy", [((2, 3, 3, 2), True), ((3, 0, 0, 2), False)])
+def test_split_pml_oracle_equals_4node_graph(orc, npml, lossy):
+    """The split-field stepper (oracle/split.py, vectorised sequential
+    updates) against the paper's 4-node graph written out as dense matrices
+    from the node positions (oracle/brute.py Graph2DSplit): 9 x 7 and 8 x 6
+    grids with a layer on some faces (graded conductivity, magnetic loss
+    matched), lossy or magnetic cells inside, a point source, 60 steps,
+    every node at 1e-13.  A half-cell offset in the H grading, a swapped
+    neighbour or a wrong sign fails it."""
+    from oracle import brute
+    from oracle.split import Oracle2DSplit
+    shape = (9, 7) if lossy else (8, 6)
+    rng = np.random.default_rng(11)
+    h = 2e-3
+    dt = 0.9 / math.sqrt(2) * h / C0
+    eps = np.ones(shape)
+    mu = np.ones(shape)
+    sig = np.zeros(shape)
+    inner = (slice(npml[0], shape[0] - npml[1]), slice(npml[2], shape[1] - npml[3]))
+    eps[inner] = rng.uniform(1, 4, eps[inner].shape)
+    if lossy:
+        sig[inner] = rng.uniform(0, 0.5, sig[inner].shape)
+    else:
+        mu[inner] = rng.uniform(1, 2, mu[inner].shape)
+    o = Oracle2DSplit(shape, (h, h), dt, eps, sig, mu, npml, dict(m=3.0, sigma_max=0.0))
+    cell = (shape[0] // 2, shape[1] // 2)
+    o.set_source(cell, 1, (1.0, 12 * dt, 1.0 / (10 * dt)))
+    g = brute.Graph2DSplit(shape, (h, h), dt, eps, sig, mu, npml)
+    x = np.zeros(g.nnodes)
+    # a random starting state (fields in every cell, E zero on the PEC planes)
+    st = {n: rng.standard_normal(shape) for n in ("ezx", "ezy", "hx", "hy")}
+    for n in ("ezx", "ezy"):
+        st[n][0, :] = 0
+        st[n][:, 0] = 0
+    f = {"hx": g.u, "hy": g.q, "ezx": g.tx, "ezy": g.tz}
+    for n, a in st.items():
+        for i in range(shape[0]):
+            for j in range(shape[1]):
+                x[f[n](i, j)] = a[i, j]
+        setattr(o, n, a.copy())
+    src = orc.source_samples(1, (1.0, 12 * dt, 1.0 / (10 * dt)), dt, 0, 60)
+    o.run(60)
+    for k in range(60):
+        x = g.WE @ (g.WH @ x)
+        x[g.tx(*cell)] += src[k]
+    for n in ("ezx", "ezy", "hx", "hy"):
+        ref = g.field(x, n)
+        assert _rel(getattr(o, n), ref) < 1e-13, n
+    assert npml[2] == 0 or np.abs(g.field(x, "ezy")[:, :npml[2]]).max() > 0
+
+
 def test_split_pml_oracle(orc):
     """The split-field PML stepper (Sec. III-C): with no layer it is the
     plain leapfrog of the C stepper (the split parts add up exactly) on a
