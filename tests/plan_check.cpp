@@ -181,7 +181,9 @@ int check2d(int nx, int ny, int V, int TB, int TX, int TXo, const int *xl, const
     return 0;
 }
 
-int main() {
+int main(int argc, char **argv) {
+    // argv[1]: divide the random case counts (a shorter run under sanitizers)
+    const int div = argc > 1 ? std::max(1, atoi(argv[1])) : 1;
     int bad = 0, n = 0;
     // two-step support rule: nz % 4, nz <= 512, at most 64 slab cells, no
     // 4-cell group with cells of both z slabs
@@ -204,7 +206,7 @@ int main() {
             ++bad;
         }
     srand(1);
-    for (int t = 0; t < 3000; ++t) {
+    for (int t = 0; t < 3000 / div; ++t) {
         int V = 1 << (rand() % 3);
         int nx = 1 + rand() % 40, ny = 1 + rand() % 90, nz = V * (1 + rand() % 100);
         int TX = rand() % 3 == 0 ? 0 : 1 + rand() % 20;
@@ -228,7 +230,7 @@ int main() {
         if (r) printf("  slab-tb case nx %d ny %d nz %d TX %d txo %d mat %d s %d %d %d %d %d %d\n", nx, ny, nz2, TX, txo, mat, s[0], s[1], s[2], s[3], s[4], s[5]);
         bad += r; ++n;
     }
-    for (int t = 0; t < 2000; ++t) {
+    for (int t = 0; t < 2000 / div; ++t) {
         const int V = 1 << (rand() % 3), TB = rand() % 2 ? 2 : 4;
         const int nx = 1 + rand() % 300, ny = V * (1 + rand() % 200), TX = 1 + rand() % 40;
         int s[4];
