@@ -199,8 +199,10 @@ typedef struct {
 #define IN_LAYER_E(p, n, i) (P_BE(p, n, i) != 1.0 || P_CE(p, n, i) != 0.0)
 #define IN_LAYER_H(p, n, i) (P_BH(p, n, i) != 1.0 || P_CH(p, n, i) != 0.0)
 
-/* H layer: messages from the E nodes to Hx, Hy (Eq. 8-9, TMz form). */
-void orc2d_h_layer(const orc2d_t *s)
+/* H layer: messages from the E nodes to Hx, Hy (Eq. 8-9, TMz form).  If
+ * brx / bry are given, they receive the brackets that multiply Db (Hx -=
+ * Db brx, Hy += Db bry), for the adjoint. */
+void orc2d_h_layer_br(const orc2d_t *s, double *brx, double *bry)
 {
     const int nx = s->nx, ny = s->ny;
 #pragma omp parallel for schedule(static)
@@ -217,15 +219,21 @@ void orc2d_h_layer(const orc2d_t *s)
                 s->psi_hx[c] = P_BH(s->prof_y, ny, j) * s->psi_hx[c] + P_CH(s->prof_y, ny, j) * dey;
                 phx = s->psi_hx[c];
             }
-            s->hx[c] -= s->db[c] * (dey * P_KH(s->prof_y, ny, j) + phx);
+            const double bx = dey * P_KH(s->prof_y, ny, j) + phx;
+            if (brx) brx[c] = bx;
+            s->hx[c] -= s->db[c] * bx;
             if (IN_LAYER_H(s->prof_x, nx, i)) {
                 s->psi_hy[c] = P_BH(s->prof_x, nx, i) * s->psi_hy[c] + P_CH(s->prof_x, nx, i) * dex;
                 phy = s->psi_hy[c];
             }
-            s->hy[c] += s->db[c] * (dex * P_KH(s->prof_x, nx, i) + phy);
+            const double by = dex * P_KH(s->prof_x, nx, i) + phy;
+            if (bry) bry[c] = by;
+            s->hy[c] += s->db[c] * by;
         }
     }
 }
+
+void orc2d_h_layer(const orc2d_t *s) { orc2d_h_layer_br(s, NULL, NULL); }
 
 /* E layer: messages from Hx, Hy to the Ez nodes (Eq. 7, TMz form).  If curl
  * is given, curl[c] receives the bracket multiplied by Cb (for the adjoint). */
@@ -261,18 +269,32 @@ void orc2d_e_layer(const orc2d_t *s, double *curl)
  *   c, rec[p*rec_stride + k] = Ez[probe p].
  * If design != NULL ({i0,i1,j0,j1}), the Ez value before the E layer and
  * the bracket of the E layer at every design cell are stored per step in
- * traj_ez / traj_br ([nsteps][(i1-i0)*(j1-j0)]) for the adjoint.
+ * traj_ez / traj_br ([nsteps][(i1-i0)*(j1-j0)]) for the adjoint, and, if
+ * traj_bx / traj_by are given, the brackets of the H layer (Hx -= Db bx,
+ * Hy += Db by) likewise.
  */
-void orc2d_run(const orc2d_t *s, long nsteps, long nsrc, const long *src_cells, const double *src_vals,
-               int np, const long *probe_idx, double *rec, long rec_stride,
-               const int *design, double *traj_ez, double *traj_br)
+void orc2d_run_mu(const orc2d_t *s, long nsteps, long nsrc, const long *src_cells, const double *src_vals,
+                  int np, const long *probe_idx, double *rec, long rec_stride,
+                  const int *design, double *traj_ez, double *traj_br, double *traj_bx, double *traj_by)
 {
     const int ny = s->ny;
     long nd = design ? (long)(design[1] - design[0]) * (design[3] - design[2]) : 0;
-    double *curl = NULL;
+    double *curl = NULL, *bx = NULL, *by = NULL;
     if (design) curl = (double *)calloc((size_t)s->nx * ny, sizeof(double));
+    if (design && traj_bx && traj_by) {
+        bx = (double *)calloc((size_t)s->nx * ny, sizeof(double));
+        by = (double *)calloc((size_t)s->nx * ny, sizeof(double));
+    }
     for (long k = 0; k < nsteps; ++k) {
-        orc2d_h_layer(s);
+        orc2d_h_layer_br(s, bx, by);
+        if (bx) {
+            long q = 0;
+            for (int i = design[0]; i < design[1]; ++i)
+                for (int j = design[2]; j < design[3]; ++j, ++q) {
+                    traj_bx[k * nd + q] = bx[(long)i * ny + j];
+                    traj_by[k * nd + q] = by[(long)i * ny + j];
+                }
+        }
         if (design) {
             long q = 0;
             for (int i = design[0]; i < design[1]; ++i)
@@ -290,6 +312,16 @@ void orc2d_run(const orc2d_t *s, long nsteps, long nsrc, const long *src_cells, 
         for (int p = 0; p < np; ++p) rec[(long)p * rec_stride + k] = s->ez[probe_idx[p]];
     }
     free(curl);
+    free(bx);
+    free(by);
+}
+
+void orc2d_run(const orc2d_t *s, long nsteps, long nsrc, const long *src_cells, const double *src_vals,
+               int np, const long *probe_idx, double *rec, long rec_stride,
+               const int *design, double *traj_ez, double *traj_br)
+{
+    orc2d_run_mu(s, nsteps, nsrc, src_cells, src_vals, np, probe_idx, rec, rec_stride, design, traj_ez,
+                 traj_br, NULL, NULL);
 }
 
 /* Adjoint variables: one per forward state variable. */
@@ -379,10 +411,11 @@ void orc2d_adj_step(const orc2d_t *s, orc2d_adj_t *a)
  * box.  grad[(i-i0)*(j1-j0) + (j-j0)] receives dL/d eps_r for each design
  * cell; a (zero on entry) holds the adjoint of the initial state on return.
  */
-void orc2d_adjoint(const orc2d_t *s, orc2d_adj_t *a, long T, int np,
-                   const long *probe_idx, const double *probe_ez, long n0, long n1,
-                   const int *design, const double *traj_ez, const double *traj_br,
-                   const double *eps_r, const double *sigma, double dt, double *grad)
+void orc2d_adjoint_mu(const orc2d_t *s, orc2d_adj_t *a, long T, int np,
+                      const long *probe_idx, const double *probe_ez, long n0, long n1,
+                      const int *design, const double *traj_ez, const double *traj_br,
+                      const double *eps_r, const double *sigma, double dt, double *grad,
+                      const double *traj_bx, const double *traj_by, const double *mu_r, double *grad_mu)
 {
     const int ny = s->ny;
     long n = (long)s->nx * ny;
@@ -391,6 +424,8 @@ void orc2d_adjoint(const orc2d_t *s, orc2d_adj_t *a, long T, int np,
     double *gx = (double *)malloc(sizeof(double) * (size_t)n);
     double *gy = (double *)malloc(sizeof(double) * (size_t)n);
     for (long q = 0; q < nd; ++q) grad[q] = 0.0;
+    if (grad_mu)
+        for (long q = 0; q < nd; ++q) grad_mu[q] = 0.0;
     for (long k = T - 1; k >= 0; --k) {
         /* loss term of Ez^{k+1} (probe recorded after step k) */
         long m = k + 1;
@@ -408,10 +443,32 @@ void orc2d_adjoint(const orc2d_t *s, orc2d_adj_t *a, long T, int np,
             }
         }
         orc2d_adj_e_layer(s, a, gx, gy);
+        /* gradient with respect to mu_r: Hx -= Db bx and Hy += Db by with
+         * Db = dt / (mu0 mu_r), weighted by the adjoints of Hx, Hy after the
+         * H layer (they hold them now): dL/dmu_r += (Db / mu_r) (aHx bx - aHy by) */
+        if (grad_mu) {
+            for (int i = design[0]; i < design[1]; ++i) {
+                for (int j = design[2]; j < design[3]; ++j) {
+                    long c = (long)i * ny + j;
+                    long q = (long)(i - design[0]) * dj + (j - design[2]);
+                    double mr = mu_r ? mu_r[c] : 1.0;
+                    grad_mu[q] += s->db[c] / mr * (a->hx[c] * traj_bx[k * nd + q] - a->hy[c] * traj_by[k * nd + q]);
+                }
+            }
+        }
         orc2d_adj_h_layer(s, a);
     }
     free(gx);
     free(gy);
+}
+
+void orc2d_adjoint(const orc2d_t *s, orc2d_adj_t *a, long T, int np,
+                   const long *probe_idx, const double *probe_ez, long n0, long n1,
+                   const int *design, const double *traj_ez, const double *traj_br,
+                   const double *eps_r, const double *sigma, double dt, double *grad)
+{
+    orc2d_adjoint_mu(s, a, T, np, probe_idx, probe_ez, n0, n1, design, traj_ez, traj_br, eps_r, sigma, dt,
+                     grad, NULL, NULL, NULL, NULL);
 }
 
 /* ======================================================================== */

@@ -88,6 +88,8 @@ def lib():
             L.orc2d_adjoint.argtypes = [C.POINTER(_O2), C.POINTER(_A2), C.c_long, C.c_int, LP,
                                         DP, C.c_long, C.c_long, IP, DP, DP, DP, DP,
                                         C.c_double, DP]
+            L.orc2d_run_mu.argtypes = L.orc2d_run.argtypes + [DP, DP]
+            L.orc2d_adjoint_mu.argtypes = L.orc2d_adjoint.argtypes + [DP, DP, DP, DP]
             L.orc3d_h_layer.argtypes = [C.POINTER(_O3)]
             L.orc3d_e_layer.argtypes = [C.POINTER(_O3)]
             L.orc3d_run.argtypes = [C.POINTER(_O3), C.c_long, DP, C.c_long, LP, DP, DP, C.c_int,
@@ -195,9 +197,11 @@ class Oracle2D:
         cells = np.asarray(cells, np.int64).reshape(-1, 2)
         self.probes = np.ascontiguousarray(cells[:, 0] * self.shape[1] + cells[:, 1])
 
-    def run(self, nsteps, design=None):
+    def run(self, nsteps, design=None, hbr=False):
         """Advance nsteps; returns probe samples [P, nsteps] and, with a
-        design box, the per-step (Ez before E layer, bracket) trajectories."""
+        design box, the per-step (Ez before E layer, bracket) trajectories,
+        and with hbr also those of the H layer's brackets (Hx -= Db bx,
+        Hy += Db by)."""
         if self.dft is not None and design is None and nsteps > 1:
             return np.concatenate([self.run(1) for _ in range(nsteps)], axis=1)
         s = self._struct()
@@ -208,21 +212,24 @@ class Oracle2D:
             cells = self.src[0]
             vals = source_samples(self.src[1], self.src[2], self.dt, self.n, nsteps)
         nsrc = len(cells) if self.src is not None else 0
-        dz = tz = tb = None
+        dz = tz = tb = hx = hy = None
         if design is not None:
             dz = (C.c_int * 4)(*design)
             nd = (design[1] - design[0]) * (design[3] - design[2])
             tz = np.zeros((nsteps, nd), np.float64)
             tb = np.zeros((nsteps, nd), np.float64)
+            if hbr:
+                hx = np.zeros((nsteps, nd), np.float64)
+                hy = np.zeros((nsteps, nd), np.float64)
         pr = self.probes if P else np.zeros(1, np.int64)
-        lib().orc2d_run(C.byref(s), nsteps, nsrc, cells.ctypes.data_as(LP), _p(vals), P, pr.ctypes.data_as(LP),
-                        _p(rec), nsteps, dz, _p(tz), _p(tb))
+        lib().orc2d_run_mu(C.byref(s), nsteps, nsrc, cells.ctypes.data_as(LP), _p(vals), P,
+                           pr.ctypes.data_as(LP), _p(rec), nsteps, dz, _p(tz), _p(tb), _p(hx), _p(hy))
         self.n += nsteps
         self.rec.append(rec)
         if self.dft is not None:
             _dft_sample(self, nsteps)
         if design is not None:
-            return rec, tz, tb
+            return (rec, tz, tb, hx, hy) if hbr else (rec, tz, tb)
         return rec
 
     def h_layer(self):
@@ -254,14 +261,19 @@ class Oracle2D:
             setattr(a, n, _p(adj[n]))
         lib().orc2d_adj_step(C.byref(s), C.byref(a))
 
-    def loss_and_grad(self, T, window, design):
+    def loss_and_grad(self, T, window, design, mu=False):
         """From the zero state: run T steps, L = sum over probes and
-        m in (n0, n1] of Ez^m[p]^2, and dL/d eps_r on the design box."""
+        m in (n0, n1] of Ez^m[p]^2, and dL/d eps_r on the design box (with
+        mu: also dL/d mu_r, returned third)."""
         for n in self.fields + self.psis:
             getattr(self, n)[...] = 0.0
         self.n = 0
         self.rec = []
-        rec, tz, tb = self.run(T, design=design)
+        if mu:
+            rec, tz, tb, hx, hy = self.run(T, design=design, hbr=True)
+        else:
+            rec, tz, tb = self.run(T, design=design)
+            hx = hy = None
         n0, n1 = window
         loss = float(np.sum(rec[:, n0:n1] ** 2))
         for n in self.fields + self.psis:
@@ -276,11 +288,16 @@ class Oracle2D:
         er = self.eps_r if self.eps_r is not None else np.ones(self.shape)
         er = np.ascontiguousarray(er, np.float64)
         sg = self.sigma
-        lib().orc2d_adjoint(C.byref(s), C.byref(a), T, len(self.probes),
-                            self.probes.ctypes.data_as(LP), _p(np.ascontiguousarray(rec)),
-                            n0, n1, (C.c_int * 4)(*design), _p(tz), _p(tb), _p(er), _p(sg),
-                            self.dt, _p(grad))
-        return loss, grad.reshape(design[1] - design[0], design[3] - design[2])
+        gmu = np.zeros(nd, np.float64) if mu else None
+        mr = None if self.mu_r is None else np.ascontiguousarray(self.mu_r, np.float64)
+        lib().orc2d_adjoint_mu(C.byref(s), C.byref(a), T, len(self.probes),
+                               self.probes.ctypes.data_as(LP), _p(np.ascontiguousarray(rec)),
+                               n0, n1, (C.c_int * 4)(*design), _p(tz), _p(tb), _p(er), _p(sg),
+                               self.dt, _p(grad), _p(hx), _p(hy), _p(mr), _p(gmu))
+        shape = (design[1] - design[0], design[3] - design[2])
+        if mu:
+            return loss, grad.reshape(shape), gmu.reshape(shape)
+        return loss, grad.reshape(shape)
 
 
 class Oracle3D:
