@@ -60,17 +60,29 @@ extern "C" int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1
         set_error("NULL argument");
         return FDTD_EINVAL;
     }
-    return fdtd_adjoint(sim, T, n0, n1, design, ckpt_interval, loss_out, grad_dev, nullptr);
+    return fdtd_adjoint_grads(sim, T, n0, n1, design, ckpt_interval, loss_out, grad_dev, nullptr, nullptr);
 }
 
 extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
                             int32_t ckpt_interval, double *loss_out, float *grad_eps_dev, float *grad_sigma_dev) {
+    if (!grad_eps_dev && !grad_sigma_dev) {
+        set_error("NULL argument");
+        return FDTD_EINVAL;
+    }
+    return fdtd_adjoint_grads(sim, T, n0, n1, design, ckpt_interval, loss_out, grad_eps_dev, grad_sigma_dev,
+                              nullptr);
+}
+
+extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
+                                  int32_t ckpt_interval, double *loss_out, float *grad_eps_dev,
+                                  float *grad_sigma_dev, float *grad_mu_dev) {
     std::vector<void *> tmp;
     Sim *sp = nullptr;
     fdtd_kernel_config saved{};
     bool restore_cfg = false;
     try {
-        if (!sim || !design || (!grad_eps_dev && !grad_sigma_dev)) fail(FDTD_EINVAL, "NULL argument");
+        if (!sim || !design || (!grad_eps_dev && !grad_sigma_dev && !grad_mu_dev))
+            fail(FDTD_EINVAL, "NULL argument");
         Sim &s = sim->s;
         sp = &s;
         if (s.ndim != 2 || s.is_graph) fail(FDTD_EINVAL, "the adjoint supports the 2D implicit stepper");
@@ -82,11 +94,19 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
             fail(FDTD_EINVAL, "invalid design box");
         if (s.probe_cells.empty() || s.probe_comp != FDTD_EZ)
             fail(FDTD_EINVAL, "the loss needs Ez probes (fdtd_set_probes)");
+        // the H layer's brackets at the design cells are rebuilt from the
+        // captured Ez: no CPML auxiliary term may enter them
+        if (grad_mu_dev && (i0 < s.ax[0].lo || i1 > s.nx - s.ax[0].hi || j0 < s.ax[1].lo || j1 > s.ny - s.ax[1].hi))
+            fail(FDTD_EINVAL, "the mu_r gradient needs a design box clear of the CPML slabs");
         // an interval beyond T is one segment of T steps
         const int64_t L = std::min<int64_t>(T, ckpt_interval > 0 ? ckpt_interval
                                                                  : (int64_t)std::ceil(std::sqrt((double)T)));
         const int64_t nseg = (T + L - 1) / L;
         const int64_t nd = (int64_t)(i1 - i0) * (j1 - j0);
+        // captured box: the design box and one row and column beyond it
+        // (clipped to the grid), whose Ez the H brackets need
+        const int i1c = std::min(i1 + 1, s.nx), j1c = std::min(j1 + 1, s.ny);
+        const int64_t ndc = (int64_t)(i1c - i0) * (j1c - j0);
         const int64_t P = (int64_t)s.probe_cells.size();
 
         // forward and recompute: the chosen fused configuration (variant 2
@@ -113,9 +133,10 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
         const int64_t S = state_floats(s);
         float *ck = (float *)get((size_t)(std::max<int64_t>(1, nseg - 1) * S) * 4);
         float *fin = (float *)get((size_t)S * 4);
-        float *cap_ez = (float *)get((size_t)(L * nd) * 4);
-        float *cap_br = (float *)get((size_t)(L * nd) * 4);
+        float *cap_ez = (float *)get((size_t)(L * ndc) * 4);
+        float *cap_br = (float *)get((size_t)(L * ndc) * 4);
         const int dbox[4] = {i0, i1, j0, j1};
+        const int cbox[4] = {i0, i1c, j0, j1c};
         ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
         const Fused2DCfg fc = s.single2d();
         // steps [k0, k1) from the current state; with `cap`, keeping the
@@ -132,8 +153,8 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
                 if (cap) {
                     const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
                     const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
-                    hip_check(launch_2d_fused(p, fc, pt, k, s.st, dbox, cap_ez + (k - k0) * nd,
-                                              cap_br + (k - k0) * nd, s.split2d() ? &sp : nullptr),
+                    hip_check(launch_2d_fused(p, fc, pt, k, s.st, cbox, cap_ez + (k - k0) * ndc,
+                                              cap_br + (k - k0) * ndc, s.split2d() ? &sp : nullptr),
                               "forward step");
                     s.cur = 1 - s.cur;
                 } else {
@@ -152,7 +173,7 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
                 copy_state(s, s.cur, ck + g * S, true);
                 run(k0, k1, nullptr);
             } else {
-                const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
+                const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez, cap_br, k0, ndc};
                 run(k0, k1, &cap);
             }
         }
@@ -181,11 +202,15 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
         int acur = 0;
         double *sez = (double *)get((size_t)nd * 8);  // zero-filled
         double *sbr = (double *)get((size_t)nd * 8);
+        double *shx = grad_mu_dev ? (double *)get((size_t)nd * 8) : nullptr;
+        double *shy = grad_mu_dev ? (double *)get((size_t)nd * 8) : nullptr;
         // derivatives of Ca = (e - h)/(e + h) and Cb = dt/(e + h), e = eps0
         // eps_r, h = sigma dt / 2, at the design cells (FP64):
         //   d/d eps_r: dCa = 2 eps0 h / (e + h)^2,  dCb = -eps0 dt / (e + h)^2
         //   d/d sigma: dCa = -dt e / (e + h)^2,     dCb = -dt^2 / (2 (e + h)^2)
-        std::vector<double> hd((size_t)(4 * nd));
+        //   d/d mu_r (Hx -= Db bx, Hy += Db by, Db = dt / (mu0 mu_r)):
+        //     dL/d mu_r = (Db / mu_r) (sum aHx bx - sum aHy by)
+        std::vector<double> hd((size_t)(6 * nd));
         for (int i = i0; i < i1; ++i)
             for (int j = j0; j < j1; ++j) {
                 const int64_t c = (int64_t)i * s.ny + j;
@@ -198,9 +223,13 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
                 hd[(size_t)(nd + q)] = -kEps0 * s.dt / den;
                 hd[(size_t)(2 * nd + q)] = -s.dt * e / den;
                 hd[(size_t)(3 * nd + q)] = -0.5 * s.dt * s.dt / den;
+                const double mr = s.mu_r.empty() ? 1.0 : s.mu_r[(size_t)c];
+                const double dbm = s.dt / (kMu0 * mr) / mr;
+                hd[(size_t)(4 * nd + q)] = dbm;
+                hd[(size_t)(5 * nd + q)] = -dbm;
             }
-        double *dcoef = (double *)get((size_t)(4 * nd) * 8);
-        hip_check(hipMemcpyAsync(dcoef, hd.data(), (size_t)(4 * nd) * 8, hipMemcpyHostToDevice, s.st), "upload");
+        double *dcoef = (double *)get((size_t)(6 * nd) * 8);
+        hip_check(hipMemcpyAsync(dcoef, hd.data(), (size_t)(6 * nd) * 8, hipMemcpyHostToDevice, s.st), "upload");
         // probed cells (sorted) and their probe entries, for the loss seed
         std::vector<int> ust, pcell, pslot;
         {
@@ -256,7 +285,7 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
                 s.cur = 0;
                 s.n_done = k0;
                 s.n_rec = k0;
-                const CapArgs cap{make_int4(i0, i1, j0, j1), cap_ez, cap_br, k0, nd};
+                const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez, cap_br, k0, ndc};
                 run(k0, k1, &cap);
             }
             const Prob2D p = s.prob2d(0, 0);
@@ -268,9 +297,9 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
                                                 s.st),
                               "adjoint seed");
                 const int seed_out = (k > n0 && k <= n1) ? 1 : 0;
-                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cap_ez + (k - k0) * nd,
-                                             cap_br + (k - k0) * nd, sez, sbr, seed_out, apt, s.rec_dev,
-                                             s.rec_cap, k - 1, ac.V, ac.TX, s.st),
+                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cbox, cap_ez + (k - k0) * ndc,
+                                             cap_br + (k - k0) * ndc, sez, sbr, shx, shy, seed_out, apt,
+                                             s.rec_dev, s.rec_cap, k - 1, ac.V, ac.TX, s.st),
                           "adjoint step");
                 acur = 1 - acur;
             }
@@ -279,6 +308,9 @@ extern "C" int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, co
             hip_check(launch_grad_combine(sez, sbr, dcoef, dcoef + nd, grad_eps_dev, nd, s.st), "gradient");
         if (grad_sigma_dev)
             hip_check(launch_grad_combine(sez, sbr, dcoef + 2 * nd, dcoef + 3 * nd, grad_sigma_dev, nd, s.st),
+                      "gradient");
+        if (grad_mu_dev)
+            hip_check(launch_grad_combine(shx, shy, dcoef + 4 * nd, dcoef + 5 * nd, grad_mu_dev, nd, s.st),
                       "gradient");
         // leave the forward state after T steps
         copy_state(s, 0, fin, false);

@@ -310,10 +310,14 @@ hipError_t launch_grad_combine(const double *sez, const double *sbr, const doubl
 // l1.ez[probe] += 2 * rec[slot][seed_k] (pt: probes grouped by tile in tile
 // order, tile = (i / TX) * nsy + j / (62 V), entries of one cell
 // consecutive).  Tiles of TX rows by 62*V columns; ny % V == 0.
+// cbox: the captured box (design box plus one row and column, clipped) that
+// cap_ez / cap_br cover; shx, shy (nullptr: none): per design cell sums of
+// aHx bx and aHy by for the mu_r gradient (the H brackets rebuilt from the
+// captured Ez; the design box must be clear of the CPML slabs).
 hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
-                              const float *cap_ez, const float *cap_br, double *sez, double *sbr, int seed_out,
-                              const ProbeTiles &pt, const float *rec, int64_t rec_stride, int64_t seed_k, int V,
-                              int TX, hipStream_t st);
+                              const int *cbox, const float *cap_ez, const float *cap_br, double *sez, double *sbr,
+                              double *shx, double *shy, int seed_out, const ProbeTiles &pt, const float *rec,
+                              int64_t rec_stride, int64_t seed_k, int V, int TX, hipStream_t st);
 // The seed of the first adjoint step: ez[cell u] += 2 * rec[slot][k] over
 // the probe entries [start[u], start[u+1]) of the nu probed cells.
 hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_cell, const int *seed_slot, int nu,

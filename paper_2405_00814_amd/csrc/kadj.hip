@@ -31,11 +31,20 @@ struct AdjFArgs {
     Prob2D p;
     Adj2D l0, l1;      // adjoint state read (step k+1) and written (step k)
     int4 design;
+    // captured values of this step on the box cbox (the design box and one
+    // row and column beyond it, clipped to the grid): Ez before the E layer
+    // and the E layer's bracket, row width cw
+    int4 cbox;
+    int cw;
     const float *cap_ez, *cap_br;
     // per design cell: sez += a Ez^n, sbr += a bracket (the gradients with
     // respect to any per-cell parameter of Ca and Cb follow from these two
     // sums and the coefficients' derivatives)
     double *sez, *sbr;
+    // with the mu_r gradient (nullptr: none), per design cell: shx += aHx bx,
+    // shy += aHy by, the H layer's brackets rebuilt from the captured Ez
+    // (the design box is clear of the CPML slabs: no auxiliary term)
+    double *shx, *shy;
     // probe-loss seed of the next step, added to the written adjoint Ez:
     // l1.ez[probe] += 2 * rec[slot][seed_k] (probes grouped by tile, entries
     // of one cell consecutive)
@@ -140,8 +149,9 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 gx[v] = -u * kEy[v] + cEy[v] * py;
                 if (write && i >= A.design.x && i < A.design.y && j >= A.design.z && j < A.design.w) {
                     const int64_t q = (int64_t)(i - A.design.x) * dw + (j - A.design.z);
-                    A.sez[q] += (double)a[v] * A.cap_ez[q];
-                    A.sbr[q] += (double)a[v] * A.cap_br[q];
+                    const int64_t qc = (int64_t)(i - A.cbox.x) * A.cw + (j - A.cbox.z);
+                    A.sez[q] += (double)a[v] * A.cap_ez[qc];
+                    A.sbr[q] += (double)a[v] * A.cap_br[qc];
                 }
                 aca[v] = a[v] * ca[v];
             } else if (PML && jj[v] >= 0 && write) {
@@ -218,6 +228,23 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 }
                 ex[v] = db[v] * hy[v] * kHx + cHx * wy;
             }
+            // mu_r gradient at the design cells: hx, hy are now the
+            // adjoints of H after this step's H layer
+            if (A.shx && own && i >= A.design.x && i < A.design.y) {
+                const int64_t r0 = (int64_t)(i - A.cbox.x) * A.cw;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int j = jb + v;
+                    if (j < A.design.z || j >= A.design.w) continue;
+                    const int64_t q = (int64_t)(i - A.design.x) * dw + (j - A.design.z);
+                    const int64_t qc = r0 + (j - A.cbox.z);
+                    const float e0 = A.cap_ez[qc];
+                    const float ey1 = j + 1 < A.cbox.w ? A.cap_ez[qc + 1] : 0.f;
+                    const float ex1 = i + 1 < A.cbox.y ? A.cap_ez[qc + A.cw] : 0.f;
+                    A.shx[q] += (double)hx[v] * (double)((ey1 - e0) * kHy[v]);
+                    A.shy[q] += (double)hy[v] * (double)((ex1 - e0) * kHx);
+                }
+            }
             if (own) {
                 stva<V>(L1.hx + row + jb, hx);
                 stva<V>(L1.hy + row + jb, hy);
@@ -282,9 +309,9 @@ hipError_t launch_adj2d_seed(float *ez, const int *seed_start, const int *seed_c
 }
 
 hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1, const int *design,
-                              const float *cap_ez, const float *cap_br, double *sez, double *sbr, int seed_out,
-                              const ProbeTiles &pt, const float *rec, int64_t rec_stride, int64_t seed_k, int V,
-                              int TX, hipStream_t st) {
+                              const int *cbox, const float *cap_ez, const float *cap_br, double *sez, double *sbr,
+                              double *shx, double *shy, int seed_out, const ProbeTiles &pt, const float *rec,
+                              int64_t rec_stride, int64_t seed_k, int V, int TX, hipStream_t st) {
     if (p.ny % V != 0 || TX < 1) return hipErrorInvalidValue;
     AdjFArgs A;
     A.seed_out = seed_out;
@@ -296,6 +323,10 @@ hipError_t launch_adj2d_fused(const Prob2D &p, const Adj2D &l0, const Adj2D &l1,
     A.l0 = l0;
     A.l1 = l1;
     A.design = make_int4(design[0], design[1], design[2], design[3]);
+    A.cbox = make_int4(cbox[0], cbox[1], cbox[2], cbox[3]);
+    A.cw = cbox[3] - cbox[2];
+    A.shx = shx;
+    A.shy = shy;
     A.cap_ez = cap_ez;
     A.cap_br = cap_br;
     A.sez = sez;
