@@ -143,14 +143,14 @@ def bench_2d(args, steps=10000):
     ab = alg_bytes_implicit(pb.cells, psi_floats_of(pb), 3, ncoef_of(pb))
     k = sim.get_kernel()
     tb = k["tile"][2] if k["variant"] == 3 else 1
-    # hbm_frac: algorithmic bytes per cell-update x cell-updates/s; a pass of
-    # tb steps moves one step's bytes, so pass_frac is the memory-side view
+    # hbm_frac: a pass of tb steps must move one step's algorithmic bytes
+    # (state in and out once); step_equiv_frac counts them per step
     out = dict(workload="dielectric2d_4096x4096_cpml16_200rects", steps=steps,
                kernel=k, steps_per_pass=tb, gcells_per_s=pb.cells * steps / t / 1e9,
-               bytes_per_cell_update=ab / pb.cells,
-               achieved_GBps=ab * steps / t / 1e9,
-               hbm_frac=ab * steps / t / PEAK_HBM,
-               pass_frac=ab * steps / tb / t / PEAK_HBM)
+               bytes_per_cell_pass=ab / pb.cells,
+               achieved_GBps=ab * steps / tb / t / 1e9,
+               hbm_frac=ab * steps / tb / t / PEAK_HBM,
+               step_equiv_frac=ab * steps / t / PEAK_HBM)
     sim.close()
     # explicit graph form on the same grid
     g = Sim.from_problem(pb, graph=True)
@@ -160,7 +160,8 @@ def bench_2d(args, steps=10000):
     out["graph_form"] = dict(steps=gs, gcells_per_s=pb.cells * gs / tg / 1e9,
                              bytes_per_cell_update=gbytes / pb.cells,
                              achieved_GBps=gbytes * gs / tg / 1e9,
-                             hbm_frac=gbytes * gs / tg / PEAK_HBM, launches_per_step=lg / gs)
+                             hbm_frac=gbytes * gs / tg / PEAK_HBM, launches_per_step=lg / gs,
+                             impl_bytes_per_cell_update=csr_impl_bytes(pb) / pb.cells)
     g.close()
     # frequency-domain monitor: Ez on the central 2048^2 box at 4 frequencies
     # (single steps while it is set), against single steps without it
@@ -192,23 +193,39 @@ def bench_2d(args, steps=10000):
     return out
 
 
-def csr_alg_bytes(pb):
-    """Algorithmic bytes of one CSR step: every matrix entry (column index and
-    weight) and every row pointer / destination index read once, every node
-    value read once and every updated node written once."""
+def _csr_counts(pb):
+    """(nonzeros, rows, nodes) of one step of the explicit graph of a 2D
+    CPML problem: H rows (Hx, Hy: self, two E nodes, psi in a slab), psi_H
+    rows (self, two E nodes), E rows (self, four H nodes, psi in a slab),
+    psi_E rows (self, two H nodes)."""
     nx, ny = pb.shape
     N = nx * ny
     sx, sy = pb.npml[0] + pb.npml[1], pb.npml[2] + pb.npml[3]
-    npsi = 2 * nx * sy + 2 * sx * ny
-    nnz_h = 2 * N * 3 + 2 * nx * sy // 2 + 2 * sx * ny // 2  # field rows + psi edges
-    nnz_h += 3 * (nx * sy + sx * ny)                          # psi rows
-    nnz_e = 5 * N + (nx * sy + sx * ny) + 3 * (nx * sy + sx * ny)
-    rows = 3 * N + npsi
-    nodes = 3 * N + npsi
-    return 8 * (nnz_h + nnz_e) + 8 * rows + 4 * nodes * 2 + 4 * rows
+    slab = nx * sy + sx * ny        # psi values of one layer's field (x and y slabs)
+    nnz_h = 2 * 3 * N + slab + 3 * slab
+    nnz_e = 5 * N + slab + 3 * slab
+    rows = 3 * N + 2 * slab
+    return nnz_h + nnz_e, rows, rows
 
 
-def bench_batch(args, steps=500):
+def csr_alg_bytes(pb):
+    """Algorithmic bytes of one step of the explicit graph (the method's
+    matrices): every matrix entry (column index and weight, 8 B) and every
+    row pointer (4 B) read once, every node value read once and written once
+    (8 B).  124 B per interior cell."""
+    nnz, rows, nodes = _csr_counts(pb)
+    return 8 * nnz + 4 * rows + 8 * nodes
+
+
+def csr_impl_bytes(pb):
+    """Bytes the CSR kernels move at least: the algorithmic bytes plus each
+    row's destination index (4 B), and every node value read in both layers
+    (the H layer gathers E and its own H, the E layer H and its own E)."""
+    nnz, rows, nodes = _csr_counts(pb)
+    return 8 * nnz + 8 * rows + 12 * nodes
+
+
+def bench_batch(args, steps=4000):
     from paper_2405_00814_amd import workloads as W
     from paper_2405_00814_amd.sim import Batch, Sim
     import torch
@@ -216,6 +233,11 @@ def bench_batch(args, steps=500):
     cells = sum(p.cells for p in probs)
     log("batch: %d problems, %.3e cells" % (len(probs), cells))
     b = Batch(probs)
+    # the autotuner picks steps per pass, tile rows and vector width for this
+    # size mix (state restored; cached when $GEMFDTD_TUNE_CACHE is set)
+    t0 = time.perf_counter()
+    tuned = b.autotune(64)
+    tune_s = time.perf_counter() - t0
     b.step(64)
     torch.cuda.synchronize()
     b.step(steps)
@@ -235,10 +257,68 @@ def bench_batch(args, steps=500):
         s.close()
     ab = sum(alg_bytes_implicit(p.cells, psi_floats_of(p), 3, ncoef_of(p)) for p in probs)
     return dict(workload="batch2d_256_problems_sides_256_2048_cpml16", problems=len(probs),
-                cells=cells, steps=steps, steps_per_pass=4, gcells_per_s=cells * steps / tb / 1e9,
-                hbm_frac=ab * steps / tb / PEAK_HBM, pass_frac=ab * steps / 4 / tb / PEAK_HBM,
+                cells=cells, steps=steps, tuned=dict(tb=tuned[0], tx=tuned[1], vmax=tuned[2], txo=tuned[3],
+                                                     seconds=tune_s),
+                steps_per_pass=tuned[0], gcells_per_s=cells * steps / tb / 1e9,
+                hbm_frac=ab * steps / tuned[0] / tb / PEAK_HBM, step_equiv_frac=ab * steps / tb / PEAK_HBM,
                 plain_sequential_gcells_per_s=cells * steps / tp / 1e9,
                 speedup_vs_plain=tp / tb, launches=lb, finite=bool(ok))
+
+
+def bench_cavity(args, steps=1000, runs=5):
+    """The 128^2 PEC cavity (1000 steps, Gaussian source, 4 probes): a grid
+    that fits one XCD's L2 many times over, so a step costs its launch; the
+    median of `runs` timed runs of the default kernel."""
+    from paper_2405_00814_amd import workloads as W
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.cavity2d(128, steps=steps, seed=0)
+    s = Sim.from_problem(pb)
+    ts, launches = [], 0
+    s.step(steps)
+    for _ in range(runs):
+        s.reset()
+        t, _, launches = timed_steps(s, steps, 0)
+        ts.append(t)
+    cfg = s.get_kernel()
+    s.close()
+    t = float(np.median(ts))
+    return dict(workload="cavity2d_128x128_pec_gaussian", steps=steps, runs=runs, kernel=cfg,
+                gcells_per_s=pb.cells * steps / t / 1e9, us_per_step=t / steps * 1e6,
+                launches_per_step=launches / steps)
+
+
+def _ci95(v):
+    """Median, and the 95 % confidence interval of the mean (Student t)."""
+    v = np.asarray(v, np.float64)
+    tq = {2: 12.706, 3: 4.303, 4: 3.182, 5: 2.776, 6: 2.571, 7: 2.447, 8: 2.365}.get(len(v), 2.0)
+    h = tq * v.std(ddof=1) / math.sqrt(len(v)) if len(v) > 1 else 0.0
+    return float(np.median(v)), float(v.mean() - h), float(v.mean() + h)
+
+
+def bench_sweep(args, sides=(250, 1000, 2000, 3000, 4000, 5000, 6400), steps=1024, runs=5):
+    """The paper's timing experiment in shape: free-space squares of the
+    given sides with a 16-cell CPML and a Gaussian source at the centre,
+    1024 steps, `runs` timed runs each: Gcell-updates/s median and 95 %
+    confidence interval, default kernel."""
+    from paper_2405_00814_amd import workloads as W
+    from paper_2405_00814_amd.sim import Sim
+    out = []
+    for n in sides:
+        pb = W.freespace2d(n, steps=steps)
+        s = Sim.from_problem(pb)
+        s.step(8)
+        rates = []
+        for _ in range(runs):
+            s.reset()
+            t, _, _ = timed_steps(s, steps, 0)
+            rates.append(pb.cells * steps / t / 1e9)
+        k = s.get_kernel()
+        s.close()
+        med, lo, hi = _ci95(rates)
+        out.append(dict(side=n, cells=pb.cells, kernel_variant=k["variant"], gcells_per_s=med,
+                        ci95=[lo, hi], seconds_per_sim=pb.cells * steps / (med * 1e9)))
+    return dict(workload="freespace2d_sides_250_6400_cpml16_1024steps", steps=steps, runs=runs,
+                points=out)
 
 
 def bench_adjoint(args):
@@ -264,54 +344,103 @@ def bench_adjoint(args):
     same = bool(loss_f == loss and torch.equal(grad_f, grad))
     s.close()
     return dict(workload="adjoint2d_1024x1024_design_256x256_T4000", steps=pb.steps,
-                forward_ms=tf, adjoint_ms=ta, adjoint_over_forward=ta / tf,
+                forward_ms=tf, forward_gcells_per_s=pb.cells * pb.steps / (tf / 1e3) / 1e9,
+                forward_us_per_step=tf / pb.steps * 1e3, adjoint_ms=ta, adjoint_over_forward=ta / tf,
                 checkpoint_interval=int(math.ceil(math.sqrt(pb.steps))),
                 no_recompute_ms=tn, no_recompute_over_forward=tn / tf, no_recompute_same_bits=same,
                 loss=loss, grad_finite=bool(np.isfinite(g).all()))
 
 
-def cpu_baseline(target_s=15.0):
-    """FP64 oracle on the host cores, on a bounded sample of the headline
-    workload: the first 48 x planes (incl. the low CPML slab) of the 512^3
-    scene, with as many steps as fit in about target_s seconds."""
+def _oracle_rate(planes, target_s, threads=None):
+    """Gcell-updates/s of the FP64 oracle on the first `planes` x planes of
+    the 512^3 scene (CPML on the five faces it keeps), as many steps as fit
+    in about target_s seconds; threads: OpenMP threads (None: all)."""
+    import ctypes as C
     from oracle import oracle as O
     from paper_2405_00814_amd import workloads as W
+    gomp = C.CDLL("libgomp.so.1")
     pb = W.yee3d(512, steps=1, seed=0)
-    sub = (48, 512, 512)
-    o = O.Oracle3D(sub, pb.dx, pb.dt, pb.eps_r[:48], None, None, (12, 0, 12, 12, 12, 12), pb.cpml)
-    o.set_source((20, 256, 256), pb.source.kind, pb.source.params)
-    o.set_probes([(30, 100, 100)])
-    o.run(2)  # warm-up (thread start, first touch)
-    t0 = time.perf_counter()
-    o.run(4)
-    t1 = time.perf_counter() - t0
-    n = max(2, int(target_s / max(t1 / 4, 1e-3)))
-    t0 = time.perf_counter()
-    o.run(n)
-    t = time.perf_counter() - t0
+    sub = (planes, 512, 512)
+    o = O.Oracle3D(sub, pb.dx, pb.dt, pb.eps_r[:planes], None, None, (12, 0, 12, 12, 12, 12), pb.cpml)
+    o.set_source((min(20, planes - 2), 256, 256), pb.source.kind, pb.source.params)
+    o.set_probes([(planes - 2, 100, 100)])
+    if threads:
+        gomp.omp_set_num_threads(int(threads))
+    try:
+        o.run(2)  # warm-up (thread start, first touch)
+        t0 = time.perf_counter()
+        o.run(2)
+        t1 = time.perf_counter() - t0
+        n = max(2, int(target_s / max(t1 / 2, 1e-3)))
+        t0 = time.perf_counter()
+        o.run(n)
+        t = time.perf_counter() - t0
+    finally:
+        if threads:
+            gomp.omp_set_num_threads(len(os.sched_getaffinity(0)))
+    return int(np.prod(sub)) * n / t / 1e9, n, t
+
+
+def cpu_baseline(target_s=12.0):
+    """FP64 oracle on the host cores, on a bounded sample of the headline
+    workload: the first 48 x planes (incl. the low CPML slab) of the 512^3
+    scene with all cores, the first 12 with one core."""
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return dict(value=int(np.prod(sub)) * n / t / 1e9, unit="Gcell-updates/s", cores=cores,
-                kind="oracle",
+    v, n, t = _oracle_rate(48, target_s)
+    v1, n1, t1 = _oracle_rate(12, target_s / 3, threads=1)
+    return dict(value=v, unit="Gcell-updates/s", cores=cores, kind="oracle",
+                cpu_model=cpu_model(), single_thread_value=v1,
                 sample="FP64 oracle, first 48 x-planes of the 512^3 scene (48x512x512 cells, "
-                       "CPML on 5 faces), %d steps, %.1f s" % (n, t))
+                       "CPML on 5 faces), %d steps, %.1f s on %d threads; single thread: first 12 "
+                       "x-planes, %d steps, %.1f s" % (n, t, cores, n1, t1))
+
+
+def stream_copy(nbytes=1 << 30, reps=10):
+    """The library's copy kernel (fdtd_stream_copy) on two nbytes device
+    buffers: bytes read plus written per second, the practical HBM ceiling."""
+    import ctypes as C
+    import torch
+    from paper_2405_00814_amd import _lib as L
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    lib = L.load()
+
+    def go():
+        L.check(lib.fdtd_stream_copy(C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()), nbytes,
+                                     C.c_void_p(st.cuda_stream)), "fdtd_stream_copy")
+    for _ in range(3):
+        go()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        go()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:1024], b[:1024]) and torch.equal(a[-1024:], b[-1024:]))
+    del a, b
+    return dict(bytes=nbytes, ms=ms, GBps=2 * nbytes / (ms / 1e3) / 1e9, correct=ok)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_calibration(nbytes=1 << 30, reps=5):
-    """A plain device copy of known size (torch's copy kernel): the reference
-    point that scales rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes."""
-    import torch
-    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps(dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes, reps=reps, ms=ms,
-                          GBps=2 * nbytes / (ms / 1e3) / 1e9)), flush=True)
+    """A plain device copy of known size (the library's copy kernel,
+    k_stream_copy): the reference point that scales rocprofv3's FETCH_SIZE /
+    WRITE_SIZE readings to bytes."""
+    r = stream_copy(nbytes, reps)
+    print(json.dumps(dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes, reps=reps, ms=r["ms"],
+                          GBps=r["GBps"])), flush=True)
 
 
 def main():
@@ -342,19 +471,30 @@ def main():
     src3 = os.path.join(ROOT, "paper_2405_00814_amd", "csrc", "k3dt.hip" if two else "k3dw.hip")
     traffic = traffic_record("yee3d_512_two" if two else "yee3d_512_interior", src3)
     dcells = r["prof"][r["dom"]]["cells"]
-    roof = dict(bound="hbm", achieved=r["dom_achieved"] / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                frac=r["dom_achieved"] / PEAK_HBM, traffic=traffic,
+    launch_s = r["dom_ms"] / 1e3
+    copy = stream_copy()
+    # achieved: the algorithmic bytes one launch must move (its cells' state
+    # read once and written once, coefficient maps and CPML values once: one
+    # pass, whatever the steps it advances) over its mean duration
+    achieved = r["dom_pass_bytes"] / launch_s
+    roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                frac=achieved / PEAK_HBM,
+                traffic=traffic,
+                traffic_GBps=(traffic / launch_s / 1e9) if traffic else None,
                 kernel=("k3d_two launch (interior tiles, two steps per pass, z-slab CPML)" if two
                         else "k3d_march interior launch (z-slab CPML only)"),
-                bytes_per_launch=r["dom_bytes"], bytes_per_cell_update=r["dom_bpc"],
-                steps_per_launch=r["dom_steps"], cells_per_launch=dcells,
+                bytes_per_launch=r["dom_pass_bytes"], bytes_per_cell_per_pass=r["dom_bpc"],
+                cells_per_launch=dcells, steps_per_launch=r["dom_steps"],
                 cell_updates_per_launch=r["dom_steps"] * dcells,
                 psi_per_launch=r["prof"][r["dom"]]["psi"], avg_launch_ms=r["dom_ms"],
-                min_bytes_per_launch=r["dom_pass_bytes"],
-                pass_frac=r["dom_pass_bytes"] / (r["dom_ms"] / 1e3) / PEAK_HBM,
+                stream_copy_GBps=copy["GBps"], frac_of_stream_copy=achieved / 1e9 / copy["GBps"],
+                # the same launch counted per cell-update (bytes of one step
+                # per step it advances): above 1 when steps share a pass
+                step_equiv_achieved=r["dom_achieved"] / 1e9, step_equiv_frac=r["dom_achieved"] / PEAK_HBM,
                 step=dict(launches_per_step=r["launches"] / args.steps,
                           bytes_per_step=r["bytes"], bytes_per_cell_update=r["bytes"] / pb.cells,
-                          achieved=r["step_achieved"] / 1e9, frac=r["step_achieved"] / PEAK_HBM,
+                          step_equiv_achieved=r["step_achieved"] / 1e9,
+                          step_equiv_frac=r["step_achieved"] / PEAK_HBM,
                           launch_ms=[round(x["ms"], 4) for x in r["prof"]],
                           launch_cells=[x["cells"] for x in r["prof"]],
                           launch_steps=[x["steps"] for x in r["prof"]]))
@@ -366,6 +506,10 @@ def main():
         forms["batched"] = bench_batch(args)
         log("adjoint ...")
         forms["adjoint"] = bench_adjoint(args)
+        log("cavity ...")
+        forms["cavity128"] = bench_cavity(args)
+        log("sweep ...")
+        forms["sweep"] = bench_sweep(args)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline ...")

@@ -197,15 +197,26 @@ int fdtd_get_dft(fdtd_sim *sim, double *re, double *im, int64_t *nsteps);
 int fdtd_dft_sar(fdtd_sim *sim, const float *rho, const double *norm, float *sar);
 
 /* Probe cells (ijk: n*ndim int32, host) sampled on `component` after every
- * step.  Replaces earlier probes and clears the record.  n <= 4096. */
+ * step: the waveform at chosen points that the paper records from each
+ * run (Sec. V-A, the time-domain waveforms of its Fig. 2).  Replaces
+ * earlier probes and clears the record.  n <= 4096; cells inside the grid,
+ * else FDTD_EINVAL. */
 int fdtd_set_probes(fdtd_sim *sim, int component, const int32_t *ijk, int32_t n);
 
-/* Enqueue n >= 0 steps on the handle's stream (asynchronous). */
+/* Enqueue n >= 0 leapfrog steps on the handle's stream (asynchronous):
+ * each step is the two message-passing layers of Prop. 2 (Sec. IV-A), the
+ * H layer then the E layer, with the CPML terms, then the soft source and
+ * the probe samples.  The kernel configuration (fdtd_set_kernel) decides
+ * how steps are grouped into passes over memory; the result is the same
+ * leapfrog.  FDTD_EINVAL for n < 0; errors of earlier asynchronous work
+ * surface at the next synchronising call. */
 int fdtd_step(fdtd_sim *sim, int64_t n);
 
-/* Copy the probe record to host memory out[p*cap + s] for the samples
- * s < min(cap, recorded) of probe p; *n_recorded = samples recorded since
- * the probes were set.  Synchronises.  out may be NULL to query. */
+/* Copy the probe record (the waveforms of Sec. V-A) to host memory
+ * out[p*cap + s] for the samples s < min(cap, recorded) of probe p, sample
+ * s being the field after step s since the probes were set;
+ * *n_recorded = samples recorded since then.  Synchronises.  out may be
+ * NULL to query; FDTD_EINVAL for cap < 0. */
 int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
 
 /* fdtd_probe for callers that cannot allocate device memory (code running
@@ -221,13 +232,35 @@ int fdtd_probe(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
  * the caller. */
 int fdtd_probe_noalloc(fdtd_sim *sim, float *out, int64_t cap, int64_t *n_recorded);
 
-/* Copy one component (nx*ny*nz float32, same layout as the maps) to dst.
- * dst_on_device != 0: dst is device memory, the copy is enqueued on the
- * stream; else host memory and the call synchronises. */
+/* Copy one component (nx*ny*nz float32, same layout as the maps) to dst:
+ * the field snapshots of Sec. V-A (Fig. 2).  E components hold step n, H
+ * components step n - 1/2 after n steps (the leapfrog staggering of Eq.
+ * 7-9).  dst_on_device != 0: dst is device memory (caller-owned), the copy
+ * is enqueued on the stream; else host memory and the call synchronises.
+ * FDTD_EINVAL for a component the grid does not have (2D: Ez, Hx, Hy). */
 int fdtd_get_field(fdtd_sim *sim, int component, void *dst, int dst_on_device);
 
 /* Overwrite one component (tests, resume).  Same layout and flag. */
 int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_device);
+
+/* Whole-state checkpoint and resume (a run continued on another handle of
+ * the same problem gives the same bits as an uninterrupted run).  The
+ * state is everything a step reads: all field components and every CPML
+ * auxiliary array of the current state (the split-field PML: also Ezy;
+ * the explicit graph form: its node vector), and the step count, which
+ * fixes the source sample of the next step.  Probe records and
+ * frequency-domain sums are not part of it.
+ *   fdtd_state_bytes: size of the saved state in bytes (a 64-byte header,
+ *     then the arrays as float32).
+ *   fdtd_save_state: write it to dst (caller-owned, fdtd_state_bytes long;
+ *     device memory if dst_on_device, else host).  Synchronises.
+ *   fdtd_load_state: replace this handle's state by a saved one; the grid,
+ *     absorbing layer, split flag and form must match (FDTD_EINVAL
+ *     otherwise, state unchanged).  The probe record restarts empty.
+ *     Synchronises. */
+int fdtd_state_bytes(fdtd_sim *sim, int64_t *bytes);
+int fdtd_save_state(fdtd_sim *sim, void *dst, int dst_on_device);
+int fdtd_load_state(fdtd_sim *sim, const void *src, int src_on_device);
 
 /* Zero all fields, auxiliary CPML values, the probe record and the step
  * counter. */
@@ -354,6 +387,18 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n);
  * kept.  FDTD_EINVAL for other values (the configuration is then
  * unchanged). */
 int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax, int32_t txo);
+/* Autotuner of the batch: time every candidate configuration of
+ * fdtd_batch_set_kernel (tb in {4, 2}, tx in {8, 16, 32}, vmax in {1, 2,
+ * 4}, txo in {0, 4, 8} below tx) for trial_steps steps (8..4096; 64 runs one
+ * captured graph) after an 8-step warm-up, and keep the fastest.  The
+ * problems' state, step count and probe record lengths are saved before and
+ * restored after (the batch continues as if the call had not been made).
+ * The choice is cached in the JSON file named by $GEMFDTD_TUNE_CACHE (if
+ * set) under the device and the batch's size mix (count, cells, the sorted
+ * list of dimensions and material kinds) and reused without timing.
+ * out (4 int32, may be NULL): the chosen tb, tx, vmax, txo.  Synchronises.
+ * Device memory: a copy of the state while it runs. */
+int fdtd_batch_autotune(fdtd_batch *b, int32_t trial_steps, int32_t *out);
 int fdtd_batch_probe(fdtd_batch *b, int32_t problem, float *out, int64_t cap,
                      int64_t *n_recorded);
 int fdtd_batch_get_field(fdtd_batch *b, int32_t problem, int component, void *dst,
@@ -378,7 +423,10 @@ int fdtd_batch_cells(const fdtd_batch *b, int64_t *cells);
  * all T steps.
  * loss_out (host, may be NULL); grad_dev: device float32
  * [(i1-i0)*(j1-j0)], written.  On return the handle holds the forward state
- * after T steps and the probe record of the forward run. */
+ * after T steps and the probe record of the forward run.  FDTD_EINVAL
+ * (arguments) leaves the handle unchanged; after FDTD_ENOMEM (checkpoint or
+ * design buffers) or FDTD_EDEVICE the handle is usable, every block the
+ * call took is released, and its fields may have been reset to zero. */
 int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
                      const int32_t *design, int32_t ckpt_interval, double *loss_out,
                      float *grad_dev);
@@ -391,6 +439,30 @@ int fdtd_adjoint_eps(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1,
  * this call with grad_sigma_dev = NULL.  dL/d sigma is per S/m. */
 int fdtd_adjoint(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
                  int32_t ckpt_interval, double *loss_out, float *grad_eps_dev, float *grad_sigma_dev);
+
+/* Measurement: enqueue a device-to-device copy of `bytes` bytes from src
+ * to dst (device pointers, both and bytes multiples of 16, not
+ * overlapping) on `stream` (hipStream_t, NULL: null stream) with the
+ * library's copy kernel, one 16-byte vector per thread.  Its rate (bytes
+ * read plus written per second) is the practical HBM ceiling that the
+ * stepping kernels are reported against next to the published peak.
+ * Asynchronous; FDTD_EINVAL for misaligned or NULL arguments. */
+int fdtd_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* The same adjoint run with the gradient with respect to the H layer's
+ * per-cell weight as well: dL/d mu_r on the design box (Db = dt/(mu0 mu_r)
+ * weighs every message into an H node, Eq. 8-9; the paper's learnable
+ * components, Sec. I and VI).  Hx -= Db bx and Hy += Db by at every step, so
+ * dL/d mu_r = (Db / mu_r) sum over steps of (aHx bx - aHy by), with aHx,
+ * aHy the adjoints of Hx, Hy after the step's H layer; the brackets bx, by
+ * are rebuilt from the captured Ez of the design box and one row and
+ * column beyond it.  grad_mu_dev: device float32 [(i1-i0)*(j1-j0)] or
+ * NULL; any of the three may be NULL, not all.  With grad_mu_dev the
+ * design box must lie clear of the CPML slabs (FDTD_EINVAL otherwise).
+ * fdtd_adjoint is this call with grad_mu_dev = NULL. */
+int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t n1, const int32_t *design,
+                       int32_t ckpt_interval, double *loss_out, float *grad_eps_dev, float *grad_sigma_dev,
+                       float *grad_mu_dev);
 
 /* Thread-local text of the calling thread's last failure ("" if none). */
 const char *fdtd_last_error(void);

@@ -79,6 +79,9 @@ _SIGS = {
     "fdtd_probe_noalloc": (C.c_int, [P, f32p, i64, i64p]),
     "fdtd_get_field": (C.c_int, [P, C.c_int, P, C.c_int]),
     "fdtd_set_field": (C.c_int, [P, C.c_int, P, C.c_int]),
+    "fdtd_state_bytes": (C.c_int, [P, i64p]),
+    "fdtd_save_state": (C.c_int, [P, P, C.c_int]),
+    "fdtd_load_state": (C.c_int, [P, P, C.c_int]),
     "fdtd_reset": (C.c_int, [P]),
     "fdtd_steps_done": (C.c_int, [P, i64p]),
     "fdtd_check_finite": (C.c_int, [P]),
@@ -94,12 +97,15 @@ _SIGS = {
     "fdtd_batch_set_probes": (C.c_int, [P, i32, i32p, i32]),
     "fdtd_batch_step": (C.c_int, [P, i64]),
     "fdtd_batch_set_kernel": (C.c_int, [P, i32, i32, i32, i32]),
+    "fdtd_batch_autotune": (C.c_int, [P, i32, i32p]),
     "fdtd_batch_probe": (C.c_int, [P, i32, f32p, i64, i64p]),
     "fdtd_batch_get_field": (C.c_int, [P, i32, C.c_int, P, C.c_int]),
     "fdtd_batch_last_step_time": (C.c_int, [P, C.POINTER(C.c_float), i64p]),
     "fdtd_batch_cells": (C.c_int, [P, i64p]),
     "fdtd_adjoint_eps": (C.c_int, [P, i64, i64, i64, i32p, i32, f64p, f32p]),
     "fdtd_adjoint": (C.c_int, [P, i64, i64, i64, i32p, i32, f64p, f32p, f32p]),
+    "fdtd_adjoint_grads": (C.c_int, [P, i64, i64, i64, i32p, i32, f64p, f32p, f32p, f32p]),
+    "fdtd_stream_copy": (C.c_int, [P, P, C.c_size_t, P]),
     "fdtd_last_error": (C.c_char_p, []),
     "fdtd_version": (C.c_char_p, []),
 }

@@ -13,8 +13,11 @@
 // number from a device counter, which lets a captured HIP graph of passes be
 // replayed for any step range.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
+#include <tuple>
 
 #include "sim.hpp"
 
@@ -436,6 +439,127 @@ int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax, i
         return FDTD_OK;
     } catch (...) {
         return gem::status_of_current_exception();
+    }
+}
+
+// Autotuner of the batch: every candidate (steps per pass, rows per tile,
+// widest vector, rows per CPML tile) times trial_steps steps of the whole
+// batch (one captured graph when trial_steps >= 64) after a short warm-up;
+// the fastest is kept.  The state of every problem (fields and CPML values
+// of the current buffer set), the step count and the probe records'
+// lengths are saved first and restored after, so the batch continues as if
+// the call had not been made.  Cached in $GEMFDTD_TUNE_CACHE under the
+// device and the batch's size mix.
+int fdtd_batch_autotune(fdtd_batch *b, int32_t trial_steps, int32_t *out) {
+    std::vector<void *> tmp;
+    try {
+        if (!b) fail(FDTD_EINVAL, "batch is NULL");
+        if (trial_steps < 8 || trial_steps > 4096) fail(FDTD_EINVAL, "trial_steps must be in [8, 4096]");
+        hipDeviceProp_t pr{};
+        std::string arch = "unknown";
+        if (hipGetDeviceProperties(&pr, b->sims[0]->device) == hipSuccess) arch = pr.gcnArchName;
+        // size mix: count, and a hash of the sorted (nx, ny, material kind) list
+        std::vector<std::tuple<int, int, int>> dims;
+        int64_t cells = 0;
+        for (auto *sp : b->sims) {
+            dims.emplace_back(sp->nx, sp->ny, sp->mat());
+            cells += sp->ncell;
+        }
+        std::sort(dims.begin(), dims.end());
+        uint64_t h = 1469598103934665603ull;
+        for (auto &d : dims)
+            for (int v : {std::get<0>(d), std::get<1>(d), std::get<2>(d)}) {
+                h ^= (uint64_t)(uint32_t)v;
+                h *= 1099511628211ull;
+            }
+        char key[160];
+        snprintf(key, sizeof key, "%s|batch|n%zu|c%lld|h%016llx", arch.c_str(), dims.size(), (long long)cells,
+                 (unsigned long long)h);
+        const char *path = std::getenv("GEMFDTD_TUNE_CACHE");
+        std::map<std::string, std::vector<int>> cache;
+        if (path) cache = read_cache(path);
+        auto it = cache.find(key);
+        std::vector<int> best;
+        if (it != cache.end() && it->second.size() == 4) {
+            best = it->second;
+        } else {
+            // save the state
+            hip_check(hipStreamSynchronize(b->st), "sync");
+            const int cur = b->cur;
+            const int64_t n_done = b->n_done;
+            std::vector<int64_t> n_rec;
+            std::vector<std::pair<float *, size_t>> parts;
+            for (auto *sp : b->sims) {
+                n_rec.push_back(sp->n_rec);
+                for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) parts.emplace_back(sp->f[cur][c], (size_t)sp->ncell);
+                for (int a = 0; a < 4; ++a)
+                    if (sp->psi[cur][a]) parts.emplace_back(sp->psi[cur][a], (size_t)sp->psi_len[a]);
+            }
+            size_t total = 0;
+            for (auto &p : parts) total += p.second;
+            float *save = (float *)b->al.get(total * 4);
+            tmp.push_back(save);
+            size_t off = 0;
+            for (auto &p : parts) {
+                hip_check(hipMemcpyAsync(save + off, p.first, p.second * 4, hipMemcpyDeviceToDevice, b->st), "save");
+                off += p.second;
+            }
+            const int old[4] = {b->tb, b->tb_tx, b->tb_vmax, b->tb_txo};
+            float best_ms = 1e30f;
+            for (int tb : {4, 2})
+                for (int tx : {8, 16, 32})
+                    for (int vmax : {1, 2, 4})
+                        for (int txo : {0, 4, 8}) {
+                            if (txo >= tx) continue;
+                            if (fdtd_batch_set_kernel(b, tb, tx, vmax, txo) != FDTD_OK) continue;
+                            if (fdtd_batch_step(b, 8) != FDTD_OK) continue;
+                            if (fdtd_batch_step(b, trial_steps) != FDTD_OK) continue;
+                            float ms = 0;
+                            int64_t launches = 0;
+                            if (fdtd_batch_last_step_time(b, &ms, &launches) != FDTD_OK) continue;
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                best = {tb, tx, vmax, txo};
+                            }
+                        }
+            // restore the state (the buffer set, step count, records)
+            hip_check(hipStreamSynchronize(b->st), "sync");
+            off = 0;
+            for (auto &p : parts) {
+                hip_check(hipMemcpyAsync(p.first, save + off, p.second * 4, hipMemcpyDeviceToDevice, b->st), "restore");
+                off += p.second;
+            }
+            b->cur = cur;
+            b->n_done = n_done;
+            for (size_t q = 0; q < b->sims.size(); ++q) {
+                Sim &s = *b->sims[q];
+                s.cur = cur;
+                s.n_done = n_done;
+                s.n_rec = n_rec[q];
+            }
+            hip_check(hipStreamSynchronize(b->st), "sync");
+            for (void *p : tmp) b->al.put(p);
+            tmp.clear();
+            if (best.empty()) {
+                fdtd_batch_set_kernel(b, old[0], old[1], old[2], old[3]);
+                fail(FDTD_EDEVICE, "no batch configuration ran");
+            }
+            if (path) {
+                cache[key] = best;
+                write_cache(path, cache);
+            }
+        }
+        const int rc = fdtd_batch_set_kernel(b, best[0], best[1], best[2], best[3]);
+        if (rc != FDTD_OK) return rc;
+        if (out)
+            for (int q = 0; q < 4; ++q) out[q] = best[(size_t)q];
+        set_error("");
+        return FDTD_OK;
+    } catch (...) {
+        const int rc = gem::status_of_current_exception();
+        if (b)
+            for (void *p : tmp) b->al.put(p);
+        return rc;
     }
 }
 

@@ -350,6 +350,14 @@ void Sim::build_probe_tiles() {
     if (pt_ntiles >= 0 && pt_cfg[0] == a && pt_cfg[1] == b && pt_cfg[2] == (int)probe_cells.size() &&
         pt_cfg[3] == c3 && pt_cfg[4] == vm && pt_cfg[5] == kcfg.tile[3] && pt_start)
         return;
+    // invalid until the rebuild completes: a failure below (out of memory)
+    // leaves the cache empty, and every stepping call rebuilds before it
+    // launches; each list is uploaded before its predecessor is released
+    pt_ntiles = -1;
+    auto swap_in = [&](auto *&slot, auto *fresh) {
+        al.put(slot);
+        slot = fresh;
+    };
     if (ndim == 2) {
         const Fused2DCfg c = single2d();
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi};
@@ -359,27 +367,23 @@ void Sim::build_probe_tiles() {
         tl2_inner = (int)ids.size();
         tl2_outer = (int)outer.size();
         ids.insert(ids.end(), outer.begin(), outer.end());
-        al.put(tl2_dev);
-        tl2_dev = dev_upload(al, ids.data(), std::max<size_t>(ids.size(), 1), st);
+        swap_in(tl2_dev, dev_upload(al, ids.data(), std::max<size_t>(ids.size(), 1), st));
     }
     if (ndim == 3) {
         const int xl[2] = {ax[0].lo, ax[0].hi}, yl[2] = {ax[1].lo, ax[1].hi}, zl[2] = {ax[2].lo, ax[2].hi};
         wave3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, xl, yl, zl, plan3);
-        al.put(tl_dev);
-        tl_dev = dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st);
+        swap_in(tl_dev, dev_upload(al, plan3.tiles.data(), plan3.tiles.size(), st));
         if (kcfg.variant == 3) {
             two3d_plan(nx, ny, nz, Fused3DCfg{a, c3}, mat, b == 0, kcfg.tile[3], cus, xl, yl, zl, plan2);
             plan2_mat = mat;
-            al.put(tb_dev);
-            al.put(tbo_dev);
-            al.put(p1_dev);
-            al.put(p2_dev);
-            tb_dev = plan2.tb.empty() ? nullptr : dev_upload(al, plan2.tb.data(), plan2.tb.size(), st);
-            tbo_dev = plan2.tbo.empty() ? nullptr : dev_upload(al, plan2.tbo.data(), plan2.tbo.size(), st);
-            p1_dev = plan2.pass1.tiles.empty() ? nullptr
-                                               : dev_upload(al, plan2.pass1.tiles.data(), plan2.pass1.tiles.size(), st);
-            p2_dev = plan2.pass2.tiles.empty() ? nullptr
-                                               : dev_upload(al, plan2.pass2.tiles.data(), plan2.pass2.tiles.size(), st);
+            swap_in(tb_dev, plan2.tb.empty() ? nullptr : dev_upload(al, plan2.tb.data(), plan2.tb.size(), st));
+            swap_in(tbo_dev, plan2.tbo.empty() ? nullptr : dev_upload(al, plan2.tbo.data(), plan2.tbo.size(), st));
+            swap_in(p1_dev, plan2.pass1.tiles.empty()
+                                ? nullptr
+                                : dev_upload(al, plan2.pass1.tiles.data(), plan2.pass1.tiles.size(), st));
+            swap_in(p2_dev, plan2.pass2.tiles.empty()
+                                ? nullptr
+                                : dev_upload(al, plan2.pass2.tiles.data(), plan2.pass2.tiles.size(), st));
             alloc_set(2);
         }
     }
@@ -411,13 +415,9 @@ void Sim::build_probe_tiles() {
         start[(size_t)tile[order[q]] + 1]++;
     }
     for (int t = 0; t < ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
-    al.put(pt_start);
-    al.put(pt_cell);
-    al.put(pt_slot);
-    pt_start = dev_upload(al, start.data(), start.size(), st);
-    pt_cell = dev_upload(al, cell.data(), std::max<size_t>(cell.size(), 1), st);
-    pt_slot = dev_upload(al, slot.data(), std::max<size_t>(slot.size(), 1), st);
-    pt_ntiles = ntiles;
+    swap_in(pt_start, dev_upload(al, start.data(), start.size(), st));
+    swap_in(pt_cell, dev_upload(al, cell.data(), std::max<size_t>(cell.size(), 1), st));
+    swap_in(pt_slot, dev_upload(al, slot.data(), std::max<size_t>(slot.size(), 1), st));
     pt_cfg[0] = a;
     pt_cfg[1] = b;
     pt_cfg[2] = (int)probe_cells.size();
@@ -432,8 +432,7 @@ void Sim::build_probe_tiles() {
         tb2_inner = (int)in.size();
         tb2_outer = (int)out.size();
         in.insert(in.end(), out.begin(), out.end());
-        al.put(tb2_dev);
-        tb2_dev = dev_upload(al, in.data(), std::max<size_t>(in.size(), 1), st);
+        swap_in(tb2_dev, dev_upload(al, in.data(), std::max<size_t>(in.size(), 1), st));
         // probe groups by position in the list: the tile starting at or
         // last before the probe's row in its strip
         const int ow = tb2d_own(V, TB), nstrip = (ny + ow - 1) / ow;
@@ -456,13 +455,11 @@ void Sim::build_probe_tiles() {
             st2[(size_t)tl[ord[q]] + 1]++;
         }
         for (size_t t = 0; t < in.size(); ++t) st2[t + 1] += st2[t];
-        al.put(pt2_start);
-        al.put(pt2_cell);
-        al.put(pt2_slot);
-        pt2_start = dev_upload(al, st2.data(), st2.size(), st);
-        pt2_cell = dev_upload(al, ce.data(), std::max<size_t>(ce.size(), 1), st);
-        pt2_slot = dev_upload(al, sl.data(), std::max<size_t>(sl.size(), 1), st);
+        swap_in(pt2_start, dev_upload(al, st2.data(), st2.size(), st));
+        swap_in(pt2_cell, dev_upload(al, ce.data(), std::max<size_t>(ce.size(), 1), st));
+        swap_in(pt2_slot, dev_upload(al, sl.data(), std::max<size_t>(sl.size(), 1), st));
     }
+    pt_ntiles = ntiles;
 }
 
 Fused2DCfg Sim::single2d() const {
@@ -564,13 +561,23 @@ void Sim::launch_step(int64_t step) {
 void Sim::alloc_set(int set) {
     if (f[set][FDTD_EZ]) return;
     const size_t n = (size_t)ncell;
-    if (ndim == 2) {
-        for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) f[set][c] = (float *)al.get(n * 4);
-    } else {
-        for (int c = 0; c < 6; ++c) f[set][c] = (float *)al.get(n * 4);
+    // all or nothing: a set is used only when every array of it exists
+    float *nf[6] = {}, *np[NPSI3] = {};
+    try {
+        if (ndim == 2) {
+            for (int c : {FDTD_EZ, FDTD_HX, FDTD_HY}) nf[c] = (float *)al.get(n * 4);
+        } else {
+            for (int c = 0; c < 6; ++c) nf[c] = (float *)al.get(n * 4);
+        }
+        for (int a = 0; a < NPSI3; ++a)
+            if (psi_len[a] > 0) np[a] = (float *)al.get((size_t)psi_len[a] * 4);
+    } catch (...) {
+        for (float *p : nf) al.put(p);
+        for (float *p : np) al.put(p);
+        throw;
     }
-    for (int a = 0; a < NPSI3; ++a)
-        if (psi_len[a] > 0) psi[set][a] = (float *)al.get((size_t)psi_len[a] * 4);
+    for (int c = 0; c < 6; ++c) f[set][c] = nf[c];
+    for (int a = 0; a < NPSI3; ++a) psi[set][a] = np[a];
 }
 
 // Two steps n -> n+2 from set cur into set 1-cur.  Slab tiles in the
@@ -913,7 +920,7 @@ static std::string tune_key(const Sim &s) {
     return o.str();
 }
 
-static std::map<std::string, std::vector<int>> read_cache(const char *path) {
+std::map<std::string, std::vector<int>> read_cache(const char *path) {
     std::map<std::string, std::vector<int>> m;
     std::ifstream f(path);
     if (!f) return m;
@@ -939,7 +946,7 @@ static std::map<std::string, std::vector<int>> read_cache(const char *path) {
     return m;
 }
 
-static void write_cache(const char *path, const std::map<std::string, std::vector<int>> &m) {
+void write_cache(const char *path, const std::map<std::string, std::vector<int>> &m) {
     const std::string tmp = std::string(path) + ".tmp";
     std::ofstream f(tmp);
     if (!f) return;
@@ -1497,6 +1504,119 @@ int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_dev
               "copy");
     // split-field PML: a set Ez is all Ezx
     if (s.split && component == FDTD_EZ) hip_check(hipMemsetAsync(s.ezy, 0, bytes, s.st), "memset");
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+// ---------------------------------------------------------------------------
+// Whole-state save / restore: a 64-byte header (magic, grid, layer widths,
+// form, step count), then every field and CPML array of the current state
+// set in a fixed order (implicit form), or the node vector (graph form).
+// ---------------------------------------------------------------------------
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t ndim, nx, ny, nz;
+    int32_t npml[6];
+    int32_t split, graph;
+    int64_t n_done;
+};
+static_assert(sizeof(StateHeader) <= 64, "state header");
+constexpr char kStateMagic[8] = {'G', 'E', 'M', 'S', 'T', 'A', 'T', '1'};
+
+StateHeader state_header(const Sim &s) {
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.ndim = s.ndim;
+    h.nx = s.nx;
+    h.ny = s.ny;
+    h.nz = s.nz;
+    for (int q = 0; q < 6; ++q) h.npml[q] = s.cpml.npml[q];
+    h.split = s.split ? 1 : 0;
+    h.graph = s.is_graph ? 1 : 0;
+    h.n_done = s.n_done;
+    return h;
+}
+
+// (device pointer, bytes) of every array of the state, in file order
+std::vector<std::pair<float *, size_t>> state_arrays(Sim &s) {
+    std::vector<std::pair<float *, size_t>> v;
+    if (s.is_graph) {
+        v.emplace_back(s.g.x, (size_t)s.g.nnodes * 4);
+        return v;
+    }
+    for (int c = 0; c < 6; ++c)
+        if (s.f[s.cur][c]) v.emplace_back(s.f[s.cur][c], (size_t)s.ncell * 4);
+    for (int a = 0; a < NPSI3; ++a)
+        if (s.psi[s.cur][a]) v.emplace_back(s.psi[s.cur][a], (size_t)s.psi_len[a] * 4);
+    if (s.ezy) v.emplace_back(s.ezy, (size_t)s.ncell * 4);
+    return v;
+}
+
+int64_t state_size(Sim &s) {
+    int64_t n = 64;
+    for (auto &a : state_arrays(s)) n += (int64_t)a.second;
+    return n;
+}
+}  // namespace
+
+int fdtd_state_bytes(fdtd_sim *sim, int64_t *bytes) {
+    GEM_TRY
+    if (!sim || !bytes) fail(FDTD_EINVAL, "NULL argument");
+    *bytes = state_size(sim->s);
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_save_state(fdtd_sim *sim, void *dst, int dst_on_device) {
+    GEM_TRY
+    if (!sim || !dst) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    if (s.dft.comp >= 0) s.dft_flush();
+    const StateHeader h = state_header(s);
+    char hb[64] = {};
+    std::memcpy(hb, &h, sizeof h);
+    const hipMemcpyKind up = dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    const hipMemcpyKind down = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hip_check(hipMemcpyAsync(dst, hb, 64, up, s.st), "state copy");
+    size_t off = 64;
+    for (auto &a : state_arrays(s)) {
+        hip_check(hipMemcpyAsync((char *)dst + off, a.first, a.second, down, s.st), "state copy");
+        off += a.second;
+    }
+    // the header leaves from host memory: wait for it in either case
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    return FDTD_OK;
+    GEM_CATCH
+}
+
+int fdtd_load_state(fdtd_sim *sim, const void *src, int src_on_device) {
+    GEM_TRY
+    if (!sim || !src) fail(FDTD_EINVAL, "NULL argument");
+    Sim &s = sim->s;
+    StateHeader h{};
+    if (src_on_device) {
+        hip_check(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDeviceToHost, s.st), "state copy");
+        hip_check(hipStreamSynchronize(s.st), "sync");
+    } else {
+        std::memcpy(&h, src, sizeof h);
+    }
+    const StateHeader mine = state_header(s);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0) fail(FDTD_EINVAL, "not a saved state");
+    bool same = h.ndim == mine.ndim && h.nx == mine.nx && h.ny == mine.ny && h.nz == mine.nz &&
+                h.split == mine.split && h.graph == mine.graph;
+    for (int q = 0; q < 6; ++q) same = same && h.npml[q] == mine.npml[q];
+    if (!same) fail(FDTD_EINVAL, "the saved state belongs to a different grid, absorbing layer or form");
+    if (h.n_done < 0) fail(FDTD_EINVAL, "invalid step count in the saved state");
+    const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    size_t off = 64;
+    for (auto &a : state_arrays(s)) {
+        hip_check(hipMemcpyAsync(a.first, (const char *)src + off, a.second, kind, s.st), "state copy");
+        off += a.second;
+    }
+    s.n_done = h.n_done;
+    s.n_rec = 0;
     hip_check(hipStreamSynchronize(s.st), "sync");
     return FDTD_OK;
     GEM_CATCH

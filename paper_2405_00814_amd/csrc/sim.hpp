@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -217,6 +218,10 @@ int64_t graph_layer_nnz_max(int nx, int ny, int sx, int sy, bool split);
 // configuration of a simulation (runtime.cpp)
 Fused2DCfg default_single2d(int nx, int ny);
 int default_variant_tiles(const Sim &s, fdtd_kernel_config &k);
+
+// autotuner cache: a JSON object of key -> integer list (runtime.cpp)
+std::map<std::string, std::vector<int>> read_cache(const char *path);
+void write_cache(const char *path, const std::map<std::string, std::vector<int>> &m);
 
 // creation helpers (runtime.cpp)
 void validate_desc(const fdtd_desc *d);

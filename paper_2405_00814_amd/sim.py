@@ -244,6 +244,23 @@ class Sim:
         a = np.ascontiguousarray(np.asarray(arr, np.float32).reshape(self.shape))
         L.call("fdtd_set_field", self.h, _comp(comp), a.ctypes.data_as(C.c_void_p), 0)
 
+    def save_state(self) -> np.ndarray:
+        """The whole stepping state (fdtd_save_state) as a host byte array."""
+        n = C.c_int64()
+        L.call("fdtd_state_bytes", self.h, C.byref(n))
+        buf = np.zeros(n.value, np.uint8)
+        L.call("fdtd_save_state", self.h, buf.ctypes.data_as(C.c_void_p), 0)
+        return buf
+
+    def load_state(self, buf: np.ndarray):
+        """Resume from a state saved by save_state (fdtd_load_state)."""
+        n = C.c_int64()
+        L.call("fdtd_state_bytes", self.h, C.byref(n))
+        b = np.ascontiguousarray(buf, np.uint8)
+        if b.size != n.value:
+            raise ValueError("saved state has %d bytes, this handle's state %d" % (b.size, n.value))
+        L.call("fdtd_load_state", self.h, b.ctypes.data_as(C.c_void_p), 0)
+
     def reset(self):
         L.call("fdtd_reset", self.h)
 
@@ -316,21 +333,26 @@ class Sim:
                int(ckpt_interval), C.byref(loss), C.cast(C.c_void_p(grad.data_ptr()), C.POINTER(C.c_float)))
         return loss.value, grad
 
-    def adjoint_grads(self, T, window, design, ckpt_interval=0):
+    def adjoint_grads(self, T, window, design, ckpt_interval=0, mu=False):
         """Loss and its gradients with respect to eps_r and sigma (per S/m)
         on the design box, from one adjoint run: (loss, g_eps, g_sigma) with
-        torch float32 CUDA tensors of the box size."""
+        torch float32 CUDA tensors of the box size; with mu, also the
+        gradient with respect to mu_r: (loss, g_eps, g_sigma, g_mu)."""
         torch = _torch()
         i0, i1, j0, j1 = design
         n = (i1 - i0) * (j1 - j0)
         ge = torch.empty(n, dtype=torch.float32, device="cuda")
         gs = torch.empty(n, dtype=torch.float32, device="cuda")
+        gm = torch.empty(n, dtype=torch.float32, device="cuda") if mu else None
         d = (C.c_int32 * 4)(*[int(v) for v in design])
         loss = C.c_double()
         fp = C.POINTER(C.c_float)
-        L.call("fdtd_adjoint", self.h, int(T), int(window[0]), int(window[1]), d, int(ckpt_interval),
-               C.byref(loss), C.cast(C.c_void_p(ge.data_ptr()), fp), C.cast(C.c_void_p(gs.data_ptr()), fp))
-        return loss.value, ge, gs
+
+        def ptr(t):
+            return C.cast(C.c_void_p(t.data_ptr()), fp) if t is not None else None
+        L.call("fdtd_adjoint_grads", self.h, int(T), int(window[0]), int(window[1]), d, int(ckpt_interval),
+               C.byref(loss), ptr(ge), ptr(gs), ptr(gm))
+        return (loss.value, ge, gs, gm) if mu else (loss.value, ge, gs)
 
 
 class Batch:
@@ -385,6 +407,13 @@ class Batch:
         """Steps per pass (1, 2, 4), rows per tile, widest column vector,
         rows per tile near a CPML slab (0: tx)."""
         L.call("fdtd_batch_set_kernel", self.h, int(tb), int(tx), int(vmax), int(txo))
+
+    def autotune(self, trial_steps=64):
+        """Time the batch configurations and keep the fastest
+        (fdtd_batch_autotune); returns (tb, tx, vmax, txo)."""
+        out = (C.c_int32 * 4)()
+        L.call("fdtd_batch_autotune", self.h, int(trial_steps), out)
+        return tuple(int(v) for v in out)
 
     def probe(self, q):
         n = C.c_int64()

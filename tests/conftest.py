@@ -9,6 +9,8 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    import helpers
+    helpers.PYTEST_CONFIG = config
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
     config.addinivalue_line("markers", "slow: long CPU test")
 

@@ -10,6 +10,21 @@ def log(*a):
     sys.stdout.flush()
 
 
+# set by conftest.py: the pytest config, for progress() below
+PYTEST_CONFIG = None
+
+
+def progress(*a):
+    """A progress line of a long test (a step of the work done), written
+    past pytest's output capture so that it appears while the test runs."""
+    capman = PYTEST_CONFIG.pluginmanager.getplugin("capturemanager") if PYTEST_CONFIG else None
+    if capman is None:
+        log(*a)
+        return
+    with capman.global_and_fixture_disabled():
+        print(*a, flush=True)
+
+
 def rel_l2(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -85,62 +100,77 @@ def assert_parity_energy(gpu, ref, pb, tol=1e-4, what=""):
     return e
 
 
-def group_norm(state, group):
-    """Norm of the E ("e") or H ("h") components of a state together."""
-    return float(np.sqrt(sum(float(np.sum(np.asarray(v, np.float64) ** 2))
-                             for k, v in state.items() if k.startswith(group))))
+def energy_weights(pb):
+    """Per-cell weights of the energy norm: eps0 eps_r for E components,
+    mu0 mu_r for H components (scalars when the map is absent)."""
+    we = EPS0 * (1.0 if pb.eps_r is None else np.asarray(pb.eps_r, np.float64))
+    wh = MU0 * (1.0 if pb.mu_r is None else np.asarray(pb.mu_r, np.float64))
+    return {"e": we, "h": wh}
 
 
-def run_oracle_tracked(o, steps, chunk, at=()):
+def _wnorm(a, w):
+    a = np.asarray(a, np.float64)
+    return float(np.sqrt(np.sum(w * a * a)))
+
+
+def state_energy_norm(state, w):
+    """sqrt(sum over cells and components of w f^2): the energy norm of a
+    state (field components keyed ex..hz), the norm the leapfrog conserves
+    in a lossless cavity."""
+    return float(np.sqrt(sum(_wnorm(v, w[k[0]]) ** 2 for k, v in state.items())))
+
+
+def run_oracle_tracked(o, steps, chunk, w, at=(), tag=None):
     """Advance the FP64 oracle `o` by `steps` in chunks of at most `chunk`,
-    tracking the largest norm the E and the H components reached (at the
-    chunk ends; a lower bound of the true peak).  Returns the probe record,
-    {"e": peak, "h": peak} and copies of the fields at the steps in `at`
-    (counted from o's start)."""
+    tracking the largest energy norm (weights w, energy_weights) the state
+    reached at the chunk ends (a lower bound of the true peak).  Returns the
+    probe record, that peak and copies of the fields at the steps in `at`
+    (counted from o's start).  With a tag, each chunk's end is reported by
+    progress()."""
     fields = o.fields
-    peaks = {"e": 0.0, "h": 0.0}
+    peak = 0.0
     snaps = {}
     stops = sorted(set(list(range(chunk, steps, chunk)) + [int(a) for a in at if 0 < a < steps] + [steps]))
     done, recs = 0, []
     for stop in stops:
         recs.append(o.run(stop - done))
         done = stop
-        st = {f: getattr(o, f) for f in fields}
-        for g in peaks:
-            peaks[g] = max(peaks[g], group_norm(st, g))
+        if tag:
+            progress("  %s: oracle step %d of %d" % (tag, done, steps))
+        peak = max(peak, state_energy_norm({f: getattr(o, f) for f in fields}, w))
         if done in at:
             snaps[done] = {f: getattr(o, f).copy() for f in fields}
-    return np.concatenate(recs, axis=1), peaks, snaps
+    return np.concatenate(recs, axis=1), peak, snaps
 
 
-def run_errors(got, ref, peaks):
-    """Per component: the literal rel-L2 ||got - ref|| / ||ref||, the error
-    relative to the peak norm of its field group over the run
-    ||got - ref|| / P_group, and ||ref|| / P_group."""
+def run_errors(got, ref, peak, w):
+    """Per component: the literal rel-L2 ||got - ref|| / ||ref||; its error
+    in the energy norm relative to the peak energy norm of the whole state
+    over the run, ||got - ref||_w / P; and ||ref||_w / P (its share)."""
     out = {}
     for k in ref:
-        d = float(np.linalg.norm((np.asarray(got[k], np.float64) - ref[k]).ravel()))
+        d = np.asarray(got[k], np.float64) - ref[k]
         n = float(np.linalg.norm(np.asarray(ref[k], np.float64).ravel()))
-        p = peaks[k[0]]
-        out[k] = (d / n if n > 0 else d, d / p, n / p)
+        dn = float(np.linalg.norm(d.ravel()))
+        out[k] = (dn / n if n > 0 else dn, _wnorm(d, w[k[0]]) / peak, _wnorm(ref[k], w[k[0]]) / peak)
     return out
 
 
 LIVE = 0.1
 
 
-def assert_run_parity(got, ref, peaks, tol=1e-4, what=""):
-    """The parity bar of a whole run at a checkpoint: every component within
-    tol of the peak norm its field group (E or H) reached over the run, and
-    every live component (norm at least LIVE of that peak) also within tol
-    of its own norm.  A component far below its group's peak (a pulse that
-    has been absorbed, the H of the static field a DC-carrying source
-    leaves) carries the rounding of the whole run in units of that peak:
-    no FP32 evaluation meets the literal bar there (the FP32 build of the
-    oracle shows it)."""
-    errs = run_errors(got, ref, peaks)
+def assert_run_parity(got, ref, peak, w, tol=1e-4, what=""):
+    """The parity bar of a whole run at a checkpoint: every component's error
+    in the energy norm within tol of the peak energy norm the state reached
+    over the run, and every live component (its own energy norm at least
+    LIVE of that peak) also within tol of its own norm (relative L2).  A
+    component far below the peak (a pulse that has been absorbed, the H of
+    the static field a DC-carrying source leaves) carries the rounding of
+    the whole run in units of that peak: no FP32 evaluation meets the
+    relative bar there (the FP32 build of the oracle shows it)."""
+    errs = run_errors(got, ref, peak, w)
     for k, (lit, grp, frac) in errs.items():
-        assert grp <= tol, "%s %s error / group peak %.3e > %.1e" % (what, k, grp, tol)
+        assert grp <= tol, "%s %s energy-norm error / peak %.3e > %.1e" % (what, k, grp, tol)
         if frac >= LIVE:
             assert lit <= tol, "%s %s rel-L2 %.3e > %.1e (live: %.2f of the peak)" % (what, k, lit, tol, frac)
     return errs

@@ -8,7 +8,7 @@ import pytest
 
 from paper_2405_00814_amd import workloads as W
 
-from helpers import assert_parity, assert_parity_energy, log, rel_l2, run_gpu, run_oracle
+from helpers import assert_parity, assert_parity_energy, fields_of, log, rel_l2, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -132,6 +132,64 @@ def test_resume_from_fields_bitwise():
     for k in full:
         assert np.array_equal(s.get_field(k), full[k]), k
     s.close()
+
+
+@pytest.mark.parametrize("case", ["2d_default", "2d_multi", "2d_split_ref", "2d_graph", "3d_default", "3d_two"])
+def test_resume_from_saved_state_with_cpml_bitwise(case):
+    """run(2N) == run(N) -> fdtd_save_state -> new handle -> fdtd_load_state
+    -> run(N), bit for bit in every field and in the probe samples of the
+    second half, with a CPML (its auxiliary values are part of the state), a
+    source still active across the cut (the step count is part of it), and
+    the split-field PML and the graph form."""
+    from paper_2405_00814_amd.sim import Sim
+    graph = case == "2d_graph"
+    if case.startswith("3d"):
+        pb = W.yee3d(shape=(40, 36, 48), steps=120, seed=3, nbox=5, side=(3, 10), npml=6, nprobes=3,
+                     tau_steps=10.0)
+        N = 60
+    else:
+        pb = W.dielectric2d(140, ny=128, steps=400, seed=6, nrect=5, side=(6, 30), npml=12, nprobes=3)
+        if case == "2d_split_ref":
+            pb.cpml = dict(split=1)
+            pb.sigma = None
+            pb.eps_r = np.ones(pb.shape, np.float32)
+        N = 200
+    kernel = {"2d_multi": (3, (1, 8, 4)), "2d_split_ref": (1,), "3d_two": (3, (4,))}.get(case)
+
+    def mk():
+        s = Sim.from_problem(pb, graph=graph)
+        if kernel is not None:
+            s.set_kernel(*kernel)
+        return s
+
+    fields = fields_of(pb)
+    s = mk()
+    s.step(2 * N)
+    full = {k: s.get_field(k) for k in fields}
+    rec_full = s.probe()
+    s.close()
+    s = mk()
+    s.step(N)
+    st = s.save_state()
+    s.close()
+    s = mk()
+    s.load_state(st)
+    assert s.steps_done() == N
+    s.step(N)
+    for k in fields:
+        assert np.array_equal(s.get_field(k), full[k]), (case, k)
+    assert np.array_equal(s.probe(), rec_full[:, N:]), case
+    assert np.abs(full[fields[0]]).max() > 0
+    s.close()
+    # a state of another grid is refused and leaves the handle as it was
+    other = W.dielectric2d(64, ny=64, steps=10, seed=1, nrect=2, side=(4, 8), npml=8)
+    o = Sim.from_problem(other)
+    with pytest.raises(Exception):
+        o.load_state(np.zeros(o.save_state().size, np.uint8))
+    if case == "2d_default":
+        with pytest.raises(Exception):
+            o.load_state(st[:o.save_state().size])
+    o.close()
 
 
 def test_source_table_and_probe_components():
@@ -546,3 +604,34 @@ def test_split_field_pml():
     pb3.cpml = dict(pb3.cpml, split=1)
     with pytest.raises(FdtdError):
         Sim.from_problem(pb3)
+
+
+def test_gaussian_h_error_is_the_fp32_floor():
+    """The headline scene's 3D Gaussian source at 192^3 for 600 steps: the
+    GPU kernels (two-step default, fused single step, two-pass reference)
+    and the FP32 build of the oracle (the oracle's own code in single
+    precision) miss the relative 1e-4 bar on H alike, against the FP64
+    oracle; the GPU's H error is within 2x of the CPU FP32 build's and every
+    component's error is far inside 1e-4 of the peak energy norm."""
+    from oracle import oracle as O
+    from paper_2405_00814_amd.sim import Sim
+    from helpers import energy_weights, run_errors, run_oracle_tracked
+    pb = W.yee3d(shape=(192, 192, 192), steps=600, seed=0, nbox=24, side=(3, 36), npml=12)
+    w = energy_weights(pb)
+    o = O.for_problem(pb)
+    f32, _ = O.run_fp32(o, 600)
+    rec, peak, _ = run_oracle_tracked(o, 600, 50, w)
+    ref = {f: getattr(o, f) for f in O.F3}
+    cpu = run_errors({f: f32[f] for f in O.F3}, ref, peak, w)
+    log("cpu fp32", {f: "%.1e/%.1e" % v[:2] for f, v in cpu.items()})
+    assert max(cpu[f][0] for f in ("hx", "hy", "hz")) > TOL  # the relative bar is out of FP32 reach on H
+    for kernel in (None, (2, (4,)), (1,)):
+        got, grec, cfg = run_gpu(pb, 600, kernel)
+        e = run_errors(got, ref, peak, w)
+        log("gpu", cfg["variant"], {f: "%.1e/%.1e" % v[:2] for f, v in e.items()})
+        for f in O.F3:
+            assert e[f][1] <= 1e-5, (cfg, f, e[f])
+            assert e[f][1] <= 2 * cpu[f][1] + 1e-8, (cfg, f, e[f], cpu[f])
+        for f in ("ex", "ey", "ez"):
+            assert e[f][0] <= TOL, (cfg, f)
+        assert rel_l2(grec, rec) <= TOL
