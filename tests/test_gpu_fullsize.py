@@ -110,14 +110,14 @@ def test_full_yee3d_512_2000_steps_vs_oracle():
         ref = {f: getattr(o, f) for f in fields_of(pb)}
         errs = assert_run_parity(got, ref, peak, w, TOL, "yee3d 512^3 step %d" % c)
         _log_errs("step %d" % c, errs)
-        log("step %d energy-norm rel-L2 %.2e" % (c, energy_rel_l2(got, ref, pb)))
+        progress("step %d energy-norm rel-L2 %.2e" % (c, energy_rel_l2(got, ref, pb)))
         for f in ("ex", "ey", "ez"):  # the static E of the Gaussian holds the energy
             assert errs[f][2] >= 0.1, f
         del got, ref
     assert s.get_kernel()["variant"] == 3 and s.check_finite()
     rec, rrec = s.probe(), np.concatenate(recs, axis=1)
     s.close()
-    log("probes rel-L2 %.2e" % rel_l2(rec, rrec))
+    progress("probes rel-L2 %.2e" % rel_l2(rec, rrec))
     assert rec.shape == rrec.shape
     # the probes lie in the far field (signals 1e-6..3e-5 V/m) of a source
     # whose static near field is of order 1: their records carry the FP32
@@ -194,7 +194,7 @@ def test_full_dielectric2d_4096():
     assert s.get_kernel()["variant"] == 3 and s.check_finite()
     rec, rrec = s.probe(), np.concatenate(recs, axis=1)
     s.close()
-    log("probes rel-L2 %.2e" % rel_l2(rec, rrec))
+    progress("probes rel-L2 %.2e" % rel_l2(rec, rrec))
     assert rel_l2(rec, rrec) <= TOL
 
 
@@ -232,7 +232,7 @@ def test_full_batch_256_4000_steps_sampled():
         errs = assert_run_parity(got, {f: getattr(o, f) for f in got}, peak, w, TOL, "batch[%d] step 4000" % q)
         _log_errs("  step 4000", errs)
         rec = b.probe(q)
-        log("  probes rel-L2 %.2e" % rel_l2(rec, rrec))
+        progress("  probes rel-L2 %.2e" % rel_l2(rec, rrec))
         assert rec.shape == rrec.shape
         assert rel_l2(rec, rrec) <= TOL
     b.close()
@@ -261,7 +261,7 @@ def test_full_adjoint_1024_T4000():
     o = O.for_problem(pb)
     lref, gref, gmref = o.loss_and_grad(pb.steps, pb.window, pb.design, mu=True)
     eg = rel_l2(g, gref)
-    log("loss gpu %.6e oracle adjoint %.6e; gradient rel-L2 over %d cells %.2e, max |diff| / max |g| %.2e"
+    progress("loss gpu %.6e oracle adjoint %.6e; gradient rel-L2 over %d cells %.2e, max |diff| / max |g| %.2e"
         % (loss, lref, gref.size, eg, np.abs(g - gref).max() / np.abs(gref).max()))
     assert abs(loss - lref) <= TOL * abs(lref)
     assert eg <= 1e-3
@@ -271,7 +271,7 @@ def test_full_adjoint_1024_T4000():
     lm, ge2, _, gm = s.adjoint_grads(pb.steps, pb.window, pb.design, 0, mu=True)
     gm = gm.cpu().numpy().reshape(gmref.shape)
     s.close()
-    log("mu_r gradient rel-L2 over the box %.2e" % rel_l2(gm, gmref))
+    progress("mu_r gradient rel-L2 over the box %.2e" % rel_l2(gm, gmref))
     assert lm == loss and np.array_equal(ge2.cpu().numpy().reshape(g.shape), g)
     assert rel_l2(gm, gmref) <= 1e-3
     e0 = pb.eps_r.astype(np.float64)
