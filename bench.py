@@ -443,6 +443,31 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                           GBps=r["GBps"])), flush=True)
 
 
+def forms_brief():
+    """A few steps of every form in its bench configuration: one kernel
+    dispatch per step or pass of each, for rocprofv3 counter runs (which
+    serialise dispatches)."""
+    import torch
+    from paper_2405_00814_amd import workloads as W
+    from paper_2405_00814_amd.sim import Batch, Sim
+    pb = W.dielectric2d(4096, steps=8, seed=0)
+    s = Sim.from_problem(pb)
+    s.step(8)
+    s.close()
+    g = Sim.from_problem(pb, graph=True)
+    g.step(4)
+    g.close()
+    b = Batch(W.batch2d(count=256, steps=8, seed=0))
+    b.step(8)
+    b.close()
+    pa = W.adjoint2d(1024, steps=64, seed=0)
+    a = Sim.from_problem(pa)
+    a.adjoint_eps(64, (32, 64), pa.design, 0)
+    a.close()
+    torch.cuda.synchronize()
+    print(json.dumps(dict(forms_brief="done")), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -453,6 +478,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--forms-brief", action="store_true",
+                    help="only a few steps of each form (2D 4096^2, its CSR graph, the 256-problem batch, "
+                         "the 1024^2 adjoint), for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (the method's independent grids and batches run "
@@ -463,6 +491,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.forms_brief:
+        forms_brief()
         return
 
     r = bench_3d(args)

@@ -293,7 +293,14 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *           the x/y slabs take two fused single steps through the third
  *           set instead.  An odd remainder of fdtd_step's n is one single
  *           step.
- *  tile[0..3]: variant-specific tile sizes (0 = default); tb reserved (1).
+ *  tile[0..3]: variant-specific tile sizes (0 = default).
+ *  tb: 0 or 1, except for 2D multi-step passes (variant 3 on a 2D grid),
+ *    where tb >= 2 TB, a multiple of 2 TB and at most 1024, replays a
+ *    captured HIP graph of tb steps (tb / TB passes and a device step
+ *    counter, so one graph serves any step range) for the whole multiples
+ *    of tb in fdtd_step's n; for grids whose pass costs about as much as its
+ *    launch.  The graph is captured on a stream of the library on first use
+ *    and again when the tile lists change.
  *    2D fused: tile[0] = V (1, 2 or 4 consecutive y cells per lane; ny % V
  *    must be 0), tile[1] = TX (x rows marched by one wavefront).
  *    3D fused: tile[0] = V (1, 2 or 4 consecutive z cells per thread;

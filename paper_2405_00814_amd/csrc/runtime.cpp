@@ -221,6 +221,8 @@ double source_sample(int kind, const double *par, double dt, int64_t n) {
 // Sim
 // ---------------------------------------------------------------------------
 Sim::~Sim() {
+    graph_reset();
+    if (gr.cap_st) (void)hipStreamDestroy(gr.cap_st);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (evf) (void)hipEventDestroy(evf);
@@ -618,6 +620,64 @@ void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
     last_launches += (int64_t)(n1 + plan2.pass2.l.size()) + (plan2.tb.empty() ? 0 : 1);
 }
 
+void Sim::graph_reset() {
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (gr.graph) (void)hipGraphDestroy(gr.graph);
+    gr.exec = nullptr;
+    gr.graph = nullptr;
+    gr.key.clear();
+}
+
+// Whole replays of the captured graph of kcfg.tb steps (multi-step passes
+// of both tile lists, an even number of passes, then the counter advance)
+// from buffer set 0: the state must start on set 0 (the caller aligns it).
+// Returns the steps done.
+int64_t Sim::graph_advance(int64_t n) {
+    const int G = kcfg.tb, TB = kcfg.tile[2], V = kcfg.tile[0];
+    const int64_t reps = n / G;
+    if (reps == 0) return 0;
+    if (!gr.probs) {
+        gr.probs = (Prob2D *)al.get(2 * sizeof(Prob2D));
+        gr.step_base = (int64_t *)al.get(sizeof(int64_t));
+    }
+    // the problem of each parity (its source table and record may have
+    // moved): data, not part of the graph
+    const Prob2D h[2] = {prob2d(0, 1), prob2d(1, 0)};
+    hip_check(hipMemcpyAsync(gr.probs, h, sizeof h, hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipMemcpyAsync(gr.step_base, &n_done, sizeof(int64_t), hipMemcpyHostToDevice, st), "upload");
+    const std::vector<const void *> key = {tb2_dev, pt2_start, pt2_cell, pt2_slot, gr.probs, gr.step_base,
+                                           (const void *)(intptr_t)G, (const void *)(intptr_t)TB,
+                                           (const void *)(intptr_t)V, (const void *)(intptr_t)tb2_inner,
+                                           (const void *)(intptr_t)tb2_outer, (const void *)(intptr_t)mat()};
+    if (!gr.exec || key != gr.key) {
+        graph_reset();
+        if (!gr.cap_st) hip_check(hipStreamCreateWithFlags(&gr.cap_st, hipStreamNonBlocking), "stream");
+        hip_check(hipStreamBeginCapture(gr.cap_st, hipStreamCaptureModeRelaxed), "begin capture");
+        const Prob2D none{};
+        const ProbeTiles pt{pt2_start, pt2_cell, pt2_slot};
+        const ProbeTiles po{pt2_start + tb2_inner, pt2_cell, pt2_slot};
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < G / TB && e == hipSuccess; ++k) {
+            e = launch_2d_tb(none, gr.probs + (k & 1), tb2_dev, tb2_inner, false, mat(), pt, V, TB, gr.step_base,
+                             (int64_t)k * TB, gr.cap_st);
+            if (e == hipSuccess)
+                e = launch_2d_tb(none, gr.probs + (k & 1), tb2_dev + tb2_inner, tb2_outer, true, mat(), po, V, TB,
+                                 gr.step_base, (int64_t)k * TB, gr.cap_st);
+        }
+        if (e == hipSuccess) e = launch_advance(gr.step_base, G, gr.cap_st);
+        const hipError_t e2 = hipStreamEndCapture(gr.cap_st, &gr.graph);
+        hip_check(e, "graph capture");
+        hip_check(e2, "end capture");
+        hip_check(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0), "instantiate");
+        gr.key = key;
+        gr.steps = G;
+    }
+    for (int64_t r = 0; r < reps; ++r) hip_check(hipGraphLaunch(gr.exec, st), "graph launch");
+    const int per = G / TB;
+    last_launches += reps * (per * ((tb2_inner > 0) + (tb2_outer > 0)) + 1);
+    return reps * G;
+}
+
 // n steps: pairs through the two-step pass where it is selected, single
 // steps otherwise
 void Sim::advance(int64_t n) {
@@ -635,6 +695,19 @@ void Sim::advance(int64_t n) {
         }
     if (tb2) {
         const int TB = kcfg.tile[2];
+        // graph replays start on buffer set 0: one eager pass aligns
+        if (kcfg.tb > 1 && n - q >= kcfg.tb + (cur ? TB : 0)) {
+            if (cur == 1) {
+                launch_tb2d(n_done);
+                n_done += TB;
+                n_rec += TB * inc;
+                q += TB;
+            }
+            const int64_t g = graph_advance(n - q);
+            n_done += g;
+            n_rec += g * inc;
+            q += g;
+        }
         for (; q + TB <= n; q += TB) {
             launch_tb2d(n_done);
             n_done += TB;
@@ -768,7 +841,11 @@ int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
 }
 
 static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
-    if (k.tb != 0 && k.tb != 1) return false;
+    // tb: 0 or 1; for 2D multi-step passes also the steps per replayed graph
+    // (an even number of passes, at most 1024 steps)
+    const bool graph_tb = s.ndim == 2 && k.variant == 3 && k.tile[2] > 0 && k.tb >= 2 * k.tile[2] && k.tb <= 1024 &&
+                          k.tb % (2 * k.tile[2]) == 0 && !s.is_graph;
+    if (k.tb != 0 && k.tb != 1 && !graph_tb) return false;
     if (k.variant == 1) return true;
     if (s.split) return false;
     if (k.variant != 2 && k.variant != 3) return false;

@@ -128,6 +128,23 @@ struct Sim {
     Tile3 *p1_dev = nullptr, *p2_dev = nullptr;
     int plan2_mat = -1;
 
+    // 2D multi-step passes replayed from a captured HIP graph (kernel
+    // config tb = steps per replay, 0/1: none): the kernels read the problem
+    // of the buffer parity from `probs` and the step from `step_base`, so
+    // one graph serves every step range; captured again when a list or
+    // table it holds is rebuilt
+    struct GraphRun {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipStream_t cap_st = nullptr;
+        int steps = 0;
+        Prob2D *probs = nullptr;       // device [2]: set 0 -> 1, set 1 -> 0
+        int64_t *step_base = nullptr;  // device step counter
+        std::vector<const void *> key; // pointers the graph holds
+    } gr;
+    void graph_reset();
+    int64_t graph_advance(int64_t n);  // steps advanced by graph replays
+
     int64_t n_done = 0;
     fdtd_kernel_config kcfg{};
     bool kcfg_explicit = false;

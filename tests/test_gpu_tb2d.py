@@ -148,3 +148,33 @@ def test_tb2d_profile_and_rules():
     s.step(5)
     assert s.check_finite()
     s.close()
+
+
+@pytest.mark.parametrize("shape,V,TX,TB,G", [((128, 128), 1, 8, 4, 32), ((203, 146), 2, 5, 2, 8),
+                                             ((160, 96), 1, 16, 4, 64)])
+def test_graph_replay_matches_eager_passes(shape, V, TX, TB, G):
+    """Multi-step passes replayed from a captured graph (kernel config tb =
+    G steps per replay): the same fields and probe records as the passes
+    launched one by one, over calls that start on either buffer set and
+    leave remainders, and the oracle's within 1e-4."""
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.dielectric2d(shape[0], ny=shape[1], steps=0, seed=4, nrect=5, side=(6, 30), npml=12, nprobes=5)
+    chunks = (TB, 3 * G + TB, G, 2 * G + 3, 5)
+    n = sum(chunks)
+    out = []
+    for g in (1, G):
+        s = Sim.from_problem(pb)
+        s.set_kernel(3, (V, TX, TB), tb=g)
+        for c in chunks:
+            s.step(c)
+        assert s.get_kernel()["tb"] == g
+        out.append(({k: s.get_field(k) for k in ("ez", "hx", "hy")}, s.probe()))
+        ms, launches = s.last_step_time()
+        s.close()
+    (a, ra), (b, rb) = out
+    for k in a:
+        assert rel_l2(b[k], a[k]) <= 1e-6, k
+    assert rel_l2(rb, ra) <= 1e-6
+    ref, rrec = run_oracle(pb, n)
+    assert_parity(b, ref, 1e-4, "graph %s" % (shape,))
+    assert rel_l2(rb, rrec) <= 1e-4
