@@ -390,6 +390,22 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     zero(ez1y);
 
     const int iend = min(T.i1, nx);
+    // Without x/y-slab code, Ex, Hx, Hy, Hz of the next plane are loaded
+    // before the current plane's second step, so that their latency overlaps
+    // it (the waves of a workgroup would otherwise all wait for them at the
+    // plane's first barrier).  The instances with x/y-slab code or a Ca
+    // map have no registers to spare for them (they would spill).
+    constexpr bool PF = !PXY && MAT == 0;
+    float pf_ex[V], pf_hx[V], pf_hy[V], pf_hz[V];
+    auto prefetch = [&](int in) {
+        const bool lan = in < nx && in <= iend && ok;
+        const unsigned cn = ((unsigned)(lan ? in : 0) * ny + jr) * nz + kb;
+        ld(pf_ex, ex0, cn, lan);
+        ld(pf_hx, hx0, cn, lan);
+        ld(pf_hy, hy0, cn, lan);
+        ld(pf_hz, hz0, cn, lan);
+    };
+    if (PF) prefetch(ia);
     for (int i = ia; i <= iend; ++i) {
         const bool pa = i < nx;
         const bool xi = i + 1 < nx, im = i >= 1;
@@ -433,14 +449,21 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         float ex[V], ey[V], ez[V], eyx[V], ezx[V], exy[V], ezy[V], hx[V], hy[V], hz[V], cb[V], ca[V], db[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) { ey[v] = eyc[v]; ez[v] = ezc[v]; }
-        ld(ex, ex0, c, la);
+        if (PF) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) { ex[v] = pf_ex[v]; hx[v] = pf_hx[v]; hy[v] = pf_hy[v]; hz[v] = pf_hz[v]; }
+        } else {
+            ld(ex, ex0, c, la);
+        }
         ld(eyx, ey0, c + sxs, la && xi);
         ld(ezx, ez0, c + sxs, la && xi);
         ld(exy, ex0, c + sys, la && yj && bot);
         ld(ezy, ez0, c + sys, la && yj && bot);
-        ld(hx, hx0, c, la);
-        ld(hy, hy0, c, la);
-        ld(hz, hz0, c, la);
+        if (!PF) {
+            ld(hx, hx0, c, la);
+            ld(hy, hy0, c, la);
+            ld(hz, hz0, c, la);
+        }
         coef(cb, ca, db, c, la);
         // x/y-slab psi of H at (i, j), state n in, n+1 out: issued with the
         // field loads (those of E are issued right before use: registers)
@@ -546,6 +569,7 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
         stv<V>(&L1z[tq], ez1);
         if (lane == 0) { Se1[rr][seg][0] = ex1[0]; Se1[rr][seg][1] = ey1[0]; }
 
+        if (PF) prefetch(i + 1);
         // ---- step 2 at plane ib = i-1 (H on the halo row above too) ----
         const int ib = i - 1;
         const bool pb = ib >= ia && rr <= T.nrows && rok;  // wave-uniform
