@@ -390,7 +390,7 @@ int fdtd_batch_step(fdtd_batch *b, int64_t n);
  * 4; 1 = single steps only), tx rows per wavefront tile (1..65536), vmax
  * the widest vector of columns per lane (1, 2 or 4; each problem takes the
  * widest its row length allows), txo rows per tile of the tiles near a
- * CPML slab (0 = tx).  Default 4, 16, 2, 0.  Synchronises; the state is
+ * CPML slab (0 = tx).  Default 4, 16, 1, 0.  Synchronises; the state is
  * kept.  FDTD_EINVAL for other values (the configuration is then
  * unchanged). */
 int fdtd_batch_set_kernel(fdtd_batch *b, int32_t tb, int32_t tx, int32_t vmax, int32_t txo);

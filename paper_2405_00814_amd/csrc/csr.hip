@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowpt
                                                    float *y, int nrows) {
     __shared__ int sc[4][kCsrCap];
     __shared__ float sw[4][kCsrCap];
-    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
     const int r0 = ((int)blockIdx.x * 4 + wv) * 64;
     const int r = r0 + lane;
     const bool live = r0 < nrows;  // wave-uniform

@@ -40,7 +40,11 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                                               CapArgs cap) {
     constexpr int HL = (TB + V - 1) / V;  // halo lanes per side
     constexpr int OW = (64 - 2 * HL) * V;  // own columns per strip
-    const int tw = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+    // the wavefront's tile index, uniform across its lanes: read once as a
+    // scalar, so the tile, its problem and the row loop bounds stay scalar
+    // (as per-lane values they held 10-30 more VGPRs per lane and made the
+    // row loop divergent)
+    const int tw = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (tw >= ntiles) return;  // whole wavefront leaves; no barriers below
     const Tile2T T = tiles[tw];
     const Prob2D &p = BATCH ? probs[T.prob] : p1;

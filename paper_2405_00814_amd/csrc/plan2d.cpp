@@ -12,13 +12,14 @@ bool tb2d_supported(int ny, int V, int TB, int TX) {
     return ny % V == 0;
 }
 
-// The default row chunk.  Measured on 2048^2 - 6400^2 dielectric grids
-// (four steps per pass, CPML tiles on a second stream): at V = 2 the pass is
-// fastest when all interior workgroups (four strips each) are resident at
-// once, 4-5 per CU at the kernel's register use, with chunks as long as
-// that allows (fewer recomputed rows); grids too large for one round run
-// best with short chunks of 8 rows.  At V = 1 (lighter registers) the
-// longest chunk that still gives 2 workgroups per CU wins.
+// The default row chunk.  Measured on 1448^2 - 6400^2 dielectric grids
+// (four steps per pass, CPML tiles on a second stream, one column per lane):
+// 32-row chunks where the interior workgroups (four strips each) still
+// number at least 4 per CU, else 16 where they number 2 per CU, else 8 or
+// 4 (4096^2: 373 Gcell/s at 32 rows, 376 at 16; 6400^2: 454 vs 412;
+// 3000^2: 334 vs 317; 2048^2: 16 rows, 234 vs 214).  With two columns per
+// lane: 32 rows where the interior workgroups number 4-5 per CU, 16 in
+// that band, else 8.
 int tb2d_default_tx(int nx, int ny, int V, int cus) {
     const int own = tb2d_own(V, 4);
     auto wgs = [&](int tx) { return (int64_t)((nx + tx - 1) / tx) * ((ny + own - 1) / own) / 4; };
@@ -27,6 +28,7 @@ int tb2d_default_tx(int nx, int ny, int V, int cus) {
             if (wgs(tx) >= 4 * (int64_t)cus && wgs(tx) <= 5 * (int64_t)cus) return tx;
         return 8;
     }
+    if (wgs(32) >= 4 * (int64_t)cus) return 32;
     for (int tx : {16, 8})
         if (wgs(tx) >= 2 * (int64_t)cus) return tx;
     return 4;

@@ -785,9 +785,9 @@ void Sim::refold(int64_t c0, int64_t c1) {
 }
 
 // 2D defaults (measured on MI355X over grids of 256^2 .. 6400^2): single
-// steps below 1.5M cells, four steps per pass from there on; one column per
-// lane below 8M cells, two columns above; the row chunk from
-// tb2d_default_tx.
+// steps below 1.5M cells (one column per lane below 8M cells, two above),
+// four steps per pass from 1.5M cells on with one column per lane (two were
+// 10-20 % slower at every size) and the row chunk from tb2d_default_tx.
 constexpr int64_t kTB2MinCells = (int64_t)3 << 19;
 constexpr int64_t kWide2DCells = (int64_t)8 << 20;
 constexpr int kTB2DefaultTX = 4;
@@ -807,8 +807,7 @@ int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
         return 0;
     }
     if (s.ndim == 2) {
-        const bool wide = s.ncell >= kWide2DCells && s.ny % 2 == 0;
-        const int vt = wide ? 2 : 1, tx = tb2d_default_tx(s.nx, s.ny, vt, s.cus);
+        const int vt = 1, tx = tb2d_default_tx(s.nx, s.ny, vt, s.cus);
         if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, tx)) {
             k.variant = 3;
             k.tile[0] = vt;

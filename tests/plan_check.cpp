@@ -197,9 +197,11 @@ int main(int argc, char **argv) {
         }
     // default row chunk of the 2D four-step pass on 256 CUs, at the grids it
     // was measured on (V = 2: the chunk whose interior workgroups number 4-5
-    // per CU, else 8; V = 1: the longest with 2 per CU, else 4)
+    // per CU, else 8; V = 1: 32 rows with 4 per CU, else the longest with 2
+    // per CU, else 4)
     const struct { int n, V, tx; } dtx[] = {
-        {4096, 2, 32}, {3072, 2, 16}, {6400, 2, 8}, {2048, 2, 8}, {2048, 1, 16}, {1448, 1, 16}, {1024, 1, 8}, {256, 1, 4}};
+        {4096, 2, 32}, {3072, 2, 16}, {6400, 2, 8}, {2048, 2, 8}, {6400, 1, 32}, {4096, 1, 32}, {3000, 1, 32},
+        {2048, 1, 16}, {1448, 1, 16}, {1024, 1, 8}, {256, 1, 4}};
     for (const auto &c : dtx)
         if (tb2d_default_tx(c.n, c.n, c.V, 256) != c.tx) {
             printf("tb2d_default_tx(%d, V %d) = %d, expected %d\n", c.n, c.V, tb2d_default_tx(c.n, c.n, c.V, 256), c.tx);

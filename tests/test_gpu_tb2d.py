@@ -15,10 +15,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
-# ragged shapes; tiles of 1 .. 64 rows; slabs of both kinds in the cones
+# ragged shapes; tiles of 1 .. 64 rows; slabs of both kinds in the cones;
+# odd row lengths (one column per lane)
 CASES = [
     ((192, 160), 4, 2, 16, 601), ((203, 146), 2, 2, 9, 600), ((131, 96), 2, 4, 32, 603),
     ((70, 256), 4, 4, 70, 602), ((256, 64), 2, 4, 1, 301), ((300, 520), 4, 2, 3, 400),
+    ((203, 147), 1, 4, 9, 600), ((97, 251), 1, 2, 33, 401), ((130, 129), 1, 4, 16, 500),
 ]
 
 
@@ -147,6 +149,14 @@ def test_tb2d_profile_and_rules():
     s.set_kernel(3, (2, 16, 2))
     s.step(5)
     assert s.check_finite()
+    s.close()
+    pb = W.dielectric2d(64, ny=67, steps=10, seed=0, nrect=2, side=(4, 8), npml=4, nprobes=1)
+    s = Sim.from_problem(pb)
+    with pytest.raises(FdtdError):  # ny % 2 != 0
+        s.set_kernel(3, (2, 16, 2))
+    s.set_kernel(3, (1, 16, 2))
+    s.step(10)
+    assert s.check_finite() and s.get_kernel()["tile"][0] == 1
     s.close()
 
 
