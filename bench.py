@@ -218,11 +218,13 @@ def csr_alg_bytes(pb):
 
 
 def csr_impl_bytes(pb):
-    """Bytes the CSR kernels move at least: the algorithmic bytes plus each
-    row's destination index (4 B), and every node value read in both layers
-    (the H layer gathers E and its own H, the E layer H and its own E)."""
+    """Bytes the CSR kernels move at least: the algorithmic bytes plus a
+    second read of every field node (the H layer gathers E and its own H,
+    the E layer H and its own E).  Destinations come from a table of 8 B per
+    64 rows (the per-row index only where a chunk straddles a grid row) and
+    the psi rows run inside the field rows that read them."""
     nnz, rows, nodes = _csr_counts(pb)
-    return 8 * nnz + 8 * rows + 12 * nodes
+    return 8 * nnz + 4 * rows + 8 * nodes + 4 * 3 * pb.cells
 
 
 def bench_batch(args, steps=4000):

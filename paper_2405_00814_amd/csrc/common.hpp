@@ -277,10 +277,22 @@ struct SarScale {
 hipError_t launch_sar(const double *acc, int64_t npts, int nf, const float *sig, const float *rho,
                       const SarScale &sc, float *out, hipStream_t st);
 
-// CSR layer: y[dst[r]] = sum_{e in row r} w[e] * x[col[e]] for r < nrows.
-hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w,
-                            const int *dst, const float *x, float *y, int nrows,
-                            hipStream_t st);
+// One layer of the explicit graph, in place on the node vector x:
+// x[dest(r)] = sum over the edges e of row r of w[e] * x[col[e]] for
+// r < nrows, except that an edge with col[e] = -1 - k (k > 0) opens an
+// auxiliary group: the next k edges of the row are an auxiliary row (its
+// first edge its own node, read by no other row), whose sum is stored at
+// that node and enters the row's sum times w[e].  dest(r): chunk[r / 64] =
+// {d0, s, aux, 0} gives d0 + (r % 64) s when s != 0, else dst[r]; aux != 0
+// when a row of the chunk has a group.
+struct CsrLayerArgs {
+    const int *rowptr, *col;
+    const float *w;
+    const int *dst;
+    const int4 *chunk;
+    int nrows;
+};
+hipError_t launch_csr_layer(const CsrLayerArgs &L, float *x, hipStream_t st);
 // Soft source and probes on a node vector.
 hipError_t launch_node_source_probe(float *x, const int *src_nodes, int nsrc, const float *src_vals,
                                     int64_t src_len, int64_t step, int np,

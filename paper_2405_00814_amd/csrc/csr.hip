@@ -3,6 +3,7 @@
 // the fixed coefficients.  Gather only (each row written by one thread, its
 // edges summed in order), so results are deterministic.
 #include "common.hpp"
+#include "devutil.hpp"
 
 namespace gem {
 
@@ -10,42 +11,78 @@ namespace gem {
 // rowptr[r0 + 64]) is staged in LDS by coalesced loads; each lane then sums
 // its row from LDS in edge order (a segment longer than the staging space
 // reads memory directly, same order).  A row of at most 8 edges (every row
-// of the FDTD graphs) issues all its gathers before the first product, so
-// they are in flight together instead of one per loop trip (4096^2 TMz
-// graph: 24.6 -> 29.1 Gcell/s); the sum keeps the edge order.
-constexpr int kCsrCap = 512;  // staged edges per wavefront
+// without an auxiliary group) issues all its gathers before the first
+// product, so they are in flight together instead of one per loop trip
+// (4096^2 TMz graph: 24.6 -> 29.1 Gcell/s); the sum keeps the edge order.
+// An auxiliary group (a CPML psi row that only this row reads, stored
+// inside the row behind a marker edge) is summed in place, stored at its
+// node and weighted by the marker: one launch per layer, and its edges come
+// with the row's own (one dependent gather, not three).  Rows whose
+// destinations step evenly (all but the chunks that straddle a grid row)
+// take them from the chunk table, not from dst.
+constexpr int kCsrCap = 640;  // staged edges per wavefront (20 KB per workgroup)
 
-__global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowptr,
-                                                   const int *__restrict__ col,
-                                                   const float *__restrict__ w,
-                                                   const int *__restrict__ dst, const float *x,
-                                                   float *y, int nrows) {
+// the row's sum, edges [q, q + len) read through col_at / w_at
+template <class C, class Wt>
+__device__ __forceinline__ float csr_row_groups(float *x, int q, int len, C col_at, Wt w_at) {
+    float acc = 0.f, s = 0.f, wm = 0.f;
+    int rem = 0, node = 0;
+    for (int u = 0; u < len; ++u) {
+        const int c = col_at(q + u);
+        const float w = w_at(q + u);
+        if (rem > 0) {  // inside an auxiliary group: its first edge is its own node
+            const float v = x[c];
+            if (node < 0) node = c;
+            s += w * v;
+            if (--rem == 0) {
+                x[node] = s;
+                acc += wm * s;
+            }
+        } else if (c < 0) {
+            rem = -1 - c;
+            wm = w;
+            s = 0.f;
+            node = -1;
+        } else {
+            acc += w * x[c];
+        }
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_csr_layer(CsrLayerArgs L, float *x) {
     __shared__ int sc[4][kCsrCap];
     __shared__ float sw[4][kCsrCap];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
-    const int r0 = ((int)blockIdx.x * 4 + wv) * 64;
+    const int nrows = L.nrows;
+    // the slab rows recur at a fixed stride in row order: in plain
+    // round-robin they would fall on the same XCDs (the H layer of a
+    // 4096-wide grid: all on two of the eight; 627 -> 563 us per step)
+    const int r0 = (xcd_scatter((int)blockIdx.x, (int)gridDim.x) * 4 + wv) * 64;
     const int r = r0 + lane;
     const bool live = r0 < nrows;  // wave-uniform
+    // {first destination, stride (0: dst[]), rows with auxiliary groups}
+    const int4 ch = live ? L.chunk[r0 >> 6] : make_int4(0, 0, 0, 0);
     int b0 = 0, n = 0, b = 0, e = 0;
     if (live) {
         const int rl = min(r0 + 64, nrows);
-        b0 = rowptr[r0];
-        n = rowptr[rl] - b0;
+        b0 = L.rowptr[r0];
+        n = L.rowptr[rl] - b0;
         if (r < nrows) {
-            b = rowptr[r];
-            e = rowptr[r + 1];
+            b = L.rowptr[r];
+            e = L.rowptr[r + 1];
         }
         if (n <= kCsrCap)
             for (int q = lane; q < n; q += 64) {
-                sc[wv][q] = col[b0 + q];
-                sw[wv][q] = w[b0 + q];
+                sc[wv][q] = L.col[b0 + q];
+                sw[wv][q] = L.w[b0 + q];
             }
     }
     __syncthreads();
     if (!live || r >= nrows) return;
     float acc = 0.f;
-    if (n <= kCsrCap && e - b <= 8) {
-        const int q0 = b - b0, len = e - b;
+    const int q0 = b - b0, len = e - b;
+    if (n <= kCsrCap && !ch.z && len <= 8) {
         float wq[8], xq[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -55,19 +92,51 @@ __global__ __launch_bounds__(256) void k_csr_layer(const int *__restrict__ rowpt
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (u < len) acc += wq[u] * xq[u];
-    } else if (n <= kCsrCap) {
-        for (int q = b - b0; q < e - b0; ++q) acc += sw[wv][q] * x[sc[wv][q]];  // longer rows (none in the graphs built here)
+    } else if (n <= kCsrCap && len <= 16) {
+        // auxiliary groups: every node value first (in flight together),
+        // then the sums in edge order
+        float xq[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = u < len ? sc[wv][q0 + u] : -1;
+            xq[u] = c >= 0 ? x[c] : 0.f;
+        }
+        float s = 0.f, wm = 0.f;
+        int rem = 0, node = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u < len) {
+                const int c = sc[wv][q0 + u];
+                const float w = sw[wv][q0 + u];
+                if (rem > 0) {  // inside a group: its first edge is its own node
+                    if (node < 0) node = c;
+                    s += w * xq[u];
+                    if (--rem == 0) {
+                        x[node] = s;
+                        acc += wm * s;
+                    }
+                } else if (c < 0) {
+                    rem = -1 - c;
+                    wm = w;
+                    s = 0.f;
+                    node = -1;
+                } else {
+                    acc += w * xq[u];
+                }
+            }
+        }
+    } else if (n <= kCsrCap) {  // longer rows (none in the graphs built here)
+        acc = csr_row_groups(x, q0, len, [&](int q) { return sc[wv][q]; }, [&](int q) { return sw[wv][q]; });
     } else {
-        for (int q = b; q < e; ++q) acc += w[q] * x[col[q]];
+        acc = csr_row_groups(x, b, len, [&](int q) { return L.col[q]; }, [&](int q) { return L.w[q]; });
     }
-    y[dst[r]] = acc;
+    x[ch.y != 0 ? ch.x + (r - r0) * ch.y : L.dst[r]] = acc;
 }
 
-hipError_t launch_csr_layer(const int *rowptr, const int *col, const float *w, const int *dst,
-                            const float *x, float *y, int nrows, hipStream_t st) {
-    if (nrows <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((nrows + 255) / 256);
-    hipLaunchKernelGGL(k_csr_layer, dim3(nb), dim3(256), 0, st, rowptr, col, w, dst, x, y, nrows);
+hipError_t launch_csr_layer(const CsrLayerArgs &L, float *x, hipStream_t st) {
+    if (L.nrows <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((L.nrows + 255) / 256);
+    hipLaunchKernelGGL(k_csr_layer, dim3(nb), dim3(256), 0, st, L, x);
     return hipGetLastError();
 }
 

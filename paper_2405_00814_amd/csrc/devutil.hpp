@@ -30,6 +30,17 @@ __device__ __forceinline__ void stv(float *p, const float (&r)[V]) {
     }
 }
 
+// Blocks stay round-robin over the XCDs in aligned groups of 8, but each
+// group is rotated by a hash of its index, so work that recurs at a fixed
+// block stride (a multiple of 8) does not fall on the same XCDs; the last
+// nb % 8 blocks stay in place.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_scatter(int b, int nb) {
+    if (b >= (nb & ~7)) return b;
+    const unsigned g = (unsigned)b >> 3;
+    const unsigned h = (g * 2654435761u) >> 29;
+    return (int)((g << 3) | (((unsigned)b + h) & 7u));
+}
+
 // Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works
 // on a contiguous range of tiles (neighbouring tiles share halo lines in the
 // same L2).

@@ -5,14 +5,16 @@
 //   Ez(i,j): t = 2i + 1 + nx(3j + 1)
 //   Hx(i,j): u = i + 3 j nx
 //   Hy(i,j): q = 2i + nx(3j + 1)
-// followed by the CPML auxiliary values (psi_hx, psi_hy, psi_ezx, psi_ezy in
-// their slab layouts).  Neighbourhoods: an Ez node gathers {itself, Hx(i,j),
+// followed by the CPML auxiliary values (psi_hx, psi_hy, psi_ezx, psi_ezy),
+// each slab row by row with i fastest, the order of the field rows that
+// read them.  Neighbourhoods: an Ez node gathers {itself, Hx(i,j),
 // Hx(i,j-1), Hy(i,j), Hy(i-1,j)} (as printed in Prop. 1); Hx gathers
 // {itself, Ez(i,j), Ez(i,j+1)} and Hy gathers {itself, Ez(i,j), Ez(i+1,j)}
 // (forward offsets: with E owned at the lower cell corner this is the
-// consistent staggering).  Each layer is two CSR sweeps, both in place:
-// first the auxiliary rows (psi <- b psi + c D), then the field rows, whose
-// weights multiply the just-updated psi.
+// consistent staggering).  Each layer is one CSR sweep in place: the field
+// rows, of which those with a psi edge first evaluate that auxiliary row
+// (psi <- b psi + c D, read by no other row) and then use the new psi, as a
+// sweep of the auxiliary rows followed by one of the field rows would.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -50,11 +52,77 @@ T *up(DevAlloc &al, const std::vector<T> &h, hipStream_t st, int64_t &bytes) {
 }  // namespace
 
 static void free_layer(Sim &s, Sim::Graph::Layer &L) {
-    s.al.put(L.rowptr);
-    s.al.put(L.col);
-    s.al.put(L.dst);
-    s.al.put(L.w);
+    for (void *p : {(void *)L.rowptr, (void *)L.col, (void *)L.dst, (void *)L.w, (void *)L.chunk}) s.al.put(p);
     L = Sim::Graph::Layer{};
+}
+
+// Upload one layer: the field rows `m`, each edge to a node that a row of
+// `aux` writes replaced by that row as a group of edges (a marker edge
+// -1 - k with the edge's weight, then the auxiliary row's k edges, its own
+// node first; every auxiliary row has exactly one such edge), and the
+// chunk table of the field rows (per 64 rows: first destination and stride
+// when the destinations step evenly, stride 0 otherwise; whether a row of
+// the chunk holds a group).
+static void put_layer(Sim &s, Sim::Graph::Layer &L, RowBuilder &m, RowBuilder *aux) {
+    free_layer(s, L);
+    if (aux && !aux->dst.empty()) {
+        const auto mm = std::minmax_element(aux->dst.begin(), aux->dst.end());
+        const int lo = *mm.first;
+        std::vector<int> row_of((size_t)(*mm.second - lo) + 1, -1), readers(aux->dst.size(), 0);
+        for (size_t a = 0; a < aux->dst.size(); ++a) {
+            row_of[(size_t)(aux->dst[a] - lo)] = (int)a;
+            if (aux->rowptr[a + 1] == aux->rowptr[a] || aux->col[(size_t)aux->rowptr[a]] != aux->dst[a])
+                fail(FDTD_EINVAL, "graph builder: an auxiliary row must start with its own node");
+        }
+        RowBuilder g;
+        for (size_t r = 0; r < m.dst.size(); ++r) {
+            for (int q = m.rowptr[r]; q < m.rowptr[r + 1]; ++q) {
+                const int c = m.col[(size_t)q];
+                const int a = (c >= lo && c - lo < (int)row_of.size()) ? row_of[(size_t)(c - lo)] : -1;
+                if (a < 0) {
+                    g.col.push_back(c);
+                    g.w.push_back(m.w[(size_t)q]);
+                    continue;
+                }
+                readers[(size_t)a]++;
+                const int k = aux->rowptr[(size_t)a + 1] - aux->rowptr[(size_t)a];
+                g.col.push_back(-1 - k);
+                g.w.push_back(m.w[(size_t)q]);
+                for (int p = aux->rowptr[(size_t)a]; p < aux->rowptr[(size_t)a + 1]; ++p) {
+                    g.col.push_back(aux->col[(size_t)p]);
+                    g.w.push_back(aux->w[(size_t)p]);
+                }
+            }
+            if (g.col.size() >= (size_t)INT32_MAX) fail(FDTD_EINVAL, "graph layer has 2^31 or more nonzeros");
+            g.end_row(m.dst[r]);
+        }
+        for (int u : readers)
+            if (u != 1) fail(FDTD_EINVAL, "graph builder: an auxiliary row without exactly one reader");
+        L.naux = (int)aux->dst.size();
+        m = std::move(g);
+    }
+    const int n = (int)m.dst.size();
+    std::vector<int4> ch((size_t)(n + 63) / 64);
+    for (int c = 0; c < (int)ch.size(); ++c) {
+        const int r0 = 64 * c, r1 = std::min(n, r0 + 64);
+        const int st = r1 - r0 > 1 ? m.dst[(size_t)r0 + 1] - m.dst[(size_t)r0] : 1;
+        bool even = st != 0;
+        for (int r = r0 + 1; r < r1 && even; ++r) even = m.dst[(size_t)r] - m.dst[(size_t)r - 1] == st;
+        bool grp = false;
+        for (int q = m.rowptr[(size_t)r0]; q < m.rowptr[(size_t)r1] && !grp; ++q) grp = m.col[(size_t)q] < 0;
+        ch[(size_t)c] = make_int4(m.dst[(size_t)r0], even ? st : 0, grp ? 1 : 0, 0);
+    }
+    Sim::Graph &g = s.g;
+    L.nrows = n;
+    L.nnz = (int64_t)m.col.size();
+    L.rowptr = up(s.al, m.rowptr, s.st, g.bytes);
+    L.col = up(s.al, m.col, s.st, g.bytes);
+    L.dst = up(s.al, m.dst, s.st, g.bytes);
+    L.w = up(s.al, m.w, s.st, g.bytes);
+    L.chunk = up(s.al, ch, s.st, g.bytes);
+    hip_check(hipStreamSynchronize(s.st), "sync");
+    m = RowBuilder{};
+    if (aux) *aux = RowBuilder{};
 }
 
 // The graph of the split-field PML (Sec. IV, the 4 Nx Nz-node form, in the
@@ -121,20 +189,9 @@ static void build_graph_split(Sim &s) {
             em.end_row(tz(i, j));
         }
     Sim::Graph &g = s.g;
-    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) free_layer(s, *L);
     g.bytes = 0;
-    auto put = [&](Sim::Graph::Layer &L, RowBuilder &b) {
-        L.nrows = (int)b.dst.size();
-        L.nnz = (int64_t)b.col.size();
-        L.rowptr = up(s.al, b.rowptr, s.st, g.bytes);
-        L.col = up(s.al, b.col, s.st, g.bytes);
-        L.dst = up(s.al, b.dst, s.st, g.bytes);
-        L.w = up(s.al, b.w, s.st, g.bytes);
-        hip_check(hipStreamSynchronize(s.st), "sync");
-        b = RowBuilder{};
-    };
-    put(g.h_main, hm);
-    put(g.e_main, em);
+    put_layer(s, g.h, hm, nullptr);
+    put_layer(s, g.e, em, nullptr);
     g.nmain = nnodes;
     g.nnodes = nnodes;
     if (!g.x) g.x = (float *)s.al.get((size_t)nnodes * 4);
@@ -162,15 +219,16 @@ static void build_graph_split(Sim &s) {
 
 // Nonzeros of the largest layer of the explicit graph of an nx x ny grid
 // with sx / sy CPML cells across the x / y slabs (both faces together), an
-// upper bound for the E layer and exact for the H layer's field rows, which
-// are the largest: non-split, Hx gathers itself, Ez(i,j), Ez(i,j+1) below
-// the last row and its psi in a y slab, Hy likewise along x; split, each H
-// node gathers both Ez parts of its two E neighbours.
+// upper bound: non-split, Hx gathers itself, Ez(i,j), Ez(i,j+1) below the
+// last row and, in a y slab, its psi as a group of 4 edges (marker, psi,
+// two Ez), Hy likewise along x; Ez gathers itself and four H nodes and at
+// most one group per slab direction; split, each H node gathers both Ez
+// parts of its two E neighbours.
 int64_t graph_layer_nnz_max(int nx, int ny, int sx, int sy, bool split) {
-    const int64_t N = (int64_t)nx * ny;
+    const int64_t N = (int64_t)nx * ny, slab = (int64_t)nx * sy + (int64_t)ny * sx;
     const int64_t h = split ? 6 * N + 2LL * nx * (ny - 1) + 2LL * ny * (nx - 1)
-                            : 4 * N + (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1) + (int64_t)nx * sy + (int64_t)ny * sx;
-    const int64_t e = (split ? 6 : 7) * N;
+                            : 4 * N + (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1) + 4 * slab;
+    const int64_t e = split ? 6 * N : 5 * N + 4 * slab;
     return std::max(h, e);
 }
 
@@ -209,27 +267,32 @@ void build_graph(Sim &s) {
     };
     auto db_of = [&](int64_t c) { return s.dt / (kMu0 * (s.mu_r.empty() ? 1.0 : s.mu_r[(size_t)c])); };
 
+    // psi nodes: y slabs (psi_hx, psi_ezy) by (slab row jj, i), x slabs
+    // (psi_hy, psi_ezx) by (j, slab column ii)
+    auto phx = [&](int i, int jj) { return o_hx + (int64_t)jj * nx + i; };
+    auto phy = [&](int ii, int j) { return o_hy + (int64_t)j * sx + ii; };
+    auto pezx = [&](int ii, int j) { return o_ezx + (int64_t)j * sx + ii; };
+    auto pezy = [&](int i, int jj) { return o_ezy + (int64_t)jj * nx + i; };
     RowBuilder ha, hm, ea, em;
-    // Rows are emitted in increasing destination-node order within each sweep.
+    // Field rows in increasing destination order within each layer; the
+    // auxiliary rows in the order of the field rows that read them.
     // H layer, auxiliary rows
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            const int jj = ys(j);
-            if (jj >= 0) {
-                ha.edge(o_hx + (int64_t)i * sy + jj, Y.bH[j]);
+    for (int j = 0; j < ny; ++j) {
+        const int jj = ys(j);
+        if (jj >= 0)
+            for (int i = 0; i < nx; ++i) {
+                ha.edge(phx(i, jj), Y.bH[j]);
                 ha.edge(t(i, j), -(double)Y.cH[j]);
                 if (j + 1 < ny) ha.edge(t(i, j + 1), Y.cH[j]);
-                ha.end_row(o_hx + (int64_t)i * sy + jj);
+                ha.end_row(phx(i, jj));
             }
-        }
-    for (int i = 0; i < nx; ++i) {
-        const int ii = xs(i);
-        if (ii < 0) continue;
-        for (int j = 0; j < ny; ++j) {
-            ha.edge(o_hy + (int64_t)ii * ny + j, X.bH[i]);
+        for (int i = 0; i < nx; ++i) {
+            const int ii = xs(i);
+            if (ii < 0) continue;
+            ha.edge(phy(ii, j), X.bH[i]);
             ha.edge(t(i, j), -(double)X.cH[i]);
             if (i + 1 < nx) ha.edge(t(i + 1, j), X.cH[i]);
-            ha.end_row(o_hy + (int64_t)ii * ny + j);
+            ha.end_row(phy(ii, j));
         }
     }
     // H layer, field rows (Hx then Hy of each Prop. 1 row k = j)
@@ -241,7 +304,7 @@ void build_graph(Sim &s) {
             hm.edge(t(i, j), db * Y.kH[j]);
             if (j + 1 < ny) hm.edge(t(i, j + 1), -db * Y.kH[j]);
             const int jj = ys(j);
-            if (jj >= 0) hm.edge(o_hx + (int64_t)i * sy + jj, -db);
+            if (jj >= 0) hm.edge(phx(i, jj), -db);
             hm.end_row(u(i, j));
         }
         for (int i = 0; i < nx; ++i) {
@@ -251,30 +314,30 @@ void build_graph(Sim &s) {
             hm.edge(t(i, j), -db * X.kH[i]);
             if (i + 1 < nx) hm.edge(t(i + 1, j), db * X.kH[i]);
             const int ii = xs(i);
-            if (ii >= 0) hm.edge(o_hy + (int64_t)ii * ny + j, db);
+            if (ii >= 0) hm.edge(phy(ii, j), db);
             hm.end_row(q(i, j));
         }
     }
-    // E layer, auxiliary rows (cells the E layer updates: i >= 1, j >= 1)
-    for (int i = 1; i < nx; ++i) {
-        const int ii = xs(i);
-        if (ii < 0) continue;
-        for (int j = 1; j < ny; ++j) {
-            ea.edge(o_ezx + (int64_t)ii * ny + j, X.bE[i]);
-            ea.edge(q(i, j), X.cE[i]);
-            ea.edge(q(i - 1, j), -(double)X.cE[i]);
-            ea.end_row(o_ezx + (int64_t)ii * ny + j);
+    // E layer, auxiliary rows (cells the E layer updates: i >= 1, j >= 1),
+    // in the field rows' order (j, then i)
+    for (int j = 1; j < ny; ++j) {
+        const int jj = ys(j);
+        for (int i = 1; i < nx; ++i) {
+            const int ii = xs(i);
+            if (ii >= 0) {
+                ea.edge(pezx(ii, j), X.bE[i]);
+                ea.edge(q(i, j), X.cE[i]);
+                ea.edge(q(i - 1, j), -(double)X.cE[i]);
+                ea.end_row(pezx(ii, j));
+            }
+            if (jj >= 0) {
+                ea.edge(pezy(i, jj), Y.bE[j]);
+                ea.edge(u(i, j), Y.cE[j]);
+                ea.edge(u(i, j - 1), -(double)Y.cE[j]);
+                ea.end_row(pezy(i, jj));
+            }
         }
     }
-    for (int i = 1; i < nx; ++i)
-        for (int j = 1; j < ny; ++j) {
-            const int jj = ys(j);
-            if (jj < 0) continue;
-            ea.edge(o_ezy + (int64_t)i * sy + jj, Y.bE[j]);
-            ea.edge(u(i, j), Y.cE[j]);
-            ea.edge(u(i, j - 1), -(double)Y.cE[j]);
-            ea.end_row(o_ezy + (int64_t)i * sy + jj);
-        }
     // E layer, field rows
     for (int j = 1; j < ny; ++j)
         for (int i = 1; i < nx; ++i) {
@@ -286,28 +349,15 @@ void build_graph(Sim &s) {
             em.edge(q(i, j), cbv * X.kE[i]);
             em.edge(q(i - 1, j), -cbv * X.kE[i]);
             const int ii = xs(i), jj = ys(j);
-            if (ii >= 0) em.edge(o_ezx + (int64_t)ii * ny + j, cbv);
-            if (jj >= 0) em.edge(o_ezy + (int64_t)i * sy + jj, -cbv);
+            if (ii >= 0) em.edge(pezx(ii, j), cbv);
+            if (jj >= 0) em.edge(pezy(i, jj), -cbv);
             em.end_row(t(i, j));
         }
 
     Sim::Graph &g = s.g;
-    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) free_layer(s, *L);
     g.bytes = 0;
-    auto put = [&](Sim::Graph::Layer &L, RowBuilder &b) {
-        L.nrows = (int)b.dst.size();
-        L.nnz = (int64_t)b.col.size();
-        L.rowptr = up(s.al, b.rowptr, s.st, g.bytes);
-        L.col = up(s.al, b.col, s.st, g.bytes);
-        L.dst = up(s.al, b.dst, s.st, g.bytes);
-        L.w = up(s.al, b.w, s.st, g.bytes);
-        hip_check(hipStreamSynchronize(s.st), "sync");
-        b = RowBuilder{};
-    };
-    put(g.h_aux, ha);
-    put(g.h_main, hm);
-    put(g.e_aux, ea);
-    put(g.e_main, em);
+    put_layer(s, g.h, hm, &ha);
+    put_layer(s, g.e, em, &ea);
     g.nmain = nmain;
     g.nnodes = nnodes;
     if (!g.x) g.x = (float *)s.al.get((size_t)nnodes * 4);
@@ -362,8 +412,9 @@ void graph_set_source_probes(Sim &s) {
 
 void graph_step(Sim &s, int64_t step) {
     Sim::Graph &g = s.g;
-    for (auto *L : {&g.h_aux, &g.h_main, &g.e_aux, &g.e_main}) {
-        hip_check(launch_csr_layer(L->rowptr, L->col, L->w, L->dst, g.x, g.x, L->nrows, s.st), "csr layer");
+    for (auto *L : {&g.h, &g.e}) {
+        const CsrLayerArgs a{L->rowptr, L->col, L->w, L->dst, L->chunk, L->nrows};
+        hip_check(launch_csr_layer(a, g.x, s.st), "csr layer");
         s.last_launches += 1;
     }
     hip_check(launch_node_source_probe(g.x, g.src_nodes, g.nsrc, s.src_dev, s.src_len, step,

@@ -163,13 +163,15 @@ struct Sim {
     struct Graph {
         int64_t nmain = 0, nnodes = 0;
         float *x = nullptr;  // node vector
-        // per layer: aux rows (psi) then main rows
+        // per layer: the field rows, each holding the auxiliary (psi) row
+        // it reads as a group of its edges (CsrLayerArgs)
         struct Layer {
-            int nrows = 0;
+            int nrows = 0, naux = 0;
             int *rowptr = nullptr, *col = nullptr, *dst = nullptr;
             float *w = nullptr;
+            int4 *chunk = nullptr;
             int64_t nnz = 0;
-        } h_aux, h_main, e_aux, e_main;
+        } h, e;
         std::vector<int64_t> ez_node;     // node of Ez(i,j) (host; split field: of Ezx)
         std::vector<int64_t> ez_node2;    // split field: node of Ezy(i,j), else empty
         int *src_nodes = nullptr;  // device: the source box's Ez nodes

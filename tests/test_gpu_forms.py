@@ -38,6 +38,26 @@ def test_graph_form_cpml_lossy(shape):
         assert rel_l2(got[k], imp[k]) <= TOL   # same map, different rounding order
 
 
+def test_graph_form_launches_and_uneven_faces():
+    """Each layer is one launch (its psi rows evaluated inside the field rows
+    that read them), plus the source/probe launch: 3 per step.  CPML on some
+    faces only and row lengths that leave 64-row chunks straddling grid rows
+    (destinations then read per row): parity with the oracle."""
+    from paper_2405_00814_amd.sim import Sim
+    pb = W.dielectric2d(77, ny=70, steps=300, seed=5, nrect=5, side=(6, 20), npml=8, nprobes=3)
+    pb.npml = (6, 0, 0, 9)
+    ref, rrec = run_oracle(pb, pb.steps)
+    s = Sim.from_problem(pb, graph=True)
+    s.step(pb.steps)
+    ms, launches = s.last_step_time()
+    got = {k: s.get_field(k) for k in ("ez", "hx", "hy")}
+    rec = s.probe()
+    s.close()
+    assert launches == 3 * pb.steps
+    assert_parity(got, ref, TOL, "graph uneven faces")
+    assert rel_l2(rec, rrec) <= TOL
+
+
 def test_graph_form_set_field_and_material():
     from paper_2405_00814_amd.sim import Sim
     pb = W.dielectric2d(64, ny=60, steps=200, seed=9, nrect=3, side=(4, 12), npml=8, nprobes=2)
