@@ -5,6 +5,20 @@
 
 namespace gem {
 
+// Neighbour lanes of a wavefront through the DPP wavefront shifts of the
+// GFX9 family (a modifier of one VALU move, instead of an LDS permute):
+// lane l gets x of lane l + 1 (lane_next) or l - 1 (lane_prev); the last,
+// resp. first, lane keeps its own value, as __shfl_down / __shfl_up(x, 1)
+// do.
+__device__ __forceinline__ float lane_next(float x) {
+    const int i = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_prev(float x) {
+    const int i = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+
 // V consecutive floats (V = 1, 2, 4) as one aligned vector access.
 template <int V>
 __device__ __forceinline__ void ldv(float (&r)[V], const float *p) {

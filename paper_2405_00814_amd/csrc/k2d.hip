@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "devutil.hpp"
 
 namespace gem {
 
@@ -274,7 +275,7 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
         float ez_r[V];
 #pragma unroll
         for (int v = 0; v + 1 < V; ++v) ez_r[v] = ez_c[v + 1];
-        float sh = __shfl_down(ez_c[0], 1);
+        float sh = lane_next(ez_c[0]);
         if (lane == 63) sh = (jend < ny) ? p.s0.ez[row + jend] : 0.f;
         ez_r[V - 1] = sh;
 
@@ -310,7 +311,7 @@ __device__ __forceinline__ void fused2d_tile(const Prob2D &p, int TX, int cx, in
         float hx_l[V];
 #pragma unroll
         for (int v = 1; v < V; ++v) hx_l[v] = hx_n[v - 1];
-        float shl = __shfl_up(hx_n[V - 1], 1);
+        float shl = lane_prev(hx_n[V - 1]);
         if (lane == 0) {
             shl = 0.f;
             if (jm >= 0) {

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
             float er[V];
 #pragma unroll
             for (int v = 0; v + 1 < V; ++v) er[v] = a.e[v + 1];
-            er[V - 1] = __shfl_down(a.e[0], 1);
+            er[V - 1] = lane_next(a.e[0]);
             // ---- H layer ----
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
             float hl[V];
 #pragma unroll
             for (int v = 1; v < V; ++v) hl[v] = out.hx[v - 1];
-            hl[0] = __shfl_up(out.hx[V - 1], 1);
+            hl[0] = lane_prev(out.hx[V - 1]);
             const bool mine = own && i >= T.i0 && i < T.i1;
             // design-cell capture (single problem): Ez before the E layer
             // and the E layer's bracket, per step

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "devutil.hpp"
 
 namespace gem {
 
@@ -41,7 +42,7 @@ __device__ __forceinline__ AxP axp(const AxisDev &a, int i) {
 template <int V>
 __device__ __forceinline__ float znext(const float (&x)[V], int q, float seam, bool last) {
     if (q + 1 < V) return x[q + 1];
-    const float s = __shfl_down(x[0], 1);
+    const float s = lane_next(x[0]);
     return last ? seam : s;
 }
 

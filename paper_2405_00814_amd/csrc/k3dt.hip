@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     };
     auto prv = [&](const float (&x)[V], int q, float seam) {
         if (q > 0) return x[q - 1];
-        const float s = __shfl_up(x[V - 1], 1);
+        const float s = lane_prev(x[V - 1]);
         return lane == 0 ? seam : s;
     };
     // H from E: own, +x, +y, +z seam; the z differences are kept for the

@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * WPB) void k3d_march(Prob3D p, const Tile3 *til
             hym[v] = hy[v - 1];
         }
         {
-            const float s1 = __shfl_up(hx[V - 1], 1), s2 = __shfl_up(hy[V - 1], 1);
+            const float s1 = lane_prev(hx[V - 1]), s2 = lane_prev(hy[V - 1]);
             hxm[0] = first ? hx_l : s1;
             hym[0] = first ? hy_l : s2;
         }

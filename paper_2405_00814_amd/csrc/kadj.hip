@@ -11,6 +11,7 @@
 // gathered from; H layer^T likewise back to the E nodes.)  The 1/d factors
 // are folded in the axis tables exactly as in the forward kernels.
 #include "common.hpp"
+#include "devutil.hpp"
 
 namespace gem {
 
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
         float gxr[V];
 #pragma unroll
         for (int v = 0; v + 1 < V; ++v) gxr[v] = gx_c[v + 1];
-        gxr[V - 1] = __shfl_down(gx_c[0], 1);  // lane 63: not needed
+        gxr[V - 1] = lane_next(gx_c[0]);  // lane 63: not needed
         // ---- phase B (H layer transposed) ----
         float hx[V], hy[V], db[V], ex[V], ey[V];
         zero(hx); zero(hy); zero(ex); zero(ey);
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
         float eyl[V];
 #pragma unroll
         for (int v = 1; v < V; ++v) eyl[v] = ey[v - 1];
-        eyl[0] = __shfl_up(ey[V - 1], 1);  // lane 0: not needed
+        eyl[0] = lane_prev(ey[V - 1]);  // lane 0: not needed
         // ---- phase C (gather into adjoint Ez) ----
         if (own) {
             float ez[V];
