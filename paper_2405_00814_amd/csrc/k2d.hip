@@ -131,37 +131,6 @@ hipError_t launch_2d_ref(const Prob2D &p, int64_t step, hipStream_t st) {
 // The state is double buffered: everything is read from s0 and written to
 // s1, so neighbouring strips never see half-updated values.
 // ---------------------------------------------------------------------------
-template <int V>
-__device__ __forceinline__ void ldv(float (&r)[V], const float *p) {
-    if constexpr (V == 4) {
-        const float4 t = *reinterpret_cast<const float4 *>(p);
-        r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
-    } else if constexpr (V == 2) {
-        const float2 t = *reinterpret_cast<const float2 *>(p);
-        r[0] = t.x; r[1] = t.y;
-    } else {
-        r[0] = *p;
-    }
-}
-
-template <int V>
-__device__ __forceinline__ void stv(float *p, const float (&r)[V]) {
-    if constexpr (V == 4) {
-        *reinterpret_cast<float4 *>(p) = make_float4(r[0], r[1], r[2], r[3]);
-    } else if constexpr (V == 2) {
-        *reinterpret_cast<float2 *>(p) = make_float2(r[0], r[1]);
-    } else {
-        *p = r[0];
-    }
-}
-
-// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works
-// on a contiguous range of tiles (neighbouring tiles share halo lines in the
-// same L2).
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    return (nb % 8 == 0) ? (b % 8) * (nb / 8) + (b / 8) : b;
-}
-
 // One wavefront tile: x rows [cx*TX, cx*TX + TX) of the strip sy.  Probe
 // entries [pbeg, pend) of pt belong to this tile.
 template <int V, bool PML, bool CAPTURE>
