@@ -29,6 +29,15 @@ struct StateBuf {
     std::vector<std::pair<float *, int64_t>> parts;  // (device pointer, floats) of set 0
 };
 
+// The simulation's launches go to stream t for the scope (the recompute of
+// a segment beside the adjoint steps of the next one).
+struct StreamSwap {
+    Sim &s;
+    hipStream_t old;
+    StreamSwap(Sim &s_, hipStream_t t) : s(s_), old(s_.st) { s.st = t; }
+    ~StreamSwap() { s.st = old; }
+};
+
 }  // namespace
 
 static void copy_state(Sim &s, int set, float *buf, bool to_buf) {
@@ -80,6 +89,16 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
     Sim *sp = nullptr;
     fdtd_kernel_config saved{};
     bool restore_cfg = false;
+    hipStream_t rs = nullptr;  // recompute stream
+    hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_start = nullptr;
+    auto release_streams = [&]() {
+        if (rs) (void)hipStreamSynchronize(rs);
+        for (hipEvent_t e : {ev_rec[0], ev_rec[1], ev_adj[0], ev_adj[1], ev_start})
+            if (e) (void)hipEventDestroy(e);
+        if (rs) (void)hipStreamDestroy(rs);
+        rs = nullptr;
+        ev_rec[0] = ev_rec[1] = ev_adj[0] = ev_adj[1] = ev_start = nullptr;
+    };
     try {
         if (!sim || !design || (!grad_eps_dev && !grad_sigma_dev && !grad_mu_dev))
             fail(FDTD_EINVAL, "NULL argument");
@@ -133,8 +152,13 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
         const int64_t S = state_floats(s);
         float *ck = (float *)get((size_t)(std::max<int64_t>(1, nseg - 1) * S) * 4);
         float *fin = (float *)get((size_t)S * 4);
-        float *cap_ez = (float *)get((size_t)(L * ndc) * 4);
-        float *cap_br = (float *)get((size_t)(L * ndc) * 4);
+        // design values of a segment, two sets when segments are recomputed
+        // (one filled while the adjoint steps read the other)
+        float *cap_ez[2] = {nullptr, nullptr}, *cap_br[2] = {nullptr, nullptr};
+        for (int b = 0; b < (nseg >= 2 ? 2 : 1); ++b) {
+            cap_ez[b] = (float *)get((size_t)(L * ndc) * 4);
+            cap_br[b] = (float *)get((size_t)(L * ndc) * 4);
+        }
         const int dbox[4] = {i0, i1, j0, j1};
         const int cbox[4] = {i0, i1c, j0, j1c};
         ProbeTiles pt{s.pt_start, s.pt_cell, s.pt_slot};
@@ -153,8 +177,8 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
                 if (cap) {
                     const Prob2D p = s.prob2d(s.cur, 1 - s.cur);
                     const TileSplit2D sp{s.tl2_dev, s.tl2_inner, s.tl2_dev + s.tl2_inner, s.tl2_outer};
-                    hip_check(launch_2d_fused(p, fc, pt, k, s.st, cbox, cap_ez + (k - k0) * ndc,
-                                              cap_br + (k - k0) * ndc, s.split2d() ? &sp : nullptr),
+                    hip_check(launch_2d_fused(p, fc, pt, k, s.st, cbox, cap->ez + (k - k0) * ndc,
+                                              cap->br + (k - k0) * ndc, s.split2d() ? &sp : nullptr),
                               "forward step");
                     s.cur = 1 - s.cur;
                 } else {
@@ -173,7 +197,8 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
                 copy_state(s, s.cur, ck + g * S, true);
                 run(k0, k1, nullptr);
             } else {
-                const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez, cap_br, k0, ndc};
+                const int b = (int)(g & 1);
+                const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez[b], cap_br[b], k0, ndc};
                 run(k0, k1, &cap);
             }
         }
@@ -277,32 +302,61 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
         hip_check(hipMemcpyAsync(d_tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice, s.st), "upload");
         const ProbeTiles apt{d_tst, d_tcell, d_tslot};
         hip_check(hipStreamSynchronize(s.st), "sync");
-        // ---- backward over segments (the last one kept by the forward) ----
+        // ---- backward over segments, newest first (the last one kept by
+        //      the forward).  Segment g's adjoint steps run on the
+        //      simulation's stream while segment g-1 is recomputed on a
+        //      second stream: two sets of design values, events ordering
+        //      each set's reuse.  The adjoint steps read the probe records
+        //      from a copy taken after the forward, as a recompute rewrites
+        //      its segment's records (multi-step passes grouped from another
+        //      start step can differ in the last bits). ----
+        float *rec_snap = (float *)get((size_t)std::max<int64_t>(1, P * s.rec_cap) * 4);
+        hip_check(hipMemcpyAsync(rec_snap, s.rec_dev, (size_t)(P * s.rec_cap) * 4, hipMemcpyDeviceToDevice, s.st),
+                  "records");
+        const hipStream_t st0 = s.st;
+        if (nseg >= 2) {
+            hip_check(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking), "stream");
+            for (hipEvent_t *e : {&ev_rec[0], &ev_rec[1], &ev_adj[0], &ev_adj[1], &ev_start})
+                hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "event");
+            hip_check(hipEventRecord(ev_start, st0), "event");  // checkpoints written
+            hip_check(hipStreamWaitEvent(rs, ev_start, 0), "stream wait");
+        }
+        auto recompute = [&](int64_t g) {
+            const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
+            const int b = (int)(g & 1);
+            // set b was last read by the adjoint steps of segment g + 2 (the
+            // last segment's values come from the forward, in set b too)
+            if (g + 2 < nseg) hip_check(hipStreamWaitEvent(rs, ev_adj[b], 0), "stream wait");
+            StreamSwap sw(s, rs);
+            copy_state(s, 0, ck + g * S, false);
+            s.cur = 0;
+            s.n_done = k0;
+            s.n_rec = k0;
+            const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez[b], cap_br[b], k0, ndc};
+            run(k0, k1, &cap);
+            hip_check(hipEventRecord(ev_rec[b], rs), "event");
+        };
         for (int64_t g = nseg - 1; g >= 0; --g) {
             const int64_t k0 = g * L, k1 = std::min(T, (g + 1) * L);
-            if (g + 1 < nseg) {
-                copy_state(s, 0, ck + g * S, false);
-                s.cur = 0;
-                s.n_done = k0;
-                s.n_rec = k0;
-                const CapArgs cap{make_int4(i0, i1c, j0, j1c), cap_ez, cap_br, k0, ndc};
-                run(k0, k1, &cap);
-            }
+            const int b = (int)(g & 1);
+            if (g >= 1) recompute(g - 1);
+            if (g + 1 < nseg) hip_check(hipStreamWaitEvent(st0, ev_rec[b], 0), "stream wait");
             const Prob2D p = s.prob2d(0, 0);
             for (int64_t k = k1 - 1; k >= k0; --k) {
                 // the first step's input is seeded here, every later one by
                 // the step that writes it
                 if (k == T - 1 && T > n0 && T <= n1)
-                    hip_check(launch_adj2d_seed(a[acur].ez, d_ust, d_pcell, d_pslot, nu, s.rec_dev, s.rec_cap, T - 1,
-                                                s.st),
+                    hip_check(launch_adj2d_seed(a[acur].ez, d_ust, d_pcell, d_pslot, nu, rec_snap, s.rec_cap, T - 1,
+                                                st0),
                               "adjoint seed");
                 const int seed_out = (k > n0 && k <= n1) ? 1 : 0;
-                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cbox, cap_ez + (k - k0) * ndc,
-                                             cap_br + (k - k0) * ndc, sez, sbr, shx, shy, seed_out, apt,
-                                             s.rec_dev, s.rec_cap, k - 1, ac.V, ac.TX, s.st),
+                hip_check(launch_adj2d_fused(p, a[acur], a[1 - acur], dbox, cbox, cap_ez[b] + (k - k0) * ndc,
+                                             cap_br[b] + (k - k0) * ndc, sez, sbr, shx, shy, seed_out, apt,
+                                             rec_snap, s.rec_cap, k - 1, ac.V, ac.TX, st0),
                           "adjoint step");
                 acur = 1 - acur;
             }
+            if (rs) hip_check(hipEventRecord(ev_adj[b], st0), "event");
         }
         if (grad_eps_dev)
             hip_check(launch_grad_combine(sez, sbr, dcoef, dcoef + nd, grad_eps_dev, nd, s.st), "gradient");
@@ -321,6 +375,7 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
         s.timed = true;
         s.last_launches = T * 3 + 1;
         hip_check(hipStreamSynchronize(s.st), "sync");
+        release_streams();
         for (void *p : tmp) s.al.put(p);
         tmp.clear();
         s.kcfg = saved;
@@ -332,6 +387,7 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
         const int rc = status_of_current_exception();
         if (sp) {
             (void)hipStreamSynchronize(sp->st);
+            release_streams();
             for (void *p : tmp) sp->al.put(p);
             if (restore_cfg) {
                 sp->kcfg = saved;
