@@ -108,6 +108,22 @@ def test_graph_size_guard(n, npml, split):
     assert b"nonzeros" in L.fdtd_last_error()
 
 
+def test_stream_copy_argument_rules():
+    """fdtd_stream_copy checks its arguments before any device work: NULL
+    pointers, a byte count or an address that is not a multiple of 16 give
+    FDTD_EINVAL; a zero-byte copy of aligned addresses is a no-op."""
+    from paper_2405_00814_amd import _lib
+    L = _lib.load()
+    v = C.c_void_p
+    assert L.fdtd_stream_copy(None, v(0x1000), 16, None) == -1
+    assert L.fdtd_stream_copy(v(0x1000), None, 16, None) == -1
+    assert L.fdtd_stream_copy(v(0x1000), v(0x2000), 20, None) == -1
+    assert L.fdtd_stream_copy(v(0x1004), v(0x2000), 16, None) == -1
+    assert L.fdtd_stream_copy(v(0x1000), v(0x2008), 16, None) == -1
+    assert b"multiples of 16" in L.fdtd_last_error()
+    assert L.fdtd_stream_copy(v(0x1000), v(0x2000), 0, None) == 0
+
+
 def test_noalloc_probe_rejects_null():
     from paper_2405_00814_amd import _lib
     L = _lib.load()

@@ -635,3 +635,26 @@ def test_gaussian_h_error_is_the_fp32_floor():
         for f in ("ex", "ey", "ez"):
             assert e[f][0] <= TOL, (cfg, f)
         assert rel_l2(grec, rec) <= TOL
+
+
+def test_stream_copy_kernel():
+    """The library's copy kernel (the bandwidth reference of the bench):
+    every byte copied for sizes that leave a partial last block, on a torch
+    stream, and nothing written past the end."""
+    import ctypes as C
+    import torch
+    from paper_2405_00814_amd import _lib
+    L = _lib.load()
+    st = torch.cuda.Stream()
+    for n in (4, 256 * 4 + 4, 3 * 1024 * 1024 + 12):  # floats; bytes a multiple of 16
+        a = torch.randn(n, device="cuda")
+        b = torch.full((n + 64,), -7.0, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            rc = L.fdtd_stream_copy(C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()), n * 4,
+                                    C.c_void_p(st.cuda_stream))
+        assert rc == 0
+        st.synchronize()
+        assert torch.equal(b[:n], a)
+        assert torch.all(b[n:] == -7.0)
+
