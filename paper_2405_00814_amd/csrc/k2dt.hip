@@ -132,6 +132,9 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
         zero(hyp[k]);
     }
     const int t0 = T.i0 - TB, t1 = T.i1 + TB - 1;
+    // the tile's probe entries, read once (not at every stage: the stage
+    // would wait for the load to decide its loop)
+    const int pbeg = pt.start != nullptr ? pt.start[tw] : 0, pend = pt.start != nullptr ? pt.start[tw + 1] : 0;
     load_ez(in[0].e, t0);
     // Single-problem instances without CPML code load stage 0's memory
     // input of the next iteration (Ez^n of row t+1, the rest of state n of
@@ -258,9 +261,8 @@ __global__ __launch_bounds__(256) void k2d_tb(Prob2D p1, const Prob2D *__restric
                 hyp[k][v] = out.hy[v];
             }
             // probes of this tile, state n+k+1
-            if (mine && pt.start != nullptr) {
-                const int pend = pt.start[tw + 1];
-                for (int q = pt.start[tw]; q < pend; ++q) {
+            if (pbeg < pend && mine) {
+                for (int q = pbeg; q < pend; ++q) {
                     const int cell = pt.cell[q];
                     const int pi = cell / ny, pj = cell - pi * ny;
                     if (pi != i) continue;

@@ -189,6 +189,8 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
         }
     }
 
+    // the tile's probe entries for the loss seed, read once
+    const int qs0 = A.seed_out ? A.pt.start[tw] : 0, qs1 = A.seed_out ? A.pt.start[tw + 1] : 0;
     for (int i = x0; i < x1; ++i) {
         const int64_t row = (int64_t)i * ny;
         float gx_n[V], gy_n[V], aca_n[V];
@@ -267,9 +269,8 @@ __global__ __launch_bounds__(256) void k_adj_fused(AdjFArgs A, int TX, int nsy, 
                 if (i >= 1) w += ex_p[v];
                 ez[v] = w;
             }
-            if (A.seed_out) {
-                const int q1 = A.pt.start[tw + 1];
-                for (int q = A.pt.start[tw]; q < q1; ++q) {
+            if (qs0 < qs1) {
+                for (int q = qs0; q < qs1; ++q) {
                     const int c = A.pt.cell[q];
                     const int pi = c / ny, pj = c - pi * ny;
                     if (pi != i) continue;
