@@ -109,6 +109,10 @@ struct ProbeTiles {
     const int *start;   // [ntiles + 1]
     const int *cell;    // [np] per entry: packed (i, j[, k]) as linear index
     const int *slot;    // [np] original probe index
+    // two-step 3D lists: per tile of the launch, nonzero when a probe cell
+    // lies in its own planes and rows (nullptr: every tile looks its
+    // groups up)
+    const int *tile_any = nullptr;
 };
 
 // ---------------------------------------------------------------------------

@@ -41,8 +41,11 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     constexpr int NT = 64 * RZ * NR;     // threads
     constexpr int SEG = 64 * V;          // z cells per wavefront
     constexpr int ROW = RZ * SEG;        // LDS floats per row
-    const TileTB T = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const int tix = xcd_block(blockIdx.x, gridDim.x);
+    const TileTB T = tiles[tix];
     if (T.i0 >= T.i1) return;  // padding
+    // whether this tile records probes at all (wave-uniform)
+    const bool tprobe = pt.start != nullptr && (pt.tile_any == nullptr || pt.tile_any[tix] != 0);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int seg = w % RZ, rr = w / RZ;
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     };
     auto record = [&](int i, unsigned c, int64_t n, const float (&ex)[V], const float (&ey)[V], const float (&ez)[V],
                       const float (&hx)[V], const float (&hy)[V], const float (&hz)[V]) {
-        if (pt.start == nullptr || !ok) return;
+        if (!tprobe || !ok) return;
         const int g = i * ((ny + 3) / 4) + jr / 4;
         const int pend = pt.start[g + 1];
         for (int q = pt.start[g]; q < pend; ++q) {

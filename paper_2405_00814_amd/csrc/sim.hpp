@@ -101,6 +101,7 @@ struct Sim {
     int64_t n_rec = 0;
     // probes grouped by tile for the fused kernels
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
+    int *tb_any = nullptr, *tbo_any = nullptr;  // per two-step tile: holds a probe
     int pt_ntiles = -1;
     int pt_cfg[6] = {-1, -1, -1, -1, -1, -1};
     // 2D fused: tile ids clear of the CPML slabs, then the others.  Large
