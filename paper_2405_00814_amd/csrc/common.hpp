@@ -175,6 +175,9 @@ int fused2d_tile_of(int nx, int ny, const Fused2DCfg &c, int i, int j);
 bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
 
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
+// rec[slot[q]][step - rec_base] = p.s0 component probe_comp at cell[q], q < n
+hipError_t launch_3d_probe_list(const Prob3D &p, const int *cell, const int *slot, int n, int64_t step,
+                                hipStream_t st);
 // Fused 3D.  V: z cells per thread; TX: x planes marched by one interior
 // workgroup (0 = 16; workgroups with x/y CPML code march max(1, TX/4)).
 struct Fused3DCfg { int V; int TX; };

@@ -123,6 +123,19 @@ __global__ void k_probe_3d(Prob3D p, int64_t step) {
         p.rec[(int64_t)q * p.rec_stride + (step - p.rec_base)] = p.s0.f[p.probe_comp][p.probe_idx[q]];
 }
 
+// probe q of a list: rec[slot[q]][step] = component of set s0 at cell[q]
+__global__ void k_probe_3d_list(Prob3D p, const int *cell, const int *slot, int n, int64_t step) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p.rec[(int64_t)slot[q] * p.rec_stride + (step - p.rec_base)] = p.s0.f[p.probe_comp][cell[q]];
+}
+
+hipError_t launch_3d_probe_list(const Prob3D &p, const int *cell, const int *slot, int n, int64_t step,
+                                hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_3d_list, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, p, cell, slot, n, step);
+    return hipGetLastError();
+}
+
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st) {
     const int64_t n = (int64_t)p.nx * p.ny * p.nz;
     const unsigned nb = (unsigned)((n + 255) / 256);

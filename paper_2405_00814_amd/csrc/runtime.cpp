@@ -421,21 +421,55 @@ void Sim::build_probe_tiles() {
     swap_in(pt_cell, dev_upload(al, cell.data(), std::max<size_t>(cell.size(), 1), st));
     swap_in(pt_slot, dev_upload(al, slot.data(), std::max<size_t>(slot.size(), 1), st));
     if (ndim == 3 && kcfg.variant == 3) {
-        // which two-step tiles record probes (a probe cell in their own
-        // planes and rows), so that the others skip the group look-ups
-        // (8 probes in 512^3: the look-ups cost 3 % of the interior launch)
-        auto flags = [&](const std::vector<TileTB> &tl) {
-            std::vector<int> f(std::max<size_t>(tl.size(), 1), 0);
+        // which slab tiles record probes (a probe cell in their own planes
+        // and rows), so that the others skip the group look-ups
+        auto tile_of = [&](const std::vector<TileTB> &tl, int i, int j) {
             for (size_t t = 0; t < tl.size(); ++t)
-                for (const int64_t c : probe_cells) {
-                    const int i = (int)(c / ((int64_t)ny * nz)), j = (int)((c / nz) % ny);
-                    if (i >= tl[t].i0 && i < tl[t].i1 && j >= tl[t].j0 && j < tl[t].j0 + tl[t].nrows) f[t] = 1;
-                }
-            return f;
+                if (i >= tl[t].i0 && i < tl[t].i1 && j >= tl[t].j0 && j < tl[t].j0 + tl[t].nrows) return (int)t;
+            return -1;
         };
-        const std::vector<int> fa = flags(plan2.tb), fo = flags(plan2.tbo);
-        swap_in(tb_any, dev_upload(al, fa.data(), fa.size(), st));
+        std::vector<int> fo(std::max<size_t>(plan2.tbo.size(), 1), 0);
+        // probes of the interior tiles: the instance of the interior launch
+        // has no probe read-out (with it, its plane loop ran 4 % slower
+        // at 512^3, although no tile but the few probed ones executed it)
+        std::vector<int> gc, gs;
+        std::vector<Tile3> tw;
+        const int V = 4, seg = 64 * V;
+        for (size_t q = 0; q < probe_cells.size(); ++q) {
+            const int64_t c = probe_cells[q];
+            const int i = (int)(c / ((int64_t)ny * nz)), j = (int)((c / nz) % ny), k = (int)(c % nz);
+            const int to = tile_of(plan2.tbo, i, j);
+            if (to >= 0 || !plan2.slab_tb) {
+                if (to >= 0) fo[(size_t)to] = 1;
+                continue;
+            }
+            gc.push_back((int)c);
+            gs.push_back((int)q);
+            const int k0 = k / seg * seg;
+            const Tile3 t{i, i + 1, j, k0, std::min(k0 + seg, nz), k0, 1, 1};
+            bool dup = false;
+            for (const Tile3 &u : tw) dup = dup || (u.i0 == t.i0 && u.j0 == t.j0 && u.k0 == t.k0);
+            if (!dup) tw.push_back(t);
+        }
         swap_in(tbo_any, dev_upload(al, fo.data(), fo.size(), st));
+        pw.l.clear();
+        pw.tiles = tw;
+        if (!tw.empty()) {
+            while (pw.tiles.size() % 8) pw.tiles.push_back(Tile3{0, 0, 0, 0, 0, 0, 0, 0});
+            Wave3DLaunch l{};
+            l.V = V;
+            l.wpb = 8;
+            l.pxy = false;
+            l.pz = ax[2].lo + ax[2].hi > 0;
+            l.off = 0;
+            l.n = (int)pw.tiles.size();
+            l.cells = (int64_t)tw.size() * seg;
+            pw.l.push_back(l);
+        }
+        swap_in(pw_dev, tw.empty() ? nullptr : dev_upload(al, pw.tiles.data(), pw.tiles.size(), st));
+        swap_in(pg_cell, gc.empty() ? nullptr : dev_upload(al, gc.data(), gc.size(), st));
+        swap_in(pg_slot, gs.empty() ? nullptr : dev_upload(al, gs.data(), gs.size(), st));
+        n_pg = (int)gc.size();
     }
     pt_cfg[0] = a;
     pt_cfg[1] = b;
@@ -620,16 +654,30 @@ void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
     if ((pab.db ? 2 : (pab.ca ? 1 : 0)) != plan2_mat) fail(FDTD_ESTATE, "two-step plan out of date");
     if (plan2.slab_tb) {
         const State3D mid = prob3d(C, C).s1;
-        ProbeTiles pto = pt, pti = pt;
+        ProbeTiles pto = pt;
         pto.tile_any = tbo_any;
-        pti.tile_any = tb_any;
+        // probes of the interior tiles at step n+1: a single step of their
+        // rows from set cur into the fields of set 2 (whose psi arrays the
+        // slab tiles use: the rows are clear of the x/y slabs, so it writes
+        // none of those), on the second stream beside the slab tiles
+        if (n_pg > 0) {
+            hip_check(hipEventRecord(evf, st), "event");
+            hip_check(hipStreamWaitEvent(side, evf, 0), "stream wait");
+            hip_check(launch_3d_wave(prob3d(A, C), pw, pw_dev, pt, step, side), "3d probe rows");
+            hip_check(hipEventRecord(evj, side), "event");
+        }
         if (ev) hip_check(hipEventRecord(ev[0], st), "event");
         hip_check(launch_3d_two(pab, tbo_dev, (int)plan2.tbo.size(), pto, step, st, &mid), "3d two-step (slabs)");
         if (ev) hip_check(hipEventRecord(ev[1], st), "event");
-        hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), pti, step, st), "3d two-step");
+        const ProbeTiles none{nullptr, nullptr, nullptr};
+        hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), none, step, st), "3d two-step");
         if (ev) hip_check(hipEventRecord(ev[2], st), "event");
+        if (n_pg > 0) {  // and at step n+2, from the output set
+            hip_check(hipStreamWaitEvent(st, evj, 0), "stream wait");
+            hip_check(launch_3d_probe_list(prob3d(B, A), pg_cell, pg_slot, n_pg, step + 1, st), "3d probes");
+        }
         cur = B;
-        last_launches += (plan2.tbo.empty() ? 0 : 1) + (plan2.tb.empty() ? 0 : 1);
+        last_launches += (plan2.tbo.empty() ? 0 : 1) + (plan2.tb.empty() ? 0 : 1) + (n_pg > 0 ? 2 : 0);
         return;
     }
     hip_check(launch_3d_wave(prob3d(A, C), plan2.pass1, p1_dev, pt, step, st, ev), "3d pass1");

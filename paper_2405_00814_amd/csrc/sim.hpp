@@ -101,7 +101,14 @@ struct Sim {
     int64_t n_rec = 0;
     // probes grouped by tile for the fused kernels
     int *pt_start = nullptr, *pt_cell = nullptr, *pt_slot = nullptr;
-    int *tb_any = nullptr, *tbo_any = nullptr;  // per two-step tile: holds a probe
+    int *tbo_any = nullptr;  // per two-step slab tile: holds a probe
+    // probes of the interior two-step tiles (slab-tile mode): the single
+    // step of their plane, row and z segment (step n+1, recorded; set 2
+    // takes the fields), and the list read from the output set (step n+2)
+    Wave3DPlan pw;
+    Tile3 *pw_dev = nullptr;
+    int *pg_cell = nullptr, *pg_slot = nullptr;
+    int n_pg = 0;
     int pt_ntiles = -1;
     int pt_cfg[6] = {-1, -1, -1, -1, -1, -1};
     // 2D fused: tile ids clear of the CPML slabs, then the others.  Large
