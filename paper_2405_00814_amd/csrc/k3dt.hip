@@ -80,6 +80,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     const AxP Y = prof(p.y, jr, iky, jky);                             // row j
 
     __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
+    // step-2 H in buffers of its own, so that no barrier has to wait for
+    // the step-1 reads of LHx, LHz before it is written (12-wavefront
+    // instances without x/y-slab code or a Db map: the others would spill,
+    // or exceed the LDS, with 2 x NT x V floats more)
+    constexpr bool SB = !PXY && MAT != 2 && NR * RZ == 12;
+    __shared__ float LH2x[SB ? NT * V : 1], LH2z[SB ? NT * V : 1];
+    float *const H2x = SB ? LH2x : LHx, *const H2z = SB ? LH2z : LHz;
     __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
     // z-slab data in LDS, ZW entries per row: entry e holds cell k = e below
     // LO4 (the low slab's size rounded up to a multiple of 4) and k = HB4 +
@@ -602,9 +609,9 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
                 }
             }
         }
-        __syncthreads();  // step-1 LDS reads of this plane are done
-        stv<V>(&LHx[tq], hx2);
-        stv<V>(&LHz[tq], hz2);
+        if (!SB) __syncthreads();  // step-1 LDS reads of this plane are done
+        stv<V>(&H2x[tq], hx2);
+        stv<V>(&H2z[tq], hz2);
         if (lane == 63) { Sh2[rr][seg][0] = hx2[V - 1]; Sh2[rr][seg][1] = hy2[V - 1]; }
         __syncthreads();
         if (wb) {  // wave-uniform
@@ -612,8 +619,8 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             zero(hxj2);
             zero(hzj2);
             if (jm) {
-                ldv<V>(hxj2, &LHx[tq - ROW]);
-                ldv<V>(hzj2, &LHz[tq - ROW]);
+                ldv<V>(hxj2, &H2x[tq - ROW]);
+                ldv<V>(hzj2, &H2z[tq - ROW]);
             }
             const float hxs2 = (lane == 0 && seg > 0) ? Sh2[rr][seg > 0 ? seg - 1 : 0][0] : 0.f;
             const float hys2 = (lane == 0 && seg > 0) ? Sh2[rr][seg > 0 ? seg - 1 : 0][1] : 0.f;
