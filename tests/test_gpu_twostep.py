@@ -97,6 +97,29 @@ def test_two_step_sources_and_probes_everywhere():
             assert rel_l2(rec, rrec) <= TOL
 
 
+@pytest.mark.parametrize("comp", ["ez", "hy"])
+def test_two_step_interior_probes_at_z_seams(comp):
+    """Probes of interior tiles with two wavefronts per row (nz 300): at the
+    seam of the two z segments, in both z slabs, twice on one cell and
+    twice in one row; the slab-tile mode records them outside the interior
+    launch (a single step of their rows, then the output set)."""
+    shape, npml = (26, 32, 300), (4, 4, 4, 4, 6, 5)
+    pb = _problem(shape, npml, 41, src=(13, 16, 150))
+    pb.probe_component = comp
+    pb.probes = np.array([(12, 15, 255), (12, 15, 256), (12, 15, 257), (13, 16, 2), (13, 16, 298),
+                          (14, 17, 128), (14, 17, 128), (9, 12, 60), (9, 12, 61), (20, 25, 299), (2, 2, 150)],
+                         dtype=np.int32)
+    ref, rrec = run_oracle(pb, pb.steps)
+    one, rec1, _ = run_gpu(pb, pb.steps, (2, (4, 0, 8)))
+    for sp in (0, 1):
+        got, rec, cfg = run_gpu(pb, pb.steps, (3, (4, sp)), chunks=3)
+        log("interior probes", comp, "slab mode", sp, "rec %.1e" % rel_l2(rec, rrec))
+        assert_parity(got, ref, TOL, "two-step mode %d" % sp)
+        assert rel_l2(rec, rrec) <= TOL
+        assert rel_l2(rec, rec1) <= 1e-5
+        assert np.array_equal(rec[5], rec[6])  # the same cell twice
+
+
 @pytest.mark.parametrize("sp", [0, 1])
 def test_two_step_profile_matches_step(sp):
     from paper_2405_00814_amd.sim import Sim
