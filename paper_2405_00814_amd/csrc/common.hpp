@@ -226,9 +226,12 @@ bool two3d_supported(int nx, int ny, int nz, int zlo, int zhi);
 int two3d_rows(int nz, bool pz, int mat, bool pxy);  // mat: 0 Cb, 1 Ca+Cb, 2 Ca+Cb+Db maps
 // records probes at steps `step` and `step`+1 of cells it owns.  mid:
 // nullptr for tiles whose cone is clear of the x/y slabs; else the state
-// set whose x/y-slab psi arrays hold the step-1 psi (any tiles).
+// set whose x/y-slab psi arrays hold the step-1 psi (any tiles).  slab
+// (with mid): 3 any tiles; 4 tiles whose cones touch x slabs only or y
+// slabs only (the kernel holds a code path for each kind, without the
+// other kind's psi code: a tile touching both would miss psi terms).
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                         hipStream_t st, const State3D *mid = nullptr);
+                         hipStream_t st, const State3D *mid = nullptr, int slab = 3);
 // Plan of a two-step pass.  The interior tiles (cone clear of the x/y
 // slabs) run the two-step kernel without x/y-slab code.  The rest, S:
 //   slab_tb: tiles of the two-step kernel with x/y-slab code (tbo: x chunks
@@ -242,6 +245,9 @@ struct TwoPlan {
     int rows = 0, rows_o = 0;  // rows per band: tb, tbo
     int tx = 0;                // x planes per interior tile
     std::vector<TileTB> tb, tbo;  // each padded to a multiple of 8
+    // tbo in two groups, each a multiple of 8: the tiles whose cone touches
+    // both the x and the y slabs, then those whose cone touches one kind
+    int tbo_n[2] = {0, 0};
     int64_t tb_cells = 0, tb_psi = 0, tbo_cells = 0, tbo_psi = 0;
     Wave3DPlan pass1, pass2;
 };

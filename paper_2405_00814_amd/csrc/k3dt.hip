@@ -34,16 +34,48 @@
 
 namespace gem {
 
-template <int V, int RZ, int R, bool PZ, bool PXY, int MAT, bool REC>
-__global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const TileTB *tiles, ProbeTiles pt,
-                                                           int64_t step, State3D mid) {
+// Step-2 H in LDS buffers of its own, so that no barrier has to wait for
+// the step-1 reads of LHx, LHz before it is written: 12-wavefront instances
+// without x/y-slab code or a Db map (the others would spill, or exceed the
+// LDS, with 2 x NT x V floats more).
+constexpr bool two_sb(bool pxy, int mat, int waves) { return !pxy && mat != 2 && waves == 12; }
+
+// The workgroup's LDS arrays (declared once per kernel, shared by the code
+// paths of a kernel that holds two).  z-slab data, ZW entries per row: entry e holds
+// cell k = e below LO4 (the low slab's size rounded up to a multiple of 4)
+// and k = HB4 + e - LO4 from LO4 on (HB4: start of the high slab rounded
+// down), so a lane's V cells are V aligned consecutive entries; entries of
+// cells outside the slabs are padding (profile 0, psi 0: the correction is
+// then exactly zero).
+//   ZT: profile (kH - idzH, bH, cH, kE - idzE, bE, cE)
+//   ZP: state-n psi (Hx-z, Hy-z, Ex-z, Ey-z) of the current plane, rows
+//       j0-2 .. j0+R, copied from memory with the plane's fields
+//   Zs: step-1 psi of the last two planes (by plane parity) for step 2
+//   ZQ: step-2 psi of the own rows, written to memory coalesced after the
+//       next barrier
+template <int V, int RZ, int R, bool PZ, bool SB>
+struct TwoLds {
+    static constexpr int NR = R + 2, NT = 64 * RZ * NR, ZW = kTwoZMax + 8, NZR = NR + 1;
+    float (&LEx)[NT * V], (&LEz)[NT * V], (&LHx)[NT * V], (&LHz)[NT * V], (&L1x)[NT * V], (&L1z)[NT * V];
+    float (&LH2x)[SB ? NT * V : 1], (&LH2z)[SB ? NT * V : 1];
+    float (&Se0)[NR][RZ][2], (&Sh1)[NR][RZ][2], (&Se1)[NR][RZ][2], (&Sh2)[NR][RZ][2];
+    float (&ZT)[PZ ? 6 : 1][PZ ? ZW : 4];
+    float (&ZP)[PZ ? 4 : 1][PZ ? NZR * ZW : 4];
+    float (&Zs)[PZ ? 2 : 1][PZ ? NR : 1][PZ ? 4 : 1][PZ ? ZW : 4];
+    float (&ZQ)[PZ ? 4 : 1][PZ ? R * ZW : 4];
+};
+
+// One tile (T, at index tix of the launch's list) of the two-step pass.
+// SL: slab kinds of the instance's tiles (x/y-slab code): bit 0 x, bit 1 y;
+// the ψ code of a kind absent is left out.
+template <int V, int RZ, int R, bool PZ, bool PXY, int MAT, bool REC, int SL, class Lds>
+__device__ __forceinline__ void two_tile(const Prob3D &p, const TileTB &T, int tix, const ProbeTiles &pt,
+                                         int64_t step, const State3D &mid, Lds &L) {
     constexpr int NR = R + 2;            // rows held: halo, R own, halo
     constexpr int NT = 64 * RZ * NR;     // threads
     constexpr int SEG = 64 * V;          // z cells per wavefront
     constexpr int ROW = RZ * SEG;        // LDS floats per row
-    const int tix = xcd_block(blockIdx.x, gridDim.x);
-    const TileTB T = tiles[tix];
-    if (T.i0 >= T.i1) return;  // padding
+    constexpr bool SX = PXY && (SL & 1) != 0, SY = PXY && (SL & 2) != 0;
     // whether this tile records probes (wave-uniform)
     const bool tprobe = REC && pt.start != nullptr && (pt.tile_any == nullptr || pt.tile_any[tix] != 0);
     const int lane = threadIdx.x & 63;
@@ -79,33 +111,16 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     };
     const AxP Y = prof(p.y, jr, iky, jky);                             // row j
 
-    __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
-    // step-2 H in buffers of its own, so that no barrier has to wait for
-    // the step-1 reads of LHx, LHz before it is written (12-wavefront
-    // instances without x/y-slab code or a Db map: the others would spill,
-    // or exceed the LDS, with 2 x NT x V floats more)
-    constexpr bool SB = !PXY && MAT != 2 && NR * RZ == 12;
-    __shared__ float LH2x[SB ? NT * V : 1], LH2z[SB ? NT * V : 1];
-    float *const H2x = SB ? LH2x : LHx, *const H2z = SB ? LH2z : LHz;
-    __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
-    // z-slab data in LDS, ZW entries per row: entry e holds cell k = e below
-    // LO4 (the low slab's size rounded up to a multiple of 4) and k = HB4 +
-    // e - LO4 from LO4 on (HB4: start of the high slab rounded down), so a
-    // lane's V cells are V aligned consecutive entries; entries of cells
-    // outside the slabs are padding (profile 0, psi 0: the correction is
-    // then exactly zero).
-    //   ZT: profile (kH - idzH, bH, cH, kE - idzE, bE, cE)
-    //   ZP: state-n psi (Hx-z, Hy-z, Ex-z, Ey-z) of the current plane, rows
-    //       j0-2 .. j0+R, copied from memory with the plane's fields
-    //   Zs: step-1 psi of the last two planes (by plane parity) for step 2
-    //   ZQ: step-2 psi of the own rows, written to memory coalesced after
-    //       the next barrier
+    constexpr bool SB = two_sb(PXY, MAT, NR * RZ);
+    auto &LEx = L.LEx, &LEz = L.LEz, &LHx = L.LHx, &LHz = L.LHz, &L1x = L.L1x, &L1z = L.L1z;
+    auto &Se0 = L.Se0, &Sh1 = L.Sh1, &Se1 = L.Se1, &Sh2 = L.Sh2;
+    auto &ZT = L.ZT;
+    auto &ZP = L.ZP;
+    auto &Zs = L.Zs;
+    auto &ZQ = L.ZQ;
+    float *const H2x = SB ? L.LH2x : L.LHx, *const H2z = SB ? L.LH2z : L.LHz;
     constexpr int ZW = kTwoZMax + 8;
     constexpr int NZR = NR + 1;
-    __shared__ __align__(16) float ZT[PZ ? 6 : 1][PZ ? ZW : 4];
-    __shared__ __align__(16) float ZP[PZ ? 4 : 1][PZ ? NZR * ZW : 4];
-    __shared__ __align__(16) float Zs[PZ ? 2 : 1][PZ ? NR : 1][PZ ? 4 : 1][PZ ? ZW : 4];
-    __shared__ __align__(16) float ZQ[PZ ? 4 : 1][PZ ? R * ZW : 4];
     const int zlo = p.z.lo, zhi = p.z.hi;
     const int LO4 = (zlo + 3) & ~3, HB4 = (nz - zhi) & ~3;
     const bool zany = PZ && ok && (kb < LO4 || kb >= HB4);
@@ -153,13 +168,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             dyz[v] = dEyz;
             dxz[v] = dExz;
             float ty = Ya.kH * dEzy, tzy = Ya.kH * dExy, tx = Xa.kH * dEzx, tzx = Xa.kH * dEyx;
-            if (PXY && iny) {
+            if (SY && iny) {
                 q[0][v] = Ya.bH * q[0][v] + Ya.cH * dEzy;
                 q[1][v] = Ya.bH * q[1][v] + Ya.cH * dExy;
                 ty += q[0][v];
                 tzy += q[1][v];
             }
-            if (PXY && inx) {
+            if (SX && inx) {
                 q[2][v] = Xa.bH * q[2][v] + Xa.cH * dEzx;
                 q[3][v] = Xa.bH * q[3][v] + Xa.cH * dEyx;
                 tx += q[2][v];
@@ -202,13 +217,13 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
             const float dHyx = hy[v] - hyp[v], dHxy = hx[v] - hxj[v];
             const bool ux = jm && k >= 1, uy = im && k >= 1, uz = im && jm;
             float ty = Ya.kE * dHzy, tx = Xa.kE * dHzx, tzx = Xa.kE * dHyx, tzy = Ya.kE * dHxy;
-            if (PXY && iny) {
+            if (SY && iny) {
                 if (ux) q[0][v] = Ya.bE * q[0][v] + Ya.cE * dHzy;
                 if (uz) q[1][v] = Ya.bE * q[1][v] + Ya.cE * dHxy;
                 ty += q[0][v];
                 tzy += q[1][v];
             }
-            if (PXY && inx) {
+            if (SX && inx) {
                 if (uy) q[2][v] = Xa.bE * q[2][v] + Xa.cE * dHzx;
                 if (uz) q[3][v] = Xa.bE * q[3][v] + Xa.cE * dHyx;
                 tx += q[2][v];
@@ -224,18 +239,18 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     // inx), else zero; and the reverse
     auto qload = [&](float (&q)[4][V], float *const *S, int a, int b, int c, int d, unsigned qy, bool iny,
                      unsigned qx, bool inx) {
-        ld(q[0], S[a], qy, iny);
-        ld(q[1], S[b], qy, iny);
-        ld(q[2], S[c], qx, inx);
-        ld(q[3], S[d], qx, inx);
+        ld(q[0], S[a], qy, SY && iny);
+        ld(q[1], S[b], qy, SY && iny);
+        ld(q[2], S[c], qx, SX && inx);
+        ld(q[3], S[d], qx, SX && inx);
     };
     auto qstore = [&](const float (&q)[4][V], float *const *S, int a, int b, int c, int d, unsigned qy, bool iny,
                       unsigned qx, bool inx) {
-        if (iny) {
+        if (SY && iny) {
             stv<V>(S[a] + qy, q[0]);
             stv<V>(S[b] + qy, q[1]);
         }
-        if (inx) {
+        if (SX && inx) {
             stv<V>(S[c] + qx, q[2]);
             stv<V>(S[d] + qx, q[3]);
         }
@@ -668,48 +683,83 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
     }
 }
 
+template <int V, int RZ, int R, bool PZ, bool PXY, int MAT, bool REC, int SL>
+__global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const TileTB *tiles, ProbeTiles pt,
+                                                           int64_t step, State3D mid) {
+    constexpr int NR = R + 2, NT = 64 * RZ * NR, ZW = kTwoZMax + 8, NZR = NR + 1;
+    constexpr bool SB = two_sb(PXY, MAT, NR * RZ);
+    __shared__ float LEx[NT * V], LEz[NT * V], LHx[NT * V], LHz[NT * V], L1x[NT * V], L1z[NT * V];
+    __shared__ float LH2x[SB ? NT * V : 1], LH2z[SB ? NT * V : 1];
+    __shared__ float Se0[NR][RZ][2], Sh1[NR][RZ][2], Se1[NR][RZ][2], Sh2[NR][RZ][2];
+    __shared__ __align__(16) float ZT[PZ ? 6 : 1][PZ ? ZW : 4];
+    __shared__ __align__(16) float ZP[PZ ? 4 : 1][PZ ? NZR * ZW : 4];
+    __shared__ __align__(16) float Zs[PZ ? 2 : 1][PZ ? NR : 1][PZ ? 4 : 1][PZ ? ZW : 4];
+    __shared__ __align__(16) float ZQ[PZ ? 4 : 1][PZ ? R * ZW : 4];
+    TwoLds<V, RZ, R, PZ, SB> L{LEx, LEz, LHx, LHz, L1x, L1z, LH2x, LH2z, Se0, Sh1, Se1, Sh2, ZT, ZP, Zs, ZQ};
+    const int tix = xcd_block(blockIdx.x, gridDim.x);
+    const TileTB T = tiles[tix];
+    if (T.i0 >= T.i1) return;  // padding
+    if constexpr (SL == 4) {
+        // tiles near x slabs only or y slabs only: the code path of the
+        // tile's kind (wave-uniform), the register allocation of the larger
+        const int a = max(T.i0 - 2, 0), b = min(T.i1, p.nx - 1);
+        const bool onx = (p.x.lo > 0 && a < p.x.lo) || (p.x.hi > 0 && b >= p.nx - p.x.hi);
+        if (onx) two_tile<V, RZ, R, PZ, PXY, MAT, REC, 1>(p, T, tix, pt, step, mid, L);
+        else two_tile<V, RZ, R, PZ, PXY, MAT, REC, 2>(p, T, tix, pt, step, mid, L);
+    } else {
+        two_tile<V, RZ, R, PZ, PXY, MAT, REC, SL>(p, T, tix, pt, step, mid, L);
+    }
+}
+
 // REC: the instance holds the probe read-out.  Without x/y-slab code a
 // launch with no probe entries (pt.start == nullptr) runs the instance
 // without it: the read-out code, even where no tile executes it, made the
-// plane loop 4 % slower.
-template <int RZ, bool PZ, bool PXY, int MAT, bool REC>
+// plane loop 4 % slower.  SL: slab kinds of the x/y-slab instance.
+template <int RZ, bool PZ, bool PXY, int MAT, bool REC, int SL>
 static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
                    const State3D &mid, hipStream_t st) {
     constexpr int W = two_waves(PZ, MAT, PXY), R = W / RZ - 2;
-    hipLaunchKernelGGL((k3d_two<4, RZ, R, PZ, PXY, MAT, REC>), dim3((unsigned)n), dim3(64 * W), 0, st, p, tiles, pt,
-                       step, mid);
+    hipLaunchKernelGGL((k3d_two<4, RZ, R, PZ, PXY, MAT, REC, SL>), dim3((unsigned)n), dim3(64 * W), 0, st, p, tiles,
+                       pt, step, mid);
 }
 
-template <int RZ, bool PZ, bool PXY, bool REC>
+template <int RZ, bool PZ, bool PXY, bool REC, int SL>
 static void go_two_m(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
                      const State3D &mid, hipStream_t st) {
     const int mat = p.db ? 2 : (p.ca ? 1 : 0);
-    if (mat == 0) go_two<RZ, PZ, PXY, 0, REC>(p, tiles, n, pt, step, mid, st);
-    else if (mat == 1) go_two<RZ, PZ, PXY, 1, REC>(p, tiles, n, pt, step, mid, st);
-    else go_two<RZ, PZ, PXY, 2, REC>(p, tiles, n, pt, step, mid, st);
+    if (mat == 0) go_two<RZ, PZ, PXY, 0, REC, SL>(p, tiles, n, pt, step, mid, st);
+    else if (mat == 1) go_two<RZ, PZ, PXY, 1, REC, SL>(p, tiles, n, pt, step, mid, st);
+    else go_two<RZ, PZ, PXY, 2, REC, SL>(p, tiles, n, pt, step, mid, st);
+}
+
+template <int RZ, bool PZ>
+static void go_two_s(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
+                     const State3D &mid, int slab, hipStream_t st) {
+    if (slab == 4) go_two_m<RZ, PZ, true, true, 4>(p, tiles, n, pt, step, mid, st);
+    else go_two_m<RZ, PZ, true, true, 3>(p, tiles, n, pt, step, mid, st);
 }
 
 template <int RZ>
 static void go_two_c(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                     const State3D *mid, hipStream_t st) {
+                     const State3D *mid, int slab, hipStream_t st) {
     const bool pz = p.z.lo + p.z.hi > 0;
     if (mid) {
-        if (pz) go_two_m<RZ, true, true, true>(p, tiles, n, pt, step, *mid, st);
-        else go_two_m<RZ, false, true, true>(p, tiles, n, pt, step, *mid, st);
+        if (pz) go_two_s<RZ, true>(p, tiles, n, pt, step, *mid, slab, st);
+        else go_two_s<RZ, false>(p, tiles, n, pt, step, *mid, slab, st);
     } else {
         const State3D none{};
         if (pt.start) {
-            if (pz) go_two_m<RZ, true, false, true>(p, tiles, n, pt, step, none, st);
-            else go_two_m<RZ, false, false, true>(p, tiles, n, pt, step, none, st);
+            if (pz) go_two_m<RZ, true, false, true, 0>(p, tiles, n, pt, step, none, st);
+            else go_two_m<RZ, false, false, true, 0>(p, tiles, n, pt, step, none, st);
         } else {
-            if (pz) go_two_m<RZ, true, false, false>(p, tiles, n, pt, step, none, st);
-            else go_two_m<RZ, false, false, false>(p, tiles, n, pt, step, none, st);
+            if (pz) go_two_m<RZ, true, false, false, 0>(p, tiles, n, pt, step, none, st);
+            else go_two_m<RZ, false, false, false, 0>(p, tiles, n, pt, step, none, st);
         }
     }
 }
 
 hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
-                         hipStream_t st, const State3D *mid) {
+                         hipStream_t st, const State3D *mid, int slab) {
     if (n <= 0) return hipSuccess;
     if (!two3d_supported(p.nx, p.ny, p.nz, p.z.lo, p.z.hi)) return hipErrorInvalidValue;
     if (mid && p.x.lo + p.x.hi + p.y.lo + p.y.hi > 0) {
@@ -719,8 +769,9 @@ hipError_t launch_3d_two(const Prob3D &p, const TileTB *tiles, int n, const Prob
         for (int a : {PSI_HYX, PSI_HZX, PSI_EYX, PSI_EZX})
             if (p.x.lo + p.x.hi > 0 && !mid->psi[a]) return hipErrorInvalidValue;
     }
-    if (p.nz <= 64 * 4) go_two_c<1>(p, tiles, n, pt, step, mid, st);
-    else go_two_c<2>(p, tiles, n, pt, step, mid, st);
+    if (slab != 3 && slab != 4) return hipErrorInvalidValue;
+    if (p.nz <= 64 * 4) go_two_c<1>(p, tiles, n, pt, step, mid, slab, st);
+    else go_two_c<2>(p, tiles, n, pt, step, mid, slab, st);
     return hipGetLastError();
 }
 

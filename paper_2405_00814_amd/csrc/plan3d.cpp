@@ -243,6 +243,7 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_
                 const int *xlohi, const int *ylohi, const int *zlohi, TwoPlan &pl) {
     pl.tb.clear();
     pl.tbo.clear();
+    pl.tbo_n[0] = pl.tbo_n[1] = 0;
     pl.tb_cells = pl.tb_psi = pl.tbo_cells = pl.tbo_psi = 0;
     pl.pass1.l.clear();
     pl.pass1.tiles.clear();
@@ -311,6 +312,7 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_
         chunks(xo, xa, xb, TXo);
         const size_t nmid = xo.size();
         chunks(xo, xb, nx, TXo);
+        std::vector<TileTB> kind[3];  // cones touching both slab kinds, x slabs only, y slabs only
         for (size_t q = 0; q < xo.size(); ++q) {
             const int i0 = xo[q].a, i1 = xo[q].b;
             int64_t xs = 0;
@@ -320,7 +322,9 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_
                     const int nr = std::min(Ro, b - j0);
                     int64_t ysn = 0;
                     for (int jj = j0; jj < j0 + nr; ++jj) ysn += inslab(ny, ylohi[0], ylohi[1], jj);
-                    pl.tbo.push_back(TileTB{i0, i1, j0, nr});
+                    const bool onx = !clear(nx, xlohi[0], xlohi[1], i0 - 2, i1);
+                    const bool ony = !clear(ny, ylohi[0], ylohi[1], j0 - 2, j0 + nr);
+                    kind[onx && ony ? 0 : (ony ? 2 : 1)].push_back(TileTB{i0, i1, j0, nr});
                     pl.tbo_cells += (int64_t)(i1 - i0) * nr * nz;
                     pl.tbo_psi += 4 * (xs * nr * nz + (int64_t)(i1 - i0) * ysn * nz + (int64_t)(i1 - i0) * nr * zs);
                 }
@@ -332,8 +336,28 @@ void two3d_plan(int nx, int ny, int nz, const Fused3DCfg &c, int mat, bool slab_
                 band(yb, ny);
             }
         }
+        // the tiles near both slab kinds, then those near one kind: the
+        // launch hands each XCD a contiguous eighth of its list, so each
+        // eighth takes an eighth of the x-slab tiles and an eighth of the
+        // y-slab ones (their chunk lengths differ), padded to a common length
+        while (kind[0].size() % 8) kind[0].push_back(TileTB{0, 0, 0, 0});
+        pl.tbo = kind[0];
+        pl.tbo_n[0] = (int)kind[0].size();
+        std::vector<std::vector<TileTB>> part(8);
+        size_t Lp = 0;
+        for (int e = 0; e < 8; ++e) {
+            for (int g = 1; g <= 2; ++g) {
+                const size_t n = kind[g].size(), a = n * e / 8, b = n * (e + 1) / 8;
+                part[(size_t)e].insert(part[(size_t)e].end(), kind[g].begin() + (long)a, kind[g].begin() + (long)b);
+            }
+            Lp = std::max(Lp, part[(size_t)e].size());
+        }
+        for (auto &q : part) {
+            q.resize(Lp, TileTB{0, 0, 0, 0});
+            pl.tbo.insert(pl.tbo.end(), q.begin(), q.end());
+        }
+        pl.tbo_n[1] = (int)(8 * Lp);
         while (pl.tb.size() % 8) pl.tb.push_back(TileTB{0, 0, 0, 0});
-        while (pl.tbo.size() % 8) pl.tbo.push_back(TileTB{0, 0, 0, 0});
         return;
     }
     pl.tx = TX;

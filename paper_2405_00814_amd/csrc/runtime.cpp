@@ -654,30 +654,40 @@ void Sim::launch_pair(int64_t step, hipEvent_t *ev) {
     if ((pab.db ? 2 : (pab.ca ? 1 : 0)) != plan2_mat) fail(FDTD_ESTATE, "two-step plan out of date");
     if (plan2.slab_tb) {
         const State3D mid = prob3d(C, C).s1;
-        ProbeTiles pto = pt;
-        pto.tile_any = tbo_any;
-        // probes of the interior tiles at step n+1: a single step of their
-        // rows from set cur into the fields of set 2 (whose psi arrays the
-        // slab tiles use: the rows are clear of the x/y slabs, so it writes
-        // none of those), on the second stream beside the slab tiles
-        if (n_pg > 0) {
+        // the slab tiles in two groups: those near both slab kinds, and
+        // those near one kind (a code path per kind, without the other
+        // kind's psi code)
+        const int nb = plan2.tbo_n[0], n1 = plan2.tbo_n[1];
+        auto slab_pt = [&](int off) {
+            ProbeTiles q = pt;
+            q.tile_any = tbo_any + off;
+            return q;
+        };
+        // second stream: the probes of the interior tiles at step n+1 (a
+        // single step of their rows from set cur into the fields of set 2,
+        // whose psi arrays the slab tiles use: the rows are clear of the x/y
+        // slabs, so it writes none of those), and the few tiles near both
+        // slab kinds, beside the others (all only read set cur)
+        const bool fork = n_pg > 0 || nb > 0;
+        if (fork) {
             hip_check(hipEventRecord(evf, st), "event");
             hip_check(hipStreamWaitEvent(side, evf, 0), "stream wait");
-            hip_check(launch_3d_wave(prob3d(A, C), pw, pw_dev, pt, step, side), "3d probe rows");
+            if (n_pg > 0) hip_check(launch_3d_wave(prob3d(A, C), pw, pw_dev, pt, step, side), "3d probe rows");
+            if (nb > 0)
+                hip_check(launch_3d_two(pab, tbo_dev, nb, slab_pt(0), step, side, &mid, 3), "3d two-step (slab corners)");
             hip_check(hipEventRecord(evj, side), "event");
         }
         if (ev) hip_check(hipEventRecord(ev[0], st), "event");
-        hip_check(launch_3d_two(pab, tbo_dev, (int)plan2.tbo.size(), pto, step, st, &mid), "3d two-step (slabs)");
+        if (n1 > 0) hip_check(launch_3d_two(pab, tbo_dev + nb, n1, slab_pt(nb), step, st, &mid, 4), "3d two-step (slabs)");
         if (ev) hip_check(hipEventRecord(ev[1], st), "event");
         const ProbeTiles none{nullptr, nullptr, nullptr};
         hip_check(launch_3d_two(pab, tb_dev, (int)plan2.tb.size(), none, step, st), "3d two-step");
         if (ev) hip_check(hipEventRecord(ev[2], st), "event");
-        if (n_pg > 0) {  // and at step n+2, from the output set
-            hip_check(hipStreamWaitEvent(st, evj, 0), "stream wait");
+        if (fork) hip_check(hipStreamWaitEvent(st, evj, 0), "stream wait");
+        if (n_pg > 0)  // and at step n+2, from the output set
             hip_check(launch_3d_probe_list(prob3d(B, A), pg_cell, pg_slot, n_pg, step + 1, st), "3d probes");
-        }
         cur = B;
-        last_launches += (plan2.tbo.empty() ? 0 : 1) + (plan2.tb.empty() ? 0 : 1) + (n_pg > 0 ? 2 : 0);
+        last_launches += (nb > 0) + (n1 > 0) + (plan2.tb.empty() ? 0 : 1) + (n_pg > 0 ? 2 : 0);
         return;
     }
     hip_check(launch_3d_wave(prob3d(A, C), plan2.pass1, p1_dev, pt, step, st, ev), "3d pass1");

@@ -118,6 +118,28 @@ int check2s(int nx, int ny, int nz, int TX, int txo, int mat, const int *xl, con
         return 1;
     }
     if (pl.tb.size() % 8 || pl.tbo.size() % 8) { printf("slab plan lists not mult of 8\n"); return 1; }
+    // slab list in two groups (cones touching both slab kinds, then one
+    // kind), each a multiple of 8: the second group's kernel holds a code
+    // path per kind, without the other kind's psi code
+    if (pl.tbo_n[0] + pl.tbo_n[1] != (int)pl.tbo.size() || pl.tbo_n[0] % 8 || pl.tbo_n[1] % 8) {
+        printf("slab groups\n");
+        return 1;
+    }
+    for (size_t q = 0; q < pl.tbo.size(); ++q) {
+        const TileTB &T = pl.tbo[q];
+        if (T.i0 >= T.i1) continue;
+        const bool both = q < (size_t)pl.tbo_n[0];
+        bool onx = false, ony = false;
+        for (int i = T.i0 - 2; i <= T.i1; ++i) onx = onx || inslab(nx, xl[0], xl[1], i);
+        for (int j = T.j0 - 2; j <= T.j0 + T.nrows; ++j) ony = ony || inslab(ny, yl[0], yl[1], j);
+        // the kernel's test of the kind: planes [i0-2, i1] clipped to the grid
+        const int a = std::max(T.i0 - 2, 0), b = std::min(T.i1, nx - 1);
+        const bool kx = (xl[0] > 0 && a < xl[0]) || (xl[1] > 0 && b >= nx - xl[1]);
+        if ((both && !(onx && ony)) || (!both && (onx == ony || kx != onx))) {
+            printf("slab group of tile %d\n", (int)q);
+            return 1;
+        }
+    }
     std::vector<int> own((size_t)nx * ny, 0);
     int64_t zs = 0;
     for (int k = 0; k < nz; ++k) zs += inslab(nz, zl[0], zl[1], k);
