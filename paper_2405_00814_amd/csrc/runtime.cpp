@@ -1668,6 +1668,9 @@ int fdtd_set_field(fdtd_sim *sim, int component, const void *src, int src_on_dev
 // form, step count), then every field and CPML array of the current state
 // set in a fixed order (implicit form), or the node vector (graph form).
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+// state file helpers (C++ linkage)
 namespace {
 struct StateHeader {
     char magic[8];
@@ -1714,6 +1717,8 @@ int64_t state_size(Sim &s) {
     return n;
 }
 }  // namespace
+
+extern "C" {
 
 int fdtd_state_bytes(fdtd_sim *sim, int64_t *bytes) {
     GEM_TRY
