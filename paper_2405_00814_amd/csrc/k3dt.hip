@@ -25,6 +25,9 @@
 // wave-uniform scalars; the step-1 psi of a slab cell goes to the psi
 // arrays of a third state set (the same thread reads it back at the next
 // plane; a halo row's value, written by two tiles, is the same in both).
+// The tiles near one slab kind run a kernel with a code path per kind
+// (SL 4: each without the other kind's psi code, chosen per tile); those
+// near both kinds an instance with all of it (SL 3).
 #include <algorithm>
 #include <vector>
 
@@ -714,7 +717,8 @@ __global__ __launch_bounds__(64 * RZ * (R + 2)) void k3d_two(Prob3D p, const Til
 // REC: the instance holds the probe read-out.  Without x/y-slab code a
 // launch with no probe entries (pt.start == nullptr) runs the instance
 // without it: the read-out code, even where no tile executes it, made the
-// plane loop 4 % slower.  SL: slab kinds of the x/y-slab instance.
+// plane loop 4 % slower.  SL: slab kinds of the x/y-slab instance (3 both,
+// 4 one kind per tile, by a code path each; 0 without x/y-slab code).
 template <int RZ, bool PZ, bool PXY, int MAT, bool REC, int SL>
 static void go_two(const Prob3D &p, const TileTB *tiles, int n, const ProbeTiles &pt, int64_t step,
                    const State3D &mid, hipStream_t st) {
