@@ -283,7 +283,14 @@ int fdtd_set_material(fdtd_sim *sim, const int32_t *lo, const int32_t *hi,
  *  variant: 0 = auto (autotuned or default), 1 = two-pass reference
  *           (separate H and E kernels, in place), 2 = fused single pass
  *           (one kernel per step, double-buffered state), 3 = several
- *           leapfrog steps per pass over memory.  3D: every tile
+ *           leapfrog steps per pass over memory, 4 = (2D) the whole grid
+ *           in one workgroup, its state in registers for all the steps of
+ *           an fdtd_step call, the two layers of a step separated by
+ *           workgroup barriers: grids without CPML or mu_r map, ny <= 1024
+ *           and at most 16 rows per band of ny (rounded up to 64) columns
+ *           (16384 cells at most, e.g. 128 x 128), at most 64 probes (an
+ *           fdtd_step call with more probes runs variant 2's single
+ *           steps); the default where it applies.  3D: every tile
  *           advances two steps in one kernel (state n+1 never leaves the
  *           chip, the x/y-CPML auxiliary values of step n+1 excepted: they
  *           pass through a third state set, allocated on first use, 24 B

@@ -135,6 +135,14 @@ extern "C" int fdtd_adjoint_grads(fdtd_sim *sim, int64_t T, int64_t n0, int64_t 
         saved = s.kcfg;
         restore_cfg = true;
         if ((s.kcfg.variant != 2 && s.kcfg.variant != 3) || !s.kcfg_explicit) default_variant_tiles(s, s.kcfg);
+        if (s.kcfg.variant == 4) {  // one-workgroup default (no per-step captures): single steps
+            const Fused2DCfg c = default_single2d(s.nx, s.ny);
+            s.kcfg = fdtd_kernel_config{};
+            s.kcfg.variant = 2;
+            s.kcfg.tile[0] = c.V;
+            s.kcfg.tile[1] = c.TX;
+            s.kcfg.tb = 1;
+        }
         if (s.kcfg.variant != 2 && s.kcfg.variant != 3) fail(FDTD_EINVAL, "no fused 2D kernel for this grid");
         const bool multi = s.kcfg.variant == 3;
         const int TB = multi ? s.kcfg.tile[2] : 1;

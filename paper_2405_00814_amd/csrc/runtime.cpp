@@ -97,7 +97,9 @@ void DevAlloc::release_all() {
 template <class T>
 static T *dev_upload(DevAlloc &al, const T *h, size_t n, hipStream_t st) {
     T *d = (T *)al.get(n * sizeof(T));
-    if (n) hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    // an empty host list (nullptr) padded to one element uploads zeros
+    if (n && h) hip_check(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    else if (n) hip_check(hipMemsetAsync(d, 0, n * sizeof(T), st), "upload");
     // callers pass short-lived host vectors: finish the copy before returning
     hip_check(hipStreamSynchronize(st), "upload sync");
     return d;
@@ -765,6 +767,16 @@ void Sim::advance(int64_t n) {
     const bool tb2 = kcfg.variant == 3 && ndim == 2 && !is_graph && !mon;
     const int64_t inc = probe_cells.empty() ? 0 : 1;
     int64_t q = 0;
+    // whole grid in one workgroup: all n steps in one launch (single steps
+    // where the probes no longer fit it)
+    if (kcfg.variant == 4 && ndim == 2 && !is_graph && !mon && n > 0 && res2d_ok()) {
+        hip_check(launch_2d_resident(prob2d(cur, 1 - cur), mat(), n_done, n, st), "2d resident steps");
+        cur = 1 - cur;
+        n_done += n;
+        n_rec += n * inc;
+        last_launches += (n + 65535) / 65536;
+        return;
+    }
     if (two)
         for (; q + 2 <= n; q += 2) {
             launch_pair(n_done);
@@ -885,6 +897,10 @@ int default_variant_tiles(const Sim &s, fdtd_kernel_config &k) {
         return 0;
     }
     if (s.ndim == 2) {
+        if (!s.is_graph && s.res2d_ok()) {  // small grid without CPML: one workgroup
+            k.variant = 4;
+            return 0;
+        }
         const int vt = 1, tx = tb2d_default_tx(s.nx, s.ny, vt, s.cus);
         if (s.ncell >= kTB2MinCells && tb2d_supported(s.ny, vt, 4, tx)) {
             k.variant = 3;
@@ -925,6 +941,9 @@ static bool config_ok(const Sim &s, const fdtd_kernel_config &k) {
     if (k.tb != 0 && k.tb != 1 && !graph_tb) return false;
     if (k.variant == 1) return true;
     if (s.split) return false;
+    if (k.variant == 4)  // whole grid in one workgroup: checked again (probes) at every step call
+        return s.ndim == 2 && !s.is_graph && k.tile[0] == 0 && k.tile[1] == 0 && k.tile[2] == 0 &&
+               k.tile[3] == 0 && s.res2d_ok();
     if (k.variant != 2 && k.variant != 3) return false;
     if (s.ndim == 2) {
         if (k.variant == 2) return fused2d_supported(s.nx, s.ny, Fused2DCfg{k.tile[0], k.tile[1]});
@@ -1394,9 +1413,10 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
     const bool fused3 = s.ndim == 3 && !s.is_graph && s.kcfg.variant >= 2;
     const bool two = fused3 && s.kcfg.variant == 3 && steps >= 2;
     const bool tb2 = s.ndim == 2 && !s.is_graph && s.kcfg.variant == 3 && steps >= s.kcfg.tile[2];
-    // one timed unit: a step, a pair of steps for the 3D two-step pass, or
-    // the TB steps of the 2D multi-step pass
-    const int32_t per = two ? 2 : (tb2 ? s.kcfg.tile[2] : 1);
+    const bool res = s.ndim == 2 && !s.is_graph && s.kcfg.variant == 4 && s.res2d_ok();
+    // one timed unit: a step, a pair of steps for the 3D two-step pass, the
+    // TB steps of the 2D multi-step pass, or all steps (one workgroup)
+    const int32_t per = two ? 2 : (tb2 ? s.kcfg.tile[2] : (res ? steps : 1));
     const int32_t units = steps / per;
     const size_t nl = two ? s.pair_launches() : (fused3 ? s.plan3.l.size() : 1);
     // all events of all units are recorded first; one synchronisation at the end
@@ -1421,6 +1441,12 @@ int fdtd_step_profile(fdtd_sim *sim, int32_t steps, fdtd_launch_stat *out, int32
         } else if (tb2) {
             hip_check(hipEventRecord(e[0], s.st), "event");
             s.launch_tb2d(s.n_done);
+            hip_check(hipEventRecord(e[1], s.st), "event");
+        } else if (res) {
+            hip_check(hipEventRecord(e[0], s.st), "event");
+            hip_check(launch_2d_resident(s.prob2d(s.cur, 1 - s.cur), s.mat(), s.n_done, per, s.st), "2d resident steps");
+            s.cur = 1 - s.cur;
+            s.last_launches += (per + 65535) / 65536;
             hip_check(hipEventRecord(e[1], s.st), "event");
         } else {
             if (fused3) s.lev = e;
@@ -1882,11 +1908,14 @@ int fdtd_set_kernel(fdtd_sim *sim, const fdtd_kernel_config *cfg) {
         if (k.tile[0] == 0) k.tile[0] = 1;
         if (k.tile[1] == 0) k.tile[1] = kTB2DefaultTX;
         if (k.tile[2] == 0) k.tile[2] = 4;
+    } else if (s.ndim == 2 && k.variant == 2) {
+        const Fused2DCfg c = default_single2d(s.nx, s.ny);
+        if (k.tile[0] == 0) k.tile[0] = c.V;
+        if (k.tile[1] == 0) k.tile[1] = c.TX;
     } else if (k.variant == 2 || k.variant == 3) {
         fdtd_kernel_config d;
         default_variant_tiles(s, d);
         if (k.tile[0] == 0) k.tile[0] = d.tile[0];
-        if (s.ndim == 2 && k.tile[1] == 0) k.tile[1] = d.tile[1];
     }
     if (!config_ok(s, k)) fail(FDTD_EINVAL, "unsupported kernel configuration for this grid");
     hip_check(hipStreamSynchronize(s.st), "sync");
@@ -1937,6 +1966,12 @@ int fdtd_autotune(fdtd_sim *sim, int32_t trial_steps, fdtd_kernel_config *out) {
     // candidates
     std::vector<fdtd_kernel_config> cand;
     if (s.ndim == 2) {
+        {
+            fdtd_kernel_config k{};
+            k.variant = 4;
+            k.tb = 1;
+            if (config_ok(s, k)) cand.push_back(k);
+        }
         for (int V : {1, 2, 4})
             for (int TX : {4, 8, 16, 32}) {
                 fdtd_kernel_config k{};

@@ -127,6 +127,13 @@ struct Sim {
     int tb2_inner = 0, tb2_outer = 0;
     int *pt2_start = nullptr, *pt2_cell = nullptr, *pt2_slot = nullptr;
     int mat() const { return mumap ? 2 : (lossy ? 1 : 0); }
+    // the 2D grid (no CPML, split field, mu_r map or graph) fits the
+    // one-workgroup kernel with the current probes
+    bool res2d_ok() const {
+        return ndim == 2 && !split && !is_graph && mat() <= 1 &&
+               res2d_supported(nx, ny, ax[0].lo + ax[0].hi + ax[1].lo + ax[1].hi > 0, probe_cells.data(),
+                               (int)probe_cells.size());
+    }
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
     Tile3 *tl_dev = nullptr;
