@@ -179,7 +179,7 @@ bool fused2d_supported(int nx, int ny, const Fused2DCfg &c);
 // rows per band of ny (rounded up to 64) columns in 1024 threads, at most
 // 64 probes; the state in registers for all nsteps steps (s0 in, s1 out;
 // several launches for more than 65536 steps).
-bool res2d_supported(int nx, int ny, bool cpml, const int64_t *probe_cells, int np);
+bool res2d_supported(int nx, int ny, bool cpml, int np);
 hipError_t launch_2d_resident(const Prob2D &p, int mat, int64_t step, int64_t nsteps, hipStream_t st);
 hipError_t launch_3d_ref(const Prob3D &p, int64_t step, hipStream_t st);
 // rec[slot[q]][step - rec_base] = p.s0 component probe_comp at cell[q], q < n

@@ -16,7 +16,6 @@
 // mu_r map (uniform Db).
 // Soft source after the E layer; probes sample after the step.
 #include <algorithm>
-#include <vector>
 
 #include "common.hpp"
 #include "devutil.hpp"
@@ -101,8 +100,8 @@ __global__ __launch_bounds__(kResThreads) void k2d_resident(Prob2D p, int64_t st
         for (int r = 0; r < RR; ++r) sEz[w][r] = ez[r];
     sEzR[t] = ez[0];
     __syncthreads();
-    // the source value of each step is loaded one step ahead (a load issued
-    // and awaited within the step would cost its whole latency every step)
+    // the source value of each step is loaded at the start of the step
+    // before (its latency then overlaps that step's work)
     float sv = (scol && step0 < p.src_len) ? p.src_vals[step0] : 0.f;
     for (int s = 0; s < nsteps; ++s) {
         const int64_t n = step0 + s;
@@ -174,12 +173,10 @@ __global__ __launch_bounds__(kResThreads) void k2d_resident(Prob2D p, int64_t st
         }
 }
 
-bool res2d_supported(int nx, int ny, bool cpml, const int64_t *probe_cells, int np) {
+bool res2d_supported(int nx, int ny, bool cpml, int np) {
     if (cpml || nx < 1 || ny < 1) return false;
     const ResLayout L = res_layout(nx, ny);
-    if (L.nbk < 1 || L.rb > kResRows) return false;
-    (void)probe_cells;
-    return np <= kResProbes;
+    return L.nbk >= 1 && L.rb <= kResRows && np <= kResProbes;
 }
 
 template <int MAT>

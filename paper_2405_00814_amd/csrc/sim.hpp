@@ -131,8 +131,7 @@ struct Sim {
     // one-workgroup kernel with the current probes
     bool res2d_ok() const {
         return ndim == 2 && !split && !is_graph && mat() <= 1 &&
-               res2d_supported(nx, ny, ax[0].lo + ax[0].hi + ax[1].lo + ax[1].hi > 0, probe_cells.data(),
-                               (int)probe_cells.size());
+               res2d_supported(nx, ny, ax[0].lo + ax[0].hi + ax[1].lo + ax[1].hi > 0, (int)probe_cells.size());
     }
     // 3D fused: launch plan and its tile lists on the device
     Wave3DPlan plan3;
