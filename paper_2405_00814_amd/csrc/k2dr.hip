@@ -60,31 +60,42 @@ __global__ __launch_bounds__(kResThreads) void k2d_resident(Prob2D p, int64_t st
     __shared__ float sHx[kResThreads / 64][RR];  // lane 63's Hx, per wavefront
     __shared__ float sEzR[kResThreads];          // band's first-row Ez, per band and column
     __shared__ float sHyR[kResThreads];          // band's last-row Hy
-    __shared__ int sPo[kResProbes], sPr[kResProbes];  // probe q: owner thread, its row
+    __shared__ int sPr[kResProbes], sNext[kResProbes];  // probe q: its row, the holder's next probe
+    __shared__ int sFirst[kResThreads];                 // a thread's first probe (-1: none)
     // Ca map in LDS (row r of thread t at r * 1024 + t): in registers as
     // well it would make the kernel spill
     __shared__ float sCa[MAT >= 1 ? RR * kResThreads : 1];
-    const float ikx = p.x.kH[0], iky = p.y.kH[0], jkx = p.x.kE[0], jky = p.y.kE[0], db0 = p.db0;
+    const float jkx = p.x.kE[0], jky = p.y.kE[0];
+    const float dbx = p.db0 * p.x.kH[0], dby = p.db0 * p.y.kH[0];  // the H layer's weights
 
+    // Cb = 0, Ca = 1 where the E layer leaves Ez as it is (row 0, column 0,
+    // and the lanes and rows outside the grid): the update then needs no
+    // per-cell condition
     float ez[RR], hx[RR], hy[RR], cb[RR];  // Ca: sCa
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
         const bool in = col && r < nr;
+        const bool upd = in && i0 + r >= 1 && j >= 1;
         const int64_t c = (int64_t)(i0 + r) * ny + j;
         ez[r] = in ? p.s0.ez[c] : 0.f;
         hx[r] = in ? p.s0.hx[c] : 0.f;
         hy[r] = in ? p.s0.hy[c] : 0.f;
-        cb[r] = in ? p.cb[c] : 0.f;
-        if (MAT >= 1) sCa[MAT >= 1 ? r * kResThreads + t : 0] = (in && p.ca) ? p.ca[c] : 1.f;
+        cb[r] = upd ? p.cb[c] : 0.f;
+        if (MAT >= 1) sCa[MAT >= 1 ? r * kResThreads + t : 0] = (upd && p.ca) ? p.ca[c] : 1.f;
     }
-    // probes: the thread holding the cell, and the cell's row in it
+    // probes: a list per thread holding probe cells (first in sFirst,
+    // then sNext), built once; the thread keeps its first in a register
     const int np = min(p.np, kResProbes);
+    sFirst[t] = -1;
+    __syncthreads();
     if (t < np) {
         const int cell = p.probe_idx[t];
         const int pi = cell / ny, pj = cell - pi * ny;
-        sPo[t] = pi / L.rb * L.nyp + pj;
         sPr[t] = pi % L.rb;
+        sNext[t] = atomicExch(&sFirst[pi / L.rb * L.nyp + pj], t);
     }
+    __syncthreads();
+    const int myq = sFirst[t];
     auto pick = [&](const float (&a)[RR], int r) {
         float v = 0.f;
 #pragma unroll
@@ -116,16 +127,14 @@ __global__ __launch_bounds__(kResThreads) void k2d_resident(Prob2D p, int64_t st
             const float seam = sEz[wn][r];  // same address on every lane
             const float en = lane == 63 ? (e63 ? seam : 0.f) : sh;
             const float es = r + 1 < nr ? ez[r + 1 < RR ? r + 1 : r] : elast;
-            const float ty = (en - ez[r]) * iky;
-            const float tx = (es - ez[r]) * ikx;
-            hx[r] -= db0 * ty;
-            hy[r] += db0 * tx;
+            hx[r] -= dby * (en - ez[r]);
+            hy[r] += dbx * (es - ez[r]);
         }
         // H seams for the E layer
         if (lane == 63)
 #pragma unroll
             for (int r = 0; r < RR; ++r) sHx[w][r] = hx[r];
-        sHyR[t] = pick(hy, nr - 1);
+        sHyR[t] = nr == RR ? hy[RR - 1] : pick(hy, nr - 1);  // uniform
         __syncthreads();
         // ---- E layer: Hx(i, j-1), Hy(i-1, j) ----
         const float hfirst = b > 0 ? sHyR[t - L.nyp] : 0.f;  // Hy of row i0 - 1
@@ -137,24 +146,21 @@ __global__ __launch_bounds__(kResThreads) void k2d_resident(Prob2D p, int64_t st
             const float sh = lane_prev(hx[r]);
             const float seam = sHx[wp][r];
             const float hw = lane == 0 ? (wprev ? seam : 0.f) : sh;
-            if (col && r < nr && i >= 1 && j >= 1) {
-                const float hn = r > 0 ? hy[r > 0 ? r - 1 : 0] : hfirst;
-                const float tx = (hy[r] - hn) * jkx;
-                const float ty = (hx[r] - hw) * jky;
-                ez[r] = (MAT >= 1 ? sCa[MAT >= 1 ? r * kResThreads + t : 0] * ez[r] : ez[r]) + cb[r] * (tx - ty);
-            }
+            const float hn = r > 0 ? hy[r > 0 ? r - 1 : 0] : hfirst;
+            const float tx = (hy[r] - hn) * jkx;
+            const float ty = (hx[r] - hw) * jky;
+            ez[r] = (MAT >= 1 ? sCa[MAT >= 1 ? r * kResThreads + t : 0] * ez[r] : ez[r]) + cb[r] * (tx - ty);
             if (srcn && r < nr && (unsigned)(i - sb[0]) < (unsigned)(sb[1] - sb[0])) ez[r] += sval;
         }
         // probes (after the step), by the thread holding the cell
-        for (int q = 0; q < np; ++q)
-            if (sPo[q] == t) {
-                const int r = sPr[q];
-                float v;
-                if (p.probe_comp == FDTD_HX) v = pick(hx, r);  // uniform
-                else if (p.probe_comp == FDTD_HY) v = pick(hy, r);
-                else v = pick(ez, r);
-                p.rec[(int64_t)q * p.rec_stride + (n - p.rec_base)] = v;
-            }
+        for (int q = myq; q >= 0; q = sNext[q]) {
+            const int r = sPr[q];
+            float v;
+            if (p.probe_comp == FDTD_HX) v = pick(hx, r);  // uniform
+            else if (p.probe_comp == FDTD_HY) v = pick(hy, r);
+            else v = pick(ez, r);
+            p.rec[(int64_t)q * p.rec_stride + (n - p.rec_base)] = v;
+        }
         // E seams for the next H layer
         if (lane == 0)
 #pragma unroll
