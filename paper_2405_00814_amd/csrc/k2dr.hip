@@ -7,7 +7,7 @@
 //
 // 1024 threads: the columns j of a row band are consecutive lanes (bands
 // start on a wavefront, ny rounded up to 64 lanes); a thread holds the Ez,
-// Hx, Hy (and Cb, Ca, Db maps) of up to 16 rows of its column.  Neighbours:
+// Hx, Hy and Cb of up to 16 rows of its column (Ca in LDS).  Neighbours:
 // j+1 and j-1 from the DPP lane shifts, across a wavefront edge from a
 // column of the neighbouring wavefront in LDS; i+1 and i-1 from the
 // thread's own rows, across a band edge from the neighbouring band's first
